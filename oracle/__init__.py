@@ -1,0 +1,26 @@
+"""FP64 reference solver for the batched PDHG library -- TEST INFRASTRUCTURE ONLY.
+
+A plain, slow CPU implementation of what the GPU path computes, written from
+arXiv 2601.21990 (Sections 3-5): the LP and its saddle form, the PDHG operator,
+reflected Halpern iterations, the fixed-point residual, adaptive restarts,
+primal-weight smoothing, the stopping criteria and the batched restart scope.
+It solves one LP at a time in float64 with numpy/scipy.
+
+Only the test suite, the smoke check and the benchmark's CPU-baseline leg may
+import this package.  It shares no code with the GPU library (kernels, headers,
+helpers or constants), and the GPU library never calls it.
+
+Pins: every function is checked in the CPU test suite against closed forms,
+brute-force vertex enumeration, an independent LP solver (HiGHS via scipy),
+first-order optimality of the proximal steps, firm nonexpansiveness, and
+KKT/complementary-slackness invariants.  Parity unpinned: iterate trajectories
+and iteration counts (the paper prints none), and the values of the restart
+constants beta_s, beta_n, beta_a, theta (named, not valued, in the paper).
+"""
+from .lp import LP, row_bounds, from_arrays, from_instance, apply_delta, BASE, SET_LO, SET_HI, OBJ_UNIT
+from .pdhg import (Options, Result, KKT, solve, solve_batch_avg, pdhg_operator,
+                   fixed_point_residual, kkt, reduced_cost, proj_box, support,
+                   proj_barrier_cone, opnorm, step_size, initial_primal_weight,
+                   smoothed_primal_weight, restart_due,
+                   RUNNING, OPTIMAL, ITERATION_LIMIT, INFEASIBLE_BOUNDS, NUMERICAL_ERROR,
+                   STATUS_NAMES)

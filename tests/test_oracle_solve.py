@@ -1,0 +1,202 @@
+"""End-to-end pins of the reference solver: the converged objective against
+exact optima (vertex enumeration, box closed form, hand-solved LPs, HiGHS),
+KKT and complementary-slackness invariants at every returned point, the
+strong-branching / bound-tightening semantics of Section 5, statuses, and the
+batched restart scope."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle as O
+from tests.lp_exact import vertex_enum, box_closed_form, highs
+from workloads import (make_tiny, make_cfg1, make_cfg2, choose_fractional, fsb_deltas,
+                       obbt_deltas, choose_vars)
+
+INF = np.inf
+
+
+def _check_invariants(lp, res, tol):
+    """At a returned point: x~ in the box and y~ in the barrier cone exactly;
+    the two nonnegative parts of the duality gap are small, which bounds the
+    complementary-slackness violation."""
+    x, y = res.x, res.y
+    assert np.all(x >= lp.xl) and np.all(x <= lp.xu)
+    np.testing.assert_array_equal(O.proj_barrier_cone(y, lp.l, lp.u), y)
+    r = O.reduced_cost(lp, y)
+    ax = lp.A @ x
+    # gap = (phi(y) - y'Ax) + (phi(r) - r'x) + (c + A'y + r)'x, first two parts >= 0 when Ax, x feasible
+    part_y = O.support(y, lp.l, lp.u) - float(y @ O.proj_box(ax, lp.l, lp.u))
+    part_r = O.support(r, lp.xl, lp.xu) - float(r @ x)
+    assert part_y >= -1e-9 * (1 + abs(part_y)) and part_r >= -1e-9 * (1 + abs(part_r))
+    scale = 1 + abs(res.kkt.obj) + abs(res.kkt.dual_obj)
+    assert part_r <= 10 * tol * scale
+    # complementary slackness per coordinate: r_j > 0 only where x_j sits near its upper bound, etc.
+    big = np.abs(r) > 1e-3
+    dist = np.where(r > 0, lp.xu - x, x - lp.xl)
+    assert np.all(np.abs(r[big]) * dist[big] <= 10 * tol * scale + 1e-9)
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_converges_to_vertex_enumeration_optimum(seed):
+    inst = make_tiny(seed, m=3, n=5, senses="ELG", box=(0.0, 4.0))
+    lp = O.from_instance(inst)
+    best, _ = vertex_enum(lp.A.toarray(), lp.l, lp.u, lp.xl, lp.xu, lp.c)
+    res = O.solve(lp, O.Options(tol=1e-9, max_iters=400000))
+    assert res.status == O.OPTIMAL
+    assert abs(res.obj - best) <= 1e-7 * (1 + abs(best))
+    _check_invariants(lp, res, 1e-9)
+
+
+def test_textbook_lps_solved():
+    with open(os.path.join(os.path.dirname(__file__), "golden", "textbook_lps.json")) as f:
+        data = json.load(f)["lps"]
+    for d in data:
+        A = np.array(d["A"])
+        csr = sp.csr_matrix(A)
+        lp = O.from_arrays(A.shape[0], A.shape[1], csr.indptr, csr.indices, csr.data, d["c"],
+                           d["b"], np.frombuffer(d["sense"].encode(), dtype=np.uint8),
+                           d["l"], d["u"])
+        res = O.solve(lp, O.Options(tol=1e-10, max_iters=200000))
+        assert res.status == O.OPTIMAL, d["name"]
+        assert abs(res.obj - d["obj"]) <= 1e-8 * (1 + abs(d["obj"])), d["name"]
+        np.testing.assert_allclose(res.x, d["x"], atol=1e-6)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_box_only_closed_form(seed):
+    """All rows free (l = -inf, u = +inf): y = 0 and each x_j sits at the bound
+    selected by the sign of c_j."""
+    rng = np.random.default_rng(seed)
+    m, n = 6, 12
+    A = sp.random(m, n, density=0.5, random_state=seed, data_rvs=rng.standard_normal).tocsr()
+    xl = rng.uniform(-3, 0, n)
+    xu = xl + rng.uniform(0.1, 4, n)
+    c = rng.standard_normal(n)
+    lp = O.LP(A=A, c=c, l=np.full(m, -INF), u=np.full(m, INF), xl=xl, xu=xu, b=np.ones(m))
+    res = O.solve(lp, O.Options(tol=1e-12, max_iters=100000))
+    obj, x = box_closed_form(c, xl, xu)
+    assert res.status == O.OPTIMAL
+    assert math.isclose(res.obj, obj, rel_tol=1e-10, abs_tol=1e-10)
+    np.testing.assert_allclose(res.x, x, atol=1e-9)
+    np.testing.assert_array_equal(res.y, 0.0)
+
+
+def test_zero_matrix_closed_form():
+    n = 8
+    rng = np.random.default_rng(4)
+    c = rng.standard_normal(n)
+    lp = O.LP(A=sp.csr_matrix((3, n)), c=c, l=np.zeros(3), u=np.zeros(3),
+              xl=np.zeros(n), xu=np.full(n, 2.0), b=np.zeros(3))
+    res = O.solve(lp, O.Options(tol=1e-12, max_iters=10000))
+    assert res.status == O.OPTIMAL
+    assert math.isclose(res.obj, box_closed_form(c, lp.xl, lp.xu)[0], rel_tol=1e-12)
+
+
+def test_cfg1_matches_highs():
+    lp = O.from_instance(make_cfg1())
+    res = O.solve(lp, O.Options(tol=1e-8))
+    obj, _, _ = highs(lp)
+    assert res.status == O.OPTIMAL
+    assert abs(res.obj - obj) <= 1e-6 * (1 + abs(obj))
+    _check_invariants(lp, res, 1e-8)
+
+
+def test_cfg2_shape_matches_highs_at_1e4():
+    """A 200 x 500 member of the strong-branching family at the throughput
+    tolerance: two 1e-4-optimal points bracket the optimum by the gap test."""
+    lp = O.from_instance(make_cfg2(m=200, n=500))
+    res = O.solve(lp, O.Options(tol=1e-4))
+    obj, _, _ = highs(lp)
+    assert res.status == O.OPTIMAL
+    assert abs(res.obj - obj) <= 4e-4 * (1 + abs(obj))
+    _check_invariants(lp, res, 1e-4)
+
+
+def test_strong_branching_batch_semantics():
+    """Each branch restricts the base LP (Section 5.1), so its optimum is no
+    better than the base optimum; both children are checked against HiGHS."""
+    lp = O.from_instance(make_cfg2(m=200, n=500))
+    base = O.solve(lp, O.Options(tol=1e-8))
+    vars_ = choose_fractional(base.x, 3, seed=7)
+    D = fsb_deltas(base.x, vars_)
+    assert list(D["kind"]) == [O.SET_LO] * 3 + [O.SET_HI] * 3
+    for d in D:
+        lpj = O.apply_delta(lp, int(d["kind"]), int(d["var"]), float(d["value"]))
+        r = O.solve(lpj, O.Options(tol=1e-7), x_init=base.x, y_init=base.y, w_init=base.w)
+        obj, _, _ = highs(lpj)
+        assert r.status == O.OPTIMAL
+        assert abs(r.obj - obj) <= 1e-5 * (1 + abs(obj))
+        assert obj >= base.obj - 1e-6 * (1 + abs(base.obj))
+
+
+def test_bound_tightening_semantics():
+    """min x_j <= x0_j <= max x_j for the feasible witness x0 (Section 5.2)."""
+    inst = make_cfg2(m=100, n=250)
+    lp = O.from_instance(inst)
+    vars_ = choose_vars(lp.n, 3, seed=5)
+    D = obbt_deltas(vars_)
+    res = [O.solve(O.apply_delta(lp, int(d["kind"]), int(d["var"]), float(d["value"])),
+                   O.Options(tol=1e-7)) for d in D]
+    for i, j in enumerate(vars_):
+        lo = res[i].obj            # min x_j
+        hi = -res[i + 3].obj       # max x_j = -min(-x_j)
+        assert lp.xl[j] - 1e-6 <= lo <= inst.x0[j] + 1e-4 * (1 + abs(lo))
+        assert inst.x0[j] - 1e-4 * (1 + abs(hi)) <= hi <= lp.xu[j] + 1e-6
+
+
+def test_statuses():
+    lp = O.from_instance(make_cfg1())
+    # crossing bounds after a delta: closed form, never iterated
+    bad = O.apply_delta(lp, O.SET_LO, 3, 11.0)
+    r = O.solve(bad)
+    assert r.status == O.INFEASIBLE_BOUNDS and r.iters == 0
+    # exact iteration limit
+    for K in (1, 2, 63, 64, 65, 130):
+        r = O.solve(lp, O.Options(tol=0.0, max_iters=K))
+        assert r.status == O.ITERATION_LIMIT and r.iters == K
+    # NaN data is caught at the first evaluation
+    lpn = O.LP(A=lp.A, c=lp.c.copy(), l=lp.l, u=lp.u, xl=lp.xl, xu=lp.xu, b=lp.b)
+    lpn.c[5] = np.nan
+    r = O.solve(lpn)
+    assert r.status == O.NUMERICAL_ERROR and r.iters == 1
+
+
+def test_restart_resets_iterate_to_tilde():
+    """After a restart the next iteration starts from the anchor z~ (a restart
+    leaves x inside the box); the Halpern iterate returned at a limit is the
+    reflected-average of the last step."""
+    lp = O.from_instance(make_cfg1())
+    # the stopping tests precede the restart test: a limit at t = 64 wins
+    assert O.solve(lp, O.Options(tol=0.0, max_iters=65)).restarts == []
+    r1 = O.solve(lp, O.Options(tol=0.0, max_iters=66))
+    assert r1.restarts == [64]
+    # at the limit t=65 (k=0 after the restart), the Halpern weight is 1/2:
+    # z^1 = (2 z~ - z) / 2 + z0 / 2 with z = z0 = anchor  ->  z~
+    np.testing.assert_allclose(r1.x_iter, r1.x, atol=1e-14)
+
+
+def test_batch_avg_single_lp_equals_solve():
+    lp = O.from_instance(make_cfg1())
+    a = O.solve(lp, O.Options(tol=1e-6))
+    b = O.solve_batch_avg([lp], O.Options(tol=1e-6))[0]
+    assert a.status == b.status and a.iters == b.iters and a.restarts == b.restarts
+    np.testing.assert_array_equal(a.x, b.x)
+    np.testing.assert_array_equal(a.y, b.y)
+
+
+def test_batch_avg_converges_each_lp():
+    lp = O.from_instance(make_cfg2(m=100, n=250))
+    lps = [O.apply_delta(lp, O.OBJ_UNIT, j, s) for j in (3, 17) for s in (1.0, -1.0)]
+    res = O.solve_batch_avg(lps, O.Options(tol=1e-6))
+    for lpj, r in zip(lps, res):
+        obj, _, _ = highs(lpj)
+        assert r.status == O.OPTIMAL
+        assert abs(r.obj - obj) <= 2e-5 * (1 + abs(obj))
+    # all LPs restart together
+    longest = max(res, key=lambda r: r.iters)
+    for r in res:
+        assert set(r.restarts) == {t for t in longest.restarts if t < r.iters - 1}
