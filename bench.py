@@ -1,0 +1,259 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the batched PDHG library on one MI355X.
+
+Default workload (strong branching, Section 5.1 of the paper): a 2000 x 5000
+constraint matrix with 5 N(0,1) nonzeros per column, 1000 equality and 1000
+<= rows, box [0,10], c ~ N(0,1).  The root LP is solved on the GPU (outside
+the timed region); 32 variables with fractional parts in [0.1, 0.9] give a
+batch of B = 64 bound-changed LPs, each warm-started from the root solution.
+One step = set the batch from device-resident deltas and warm start, solve
+every LP to 1e-4 relative KKT in FP64, copy the solutions to device buffers.
+
+Reported: LPs solved per second (value), the same LPs solved one at a time
+by the same library (plain PDHG, B = 1), the dominant kernel's achieved HBM
+bandwidth against 8 TB/s (HIP events on the library's stream), and the FP64
+reference solver timed on the host cores on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = ("LPs solved/s to 1e-4 rel KKT, batched vs plain PDHG; SpMM HBM GB/s; p99 latency")
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def fused_bytes(kind, m, n, nnz, B, s_val, s_it):
+    """Compulsory HBM bytes of one launch of a fused product + step kernel:
+    the sparse matrix (values + int32 column indices + int32 row pointers),
+    one read of the gathered block, and the streamed per-row blocks.
+      primal (A'Y + primal step): Y gathered (m*B), Xbar and X0 read, Xbar written (3*n*B)
+      dual   (A Xbar + dual step): Xbar gathered (n*B), Y and Y0 read, Y written (3*m*B)"""
+    if kind == 0:
+        return nnz * (s_val + 4) + 4 * (n + 1) + s_it * B * (m + 3 * n)
+    return nnz * (s_val + 4) + 4 * (m + 1) + s_it * B * (n + 3 * m)
+
+
+def cpu_sample(n_lps, workers):
+    """FP64 reference solver on the host cores: its own root solve, then n_lps
+    branch LPs of the same family warm-started from it, one LP per task."""
+    import numpy as np
+    from concurrent.futures import ProcessPoolExecutor
+    import oracle as O
+    from workloads import make_cfg2, choose_fractional, fsb_deltas, seed_for
+    inst = make_cfg2()
+    lp = O.from_instance(inst)
+    eta = O.step_size(lp.A)
+    base = O.solve(lp, O.Options(tol=1e-6, step_size=eta))
+    vars_ = choose_fractional(base.x, n_lps // 2, seed_for(2, 1))
+    D = fsb_deltas(base.x, vars_)
+    tasks = [(int(d["kind"]), int(d["var"]), float(d["value"])) for d in D]
+    t0 = time.perf_counter()
+    with ProcessPoolExecutor(max_workers=workers, initializer=_cpu_init,
+                             initargs=(eta, base.x, base.y, base.w)) as ex:
+        res = list(ex.map(_cpu_task, tasks, chunksize=1))
+    dt = time.perf_counter() - t0
+    solved = sum(1 for s in res if s == O.OPTIMAL)
+    return solved, dt
+
+
+_CPU = {}
+
+
+def _cpu_init(eta, x, y, w):
+    from threadpoolctl import threadpool_limits
+    threadpool_limits(1)          # one thread per worker process
+    import oracle as O
+    from workloads import make_cfg2
+    _CPU["lp"] = O.from_instance(make_cfg2())
+    _CPU.update(eta=eta, x=x, y=y, w=w)
+
+
+def _cpu_task(t):
+    import oracle as O
+    lpj = O.apply_delta(_CPU["lp"], *t)
+    r = O.solve(lpj, O.Options(tol=1e-4, step_size=_CPU["eta"]), x_init=_CPU["x"],
+                y_init=_CPU["y"], w_init=_CPU["w"])
+    return r.status
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-lps", type=int, default=128)
+    ap.add_argument("--plain-lps", type=int, default=64, help="LPs of the batch solved one at a time")
+    ap.add_argument("--graphs", type=int, default=1)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU only; the batch shards by LP columns with no "
+              "communication, so N GPUs give N independent copies of this measurement",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    log("importing torch")
+    import torch
+    import paper_2601_21990_amd.pdlpb as P
+    from workloads import make_cfg2, choose_fractional, fsb_deltas, seed_for, deltas, BASE
+
+    dev = torch.device("cuda:0")
+    torch.cuda.init()
+    inst = make_cfg2()
+    m, n, nnz = inst.m, inst.n, inst.nnz
+    log(f"instance m={m} n={n} nnz={nnz}")
+
+    opts = dict(device=0, use_graphs=args.graphs)
+    ctx = P.Context.from_instance(inst, **opts)
+    eta, norm_a = ctx.step_size
+    log(f"eta={eta:.6g} ||A||={norm_a:.6g}")
+
+    # root LP on the GPU (untimed): the MIP's relaxation solution
+    ctx.set_batch(deltas([BASE], [0], [0.0]))
+    ctx.solve(tol=1e-6, max_iters=200000)
+    root = ctx.get(0)
+    root_w = ctx.get_trace(0)["w"]
+    log(f"root: status={P.STATUS_NAMES[root['status']]} iters={root['iters']} obj={root['obj']:.6f}")
+    vars_ = choose_fractional(root["x"], 32, seed_for(2, 0))
+    D = fsb_deltas(root["x"], vars_)
+    B = len(D)
+
+    # inputs resident in HBM before the timed region
+    d_deltas = torch.from_numpy(D.view(np.uint8).copy()).to(dev)
+    d_x = torch.from_numpy(root["x"]).to(dev)
+    d_y = torch.from_numpy(root["y"]).to(dev)
+    d_w = torch.full((B,), root_w, dtype=torch.float64, device=dev)
+    d_X = torch.empty((B, n), dtype=torch.float64, device=dev)
+    d_Y = torch.empty((B, m), dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+
+    def step():
+        rc = P.lib.pdlpb_set_batch(ctx._h, B, d_deltas.data_ptr(), d_x.data_ptr(), d_y.data_ptr(),
+                                   d_w.data_ptr(), P.WARM_SHARED, P.MEM_DEVICE)
+        ctx._check(rc)
+        ctx.B = B
+        ctx.solve(tol=1e-4, max_iters=100000)
+        return ctx.get_batch(X=d_X, Y=d_Y, mem=P.MEM_DEVICE)
+
+    for i in range(args.warmup):
+        out = step()
+    log(f"warmup done: iters min/median/max = {out['iters'].min()}/{int(np.median(out['iters']))}/"
+        f"{out['iters'].max()}, statuses {np.bincount(out['status'], minlength=6).tolist()}")
+
+    # timed region: K steps, kernel durations taken with HIP events on the library stream
+    ctx.set_kernel_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    solved = 0
+    for i in range(args.steps):
+        out = step()
+        solved += int(np.sum(out["status"] == P.STATUS_OPTIMAL))
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    counts, total_ms = ctx.kernel_times()
+    ctx.set_kernel_timing(False)
+    value = solved / dt
+    log(f"timed: {args.steps} steps in {dt:.4f}s, {solved} LPs solved -> {value:.1f} LPs/s")
+
+    # same steps replayed as captured graphs (no per-launch events)
+    graph_value = None
+    if args.graphs:
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        gs = 0
+        for i in range(args.steps):
+            gs += int(np.sum(step()["status"] == P.STATUS_OPTIMAL))
+        torch.cuda.synchronize()
+        graph_value = gs / (time.perf_counter() - t1)
+        log(f"graph replay: {graph_value:.1f} LPs/s")
+
+    # roofline of the dominant kernel
+    names = ["primal: A'Y + primal step", "dual: A Xbar + dual step", "evaluation", "control"]
+    dom = 0 if total_ms[0] >= total_ms[1] else 1
+    avg_ms = total_ms[dom] / max(counts[dom], 1)
+    q = fused_bytes(dom, m, n, nnz, B, 8, 8)
+    achieved = q / (avg_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+                "kernel": names[dom], "bytes_per_launch": int(q),
+                "avg_launch_us": round(avg_ms * 1e3, 3), "launches": int(counts[dom])}
+    kernel_us = {names[k]: round(total_ms[k] / max(counts[k], 1) * 1e3, 3) for k in range(4)}
+
+    # plain PDHG: the same LPs one at a time (B = 1) with the same library
+    np_plain = min(args.plain_lps, B)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    plain_solved = 0
+    plain_iters = []
+    for j in range(np_plain):
+        rc = P.lib.pdlpb_set_batch(ctx._h, 1, d_deltas.data_ptr() + 16 * j, d_x.data_ptr(),
+                                   d_y.data_ptr(), d_w.data_ptr(), P.WARM_SHARED, P.MEM_DEVICE)
+        ctx._check(rc)
+        ctx.B = 1
+        ctx.solve(tol=1e-4, max_iters=100000)
+        o = ctx.get_batch(X=d_X, Y=d_Y, mem=P.MEM_DEVICE)
+        plain_solved += int(o["status"][0] == P.STATUS_OPTIMAL)
+        plain_iters.append(int(o["iters"][0]))
+    torch.cuda.synchronize()
+    plain_dt = time.perf_counter() - t2
+    plain_value = plain_solved / plain_dt
+    log(f"plain: {np_plain} LPs in {plain_dt:.4f}s -> {plain_value:.1f} LPs/s")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        workers = max(1, min(16, os.cpu_count() or 1))
+        log(f"cpu baseline: reference solver, {args.cpu_lps} LPs on {workers} processes")
+        cs, cdt = cpu_sample(args.cpu_lps, workers)
+        cpu = {"value": round(cs / cdt, 2), "unit": "LPs/s", "cores": workers, "kind": "oracle",
+               "sample": f"{args.cpu_lps} strong-branching LPs of the same 2000x5000 family, "
+                         f"warm-started from the reference solver's own root solve, "
+                         f"one LP per process task; {cs} solved in {cdt:.2f}s"}
+        log(f"cpu: {cpu['value']} LPs/s")
+
+    ctx.close()
+    line = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "LPs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(dt / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "strong-branching batch: A 2000x5000 (5 N(0,1) nnz/col), 1000 E + "
+                               "1000 L rows, box [0,10], B=64 bound changes on 32 fractional "
+                               "variables, warm start from the root LP, FP64, tol 1e-4 rel KKT",
+                   "m": m, "n": n, "nnz": nnz, "B": B, "tol": 1e-4},
+        "plain": {"value": round(plain_value, 2), "unit": "LPs/s", "lps": np_plain,
+                  "iters_median": int(np.median(plain_iters))},
+        "batched_vs_plain": round(value / plain_value, 3) if plain_value > 0 else None,
+        "graph_replay_value": None if graph_value is None else round(graph_value, 2),
+        "iters": {"min": int(out["iters"].min()), "median": int(np.median(out["iters"])),
+                  "max": int(out["iters"].max())},
+        "kernel_avg_us": kernel_us,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

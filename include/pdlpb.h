@@ -1,0 +1,218 @@
+/*
+ * pdlpb.h -- batched restarted PDHG for many LPs that share one constraint
+ * matrix, on AMD Instinct MI355X (gfx950).  C ABI.
+ *
+ * Method: arXiv 2601.21990, "Batched First-Order Methods for Parallel LP
+ * Solving in MIP".  Every LP of a batch is
+ *
+ *     min c_j'x   s.t.   l <= A x <= u,   xl_j <= x <= xu_j        (eq:main_lp, Section 3)
+ *
+ * with A, l, u shared by the whole batch and c_j, xl_j, xu_j equal to the base
+ * vectors except for one change per LP: a raised lower bound or lowered upper
+ * bound of one variable (full strong branching, Section 5.1) or the objective
+ * +-e_var (bound tightening, Section 5.2).  The batch is solved together by the
+ * reflected Halpern PDHG iteration with adaptive restarts (Section 4; batched
+ * form eq:batched_iter and eq:main-iterate, Section 5): each iteration is one
+ * sparse-matrix times dense-block product with A' and one with A, fused with
+ * the per-LP projection, reflection and averaging steps.
+ *
+ * Conventions
+ *   - Row bounds come from a right-hand side b and one sense byte per row:
+ *     'E' (l = u = b), 'L' (A x <= b), 'G' (A x >= b), 'N' (free row).
+ *   - Dual signs follow the paper's saddle function c'x + y'Ax - phi_[l,u](y)
+ *     (eq:lp_saddle): y_i >= 0 on an 'L' row, y_i <= 0 on a 'G' row.
+ *   - Dense vectors of one LP are contiguous float64 arrays (x: n, y: m).
+ *     Per-LP blocks passed or returned for a whole batch are LP-major: LP j
+ *     occupies elements [j*n, (j+1)*n) (resp. [j*m, (j+1)*m)).
+ *   - All pointer arguments are host memory unless a `mem` argument says
+ *     PDLPB_MEM_DEVICE, in which case they are device pointers on the
+ *     context's GPU.  Inputs are copied during the call; the caller keeps
+ *     ownership and may free them on return.  The context owns every device
+ *     buffer it allocates.
+ *   - Every call returns PDLPB_OK (0) or a negative error code and never
+ *     throws.  pdlpb_last_error() describes the last failure.  Solver outcomes
+ *     of single LPs are statuses (PDLPB_STATUS_*), not errors.
+ *   - A context is not thread-safe; distinct contexts may be used from
+ *     distinct threads.
+ */
+#ifndef PDLPB_H
+#define PDLPB_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ---------------------------------------------------- */
+#define PDLPB_OK        0
+#define PDLPB_EINVAL   (-1)   /* malformed argument: bad CSR, NaN data, unknown sense, B <= 0, var out of range */
+#define PDLPB_ENOMEM   (-2)   /* device or host allocation failed, or the batch exceeds the capacity limit */
+#define PDLPB_EDEVICE  (-3)   /* a HIP runtime call failed (no GPU, launch failure, ...) */
+#define PDLPB_ESTATE   (-4)   /* call out of order, e.g. solve before set_batch */
+
+/* ---- per-LP statuses -------------------------------------------------- */
+#define PDLPB_STATUS_RUNNING            0
+#define PDLPB_STATUS_OPTIMAL            1  /* max(gap, primal, dual) <= tol (eq:stopping) at an evaluation */
+#define PDLPB_STATUS_ITERATION_LIMIT    2  /* max_iters applications of T without meeting tol */
+#define PDLPB_STATUS_INFEASIBLE_BOUNDS  3  /* the LP's change crosses its variable bounds (xl > xu); never iterated */
+#define PDLPB_STATUS_NUMERICAL_ERROR    4  /* a NaN or infinity reached the residual or the KKT measures */
+#define PDLPB_STATUS_INVALID_INPUT      5  /* the LP's change carries NaN, or +inf as a lower / -inf as an upper bound */
+
+/* ---- per-LP change ("delta") ------------------------------------------- */
+#define PDLPB_BASE      0   /* the base LP itself */
+#define PDLPB_SET_LO    1   /* xl[var] = value  (branch up: value = ceil(x_rel[var]), Section 5.1) */
+#define PDLPB_SET_HI    2   /* xu[var] = value  (branch down: value = floor(x_rel[var]), Section 5.1) */
+#define PDLPB_OBJ_UNIT  3   /* c = value * e_var (bound tightening: +1 minimises, -1 maximises x_var, Section 5.2) */
+
+typedef struct pdlpb_delta {
+    int32_t kind;      /* PDLPB_BASE / PDLPB_SET_LO / PDLPB_SET_HI / PDLPB_OBJ_UNIT */
+    int32_t var;       /* variable index in [0, n); ignored for PDLPB_BASE */
+    double  value;
+} pdlpb_delta;         /* 16 bytes, no padding */
+
+/* ---- options ----------------------------------------------------------- */
+#define PDLPB_FP64      0   /* A, iterates and products in float64 */
+#define PDLPB_MIXED32   1   /* A (rounded), iterates and products in float32; residual, KKT and restart sums in float64 */
+
+#define PDLPB_RESTART_PER_LP     0  /* each LP applies the restart tests to its own residual */
+#define PDLPB_RESTART_BATCH_AVG  1  /* restart tests on the batch-average residual, all LPs restart together (Section 5) */
+
+#define PDLPB_WARM_NONE    0   /* x = projection of 0 onto the LP's box, y = 0 */
+#define PDLPB_WARM_SHARED  1   /* one x (n) and y (m) for every LP, projected onto each LP's box */
+#define PDLPB_WARM_PER_LP  2   /* LP-major blocks x (B*n) and y (B*m) */
+
+#define PDLPB_MEM_HOST     0
+#define PDLPB_MEM_DEVICE   1
+
+typedef struct pdlpb_options {
+    int32_t struct_size;      /* sizeof(pdlpb_options); set by pdlpb_default_options */
+    int32_t precision;        /* PDLPB_FP64 (default) or PDLPB_MIXED32 */
+    int32_t restart_scope;    /* PDLPB_RESTART_PER_LP (default) or PDLPB_RESTART_BATCH_AVG */
+    int32_t eval_every;       /* C: residual, KKT and restart tests every C iterations (default 64) */
+    double  beta_sufficient;  /* restart when r <= beta_s r0                      (default 0.2)  */
+    double  beta_necessary;   /* ... or r <= beta_n r0 and r grew since last test (default 0.8)  */
+    double  beta_artificial;  /* ... or k > beta_a * iterations so far            (default 0.36) */
+    double  theta;            /* primal-weight smoothing exponent                 (default 0.5)  */
+    double  step_size;        /* eta; 0 (default) computes 0.998 / ||A||_2 (Section 4) */
+    double  cross_sign;       /* sign s of the off-diagonal blocks of the residual metric M (default -1) */
+    int32_t pw_ratio;         /* 0 (default): d = ||dy||/||dx||; 1: d = ||dx||/||dy|| as printed */
+    int32_t device;           /* HIP device ordinal (default 0) */
+    void*   stream;           /* hipStream_t to run on; NULL = a stream owned by the context */
+    int32_t max_batch;        /* largest B accepted by set_batch (default 4096) */
+    int32_t use_graphs;       /* 1 (default): replay each block of C iterations as one captured hipGraph */
+    int32_t tile_lanes;       /* 0 = automatic; else lanes per row group of the fused SpMM kernels (1..64, power of 2) */
+    int32_t tile_vec;         /* 0 = automatic; else columns per lane (1, 2 or 4) */
+    int32_t reserved[8];
+} pdlpb_options;
+
+typedef struct pdlpb_ctx pdlpb_ctx;   /* opaque; owns all device memory of one base matrix and its batch */
+
+/* Fill *opt with the defaults listed above. */
+void pdlpb_default_options(pdlpb_options* opt);
+
+/*
+ * Create a context for one constraint matrix and base LP (eq:main_lp).
+ *   A: m x n in CSR -- row_ptr (m+1 entries, row_ptr[0] = 0, nondecreasing,
+ *      row_ptr[m] = nnz), col_idx (nnz, strictly increasing inside each row,
+ *      in [0, n)), val (nnz, finite).  m >= 0, n >= 1, nnz < 2^31.
+ *   c (n, finite), b (m, finite; unused by 'N' rows), sense (m bytes from
+ *   "ELGN"), l / u (n variable bounds; -inf / +inf allowed, l <= u, NaN not).
+ *   opt: NULL for defaults.
+ * Copies A and A' to the GPU once and computes the step size
+ * eta = 0.998 / ||A||_2 by power iteration (Section 4) unless opt->step_size > 0.
+ * Returns PDLPB_EINVAL (nothing allocated, *out = NULL) on malformed input.
+ */
+int pdlpb_create(pdlpb_ctx** out, int32_t m, int32_t n, int64_t nnz,
+                 const int64_t* row_ptr, const int32_t* col_idx, const double* val,
+                 const double* c, const double* b, const char* sense,
+                 const double* l, const double* u, const pdlpb_options* opt);
+
+/*
+ * Define a batch of B LPs, one change each (Section 5; strong branching 5.1,
+ * bound tightening 5.2).  deltas: B entries.  Warm start per warm_mode:
+ *   NONE: x_warm, y_warm ignored;  SHARED: x_warm (n), y_warm (m);
+ *   PER_LP: x_warm (B*n), y_warm (B*m), LP-major.
+ * w_warm: NULL (initial primal weight ||c_j|| / ||b||, or 1 when either is
+ * below 1e-10), else B initial primal weights (> 0, finite).
+ * mem: PDLPB_MEM_HOST or PDLPB_MEM_DEVICE for deltas, x_warm, y_warm, w_warm.
+ * An LP whose change crosses its bounds gets PDLPB_STATUS_INFEASIBLE_BOUNDS,
+ * one whose change is not a number gets PDLPB_STATUS_INVALID_INPUT; neither
+ * is iterated and neither affects the others.  A kind outside 0..3 or a var
+ * outside [0, n) fails the call with PDLPB_EINVAL.  Device storage grows to
+ * the largest B seen and is reused for smaller batches.
+ */
+int pdlpb_set_batch(pdlpb_ctx* ctx, int32_t B, const pdlpb_delta* deltas,
+                    const double* x_warm, const double* y_warm, const double* w_warm,
+                    int32_t warm_mode, int32_t mem);
+
+/*
+ * Iterate every LP of the current batch until it is OPTIMAL (relative KKT
+ * measure <= tol at an evaluation, eq:stopping), or has applied the PDHG
+ * operator max_iters times (ITERATION_LIMIT), or fails (NUMERICAL_ERROR).
+ * tol >= 0, max_iters >= 1.  All control (restarts, primal weights, statuses)
+ * runs on the GPU; the host only checks once per C iterations whether any LP
+ * is still running.  Returns PDLPB_ESTATE if no batch is set or it was
+ * already solved.
+ */
+int pdlpb_solve(pdlpb_ctx* ctx, double tol, int64_t max_iters);
+
+/*
+ * Results of LP j (0 <= j < B, in set_batch order) after pdlpb_solve.
+ * x (n) and y (m) receive z~ = T(z) of the LP's last iteration, the point at
+ * which the KKT measures are taken; either may be NULL.  kkt receives
+ * {gap, primal, dual, max} (eq:stopping), obj receives c_j'x.  Any output
+ * pointer may be NULL.  mem selects where x and y live.
+ */
+int pdlpb_get(pdlpb_ctx* ctx, int32_t j, double* x, double* y, int32_t* status,
+              double kkt[4], double* obj, int64_t* iters, int32_t mem);
+
+/*
+ * Results of the whole batch at once: X (B*n) and Y (B*m) LP-major, status
+ * (B), kkt (4*B: gap, primal, dual, max per LP), obj (B), iters (B).  Any
+ * pointer may be NULL.  mem applies to X and Y; the per-LP arrays are host.
+ */
+int pdlpb_get_batch(pdlpb_ctx* ctx, double* X, double* Y, int32_t* status, double* kkt,
+                    double* obj, int64_t* iters, int32_t mem);
+
+/*
+ * Diagnostics of LP j: the reflected Halpern iterate z^{k+1} produced by the
+ * LP's last iteration (eq:mainiter) in x_iter (n) / y_iter (m), its final
+ * primal weight w, its number of restarts, and up to log_cap iteration
+ * indices at which it restarted (restart_log).  Any pointer may be NULL.
+ */
+int pdlpb_get_trace(pdlpb_ctx* ctx, int32_t j, double* x_iter, double* y_iter, double* w,
+                    int32_t* restarts, int32_t* restart_log, int32_t log_cap);
+
+/* Step size eta in use and the computed ||A||_2 (0 if eta was given). */
+int pdlpb_get_step_size(const pdlpb_ctx* ctx, double* eta, double* norm_a);
+
+/*
+ * Kernel timing.  While enabled, pdlpb_solve runs without graph replay and
+ * brackets every launch of the fused SpMM kernels with HIP events on the
+ * context's stream.  pdlpb_kernel_times reports, per kind
+ * (0: A'Y + primal step, 1: A X + dual step, 2: evaluation, 3: control),
+ * the number of launches and their summed duration in milliseconds since the
+ * last reset.
+ */
+int pdlpb_set_kernel_timing(pdlpb_ctx* ctx, int32_t enable);
+int pdlpb_kernel_times(pdlpb_ctx* ctx, int64_t counts[4], double total_ms[4]);
+
+/* Bytes of device memory held by the context. */
+int64_t pdlpb_device_bytes(const pdlpb_ctx* ctx);
+
+/* Release every device buffer and the context.  NULL is a no-op. */
+void pdlpb_destroy(pdlpb_ctx* ctx);
+
+/*
+ * Message for the last failed call on ctx, or for the last failed
+ * pdlpb_create on this thread when ctx is NULL.  Never NULL; valid until the
+ * next call on the same context (or thread).
+ */
+const char* pdlpb_last_error(const pdlpb_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PDLPB_H */

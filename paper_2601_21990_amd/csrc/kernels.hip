@@ -1,0 +1,828 @@
+// gfx950 kernels of the batched restarted PDHG solver.
+//
+// Dense blocks are row-major with row stride `ld`: element (row i, LP slot s)
+// lives at i*ld + s, so one row of a block holds that row's entries of every
+// LP of the batch contiguously.  A sparse row's product with a block is then
+// a sum of contiguous row segments of the block, and a group of lanes that
+// covers consecutive slots reads each segment with unit stride.
+//
+// Every lane sums its row's nonzeros sequentially in CSR order, whatever the
+// tile shape, so each LP's arithmetic is independent of how many LPs share the
+// batch and of the tile configuration.  All reductions are fixed-order trees
+// (no atomics), so runs are bitwise reproducible.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "pdlpb.h"
+#include "pdlpb_internal.h"
+
+namespace pdlpb {
+
+namespace {
+
+__device__ __forceinline__ double clampd(double v, double lo, double hi) {
+    return fmax(fmin(v, hi), lo);
+}
+template <typename T>
+__device__ __forceinline__ T clampt(T v, T lo, T hi) {
+    return v > hi ? hi : (v < lo ? lo : v);   // max(min(v, hi), lo)
+}
+
+// Per-LP objective and variable bounds at variable i: the base vectors with
+// the LP's single change applied (strong branching / bound tightening).
+struct VarData {
+    double c, lo, hi;
+};
+__device__ __forceinline__ VarData var_data(const SlotState& st, int32_t i, double c, double lo,
+                                            double hi) {
+    VarData d{c, lo, hi};
+    if (i == st.var) {
+        if (st.kind == PDLPB_SET_LO) d.lo = st.value;
+        else if (st.kind == PDLPB_SET_HI) d.hi = st.value;
+    }
+    if (st.kind == PDLPB_OBJ_UNIT) d.c = (i == st.var) ? st.value : 0.0;
+    return d;
+}
+
+template <typename T, int VEC>
+struct VecT;
+template <typename T>
+struct VecT<T, 1> {
+    __device__ static void load(const T* p, T* out) { out[0] = p[0]; }
+};
+template <>
+struct VecT<double, 2> {
+    __device__ static void load(const double* p, double* out) {
+        const double2 v = *reinterpret_cast<const double2*>(p);
+        out[0] = v.x; out[1] = v.y;
+    }
+};
+template <>
+struct VecT<double, 4> {
+    __device__ static void load(const double* p, double* out) {
+        const double2 v = *reinterpret_cast<const double2*>(p);
+        const double2 w = *reinterpret_cast<const double2*>(p + 2);
+        out[0] = v.x; out[1] = v.y; out[2] = w.x; out[3] = w.y;
+    }
+};
+template <>
+struct VecT<float, 2> {
+    __device__ static void load(const float* p, float* out) {
+        const float2 v = *reinterpret_cast<const float2*>(p);
+        out[0] = v.x; out[1] = v.y;
+    }
+};
+template <>
+struct VecT<float, 4> {
+    __device__ static void load(const float* p, float* out) {
+        const float4 v = *reinterpret_cast<const float4*>(p);
+        out[0] = v.x; out[1] = v.y; out[2] = v.z; out[3] = v.w;
+    }
+};
+
+// Row product of one sparse row with VEC consecutive columns of a block:
+// acc[v] = sum_k a_k * G[col_k, s0 + v], nonzeros in CSR order.
+template <typename T, int VEC>
+__device__ __forceinline__ void row_product(const int32_t* __restrict__ rp,
+                                            const int32_t* __restrict__ ci,
+                                            const T* __restrict__ av, const T* __restrict__ G,
+                                            int32_t row, int32_t ld, int32_t s0, T* acc) {
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) acc[v] = T(0);
+    const int32_t kb = rp[row], ke = rp[row + 1];
+    int32_t k = kb;
+    // two nonzeros per trip so that both gathers are in flight together
+    for (; k + 1 < ke; k += 2) {
+        const int32_t j0 = ci[k], j1 = ci[k + 1];
+        const T a0 = av[k], a1 = av[k + 1];
+        T g0[VEC], g1[VEC];
+        VecT<T, VEC>::load(G + (size_t)j0 * ld + s0, g0);
+        VecT<T, VEC>::load(G + (size_t)j1 * ld + s0, g1);
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) acc[v] = fma(a0, g0[v], acc[v]);
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) acc[v] = fma(a1, g1[v], acc[v]);
+    }
+    if (k < ke) {
+        const int32_t j0 = ci[k];
+        const T a0 = av[k];
+        T g0[VEC];
+        VecT<T, VEC>::load(G + (size_t)j0 * ld + s0, g0);
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) acc[v] = fma(a0, g0[v], acc[v]);
+    }
+}
+
+// Halpern weights of eq:mainiter for inner index k: (k+1)/(k+2) and 1/(k+2).
+__device__ __forceinline__ double halpern_a(int32_t k) { return double(k + 1) / double(k + 2); }
+
+// ---------------------------------------------------------------------------
+// Primal step fused with G = A'Y (Section 5, eq:main-iterate, first line):
+//   x^k  = x0                               if k == 0
+//        = k/(k+1) Xbar + x0/(k+1)          otherwise (the Halpern average of
+//                                           the previous iteration, eq:mainiter)
+//   x~   = Pi_[xl_j, xu_j]( x^k - tau_j (c_j + (A'Y)_j) )
+//   Xbar = 2 x~ - x^k                       (reflection, input of the dual step)
+// Only Xbar is stored between iterations; x^{k+1} is rebuilt from Xbar and the
+// anchor by the next launch, which saves one block write per iteration.
+// ---------------------------------------------------------------------------
+template <typename T, int G, int VEC>
+__global__ __launch_bounds__(256) void k_primal(StepArgs<T> a) {
+    constexpr int RPW = 64 / G;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int32_t row = (blockIdx.x * a.wpb + wave) * RPW + lane / G;
+    const int32_t s0 = blockIdx.y * (G * VEC) + (lane % G) * VEC;
+    if (row >= a.rows || s0 >= a.ncols) return;
+    const int32_t t = a.g->t0 + a.it;
+
+    T acc[VEC];
+    row_product<T, VEC>(a.rp, a.ci, a.av, a.G, row, a.ld, s0, acc);
+
+    const double cb = a.c[row], lb = a.lo[row], hb = a.hi[row];
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) {
+        const int32_t s = s0 + v;
+        if (s >= a.ncols) break;
+        const SlotState st = a.st[s];
+        if (!(st.flags & SLOT_ACTIVE) || t > st.t_end) continue;
+        const size_t e = (size_t)row * a.ld + s;
+        const VarData d = var_data(st, row, cb, lb, hb);
+        const int32_t k = t - st.t_anchor;
+        T xk, x0;
+        if (st.flags & SLOT_FRESH) {           // first iteration after a restart: z = anchor = z~
+            xk = a.Zt[e];
+            x0 = xk;
+            a.Z0[e] = x0;
+        } else if (k == 0) {
+            x0 = a.Z0[e];
+            xk = x0;
+        } else {
+            x0 = a.Z0[e];
+            xk = T(double(k) / double(k + 1)) * a.Z[e] + x0 / T(k + 1);
+        }
+        const T xt = clampt<T>(xk - T(st.tau) * (T(d.c) + acc[v]), T(d.lo), T(d.hi));
+        a.Z[e] = T(2) * xt - xk;
+        if (a.eval || t == st.t_end) {
+            a.Zt[e] = xt;
+            a.DZ[e] = xt - xk;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Dual step fused with V = A Xbar (Section 5, eq:main-iterate, second line):
+//   q   = y^k / sigma_j + V
+//   y~  = sigma_j ( q - Pi_[l,u](q) )        (the printed expression in Moreau order)
+//   y^{k+1} = (k+1)/(k+2) (2 y~ - y^k) + y0/(k+2)   (eq:mainiter)
+// ---------------------------------------------------------------------------
+template <typename T, int G, int VEC>
+__global__ __launch_bounds__(256) void k_dual(StepArgs<T> a) {
+    constexpr int RPW = 64 / G;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int32_t row = (blockIdx.x * a.wpb + wave) * RPW + lane / G;
+    const int32_t s0 = blockIdx.y * (G * VEC) + (lane % G) * VEC;
+    if (row >= a.rows || s0 >= a.ncols) return;
+    const int32_t t = a.g->t0 + a.it;
+
+    T acc[VEC];
+    row_product<T, VEC>(a.rp, a.ci, a.av, a.G, row, a.ld, s0, acc);
+
+    const T l = T(a.lo[row]), u = T(a.hi[row]);
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) {
+        const int32_t s = s0 + v;
+        if (s >= a.ncols) break;
+        const SlotState st = a.st[s];
+        if (!(st.flags & SLOT_ACTIVE) || t > st.t_end) continue;
+        const size_t e = (size_t)row * a.ld + s;
+        const int32_t k = t - st.t_anchor;
+        T yk, y0;
+        if (st.flags & SLOT_FRESH) {
+            yk = a.Zt[e];
+            y0 = yk;
+            a.Z0[e] = y0;
+        } else {
+            yk = a.Z[e];
+            y0 = a.Z0[e];
+        }
+        const T sg = T(st.sigma);
+        const T q = yk / sg + acc[v];
+        const T yt = sg * (q - clampt<T>(q, l, u));
+        a.Z[e] = T(halpern_a(k)) * (T(2) * yt - yk) + y0 / T(k + 2);
+        if (a.eval || t == st.t_end) {
+            a.Zt[e] = yt;
+            a.DZ[e] = yt - yk;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Evaluation: per-LP float64 sums for the fixed-point residual (eq:residual),
+// the stopping measures (eq:stopping) and the primal-weight update.  A block
+// of 4 waves owns a panel of 4*pw rows and 64 slots (one per lane); wave w
+// sums rows [p0 + w*pw, p0 + (w+1)*pw) sequentially, then the four wave sums
+// are added in wave order.  The panel size depends on the row count only, so
+// each LP's sums do not depend on the batch around it.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_eval(EvalArgs<T> a) {
+    __shared__ double red[4][NTERM][64];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int32_t s = blockIdx.y * 64 + lane;
+    const bool xside = (int32_t)blockIdx.x < a.npx;
+    const int32_t panel = xside ? blockIdx.x : blockIdx.x - a.npx;
+    const int32_t pw = xside ? a.pw_x : a.pw_y;
+    const int32_t rows = xside ? a.n : a.m;
+    double acc[NTERM];
+#pragma unroll
+    for (int q = 0; q < NTERM; ++q) acc[q] = 0.0;
+
+    if (s < a.ncols) {
+        const SlotState st = a.st[s];
+        const int32_t r0 = panel * 4 * pw + wave * pw;
+        const int32_t r1 = min(r0 + pw, rows);
+        if (xside) {
+            for (int32_t i = r0; i < r1; ++i) {
+                double g = 0.0;                                   // (A' y~)_i
+                for (int32_t k = a.t_rp[i]; k < a.t_rp[i + 1]; ++k)
+                    g = fma((double)a.t_v[k], (double)a.Yt[(size_t)a.t_ci[k] * a.ld + s], g);
+                const size_t e = (size_t)i * a.ld + s;
+                const double xt = a.Xt[e], dx = a.DX[e], x0 = a.X0[e];
+                const VarData d = var_data(st, i, a.c[i], a.xl[i], a.xu[i]);
+                double rc = -d.c - g;                             // reduced cost, projected on the barrier cone
+                if (isinf(d.lo) && d.lo < 0) rc = fmax(rc, 0.0);
+                if (isinf(d.hi) && d.hi > 0) rc = fmin(rc, 0.0);
+                const double phi = (rc > 0.0 ? d.hi * rc : 0.0) + (rc < 0.0 ? d.lo * rc : 0.0);
+                const double dres = d.c + g + rc;
+                const double ea = xt - x0;
+                acc[0] += dx * dx;
+                acc[1] += d.c * xt;
+                acc[2] += phi;
+                acc[3] += dres * dres;
+                acc[4] += d.c * d.c;
+                acc[5] += ea * ea;
+            }
+        } else {
+            for (int32_t i = r0; i < r1; ++i) {
+                double ax = 0.0, adx = 0.0;                       // (A x~)_i, (A dx)_i
+                for (int32_t k = a.a_rp[i]; k < a.a_rp[i + 1]; ++k) {
+                    const size_t e = (size_t)a.a_ci[k] * a.ld + s;
+                    const double v = (double)a.a_v[k];
+                    ax = fma(v, (double)a.Xt[e], ax);
+                    adx = fma(v, (double)a.DX[e], adx);
+                }
+                const size_t e = (size_t)i * a.ld + s;
+                const double yt = a.Yt[e], dy = a.DY[e], y0 = a.Y0[e];
+                const double l = a.rl[i], u = a.ru[i];
+                const double phi = (yt > 0.0 ? u * yt : 0.0) + (yt < 0.0 ? l * yt : 0.0);
+                const double pres = ax - clampd(ax, l, u);
+                const double ea = yt - y0;
+                acc[0] += dy * dy;
+                acc[1] += dy * adx;
+                acc[2] += phi;
+                acc[3] += pres * pres;
+                acc[4] += ax * ax;
+                acc[5] += ea * ea;
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < NTERM; ++q) red[wave][q][lane] = acc[q];
+    __syncthreads();
+    if (wave == 0 && s < a.ncols) {
+        double* out = (xside ? a.part_x : a.part_y) + (size_t)panel * NTERM * a.ld;
+#pragma unroll
+        for (int q = 0; q < NTERM; ++q) {
+            const double v = ((red[0][q][lane] + red[1][q][lane]) + red[2][q][lane]) + red[3][q][lane];
+            out[(size_t)q * a.ld + s] = v;
+        }
+    }
+}
+
+// sums[q][s] = sum over panels p (in order) of part[p][q][s]; q < NTERM: x side, else y side
+__global__ __launch_bounds__(64) void k_reduce(ControlArgs a) {
+    const int32_t s = blockIdx.x * 64 + threadIdx.x;
+    const int32_t q = blockIdx.y;
+    if (s >= a.ncols) return;
+    const bool xside = q < NTERM;
+    const int32_t qq = xside ? q : q - NTERM;
+    const int32_t np = xside ? a.npx : a.npy;
+    const double* p = (xside ? a.part_x : a.part_y) + (size_t)qq * a.ld + s;
+    const size_t stride = (size_t)NTERM * a.ld;
+    double acc = 0.0;
+    for (int32_t i = 0; i < np; ++i) acc += p[(size_t)i * stride];
+    a.sums[(size_t)q * a.ld + s] = acc;
+}
+
+// ---------------------------------------------------------------------------
+// Control (Section 4: restarts, primal weight, stopping; Section 5: batched
+// restart scope and per-LP stop).  One block; thread s handles slot s.
+// ---------------------------------------------------------------------------
+__device__ bool restart_due(double r, double r0, double r_prev, int32_t k, int32_t t,
+                            const ControlArgs& a) {
+    if (r <= a.beta_s * r0) return true;
+    if (r_prev >= 0.0 && r <= a.beta_n * r0 && r > r_prev) return true;
+    if ((double)k > a.beta_a * (double)t) return true;
+    return false;
+}
+
+__global__ __launch_bounds__(1024) void k_control(ControlArgs a) {
+    __shared__ double sh_r[1024];
+    __shared__ int32_t sh_n[1024];
+    __shared__ int32_t sh_flag;
+    Globals* g = a.g;
+    const int32_t t = g->t0 + a.it;
+    const double eta = g->eta;
+    const double tol = g->tol;
+    int32_t my_active = 0;
+    double my_r = 0.0;
+    int32_t my_part = 0;   // participates in the batch-average residual
+
+    // pass 1: stopping tests and residuals
+    for (int32_t s = threadIdx.x; s < a.ncols; s += blockDim.x) {
+        SlotState& st = a.st[s];
+        SlotCtl& cl = a.ctl[s];
+        if (!(st.flags & SLOT_ACTIVE)) continue;
+        const int32_t k = t - st.t_anchor;
+        const bool final_now = (t >= st.t_end);
+        const double* sx = a.sums;
+        const double* sy = a.sums + (size_t)NTERM * a.ld;
+        const double dx2 = sx[0 * a.ld + s], cx = sx[1 * a.ld + s], phix = sx[2 * a.ld + s];
+        const double dres2 = sx[3 * a.ld + s], c2 = sx[4 * a.ld + s];
+        const double dy2 = sy[0 * a.ld + s], cross = sy[1 * a.ld + s], phiy = sy[2 * a.ld + s];
+        const double pres2 = sy[3 * a.ld + s], ax2 = sy[4 * a.ld + s];
+        const double w = cl.w;
+        // fixed-point residual r(z) = ||T(z) - z||_M (eq:residual, cross-term sign per option)
+        const double q2 = (w / eta) * dx2 + (1.0 / (eta * w)) * dy2 + 2.0 * a.cross_sign * cross;
+        const double r = isfinite(q2) ? sqrt(fmax(q2, 0.0)) : NAN;
+        // stopping measures (eq:stopping)
+        const double phis = phix + phiy;
+        const double gap = isfinite(phis) ? fabs(cx + phis) / (1.0 + fabs(cx) + fabs(phis)) : INFINITY;
+        const double pri = sqrt(pres2) / (1.0 + sqrt(ax2));
+        const double dua = sqrt(dres2) / (1.0 + sqrt(c2));
+        double rel = fmax(gap, fmax(pri, dua));
+        if (isnan(gap) || isnan(pri) || isnan(dua)) rel = NAN;
+        // The LP's last iteration happened at t_last = min(t, t_end); an LP
+        // that ran out of budget before this launch evaluates its final z~.
+        const bool at_eval = (t <= st.t_end);           // this launch evaluates the LP's current iteration
+        const bool full_here = a.full && at_eval;
+        const bool resid_here = at_eval && (a.full || k == 0);
+        int32_t status = PDLPB_STATUS_RUNNING;
+        if ((resid_here && !isfinite(r)) || (full_here && !isfinite(rel))) {
+            status = PDLPB_STATUS_NUMERICAL_ERROR;
+        } else if (full_here && rel <= tol) {
+            status = PDLPB_STATUS_OPTIMAL;
+        } else if (final_now) {
+            status = PDLPB_STATUS_ITERATION_LIMIT;
+        }
+        if (status != PDLPB_STATUS_RUNNING) {
+            const int32_t t_last = t < st.t_end ? t : st.t_end;
+            cl.status = status;
+            cl.kkt[0] = gap; cl.kkt[1] = pri; cl.kkt[2] = dua; cl.kkt[3] = rel;
+            cl.obj = cx;
+            cl.t_last = t_last;
+            cl.iters = t_last - st.t_start + 1;
+            st.flags &= ~(SLOT_ACTIVE | SLOT_FRESH);
+            continue;
+        }
+        my_active += 1;
+        if (resid_here) {
+            my_r += r;          // one slot per thread and pass when ncols <= blockDim
+            my_part += 1;
+        }
+        cl.kkt[0] = gap; cl.kkt[1] = pri; cl.kkt[2] = dua; cl.kkt[3] = rel;
+        cl.obj = cx;
+        if (!a.batch_avg) {
+            // per-LP restart scope
+            if (k == 0) {
+                if (resid_here) {
+                    cl.r0 = r;
+                    cl.r_prev = r;
+                }
+                st.flags &= ~SLOT_FRESH;
+            } else if (a.full) {
+                const int32_t tl = t - st.t_start;
+                if (restart_due(r, cl.r0, cl.r_prev, k, tl, a)) {
+                    const double dxn = sqrt(sx[5 * a.ld + s]);
+                    const double dyn = sqrt(sy[5 * a.ld + s]);
+                    const double num = a.pw_literal ? dxn : dyn;
+                    const double den = a.pw_literal ? dyn : dxn;
+                    double wn = w;
+                    if (num > 1e-10 && den > 1e-10 && isfinite(num) && isfinite(den))
+                        wn = exp(a.theta * log(num / den) + (1.0 - a.theta) * log(w));
+                    cl.w = wn;
+                    st.tau = eta / wn;
+                    st.sigma = eta * wn;
+                    st.t_anchor = t + 1;
+                    st.flags |= SLOT_FRESH;
+                    if (cl.restarts < RESTART_LOG) a.rlog[(size_t)s * RESTART_LOG + cl.restarts] = tl;
+                    cl.restarts += 1;
+                    cl.r_prev = -1.0;
+                } else {
+                    cl.r_prev = r;
+                }
+            }
+        }
+    }
+
+    // batch-average scope: mean residual over running LPs, shared decision
+    if (a.batch_avg) {
+        // each thread holds at most one slot when ncols <= blockDim (checked by the host)
+        sh_r[threadIdx.x] = (my_part ? my_r : 0.0);
+        sh_n[threadIdx.x] = my_part;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double sum = 0.0;
+            int32_t cnt = 0;
+            for (int32_t i = 0; i < (int32_t)blockDim.x; ++i) {
+                if (sh_n[i]) { sum += sh_r[i]; cnt += 1; }
+            }
+            const int32_t k = t - g->batch_k0;
+            int32_t flag = 0;   // 0 nothing, 1 set r0, 2 restart, 3 record r_prev
+            if (cnt > 0) {
+                const double rbar = sum / (double)cnt;
+                if (k == 0) {
+                    g->r0 = rbar;
+                    g->r_prev = rbar;
+                    flag = 1;
+                } else if (a.full) {
+                    // restart tests with the shared cycle; K = t (LPs of one batch start together)
+                    if (restart_due(rbar, g->r0, g->r_prev, k, t, a)) {
+                        flag = 2;
+                        g->batch_k0 = t + 1;
+                        g->r_prev = -1.0;
+                    } else {
+                        g->r_prev = rbar;
+                    }
+                }
+            }
+            sh_flag = flag;
+        }
+        __syncthreads();
+        const int32_t flag = sh_flag;
+        for (int32_t s = threadIdx.x; s < a.ncols; s += blockDim.x) {
+            SlotState& st = a.st[s];
+            SlotCtl& cl = a.ctl[s];
+            if (!(st.flags & SLOT_ACTIVE)) continue;
+            if (flag == 1 || (t - st.t_anchor) == 0) st.flags &= ~SLOT_FRESH;
+            if (flag == 2) {
+                const double* sx = a.sums;
+                const double* sy = a.sums + (size_t)NTERM * a.ld;
+                const double w = cl.w;
+                const double dxn = sqrt(sx[5 * a.ld + s]);
+                const double dyn = sqrt(sy[5 * a.ld + s]);
+                const double num = a.pw_literal ? dxn : dyn;
+                const double den = a.pw_literal ? dyn : dxn;
+                double wn = w;
+                if (num > 1e-10 && den > 1e-10 && isfinite(num) && isfinite(den))
+                    wn = exp(a.theta * log(num / den) + (1.0 - a.theta) * log(w));
+                cl.w = wn;
+                st.tau = eta / wn;
+                st.sigma = eta * wn;
+                st.t_anchor = t + 1;
+                st.flags |= SLOT_FRESH;
+                const int32_t tl = t - st.t_start;
+                if (cl.restarts < RESTART_LOG) a.rlog[(size_t)s * RESTART_LOG + cl.restarts] = tl;
+                cl.restarts += 1;
+            }
+        }
+    }
+
+    // running count (fixed-order block sum) and the block clock
+    sh_n[threadIdx.x] = my_active;
+    __syncthreads();
+    for (int32_t w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int32_t)threadIdx.x < w) sh_n[threadIdx.x] += sh_n[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        g->n_active = sh_n[0];
+        if (a.advance) g->t0 += a.block;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// batch set-up
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_init_blocks(int32_t n, int32_t m, int32_t ld, int32_t ncols,
+                              const SlotState* st, const double* xl, const double* xu,
+                              const double* xw, const double* yw, int32_t mode, T* Xbar, T* X0,
+                              T* Xt, T* DX, T* Y, T* Y0, T* Yt, T* DY) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nx = (int64_t)n * ld, ny = (int64_t)m * ld;
+    if (idx < nx) {
+        const int32_t i = (int32_t)(idx / ld), s = (int32_t)(idx % ld);
+        T x = T(0);
+        if (s < ncols && (st[s].flags & SLOT_ACTIVE)) {
+            const SlotState q = st[s];
+            const VarData d = var_data(q, i, 0.0, xl[i], xu[i]);
+            double w0 = 0.0;
+            if (mode == PDLPB_WARM_SHARED) w0 = xw[i];
+            else if (mode == PDLPB_WARM_PER_LP) w0 = xw[(size_t)s * n + i];
+            // a bound that crosses leaves the slot inactive; keep values finite
+            x = (d.lo <= d.hi) ? T(clampd(w0, d.lo, d.hi)) : T(0);
+        }
+        Xbar[idx] = x;
+        X0[idx] = x;
+        Xt[idx] = x;
+        DX[idx] = T(0);
+    } else if (idx < nx + ny) {
+        const int64_t e = idx - nx;
+        const int32_t i = (int32_t)(e / ld), s = (int32_t)(e % ld);
+        T y = T(0);
+        if (s < ncols && (st[s].flags & SLOT_ACTIVE)) {
+            if (mode == PDLPB_WARM_SHARED) y = T(yw[i]);
+            else if (mode == PDLPB_WARM_PER_LP) y = T(yw[(size_t)s * m + i]);
+        }
+        Y[e] = y;
+        Y0[e] = y;
+        Yt[e] = y;
+        DY[e] = T(0);
+    }
+}
+
+__global__ void k_begin_solve(SlotState* st, SlotCtl* ctl, int32_t ncols, int32_t max_iters,
+                              Globals* g, double tol) {
+    const int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < ncols && (st[s].flags & SLOT_ACTIVE)) {
+        st[s].t_start = 0;
+        st[s].t_anchor = 0;
+        st[s].t_end = max_iters - 1;
+        ctl[s].status = PDLPB_STATUS_RUNNING;
+        ctl[s].restarts = 0;
+        ctl[s].r_prev = -1.0;
+    }
+    if (s == 0) {
+        g->t0 = 0;
+        g->tol = tol;
+        g->batch_k0 = 0;
+        g->r_prev = -1.0;
+        g->n_active = 0;
+    }
+}
+
+template <typename T>
+__global__ void k_gather_column(const T* Z, int32_t rows, int32_t ld, int32_t slot, double* out) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < rows) out[i] = (double)Z[(size_t)i * ld + slot];
+}
+
+template <typename T>
+__global__ void k_transpose_out(const T* Z, int32_t rows, int32_t ld, int32_t ncols, double* out) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)rows * ncols) return;
+    const int32_t s = (int32_t)(idx / rows), i = (int32_t)(idx % rows);
+    out[idx] = (double)Z[(size_t)i * ld + s];
+}
+
+template <typename T>
+__global__ void k_halpern_column(const T* Xbar, const T* X0, int32_t rows, int32_t ld,
+                                 int32_t slot, double a, int32_t kp2, double* out) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < rows) {
+        const size_t e = (size_t)i * ld + slot;
+        out[i] = a * (double)Xbar[e] + (double)X0[e] / (double)kp2;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// power iteration helpers (float64)
+// ---------------------------------------------------------------------------
+__global__ void k_spmv(const int32_t* rp, const int32_t* ci, const double* v, int32_t rows,
+                       const double* x, double* y) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= rows) return;
+    double acc = 0.0;
+    for (int32_t k = rp[i]; k < rp[i + 1]; ++k) acc = fma(v[k], x[ci[k]], acc);
+    y[i] = acc;
+}
+
+constexpr int NORM_BLOCKS = 1024;
+
+__global__ __launch_bounds__(256) void k_norm_partial(const double* x, int32_t len, double* part) {
+    __shared__ double sh[256];
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < len;
+         i += (int64_t)gridDim.x * 256)
+        acc = fma(x[i], x[i], acc);
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ __launch_bounds__(256) void k_norm_final(const double* part, int32_t np, double* out) {
+    __shared__ double sh[256];
+    double acc = 0.0;
+    for (int32_t i = threadIdx.x; i < np; i += 256) acc += part[i];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = sh[0];
+}
+
+__global__ void k_scale(double* x, int32_t len, const double* nrm2sq) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < len) x[i] = x[i] / sqrt(*nrm2sq);
+}
+
+__global__ void k_fill(double* x, int32_t len, double v) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < len) x[i] = v;
+}
+
+template <typename T, int G, int VEC, bool PRIMAL>
+hipError_t launch_step_gv(const StepArgs<T>& a, hipStream_t s) {
+    constexpr int RPW = 64 / G;
+    const int rows_per_block = a.wpb * RPW;
+    const dim3 grid((a.rows + rows_per_block - 1) / rows_per_block,
+                    (a.ncols + G * VEC - 1) / (G * VEC));
+    const dim3 block(64 * a.wpb);
+    if (grid.x == 0 || grid.y == 0) return hipSuccess;
+    if (PRIMAL)
+        hipLaunchKernelGGL((k_primal<T, G, VEC>), grid, block, 0, s, a);
+    else
+        hipLaunchKernelGGL((k_dual<T, G, VEC>), grid, block, 0, s, a);
+    return hipGetLastError();
+}
+
+template <typename T, int VEC, bool PRIMAL>
+hipError_t launch_step_v(const StepArgs<T>& a, int lanes, hipStream_t s) {
+    switch (lanes) {
+        case 1: return launch_step_gv<T, 1, VEC, PRIMAL>(a, s);
+        case 2: return launch_step_gv<T, 2, VEC, PRIMAL>(a, s);
+        case 4: return launch_step_gv<T, 4, VEC, PRIMAL>(a, s);
+        case 8: return launch_step_gv<T, 8, VEC, PRIMAL>(a, s);
+        case 16: return launch_step_gv<T, 16, VEC, PRIMAL>(a, s);
+        case 32: return launch_step_gv<T, 32, VEC, PRIMAL>(a, s);
+        case 64: return launch_step_gv<T, 64, VEC, PRIMAL>(a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T, bool PRIMAL>
+hipError_t launch_step(const StepArgs<T>& a, int lanes, int vec, hipStream_t s) {
+    if (a.wpb < 1 || a.wpb > 4) return hipErrorInvalidValue;
+    if (a.ld % vec != 0) return hipErrorInvalidValue;
+    switch (vec) {
+        case 1: return launch_step_v<T, 1, PRIMAL>(a, lanes, s);
+        case 2: return launch_step_v<T, 2, PRIMAL>(a, lanes, s);
+        case 4: return launch_step_v<T, 4, PRIMAL>(a, lanes, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_primal(const StepArgs<T>& a, int lanes, int vec, hipStream_t s) {
+    return launch_step<T, true>(a, lanes, vec, s);
+}
+template <typename T>
+hipError_t launch_dual(const StepArgs<T>& a, int lanes, int vec, hipStream_t s) {
+    return launch_step<T, false>(a, lanes, vec, s);
+}
+
+template <typename T>
+hipError_t launch_eval(const EvalArgs<T>& a, hipStream_t s) {
+    const dim3 grid(a.npx + a.npy, (a.ncols + 63) / 64);
+    if (grid.x == 0 || grid.y == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_eval<T>, grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce(const ControlArgs& a, hipStream_t s) {
+    const dim3 grid((a.ncols + 63) / 64, 2 * NTERM);
+    if (grid.x == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_reduce, grid, dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_control(const ControlArgs& a, hipStream_t s) {
+    if (a.batch_avg && a.ncols > 1024) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_control, dim3(1), dim3(1024), 0, s, a);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_init_blocks(int32_t n, int32_t m, int32_t ld, int32_t ncols, const SlotState* st,
+                              const double* xl, const double* xu, const double* xw,
+                              const double* yw, int32_t mode, T* Xbar, T* X0, T* Xt, T* DX, T* Y,
+                              T* Y0, T* Yt, T* DY, hipStream_t s) {
+    const int64_t total = (int64_t)(n + m) * ld;
+    if (total == 0) return hipSuccess;
+    const int64_t blocks = (total + 255) / 256;
+    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_init_blocks<T>, dim3((uint32_t)blocks), dim3(256), 0, s, n, m, ld, ncols,
+                       st, xl, xu, xw, yw, mode, Xbar, X0, Xt, DX, Y, Y0, Yt, DY);
+    return hipGetLastError();
+}
+
+hipError_t launch_begin_solve(SlotState* st, SlotCtl* ctl, int32_t ncols, int32_t max_iters,
+                              Globals* g, double tol, hipStream_t s) {
+    const int32_t blocks = (ncols + 255) / 256;
+    hipLaunchKernelGGL(k_begin_solve, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, s, st, ctl,
+                       ncols, max_iters, g, tol);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_gather_column(const T* Z, int32_t rows, int32_t ld, int32_t slot, double* out,
+                                hipStream_t s) {
+    if (rows == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather_column<T>, dim3((rows + 255) / 256), dim3(256), 0, s, Z, rows, ld,
+                       slot, out);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_transpose_out(const T* Z, int32_t rows, int32_t ld, int32_t ncols, double* out,
+                                hipStream_t s) {
+    const int64_t total = (int64_t)rows * ncols;
+    if (total == 0) return hipSuccess;
+    const int64_t blocks = (total + 255) / 256;
+    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_transpose_out<T>, dim3((uint32_t)blocks), dim3(256), 0, s, Z, rows, ld,
+                       ncols, out);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_halpern_column(const T* Xbar, const T* X0, int32_t rows, int32_t ld, int32_t slot,
+                                 double a, int32_t kp2, double* out, hipStream_t s) {
+    if (rows == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_halpern_column<T>, dim3((rows + 255) / 256), dim3(256), 0, s, Xbar, X0,
+                       rows, ld, slot, a, kp2, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_spmv(const int32_t* rp, const int32_t* ci, const double* v, int32_t rows,
+                       const double* x, double* y, hipStream_t s) {
+    if (rows == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_spmv, dim3((rows + 255) / 256), dim3(256), 0, s, rp, ci, v, rows, x, y);
+    return hipGetLastError();
+}
+
+hipError_t launch_norm2sq(const double* x, int32_t len, double* partial, double* out,
+                          hipStream_t s) {
+    int32_t blocks = (len + 255) / 256;
+    if (blocks > NORM_BLOCKS) blocks = NORM_BLOCKS;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_norm_partial, dim3(blocks), dim3(256), 0, s, x, len, partial);
+    hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(256), 0, s, partial, blocks, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale(double* x, int32_t len, const double* nrm2sq, hipStream_t s) {
+    if (len == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_scale, dim3((len + 255) / 256), dim3(256), 0, s, x, len, nrm2sq);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(double* x, int32_t len, double v, hipStream_t s) {
+    if (len == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill, dim3((len + 255) / 256), dim3(256), 0, s, x, len, v);
+    return hipGetLastError();
+}
+
+// explicit instantiations
+template hipError_t launch_primal<double>(const StepArgs<double>&, int, int, hipStream_t);
+template hipError_t launch_primal<float>(const StepArgs<float>&, int, int, hipStream_t);
+template hipError_t launch_dual<double>(const StepArgs<double>&, int, int, hipStream_t);
+template hipError_t launch_dual<float>(const StepArgs<float>&, int, int, hipStream_t);
+template hipError_t launch_eval<double>(const EvalArgs<double>&, hipStream_t);
+template hipError_t launch_eval<float>(const EvalArgs<float>&, hipStream_t);
+template hipError_t launch_init_blocks<double>(int32_t, int32_t, int32_t, int32_t, const SlotState*,
+                                               const double*, const double*, const double*,
+                                               const double*, int32_t, double*, double*, double*,
+                                               double*, double*, double*, double*, double*,
+                                               hipStream_t);
+template hipError_t launch_init_blocks<float>(int32_t, int32_t, int32_t, int32_t, const SlotState*,
+                                              const double*, const double*, const double*,
+                                              const double*, int32_t, float*, float*, float*, float*,
+                                              float*, float*, float*, float*, hipStream_t);
+template hipError_t launch_gather_column<double>(const double*, int32_t, int32_t, int32_t, double*,
+                                                 hipStream_t);
+template hipError_t launch_gather_column<float>(const float*, int32_t, int32_t, int32_t, double*,
+                                                hipStream_t);
+template hipError_t launch_transpose_out<double>(const double*, int32_t, int32_t, int32_t, double*,
+                                                 hipStream_t);
+template hipError_t launch_transpose_out<float>(const float*, int32_t, int32_t, int32_t, double*,
+                                                hipStream_t);
+template hipError_t launch_halpern_column<double>(const double*, const double*, int32_t, int32_t,
+                                                  int32_t, double, int32_t, double*, hipStream_t);
+template hipError_t launch_halpern_column<float>(const float*, const float*, int32_t, int32_t,
+                                                 int32_t, double, int32_t, double*, hipStream_t);
+
+}  // namespace pdlpb

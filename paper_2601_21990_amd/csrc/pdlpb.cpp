@@ -1,0 +1,963 @@
+// C ABI of the batched restarted PDHG solver: argument validation, device
+// memory, the step size, batch set-up, the host loop that replays blocks of C
+// iterations, and result retrieval.  All arithmetic of an iteration runs in
+// the kernels of kernels.hip; the host only checks, once per block, whether any
+// LP is still running.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "pdlpb.h"
+#include "pdlpb_internal.h"
+
+using namespace pdlpb;
+
+namespace {
+
+thread_local std::string g_create_error = "no error";
+
+int32_t next_pow2(int64_t v) {
+    int32_t p = 1;
+    while (p < v && p < (1 << 30)) p <<= 1;
+    return p;
+}
+
+// rows per wave of the evaluation kernel: the panel size depends on the row
+// count only (so each LP's sums are independent of the batch), with at most
+// 2048 panels per side
+int32_t eval_rows_per_wave(int32_t rows) {
+    int32_t pw = 4;
+    while ((int64_t)(rows + 4 * pw - 1) / (4 * pw) > 2048) pw *= 2;
+    return pw;
+}
+
+}  // namespace
+
+struct pdlpb_ctx {
+    std::string err = "no error";
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    pdlpb_options opt{};
+    int32_t m = 0, n = 0;
+    int64_t nnz = 0;
+    bool fp32 = false;
+
+    // matrix and base vectors on the device
+    int32_t *a_rp = nullptr, *a_ci = nullptr, *t_rp = nullptr, *t_ci = nullptr;
+    double *a_v64 = nullptr, *t_v64 = nullptr;
+    float *a_v32 = nullptr, *t_v32 = nullptr;
+    double *c = nullptr, *xl = nullptr, *xu = nullptr, *rl = nullptr, *ru = nullptr;
+
+    // host copies used by set_batch
+    std::vector<double> h_xl, h_xu;
+    double norm_c = 0.0, norm_b = 0.0;
+    double eta = 0.0, norm_a = 0.0;
+
+    // batch storage
+    int32_t B = 0, ld = 0;
+    int lanes = 64, vec = 1, wpb = 4;
+    size_t cap_block_bytes = 0;     // bytes of each of the 8 dense blocks
+    void* blk[8] = {};              // Xbar, X0, Xt, DX, Y, Y0, Yt, DY
+    int32_t cap_slots = 0;
+    SlotState* st = nullptr;
+    SlotCtl* ctl = nullptr;
+    int32_t* rlog = nullptr;
+    Globals* g = nullptr;
+    size_t cap_part = 0;            // doubles in part (x and y) + sums
+    double* part = nullptr;
+    int32_t pw_x = 4, pw_y = 4, npx = 0, npy = 0;
+    size_t cap_stage = 0;
+    double* stage = nullptr;        // staging for warm starts and results
+    double* pow_buf = nullptr;      // power iteration scratch
+    int32_t* h_pinned = nullptr;    // n_active read-back
+
+    // state
+    bool batch_set = false;
+    bool solved = false;
+    std::vector<SlotState> h_st;
+    std::vector<SlotCtl> h_ctl;
+    std::vector<int32_t> h_rlog;
+
+    // epoch graph
+    hipGraphExec_t graph = nullptr;
+    bool graph_valid = false;
+
+    // kernel timing
+    bool timing = false;
+    int64_t t_counts[4] = {0, 0, 0, 0};
+    double t_ms[4] = {0, 0, 0, 0};
+    std::vector<hipEvent_t> ev;
+
+    int64_t dev_bytes = 0;
+
+    // ------------------------------------------------------------------
+    int fail(int code, const std::string& msg) {
+        err = msg;
+        return code;
+    }
+    int hip_fail(hipError_t e, const char* what) {
+        err = std::string(what) + ": " + hipGetErrorString(e);
+        return PDLPB_EDEVICE;
+    }
+    template <typename P>
+    hipError_t alloc(P** p, size_t bytes) {
+        if (bytes == 0) bytes = 256;
+        void* q = nullptr;
+        hipError_t e = hipMalloc(&q, bytes);
+        if (e == hipSuccess) {
+            *p = static_cast<P*>(q);
+            dev_bytes += (int64_t)bytes;
+        }
+        return e;
+    }
+    template <typename P>
+    void release(P*& p, size_t bytes) {
+        if (p) {
+            (void)hipFree((void*)p);
+            dev_bytes -= (int64_t)(bytes == 0 ? 256 : bytes);
+        }
+        p = nullptr;
+    }
+    void drop_graph() {
+        if (graph) (void)hipGraphExecDestroy(graph);
+        graph = nullptr;
+        graph_valid = false;
+    }
+};
+
+#define HIP_TRY(ctx, call)                                    \
+    do {                                                      \
+        hipError_t e_ = (call);                               \
+        if (e_ != hipSuccess) return (ctx)->hip_fail(e_, #call); \
+    } while (0)
+
+namespace {
+
+void free_all(pdlpb_ctx* x) {
+    if (!x) return;
+    (void)hipSetDevice(x->device);
+    if (x->stream) (void)hipStreamSynchronize(x->stream);
+    x->drop_graph();
+    for (auto e : x->ev) (void)hipEventDestroy(e);
+    x->ev.clear();
+    void* ptrs[] = {x->a_rp, x->a_ci, x->t_rp, x->t_ci, x->a_v64, x->t_v64, x->a_v32, x->t_v32,
+                    x->c, x->xl, x->xu, x->rl, x->ru, x->st, x->ctl, x->rlog, x->g, x->part,
+                    x->stage, x->pow_buf};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+    for (void*& p : x->blk)
+        if (p) {
+            (void)hipFree(p);
+            p = nullptr;
+        }
+    if (x->h_pinned) (void)hipHostFree(x->h_pinned);
+    if (x->own_stream && x->stream) (void)hipStreamDestroy(x->stream);
+    delete x;
+}
+
+// ---- step size: power iteration on A'A (float64, on the device) -------------
+// ||A||_2 = sqrt(lambda_max(A'A)); start from the normalised all-ones vector,
+// stop when the eigenvalue estimate changes by at most 1e-14 relative, or after
+// 10^4 products.  Estimates are read back 32 iterations at a time.
+int compute_opnorm(pdlpb_ctx* x, double* out) {
+    const int32_t n = x->n, m = x->m;
+    if (x->nnz == 0 || n == 0) {
+        *out = 0.0;
+        return PDLPB_OK;
+    }
+    constexpr int CH = 32;
+    const size_t need = (size_t)n * 2 + (size_t)m + 1024 + CH;
+    HIP_TRY(x, x->alloc(&x->pow_buf, need * sizeof(double)));
+    double* v = x->pow_buf;
+    double* w = v + n;
+    double* tmp = w + n;
+    double* part = tmp + m;
+    double* lam2 = part + 1024;   // CH estimates of lambda^2
+    HIP_TRY(x, launch_fill(v, n, 1.0 / std::sqrt((double)n), x->stream));
+    double lam_old = 0.0;
+    double lam = 0.0;
+    std::vector<double> h(CH);
+    for (int it0 = 0; it0 < 10000; it0 += CH) {
+        for (int j = 0; j < CH; ++j) {
+            HIP_TRY(x, launch_spmv(x->a_rp, x->a_ci, x->a_v64, m, v, tmp, x->stream));
+            HIP_TRY(x, launch_spmv(x->t_rp, x->t_ci, x->t_v64, n, tmp, w, x->stream));
+            HIP_TRY(x, launch_norm2sq(w, n, part, lam2 + j, x->stream));
+            HIP_TRY(x, launch_scale(w, n, lam2 + j, x->stream));
+            std::swap(v, w);
+        }
+        HIP_TRY(x, hipMemcpyAsync(h.data(), lam2, CH * sizeof(double), hipMemcpyDeviceToHost,
+                                  x->stream));
+        HIP_TRY(x, hipStreamSynchronize(x->stream));
+        for (int j = 0; j < CH && it0 + j < 10000; ++j) {
+            lam = std::sqrt(h[j]);
+            if (lam == 0.0) {
+                *out = 0.0;
+                return PDLPB_OK;
+            }
+            if (std::fabs(lam - lam_old) <= 1e-14 * lam) {
+                *out = std::sqrt(lam);
+                return PDLPB_OK;
+            }
+            lam_old = lam;
+        }
+    }
+    *out = std::sqrt(lam);
+    return PDLPB_OK;
+}
+
+// default tile: each row group of `lanes` lanes covers lanes*vec consecutive slots
+void choose_tile(pdlpb_ctx* x, int32_t B) {
+    int vec = 1;
+    if (x->fp32) vec = B >= 256 ? 4 : (B >= 128 ? 2 : 1);
+    else vec = B >= 128 ? 2 : 1;
+    if (x->opt.tile_vec > 0) vec = x->opt.tile_vec;
+    int lanes = next_pow2((B + vec - 1) / vec);
+    if (lanes > 64) lanes = 64;
+    if (x->opt.tile_lanes > 0) lanes = x->opt.tile_lanes;
+    x->vec = vec;
+    x->lanes = lanes;
+    x->wpb = 4;
+}
+
+template <typename T>
+StepArgs<T> step_args(pdlpb_ctx* x, bool primal, int32_t it, int32_t eval) {
+    StepArgs<T> a{};
+    T* const* b = reinterpret_cast<T* const*>(x->blk);
+    const T* av = nullptr;
+    if constexpr (sizeof(T) == 8) av = reinterpret_cast<const T*>(primal ? x->t_v64 : x->a_v64);
+    else av = reinterpret_cast<const T*>(primal ? x->t_v32 : x->a_v32);
+    a.rp = primal ? x->t_rp : x->a_rp;
+    a.ci = primal ? x->t_ci : x->a_ci;
+    a.av = av;
+    a.rows = primal ? x->n : x->m;
+    a.ld = x->ld;
+    a.ncols = x->B;
+    a.wpb = x->wpb;
+    if (primal) {
+        a.G = b[4];   // Y
+        a.Z = b[0]; a.Z0 = b[1]; a.Zt = b[2]; a.DZ = b[3];
+        a.c = x->c; a.lo = x->xl; a.hi = x->xu;
+    } else {
+        a.G = b[0];   // Xbar
+        a.Z = b[4]; a.Z0 = b[5]; a.Zt = b[6]; a.DZ = b[7];
+        a.c = nullptr; a.lo = x->rl; a.hi = x->ru;
+    }
+    a.st = x->st;
+    a.g = x->g;
+    a.it = it;
+    a.eval = eval;
+    return a;
+}
+
+template <typename T>
+EvalArgs<T> eval_args(pdlpb_ctx* x) {
+    EvalArgs<T> a{};
+    T* const* b = reinterpret_cast<T* const*>(x->blk);
+    a.n = x->n; a.m = x->m; a.ld = x->ld; a.ncols = x->B;
+    a.a_rp = x->a_rp; a.a_ci = x->a_ci;
+    a.t_rp = x->t_rp; a.t_ci = x->t_ci;
+    if constexpr (sizeof(T) == 8) {
+        a.a_v = reinterpret_cast<const T*>(x->a_v64);
+        a.t_v = reinterpret_cast<const T*>(x->t_v64);
+    } else {
+        a.a_v = reinterpret_cast<const T*>(x->a_v32);
+        a.t_v = reinterpret_cast<const T*>(x->t_v32);
+    }
+    a.Xt = b[2]; a.DX = b[3]; a.X0 = b[1];
+    a.Yt = b[6]; a.DY = b[7]; a.Y0 = b[5];
+    a.c = x->c; a.xl = x->xl; a.xu = x->xu; a.rl = x->rl; a.ru = x->ru;
+    a.st = x->st;
+    a.pw_x = x->pw_x; a.pw_y = x->pw_y; a.npx = x->npx; a.npy = x->npy;
+    a.part_x = x->part;
+    a.part_y = x->part + (size_t)x->npx * NTERM * x->ld;
+    return a;
+}
+
+ControlArgs control_args(pdlpb_ctx* x, int32_t it, int32_t full, int32_t advance) {
+    ControlArgs a{};
+    a.ncols = x->B; a.ld = x->ld; a.npx = x->npx; a.npy = x->npy;
+    a.part_x = x->part;
+    a.part_y = x->part + (size_t)x->npx * NTERM * x->ld;
+    a.sums = x->part + (size_t)(x->npx + x->npy) * NTERM * x->ld;
+    a.st = x->st; a.ctl = x->ctl; a.rlog = x->rlog; a.g = x->g;
+    a.it = it; a.full = full; a.advance = advance; a.block = x->opt.eval_every;
+    a.batch_avg = x->opt.restart_scope == PDLPB_RESTART_BATCH_AVG;
+    a.pw_literal = x->opt.pw_ratio == 1;
+    a.beta_s = x->opt.beta_sufficient; a.beta_n = x->opt.beta_necessary;
+    a.beta_a = x->opt.beta_artificial; a.theta = x->opt.theta; a.cross_sign = x->opt.cross_sign;
+    return a;
+}
+
+// event pair index for a timed launch
+int timed_begin(pdlpb_ctx* x, int kind, std::vector<std::pair<int, int>>& rec) {
+    const int idx = (int)rec.size();
+    while ((int)x->ev.size() < 2 * (idx + 1)) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return -1;
+        x->ev.push_back(e);
+    }
+    rec.push_back({kind, idx});
+    (void)hipEventRecord(x->ev[2 * idx], x->stream);
+    return idx;
+}
+
+template <typename T>
+int enqueue_iteration(pdlpb_ctx* x, int32_t it, int32_t eval,
+                      std::vector<std::pair<int, int>>* rec) {
+    StepArgs<T> p = step_args<T>(x, true, it, eval);
+    StepArgs<T> d = step_args<T>(x, false, it, eval);
+    int idx = -1;
+    if (rec) idx = timed_begin(x, 0, *rec);
+    HIP_TRY(x, launch_primal<T>(p, x->lanes, x->vec, x->stream));
+    if (rec && idx >= 0) (void)hipEventRecord(x->ev[2 * idx + 1], x->stream);
+    if (rec) idx = timed_begin(x, 1, *rec);
+    HIP_TRY(x, launch_dual<T>(d, x->lanes, x->vec, x->stream));
+    if (rec && idx >= 0) (void)hipEventRecord(x->ev[2 * idx + 1], x->stream);
+    return PDLPB_OK;
+}
+
+template <typename T>
+int enqueue_evaluation(pdlpb_ctx* x, int32_t it, int32_t full, int32_t advance,
+                       std::vector<std::pair<int, int>>* rec) {
+    EvalArgs<T> e = eval_args<T>(x);
+    ControlArgs c = control_args(x, it, full, advance);
+    int idx = -1;
+    if (rec) idx = timed_begin(x, 2, *rec);
+    HIP_TRY(x, launch_eval<T>(e, x->stream));
+    if (rec && idx >= 0) (void)hipEventRecord(x->ev[2 * idx + 1], x->stream);
+    if (rec) idx = timed_begin(x, 3, *rec);
+    HIP_TRY(x, launch_reduce(c, x->stream));
+    HIP_TRY(x, launch_control(c, x->stream));
+    if (rec && idx >= 0) (void)hipEventRecord(x->ev[2 * idx + 1], x->stream);
+    return PDLPB_OK;
+}
+
+// one block of C iterations: t = t0+1 .. t0+C; residual of fresh cycles at the
+// first, full evaluation (KKT, restarts) at the last
+template <typename T>
+int enqueue_epoch(pdlpb_ctx* x, std::vector<std::pair<int, int>>* rec) {
+    const int32_t C = x->opt.eval_every;
+    for (int32_t it = 1; it <= C; ++it) {
+        const int32_t ev = (it == 1 || it == C) ? 1 : 0;
+        int rc = enqueue_iteration<T>(x, it, ev, rec);
+        if (rc) return rc;
+        if (it == C) rc = enqueue_evaluation<T>(x, it, 1, 1, rec);
+        else if (it == 1) rc = enqueue_evaluation<T>(x, it, 0, 0, rec);
+        if (rc) return rc;
+    }
+    return PDLPB_OK;
+}
+
+template <typename T>
+int run_solve(pdlpb_ctx* x, double tol, int32_t max_iters) {
+    HIP_TRY(x, launch_begin_solve(x->st, x->ctl, x->B, max_iters, x->g, tol, x->stream));
+    std::vector<std::pair<int, int>> rec;
+    std::vector<std::pair<int, int>>* prec = x->timing ? &rec : nullptr;
+    auto harvest = [&]() {
+        for (auto& r : rec) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, x->ev[2 * r.second], x->ev[2 * r.second + 1]) ==
+                hipSuccess) {
+                x->t_counts[r.first] += 1;
+                x->t_ms[r.first] += ms;
+            }
+        }
+        rec.clear();
+    };
+    // prologue: t = 0 is a full evaluation
+    int rc = enqueue_iteration<T>(x, 0, 1, prec);
+    if (!rc) rc = enqueue_evaluation<T>(x, 0, 1, 0, prec);
+    if (rc) return rc;
+    HIP_TRY(x, hipMemcpyAsync(x->h_pinned, &x->g->n_active, sizeof(int32_t),
+                              hipMemcpyDeviceToHost, x->stream));
+    HIP_TRY(x, hipStreamSynchronize(x->stream));
+    if (prec) harvest();
+    const bool graphs = x->opt.use_graphs && !x->timing;
+    const int64_t max_epochs = (int64_t)max_iters / x->opt.eval_every + 2;
+    for (int64_t ep = 0; *x->h_pinned > 0; ++ep) {
+        if (ep > max_epochs) return x->fail(PDLPB_EDEVICE, "solve did not terminate");
+        if (graphs) {
+            if (!x->graph_valid) {
+                x->drop_graph();
+                hipGraph_t gr = nullptr;
+                HIP_TRY(x, hipStreamBeginCapture(x->stream, hipStreamCaptureModeThreadLocal));
+                int r2 = enqueue_epoch<T>(x, nullptr);
+                hipError_t e = hipStreamEndCapture(x->stream, &gr);
+                if (r2) {
+                    if (gr) (void)hipGraphDestroy(gr);
+                    return r2;
+                }
+                if (e != hipSuccess) return x->hip_fail(e, "hipStreamEndCapture");
+                e = hipGraphInstantiate(&x->graph, gr, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(gr);
+                if (e != hipSuccess) return x->hip_fail(e, "hipGraphInstantiate");
+                x->graph_valid = true;
+            }
+            HIP_TRY(x, hipGraphLaunch(x->graph, x->stream));
+        } else {
+            rc = enqueue_epoch<T>(x, prec);
+            if (rc) return rc;
+        }
+        HIP_TRY(x, hipMemcpyAsync(x->h_pinned, &x->g->n_active, sizeof(int32_t),
+                                  hipMemcpyDeviceToHost, x->stream));
+        HIP_TRY(x, hipStreamSynchronize(x->stream));
+        if (prec) harvest();
+    }
+    return PDLPB_OK;
+}
+
+int fetch_state(pdlpb_ctx* x) {
+    x->h_st.resize(x->B);
+    x->h_ctl.resize(x->B);
+    x->h_rlog.resize((size_t)x->B * RESTART_LOG);
+    HIP_TRY(x, hipMemcpyAsync(x->h_st.data(), x->st, sizeof(SlotState) * x->B,
+                              hipMemcpyDeviceToHost, x->stream));
+    HIP_TRY(x, hipMemcpyAsync(x->h_ctl.data(), x->ctl, sizeof(SlotCtl) * x->B,
+                              hipMemcpyDeviceToHost, x->stream));
+    HIP_TRY(x, hipMemcpyAsync(x->h_rlog.data(), x->rlog, sizeof(int32_t) * RESTART_LOG * x->B,
+                              hipMemcpyDeviceToHost, x->stream));
+    HIP_TRY(x, hipStreamSynchronize(x->stream));
+    return PDLPB_OK;
+}
+
+int ensure_stage(pdlpb_ctx* x, size_t doubles) {
+    if (doubles <= x->cap_stage) return PDLPB_OK;
+    x->release(x->stage, x->cap_stage * sizeof(double));
+    x->cap_stage = 0;
+    HIP_TRY(x, x->alloc(&x->stage, doubles * sizeof(double)));
+    x->cap_stage = doubles;
+    return PDLPB_OK;
+}
+
+bool finite_all(const double* p, int64_t len) {
+    for (int64_t i = 0; i < len; ++i)
+        if (!std::isfinite(p[i])) return false;
+    return true;
+}
+
+}  // namespace
+
+// ===========================================================================
+extern "C" {
+
+void pdlpb_default_options(pdlpb_options* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->struct_size = (int32_t)sizeof(pdlpb_options);
+    o->precision = PDLPB_FP64;
+    o->restart_scope = PDLPB_RESTART_PER_LP;
+    o->eval_every = 64;
+    o->beta_sufficient = 0.2;
+    o->beta_necessary = 0.8;
+    o->beta_artificial = 0.36;
+    o->theta = 0.5;
+    o->step_size = 0.0;
+    o->cross_sign = -1.0;
+    o->pw_ratio = 0;
+    o->device = 0;
+    o->stream = nullptr;
+    o->max_batch = 4096;
+    o->use_graphs = 1;
+    o->tile_lanes = 0;
+    o->tile_vec = 0;
+}
+
+int pdlpb_create(pdlpb_ctx** out, int32_t m, int32_t n, int64_t nnz, const int64_t* row_ptr,
+                 const int32_t* col_idx, const double* val, const double* c, const double* b,
+                 const char* sense, const double* l, const double* u, const pdlpb_options* opt) {
+    auto bad = [](const std::string& s) {
+        g_create_error = s;
+        return PDLPB_EINVAL;
+    };
+    if (!out) return bad("out is NULL");
+    *out = nullptr;
+    pdlpb_options o;
+    pdlpb_default_options(&o);
+    if (opt) {
+        if (opt->struct_size != (int32_t)sizeof(pdlpb_options))
+            return bad("options.struct_size does not match this library");
+        o = *opt;
+    }
+    if (m < 0 || n < 1) return bad("need m >= 0 and n >= 1");
+    if (nnz < 0 || nnz >= ((int64_t)1 << 31)) return bad("nnz must be in [0, 2^31)");
+    if (!row_ptr || !c || !l || !u || (m > 0 && (!b || !sense)) ||
+        (nnz > 0 && (!col_idx || !val)))
+        return bad("NULL input array");
+    if (o.precision != PDLPB_FP64 && o.precision != PDLPB_MIXED32) return bad("unknown precision");
+    if (o.restart_scope != PDLPB_RESTART_PER_LP && o.restart_scope != PDLPB_RESTART_BATCH_AVG)
+        return bad("unknown restart scope");
+    if (o.eval_every < 2 || o.eval_every > 4096) return bad("eval_every must be in [2, 4096]");
+    if (!(o.beta_sufficient >= 0 && o.beta_necessary >= 0 && o.beta_artificial >= 0 &&
+          o.theta >= 0 && o.theta <= 1))
+        return bad("restart parameters out of range");
+    if (!(o.step_size >= 0.0) || !std::isfinite(o.step_size)) return bad("step_size must be >= 0");
+    if (o.cross_sign != -1.0 && o.cross_sign != 1.0) return bad("cross_sign must be -1 or +1");
+    if (o.max_batch < 1 || o.max_batch > (1 << 20)) return bad("max_batch out of range");
+    if (o.restart_scope == PDLPB_RESTART_BATCH_AVG && o.max_batch > 1024) o.max_batch = 1024;
+    if (o.tile_lanes != 0 && (o.tile_lanes < 1 || o.tile_lanes > 64 ||
+                              (o.tile_lanes & (o.tile_lanes - 1))))
+        return bad("tile_lanes must be 0 or a power of two in [1, 64]");
+    if (o.tile_vec != 0 && o.tile_vec != 1 && o.tile_vec != 2 && o.tile_vec != 4)
+        return bad("tile_vec must be 0, 1, 2 or 4");
+    // CSR structure
+    if (row_ptr[0] != 0) return bad("row_ptr[0] must be 0");
+    for (int32_t i = 0; i < m; ++i) {
+        if (row_ptr[i + 1] < row_ptr[i]) return bad("row_ptr must be nondecreasing");
+        for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
+            if (k >= nnz) return bad("row_ptr exceeds nnz");
+            if (col_idx[k] < 0 || col_idx[k] >= n) return bad("column index out of range");
+            if (k > row_ptr[i] && col_idx[k] <= col_idx[k - 1])
+                return bad("column indices must be strictly increasing within a row");
+        }
+    }
+    if (row_ptr[m] != nnz) return bad("row_ptr[m] must equal nnz");
+    if (!finite_all(val, nnz)) return bad("matrix values must be finite");
+    if (!finite_all(c, n)) return bad("objective must be finite");
+    if (m > 0 && !finite_all(b, m)) return bad("right-hand side must be finite");
+    std::vector<double> rl(m), ru(m);
+    for (int32_t i = 0; i < m; ++i) {
+        switch (sense[i]) {
+            case 'E': rl[i] = b[i]; ru[i] = b[i]; break;
+            case 'L': rl[i] = -INFINITY; ru[i] = b[i]; break;
+            case 'G': rl[i] = b[i]; ru[i] = INFINITY; break;
+            case 'N': rl[i] = -INFINITY; ru[i] = INFINITY; break;
+            default: return bad(std::string("unknown row sense '") + sense[i] + "'");
+        }
+    }
+    for (int32_t j = 0; j < n; ++j) {
+        if (std::isnan(l[j]) || std::isnan(u[j])) return bad("variable bounds must not be NaN");
+        if (l[j] == INFINITY || u[j] == -INFINITY) return bad("infinite bound on the wrong side");
+        if (l[j] > u[j]) return bad("variable lower bound above upper bound");
+    }
+
+    pdlpb_ctx* x = new (std::nothrow) pdlpb_ctx();
+    if (!x) {
+        g_create_error = "out of host memory";
+        return PDLPB_ENOMEM;
+    }
+    x->opt = o;
+    x->m = m;
+    x->n = n;
+    x->nnz = nnz;
+    x->fp32 = o.precision == PDLPB_MIXED32;
+    x->device = o.device;
+    auto dev_fail = [&](hipError_t e, const char* what) {
+        g_create_error = std::string(what) + ": " + hipGetErrorString(e);
+        free_all(x);
+        return PDLPB_EDEVICE;
+    };
+    hipError_t e = hipSetDevice(o.device);
+    if (e != hipSuccess) return dev_fail(e, "hipSetDevice");
+    if (o.stream) {
+        x->stream = static_cast<hipStream_t>(o.stream);
+    } else {
+        e = hipStreamCreateWithFlags(&x->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) return dev_fail(e, "hipStreamCreate");
+        x->own_stream = true;
+    }
+    e = hipHostMalloc((void**)&x->h_pinned, sizeof(int32_t) * 4, hipHostMallocDefault);
+    if (e != hipSuccess) return dev_fail(e, "hipHostMalloc");
+
+    // A' in CSR (= A in CSC): counting sort by column keeps row order inside each column
+    std::vector<int32_t> h_arp(m + 1), h_trp(n + 1, 0), h_tci(nnz);
+    std::vector<double> h_tv(nnz);
+    for (int32_t i = 0; i <= m; ++i) h_arp[i] = (int32_t)row_ptr[i];
+    for (int64_t k = 0; k < nnz; ++k) h_trp[col_idx[k] + 1] += 1;
+    for (int32_t j = 0; j < n; ++j) h_trp[j + 1] += h_trp[j];
+    {
+        std::vector<int32_t> pos(h_trp.begin(), h_trp.end() - 1);
+        for (int32_t i = 0; i < m; ++i)
+            for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
+                const int32_t p = pos[col_idx[k]]++;
+                h_tci[p] = i;
+                h_tv[p] = val[k];
+            }
+    }
+    auto up = [&](auto** dst, const auto* src, size_t count) -> hipError_t {
+        using E = std::remove_pointer_t<std::remove_reference_t<decltype(*dst)>>;
+        hipError_t r = x->alloc(dst, count * sizeof(E));
+        if (r != hipSuccess) return r;
+        if (count == 0) return hipSuccess;
+        return hipMemcpy(*dst, src, count * sizeof(E), hipMemcpyHostToDevice);
+    };
+    if ((e = up(&x->a_rp, h_arp.data(), h_arp.size())) != hipSuccess) return dev_fail(e, "upload A");
+    if ((e = up(&x->a_ci, col_idx, (size_t)nnz)) != hipSuccess) return dev_fail(e, "upload A");
+    if ((e = up(&x->a_v64, val, (size_t)nnz)) != hipSuccess) return dev_fail(e, "upload A");
+    if ((e = up(&x->t_rp, h_trp.data(), h_trp.size())) != hipSuccess) return dev_fail(e, "upload A'");
+    if ((e = up(&x->t_ci, h_tci.data(), h_tci.size())) != hipSuccess) return dev_fail(e, "upload A'");
+    if ((e = up(&x->t_v64, h_tv.data(), h_tv.size())) != hipSuccess) return dev_fail(e, "upload A'");
+    if (x->fp32) {
+        std::vector<float> a32(val, val + nnz), t32(h_tv.begin(), h_tv.end());
+        if ((e = up(&x->a_v32, a32.data(), a32.size())) != hipSuccess) return dev_fail(e, "upload A");
+        if ((e = up(&x->t_v32, t32.data(), t32.size())) != hipSuccess) return dev_fail(e, "upload A'");
+    }
+    if ((e = up(&x->c, c, (size_t)n)) != hipSuccess) return dev_fail(e, "upload c");
+    if ((e = up(&x->xl, l, (size_t)n)) != hipSuccess) return dev_fail(e, "upload l");
+    if ((e = up(&x->xu, u, (size_t)n)) != hipSuccess) return dev_fail(e, "upload u");
+    if ((e = up(&x->rl, rl.data(), (size_t)m)) != hipSuccess) return dev_fail(e, "upload rows");
+    if ((e = up(&x->ru, ru.data(), (size_t)m)) != hipSuccess) return dev_fail(e, "upload rows");
+    if ((e = x->alloc(&x->g, sizeof(Globals))) != hipSuccess) return dev_fail(e, "alloc");
+
+    x->h_xl.assign(l, l + n);
+    x->h_xu.assign(u, u + n);
+    double sc = 0.0, sb = 0.0;
+    for (int32_t j = 0; j < n; ++j) sc += c[j] * c[j];
+    for (int32_t i = 0; i < m; ++i) sb += b[i] * b[i];
+    x->norm_c = std::sqrt(sc);
+    x->norm_b = std::sqrt(sb);
+
+    if (o.step_size > 0.0) {
+        x->eta = o.step_size;
+        x->norm_a = 0.0;
+    } else {
+        int rc = compute_opnorm(x, &x->norm_a);
+        if (rc) {
+            g_create_error = x->err;
+            free_all(x);
+            return rc;
+        }
+        x->eta = x->norm_a > 0.0 ? 0.998 / x->norm_a : 1.0;
+    }
+    Globals hg{};
+    hg.eta = x->eta;
+    hg.r_prev = -1.0;
+    e = hipMemcpy(x->g, &hg, sizeof(Globals), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return dev_fail(e, "upload globals");
+    x->pw_x = eval_rows_per_wave(n);
+    x->pw_y = eval_rows_per_wave(m);
+    x->npx = (n + 4 * x->pw_x - 1) / (4 * x->pw_x);
+    x->npy = (m + 4 * x->pw_y - 1) / (4 * x->pw_y);
+    *out = x;
+    return PDLPB_OK;
+}
+
+int pdlpb_set_batch(pdlpb_ctx* x, int32_t B, const pdlpb_delta* deltas, const double* x_warm,
+                    const double* y_warm, const double* w_warm, int32_t warm_mode, int32_t mem) {
+    if (!x) return PDLPB_EINVAL;
+    if (B < 1 || B > x->opt.max_batch) return x->fail(PDLPB_EINVAL, "B out of range [1, max_batch]");
+    if (!deltas) return x->fail(PDLPB_EINVAL, "deltas is NULL");
+    if (mem != PDLPB_MEM_HOST && mem != PDLPB_MEM_DEVICE) return x->fail(PDLPB_EINVAL, "unknown mem");
+    if (warm_mode != PDLPB_WARM_NONE && warm_mode != PDLPB_WARM_SHARED &&
+        warm_mode != PDLPB_WARM_PER_LP)
+        return x->fail(PDLPB_EINVAL, "unknown warm mode");
+    if (warm_mode != PDLPB_WARM_NONE && (!x_warm || (x->m > 0 && !y_warm)))
+        return x->fail(PDLPB_EINVAL, "warm start vectors missing");
+    HIP_TRY(x, hipSetDevice(x->device));
+    const int32_t n = x->n, m = x->m;
+
+    std::vector<pdlpb_delta> d(B);
+    std::vector<double> w0(B, 0.0);
+    if (mem == PDLPB_MEM_DEVICE) {
+        HIP_TRY(x, hipMemcpy(d.data(), deltas, sizeof(pdlpb_delta) * B, hipMemcpyDeviceToHost));
+        if (w_warm) HIP_TRY(x, hipMemcpy(w0.data(), w_warm, sizeof(double) * B, hipMemcpyDeviceToHost));
+    } else {
+        std::memcpy(d.data(), deltas, sizeof(pdlpb_delta) * B);
+        if (w_warm) std::memcpy(w0.data(), w_warm, sizeof(double) * B);
+    }
+    std::vector<SlotState> hs(B);
+    std::vector<SlotCtl> hc(B);
+    for (int32_t j = 0; j < B; ++j) {
+        const pdlpb_delta& q = d[j];
+        if (q.kind < PDLPB_BASE || q.kind > PDLPB_OBJ_UNIT)
+            return x->fail(PDLPB_EINVAL, "delta kind out of range at LP " + std::to_string(j));
+        if (q.kind != PDLPB_BASE && (q.var < 0 || q.var >= n))
+            return x->fail(PDLPB_EINVAL, "delta var out of range at LP " + std::to_string(j));
+        SlotState s{};
+        SlotCtl cl{};
+        s.kind = q.kind;
+        s.var = q.kind == PDLPB_BASE ? -1 : q.var;
+        s.value = q.value;
+        int32_t status = PDLPB_STATUS_RUNNING;
+        double cn = x->norm_c;
+        if (q.kind != PDLPB_BASE) {
+            const bool bad_value = std::isnan(q.value) ||
+                                   (q.kind == PDLPB_SET_LO && q.value == INFINITY) ||
+                                   (q.kind == PDLPB_SET_HI && q.value == -INFINITY) ||
+                                   (q.kind == PDLPB_OBJ_UNIT && !std::isfinite(q.value));
+            if (bad_value) status = PDLPB_STATUS_INVALID_INPUT;
+            else if (q.kind == PDLPB_SET_LO && q.value > x->h_xu[q.var])
+                status = PDLPB_STATUS_INFEASIBLE_BOUNDS;
+            else if (q.kind == PDLPB_SET_HI && q.value < x->h_xl[q.var])
+                status = PDLPB_STATUS_INFEASIBLE_BOUNDS;
+            if (q.kind == PDLPB_OBJ_UNIT) cn = std::fabs(q.value);
+        }
+        double w = 1.0;
+        if (w_warm) {
+            w = w0[j];
+            if (!(w > 0.0) || !std::isfinite(w)) status = PDLPB_STATUS_INVALID_INPUT;
+        } else if (cn > 1e-10 && x->norm_b > 1e-10) {
+            w = cn / x->norm_b;
+        }
+        if (status != PDLPB_STATUS_RUNNING) {
+            s.flags = 0;
+            s.value = std::isnan(q.value) ? 0.0 : q.value;
+            w = 1.0;
+        } else {
+            s.flags = SLOT_ACTIVE;
+        }
+        s.tau = x->eta / w;
+        s.sigma = x->eta * w;
+        cl.w = w;
+        cl.r_prev = -1.0;
+        cl.status = status;
+        for (double& v : cl.kkt) v = NAN;
+        cl.obj = NAN;
+        hs[j] = s;
+        hc[j] = cl;
+    }
+
+    // storage (grows, reused for smaller batches)
+    choose_tile(x, B);
+    const int32_t ld = ((B + x->vec - 1) / x->vec) * x->vec;
+    const size_t esz = x->fp32 ? sizeof(float) : sizeof(double);
+    const size_t rows_max = (size_t)std::max(n, m);
+    const size_t block_bytes = rows_max * (size_t)ld * esz;
+    if (block_bytes > x->cap_block_bytes) {
+        x->drop_graph();
+        for (void*& p : x->blk) x->release(p, x->cap_block_bytes);
+        x->cap_block_bytes = 0;
+        for (void*& p : x->blk) HIP_TRY(x, x->alloc(&p, block_bytes));
+        x->cap_block_bytes = block_bytes;
+    }
+    if (B > x->cap_slots) {
+        x->drop_graph();
+        x->release(x->st, sizeof(SlotState) * x->cap_slots);
+        x->release(x->ctl, sizeof(SlotCtl) * x->cap_slots);
+        x->release(x->rlog, sizeof(int32_t) * RESTART_LOG * x->cap_slots);
+        x->cap_slots = 0;
+        HIP_TRY(x, x->alloc(&x->st, sizeof(SlotState) * B));
+        HIP_TRY(x, x->alloc(&x->ctl, sizeof(SlotCtl) * B));
+        HIP_TRY(x, x->alloc(&x->rlog, sizeof(int32_t) * RESTART_LOG * B));
+        x->cap_slots = B;
+    }
+    const size_t part_need = (size_t)(x->npx + x->npy + 2) * NTERM * ld;
+    if (part_need > x->cap_part) {
+        x->drop_graph();
+        x->release(x->part, x->cap_part * sizeof(double));
+        x->cap_part = 0;
+        HIP_TRY(x, x->alloc(&x->part, part_need * sizeof(double)));
+        x->cap_part = part_need;
+    }
+    x->drop_graph();   // grid shapes and slot count are baked into the captured launches
+    x->B = B;
+    x->ld = ld;
+    x->batch_set = true;
+    x->solved = false;
+
+    HIP_TRY(x, hipMemcpyAsync(x->st, hs.data(), sizeof(SlotState) * B, hipMemcpyHostToDevice,
+                              x->stream));
+    HIP_TRY(x, hipMemcpyAsync(x->ctl, hc.data(), sizeof(SlotCtl) * B, hipMemcpyHostToDevice,
+                              x->stream));
+    const double* xw = nullptr;
+    const double* yw = nullptr;
+    if (warm_mode != PDLPB_WARM_NONE) {
+        const size_t nx = warm_mode == PDLPB_WARM_SHARED ? (size_t)n : (size_t)n * B;
+        const size_t ny = warm_mode == PDLPB_WARM_SHARED ? (size_t)m : (size_t)m * B;
+        if (mem == PDLPB_MEM_DEVICE) {
+            xw = x_warm;
+            yw = y_warm;
+        } else {
+            int rc = ensure_stage(x, nx + ny);
+            if (rc) return rc;
+            HIP_TRY(x, hipMemcpyAsync(x->stage, x_warm, nx * sizeof(double), hipMemcpyHostToDevice,
+                                      x->stream));
+            if (ny)
+                HIP_TRY(x, hipMemcpyAsync(x->stage + nx, y_warm, ny * sizeof(double),
+                                          hipMemcpyHostToDevice, x->stream));
+            xw = x->stage;
+            yw = x->stage + nx;
+        }
+    }
+    if (x->fp32) {
+        float* const* b = reinterpret_cast<float* const*>(x->blk);
+        HIP_TRY(x, launch_init_blocks<float>(n, m, ld, B, x->st, x->xl, x->xu, xw, yw, warm_mode,
+                                             b[0], b[1], b[2], b[3], b[4], b[5], b[6], b[7],
+                                             x->stream));
+    } else {
+        double* const* b = reinterpret_cast<double* const*>(x->blk);
+        HIP_TRY(x, launch_init_blocks<double>(n, m, ld, B, x->st, x->xl, x->xu, xw, yw, warm_mode,
+                                              b[0], b[1], b[2], b[3], b[4], b[5], b[6], b[7],
+                                              x->stream));
+    }
+    // host staging must outlive the copies
+    HIP_TRY(x, hipStreamSynchronize(x->stream));
+    x->h_st = hs;
+    x->h_ctl = hc;
+    return PDLPB_OK;
+}
+
+int pdlpb_solve(pdlpb_ctx* x, double tol, int64_t max_iters) {
+    if (!x) return PDLPB_EINVAL;
+    if (!x->batch_set) return x->fail(PDLPB_ESTATE, "no batch set");
+    if (x->solved) return x->fail(PDLPB_ESTATE, "batch already solved; call pdlpb_set_batch");
+    if (!(tol >= 0.0)) return x->fail(PDLPB_EINVAL, "tol must be >= 0");
+    if (max_iters < 1 || max_iters > (1 << 30)) return x->fail(PDLPB_EINVAL, "max_iters out of range");
+    HIP_TRY(x, hipSetDevice(x->device));
+    int rc = x->fp32 ? run_solve<float>(x, tol, (int32_t)max_iters)
+                     : run_solve<double>(x, tol, (int32_t)max_iters);
+    if (rc) return rc;
+    rc = fetch_state(x);
+    if (rc) return rc;
+    x->solved = true;
+    return PDLPB_OK;
+}
+
+int pdlpb_get(pdlpb_ctx* x, int32_t j, double* xo, double* yo, int32_t* status, double kkt[4],
+              double* obj, int64_t* iters, int32_t mem) {
+    if (!x) return PDLPB_EINVAL;
+    if (!x->batch_set) return x->fail(PDLPB_ESTATE, "no batch set");
+    if (j < 0 || j >= x->B) return x->fail(PDLPB_EINVAL, "LP index out of range");
+    if (mem != PDLPB_MEM_HOST && mem != PDLPB_MEM_DEVICE) return x->fail(PDLPB_EINVAL, "unknown mem");
+    if (!x->solved) return x->fail(PDLPB_ESTATE, "batch not solved yet");
+    HIP_TRY(x, hipSetDevice(x->device));
+    const SlotCtl& cl = x->h_ctl[j];
+    if (status) *status = cl.status;
+    if (kkt)
+        for (int q = 0; q < 4; ++q) kkt[q] = cl.kkt[q];
+    if (obj) *obj = cl.obj;
+    if (iters) *iters = cl.iters;
+    const hipMemcpyKind kind = mem == PDLPB_MEM_DEVICE ? hipMemcpyDeviceToDevice
+                                                        : hipMemcpyDeviceToHost;
+    if (xo || yo) {
+        int rc = ensure_stage(x, (size_t)x->n + x->m);
+        if (rc) return rc;
+        if (x->fp32) {
+            float* const* b = reinterpret_cast<float* const*>(x->blk);
+            if (xo) HIP_TRY(x, launch_gather_column<float>(b[2], x->n, x->ld, j, x->stage, x->stream));
+            if (yo) HIP_TRY(x, launch_gather_column<float>(b[6], x->m, x->ld, j, x->stage + x->n, x->stream));
+        } else {
+            double* const* b = reinterpret_cast<double* const*>(x->blk);
+            if (xo) HIP_TRY(x, launch_gather_column<double>(b[2], x->n, x->ld, j, x->stage, x->stream));
+            if (yo) HIP_TRY(x, launch_gather_column<double>(b[6], x->m, x->ld, j, x->stage + x->n, x->stream));
+        }
+        if (xo) HIP_TRY(x, hipMemcpyAsync(xo, x->stage, sizeof(double) * x->n, kind, x->stream));
+        if (yo && x->m)
+            HIP_TRY(x, hipMemcpyAsync(yo, x->stage + x->n, sizeof(double) * x->m, kind, x->stream));
+        HIP_TRY(x, hipStreamSynchronize(x->stream));
+    }
+    return PDLPB_OK;
+}
+
+int pdlpb_get_batch(pdlpb_ctx* x, double* X, double* Y, int32_t* status, double* kkt, double* obj,
+                    int64_t* iters, int32_t mem) {
+    if (!x) return PDLPB_EINVAL;
+    if (!x->batch_set) return x->fail(PDLPB_ESTATE, "no batch set");
+    if (!x->solved) return x->fail(PDLPB_ESTATE, "batch not solved yet");
+    if (mem != PDLPB_MEM_HOST && mem != PDLPB_MEM_DEVICE) return x->fail(PDLPB_EINVAL, "unknown mem");
+    HIP_TRY(x, hipSetDevice(x->device));
+    const int32_t B = x->B;
+    for (int32_t j = 0; j < B; ++j) {
+        const SlotCtl& cl = x->h_ctl[j];
+        if (status) status[j] = cl.status;
+        if (kkt)
+            for (int q = 0; q < 4; ++q) kkt[4 * (size_t)j + q] = cl.kkt[q];
+        if (obj) obj[j] = cl.obj;
+        if (iters) iters[j] = cl.iters;
+    }
+    const hipMemcpyKind kind = mem == PDLPB_MEM_DEVICE ? hipMemcpyDeviceToDevice
+                                                        : hipMemcpyDeviceToHost;
+    for (int side = 0; side < 2; ++side) {
+        double* dst = side == 0 ? X : Y;
+        const int32_t rows = side == 0 ? x->n : x->m;
+        if (!dst || rows == 0) continue;
+        const size_t cnt = (size_t)rows * B;
+        double* tmp = dst;
+        if (mem == PDLPB_MEM_HOST) {
+            int rc = ensure_stage(x, cnt);
+            if (rc) return rc;
+            tmp = x->stage;
+        }
+        if (x->fp32)
+            HIP_TRY(x, launch_transpose_out<float>(reinterpret_cast<float*>(x->blk[side == 0 ? 2 : 6]),
+                                                   rows, x->ld, B, tmp, x->stream));
+        else
+            HIP_TRY(x, launch_transpose_out<double>(reinterpret_cast<double*>(x->blk[side == 0 ? 2 : 6]),
+                                                    rows, x->ld, B, tmp, x->stream));
+        if (mem == PDLPB_MEM_HOST)
+            HIP_TRY(x, hipMemcpyAsync(dst, tmp, cnt * sizeof(double), kind, x->stream));
+        HIP_TRY(x, hipStreamSynchronize(x->stream));
+    }
+    return PDLPB_OK;
+}
+
+int pdlpb_get_trace(pdlpb_ctx* x, int32_t j, double* x_iter, double* y_iter, double* w,
+                    int32_t* restarts, int32_t* restart_log, int32_t log_cap) {
+    if (!x) return PDLPB_EINVAL;
+    if (!x->batch_set) return x->fail(PDLPB_ESTATE, "no batch set");
+    if (!x->solved) return x->fail(PDLPB_ESTATE, "batch not solved yet");
+    if (j < 0 || j >= x->B) return x->fail(PDLPB_EINVAL, "LP index out of range");
+    HIP_TRY(x, hipSetDevice(x->device));
+    const SlotCtl& cl = x->h_ctl[j];
+    const SlotState& st = x->h_st[j];
+    if (w) *w = cl.w;
+    if (restarts) *restarts = cl.restarts;
+    if (restart_log && log_cap > 0) {
+        const int32_t cnt = std::min(std::min(cl.restarts, (int32_t)RESTART_LOG), log_cap);
+        for (int32_t q = 0; q < cnt; ++q) restart_log[q] = x->h_rlog[(size_t)j * RESTART_LOG + q];
+    }
+    if (x_iter || y_iter) {
+        int rc = ensure_stage(x, (size_t)x->n + x->m);
+        if (rc) return rc;
+        const int32_t k = cl.t_last - st.t_anchor;   // inner index of the LP's last iteration
+        const double a = double(k + 1) / double(k + 2);
+        if (x->fp32) {
+            float* const* b = reinterpret_cast<float* const*>(x->blk);
+            HIP_TRY(x, launch_halpern_column<float>(b[0], b[1], x->n, x->ld, j, a, k + 2, x->stage, x->stream));
+            HIP_TRY(x, launch_gather_column<float>(b[4], x->m, x->ld, j, x->stage + x->n, x->stream));
+        } else {
+            double* const* b = reinterpret_cast<double* const*>(x->blk);
+            HIP_TRY(x, launch_halpern_column<double>(b[0], b[1], x->n, x->ld, j, a, k + 2, x->stage, x->stream));
+            HIP_TRY(x, launch_gather_column<double>(b[4], x->m, x->ld, j, x->stage + x->n, x->stream));
+        }
+        if (x_iter)
+            HIP_TRY(x, hipMemcpyAsync(x_iter, x->stage, sizeof(double) * x->n, hipMemcpyDeviceToHost, x->stream));
+        if (y_iter && x->m)
+            HIP_TRY(x, hipMemcpyAsync(y_iter, x->stage + x->n, sizeof(double) * x->m,
+                                      hipMemcpyDeviceToHost, x->stream));
+        HIP_TRY(x, hipStreamSynchronize(x->stream));
+    }
+    return PDLPB_OK;
+}
+
+int pdlpb_get_step_size(const pdlpb_ctx* x, double* eta, double* norm_a) {
+    if (!x) return PDLPB_EINVAL;
+    if (eta) *eta = x->eta;
+    if (norm_a) *norm_a = x->norm_a;
+    return PDLPB_OK;
+}
+
+int pdlpb_set_kernel_timing(pdlpb_ctx* x, int32_t enable) {
+    if (!x) return PDLPB_EINVAL;
+    x->timing = enable != 0;
+    for (int q = 0; q < 4; ++q) {
+        x->t_counts[q] = 0;
+        x->t_ms[q] = 0.0;
+    }
+    return PDLPB_OK;
+}
+
+int pdlpb_kernel_times(pdlpb_ctx* x, int64_t counts[4], double total_ms[4]) {
+    if (!x) return PDLPB_EINVAL;
+    for (int q = 0; q < 4; ++q) {
+        if (counts) counts[q] = x->t_counts[q];
+        if (total_ms) total_ms[q] = x->t_ms[q];
+    }
+    return PDLPB_OK;
+}
+
+int64_t pdlpb_device_bytes(const pdlpb_ctx* x) { return x ? x->dev_bytes : 0; }
+
+void pdlpb_destroy(pdlpb_ctx* x) { free_all(x); }
+
+const char* pdlpb_last_error(const pdlpb_ctx* x) {
+    return x ? x->err.c_str() : g_create_error.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,162 @@
+// Internal declarations shared by the gfx950 kernels (kernels.hip) and the
+// C ABI implementation (pdlpb.cpp).  Not installed; the public interface is
+// include/pdlpb.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pdlpb {
+
+// ---- per-slot state read by the fused step kernels ------------------------
+enum : int32_t { SLOT_ACTIVE = 1, SLOT_FRESH = 2 };
+
+struct SlotState {
+    int32_t kind;      // delta kind (PDLPB_BASE .. PDLPB_OBJ_UNIT)
+    int32_t var;       // delta variable
+    double  value;     // delta value
+    double  tau;       // eta / w
+    double  sigma;     // eta * w
+    int32_t t_anchor;  // global iteration index at which the current restart cycle began (k = t - t_anchor)
+    int32_t t_start;   // global iteration index of the LP's first iteration
+    int32_t t_end;     // global iteration index of the LP's last permitted iteration
+    int32_t flags;     // SLOT_ACTIVE: still iterating; SLOT_FRESH: the iterate and anchor are z~ of the last restart
+};
+static_assert(sizeof(SlotState) == 48, "SlotState layout");
+
+// ---- per-slot control data (control kernel only) ---------------------------
+constexpr int RESTART_LOG = 64;
+
+struct SlotCtl {
+    double  w;         // primal weight
+    double  r0;        // residual at the start of the restart cycle
+    double  r_prev;    // previous evaluated residual of the cycle; < 0 when none
+    double  kkt[4];    // gap, primal, dual, max at the LP's last evaluation
+    double  obj;       // c_j' x~
+    int32_t status;    // PDLPB_STATUS_*
+    int32_t iters;     // applications of T
+    int32_t restarts;  // number of restarts
+    int32_t t_last;    // global iteration index of the LP's last iteration
+};
+
+// ---- batch-wide scalars on the device ---------------------------------------
+struct Globals {
+    int32_t t0;          // base iteration index of the current block of C iterations
+    int32_t n_active;    // LPs still running after the last control pass
+    int32_t batch_k0;    // BATCH_AVG: global index at which the shared restart cycle began
+    int32_t pad;
+    double  tol;
+    double  eta;
+    double  r0;          // BATCH_AVG shared r(z^{n,0})
+    double  r_prev;      // BATCH_AVG shared previous residual (< 0: none)
+};
+
+// number of float64 sums each evaluation produces per LP and side
+constexpr int NTERM = 6;
+// x side: |dx|^2, c'x~, phi_box(r~), |c + A'y~ + r~|^2, |c|^2, |x~ - x0|^2
+// y side: |dy|^2, dy'(A dx), phi_[l,u](y~), |Ax~ - Pi(Ax~)|^2, |Ax~|^2, |y~ - y0|^2
+
+template <typename T>
+struct StepArgs {
+    const int32_t* rp;   // CSR row pointers of the matrix whose rows this kernel walks
+    const int32_t* ci;   // column indices
+    const T*       av;   // values
+    int32_t rows;        // rows walked (n for the primal step, m for the dual step)
+    int32_t ld;          // row stride of every dense block (>= ncols)
+    int32_t ncols;       // slots in use
+    int32_t wpb;         // waves per block
+    const T* G;          // block gathered by the product (Y for primal, Xbar for dual)
+    T* Z;                // primal: Xbar (reflected x, 2x~ - x^k)   dual: Y (Halpern iterate y^k)
+    T* Z0;               // anchor block X0 / Y0
+    T* Zt;               // z~ block Xt / Yt (written on evaluation launches and final iterations)
+    T* DZ;               // displacement z~ - z^k (same launches)
+    const double* c;     // primal: base objective (n); dual: unused
+    const double* lo;    // primal: base xl (n);  dual: row lower bounds l (m)
+    const double* hi;    // primal: base xu (n);  dual: row upper bounds u (m)
+    const SlotState* st;
+    const Globals* g;
+    int32_t it;          // iteration index inside the block; global t = g->t0 + it
+    int32_t eval;        // 1: every running LP writes z~ and its displacement
+};
+
+template <typename T>
+struct EvalArgs {
+    int32_t n, m, ld, ncols;
+    const int32_t* a_rp; const int32_t* a_ci; const T* a_v;    // A (m x n)
+    const int32_t* t_rp; const int32_t* t_ci; const T* t_v;    // A' (n x m)
+    const T *Xt, *DX, *X0, *Yt, *DY, *Y0;
+    const double *c, *xl, *xu, *rl, *ru;
+    const SlotState* st;
+    int32_t pw_x, pw_y;      // rows per wave on the x side / y side
+    int32_t npx, npy;        // row panels (4 waves each) on each side
+    double* part_x;          // [npx][NTERM][ld]
+    double* part_y;          // [npy][NTERM][ld]
+};
+
+struct ControlArgs {
+    int32_t ncols, ld, npx, npy;
+    const double* part_x;
+    const double* part_y;
+    double* sums;            // [2*NTERM][ld] scratch written by the reduce kernel
+    SlotState* st;
+    SlotCtl* ctl;
+    int32_t* rlog;           // [ncols][RESTART_LOG]
+    Globals* g;
+    int32_t it;              // iteration index inside the block
+    int32_t full;            // 1: KKT and restart tests (t mod C == 0); 0: residual of fresh cycles only
+    int32_t advance;         // 1: move g->t0 on by `block` after this pass
+    int32_t block;           // C
+    int32_t batch_avg;       // restart scope
+    int32_t pw_literal;      // primal weight ratio as printed
+    double beta_s, beta_n, beta_a, theta, cross_sign;
+};
+
+// ---- launchers (kernels.hip) ---------------------------------------------------
+// Each returns hipSuccess or the launch error.
+template <typename T>
+hipError_t launch_primal(const StepArgs<T>& a, int lanes, int vec, hipStream_t s);
+template <typename T>
+hipError_t launch_dual(const StepArgs<T>& a, int lanes, int vec, hipStream_t s);
+template <typename T>
+hipError_t launch_eval(const EvalArgs<T>& a, hipStream_t s);
+hipError_t launch_reduce(const ControlArgs& a, hipStream_t s);
+hipError_t launch_control(const ControlArgs& a, hipStream_t s);
+
+// Fill the dense blocks of a new batch.  Warm vectors: mode 0 none, 1 shared
+// (xw: n, yw: m), 2 per LP (xw: ncols*n, yw: ncols*m, LP-major).
+template <typename T>
+hipError_t launch_init_blocks(int32_t n, int32_t m, int32_t ld, int32_t ncols,
+                              const SlotState* st, const double* xl, const double* xu,
+                              const double* xw, const double* yw, int32_t mode,
+                              T* Xbar, T* X0, T* Xt, T* DX, T* Y, T* Y0, T* Yt, T* DY,
+                              hipStream_t s);
+
+// Start a solve: t_end of every active slot from the iteration budget, g->t0 = 0.
+hipError_t launch_begin_solve(SlotState* st, SlotCtl* ctl, int32_t ncols, int32_t max_iters,
+                              Globals* g, double tol, hipStream_t s);
+
+// Copy column `slot` of a row-major block (rows x ld) into a contiguous float64 vector.
+template <typename T>
+hipError_t launch_gather_column(const T* Z, int32_t rows, int32_t ld, int32_t slot,
+                                double* out, hipStream_t s);
+
+// LP-major copy of the first ncols columns of a row-major block: out[s*rows + i] = Z[i*ld + s].
+template <typename T>
+hipError_t launch_transpose_out(const T* Z, int32_t rows, int32_t ld, int32_t ncols, double* out,
+                                hipStream_t s);
+
+// Halpern iterate of the last update: x = a*Xbar + X0*b (column `slot`).
+template <typename T>
+hipError_t launch_halpern_column(const T* Xbar, const T* X0, int32_t rows, int32_t ld,
+                                 int32_t slot, double a, int32_t kp2, double* out, hipStream_t s);
+
+// Power iteration building blocks (float64, one vector).
+hipError_t launch_spmv(const int32_t* rp, const int32_t* ci, const double* v, int32_t rows,
+                       const double* x, double* y, hipStream_t s);
+// sum of squares of x (length len) -> *out, deterministic two-pass; partial holds >= 1024 doubles
+hipError_t launch_norm2sq(const double* x, int32_t len, double* partial, double* out,
+                          hipStream_t s);
+hipError_t launch_scale(double* x, int32_t len, const double* nrm2sq, hipStream_t s);
+hipError_t launch_fill(double* x, int32_t len, double v, hipStream_t s);
+
+}  // namespace pdlpb

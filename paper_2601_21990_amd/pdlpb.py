@@ -1,0 +1,273 @@
+"""ctypes binding of libpdlpb.so (include/pdlpb.h).
+
+Argument marshalling only: every function forwards to the C entry point of
+the same name, and the ``Context`` class strings those calls together.  Host
+arrays are numpy; device arrays may be torch tensors on the context's GPU
+(passed by ``data_ptr()`` with ``mem=MEM_DEVICE``).  No computation of the
+solver happens here, and there is no fallback: if the shared library is
+missing, importing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpdlpb.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, ESTATE = 0, -1, -2, -3, -4
+STATUS_RUNNING, STATUS_OPTIMAL, STATUS_ITERATION_LIMIT = 0, 1, 2
+STATUS_INFEASIBLE_BOUNDS, STATUS_NUMERICAL_ERROR, STATUS_INVALID_INPUT = 3, 4, 5
+BASE, SET_LO, SET_HI, OBJ_UNIT = 0, 1, 2, 3
+FP64, MIXED32 = 0, 1
+RESTART_PER_LP, RESTART_BATCH_AVG = 0, 1
+WARM_NONE, WARM_SHARED, WARM_PER_LP = 0, 1, 2
+MEM_HOST, MEM_DEVICE = 0, 1
+
+STATUS_NAMES = {0: "RUNNING", 1: "OPTIMAL", 2: "ITERATION_LIMIT", 3: "INFEASIBLE_BOUNDS",
+                4: "NUMERICAL_ERROR", 5: "INVALID_INPUT"}
+
+EXPORTED = ["pdlpb_default_options", "pdlpb_create", "pdlpb_set_batch", "pdlpb_solve",
+            "pdlpb_get", "pdlpb_get_batch", "pdlpb_get_trace", "pdlpb_get_step_size",
+            "pdlpb_set_kernel_timing", "pdlpb_kernel_times", "pdlpb_device_bytes",
+            "pdlpb_destroy", "pdlpb_last_error"]
+
+
+class Delta(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("var", C.c_int32), ("value", C.c_double)]
+
+
+class Options(C.Structure):
+    _fields_ = [("struct_size", C.c_int32), ("precision", C.c_int32),
+                ("restart_scope", C.c_int32), ("eval_every", C.c_int32),
+                ("beta_sufficient", C.c_double), ("beta_necessary", C.c_double),
+                ("beta_artificial", C.c_double), ("theta", C.c_double),
+                ("step_size", C.c_double), ("cross_sign", C.c_double),
+                ("pw_ratio", C.c_int32), ("device", C.c_int32), ("stream", C.c_void_p),
+                ("max_batch", C.c_int32), ("use_graphs", C.c_int32),
+                ("tile_lanes", C.c_int32), ("tile_vec", C.c_int32),
+                ("reserved", C.c_int32 * 8)]
+
+
+class PdlpbError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"pdlpb error {code}: {msg}")
+        self.code = code
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                          "(hipcc --offload-arch=gfx950); there is no fallback path")
+    lib = C.CDLL(LIB_PATH)
+    P = C.c_void_p
+    d, i32, i64 = C.c_double, C.c_int32, C.c_int64
+    dp, i32p, i64p = C.POINTER(C.c_double), C.POINTER(C.c_int32), C.POINTER(C.c_int64)
+    sig = {
+        "pdlpb_default_options": (None, [C.POINTER(Options)]),
+        "pdlpb_create": (C.c_int, [C.POINTER(P), i32, i32, i64, P, P, P, P, P, P, P, P,
+                                    C.POINTER(Options)]),
+        "pdlpb_set_batch": (C.c_int, [P, i32, P, P, P, P, i32, i32]),
+        "pdlpb_solve": (C.c_int, [P, d, i64]),
+        "pdlpb_get": (C.c_int, [P, i32, P, P, i32p, dp, dp, i64p, i32]),
+        "pdlpb_get_batch": (C.c_int, [P, P, P, i32p, dp, dp, i64p, i32]),
+        "pdlpb_get_trace": (C.c_int, [P, i32, dp, dp, dp, i32p, i32p, i32]),
+        "pdlpb_get_step_size": (C.c_int, [P, dp, dp]),
+        "pdlpb_set_kernel_timing": (C.c_int, [P, i32]),
+        "pdlpb_kernel_times": (C.c_int, [P, i64p, dp]),
+        "pdlpb_device_bytes": (C.c_int64, [P]),
+        "pdlpb_destroy": (None, [P]),
+        "pdlpb_last_error": (C.c_char_p, [P]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+lib = _load()
+
+# C entry points under their own names
+pdlpb_default_options = lib.pdlpb_default_options
+pdlpb_create = lib.pdlpb_create
+pdlpb_set_batch = lib.pdlpb_set_batch
+pdlpb_solve = lib.pdlpb_solve
+pdlpb_get = lib.pdlpb_get
+pdlpb_get_batch = lib.pdlpb_get_batch
+pdlpb_get_trace = lib.pdlpb_get_trace
+pdlpb_get_step_size = lib.pdlpb_get_step_size
+pdlpb_set_kernel_timing = lib.pdlpb_set_kernel_timing
+pdlpb_kernel_times = lib.pdlpb_kernel_times
+pdlpb_device_bytes = lib.pdlpb_device_bytes
+pdlpb_destroy = lib.pdlpb_destroy
+pdlpb_last_error = lib.pdlpb_last_error
+
+
+def default_options(**kw) -> Options:
+    o = Options()
+    lib.pdlpb_default_options(C.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise AttributeError(f"unknown option {k}")
+        setattr(o, k, v)
+    return o
+
+
+def _ptr(a) -> Optional[int]:
+    """Address of a numpy array (host) or a torch tensor (device); None for None."""
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data
+    if hasattr(a, "data_ptr"):
+        return a.data_ptr()
+    raise TypeError(f"unsupported buffer type {type(a)}")
+
+
+def _f64(a, n=None):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if n is not None and a.size != n:
+        raise ValueError(f"expected {n} entries, got {a.size}")
+    return a
+
+
+def deltas_array(kinds, vars_, values) -> np.ndarray:
+    d = np.zeros(len(kinds), dtype=[("kind", "<i4"), ("var", "<i4"), ("value", "<f8")])
+    d["kind"], d["var"], d["value"] = kinds, vars_, values
+    return d
+
+
+class Context:
+    """One constraint matrix on the GPU and its current batch of LPs."""
+
+    def __init__(self, m, n, row_ptr, col_idx, val, c, b, sense, l, u,
+                 options: Optional[Options] = None, **opt_kw):
+        opts = options if options is not None else default_options(**opt_kw)
+        self.m, self.n = int(m), int(n)
+        rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+        ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+        vv = _f64(val)
+        cc, bb = _f64(c, self.n), _f64(b, self.m)
+        ss = np.ascontiguousarray(np.frombuffer(bytes(sense), dtype=np.uint8)
+                                  if isinstance(sense, (bytes, bytearray)) else sense,
+                                  dtype=np.uint8)
+        ll, uu = _f64(l, self.n), _f64(u, self.n)
+        h = C.c_void_p()
+        rc = lib.pdlpb_create(C.byref(h), self.m, self.n, int(rp[-1]) if rp.size else 0,
+                              _ptr(rp), _ptr(ci), _ptr(vv), _ptr(cc), _ptr(bb), _ptr(ss),
+                              _ptr(ll), _ptr(uu), C.byref(opts))
+        if rc != OK:
+            raise PdlpbError(rc, lib.pdlpb_last_error(None).decode())
+        self._h = h
+        self.options = opts
+        self.B = 0
+
+    @classmethod
+    def from_instance(cls, inst, **kw):
+        return cls(inst.m, inst.n, inst.row_ptr, inst.col_idx, inst.val, inst.c, inst.b,
+                   inst.sense, inst.l, inst.u, **kw)
+
+    def _check(self, rc):
+        if rc != OK:
+            raise PdlpbError(rc, lib.pdlpb_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.pdlpb_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    @property
+    def step_size(self):
+        eta, na = C.c_double(), C.c_double()
+        self._check(lib.pdlpb_get_step_size(self._h, C.byref(eta), C.byref(na)))
+        return eta.value, na.value
+
+    @property
+    def device_bytes(self) -> int:
+        return int(lib.pdlpb_device_bytes(self._h))
+
+    def set_batch(self, deltas, x_warm=None, y_warm=None, w_warm=None,
+                  warm_mode: Optional[int] = None, mem: int = MEM_HOST):
+        B = len(deltas)
+        if mem == MEM_HOST:
+            dd = np.ascontiguousarray(deltas)
+            if dd.dtype.itemsize != 16:
+                raise ValueError("deltas must have the 16-byte (kind, var, value) layout")
+            xw = None if x_warm is None else _f64(x_warm)
+            yw = None if y_warm is None else _f64(y_warm)
+            ww = None if w_warm is None else _f64(w_warm, B)
+        else:
+            dd, xw, yw, ww = deltas, x_warm, y_warm, w_warm
+        if warm_mode is None:
+            if x_warm is None:
+                warm_mode = WARM_NONE
+            else:
+                nx = x_warm.size if hasattr(x_warm, "size") and not callable(x_warm.size) \
+                    else x_warm.numel()
+                warm_mode = WARM_SHARED if nx == self.n else WARM_PER_LP
+        self._check(lib.pdlpb_set_batch(self._h, B, _ptr(dd), _ptr(xw), _ptr(yw), _ptr(ww),
+                                        int(warm_mode), int(mem)))
+        self.B = B
+
+    def solve(self, tol: float = 1e-4, max_iters: int = 100000):
+        self._check(lib.pdlpb_solve(self._h, float(tol), int(max_iters)))
+
+    def get(self, j: int, want_x=True, want_y=True):
+        x = np.empty(self.n) if want_x else None
+        y = np.empty(self.m) if want_y else None
+        st = C.c_int32()
+        kkt = (C.c_double * 4)()
+        obj = C.c_double()
+        it = C.c_int64()
+        self._check(lib.pdlpb_get(self._h, int(j), _ptr(x), _ptr(y), C.byref(st), kkt,
+                                  C.byref(obj), C.byref(it), MEM_HOST))
+        return dict(x=x, y=y, status=st.value, kkt=list(kkt), obj=obj.value, iters=it.value)
+
+    def get_batch(self, want_x=True, want_y=True, X=None, Y=None, mem: int = MEM_HOST):
+        B = self.B
+        if mem == MEM_HOST:
+            X = np.empty((B, self.n)) if want_x else None
+            Y = np.empty((B, self.m)) if want_y else None
+        status = np.empty(B, dtype=np.int32)
+        kkt = np.empty((B, 4))
+        obj = np.empty(B)
+        iters = np.empty(B, dtype=np.int64)
+        self._check(lib.pdlpb_get_batch(
+            self._h, _ptr(X), _ptr(Y), status.ctypes.data_as(C.POINTER(C.c_int32)),
+            kkt.ctypes.data_as(C.POINTER(C.c_double)), obj.ctypes.data_as(C.POINTER(C.c_double)),
+            iters.ctypes.data_as(C.POINTER(C.c_int64)), int(mem)))
+        return dict(X=X, Y=Y, status=status, kkt=kkt, obj=obj, iters=iters)
+
+    def get_trace(self, j: int, log_cap: int = 64):
+        x = np.empty(self.n)
+        y = np.empty(self.m)
+        w = C.c_double()
+        nr = C.c_int32()
+        log = (C.c_int32 * log_cap)()
+        self._check(lib.pdlpb_get_trace(self._h, int(j), x.ctypes.data_as(C.POINTER(C.c_double)),
+                                        y.ctypes.data_as(C.POINTER(C.c_double)), C.byref(w),
+                                        C.byref(nr), log, log_cap))
+        k = min(nr.value, log_cap)
+        return dict(x_iter=x, y_iter=y, w=w.value, restarts=nr.value, restart_log=list(log[:k]))
+
+    def set_kernel_timing(self, enable: bool):
+        self._check(lib.pdlpb_set_kernel_timing(self._h, int(bool(enable))))
+
+    def kernel_times(self):
+        cnt = (C.c_int64 * 4)()
+        ms = (C.c_double * 4)()
+        self._check(lib.pdlpb_kernel_times(self._h, cnt, ms))
+        return list(cnt), list(ms)

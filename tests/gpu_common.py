@@ -1,0 +1,63 @@
+"""Helpers shared by the GPU parity tests: build a library context and the
+matching reference LPs from one seeded instance, and compare results."""
+from __future__ import annotations
+
+import functools
+
+import numpy as np
+
+import oracle as O
+from workloads import (make_cfg1, make_cfg2, choose_fractional, fsb_deltas, seed_for)
+
+ITER_RTOL = 1e-9          # relative error on iterates after a fixed iteration count (FP64)
+
+
+def rel_err(a, b) -> float:
+    a, b = np.asarray(a, dtype=np.float64), np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1.0))
+
+
+def lp_for(base_lp, delta):
+    return O.apply_delta(base_lp, int(delta["kind"]), int(delta["var"]), float(delta["value"]))
+
+
+def make_ctx(inst, eta=None, **kw):
+    import paper_2601_21990_amd.pdlpb as P
+    opts = {}
+    if eta is not None:
+        opts["step_size"] = float(eta)
+    opts.update(kw)
+    return P.Context.from_instance(inst, **opts)
+
+
+@functools.lru_cache(maxsize=None)
+def cfg2_setup(m=2000, n=5000, p=32):
+    """Strong-branching batch: base LP solved by the reference solver to 1e-6,
+    2p bound changes on fractional variables, warm start from the base."""
+    inst = make_cfg2(m=m, n=n)
+    lp = O.from_instance(inst)
+    eta = O.step_size(lp.A)
+    base = O.solve(lp, O.Options(tol=1e-6, step_size=eta))
+    vars_ = choose_fractional(base.x, p, seed_for(2, 0))
+    D = fsb_deltas(base.x, vars_)
+    return inst, lp, eta, base, D
+
+
+def oracle_run(lp, eta, tol, max_iters, x0=None, y0=None, w0=None, **kw):
+    return O.solve(lp, O.Options(tol=tol, max_iters=max_iters, step_size=eta, **kw),
+                   x_init=x0, y_init=y0, w_init=w0)
+
+
+def assert_trajectory_match(gpu_res, gpu_trace, ores, rtol=ITER_RTOL, what=""):
+    assert gpu_res["status"] == ores.status, (what, gpu_res["status"], ores.status)
+    assert gpu_res["iters"] == ores.iters, (what, gpu_res["iters"], ores.iters)
+    assert gpu_trace["restart_log"] == ores.restarts[:64], (what, gpu_trace["restart_log"],
+                                                            ores.restarts)
+    ex = rel_err(gpu_res["x"], ores.x)
+    ey = rel_err(gpu_res["y"], ores.y)
+    assert ex <= rtol and ey <= rtol, (what, ex, ey)
+    if ores.x_iter is not None:
+        exi = rel_err(gpu_trace["x_iter"], ores.x_iter)
+        eyi = rel_err(gpu_trace["y_iter"], ores.y_iter)
+        assert exi <= rtol and eyi <= rtol, (what, exi, eyi)
+    return max(ex, ey)
