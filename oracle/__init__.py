@@ -20,7 +20,8 @@ constants beta_s, beta_n, beta_a, theta (named, not valued, in the paper).
 from .lp import LP, row_bounds, from_arrays, from_instance, apply_delta, BASE, SET_LO, SET_HI, OBJ_UNIT
 from .pdhg import (Options, Result, KKT, solve, solve_batch_avg, pdhg_operator,
                    fixed_point_residual, kkt, reduced_cost, proj_box, support,
-                   proj_barrier_cone, opnorm, step_size, initial_primal_weight,
+                   proj_barrier_cone, proj_recession_cone, infeasibility, Infeasibility, opnorm, step_size, initial_primal_weight,
                    smoothed_primal_weight, restart_due,
                    RUNNING, OPTIMAL, ITERATION_LIMIT, INFEASIBLE_BOUNDS, NUMERICAL_ERROR,
+                   PRIMAL_INFEASIBLE, DUAL_INFEASIBLE,
                    STATUS_NAMES)

@@ -25,9 +25,12 @@ OPTIMAL = 1
 ITERATION_LIMIT = 2
 INFEASIBLE_BOUNDS = 3
 NUMERICAL_ERROR = 4
+PRIMAL_INFEASIBLE = 6
+DUAL_INFEASIBLE = 7
 
 STATUS_NAMES = {RUNNING: "RUNNING", OPTIMAL: "OPTIMAL", ITERATION_LIMIT: "ITERATION_LIMIT",
-                INFEASIBLE_BOUNDS: "INFEASIBLE_BOUNDS", NUMERICAL_ERROR: "NUMERICAL_ERROR"}
+                INFEASIBLE_BOUNDS: "INFEASIBLE_BOUNDS", NUMERICAL_ERROR: "NUMERICAL_ERROR",
+                PRIMAL_INFEASIBLE: "PRIMAL_INFEASIBLE", DUAL_INFEASIBLE: "DUAL_INFEASIBLE"}
 
 
 # ---------------------------------------------------------------------------
@@ -60,6 +63,23 @@ def proj_barrier_cone(v: np.ndarray, a: np.ndarray, b: np.ndarray) -> np.ndarray
     hi_inf = np.isposinf(b)
     out[lo_inf] = np.maximum(out[lo_inf], 0.0)
     out[hi_inf] = np.minimum(out[hi_inf], 0.0)
+    return out
+
+
+def proj_recession_cone(v: np.ndarray, a: np.ndarray, b: np.ndarray) -> np.ndarray:
+    """Projection onto the recession cone of the box [a, b] (Section 4, infeasibility
+    detection).  The printed definition lists v_i >= 0 when b_i = +inf and v_i <= 0
+    when the lower end is -inf, 0 otherwise, which contradicts itself for a free
+    coordinate.  Reading: free coordinate (both ends infinite) -> unconstrained;
+    only b_i = +inf -> v_i >= 0; only a_i = -inf -> v_i <= 0; both finite -> 0."""
+    out = np.array(v, dtype=np.float64, copy=True)
+    lo_inf = np.isneginf(a)
+    hi_inf = np.isposinf(b)
+    out[~lo_inf & ~hi_inf] = 0.0
+    up = hi_inf & ~lo_inf
+    dn = lo_inf & ~hi_inf
+    out[up] = np.maximum(out[up], 0.0)
+    out[dn] = np.minimum(out[dn], 0.0)
     return out
 
 
@@ -135,19 +155,62 @@ def kkt(lp: LP, x: np.ndarray, y: np.ndarray) -> KKT:
     return KKT(gap=gap, primal=primal, dual=dual, rel=rel, obj=cx, dual_obj=-phis)
 
 
+@dataclass
+class Infeasibility:
+    primal: bool
+    dual: bool
+    primal_ratio: float     # ||A'dy + dr|| / |phi(dy) + phi(dr)|   (inf when phi >= 0)
+    dual_ratio: float       # max of the two recession residuals / |c'dx|  (inf when c'dx >= 0)
+
+
+def infeasibility(lp: LP, x, y, x_t, y_t, eps: float) -> Infeasibility:
+    """eps-approximate infeasibility tests of Section 4 (eq:primal-infeas,
+    eq:dual-infeas) on the displacement of one application of T:
+        dx = x~ - x,  dy = Pi_B[l,u](y~ - y),  dr = Pi_B[xl,xu](r~ - r),
+    r = Pi_B[xl,xu](-c - A'y), r~ = Pi_B[xl,xu](-c - A'y~).
+      primal infeasible:  phi_[l,u](dy) + phi_box(dr) < 0  and
+                          ||A'dy + dr|| <= eps |phi_[l,u](dy) + phi_box(dr)|
+      dual infeasible:    c'dx < 0,  ||dx - Pi_R[xl,xu](dx)|| <= eps |c'dx|,
+                          ||A dx - Pi_R[l,u](A dx)|| <= eps |c'dx|.
+    The printed right-hand side of the second primal test, eps(phi(dy) + phi(dr)),
+    is negative whenever the first test holds; reading: its absolute value."""
+    r = reduced_cost(lp, y)
+    r_t = reduced_cost(lp, y_t)
+    dx = x_t - x
+    dy = proj_barrier_cone(y_t - y, lp.l, lp.u)
+    dr = proj_barrier_cone(r_t - r, lp.xl, lp.xu)
+    phi = support(dy, lp.l, lp.u) + support(dr, lp.xl, lp.xu)
+    if phi < 0.0:
+        pr = float(np.linalg.norm(lp.A.T @ dy + dr)) / abs(phi)
+    else:
+        pr = float("inf")
+    cdx = float(lp.c @ dx)
+    if cdx < 0.0:
+        adx = lp.A @ dx
+        res = max(float(np.linalg.norm(dx - proj_recession_cone(dx, lp.xl, lp.xu))),
+                  float(np.linalg.norm(adx - proj_recession_cone(adx, lp.l, lp.u))))
+        dr_ = res / abs(cdx)
+    else:
+        dr_ = float("inf")
+    return Infeasibility(primal=pr <= eps, dual=dr_ <= eps, primal_ratio=pr, dual_ratio=dr_)
+
+
 # ---------------------------------------------------------------------------
 # step size, primal weight, restart rule (Section 4)
 # ---------------------------------------------------------------------------
 
 def opnorm(A, tol: float = 1e-14, maxit: int = 10000) -> float:
     """Spectral norm ||A||_2 for the constant step size.  The paper does not say
-    how it is computed; this is power iteration on A'A from the normalised
-    all-ones vector, stopped when the eigenvalue estimate changes by at most
-    `tol` relative (or after `maxit` products)."""
+    how it is computed; this is power iteration on A'A, stopped when the
+    eigenvalue estimate changes by at most `tol` relative (or after `maxit`
+    products).  The start vector is v_j = 1 + frac(j g), g = (sqrt(5)-1)/2 (a
+    Weyl sequence), normalised: a constant start vector lies in the null space
+    of matrices whose rows sum to zero (e.g. A = [1, -1])."""
     n = A.shape[1]
     if n == 0 or A.nnz == 0:
         return 0.0
-    v = np.full(n, 1.0 / math.sqrt(n))
+    v = 1.0 + np.modf(np.arange(n, dtype=np.float64) * 0.6180339887498949)[0]
+    v = v / np.linalg.norm(v)
     lam_old = 0.0
     lam = 0.0
     for _ in range(maxit):
@@ -225,6 +288,7 @@ class Options:
     step_size: Optional[float] = None    # eta; None -> 0.998/||A||_2
     cross_sign: float = -1.0
     pw_ratio: str = "dy/dx"
+    infeas_tol: float = 1e-8        # eps of the infeasibility tests; 0 disables them
 
 
 @dataclass
@@ -243,6 +307,15 @@ class Result:
     @property
     def obj(self) -> float:
         return self.kkt.obj if self.kkt is not None else float("nan")
+
+
+def _infeasible_status(inf: Infeasibility) -> int:
+    """Primal infeasibility is reported first when both tests pass."""
+    if inf.primal:
+        return PRIMAL_INFEASIBLE
+    if inf.dual:
+        return DUAL_INFEASIBLE
+    return 0
 
 
 def _halpern(k: int, x_t, x, x_anchor):
@@ -264,8 +337,10 @@ def solve(lp: LP, opt: Options = Options(), x_init=None, y_init=None,
         is smoothed from the anchor displacement, k returns to 0 and the
         iteration counts as spent;
       * the LP stops OPTIMAL when max(gap, primal, dual) <= tol at an evaluation
-        point, and ITERATION_LIMIT after max_iters applications of T; either
-        way it returns z~ of its last iteration.
+        point, PRIMAL_INFEASIBLE / DUAL_INFEASIBLE when the infeasibility tests
+        pass there (after the stopping test), and ITERATION_LIMIT after
+        max_iters applications of T; in every case it returns z~ of its last
+        iteration.
     """
     n, m = lp.n, lp.m
     if np.any(lp.xl > lp.xu):
@@ -300,6 +375,11 @@ def solve(lp: LP, opt: Options = Options(), x_init=None, y_init=None,
         if kk is not None and kk.rel <= opt.tol:
             return Result(OPTIMAL, x_t, y_t, _halpern(k, x_t, x, x_a), _halpern(k, y_t, y, y_a),
                           t + 1, restarts, w, eta, kk)
+        if full and opt.infeas_tol > 0.0:
+            st = _infeasible_status(infeasibility(lp, x, y, x_t, y_t, opt.infeas_tol))
+            if st:
+                return Result(st, x_t, y_t, _halpern(k, x_t, x, x_a), _halpern(k, y_t, y, y_a),
+                              t + 1, restarts, w, eta, kk)
         if t + 1 >= opt.max_iters:
             return Result(ITERATION_LIMIT, x_t, y_t, _halpern(k, x_t, x, x_a),
                           _halpern(k, y_t, y, y_a), t + 1, restarts, w, eta,
@@ -373,6 +453,11 @@ def solve_batch_avg(lps: Sequence[LP], opt: Options = Options(), x_inits=None, y
                                 s["eta"], kk or kkt(lps[j], x_t, y_t))
             elif kk is not None and kk.rel <= opt.tol:
                 res[j] = Result(OPTIMAL, x_t, y_t, hx(), hy(), t + 1, s["restarts"], s["w"], s["eta"], kk)
+            elif full and opt.infeas_tol > 0.0 and _infeasible_status(
+                    infeasibility(lps[j], s["x"], s["y"], x_t, y_t, opt.infeas_tol)):
+                st = _infeasible_status(infeasibility(lps[j], s["x"], s["y"], x_t, y_t,
+                                                      opt.infeas_tol))
+                res[j] = Result(st, x_t, y_t, hx(), hy(), t + 1, s["restarts"], s["w"], s["eta"], kk)
             elif t + 1 >= opt.max_iters:
                 res[j] = Result(ITERATION_LIMIT, x_t, y_t, hx(), hy(), t + 1, s["restarts"], s["w"],
                                 s["eta"], kk or kkt(lps[j], x_t, y_t))

@@ -163,7 +163,7 @@ void free_all(pdlpb_ctx* x) {
 }
 
 // ---- step size: power iteration on A'A (float64, on the device) -------------
-// ||A||_2 = sqrt(lambda_max(A'A)); start from the normalised all-ones vector,
+// ||A||_2 = sqrt(lambda_max(A'A)); start from a normalised Weyl-sequence vector,
 // stop when the eigenvalue estimate changes by at most 1e-14 relative, or after
 // 10^4 products.  Estimates are read back 32 iterations at a time.
 int compute_opnorm(pdlpb_ctx* x, double* out) {
@@ -180,7 +180,21 @@ int compute_opnorm(pdlpb_ctx* x, double* out) {
     double* tmp = w + n;
     double* part = tmp + m;
     double* lam2 = part + 1024;   // CH estimates of lambda^2
-    HIP_TRY(x, launch_fill(v, n, 1.0 / std::sqrt((double)n), x->stream));
+    {   // start vector v_j = 1 + frac(j g), g = (sqrt(5)-1)/2, normalised; a constant
+        // vector is in the null space of matrices whose rows sum to zero
+        std::vector<double> hv(n);
+        double s2 = 0.0;
+        for (int32_t j = 0; j < n; ++j) {
+            const double t = (double)j * 0.6180339887498949;
+            hv[j] = 1.0 + (t - std::floor(t));
+            s2 += hv[j] * hv[j];
+        }
+        const double inv = 1.0 / std::sqrt(s2);
+        for (double& e : hv) e *= inv;
+        HIP_TRY(x, hipMemcpyAsync(v, hv.data(), sizeof(double) * n, hipMemcpyHostToDevice,
+                                  x->stream));
+        HIP_TRY(x, hipStreamSynchronize(x->stream));
+    }
     double lam_old = 0.0;
     double lam = 0.0;
     std::vector<double> h(CH);

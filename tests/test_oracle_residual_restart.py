@@ -124,3 +124,8 @@ def test_initial_primal_weight():
                         np.linalg.norm(lp.c) / np.linalg.norm(lp.b), rel_tol=1e-14)
     lp.c = np.zeros(lp.n)
     assert O.initial_primal_weight(lp) == 1.0
+
+
+def test_opnorm_when_constant_vector_is_in_null_space():
+    A = sp.csr_matrix(np.array([[1.0, -1.0], [2.0, -2.0]]))
+    assert math.isclose(O.opnorm(A), np.linalg.norm(A.toarray(), 2), rel_tol=1e-12)
