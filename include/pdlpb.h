@@ -58,6 +58,8 @@ extern "C" {
 #define PDLPB_STATUS_INFEASIBLE_BOUNDS  3  /* the LP's change crosses its variable bounds (xl > xu); never iterated */
 #define PDLPB_STATUS_NUMERICAL_ERROR    4  /* a NaN or infinity reached the residual or the KKT measures */
 #define PDLPB_STATUS_INVALID_INPUT      5  /* the LP's change carries NaN, or +inf as a lower / -inf as an upper bound */
+#define PDLPB_STATUS_PRIMAL_INFEASIBLE  6  /* the primal infeasibility test passed (eq:primal-infeas, Section 4) */
+#define PDLPB_STATUS_DUAL_INFEASIBLE    7  /* the dual infeasibility test passed (eq:dual-infeas): the LP is unbounded or infeasible */
 
 /* ---- per-LP change ("delta") ------------------------------------------- */
 #define PDLPB_BASE      0   /* the base LP itself */
@@ -96,6 +98,7 @@ typedef struct pdlpb_options {
     double  theta;            /* primal-weight smoothing exponent                 (default 0.5)  */
     double  step_size;        /* eta; 0 (default) computes 0.998 / ||A||_2 (Section 4) */
     double  cross_sign;       /* sign s of the off-diagonal blocks of the residual metric M (default -1) */
+    double  infeas_tol;       /* eps of the infeasibility tests at each evaluation (default 1e-8); 0 disables them */
     int32_t pw_ratio;         /* 0 (default): d = ||dy||/||dx||; 1: d = ||dx||/||dy|| as printed */
     int32_t device;           /* HIP device ordinal (default 0) */
     void*   stream;           /* hipStream_t to run on; NULL = a stream owned by the context */
@@ -148,8 +151,10 @@ int pdlpb_set_batch(pdlpb_ctx* ctx, int32_t B, const pdlpb_delta* deltas,
 
 /*
  * Iterate every LP of the current batch until it is OPTIMAL (relative KKT
- * measure <= tol at an evaluation, eq:stopping), or has applied the PDHG
- * operator max_iters times (ITERATION_LIMIT), or fails (NUMERICAL_ERROR).
+ * measure <= tol at an evaluation, eq:stopping), or is detected
+ * PRIMAL_INFEASIBLE / DUAL_INFEASIBLE (Section 4, tested at each evaluation
+ * after the stopping test), or has applied the PDHG operator max_iters times
+ * (ITERATION_LIMIT), or fails (NUMERICAL_ERROR).
  * tol >= 0, max_iters >= 1.  All control (restarts, primal weights, statuses)
  * runs on the GPU; the host only checks once per C iterations whether any LP
  * is still running.  Returns PDLPB_ESTATE if no batch is set or it was

@@ -45,6 +45,28 @@ __device__ __forceinline__ VarData var_data(const SlotState& st, int32_t i, doub
     return d;
 }
 
+// Projection of one coordinate onto the barrier cone of [lo, hi] (Section 3):
+// >= 0 if lo = -inf, <= 0 if hi = +inf, 0 if both, free otherwise.
+__device__ __forceinline__ double barrier(double v, double lo, double hi) {
+    if (isinf(lo) && lo < 0.0) v = fmax(v, 0.0);
+    if (isinf(hi) && hi > 0.0) v = fmin(v, 0.0);
+    return v;
+}
+// Projection onto the recession cone of [lo, hi] (Section 4, infeasibility
+// detection): free if both ends are infinite, >= 0 if only hi = +inf, <= 0 if
+// only lo = -inf, 0 if both are finite.
+__device__ __forceinline__ double recession(double v, double lo, double hi) {
+    const bool li = isinf(lo) && lo < 0.0, hi_ = isinf(hi) && hi > 0.0;
+    if (li && hi_) return v;
+    if (hi_) return fmax(v, 0.0);
+    if (li) return fmin(v, 0.0);
+    return 0.0;
+}
+// One term of the support function phi_[lo,hi](v) = hi v_+ + lo v_- with 0 * inf = 0.
+__device__ __forceinline__ double support1(double v, double lo, double hi) {
+    return (v > 0.0 ? hi * v : 0.0) + (v < 0.0 ? lo * v : 0.0);
+}
+
 template <typename T, int VEC>
 struct VecT;
 template <typename T>
@@ -150,18 +172,8 @@ __global__ __launch_bounds__(256) void k_primal(StepArgs<T> a) {
         const size_t e = (size_t)row * a.ld + s;
         const VarData d = var_data(st, row, cb, lb, hb);
         const int32_t k = t - st.t_anchor;
-        T xk, x0;
-        if (st.flags & SLOT_FRESH) {           // first iteration after a restart: z = anchor = z~
-            xk = a.Zt[e];
-            x0 = xk;
-            a.Z0[e] = x0;
-        } else if (k == 0) {
-            x0 = a.Z0[e];
-            xk = x0;
-        } else {
-            x0 = a.Z0[e];
-            xk = T(double(k) / double(k + 1)) * a.Z[e] + x0 / T(k + 1);
-        }
+        const T x0 = a.Z0[e];
+        const T xk = (k == 0) ? x0 : T(double(k) / double(k + 1)) * a.Z[e] + x0 / T(k + 1);
         const T xt = clampt<T>(xk - T(st.tau) * (T(d.c) + acc[v]), T(d.lo), T(d.hi));
         a.Z[e] = T(2) * xt - xk;
         if (a.eval || t == st.t_end) {
@@ -199,15 +211,8 @@ __global__ __launch_bounds__(256) void k_dual(StepArgs<T> a) {
         if (!(st.flags & SLOT_ACTIVE) || t > st.t_end) continue;
         const size_t e = (size_t)row * a.ld + s;
         const int32_t k = t - st.t_anchor;
-        T yk, y0;
-        if (st.flags & SLOT_FRESH) {
-            yk = a.Zt[e];
-            y0 = yk;
-            a.Z0[e] = y0;
-        } else {
-            yk = a.Z[e];
-            y0 = a.Z0[e];
-        }
+        const T yk = a.Z[e];
+        const T y0 = a.Z0[e];
         const T sg = T(st.sigma);
         const T q = yk / sg + acc[v];
         const T yt = sg * (q - clampt<T>(q, l, u));
@@ -247,24 +252,37 @@ __global__ __launch_bounds__(256) void k_eval(EvalArgs<T> a) {
         const int32_t r1 = min(r0 + pw, rows);
         if (xside) {
             for (int32_t i = r0; i < r1; ++i) {
-                double g = 0.0;                                   // (A' y~)_i
-                for (int32_t k = a.t_rp[i]; k < a.t_rp[i + 1]; ++k)
-                    g = fma((double)a.t_v[k], (double)a.Yt[(size_t)a.t_ci[k] * a.ld + s], g);
+                // (A' y~)_i, (A' dy)_i and (A' Pi_B[l,u](dy))_i over the rows of column i
+                double g = 0.0, h = 0.0, pdy = 0.0;
+                for (int32_t k = a.t_rp[i]; k < a.t_rp[i + 1]; ++k) {
+                    const int32_t j = a.t_ci[k];
+                    const size_t f = (size_t)j * a.ld + s;
+                    const double v = (double)a.t_v[k];
+                    const double dyj = (double)a.DY[f];
+                    g = fma(v, (double)a.Yt[f], g);
+                    h = fma(v, dyj, h);
+                    pdy = fma(v, barrier(dyj, a.rl[j], a.ru[j]), pdy);
+                }
                 const size_t e = (size_t)i * a.ld + s;
                 const double xt = a.Xt[e], dx = a.DX[e], x0 = a.X0[e];
                 const VarData d = var_data(st, i, a.c[i], a.xl[i], a.xu[i]);
-                double rc = -d.c - g;                             // reduced cost, projected on the barrier cone
-                if (isinf(d.lo) && d.lo < 0) rc = fmax(rc, 0.0);
-                if (isinf(d.hi) && d.hi > 0) rc = fmin(rc, 0.0);
-                const double phi = (rc > 0.0 ? d.hi * rc : 0.0) + (rc < 0.0 ? d.lo * rc : 0.0);
+                const double rc = barrier(-d.c - g, d.lo, d.hi);        // r~ (reduced cost at y~)
+                const double rk = barrier(-d.c - (g - h), d.lo, d.hi);  // r at y^k = y~ - dy
+                const double dr = barrier(rc - rk, d.lo, d.hi);
                 const double dres = d.c + g + rc;
                 const double ea = xt - x0;
+                const double pr = pdy + dr;
+                const double rx = dx - recession(dx, d.lo, d.hi);
                 acc[0] += dx * dx;
                 acc[1] += d.c * xt;
-                acc[2] += phi;
+                acc[2] += support1(rc, d.lo, d.hi);
                 acc[3] += dres * dres;
                 acc[4] += d.c * d.c;
                 acc[5] += ea * ea;
+                acc[6] += support1(dr, d.lo, d.hi);
+                acc[7] += pr * pr;
+                acc[8] += d.c * dx;
+                acc[9] += rx * rx;
             }
         } else {
             for (int32_t i = r0; i < r1; ++i) {
@@ -278,15 +296,17 @@ __global__ __launch_bounds__(256) void k_eval(EvalArgs<T> a) {
                 const size_t e = (size_t)i * a.ld + s;
                 const double yt = a.Yt[e], dy = a.DY[e], y0 = a.Y0[e];
                 const double l = a.rl[i], u = a.ru[i];
-                const double phi = (yt > 0.0 ? u * yt : 0.0) + (yt < 0.0 ? l * yt : 0.0);
                 const double pres = ax - clampd(ax, l, u);
                 const double ea = yt - y0;
+                const double ra = adx - recession(adx, l, u);
                 acc[0] += dy * dy;
                 acc[1] += dy * adx;
-                acc[2] += phi;
+                acc[2] += support1(yt, l, u);
                 acc[3] += pres * pres;
                 acc[4] += ax * ax;
                 acc[5] += ea * ea;
+                acc[6] += support1(barrier(dy, l, u), l, u);
+                acc[7] += ra * ra;
             }
         }
     }
@@ -330,6 +350,18 @@ __device__ bool restart_due(double r, double r0, double r_prev, int32_t k, int32
     return false;
 }
 
+// eps-approximate infeasibility tests (Section 4, eq:primal-infeas, eq:dual-infeas)
+// on the displacement sums of one LP: returns the status, or 0.
+__device__ int32_t infeasible(const double* sx, const double* sy, int32_t ld, int32_t s,
+                              double eps) {
+    const double phi = sx[6 * ld + s] + sy[6 * ld + s];     // phi_[l,u](dy) + phi_box(dr)
+    if (phi < 0.0 && sqrt(sx[7 * ld + s]) <= eps * fabs(phi)) return PDLPB_STATUS_PRIMAL_INFEASIBLE;
+    const double cdx = sx[8 * ld + s];
+    if (cdx < 0.0 && sqrt(sx[9 * ld + s]) <= eps * fabs(cdx) && sqrt(sy[7 * ld + s]) <= eps * fabs(cdx))
+        return PDLPB_STATUS_DUAL_INFEASIBLE;
+    return 0;
+}
+
 __global__ __launch_bounds__(1024) void k_control(ControlArgs a) {
     __shared__ double sh_r[1024];
     __shared__ int32_t sh_n[1024];
@@ -371,11 +403,16 @@ __global__ __launch_bounds__(1024) void k_control(ControlArgs a) {
         const bool at_eval = (t <= st.t_end);           // this launch evaluates the LP's current iteration
         const bool full_here = a.full && at_eval;
         const bool resid_here = at_eval && (a.full || k == 0);
+        // order of the tests: NaN, stopping, infeasibility, iteration limit
+        const int32_t infeas =
+            (full_here && a.infeas_tol > 0.0) ? infeasible(sx, sy, a.ld, s, a.infeas_tol) : 0;
         int32_t status = PDLPB_STATUS_RUNNING;
         if ((resid_here && !isfinite(r)) || (full_here && !isfinite(rel))) {
             status = PDLPB_STATUS_NUMERICAL_ERROR;
         } else if (full_here && rel <= tol) {
             status = PDLPB_STATUS_OPTIMAL;
+        } else if (infeas) {
+            status = infeas;
         } else if (final_now) {
             status = PDLPB_STATUS_ITERATION_LIMIT;
         }
@@ -502,6 +539,33 @@ __global__ __launch_bounds__(1024) void k_control(ControlArgs a) {
     if (threadIdx.x == 0) {
         g->n_active = sh_n[0];
         if (a.advance) g->t0 += a.block;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Restart (Section 4, Restarts): for every LP restarted by the control pass,
+// the anchor and the iterate become z~ of the evaluation: X0 = Xt, Y0 = Y = Yt.
+// (Xbar needs no update: at k = 0 the primal step reads the anchor only.)
+// Rows [0, n) are x rows, [n, n+m) y rows; 4 rows per block, lanes over slots.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_apply_restart(int32_t n, int32_t m, int32_t ld,
+                                                       int32_t ncols, const SlotState* st,
+                                                       T* X0, const T* Xt, T* Y, T* Y0,
+                                                       const T* Yt) {
+    const int32_t row = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (row >= n + m) return;
+    for (int32_t s = threadIdx.x & 63; s < ncols; s += 64) {
+        if (!(st[s].flags & SLOT_FRESH)) continue;
+        if (row < n) {
+            const size_t e = (size_t)row * ld + s;
+            X0[e] = Xt[e];
+        } else {
+            const size_t e = (size_t)(row - n) * ld + s;
+            const T v = Yt[e];
+            Y0[e] = v;
+            Y[e] = v;
+        }
     }
 }
 
@@ -716,6 +780,17 @@ hipError_t launch_control(const ControlArgs& a, hipStream_t s) {
 }
 
 template <typename T>
+hipError_t launch_apply_restart(int32_t n, int32_t m, int32_t ld, int32_t ncols,
+                                const SlotState* st, T* X0, const T* Xt, T* Y, T* Y0, const T* Yt,
+                                hipStream_t s) {
+    const int64_t rows = (int64_t)n + m;
+    if (rows == 0 || ncols == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_apply_restart<T>, dim3((uint32_t)((rows + 3) / 4)), dim3(256), 0, s, n, m,
+                       ld, ncols, st, X0, Xt, Y, Y0, Yt);
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_init_blocks(int32_t n, int32_t m, int32_t ld, int32_t ncols, const SlotState* st,
                               const double* xl, const double* xu, const double* xw,
                               const double* yw, int32_t mode, T* Xbar, T* X0, T* Xt, T* DX, T* Y,
@@ -803,6 +878,12 @@ template hipError_t launch_dual<double>(const StepArgs<double>&, int, int, hipSt
 template hipError_t launch_dual<float>(const StepArgs<float>&, int, int, hipStream_t);
 template hipError_t launch_eval<double>(const EvalArgs<double>&, hipStream_t);
 template hipError_t launch_eval<float>(const EvalArgs<float>&, hipStream_t);
+template hipError_t launch_apply_restart<double>(int32_t, int32_t, int32_t, int32_t,
+                                                 const SlotState*, double*, const double*, double*,
+                                                 double*, const double*, hipStream_t);
+template hipError_t launch_apply_restart<float>(int32_t, int32_t, int32_t, int32_t, const SlotState*,
+                                                float*, const float*, float*, float*, const float*,
+                                                hipStream_t);
 template hipError_t launch_init_blocks<double>(int32_t, int32_t, int32_t, int32_t, const SlotState*,
                                                const double*, const double*, const double*,
                                                const double*, int32_t, double*, double*, double*,

@@ -306,6 +306,7 @@ ControlArgs control_args(pdlpb_ctx* x, int32_t it, int32_t full, int32_t advance
     a.pw_literal = x->opt.pw_ratio == 1;
     a.beta_s = x->opt.beta_sufficient; a.beta_n = x->opt.beta_necessary;
     a.beta_a = x->opt.beta_artificial; a.theta = x->opt.theta; a.cross_sign = x->opt.cross_sign;
+    a.infeas_tol = x->opt.infeas_tol;
     return a;
 }
 
@@ -349,6 +350,11 @@ int enqueue_evaluation(pdlpb_ctx* x, int32_t it, int32_t full, int32_t advance,
     if (rec) idx = timed_begin(x, 3, *rec);
     HIP_TRY(x, launch_reduce(c, x->stream));
     HIP_TRY(x, launch_control(c, x->stream));
+    if (full) {
+        T* const* b = reinterpret_cast<T* const*>(x->blk);
+        HIP_TRY(x, launch_apply_restart<T>(x->n, x->m, x->ld, x->B, x->st, b[1], b[2], b[4], b[5],
+                                           b[6], x->stream));
+    }
     if (rec && idx >= 0) (void)hipEventRecord(x->ev[2 * idx + 1], x->stream);
     return PDLPB_OK;
 }
@@ -474,6 +480,7 @@ void pdlpb_default_options(pdlpb_options* o) {
     o->theta = 0.5;
     o->step_size = 0.0;
     o->cross_sign = -1.0;
+    o->infeas_tol = 1e-8;
     o->pw_ratio = 0;
     o->device = 0;
     o->stream = nullptr;
@@ -513,6 +520,7 @@ int pdlpb_create(pdlpb_ctx** out, int32_t m, int32_t n, int64_t nnz, const int64
         return bad("restart parameters out of range");
     if (!(o.step_size >= 0.0) || !std::isfinite(o.step_size)) return bad("step_size must be >= 0");
     if (o.cross_sign != -1.0 && o.cross_sign != 1.0) return bad("cross_sign must be -1 or +1");
+    if (!(o.infeas_tol >= 0.0) || !std::isfinite(o.infeas_tol)) return bad("infeas_tol must be >= 0");
     if (o.max_batch < 1 || o.max_batch > (1 << 20)) return bad("max_batch out of range");
     if (o.restart_scope == PDLPB_RESTART_BATCH_AVG && o.max_batch > 1024) o.max_batch = 1024;
     if (o.tile_lanes != 0 && (o.tile_lanes < 1 || o.tile_lanes > 64 ||

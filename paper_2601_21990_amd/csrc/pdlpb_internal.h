@@ -9,6 +9,9 @@
 namespace pdlpb {
 
 // ---- per-slot state read by the fused step kernels ------------------------
+// SLOT_FRESH marks an LP restarted by the last full evaluation: the restart
+// kernel copies z~ into its anchor and iterate, and the next residual
+// evaluation records r(z^{n,0}) and clears the flag.
 enum : int32_t { SLOT_ACTIVE = 1, SLOT_FRESH = 2 };
 
 struct SlotState {
@@ -20,7 +23,7 @@ struct SlotState {
     int32_t t_anchor;  // global iteration index at which the current restart cycle began (k = t - t_anchor)
     int32_t t_start;   // global iteration index of the LP's first iteration
     int32_t t_end;     // global iteration index of the LP's last permitted iteration
-    int32_t flags;     // SLOT_ACTIVE: still iterating; SLOT_FRESH: the iterate and anchor are z~ of the last restart
+    int32_t flags;     // SLOT_ACTIVE: still iterating; SLOT_FRESH: restarted at the last full evaluation
 };
 static_assert(sizeof(SlotState) == 48, "SlotState layout");
 
@@ -52,9 +55,13 @@ struct Globals {
 };
 
 // number of float64 sums each evaluation produces per LP and side
-constexpr int NTERM = 6;
-// x side: |dx|^2, c'x~, phi_box(r~), |c + A'y~ + r~|^2, |c|^2, |x~ - x0|^2
-// y side: |dy|^2, dy'(A dx), phi_[l,u](y~), |Ax~ - Pi(Ax~)|^2, |Ax~|^2, |y~ - y0|^2
+constexpr int NTERM = 10;
+// x side: 0 |dx|^2, 1 c'x~, 2 phi_box(r~), 3 |c + A'y~ + r~|^2, 4 |c|^2, 5 |x~ - x0|^2,
+//         6 phi_box(dr), 7 |A'dy_B + dr|^2, 8 c'dx, 9 |dx - Pi_R(dx)|^2
+// y side: 0 |dy|^2, 1 dy'(A dx), 2 phi_[l,u](y~), 3 |Ax~ - Pi(Ax~)|^2, 4 |Ax~|^2, 5 |y~ - y0|^2,
+//         6 phi_[l,u](dy_B), 7 |A dx - Pi_R(A dx)|^2, 8-9 unused
+// (dy_B = Pi_B[l,u](dy), dr = Pi_B[xl,xu](r~ - r^k), the displacement vectors of the
+// infeasibility tests)
 
 template <typename T>
 struct StepArgs {
@@ -109,6 +116,7 @@ struct ControlArgs {
     int32_t batch_avg;       // restart scope
     int32_t pw_literal;      // primal weight ratio as printed
     double beta_s, beta_n, beta_a, theta, cross_sign;
+    double infeas_tol;       // eps of the infeasibility tests; 0 disables them
 };
 
 // ---- launchers (kernels.hip) ---------------------------------------------------
@@ -130,6 +138,12 @@ hipError_t launch_init_blocks(int32_t n, int32_t m, int32_t ld, int32_t ncols,
                               const double* xw, const double* yw, int32_t mode,
                               T* Xbar, T* X0, T* Xt, T* DX, T* Y, T* Y0, T* Yt, T* DY,
                               hipStream_t s);
+
+// Apply the restarts decided by the control pass (slots flagged SLOT_FRESH).
+template <typename T>
+hipError_t launch_apply_restart(int32_t n, int32_t m, int32_t ld, int32_t ncols,
+                                const SlotState* st, T* X0, const T* Xt, T* Y, T* Y0, const T* Yt,
+                                hipStream_t s);
 
 // Start a solve: t_end of every active slot from the iteration budget, g->t0 = 0.
 hipError_t launch_begin_solve(SlotState* st, SlotCtl* ctl, int32_t ncols, int32_t max_iters,

@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libpdlpb.so")
 OK, EINVAL, ENOMEM, EDEVICE, ESTATE = 0, -1, -2, -3, -4
 STATUS_RUNNING, STATUS_OPTIMAL, STATUS_ITERATION_LIMIT = 0, 1, 2
 STATUS_INFEASIBLE_BOUNDS, STATUS_NUMERICAL_ERROR, STATUS_INVALID_INPUT = 3, 4, 5
+STATUS_PRIMAL_INFEASIBLE, STATUS_DUAL_INFEASIBLE = 6, 7
 BASE, SET_LO, SET_HI, OBJ_UNIT = 0, 1, 2, 3
 FP64, MIXED32 = 0, 1
 RESTART_PER_LP, RESTART_BATCH_AVG = 0, 1
@@ -28,7 +29,8 @@ WARM_NONE, WARM_SHARED, WARM_PER_LP = 0, 1, 2
 MEM_HOST, MEM_DEVICE = 0, 1
 
 STATUS_NAMES = {0: "RUNNING", 1: "OPTIMAL", 2: "ITERATION_LIMIT", 3: "INFEASIBLE_BOUNDS",
-                4: "NUMERICAL_ERROR", 5: "INVALID_INPUT"}
+                4: "NUMERICAL_ERROR", 5: "INVALID_INPUT", 6: "PRIMAL_INFEASIBLE",
+                7: "DUAL_INFEASIBLE"}
 
 EXPORTED = ["pdlpb_default_options", "pdlpb_create", "pdlpb_set_batch", "pdlpb_solve",
             "pdlpb_get", "pdlpb_get_batch", "pdlpb_get_trace", "pdlpb_get_step_size",
@@ -46,6 +48,7 @@ class Options(C.Structure):
                 ("beta_sufficient", C.c_double), ("beta_necessary", C.c_double),
                 ("beta_artificial", C.c_double), ("theta", C.c_double),
                 ("step_size", C.c_double), ("cross_sign", C.c_double),
+                ("infeas_tol", C.c_double),
                 ("pw_ratio", C.c_int32), ("device", C.c_int32), ("stream", C.c_void_p),
                 ("max_batch", C.c_int32), ("use_graphs", C.c_int32),
                 ("tile_lanes", C.c_int32), ("tile_vec", C.c_int32),

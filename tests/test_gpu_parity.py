@@ -100,13 +100,15 @@ def test_cfg2_batch_converged(P):
         ctx.solve(tol=1e-4, max_iters=100000)
         out = ctx.get_batch()
         traces = [ctx.get_trace(j) for j in range(len(D))]
-    assert np.all(out["status"] == P.STATUS_OPTIMAL)
-    assert np.all(out["kkt"][:, 3] <= 1e-4)
+    opt = out["status"] == P.STATUS_OPTIMAL
+    assert opt.sum() >= len(D) - 2
+    assert np.all(out["kkt"][opt, 3] <= 1e-4)
     same_traj = 0
     for j, d in enumerate(D):
         ores = oracle_run(lp_for(lp, d), eta, 1e-4, 100000, base.x, base.y, base.w)
-        assert ores.status == O.OPTIMAL
-        assert abs(out["obj"][j] - ores.obj) <= 4e-4 * (1 + abs(ores.obj)), j
+        assert out["status"][j] == ores.status, (j, out["status"][j], ores.status)
+        if ores.status == O.OPTIMAL:
+            assert abs(out["obj"][j] - ores.obj) <= 4e-4 * (1 + abs(ores.obj)), j
         if out["iters"][j] == ores.iters and traces[j]["restart_log"] == ores.restarts:
             same_traj += 1
             assert rel_err(out["X"][j], ores.x) <= ITER_RTOL
@@ -333,6 +335,37 @@ def test_batch_avg_matches_oracle(P):
             for j in range(len(D)):
                 assert_trajectory_match(ctx.get(j), ctx.get_trace(j), ores[j],
                                         rtol=1e-8, what=f"avg tol={tol} LP {j}")
+
+
+def test_infeasible_and_unbounded_lps_detected(P):
+    """Section 4 infeasibility tests on the GPU: an infeasible box-constrained
+    LP and an unbounded LP, each in a batch with a feasible neighbour."""
+    import scipy.sparse as sp
+    from workloads.generators import LPInstance
+    # rows: x0 + x1 = 5 (E), x0 - x1 <= 3 (L); box [0, 1]^2 (infeasible) / [0, 4]^2 (feasible)
+    A = sp.csr_matrix(np.array([[1.0, 1.0], [1.0, -1.0]]))
+    def inst(hi):
+        return LPInstance(m=2, n=2, row_ptr=A.indptr.astype(np.int64), col_idx=A.indices,
+                          val=A.data, c=np.array([1.0, -1.0]), b=np.array([5.0, 3.0]),
+                          sense=np.frombuffer(b"EL", dtype=np.uint8), l=np.zeros(2),
+                          u=np.full(2, hi), x0=np.zeros(2))
+    with make_ctx(inst(4.0)) as ctx:
+        ctx.set_batch(deltas([SET_HI, BASE], [0, 0], [0.5, 0.0]))   # x0 <= 0.5 -> x1 >= 4.5 > 4
+        ctx.solve(tol=1e-8, max_iters=200000)
+        out = ctx.get_batch()
+    assert list(out["status"]) == [P.STATUS_PRIMAL_INFEASIBLE, P.STATUS_OPTIMAL]
+    lp = O.apply_delta(O.from_instance(inst(4.0)), SET_HI, 0, 0.5)
+    assert O.solve(lp, O.Options(tol=1e-8, max_iters=200000)).status == O.PRIMAL_INFEASIBLE
+    # unbounded: min -x0 s.t. x0 - x1 = 0, x >= 0 with no upper bounds
+    B1 = sp.csr_matrix(np.array([[1.0, -1.0]]))
+    unb = LPInstance(m=1, n=2, row_ptr=B1.indptr.astype(np.int64), col_idx=B1.indices, val=B1.data,
+                     c=np.array([-1.0, 0.0]), b=np.zeros(1), sense=np.frombuffer(b"E", np.uint8),
+                     l=np.zeros(2), u=np.full(2, np.inf), x0=np.zeros(2))
+    with make_ctx(unb) as ctx:
+        ctx.set_batch(deltas([BASE, OBJ_UNIT], [0, 1], [0.0, 1.0]))   # min -x0 (unbounded), min x1
+        ctx.solve(tol=1e-8, max_iters=200000)
+        out = ctx.get_batch()
+    assert list(out["status"]) == [P.STATUS_DUAL_INFEASIBLE, P.STATUS_OPTIMAL]
 
 
 def test_tiny_lps_reach_exact_optimum(P):
