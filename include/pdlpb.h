@@ -98,7 +98,8 @@ typedef struct pdlpb_options {
     double  theta;            /* primal-weight smoothing exponent                 (default 0.5)  */
     double  step_size;        /* eta; 0 (default) computes 0.998 / ||A||_2 (Section 4) */
     double  cross_sign;       /* sign s of the off-diagonal blocks of the residual metric M (default -1) */
-    double  infeas_tol;       /* eps of the infeasibility tests at each evaluation (default 1e-8); 0 disables them */
+    double  infeas_tol;       /* eps of the infeasibility tests at each evaluation: < 0 (default -1) uses the
+                                 stopping tolerance of pdlpb_solve, 0 disables them, > 0 as given */
     int32_t pw_ratio;         /* 0 (default): d = ||dy||/||dx||; 1: d = ||dx||/||dy|| as printed */
     int32_t device;           /* HIP device ordinal (default 0) */
     void*   stream;           /* hipStream_t to run on; NULL = a stream owned by the context */

@@ -288,7 +288,7 @@ class Options:
     step_size: Optional[float] = None    # eta; None -> 0.998/||A||_2
     cross_sign: float = -1.0
     pw_ratio: str = "dy/dx"
-    infeas_tol: float = 1e-8        # eps of the infeasibility tests; 0 disables them
+    infeas_tol: Optional[float] = None   # eps of the infeasibility tests; None: tol; 0: off
 
 
 @dataclass
@@ -307,6 +307,13 @@ class Result:
     @property
     def obj(self) -> float:
         return self.kkt.obj if self.kkt is not None else float("nan")
+
+
+def _infeasibility_eps(opt: "Options") -> float:
+    """The infeasibility tests of Section 4 are stated with the same epsilon as
+    the stopping criteria (eq:stopping) and no separate value is given; reading:
+    the stopping tolerance unless an explicit value is set."""
+    return opt.tol if opt.infeas_tol is None else opt.infeas_tol
 
 
 def _infeasible_status(inf: Infeasibility) -> int:
@@ -359,6 +366,7 @@ def solve(lp: LP, opt: Options = Options(), x_init=None, y_init=None,
     r_prev = None
     restarts: List[int] = []
     C = opt.eval_every
+    eps_inf = _infeasibility_eps(opt)
 
     while True:
         tau, sigma = eta / w, eta * w
@@ -375,8 +383,8 @@ def solve(lp: LP, opt: Options = Options(), x_init=None, y_init=None,
         if kk is not None and kk.rel <= opt.tol:
             return Result(OPTIMAL, x_t, y_t, _halpern(k, x_t, x, x_a), _halpern(k, y_t, y, y_a),
                           t + 1, restarts, w, eta, kk)
-        if full and opt.infeas_tol > 0.0:
-            st = _infeasible_status(infeasibility(lp, x, y, x_t, y_t, opt.infeas_tol))
+        if full and eps_inf > 0.0:
+            st = _infeasible_status(infeasibility(lp, x, y, x_t, y_t, eps_inf))
             if st:
                 return Result(st, x_t, y_t, _halpern(k, x_t, x, x_a), _halpern(k, y_t, y, y_a),
                               t + 1, restarts, w, eta, kk)
@@ -427,6 +435,7 @@ def solve_batch_avg(lps: Sequence[LP], opt: Options = Options(), x_inits=None, y
         y = np.zeros(lp.m) if y_inits is None else np.array(y_inits[j], dtype=np.float64)
         state.append(dict(eta=eta, w=w, x=x, y=y, xa=x, ya=y, restarts=[]))
     active = [j for j in range(N) if state[j] is not None]
+    eps_inf = _infeasibility_eps(opt)
     k, t = 0, 0
     r0 = None
     r_prev = None
@@ -453,10 +462,9 @@ def solve_batch_avg(lps: Sequence[LP], opt: Options = Options(), x_inits=None, y
                                 s["eta"], kk or kkt(lps[j], x_t, y_t))
             elif kk is not None and kk.rel <= opt.tol:
                 res[j] = Result(OPTIMAL, x_t, y_t, hx(), hy(), t + 1, s["restarts"], s["w"], s["eta"], kk)
-            elif full and opt.infeas_tol > 0.0 and _infeasible_status(
-                    infeasibility(lps[j], s["x"], s["y"], x_t, y_t, opt.infeas_tol)):
-                st = _infeasible_status(infeasibility(lps[j], s["x"], s["y"], x_t, y_t,
-                                                      opt.infeas_tol))
+            elif full and eps_inf > 0.0 and _infeasible_status(
+                    infeasibility(lps[j], s["x"], s["y"], x_t, y_t, eps_inf)):
+                st = _infeasible_status(infeasibility(lps[j], s["x"], s["y"], x_t, y_t, eps_inf))
                 res[j] = Result(st, x_t, y_t, hx(), hy(), t + 1, s["restarts"], s["w"], s["eta"], kk)
             elif t + 1 >= opt.max_iters:
                 res[j] = Result(ITERATION_LIMIT, x_t, y_t, hx(), hy(), t + 1, s["restarts"], s["w"],

@@ -104,7 +104,12 @@ struct VecT<float, 4> {
 };
 
 // Row product of one sparse row with VEC consecutive columns of a block:
-// acc[v] = sum_k a_k * G[col_k, s0 + v], nonzeros in CSR order.
+// acc[v] = sum_k a_k * G[col_k, s0 + v], nonzeros added in CSR order.  The
+// nonzeros are taken CH at a time: their indices and values are loaded
+// together, then all CH gathers are issued before the first one is used, so a
+// row costs about two memory latencies per chunk instead of two per nonzero.
+constexpr int CH = 8;
+
 template <typename T, int VEC>
 __device__ __forceinline__ void row_product(const int32_t* __restrict__ rp,
                                             const int32_t* __restrict__ ci,
@@ -113,26 +118,30 @@ __device__ __forceinline__ void row_product(const int32_t* __restrict__ rp,
 #pragma unroll
     for (int v = 0; v < VEC; ++v) acc[v] = T(0);
     const int32_t kb = rp[row], ke = rp[row + 1];
-    int32_t k = kb;
-    // two nonzeros per trip so that both gathers are in flight together
-    for (; k + 1 < ke; k += 2) {
-        const int32_t j0 = ci[k], j1 = ci[k + 1];
-        const T a0 = av[k], a1 = av[k + 1];
-        T g0[VEC], g1[VEC];
-        VecT<T, VEC>::load(G + (size_t)j0 * ld + s0, g0);
-        VecT<T, VEC>::load(G + (size_t)j1 * ld + s0, g1);
+    for (int32_t k0 = kb; k0 < ke; k0 += CH) {
+        int32_t j[CH];
+        T a[CH];
 #pragma unroll
-        for (int v = 0; v < VEC; ++v) acc[v] = fma(a0, g0[v], acc[v]);
+        for (int u = 0; u < CH; ++u) {
+            j[u] = 0;
+            a[u] = T(0);
+            if (k0 + u < ke) {
+                j[u] = ci[k0 + u];
+                a[u] = av[k0 + u];
+            }
+        }
+        T g[CH][VEC];
 #pragma unroll
-        for (int v = 0; v < VEC; ++v) acc[v] = fma(a1, g1[v], acc[v]);
-    }
-    if (k < ke) {
-        const int32_t j0 = ci[k];
-        const T a0 = av[k];
-        T g0[VEC];
-        VecT<T, VEC>::load(G + (size_t)j0 * ld + s0, g0);
+        for (int u = 0; u < CH; ++u) {
+            if (k0 + u < ke) VecT<T, VEC>::load(G + (size_t)j[u] * ld + s0, g[u]);
+        }
 #pragma unroll
-        for (int v = 0; v < VEC; ++v) acc[v] = fma(a0, g0[v], acc[v]);
+        for (int u = 0; u < CH; ++u) {
+            if (k0 + u < ke) {
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) acc[v] = fma(a[u], g[u][v], acc[v]);
+            }
+        }
     }
 }
 
@@ -159,24 +168,36 @@ __global__ __launch_bounds__(256) void k_primal(StepArgs<T> a) {
     if (row >= a.rows || s0 >= a.ncols) return;
     const int32_t t = a.g->t0 + a.it;
 
+    // operands of the epilogue, fetched before the product so their latency overlaps it
+    SlotState st[VEC];
+    T zb[VEC], z0[VEC];
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) {
+        if (s0 + v < a.ncols) {
+            const size_t e = (size_t)row * a.ld + s0 + v;
+            st[v] = a.st[s0 + v];
+            zb[v] = a.Z[e];
+            z0[v] = a.Z0[e];
+        }
+    }
+    const double cb = a.c[row], lb = a.lo[row], hb = a.hi[row];
+
     T acc[VEC];
     row_product<T, VEC>(a.rp, a.ci, a.av, a.G, row, a.ld, s0, acc);
 
-    const double cb = a.c[row], lb = a.lo[row], hb = a.hi[row];
 #pragma unroll
     for (int v = 0; v < VEC; ++v) {
         const int32_t s = s0 + v;
         if (s >= a.ncols) break;
-        const SlotState st = a.st[s];
-        if (!(st.flags & SLOT_ACTIVE) || t > st.t_end) continue;
+        if (!(st[v].flags & SLOT_ACTIVE) || t > st[v].t_end) continue;
         const size_t e = (size_t)row * a.ld + s;
-        const VarData d = var_data(st, row, cb, lb, hb);
-        const int32_t k = t - st.t_anchor;
-        const T x0 = a.Z0[e];
-        const T xk = (k == 0) ? x0 : T(double(k) / double(k + 1)) * a.Z[e] + x0 / T(k + 1);
-        const T xt = clampt<T>(xk - T(st.tau) * (T(d.c) + acc[v]), T(d.lo), T(d.hi));
+        const VarData d = var_data(st[v], row, cb, lb, hb);
+        const int32_t k = t - st[v].t_anchor;
+        const T x0 = z0[v];
+        const T xk = (k == 0) ? x0 : T(double(k) / double(k + 1)) * zb[v] + x0 / T(k + 1);
+        const T xt = clampt<T>(xk - T(st[v].tau) * (T(d.c) + acc[v]), T(d.lo), T(d.hi));
         a.Z[e] = T(2) * xt - xk;
-        if (a.eval || t == st.t_end) {
+        if (a.eval || t == st[v].t_end) {
             a.Zt[e] = xt;
             a.DZ[e] = xt - xk;
         }
@@ -199,25 +220,36 @@ __global__ __launch_bounds__(256) void k_dual(StepArgs<T> a) {
     if (row >= a.rows || s0 >= a.ncols) return;
     const int32_t t = a.g->t0 + a.it;
 
+    SlotState st[VEC];
+    T zy[VEC], z0[VEC];
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) {
+        if (s0 + v < a.ncols) {
+            const size_t e = (size_t)row * a.ld + s0 + v;
+            st[v] = a.st[s0 + v];
+            zy[v] = a.Z[e];
+            z0[v] = a.Z0[e];
+        }
+    }
+    const T l = T(a.lo[row]), u = T(a.hi[row]);
+
     T acc[VEC];
     row_product<T, VEC>(a.rp, a.ci, a.av, a.G, row, a.ld, s0, acc);
 
-    const T l = T(a.lo[row]), u = T(a.hi[row]);
 #pragma unroll
     for (int v = 0; v < VEC; ++v) {
         const int32_t s = s0 + v;
         if (s >= a.ncols) break;
-        const SlotState st = a.st[s];
-        if (!(st.flags & SLOT_ACTIVE) || t > st.t_end) continue;
+        if (!(st[v].flags & SLOT_ACTIVE) || t > st[v].t_end) continue;
         const size_t e = (size_t)row * a.ld + s;
-        const int32_t k = t - st.t_anchor;
-        const T yk = a.Z[e];
-        const T y0 = a.Z0[e];
-        const T sg = T(st.sigma);
+        const int32_t k = t - st[v].t_anchor;
+        const T yk = zy[v];
+        const T y0 = z0[v];
+        const T sg = T(st[v].sigma);
         const T q = yk / sg + acc[v];
         const T yt = sg * (q - clampt<T>(q, l, u));
         a.Z[e] = T(halpern_a(k)) * (T(2) * yt - yk) + y0 / T(k + 2);
-        if (a.eval || t == st.t_end) {
+        if (a.eval || t == st[v].t_end) {
             a.Zt[e] = yt;
             a.DZ[e] = yt - yk;
         }
@@ -254,14 +286,38 @@ __global__ __launch_bounds__(256) void k_eval(EvalArgs<T> a) {
             for (int32_t i = r0; i < r1; ++i) {
                 // (A' y~)_i, (A' dy)_i and (A' Pi_B[l,u](dy))_i over the rows of column i
                 double g = 0.0, h = 0.0, pdy = 0.0;
-                for (int32_t k = a.t_rp[i]; k < a.t_rp[i + 1]; ++k) {
-                    const int32_t j = a.t_ci[k];
-                    const size_t f = (size_t)j * a.ld + s;
-                    const double v = (double)a.t_v[k];
-                    const double dyj = (double)a.DY[f];
-                    g = fma(v, (double)a.Yt[f], g);
-                    h = fma(v, dyj, h);
-                    pdy = fma(v, barrier(dyj, a.rl[j], a.ru[j]), pdy);
+                const int32_t kb = a.t_rp[i], ke = a.t_rp[i + 1];
+                for (int32_t k0 = kb; k0 < ke; k0 += CH) {
+                    int32_t jj[CH];
+                    double vv[CH];
+#pragma unroll
+                    for (int u = 0; u < CH; ++u) {
+                        jj[u] = 0;
+                        vv[u] = 0.0;
+                        if (k0 + u < ke) {
+                            jj[u] = a.t_ci[k0 + u];
+                            vv[u] = (double)a.t_v[k0 + u];
+                        }
+                    }
+                    double yv[CH], dv[CH], lv[CH], uv[CH];
+#pragma unroll
+                    for (int u = 0; u < CH; ++u) {
+                        if (k0 + u < ke) {
+                            const size_t f = (size_t)jj[u] * a.ld + s;
+                            yv[u] = (double)a.Yt[f];
+                            dv[u] = (double)a.DY[f];
+                            lv[u] = a.rl[jj[u]];
+                            uv[u] = a.ru[jj[u]];
+                        }
+                    }
+#pragma unroll
+                    for (int u = 0; u < CH; ++u) {
+                        if (k0 + u < ke) {
+                            g = fma(vv[u], yv[u], g);
+                            h = fma(vv[u], dv[u], h);
+                            pdy = fma(vv[u], barrier(dv[u], lv[u], uv[u]), pdy);
+                        }
+                    }
                 }
                 const size_t e = (size_t)i * a.ld + s;
                 const double xt = a.Xt[e], dx = a.DX[e], x0 = a.X0[e];
@@ -287,11 +343,35 @@ __global__ __launch_bounds__(256) void k_eval(EvalArgs<T> a) {
         } else {
             for (int32_t i = r0; i < r1; ++i) {
                 double ax = 0.0, adx = 0.0;                       // (A x~)_i, (A dx)_i
-                for (int32_t k = a.a_rp[i]; k < a.a_rp[i + 1]; ++k) {
-                    const size_t e = (size_t)a.a_ci[k] * a.ld + s;
-                    const double v = (double)a.a_v[k];
-                    ax = fma(v, (double)a.Xt[e], ax);
-                    adx = fma(v, (double)a.DX[e], adx);
+                const int32_t kb = a.a_rp[i], ke = a.a_rp[i + 1];
+                for (int32_t k0 = kb; k0 < ke; k0 += CH) {
+                    int32_t jj[CH];
+                    double vv[CH];
+#pragma unroll
+                    for (int u = 0; u < CH; ++u) {
+                        jj[u] = 0;
+                        vv[u] = 0.0;
+                        if (k0 + u < ke) {
+                            jj[u] = a.a_ci[k0 + u];
+                            vv[u] = (double)a.a_v[k0 + u];
+                        }
+                    }
+                    double xv[CH], dv[CH];
+#pragma unroll
+                    for (int u = 0; u < CH; ++u) {
+                        if (k0 + u < ke) {
+                            const size_t f = (size_t)jj[u] * a.ld + s;
+                            xv[u] = (double)a.Xt[f];
+                            dv[u] = (double)a.DX[f];
+                        }
+                    }
+#pragma unroll
+                    for (int u = 0; u < CH; ++u) {
+                        if (k0 + u < ke) {
+                            ax = fma(vv[u], xv[u], ax);
+                            adx = fma(vv[u], dv[u], adx);
+                        }
+                    }
                 }
                 const size_t e = (size_t)i * a.ld + s;
                 const double yt = a.Yt[e], dy = a.DY[e], y0 = a.Y0[e];
@@ -314,28 +394,36 @@ __global__ __launch_bounds__(256) void k_eval(EvalArgs<T> a) {
     for (int q = 0; q < NTERM; ++q) red[wave][q][lane] = acc[q];
     __syncthreads();
     if (wave == 0 && s < a.ncols) {
-        double* out = (xside ? a.part_x : a.part_y) + (size_t)panel * NTERM * a.ld;
+        // layout [term][slot][panel]: the reduction reads each (term, slot) row of panels contiguously
+        const int32_t np = xside ? a.npx : a.npy;
+        double* out = (xside ? a.part_x : a.part_y) + (size_t)s * np + panel;
 #pragma unroll
         for (int q = 0; q < NTERM; ++q) {
             const double v = ((red[0][q][lane] + red[1][q][lane]) + red[2][q][lane]) + red[3][q][lane];
-            out[(size_t)q * a.ld + s] = v;
+            out[(size_t)q * a.ld * np] = v;
         }
     }
 }
 
-// sums[q][s] = sum over panels p (in order) of part[p][q][s]; q < NTERM: x side, else y side
-__global__ __launch_bounds__(64) void k_reduce(ControlArgs a) {
-    const int32_t s = blockIdx.x * 64 + threadIdx.x;
-    const int32_t q = blockIdx.y;
-    if (s >= a.ncols) return;
+// sums[q][s] = sum over panels of part[q][s][panel]; q < NTERM: x side, else y side.
+// One wave per (term, slot): lane l adds panels l, l+64, ... in order, then a
+// butterfly over the 64 lanes (every lane ends with the same bits, since each
+// level adds the same pair in either order).  The tree depends on the panel
+// count only, not on the batch.
+__global__ __launch_bounds__(256) void k_reduce(ControlArgs a) {
+    const int32_t lane = threadIdx.x & 63;
+    const int32_t pair = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (pair >= 2 * NTERM * a.ncols) return;
+    const int32_t q = pair / a.ncols, s = pair % a.ncols;
     const bool xside = q < NTERM;
     const int32_t qq = xside ? q : q - NTERM;
     const int32_t np = xside ? a.npx : a.npy;
-    const double* p = (xside ? a.part_x : a.part_y) + (size_t)qq * a.ld + s;
-    const size_t stride = (size_t)NTERM * a.ld;
+    const double* p = (xside ? a.part_x : a.part_y) + ((size_t)qq * a.ld + s) * np;
     double acc = 0.0;
-    for (int32_t i = 0; i < np; ++i) acc += p[(size_t)i * stride];
-    a.sums[(size_t)q * a.ld + s] = acc;
+    for (int32_t i = lane; i < np; i += 64) acc += p[i];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if (lane == 0) a.sums[(size_t)q * a.ld + s] = acc;
 }
 
 // ---------------------------------------------------------------------------
@@ -404,8 +492,9 @@ __global__ __launch_bounds__(1024) void k_control(ControlArgs a) {
         const bool full_here = a.full && at_eval;
         const bool resid_here = at_eval && (a.full || k == 0);
         // order of the tests: NaN, stopping, infeasibility, iteration limit
+        const double eps_inf = a.infeas_tol < 0.0 ? tol : a.infeas_tol;
         const int32_t infeas =
-            (full_here && a.infeas_tol > 0.0) ? infeasible(sx, sy, a.ld, s, a.infeas_tol) : 0;
+            (full_here && eps_inf > 0.0) ? infeasible(sx, sy, a.ld, s, eps_inf) : 0;
         int32_t status = PDLPB_STATUS_RUNNING;
         if ((resid_here && !isfinite(r)) || (full_here && !isfinite(rel))) {
             status = PDLPB_STATUS_NUMERICAL_ERROR;
@@ -767,9 +856,9 @@ hipError_t launch_eval(const EvalArgs<T>& a, hipStream_t s) {
 }
 
 hipError_t launch_reduce(const ControlArgs& a, hipStream_t s) {
-    const dim3 grid((a.ncols + 63) / 64, 2 * NTERM);
-    if (grid.x == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_reduce, grid, dim3(64), 0, s, a);
+    const int64_t pairs = (int64_t)2 * NTERM * a.ncols;
+    if (pairs == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_reduce, dim3((uint32_t)((pairs + 3) / 4)), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

@@ -306,7 +306,7 @@ ControlArgs control_args(pdlpb_ctx* x, int32_t it, int32_t full, int32_t advance
     a.pw_literal = x->opt.pw_ratio == 1;
     a.beta_s = x->opt.beta_sufficient; a.beta_n = x->opt.beta_necessary;
     a.beta_a = x->opt.beta_artificial; a.theta = x->opt.theta; a.cross_sign = x->opt.cross_sign;
-    a.infeas_tol = x->opt.infeas_tol;
+    a.infeas_tol = x->opt.infeas_tol;   // < 0: the stopping tolerance (resolved on the device)
     return a;
 }
 
@@ -480,7 +480,7 @@ void pdlpb_default_options(pdlpb_options* o) {
     o->theta = 0.5;
     o->step_size = 0.0;
     o->cross_sign = -1.0;
-    o->infeas_tol = 1e-8;
+    o->infeas_tol = -1.0;
     o->pw_ratio = 0;
     o->device = 0;
     o->stream = nullptr;
@@ -520,7 +520,7 @@ int pdlpb_create(pdlpb_ctx** out, int32_t m, int32_t n, int64_t nnz, const int64
         return bad("restart parameters out of range");
     if (!(o.step_size >= 0.0) || !std::isfinite(o.step_size)) return bad("step_size must be >= 0");
     if (o.cross_sign != -1.0 && o.cross_sign != 1.0) return bad("cross_sign must be -1 or +1");
-    if (!(o.infeas_tol >= 0.0) || !std::isfinite(o.infeas_tol)) return bad("infeas_tol must be >= 0");
+    if (std::isnan(o.infeas_tol) || !std::isfinite(o.infeas_tol)) return bad("infeas_tol must be finite");
     if (o.max_batch < 1 || o.max_batch > (1 << 20)) return bad("max_batch out of range");
     if (o.restart_scope == PDLPB_RESTART_BATCH_AVG && o.max_batch > 1024) o.max_batch = 1024;
     if (o.tile_lanes != 0 && (o.tile_lanes < 1 || o.tile_lanes > 64 ||

@@ -96,8 +96,8 @@ struct EvalArgs {
     const SlotState* st;
     int32_t pw_x, pw_y;      // rows per wave on the x side / y side
     int32_t npx, npy;        // row panels (4 waves each) on each side
-    double* part_x;          // [npx][NTERM][ld]
-    double* part_y;          // [npy][NTERM][ld]
+    double* part_x;          // [NTERM][ld][npx]
+    double* part_y;          // [NTERM][ld][npy]
 };
 
 struct ControlArgs {
@@ -116,7 +116,7 @@ struct ControlArgs {
     int32_t batch_avg;       // restart scope
     int32_t pw_literal;      // primal weight ratio as printed
     double beta_s, beta_n, beta_a, theta, cross_sign;
-    double infeas_tol;       // eps of the infeasibility tests; 0 disables them
+    double infeas_tol;       // eps of the infeasibility tests; < 0: the stopping tolerance; 0: off
 };
 
 // ---- launchers (kernels.hip) ---------------------------------------------------

@@ -37,7 +37,7 @@ def test_options_layout_matches_header():
     assert (o.eval_every, o.beta_sufficient, o.beta_necessary, o.beta_artificial, o.theta) == \
         (64, 0.2, 0.8, 0.36, 0.5)
     assert o.cross_sign == -1.0 and o.use_graphs == 1 and o.max_batch == 4096
-    assert o.infeas_tol == 1e-8
+    assert o.infeas_tol == -1.0
     assert P.C.sizeof(P.Delta) == 16
 
 
@@ -78,7 +78,7 @@ def test_create_rejects_malformed_input(over, msg):
     (dict(tile_lanes=3), "tile_lanes"),
     (dict(tile_vec=3), "tile_vec"),
     (dict(step_size=-1.0), "step_size"),
-    (dict(infeas_tol=-1.0), "infeas_tol"),
+    (dict(infeas_tol=float("nan")), "infeas_tol"),
 ])
 def test_create_rejects_bad_options(opt, msg):
     with pytest.raises(P.PdlpbError) as e:
