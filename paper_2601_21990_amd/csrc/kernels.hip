@@ -165,7 +165,8 @@ __global__ __launch_bounds__(256) void k_primal(StepArgs<T> a) {
     const int wave = threadIdx.x >> 6;
     const int32_t row = (blockIdx.x * a.wpb + wave) * RPW + lane / G;
     const int32_t s0 = blockIdx.y * (G * VEC) + (lane % G) * VEC;
-    if (row >= a.rows || s0 >= a.ncols) return;
+    const int32_t ncols = min(a.ncols, a.g->n_cols);
+    if (row >= a.rows || s0 >= ncols) return;
     const int32_t t = a.g->t0 + a.it;
 
     // operands of the epilogue, fetched before the product so their latency overlaps it
@@ -173,7 +174,7 @@ __global__ __launch_bounds__(256) void k_primal(StepArgs<T> a) {
     T zb[VEC], z0[VEC];
 #pragma unroll
     for (int v = 0; v < VEC; ++v) {
-        if (s0 + v < a.ncols) {
+        if (s0 + v < ncols) {
             const size_t e = (size_t)row * a.ld + s0 + v;
             st[v] = a.st[s0 + v];
             zb[v] = a.Z[e];
@@ -188,7 +189,7 @@ __global__ __launch_bounds__(256) void k_primal(StepArgs<T> a) {
 #pragma unroll
     for (int v = 0; v < VEC; ++v) {
         const int32_t s = s0 + v;
-        if (s >= a.ncols) break;
+        if (s >= ncols) break;
         if (!(st[v].flags & SLOT_ACTIVE) || t > st[v].t_end) continue;
         const size_t e = (size_t)row * a.ld + s;
         const VarData d = var_data(st[v], row, cb, lb, hb);
@@ -217,14 +218,15 @@ __global__ __launch_bounds__(256) void k_dual(StepArgs<T> a) {
     const int wave = threadIdx.x >> 6;
     const int32_t row = (blockIdx.x * a.wpb + wave) * RPW + lane / G;
     const int32_t s0 = blockIdx.y * (G * VEC) + (lane % G) * VEC;
-    if (row >= a.rows || s0 >= a.ncols) return;
+    const int32_t ncols = min(a.ncols, a.g->n_cols);
+    if (row >= a.rows || s0 >= ncols) return;
     const int32_t t = a.g->t0 + a.it;
 
     SlotState st[VEC];
     T zy[VEC], z0[VEC];
 #pragma unroll
     for (int v = 0; v < VEC; ++v) {
-        if (s0 + v < a.ncols) {
+        if (s0 + v < ncols) {
             const size_t e = (size_t)row * a.ld + s0 + v;
             st[v] = a.st[s0 + v];
             zy[v] = a.Z[e];
@@ -239,7 +241,7 @@ __global__ __launch_bounds__(256) void k_dual(StepArgs<T> a) {
 #pragma unroll
     for (int v = 0; v < VEC; ++v) {
         const int32_t s = s0 + v;
-        if (s >= a.ncols) break;
+        if (s >= ncols) break;
         if (!(st[v].flags & SLOT_ACTIVE) || t > st[v].t_end) continue;
         const size_t e = (size_t)row * a.ld + s;
         const int32_t k = t - st[v].t_anchor;
@@ -278,7 +280,8 @@ __global__ __launch_bounds__(256) void k_eval(EvalArgs<T> a) {
 #pragma unroll
     for (int q = 0; q < NTERM; ++q) acc[q] = 0.0;
 
-    if (s < a.ncols) {
+    const int32_t ncols = min(a.ncols, a.g->n_cols);
+    if (s < ncols) {
         const SlotState st = a.st[s];
         const int32_t r0 = panel * 4 * pw + wave * pw;
         const int32_t r1 = min(r0 + pw, rows);
@@ -393,7 +396,7 @@ __global__ __launch_bounds__(256) void k_eval(EvalArgs<T> a) {
 #pragma unroll
     for (int q = 0; q < NTERM; ++q) red[wave][q][lane] = acc[q];
     __syncthreads();
-    if (wave == 0 && s < a.ncols) {
+    if (wave == 0 && s < ncols) {
         // layout [term][slot][panel]: the reduction reads each (term, slot) row of panels contiguously
         const int32_t np = xside ? a.npx : a.npy;
         double* out = (xside ? a.part_x : a.part_y) + (size_t)s * np + panel;
@@ -450,27 +453,62 @@ __device__ int32_t infeasible(const double* sx, const double* sy, int32_t ld, in
     return 0;
 }
 
+// new primal weight by exponential smoothing (Section 4), d from the anchor displacement
+__device__ double smoothed_weight(double w, double dx2, double dy2, const ControlArgs& a) {
+    const double dxn = sqrt(dx2), dyn = sqrt(dy2);
+    const double num = a.pw_literal ? dxn : dyn;
+    const double den = a.pw_literal ? dyn : dxn;
+    if (num > 1e-10 && den > 1e-10 && isfinite(num) && isfinite(den))
+        return exp(a.theta * log(num / den) + (1.0 - a.theta) * log(w));
+    return w;
+}
+
+// restart bookkeeping of one LP: new weight and steps, cycle start, log
+__device__ void restart_slot(SlotState& st, SlotCtl& cl, int32_t* rlog, int32_t t, double eta,
+                             double wn) {
+    cl.w = wn;
+    st.tau = eta / wn;
+    st.sigma = eta * wn;
+    st.t_anchor = t + 1;
+    st.flags |= SLOT_FRESH;
+    if (cl.restarts < RESTART_LOG) rlog[cl.restarts] = t - st.t_start;
+    cl.restarts += 1;
+}
+
+// ---------------------------------------------------------------------------
+// Control (Section 4: restarts, primal weight, stopping, infeasibility;
+// Section 5: batched restart scope, per-LP stop and compaction).  One block;
+// thread s handles slot s.  On full evaluations it also plans the compaction:
+// stopped LPs are retired and running LPs beyond the new column count move
+// into the freed slots, so the live columns stay a prefix [0, n_cols).
+// ---------------------------------------------------------------------------
 __global__ __launch_bounds__(1024) void k_control(ControlArgs a) {
     __shared__ double sh_r[1024];
     __shared__ int32_t sh_n[1024];
+    __shared__ int32_t sh_flags[MAX_BATCH];
     __shared__ int32_t sh_flag;
     Globals* g = a.g;
     const int32_t t = g->t0 + a.it;
+    const int32_t nc = min(a.ncols, g->n_cols);
     const double eta = g->eta;
     const double tol = g->tol;
+    const double* sx = a.sums;
+    const double* sy = a.sums + (size_t)NTERM * a.ld;
     int32_t my_active = 0;
-    double my_r = 0.0;
-    int32_t my_part = 0;   // participates in the batch-average residual
+    if (a.batch_avg) {
+        sh_r[threadIdx.x] = 0.0;
+        sh_n[threadIdx.x] = 0;
+    }
+    __syncthreads();
 
-    // pass 1: stopping tests and residuals
-    for (int32_t s = threadIdx.x; s < a.ncols; s += blockDim.x) {
+    // pass 1: stopping tests, residuals, per-LP restarts
+    for (int32_t s = threadIdx.x; s < nc; s += blockDim.x) {
         SlotState& st = a.st[s];
-        SlotCtl& cl = a.ctl[s];
+        const int32_t lp = a.slot_lp[s];
+        SlotCtl& cl = a.ctl[lp];
         if (!(st.flags & SLOT_ACTIVE)) continue;
         const int32_t k = t - st.t_anchor;
         const bool final_now = (t >= st.t_end);
-        const double* sx = a.sums;
-        const double* sy = a.sums + (size_t)NTERM * a.ld;
         const double dx2 = sx[0 * a.ld + s], cx = sx[1 * a.ld + s], phix = sx[2 * a.ld + s];
         const double dres2 = sx[3 * a.ld + s], c2 = sx[4 * a.ld + s];
         const double dy2 = sy[0 * a.ld + s], cross = sy[1 * a.ld + s], phiy = sy[2 * a.ld + s];
@@ -486,9 +524,8 @@ __global__ __launch_bounds__(1024) void k_control(ControlArgs a) {
         const double dua = sqrt(dres2) / (1.0 + sqrt(c2));
         double rel = fmax(gap, fmax(pri, dua));
         if (isnan(gap) || isnan(pri) || isnan(dua)) rel = NAN;
-        // The LP's last iteration happened at t_last = min(t, t_end); an LP
-        // that ran out of budget before this launch evaluates its final z~.
-        const bool at_eval = (t <= st.t_end);           // this launch evaluates the LP's current iteration
+        // an LP that ran out of budget before this launch is evaluated at its final z~
+        const bool at_eval = (t <= st.t_end);
         const bool full_here = a.full && at_eval;
         const bool resid_here = at_eval && (a.full || k == 0);
         // order of the tests: NaN, stopping, infeasibility, iteration limit
@@ -505,61 +542,42 @@ __global__ __launch_bounds__(1024) void k_control(ControlArgs a) {
         } else if (final_now) {
             status = PDLPB_STATUS_ITERATION_LIMIT;
         }
+        cl.kkt[0] = gap; cl.kkt[1] = pri; cl.kkt[2] = dua; cl.kkt[3] = rel;
+        cl.obj = cx;
         if (status != PDLPB_STATUS_RUNNING) {
             const int32_t t_last = t < st.t_end ? t : st.t_end;
             cl.status = status;
-            cl.kkt[0] = gap; cl.kkt[1] = pri; cl.kkt[2] = dua; cl.kkt[3] = rel;
-            cl.obj = cx;
             cl.t_last = t_last;
+            cl.k_last = t_last - st.t_anchor;
             cl.iters = t_last - st.t_start + 1;
-            st.flags &= ~(SLOT_ACTIVE | SLOT_FRESH);
+            st.flags = SLOT_RETIRE;
             continue;
         }
         my_active += 1;
-        if (resid_here) {
-            my_r += r;          // one slot per thread and pass when ncols <= blockDim
-            my_part += 1;
-        }
-        cl.kkt[0] = gap; cl.kkt[1] = pri; cl.kkt[2] = dua; cl.kkt[3] = rel;
-        cl.obj = cx;
-        if (!a.batch_avg) {
-            // per-LP restart scope
-            if (k == 0) {
-                if (resid_here) {
-                    cl.r0 = r;
-                    cl.r_prev = r;
-                }
-                st.flags &= ~SLOT_FRESH;
-            } else if (a.full) {
-                const int32_t tl = t - st.t_start;
-                if (restart_due(r, cl.r0, cl.r_prev, k, tl, a)) {
-                    const double dxn = sqrt(sx[5 * a.ld + s]);
-                    const double dyn = sqrt(sy[5 * a.ld + s]);
-                    const double num = a.pw_literal ? dxn : dyn;
-                    const double den = a.pw_literal ? dyn : dxn;
-                    double wn = w;
-                    if (num > 1e-10 && den > 1e-10 && isfinite(num) && isfinite(den))
-                        wn = exp(a.theta * log(num / den) + (1.0 - a.theta) * log(w));
-                    cl.w = wn;
-                    st.tau = eta / wn;
-                    st.sigma = eta * wn;
-                    st.t_anchor = t + 1;
-                    st.flags |= SLOT_FRESH;
-                    if (cl.restarts < RESTART_LOG) a.rlog[(size_t)s * RESTART_LOG + cl.restarts] = tl;
-                    cl.restarts += 1;
-                    cl.r_prev = -1.0;
-                } else {
-                    cl.r_prev = r;
-                }
+        if (a.batch_avg) {
+            if (resid_here) {            // indexed by LP: the average adds LPs in LP order
+                sh_r[lp] = r;
+                sh_n[lp] = 1;
+            }
+        } else if (k == 0) {
+            if (resid_here) {
+                cl.r0 = r;
+                cl.r_prev = r;
+            }
+            st.flags &= ~SLOT_FRESH;
+        } else if (a.full) {
+            if (restart_due(r, cl.r0, cl.r_prev, k, t - st.t_start, a)) {
+                restart_slot(st, cl, a.rlog + (size_t)lp * RESTART_LOG, t, eta,
+                             smoothed_weight(w, sx[5 * a.ld + s], sy[5 * a.ld + s], a));
+                cl.r_prev = -1.0;
+            } else {
+                cl.r_prev = r;
             }
         }
     }
 
     // batch-average scope: mean residual over running LPs, shared decision
     if (a.batch_avg) {
-        // each thread holds at most one slot when ncols <= blockDim (checked by the host)
-        sh_r[threadIdx.x] = (my_part ? my_r : 0.0);
-        sh_n[threadIdx.x] = my_part;
         __syncthreads();
         if (threadIdx.x == 0) {
             double sum = 0.0;
@@ -568,7 +586,7 @@ __global__ __launch_bounds__(1024) void k_control(ControlArgs a) {
                 if (sh_n[i]) { sum += sh_r[i]; cnt += 1; }
             }
             const int32_t k = t - g->batch_k0;
-            int32_t flag = 0;   // 0 nothing, 1 set r0, 2 restart, 3 record r_prev
+            int32_t flag = 0;   // 0 nothing, 1 start of a cycle, 2 restart
             if (cnt > 0) {
                 const double rbar = sum / (double)cnt;
                 if (k == 0) {
@@ -576,7 +594,7 @@ __global__ __launch_bounds__(1024) void k_control(ControlArgs a) {
                     g->r_prev = rbar;
                     flag = 1;
                 } else if (a.full) {
-                    // restart tests with the shared cycle; K = t (LPs of one batch start together)
+                    // LPs of one batch start together, so K = t
                     if (restart_due(rbar, g->r0, g->r_prev, k, t, a)) {
                         flag = 2;
                         g->batch_k0 = t + 1;
@@ -590,43 +608,64 @@ __global__ __launch_bounds__(1024) void k_control(ControlArgs a) {
         }
         __syncthreads();
         const int32_t flag = sh_flag;
-        for (int32_t s = threadIdx.x; s < a.ncols; s += blockDim.x) {
+        for (int32_t s = threadIdx.x; s < nc; s += blockDim.x) {
             SlotState& st = a.st[s];
-            SlotCtl& cl = a.ctl[s];
             if (!(st.flags & SLOT_ACTIVE)) continue;
+            const int32_t lp = a.slot_lp[s];
             if (flag == 1 || (t - st.t_anchor) == 0) st.flags &= ~SLOT_FRESH;
             if (flag == 2) {
-                const double* sx = a.sums;
-                const double* sy = a.sums + (size_t)NTERM * a.ld;
-                const double w = cl.w;
-                const double dxn = sqrt(sx[5 * a.ld + s]);
-                const double dyn = sqrt(sy[5 * a.ld + s]);
-                const double num = a.pw_literal ? dxn : dyn;
-                const double den = a.pw_literal ? dyn : dxn;
-                double wn = w;
-                if (num > 1e-10 && den > 1e-10 && isfinite(num) && isfinite(den))
-                    wn = exp(a.theta * log(num / den) + (1.0 - a.theta) * log(w));
-                cl.w = wn;
-                st.tau = eta / wn;
-                st.sigma = eta * wn;
-                st.t_anchor = t + 1;
-                st.flags |= SLOT_FRESH;
-                const int32_t tl = t - st.t_start;
-                if (cl.restarts < RESTART_LOG) a.rlog[(size_t)s * RESTART_LOG + cl.restarts] = tl;
-                cl.restarts += 1;
+                SlotCtl& cl = a.ctl[lp];
+                restart_slot(st, cl, a.rlog + (size_t)lp * RESTART_LOG, t, eta,
+                             smoothed_weight(cl.w, sx[5 * a.ld + s], sy[5 * a.ld + s], a));
             }
         }
     }
 
-    // running count (fixed-order block sum) and the block clock
+    // running count (fixed-order block sum)
+    __syncthreads();
     sh_n[threadIdx.x] = my_active;
     __syncthreads();
     for (int32_t w = blockDim.x / 2; w > 0; w >>= 1) {
         if ((int32_t)threadIdx.x < w) sh_n[threadIdx.x] += sh_n[threadIdx.x + w];
         __syncthreads();
     }
+    const int32_t n_run = sh_n[0];
+
+    // compaction plan (full evaluations): live prefix [0, n_run)
+    if (a.full) {
+        for (int32_t s = threadIdx.x; s < nc; s += blockDim.x) sh_flags[s] = a.st[s].flags;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int32_t nr = 0, nm = 0;
+            int32_t mover = n_run;   // scan for running slots at or beyond n_run
+            for (int32_t s = 0; s < nc; ++s) {
+                if (!(sh_flags[s] & SLOT_RETIRE)) continue;
+                const int32_t lp = a.slot_lp[s];
+                const int32_t kl = a.ctl[lp].k_last;
+                a.retire[nr].slot = s;
+                a.retire[nr].lp = lp;
+                a.retire[nr].kp2 = kl + 2;
+                a.retire[nr].a = double(kl + 1) / double(kl + 2);
+                nr += 1;
+                if (s < n_run) {
+                    // the running slots at or beyond n_run are exactly as many as the
+                    // stopped slots below it; the bound only guards that count
+                    while (mover < nc && !(sh_flags[mover] & SLOT_ACTIVE)) ++mover;
+                    if (mover < nc) {
+                        a.moves[nm].src = mover;
+                        a.moves[nm].dst = s;
+                        nm += 1;
+                        ++mover;
+                    }
+                }
+            }
+            g->n_retire = nr;
+            g->n_move = nm;
+            g->n_cols_next = n_run;
+        }
+    }
     if (threadIdx.x == 0) {
-        g->n_active = sh_n[0];
+        g->n_active = n_run;
         if (a.advance) g->t0 += a.block;
     }
 }
@@ -640,11 +679,12 @@ __global__ __launch_bounds__(1024) void k_control(ControlArgs a) {
 template <typename T>
 __global__ __launch_bounds__(256) void k_apply_restart(int32_t n, int32_t m, int32_t ld,
                                                        int32_t ncols, const SlotState* st,
-                                                       T* X0, const T* Xt, T* Y, T* Y0,
-                                                       const T* Yt) {
+                                                       const Globals* g, T* X0, const T* Xt,
+                                                       T* Y, T* Y0, const T* Yt) {
     const int32_t row = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (row >= n + m) return;
-    for (int32_t s = threadIdx.x & 63; s < ncols; s += 64) {
+    const int32_t nc = min(ncols, g->n_cols);
+    for (int32_t s = threadIdx.x & 63; s < nc; s += 64) {
         if (!(st[s].flags & SLOT_FRESH)) continue;
         if (row < n) {
             const size_t e = (size_t)row * ld + s;
@@ -659,26 +699,87 @@ __global__ __launch_bounds__(256) void k_apply_restart(int32_t n, int32_t m, int
 }
 
 // ---------------------------------------------------------------------------
+// Compaction (Section 5, stopping criteria: stopped LPs leave the iterate
+// blocks so that kernel sizes shrink).  One thread per row of the blocks
+// (x rows, then y rows): first the stopped LPs' z~ and last Halpern iterate
+// are copied to the LP-major result blocks, then the running LPs listed in
+// the plan move into the freed slots.  Block 0 also moves their slot states.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct Blocks8 {
+    T* b[8];
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_compact(int32_t n, int32_t m, int32_t ld, Blocks8<T> B,
+                                                 Blocks8<T> R, const RetireEntry* retire,
+                                                 const MoveEntry* moves, SlotState* st,
+                                                 int32_t* slot_lp, Globals* g) {
+    const int32_t nr = g->n_retire, nm = g->n_move;
+    const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (row < n) {
+        const size_t base = (size_t)row * ld;
+        T* Xbar = B.b[0];
+        T* X0 = B.b[1];
+        T* Xt = B.b[2];
+        for (int32_t q = 0; q < nr; ++q) {
+            const RetireEntry e = retire[q];
+            const size_t f = base + e.slot;
+            R.b[0][(size_t)e.lp * n + row] = Xt[f];
+            R.b[1][(size_t)e.lp * n + row] =
+                T(e.a * (double)Xbar[f] + (double)X0[f] / (double)e.kp2);
+        }
+        for (int32_t q = 0; q < nm; ++q) {
+            const MoveEntry mv = moves[q];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) B.b[b][base + mv.dst] = B.b[b][base + mv.src];
+        }
+    } else if (row < (int64_t)n + m) {
+        const int64_t i = row - n;
+        const size_t base = (size_t)i * ld;
+        for (int32_t q = 0; q < nr; ++q) {
+            const RetireEntry e = retire[q];
+            const size_t f = base + e.slot;
+            R.b[2][(size_t)e.lp * m + i] = B.b[6][f];    // y~
+            R.b[3][(size_t)e.lp * m + i] = B.b[4][f];    // Halpern iterate y^{k+1}
+        }
+        for (int32_t q = 0; q < nm; ++q) {
+            const MoveEntry mv = moves[q];
+#pragma unroll
+            for (int b = 4; b < 8; ++b) B.b[b][base + mv.dst] = B.b[b][base + mv.src];
+        }
+    }
+    if (blockIdx.x == 0) {
+        for (int32_t q = threadIdx.x; q < nm; q += blockDim.x) {
+            const MoveEntry mv = moves[q];
+            st[mv.dst] = st[mv.src];
+            slot_lp[mv.dst] = slot_lp[mv.src];
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) g->n_cols = g->n_cols_next;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // batch set-up
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ void k_init_blocks(int32_t n, int32_t m, int32_t ld, int32_t ncols,
-                              const SlotState* st, const double* xl, const double* xu,
-                              const double* xw, const double* yw, int32_t mode, T* Xbar, T* X0,
-                              T* Xt, T* DX, T* Y, T* Y0, T* Yt, T* DY) {
+                              const SlotState* st, const int32_t* slot_lp, const double* xl,
+                              const double* xu, const double* xw, const double* yw, int32_t mode,
+                              T* Xbar, T* X0, T* Xt, T* DX, T* Y, T* Y0, T* Yt, T* DY) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t nx = (int64_t)n * ld, ny = (int64_t)m * ld;
     if (idx < nx) {
         const int32_t i = (int32_t)(idx / ld), s = (int32_t)(idx % ld);
         T x = T(0);
-        if (s < ncols && (st[s].flags & SLOT_ACTIVE)) {
+        if (s < ncols) {
             const SlotState q = st[s];
             const VarData d = var_data(q, i, 0.0, xl[i], xu[i]);
             double w0 = 0.0;
             if (mode == PDLPB_WARM_SHARED) w0 = xw[i];
-            else if (mode == PDLPB_WARM_PER_LP) w0 = xw[(size_t)s * n + i];
-            // a bound that crosses leaves the slot inactive; keep values finite
-            x = (d.lo <= d.hi) ? T(clampd(w0, d.lo, d.hi)) : T(0);
+            else if (mode == PDLPB_WARM_PER_LP) w0 = xw[(size_t)slot_lp[s] * n + i];
+            x = T(clampd(w0, d.lo, d.hi));
         }
         Xbar[idx] = x;
         X0[idx] = x;
@@ -688,9 +789,9 @@ __global__ void k_init_blocks(int32_t n, int32_t m, int32_t ld, int32_t ncols,
         const int64_t e = idx - nx;
         const int32_t i = (int32_t)(e / ld), s = (int32_t)(e % ld);
         T y = T(0);
-        if (s < ncols && (st[s].flags & SLOT_ACTIVE)) {
+        if (s < ncols) {
             if (mode == PDLPB_WARM_SHARED) y = T(yw[i]);
-            else if (mode == PDLPB_WARM_PER_LP) y = T(yw[(size_t)s * m + i]);
+            else if (mode == PDLPB_WARM_PER_LP) y = T(yw[(size_t)slot_lp[s] * m + i]);
         }
         Y[e] = y;
         Y0[e] = y;
@@ -699,48 +800,34 @@ __global__ void k_init_blocks(int32_t n, int32_t m, int32_t ld, int32_t ncols,
     }
 }
 
-__global__ void k_begin_solve(SlotState* st, SlotCtl* ctl, int32_t ncols, int32_t max_iters,
-                              Globals* g, double tol) {
+__global__ void k_begin_solve(SlotState* st, const int32_t* slot_lp, SlotCtl* ctl, int32_t ncols,
+                              int32_t max_iters, Globals* g, double tol) {
     const int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s < ncols && (st[s].flags & SLOT_ACTIVE)) {
+    if (s < ncols) {
         st[s].t_start = 0;
         st[s].t_anchor = 0;
         st[s].t_end = max_iters - 1;
-        ctl[s].status = PDLPB_STATUS_RUNNING;
-        ctl[s].restarts = 0;
-        ctl[s].r_prev = -1.0;
+        SlotCtl& cl = ctl[slot_lp[s]];
+        cl.status = PDLPB_STATUS_RUNNING;
+        cl.restarts = 0;
+        cl.r_prev = -1.0;
     }
     if (s == 0) {
         g->t0 = 0;
         g->tol = tol;
         g->batch_k0 = 0;
         g->r_prev = -1.0;
-        g->n_active = 0;
+        g->n_active = ncols;
+        g->n_cols = ncols;
+        g->n_retire = 0;
+        g->n_move = 0;
+        g->n_cols_next = ncols;
     }
 }
 
-template <typename T>
-__global__ void k_gather_column(const T* Z, int32_t rows, int32_t ld, int32_t slot, double* out) {
-    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < rows) out[i] = (double)Z[(size_t)i * ld + slot];
-}
-
-template <typename T>
-__global__ void k_transpose_out(const T* Z, int32_t rows, int32_t ld, int32_t ncols, double* out) {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (int64_t)rows * ncols) return;
-    const int32_t s = (int32_t)(idx / rows), i = (int32_t)(idx % rows);
-    out[idx] = (double)Z[(size_t)i * ld + s];
-}
-
-template <typename T>
-__global__ void k_halpern_column(const T* Xbar, const T* X0, int32_t rows, int32_t ld,
-                                 int32_t slot, double a, int32_t kp2, double* out) {
-    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < rows) {
-        const size_t e = (size_t)i * ld + slot;
-        out[i] = a * (double)Xbar[e] + (double)X0[e] / (double)kp2;
-    }
+__global__ void k_widen(const float* src, int64_t count, double* dst) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) dst[i] = (double)src[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -870,64 +957,56 @@ hipError_t launch_control(const ControlArgs& a, hipStream_t s) {
 
 template <typename T>
 hipError_t launch_apply_restart(int32_t n, int32_t m, int32_t ld, int32_t ncols,
-                                const SlotState* st, T* X0, const T* Xt, T* Y, T* Y0, const T* Yt,
-                                hipStream_t s) {
+                                const SlotState* st, const Globals* g, T* X0, const T* Xt, T* Y,
+                                T* Y0, const T* Yt, hipStream_t s) {
     const int64_t rows = (int64_t)n + m;
     if (rows == 0 || ncols == 0) return hipSuccess;
     hipLaunchKernelGGL(k_apply_restart<T>, dim3((uint32_t)((rows + 3) / 4)), dim3(256), 0, s, n, m,
-                       ld, ncols, st, X0, Xt, Y, Y0, Yt);
+                       ld, ncols, st, g, X0, Xt, Y, Y0, Yt);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_compact(int32_t n, int32_t m, int32_t ld, T* const* blk, T* const* res,
+                          const RetireEntry* retire, const MoveEntry* moves, SlotState* st,
+                          int32_t* slot_lp, Globals* g, hipStream_t s) {
+    Blocks8<T> B{}, R{};
+    for (int b = 0; b < 8; ++b) B.b[b] = blk[b];
+    for (int b = 0; b < 4; ++b) R.b[b] = res[b];
+    const int64_t rows = (int64_t)n + m;
+    const uint32_t blocks = (uint32_t)((rows + 255) / 256);
+    hipLaunchKernelGGL(k_compact<T>, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, s, n, m, ld, B, R,
+                       retire, moves, st, slot_lp, g);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_init_blocks(int32_t n, int32_t m, int32_t ld, int32_t ncols, const SlotState* st,
-                              const double* xl, const double* xu, const double* xw,
-                              const double* yw, int32_t mode, T* Xbar, T* X0, T* Xt, T* DX, T* Y,
-                              T* Y0, T* Yt, T* DY, hipStream_t s) {
+                              const int32_t* slot_lp, const double* xl, const double* xu,
+                              const double* xw, const double* yw, int32_t mode, T* Xbar, T* X0,
+                              T* Xt, T* DX, T* Y, T* Y0, T* Yt, T* DY, hipStream_t s) {
     const int64_t total = (int64_t)(n + m) * ld;
     if (total == 0) return hipSuccess;
     const int64_t blocks = (total + 255) / 256;
     if (blocks > 0x7fffffff) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_init_blocks<T>, dim3((uint32_t)blocks), dim3(256), 0, s, n, m, ld, ncols,
-                       st, xl, xu, xw, yw, mode, Xbar, X0, Xt, DX, Y, Y0, Yt, DY);
+                       st, slot_lp, xl, xu, xw, yw, mode, Xbar, X0, Xt, DX, Y, Y0, Yt, DY);
     return hipGetLastError();
 }
 
-hipError_t launch_begin_solve(SlotState* st, SlotCtl* ctl, int32_t ncols, int32_t max_iters,
-                              Globals* g, double tol, hipStream_t s) {
+hipError_t launch_begin_solve(SlotState* st, const int32_t* slot_lp, SlotCtl* ctl, int32_t ncols,
+                              int32_t max_iters, Globals* g, double tol, hipStream_t s) {
     const int32_t blocks = (ncols + 255) / 256;
-    hipLaunchKernelGGL(k_begin_solve, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, s, st, ctl,
-                       ncols, max_iters, g, tol);
+    hipLaunchKernelGGL(k_begin_solve, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, s, st, slot_lp,
+                       ctl, ncols, max_iters, g, tol);
     return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_gather_column(const T* Z, int32_t rows, int32_t ld, int32_t slot, double* out,
-                                hipStream_t s) {
-    if (rows == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_gather_column<T>, dim3((rows + 255) / 256), dim3(256), 0, s, Z, rows, ld,
-                       slot, out);
-    return hipGetLastError();
-}
-
-template <typename T>
-hipError_t launch_transpose_out(const T* Z, int32_t rows, int32_t ld, int32_t ncols, double* out,
-                                hipStream_t s) {
-    const int64_t total = (int64_t)rows * ncols;
-    if (total == 0) return hipSuccess;
-    const int64_t blocks = (total + 255) / 256;
+hipError_t launch_widen(const float* src, int64_t count, double* dst, hipStream_t s) {
+    if (count == 0) return hipSuccess;
+    const int64_t blocks = (count + 255) / 256;
     if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_transpose_out<T>, dim3((uint32_t)blocks), dim3(256), 0, s, Z, rows, ld,
-                       ncols, out);
-    return hipGetLastError();
-}
-
-template <typename T>
-hipError_t launch_halpern_column(const T* Xbar, const T* X0, int32_t rows, int32_t ld, int32_t slot,
-                                 double a, int32_t kp2, double* out, hipStream_t s) {
-    if (rows == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_halpern_column<T>, dim3((rows + 255) / 256), dim3(256), 0, s, Xbar, X0,
-                       rows, ld, slot, a, kp2, out);
+    hipLaunchKernelGGL(k_widen, dim3((uint32_t)blocks), dim3(256), 0, s, src, count, dst);
     return hipGetLastError();
 }
 
@@ -968,31 +1047,27 @@ template hipError_t launch_dual<float>(const StepArgs<float>&, int, int, hipStre
 template hipError_t launch_eval<double>(const EvalArgs<double>&, hipStream_t);
 template hipError_t launch_eval<float>(const EvalArgs<float>&, hipStream_t);
 template hipError_t launch_apply_restart<double>(int32_t, int32_t, int32_t, int32_t,
-                                                 const SlotState*, double*, const double*, double*,
-                                                 double*, const double*, hipStream_t);
+                                                 const SlotState*, const Globals*, double*,
+                                                 const double*, double*, double*, const double*,
+                                                 hipStream_t);
 template hipError_t launch_apply_restart<float>(int32_t, int32_t, int32_t, int32_t, const SlotState*,
-                                                float*, const float*, float*, float*, const float*,
-                                                hipStream_t);
+                                                const Globals*, float*, const float*, float*,
+                                                float*, const float*, hipStream_t);
+template hipError_t launch_compact<double>(int32_t, int32_t, int32_t, double* const*,
+                                           double* const*, const RetireEntry*, const MoveEntry*,
+                                           SlotState*, int32_t*, Globals*, hipStream_t);
+template hipError_t launch_compact<float>(int32_t, int32_t, int32_t, float* const*, float* const*,
+                                          const RetireEntry*, const MoveEntry*, SlotState*,
+                                          int32_t*, Globals*, hipStream_t);
 template hipError_t launch_init_blocks<double>(int32_t, int32_t, int32_t, int32_t, const SlotState*,
-                                               const double*, const double*, const double*,
-                                               const double*, int32_t, double*, double*, double*,
-                                               double*, double*, double*, double*, double*,
-                                               hipStream_t);
+                                               const int32_t*, const double*, const double*,
+                                               const double*, const double*, int32_t, double*,
+                                               double*, double*, double*, double*, double*, double*,
+                                               double*, hipStream_t);
 template hipError_t launch_init_blocks<float>(int32_t, int32_t, int32_t, int32_t, const SlotState*,
-                                              const double*, const double*, const double*,
-                                              const double*, int32_t, float*, float*, float*, float*,
-                                              float*, float*, float*, float*, hipStream_t);
-template hipError_t launch_gather_column<double>(const double*, int32_t, int32_t, int32_t, double*,
-                                                 hipStream_t);
-template hipError_t launch_gather_column<float>(const float*, int32_t, int32_t, int32_t, double*,
-                                                hipStream_t);
-template hipError_t launch_transpose_out<double>(const double*, int32_t, int32_t, int32_t, double*,
-                                                 hipStream_t);
-template hipError_t launch_transpose_out<float>(const float*, int32_t, int32_t, int32_t, double*,
-                                                hipStream_t);
-template hipError_t launch_halpern_column<double>(const double*, const double*, int32_t, int32_t,
-                                                  int32_t, double, int32_t, double*, hipStream_t);
-template hipError_t launch_halpern_column<float>(const float*, const float*, int32_t, int32_t,
-                                                 int32_t, double, int32_t, double*, hipStream_t);
+                                              const int32_t*, const double*, const double*,
+                                              const double*, const double*, int32_t, float*, float*,
+                                              float*, float*, float*, float*, float*, float*,
+                                              hipStream_t);
 
 }  // namespace pdlpb

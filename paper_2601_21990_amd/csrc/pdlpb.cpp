@@ -62,13 +62,21 @@ struct pdlpb_ctx {
 
     // batch storage
     int32_t B = 0, ld = 0;
+    int32_t n_run0 = 0;             // LPs placed in slots by set_batch (the others never run)
+    int32_t live = 0;               // live column count the current launches are shaped for
     int lanes = 64, vec = 1, wpb = 4;
+    int vec_ld = 1;                 // vector width ld is padded for
     size_t cap_block_bytes = 0;     // bytes of each of the 8 dense blocks
-    void* blk[8] = {};              // Xbar, X0, Xt, DX, Y, Y0, Yt, DY
+    void* blk[8] = {};              // Xbar, X0, Xt, DX, Y, Y0, Yt, DY (row-major, stride ld)
+    size_t cap_res_x = 0, cap_res_y = 0;
+    void* res[4] = {};              // Rx, Rxi (B x n), Ry, Ryi (B x m): LP-major results
     int32_t cap_slots = 0;
-    SlotState* st = nullptr;
-    SlotCtl* ctl = nullptr;
-    int32_t* rlog = nullptr;
+    SlotState* st = nullptr;        // by slot
+    int32_t* slot_lp = nullptr;     // LP held by each slot
+    SlotCtl* ctl = nullptr;         // by LP
+    int32_t* rlog = nullptr;        // by LP
+    RetireEntry* retire = nullptr;
+    MoveEntry* moves = nullptr;
     Globals* g = nullptr;
     size_t cap_part = 0;            // doubles in part (x and y) + sums
     double* part = nullptr;
@@ -81,13 +89,11 @@ struct pdlpb_ctx {
     // state
     bool batch_set = false;
     bool solved = false;
-    std::vector<SlotState> h_st;
     std::vector<SlotCtl> h_ctl;
     std::vector<int32_t> h_rlog;
 
-    // epoch graph
-    hipGraphExec_t graph = nullptr;
-    bool graph_valid = false;
+    // captured blocks of C iterations, one per launch shape (live column bound)
+    std::vector<std::pair<int32_t, hipGraphExec_t>> graphs;
 
     // kernel timing
     bool timing = false;
@@ -126,9 +132,8 @@ struct pdlpb_ctx {
         p = nullptr;
     }
     void drop_graph() {
-        if (graph) (void)hipGraphExecDestroy(graph);
-        graph = nullptr;
-        graph_valid = false;
+        for (auto& gr : graphs) (void)hipGraphExecDestroy(gr.second);
+        graphs.clear();
     }
 };
 
@@ -148,11 +153,16 @@ void free_all(pdlpb_ctx* x) {
     for (auto e : x->ev) (void)hipEventDestroy(e);
     x->ev.clear();
     void* ptrs[] = {x->a_rp, x->a_ci, x->t_rp, x->t_ci, x->a_v64, x->t_v64, x->a_v32, x->t_v32,
-                    x->c, x->xl, x->xu, x->rl, x->ru, x->st, x->ctl, x->rlog, x->g, x->part,
-                    x->stage, x->pow_buf};
+                    x->c, x->xl, x->xu, x->rl, x->ru, x->st, x->slot_lp, x->ctl, x->rlog,
+                    x->retire, x->moves, x->g, x->part, x->stage, x->pow_buf};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     for (void*& p : x->blk)
+        if (p) {
+            (void)hipFree(p);
+            p = nullptr;
+        }
+    for (void*& p : x->res)
         if (p) {
             (void)hipFree(p);
             p = nullptr;
@@ -226,18 +236,27 @@ int compute_opnorm(pdlpb_ctx* x, double* out) {
     return PDLPB_OK;
 }
 
-// default tile: each row group of `lanes` lanes covers lanes*vec consecutive slots
-void choose_tile(pdlpb_ctx* x, int32_t B) {
+// default tile for `ncols` live columns: each row group of `lanes` lanes covers
+// lanes*vec consecutive slots; vec never exceeds the width ld was padded for
+void choose_tile(pdlpb_ctx* x, int32_t ncols) {
     int vec = 1;
-    if (x->fp32) vec = B >= 256 ? 4 : (B >= 128 ? 2 : 1);
-    else vec = B >= 128 ? 2 : 1;
+    if (x->fp32) vec = ncols >= 256 ? 4 : (ncols >= 128 ? 2 : 1);
+    else vec = ncols >= 128 ? 2 : 1;
     if (x->opt.tile_vec > 0) vec = x->opt.tile_vec;
-    int lanes = next_pow2((B + vec - 1) / vec);
+    if (vec > x->vec_ld) vec = x->vec_ld;
+    int lanes = next_pow2((ncols + vec - 1) / vec);
     if (lanes > 64) lanes = 64;
     if (x->opt.tile_lanes > 0) lanes = x->opt.tile_lanes;
     x->vec = vec;
     x->lanes = lanes;
     x->wpb = 4;
+}
+
+// launch shape for a live column count: the next power of two (at most B), so
+// a shrinking batch is re-captured at most log2(B) + 1 times per solve
+int32_t shape_cols(const pdlpb_ctx* x, int32_t live) {
+    int32_t c = next_pow2(live > 0 ? live : 1);
+    return c < x->B ? c : x->B;
 }
 
 template <typename T>
@@ -252,7 +271,7 @@ StepArgs<T> step_args(pdlpb_ctx* x, bool primal, int32_t it, int32_t eval) {
     a.av = av;
     a.rows = primal ? x->n : x->m;
     a.ld = x->ld;
-    a.ncols = x->B;
+    a.ncols = x->live;
     a.wpb = x->wpb;
     if (primal) {
         a.G = b[4];   // Y
@@ -274,7 +293,7 @@ template <typename T>
 EvalArgs<T> eval_args(pdlpb_ctx* x) {
     EvalArgs<T> a{};
     T* const* b = reinterpret_cast<T* const*>(x->blk);
-    a.n = x->n; a.m = x->m; a.ld = x->ld; a.ncols = x->B;
+    a.n = x->n; a.m = x->m; a.ld = x->ld; a.ncols = x->live;
     a.a_rp = x->a_rp; a.a_ci = x->a_ci;
     a.t_rp = x->t_rp; a.t_ci = x->t_ci;
     if constexpr (sizeof(T) == 8) {
@@ -288,6 +307,7 @@ EvalArgs<T> eval_args(pdlpb_ctx* x) {
     a.Yt = b[6]; a.DY = b[7]; a.Y0 = b[5];
     a.c = x->c; a.xl = x->xl; a.xu = x->xu; a.rl = x->rl; a.ru = x->ru;
     a.st = x->st;
+    a.g = x->g;
     a.pw_x = x->pw_x; a.pw_y = x->pw_y; a.npx = x->npx; a.npy = x->npy;
     a.part_x = x->part;
     a.part_y = x->part + (size_t)x->npx * NTERM * x->ld;
@@ -296,11 +316,12 @@ EvalArgs<T> eval_args(pdlpb_ctx* x) {
 
 ControlArgs control_args(pdlpb_ctx* x, int32_t it, int32_t full, int32_t advance) {
     ControlArgs a{};
-    a.ncols = x->B; a.ld = x->ld; a.npx = x->npx; a.npy = x->npy;
+    a.ncols = x->live; a.ld = x->ld; a.npx = x->npx; a.npy = x->npy;
     a.part_x = x->part;
     a.part_y = x->part + (size_t)x->npx * NTERM * x->ld;
     a.sums = x->part + (size_t)(x->npx + x->npy) * NTERM * x->ld;
-    a.st = x->st; a.ctl = x->ctl; a.rlog = x->rlog; a.g = x->g;
+    a.st = x->st; a.slot_lp = x->slot_lp; a.ctl = x->ctl; a.rlog = x->rlog;
+    a.retire = x->retire; a.moves = x->moves; a.g = x->g;
     a.it = it; a.full = full; a.advance = advance; a.block = x->opt.eval_every;
     a.batch_avg = x->opt.restart_scope == PDLPB_RESTART_BATCH_AVG;
     a.pw_literal = x->opt.pw_ratio == 1;
@@ -352,8 +373,11 @@ int enqueue_evaluation(pdlpb_ctx* x, int32_t it, int32_t full, int32_t advance,
     HIP_TRY(x, launch_control(c, x->stream));
     if (full) {
         T* const* b = reinterpret_cast<T* const*>(x->blk);
-        HIP_TRY(x, launch_apply_restart<T>(x->n, x->m, x->ld, x->B, x->st, b[1], b[2], b[4], b[5],
-                                           b[6], x->stream));
+        T* const* r = reinterpret_cast<T* const*>(x->res);
+        HIP_TRY(x, launch_apply_restart<T>(x->n, x->m, x->ld, x->live, x->st, x->g, b[1], b[2],
+                                           b[4], b[5], b[6], x->stream));
+        HIP_TRY(x, launch_compact<T>(x->n, x->m, x->ld, b, r, x->retire, x->moves, x->st,
+                                     x->slot_lp, x->g, x->stream));
     }
     if (rec && idx >= 0) (void)hipEventRecord(x->ev[2 * idx + 1], x->stream);
     return PDLPB_OK;
@@ -375,9 +399,23 @@ int enqueue_epoch(pdlpb_ctx* x, std::vector<std::pair<int, int>>* rec) {
     return PDLPB_OK;
 }
 
+// read the running count and the live column count back to the host
+int read_counts(pdlpb_ctx* x, int32_t* n_active, int32_t* n_cols) {
+    HIP_TRY(x, hipMemcpyAsync(x->h_pinned, x->g, 4 * sizeof(int32_t), hipMemcpyDeviceToHost,
+                              x->stream));
+    HIP_TRY(x, hipStreamSynchronize(x->stream));
+    *n_active = x->h_pinned[1];   // Globals::n_active
+    *n_cols = x->h_pinned[3];     // Globals::n_cols
+    return PDLPB_OK;
+}
+
 template <typename T>
 int run_solve(pdlpb_ctx* x, double tol, int32_t max_iters) {
-    HIP_TRY(x, launch_begin_solve(x->st, x->ctl, x->B, max_iters, x->g, tol, x->stream));
+    x->live = x->n_run0;
+    choose_tile(x, shape_cols(x, x->live));
+    x->live = shape_cols(x, x->live);
+    HIP_TRY(x, launch_begin_solve(x->st, x->slot_lp, x->ctl, x->n_run0, max_iters, x->g, tol,
+                                  x->stream));
     std::vector<std::pair<int, int>> rec;
     std::vector<std::pair<int, int>>* prec = x->timing ? &rec : nullptr;
     auto harvest = [&]() {
@@ -395,17 +433,25 @@ int run_solve(pdlpb_ctx* x, double tol, int32_t max_iters) {
     int rc = enqueue_iteration<T>(x, 0, 1, prec);
     if (!rc) rc = enqueue_evaluation<T>(x, 0, 1, 0, prec);
     if (rc) return rc;
-    HIP_TRY(x, hipMemcpyAsync(x->h_pinned, &x->g->n_active, sizeof(int32_t),
-                              hipMemcpyDeviceToHost, x->stream));
-    HIP_TRY(x, hipStreamSynchronize(x->stream));
+    int32_t n_active = 0, n_cols = 0;
+    rc = read_counts(x, &n_active, &n_cols);
+    if (rc) return rc;
     if (prec) harvest();
-    const bool graphs = x->opt.use_graphs && !x->timing;
+    const bool use_graphs = x->opt.use_graphs && !x->timing;
     const int64_t max_epochs = (int64_t)max_iters / x->opt.eval_every + 2;
-    for (int64_t ep = 0; *x->h_pinned > 0; ++ep) {
+    for (int64_t ep = 0; n_active > 0; ++ep) {
         if (ep > max_epochs) return x->fail(PDLPB_EDEVICE, "solve did not terminate");
-        if (graphs) {
-            if (!x->graph_valid) {
-                x->drop_graph();
+        // shape the launches for the live columns (compaction shrinks them)
+        const int32_t shape = shape_cols(x, n_cols);
+        if (shape != x->live) {
+            x->live = shape;
+            choose_tile(x, shape);
+        }
+        if (use_graphs) {
+            hipGraphExec_t exec = nullptr;
+            for (auto& gr : x->graphs)
+                if (gr.first == x->live) exec = gr.second;
+            if (!exec) {
                 hipGraph_t gr = nullptr;
                 HIP_TRY(x, hipStreamBeginCapture(x->stream, hipStreamCaptureModeThreadLocal));
                 int r2 = enqueue_epoch<T>(x, nullptr);
@@ -415,30 +461,26 @@ int run_solve(pdlpb_ctx* x, double tol, int32_t max_iters) {
                     return r2;
                 }
                 if (e != hipSuccess) return x->hip_fail(e, "hipStreamEndCapture");
-                e = hipGraphInstantiate(&x->graph, gr, nullptr, nullptr, 0);
+                e = hipGraphInstantiate(&exec, gr, nullptr, nullptr, 0);
                 (void)hipGraphDestroy(gr);
                 if (e != hipSuccess) return x->hip_fail(e, "hipGraphInstantiate");
-                x->graph_valid = true;
+                x->graphs.push_back({x->live, exec});
             }
-            HIP_TRY(x, hipGraphLaunch(x->graph, x->stream));
+            HIP_TRY(x, hipGraphLaunch(exec, x->stream));
         } else {
             rc = enqueue_epoch<T>(x, prec);
             if (rc) return rc;
         }
-        HIP_TRY(x, hipMemcpyAsync(x->h_pinned, &x->g->n_active, sizeof(int32_t),
-                                  hipMemcpyDeviceToHost, x->stream));
-        HIP_TRY(x, hipStreamSynchronize(x->stream));
+        rc = read_counts(x, &n_active, &n_cols);
+        if (rc) return rc;
         if (prec) harvest();
     }
     return PDLPB_OK;
 }
 
 int fetch_state(pdlpb_ctx* x) {
-    x->h_st.resize(x->B);
     x->h_ctl.resize(x->B);
     x->h_rlog.resize((size_t)x->B * RESTART_LOG);
-    HIP_TRY(x, hipMemcpyAsync(x->h_st.data(), x->st, sizeof(SlotState) * x->B,
-                              hipMemcpyDeviceToHost, x->stream));
     HIP_TRY(x, hipMemcpyAsync(x->h_ctl.data(), x->ctl, sizeof(SlotCtl) * x->B,
                               hipMemcpyDeviceToHost, x->stream));
     HIP_TRY(x, hipMemcpyAsync(x->h_rlog.data(), x->rlog, sizeof(int32_t) * RESTART_LOG * x->B,
@@ -453,6 +495,32 @@ int ensure_stage(pdlpb_ctx* x, size_t doubles) {
     x->cap_stage = 0;
     HIP_TRY(x, x->alloc(&x->stage, doubles * sizeof(double)));
     x->cap_stage = doubles;
+    return PDLPB_OK;
+}
+
+// Copy `count` LPs starting at LP `first` of result block q (0: x~, 1: Halpern x,
+// 2: y~, 3: Halpern y; LP-major) into dst as float64.
+int copy_results(pdlpb_ctx* x, int q, int32_t first, int32_t count, double* dst, int32_t mem) {
+    const int64_t rows = (q < 2) ? x->n : x->m;
+    const int64_t cnt = rows * count;
+    if (cnt == 0) return PDLPB_OK;
+    const hipMemcpyKind kind = mem == PDLPB_MEM_DEVICE ? hipMemcpyDeviceToDevice
+                                                        : hipMemcpyDeviceToHost;
+    if (x->fp32) {
+        const float* src = static_cast<const float*>(x->res[q]) + (size_t)first * rows;
+        if (mem == PDLPB_MEM_DEVICE) {
+            HIP_TRY(x, launch_widen(src, cnt, dst, x->stream));
+        } else {
+            int rc = ensure_stage(x, (size_t)cnt);
+            if (rc) return rc;
+            HIP_TRY(x, launch_widen(src, cnt, x->stage, x->stream));
+            HIP_TRY(x, hipMemcpyAsync(dst, x->stage, cnt * sizeof(double), kind, x->stream));
+        }
+    } else {
+        const double* src = static_cast<const double*>(x->res[q]) + (size_t)first * rows;
+        HIP_TRY(x, hipMemcpyAsync(dst, src, cnt * sizeof(double), kind, x->stream));
+    }
+    HIP_TRY(x, hipStreamSynchronize(x->stream));
     return PDLPB_OK;
 }
 
@@ -521,7 +589,7 @@ int pdlpb_create(pdlpb_ctx** out, int32_t m, int32_t n, int64_t nnz, const int64
     if (!(o.step_size >= 0.0) || !std::isfinite(o.step_size)) return bad("step_size must be >= 0");
     if (o.cross_sign != -1.0 && o.cross_sign != 1.0) return bad("cross_sign must be -1 or +1");
     if (std::isnan(o.infeas_tol) || !std::isfinite(o.infeas_tol)) return bad("infeas_tol must be finite");
-    if (o.max_batch < 1 || o.max_batch > (1 << 20)) return bad("max_batch out of range");
+    if (o.max_batch < 1 || o.max_batch > MAX_BATCH) return bad("max_batch must be in [1, 4096]");
     if (o.restart_scope == PDLPB_RESTART_BATCH_AVG && o.max_batch > 1024) o.max_batch = 1024;
     if (o.tile_lanes != 0 && (o.tile_lanes < 1 || o.tile_lanes > 64 ||
                               (o.tile_lanes & (o.tile_lanes - 1))))
@@ -683,8 +751,11 @@ int pdlpb_set_batch(pdlpb_ctx* x, int32_t B, const pdlpb_delta* deltas, const do
         std::memcpy(d.data(), deltas, sizeof(pdlpb_delta) * B);
         if (w_warm) std::memcpy(w0.data(), w_warm, sizeof(double) * B);
     }
-    std::vector<SlotState> hs(B);
+    std::vector<SlotState> hs;
+    std::vector<int32_t> slot_lp;
     std::vector<SlotCtl> hc(B);
+    hs.reserve(B);
+    slot_lp.reserve(B);
     for (int32_t j = 0; j < B; ++j) {
         const pdlpb_delta& q = d[j];
         if (q.kind < PDLPB_BASE || q.kind > PDLPB_OBJ_UNIT)
@@ -717,13 +788,8 @@ int pdlpb_set_batch(pdlpb_ctx* x, int32_t B, const pdlpb_delta* deltas, const do
         } else if (cn > 1e-10 && x->norm_b > 1e-10) {
             w = cn / x->norm_b;
         }
-        if (status != PDLPB_STATUS_RUNNING) {
-            s.flags = 0;
-            s.value = std::isnan(q.value) ? 0.0 : q.value;
-            w = 1.0;
-        } else {
-            s.flags = SLOT_ACTIVE;
-        }
+        if (status != PDLPB_STATUS_RUNNING) w = 1.0;
+        s.flags = SLOT_ACTIVE;
         s.tau = x->eta / w;
         s.sigma = x->eta * w;
         cl.w = w;
@@ -731,12 +797,20 @@ int pdlpb_set_batch(pdlpb_ctx* x, int32_t B, const pdlpb_delta* deltas, const do
         cl.status = status;
         for (double& v : cl.kkt) v = NAN;
         cl.obj = NAN;
-        hs[j] = s;
+        if (status == PDLPB_STATUS_RUNNING) {   // running LPs fill slots [0, n_run0) in LP order
+            hs.push_back(s);
+            slot_lp.push_back(j);
+        } else {
+            cl.iters = 0;
+        }
         hc[j] = cl;
     }
+    const int32_t n_run0 = (int32_t)hs.size();
 
     // storage (grows, reused for smaller batches)
+    x->vec_ld = 4;
     choose_tile(x, B);
+    x->vec_ld = x->vec;
     const int32_t ld = ((B + x->vec - 1) / x->vec) * x->vec;
     const size_t esz = x->fp32 ? sizeof(float) : sizeof(double);
     const size_t rows_max = (size_t)std::max(n, m);
@@ -748,15 +822,34 @@ int pdlpb_set_batch(pdlpb_ctx* x, int32_t B, const pdlpb_delta* deltas, const do
         for (void*& p : x->blk) HIP_TRY(x, x->alloc(&p, block_bytes));
         x->cap_block_bytes = block_bytes;
     }
+    const size_t rx_bytes = (size_t)B * n * esz, ry_bytes = (size_t)B * m * esz;
+    if (rx_bytes > x->cap_res_x || ry_bytes > x->cap_res_y) {
+        x->drop_graph();
+        x->release(x->res[0], x->cap_res_x);
+        x->release(x->res[1], x->cap_res_x);
+        x->release(x->res[2], x->cap_res_y);
+        x->release(x->res[3], x->cap_res_y);
+        x->cap_res_x = x->cap_res_y = 0;
+        for (int q = 0; q < 2; ++q) HIP_TRY(x, x->alloc(&x->res[q], rx_bytes));
+        for (int q = 2; q < 4; ++q) HIP_TRY(x, x->alloc(&x->res[q], ry_bytes));
+        x->cap_res_x = rx_bytes;
+        x->cap_res_y = ry_bytes;
+    }
     if (B > x->cap_slots) {
         x->drop_graph();
         x->release(x->st, sizeof(SlotState) * x->cap_slots);
+        x->release(x->slot_lp, sizeof(int32_t) * x->cap_slots);
         x->release(x->ctl, sizeof(SlotCtl) * x->cap_slots);
         x->release(x->rlog, sizeof(int32_t) * RESTART_LOG * x->cap_slots);
+        x->release(x->retire, sizeof(RetireEntry) * x->cap_slots);
+        x->release(x->moves, sizeof(MoveEntry) * x->cap_slots);
         x->cap_slots = 0;
         HIP_TRY(x, x->alloc(&x->st, sizeof(SlotState) * B));
+        HIP_TRY(x, x->alloc(&x->slot_lp, sizeof(int32_t) * B));
         HIP_TRY(x, x->alloc(&x->ctl, sizeof(SlotCtl) * B));
         HIP_TRY(x, x->alloc(&x->rlog, sizeof(int32_t) * RESTART_LOG * B));
+        HIP_TRY(x, x->alloc(&x->retire, sizeof(RetireEntry) * B));
+        HIP_TRY(x, x->alloc(&x->moves, sizeof(MoveEntry) * B));
         x->cap_slots = B;
     }
     const size_t part_need = (size_t)(x->npx + x->npy + 2) * NTERM * ld;
@@ -770,13 +863,28 @@ int pdlpb_set_batch(pdlpb_ctx* x, int32_t B, const pdlpb_delta* deltas, const do
     x->drop_graph();   // grid shapes and slot count are baked into the captured launches
     x->B = B;
     x->ld = ld;
+    x->n_run0 = n_run0;
     x->batch_set = true;
     x->solved = false;
 
-    HIP_TRY(x, hipMemcpyAsync(x->st, hs.data(), sizeof(SlotState) * B, hipMemcpyHostToDevice,
-                              x->stream));
+    if (n_run0 > 0) {
+        HIP_TRY(x, hipMemcpyAsync(x->st, hs.data(), sizeof(SlotState) * n_run0,
+                                  hipMemcpyHostToDevice, x->stream));
+        HIP_TRY(x, hipMemcpyAsync(x->slot_lp, slot_lp.data(), sizeof(int32_t) * n_run0,
+                                  hipMemcpyHostToDevice, x->stream));
+    }
     HIP_TRY(x, hipMemcpyAsync(x->ctl, hc.data(), sizeof(SlotCtl) * B, hipMemcpyHostToDevice,
                               x->stream));
+    // LPs that never run report x = 0, y = 0
+    for (int32_t j = 0; j < B; ++j) {
+        if (hc[j].status == PDLPB_STATUS_RUNNING) continue;
+        for (int q = 0; q < 4; ++q) {
+            const size_t len = (size_t)(q < 2 ? n : m) * esz;
+            if (len)
+                HIP_TRY(x, hipMemsetAsync(static_cast<char*>(x->res[q]) + (size_t)j * len, 0, len,
+                                          x->stream));
+        }
+    }
     const double* xw = nullptr;
     const double* yw = nullptr;
     if (warm_mode != PDLPB_WARM_NONE) {
@@ -799,18 +907,17 @@ int pdlpb_set_batch(pdlpb_ctx* x, int32_t B, const pdlpb_delta* deltas, const do
     }
     if (x->fp32) {
         float* const* b = reinterpret_cast<float* const*>(x->blk);
-        HIP_TRY(x, launch_init_blocks<float>(n, m, ld, B, x->st, x->xl, x->xu, xw, yw, warm_mode,
-                                             b[0], b[1], b[2], b[3], b[4], b[5], b[6], b[7],
-                                             x->stream));
+        HIP_TRY(x, launch_init_blocks<float>(n, m, ld, n_run0, x->st, x->slot_lp, x->xl, x->xu, xw,
+                                             yw, warm_mode, b[0], b[1], b[2], b[3], b[4], b[5],
+                                             b[6], b[7], x->stream));
     } else {
         double* const* b = reinterpret_cast<double* const*>(x->blk);
-        HIP_TRY(x, launch_init_blocks<double>(n, m, ld, B, x->st, x->xl, x->xu, xw, yw, warm_mode,
-                                              b[0], b[1], b[2], b[3], b[4], b[5], b[6], b[7],
-                                              x->stream));
+        HIP_TRY(x, launch_init_blocks<double>(n, m, ld, n_run0, x->st, x->slot_lp, x->xl, x->xu,
+                                              xw, yw, warm_mode, b[0], b[1], b[2], b[3], b[4],
+                                              b[5], b[6], b[7], x->stream));
     }
     // host staging must outlive the copies
     HIP_TRY(x, hipStreamSynchronize(x->stream));
-    x->h_st = hs;
     x->h_ctl = hc;
     return PDLPB_OK;
 }
@@ -822,7 +929,9 @@ int pdlpb_solve(pdlpb_ctx* x, double tol, int64_t max_iters) {
     if (!(tol >= 0.0)) return x->fail(PDLPB_EINVAL, "tol must be >= 0");
     if (max_iters < 1 || max_iters > (1 << 30)) return x->fail(PDLPB_EINVAL, "max_iters out of range");
     HIP_TRY(x, hipSetDevice(x->device));
-    int rc = x->fp32 ? run_solve<float>(x, tol, (int32_t)max_iters)
+    int rc = PDLPB_OK;
+    if (x->n_run0 > 0)
+        rc = x->fp32 ? run_solve<float>(x, tol, (int32_t)max_iters)
                      : run_solve<double>(x, tol, (int32_t)max_iters);
     if (rc) return rc;
     rc = fetch_state(x);
@@ -845,26 +954,10 @@ int pdlpb_get(pdlpb_ctx* x, int32_t j, double* xo, double* yo, int32_t* status, 
         for (int q = 0; q < 4; ++q) kkt[q] = cl.kkt[q];
     if (obj) *obj = cl.obj;
     if (iters) *iters = cl.iters;
-    const hipMemcpyKind kind = mem == PDLPB_MEM_DEVICE ? hipMemcpyDeviceToDevice
-                                                        : hipMemcpyDeviceToHost;
-    if (xo || yo) {
-        int rc = ensure_stage(x, (size_t)x->n + x->m);
-        if (rc) return rc;
-        if (x->fp32) {
-            float* const* b = reinterpret_cast<float* const*>(x->blk);
-            if (xo) HIP_TRY(x, launch_gather_column<float>(b[2], x->n, x->ld, j, x->stage, x->stream));
-            if (yo) HIP_TRY(x, launch_gather_column<float>(b[6], x->m, x->ld, j, x->stage + x->n, x->stream));
-        } else {
-            double* const* b = reinterpret_cast<double* const*>(x->blk);
-            if (xo) HIP_TRY(x, launch_gather_column<double>(b[2], x->n, x->ld, j, x->stage, x->stream));
-            if (yo) HIP_TRY(x, launch_gather_column<double>(b[6], x->m, x->ld, j, x->stage + x->n, x->stream));
-        }
-        if (xo) HIP_TRY(x, hipMemcpyAsync(xo, x->stage, sizeof(double) * x->n, kind, x->stream));
-        if (yo && x->m)
-            HIP_TRY(x, hipMemcpyAsync(yo, x->stage + x->n, sizeof(double) * x->m, kind, x->stream));
-        HIP_TRY(x, hipStreamSynchronize(x->stream));
-    }
-    return PDLPB_OK;
+    int rc = PDLPB_OK;
+    if (xo) rc = copy_results(x, 0, j, 1, xo, mem);
+    if (!rc && yo) rc = copy_results(x, 2, j, 1, yo, mem);
+    return rc;
 }
 
 int pdlpb_get_batch(pdlpb_ctx* x, double* X, double* Y, int32_t* status, double* kkt, double* obj,
@@ -883,30 +976,10 @@ int pdlpb_get_batch(pdlpb_ctx* x, double* X, double* Y, int32_t* status, double*
         if (obj) obj[j] = cl.obj;
         if (iters) iters[j] = cl.iters;
     }
-    const hipMemcpyKind kind = mem == PDLPB_MEM_DEVICE ? hipMemcpyDeviceToDevice
-                                                        : hipMemcpyDeviceToHost;
-    for (int side = 0; side < 2; ++side) {
-        double* dst = side == 0 ? X : Y;
-        const int32_t rows = side == 0 ? x->n : x->m;
-        if (!dst || rows == 0) continue;
-        const size_t cnt = (size_t)rows * B;
-        double* tmp = dst;
-        if (mem == PDLPB_MEM_HOST) {
-            int rc = ensure_stage(x, cnt);
-            if (rc) return rc;
-            tmp = x->stage;
-        }
-        if (x->fp32)
-            HIP_TRY(x, launch_transpose_out<float>(reinterpret_cast<float*>(x->blk[side == 0 ? 2 : 6]),
-                                                   rows, x->ld, B, tmp, x->stream));
-        else
-            HIP_TRY(x, launch_transpose_out<double>(reinterpret_cast<double*>(x->blk[side == 0 ? 2 : 6]),
-                                                    rows, x->ld, B, tmp, x->stream));
-        if (mem == PDLPB_MEM_HOST)
-            HIP_TRY(x, hipMemcpyAsync(dst, tmp, cnt * sizeof(double), kind, x->stream));
-        HIP_TRY(x, hipStreamSynchronize(x->stream));
-    }
-    return PDLPB_OK;
+    int rc = PDLPB_OK;
+    if (X) rc = copy_results(x, 0, 0, B, X, mem);
+    if (!rc && Y) rc = copy_results(x, 2, 0, B, Y, mem);
+    return rc;
 }
 
 int pdlpb_get_trace(pdlpb_ctx* x, int32_t j, double* x_iter, double* y_iter, double* w,
@@ -917,35 +990,16 @@ int pdlpb_get_trace(pdlpb_ctx* x, int32_t j, double* x_iter, double* y_iter, dou
     if (j < 0 || j >= x->B) return x->fail(PDLPB_EINVAL, "LP index out of range");
     HIP_TRY(x, hipSetDevice(x->device));
     const SlotCtl& cl = x->h_ctl[j];
-    const SlotState& st = x->h_st[j];
     if (w) *w = cl.w;
     if (restarts) *restarts = cl.restarts;
     if (restart_log && log_cap > 0) {
         const int32_t cnt = std::min(std::min(cl.restarts, (int32_t)RESTART_LOG), log_cap);
         for (int32_t q = 0; q < cnt; ++q) restart_log[q] = x->h_rlog[(size_t)j * RESTART_LOG + q];
     }
-    if (x_iter || y_iter) {
-        int rc = ensure_stage(x, (size_t)x->n + x->m);
-        if (rc) return rc;
-        const int32_t k = cl.t_last - st.t_anchor;   // inner index of the LP's last iteration
-        const double a = double(k + 1) / double(k + 2);
-        if (x->fp32) {
-            float* const* b = reinterpret_cast<float* const*>(x->blk);
-            HIP_TRY(x, launch_halpern_column<float>(b[0], b[1], x->n, x->ld, j, a, k + 2, x->stage, x->stream));
-            HIP_TRY(x, launch_gather_column<float>(b[4], x->m, x->ld, j, x->stage + x->n, x->stream));
-        } else {
-            double* const* b = reinterpret_cast<double* const*>(x->blk);
-            HIP_TRY(x, launch_halpern_column<double>(b[0], b[1], x->n, x->ld, j, a, k + 2, x->stage, x->stream));
-            HIP_TRY(x, launch_gather_column<double>(b[4], x->m, x->ld, j, x->stage + x->n, x->stream));
-        }
-        if (x_iter)
-            HIP_TRY(x, hipMemcpyAsync(x_iter, x->stage, sizeof(double) * x->n, hipMemcpyDeviceToHost, x->stream));
-        if (y_iter && x->m)
-            HIP_TRY(x, hipMemcpyAsync(y_iter, x->stage + x->n, sizeof(double) * x->m,
-                                      hipMemcpyDeviceToHost, x->stream));
-        HIP_TRY(x, hipStreamSynchronize(x->stream));
-    }
-    return PDLPB_OK;
+    int rc = PDLPB_OK;
+    if (x_iter) rc = copy_results(x, 1, j, 1, x_iter, PDLPB_MEM_HOST);
+    if (!rc && y_iter) rc = copy_results(x, 3, j, 1, y_iter, PDLPB_MEM_HOST);
+    return rc;
 }
 
 int pdlpb_get_step_size(const pdlpb_ctx* x, double* eta, double* norm_a) {

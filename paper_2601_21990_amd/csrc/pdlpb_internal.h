@@ -11,8 +11,10 @@ namespace pdlpb {
 // ---- per-slot state read by the fused step kernels ------------------------
 // SLOT_FRESH marks an LP restarted by the last full evaluation: the restart
 // kernel copies z~ into its anchor and iterate, and the next residual
-// evaluation records r(z^{n,0}) and clears the flag.
-enum : int32_t { SLOT_ACTIVE = 1, SLOT_FRESH = 2 };
+// evaluation records r(z^{n,0}) and clears the flag.  SLOT_RETIRE marks an LP
+// that has stopped and whose results still sit in its slot; the next
+// compaction copies them out and frees the slot.
+enum : int32_t { SLOT_ACTIVE = 1, SLOT_FRESH = 2, SLOT_RETIRE = 4 };
 
 struct SlotState {
     int32_t kind;      // delta kind (PDLPB_BASE .. PDLPB_OBJ_UNIT)
@@ -27,8 +29,9 @@ struct SlotState {
 };
 static_assert(sizeof(SlotState) == 48, "SlotState layout");
 
-// ---- per-slot control data (control kernel only) ---------------------------
+// ---- per-LP control data (indexed by LP, not by slot) -----------------------
 constexpr int RESTART_LOG = 64;
+constexpr int MAX_BATCH = 4096;
 
 struct SlotCtl {
     double  w;         // primal weight
@@ -40,6 +43,21 @@ struct SlotCtl {
     int32_t iters;     // applications of T
     int32_t restarts;  // number of restarts
     int32_t t_last;    // global iteration index of the LP's last iteration
+    int32_t k_last;    // inner index k of the LP's last iteration (Halpern weight of its last update)
+    int32_t pad;
+};
+
+// ---- compaction plan written by the control pass, executed by k_compact ------
+struct RetireEntry {
+    int32_t slot;      // slot whose LP has stopped
+    int32_t lp;        // that LP
+    int32_t kp2;       // k_last + 2
+    int32_t pad;
+    double  a;         // (k_last + 1) / (k_last + 2)
+};
+struct MoveEntry {
+    int32_t src;       // running slot beyond the new column count
+    int32_t dst;       // freed slot below it
 };
 
 // ---- batch-wide scalars on the device ---------------------------------------
@@ -47,6 +65,10 @@ struct Globals {
     int32_t t0;          // base iteration index of the current block of C iterations
     int32_t n_active;    // LPs still running after the last control pass
     int32_t batch_k0;    // BATCH_AVG: global index at which the shared restart cycle began
+    int32_t n_cols;      // live columns: slots [0, n_cols) hold every running LP
+    int32_t n_retire;    // compaction plan: stopped LPs to copy out
+    int32_t n_move;      //   running LPs to move into freed slots
+    int32_t n_cols_next; //   live columns after the compaction
     int32_t pad;
     double  tol;
     double  eta;
@@ -70,7 +92,7 @@ struct StepArgs {
     const T*       av;   // values
     int32_t rows;        // rows walked (n for the primal step, m for the dual step)
     int32_t ld;          // row stride of every dense block (>= ncols)
-    int32_t ncols;       // slots in use
+    int32_t ncols;       // columns covered by the grid (the live count g->n_cols never exceeds it)
     int32_t wpb;         // waves per block
     const T* G;          // block gathered by the product (Y for primal, Xbar for dual)
     T* Z;                // primal: Xbar (reflected x, 2x~ - x^k)   dual: Y (Halpern iterate y^k)
@@ -94,6 +116,7 @@ struct EvalArgs {
     const T *Xt, *DX, *X0, *Yt, *DY, *Y0;
     const double *c, *xl, *xu, *rl, *ru;
     const SlotState* st;
+    const Globals* g;        // live column count
     int32_t pw_x, pw_y;      // rows per wave on the x side / y side
     int32_t npx, npy;        // row panels (4 waves each) on each side
     double* part_x;          // [NTERM][ld][npx]
@@ -105,9 +128,12 @@ struct ControlArgs {
     const double* part_x;
     const double* part_y;
     double* sums;            // [2*NTERM][ld] scratch written by the reduce kernel
-    SlotState* st;
-    SlotCtl* ctl;
-    int32_t* rlog;           // [ncols][RESTART_LOG]
+    SlotState* st;           // by slot
+    const int32_t* slot_lp;  // LP held by each slot
+    SlotCtl* ctl;            // by LP
+    int32_t* rlog;           // [LP][RESTART_LOG]
+    RetireEntry* retire;     // compaction plan (>= B entries each)
+    MoveEntry* moves;
     Globals* g;
     int32_t it;              // iteration index inside the block
     int32_t full;            // 1: KKT and restart tests (t mod C == 0); 0: residual of fresh cycles only
@@ -132,37 +158,35 @@ hipError_t launch_control(const ControlArgs& a, hipStream_t s);
 
 // Fill the dense blocks of a new batch.  Warm vectors: mode 0 none, 1 shared
 // (xw: n, yw: m), 2 per LP (xw: ncols*n, yw: ncols*m, LP-major).
+// slot_lp maps slots [0, ncols) to LPs (per-LP warm starts are indexed by LP).
 template <typename T>
 hipError_t launch_init_blocks(int32_t n, int32_t m, int32_t ld, int32_t ncols,
-                              const SlotState* st, const double* xl, const double* xu,
-                              const double* xw, const double* yw, int32_t mode,
+                              const SlotState* st, const int32_t* slot_lp, const double* xl,
+                              const double* xu, const double* xw, const double* yw, int32_t mode,
                               T* Xbar, T* X0, T* Xt, T* DX, T* Y, T* Y0, T* Yt, T* DY,
                               hipStream_t s);
 
 // Apply the restarts decided by the control pass (slots flagged SLOT_FRESH).
 template <typename T>
 hipError_t launch_apply_restart(int32_t n, int32_t m, int32_t ld, int32_t ncols,
-                                const SlotState* st, T* X0, const T* Xt, T* Y, T* Y0, const T* Yt,
-                                hipStream_t s);
+                                const SlotState* st, const Globals* g, T* X0, const T* Xt, T* Y,
+                                T* Y0, const T* Yt, hipStream_t s);
 
-// Start a solve: t_end of every active slot from the iteration budget, g->t0 = 0.
-hipError_t launch_begin_solve(SlotState* st, SlotCtl* ctl, int32_t ncols, int32_t max_iters,
-                              Globals* g, double tol, hipStream_t s);
-
-// Copy column `slot` of a row-major block (rows x ld) into a contiguous float64 vector.
+// Execute the compaction plan: copy stopped LPs' z~ and last Halpern iterate
+// into the LP-major result blocks, move running LPs into freed slots.
+// blk: Xbar, X0, Xt, DX, Y, Y0, Yt, DY (row-major, stride ld).
+// res: Rx (B x n), Rxi (B x n), Ry (B x m), Ryi (B x m), LP-major.
 template <typename T>
-hipError_t launch_gather_column(const T* Z, int32_t rows, int32_t ld, int32_t slot,
-                                double* out, hipStream_t s);
+hipError_t launch_compact(int32_t n, int32_t m, int32_t ld, T* const* blk, T* const* res,
+                          const RetireEntry* retire, const MoveEntry* moves, SlotState* st,
+                          int32_t* slot_lp, Globals* g, hipStream_t s);
 
-// LP-major copy of the first ncols columns of a row-major block: out[s*rows + i] = Z[i*ld + s].
-template <typename T>
-hipError_t launch_transpose_out(const T* Z, int32_t rows, int32_t ld, int32_t ncols, double* out,
-                                hipStream_t s);
+// Start a solve: t_end of every live slot from the iteration budget, g->t0 = 0.
+hipError_t launch_begin_solve(SlotState* st, const int32_t* slot_lp, SlotCtl* ctl, int32_t ncols,
+                              int32_t max_iters, Globals* g, double tol, hipStream_t s);
 
-// Halpern iterate of the last update: x = a*Xbar + X0*b (column `slot`).
-template <typename T>
-hipError_t launch_halpern_column(const T* Xbar, const T* X0, int32_t rows, int32_t ld,
-                                 int32_t slot, double a, int32_t kp2, double* out, hipStream_t s);
+// Convert n entries of a result block to float64 (FP32 mode).
+hipError_t launch_widen(const float* src, int64_t count, double* dst, hipStream_t s);
 
 // Power iteration building blocks (float64, one vector).
 hipError_t launch_spmv(const int32_t* rp, const int32_t* ci, const double* v, int32_t rows,
