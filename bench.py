@@ -89,8 +89,166 @@ def _cpu_task(t):
     return r.status
 
 
+def run_sweep(args):
+    """Fused product kernels on a large matrix (200k x 500k, 4 N(0,1) nonzeros per
+    column, the serving-stream family) at batch widths B and both precisions:
+    a fixed number of iterations per point, every launch bracketed by HIP events;
+    achieved GB/s = compulsory bytes / average launch time (8 TB/s peak)."""
+    import numpy as np
+    import paper_2601_21990_amd.pdlpb as P
+    from workloads import make_cfg5, obbt_deltas, choose_vars
+    inst = make_cfg5(m=args.sweep_m, n=int(round(2.5 * args.sweep_m)))
+    m, n, nnz = inst.m, inst.n, inst.nnz
+    log(f"sweep instance m={m} n={n} nnz={nnz}")
+    widths = [int(b) for b in args.sweep_b.split(",")]
+    points = []
+    tiles = [tuple(int(v) for v in t.split("x")) for t in args.sweep_tiles.split(",")]
+    eta = None
+    for prec, s_it, s_val, name in ((P.MIXED32, 4, 4, "fp32"), (P.FP64, 8, 8, "fp64")):
+        if name not in args.sweep_prec.split(","):
+            continue
+        kw = {} if eta is None else {"step_size": eta}
+        ctx = P.Context.from_instance(inst, device=0, precision=prec, use_graphs=0, **kw)
+        eta = ctx.step_size[0]
+        for B in widths:
+            D = obbt_deltas(choose_vars(n, max(B // 2, 1), seed=B))[:B]
+            for lanes, vec in tiles:
+                if vec > 1 and B % vec:
+                    continue
+                ctx.set_tile(lanes, vec)
+                ctx.set_batch(D)
+                ctx.set_kernel_timing(True)
+                ctx.solve(tol=0.0, max_iters=args.sweep_iters)
+                cnt, ms = ctx.kernel_times()
+                ctx.set_kernel_timing(False)
+                for kind, kname in ((0, "primal"), (1, "dual")):
+                    avg = ms[kind] / max(cnt[kind], 1)
+                    q = fused_bytes(kind, m, n, nnz, B, s_val, s_it)
+                    gbs = q / (avg * 1e-3) / 1e9
+                    points.append({"precision": name, "B": B, "tile": f"{lanes}x{vec}",
+                                   "kernel": kname, "avg_us": round(avg * 1e3, 2),
+                                   "bytes": int(q), "GBps": round(gbs, 1),
+                                   "frac": round(gbs / HBM_PEAK_GBS, 4)})
+                    log(f"{name} B={B:4d} tile={lanes}x{vec} {kname:6s}: {avg*1e3:9.1f} us "
+                        f"{q/1e6:9.1f} MB {gbs:8.1f} GB/s")
+        ctx.close()
+    best = max(points, key=lambda p: p["GBps"])
+    print(json.dumps({"metric": "SpMM HBM GB/s (fused product + PDHG step)", "value": best["GBps"],
+                      "unit": "GB/s", "peak": HBM_PEAK_GBS, "config": {
+                          "workload": f"A {m}x{n}, nnz {nnz}, 4 N(0,1) nonzeros per column",
+                          "iterations_per_point": args.sweep_iters}, "best": best,
+                      "points": points}), flush=True)
+
+
+def run_copy(args):
+    """Calibration for HBM counters: a plain device-to-device copy of a known
+    size (1 GiB read + 1 GiB written per copy), repeated 4 times."""
+    import torch
+    nbytes = 1 << 30
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda:0")
+    b = torch.empty_like(a)
+    a.fill_(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(4):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / 4
+    print(json.dumps({"metric": "device copy GB/s", "value": round(2 * nbytes / dt / 1e9, 1),
+                      "unit": "GB/s", "bytes_read_per_copy": nbytes,
+                      "bytes_written_per_copy": nbytes, "copies": 4}), flush=True)
+
+
+def run_serve(args):
+    """Serving stream: four resident base LPs (the 200k x 500k family by
+    default, FP32 products with FP64 sums), each with its root solution kept
+    on the device as warm start.  Requests arrive as a Poisson process; each
+    is a strong-branching batch of 2..512 LPs (log-uniform, even) on a random
+    base.  The loop admits requests as columns and result rows free up and
+    reports p50 / p99 latency and LPs/s per arrival rate."""
+    import numpy as np
+    import paper_2601_21990_amd.pdlpb as P
+    from paper_2601_21990_amd.serve import Server, Request, percentile
+    from workloads import make_cfg5, fsb_deltas, deltas, BASE
+    m = args.serve_m
+    n = int(round(2.5 * m))
+    prec = P.MIXED32 if args.serve_prec == "fp32" else P.FP64
+    ctxs, roots = [], []
+    for b in range(args.serve_bases):
+        inst = make_cfg5(base=b, m=m, n=n)
+        ctx = P.Context.from_instance(inst, device=0, precision=prec, max_batch=args.serve_cols)
+        ctx.set_batch(deltas([BASE], [0], [0.0]))
+        ctx.solve(tol=1e-6, max_iters=200000)
+        root = ctx.get(0)
+        w = ctx.get_trace(0)["w"]
+        log(f"base {b}: m={m} n={n} root {P.STATUS_NAMES[root['status']]} iters={root['iters']}")
+        frac = root["x"] - np.floor(root["x"])
+        cand = np.nonzero((frac > 0.1) & (frac < 0.9))[0]
+        ctx.set_base_warm(root["x"], root["y"], w)
+        ctx.serve_begin(args.serve_rows)
+        ctxs.append(ctx)
+        roots.append((root["x"], cand))
+    rng = np.random.default_rng(2601021990 + 5000)
+    lines = []
+    for rate in [float(r) for r in args.serve_rates.split(",")]:
+        srv = Server(ctxs, warm=True)
+        t_start = time.perf_counter()
+        next_arrival = t_start + rng.exponential(1.0 / rate)
+        n_req = 0
+        while True:
+            now = time.perf_counter()
+            while next_arrival <= now and next_arrival - t_start < args.serve_seconds:
+                b = int(rng.integers(0, len(ctxs)))
+                size = int(round(np.exp(rng.uniform(np.log(2), np.log(512))) / 2)) * 2
+                size = max(2, min(512, size))
+                x, cand = roots[b]
+                vars_ = np.sort(rng.choice(cand, size=size // 2, replace=False)).astype(np.int32)
+                srv.submit(Request(base=b, deltas=fsb_deltas(x, vars_), arrival=next_arrival,
+                                   tol=1e-4))
+                n_req += 1
+                next_arrival += rng.exponential(1.0 / rate)
+            if next_arrival - t_start >= args.serve_seconds and not srv.busy():
+                break
+            if srv.busy():
+                srv.step()
+            else:
+                time.sleep(max(0.0, min(next_arrival - time.perf_counter(), 0.01)))
+        wall = time.perf_counter() - t_start
+        lat = [r.latency for r in srv.completed]
+        solved = sum(sum(1 for s in r.statuses.values() if s == P.STATUS_OPTIMAL)
+                     for r in srv.completed)
+        line = {"rate_per_s": rate, "requests": n_req, "completed": len(srv.completed),
+                "lps": srv.lps_done, "lps_optimal": solved, "wall_s": round(wall, 3),
+                "lps_per_s": round(srv.lps_done / wall, 2),
+                "p50_s": round(percentile(lat, 50), 4), "p99_s": round(percentile(lat, 99), 4)}
+        log(json.dumps(line))
+        lines.append(line)
+    for c in ctxs:
+        c.close()
+    print(json.dumps({"metric": "serving p50/p99 latency and LPs/s",
+                      "config": {"workload": f"{args.serve_bases} resident bases A {m}x{n} "
+                                             f"(4 N(0,1) nnz/col), requests of 2..512 "
+                                             f"strong-branching LPs, warm start, tol 1e-4",
+                                 "precision": args.serve_prec, "columns": args.serve_cols,
+                                 "result_rows": args.serve_rows},
+                      "rates": lines}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--workload", default="fsb", choices=["fsb", "sweep", "copy", "serve"])
+    ap.add_argument("--serve-m", type=int, default=200000)
+    ap.add_argument("--serve-bases", type=int, default=4)
+    ap.add_argument("--serve-prec", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--serve-cols", type=int, default=1024)
+    ap.add_argument("--serve-rows", type=int, default=2048)
+    ap.add_argument("--serve-rates", default="1,3,10")
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--sweep-m", type=int, default=200000)
+    ap.add_argument("--sweep-b", default="1,8,32,64,128,256,512")
+    ap.add_argument("--sweep-iters", type=int, default=65)
+    ap.add_argument("--sweep-tiles", default="0x0", help="lanes x vec per point; 0x0 = automatic")
+    ap.add_argument("--sweep-prec", default="fp32,fp64")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
@@ -104,6 +262,16 @@ def main():
               "communication, so N GPUs give N independent copies of this measurement",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "sweep":
+        run_sweep(args)
+        return
+    if args.workload == "copy":
+        run_copy(args)
+        return
+    if args.workload == "serve":
+        run_serve(args)
+        return
 
     import numpy as np
     log("importing torch")
@@ -149,7 +317,8 @@ def main():
         ctx.solve(tol=1e-4, max_iters=100000)
         return ctx.get_batch(X=d_X, Y=d_Y, mem=P.MEM_DEVICE)
 
-    for i in range(args.warmup):
+    out = None
+    for i in range(max(args.warmup, 1)):
         out = step()
     log(f"warmup done: iters min/median/max = {out['iters'].min()}/{int(np.median(out['iters']))}/"
         f"{out['iters'].max()}, statuses {np.bincount(out['status'], minlength=6).tolist()}")

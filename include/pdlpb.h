@@ -83,6 +83,7 @@ typedef struct pdlpb_delta {
 #define PDLPB_WARM_NONE    0   /* x = projection of 0 onto the LP's box, y = 0 */
 #define PDLPB_WARM_SHARED  1   /* one x (n) and y (m) for every LP, projected onto each LP's box */
 #define PDLPB_WARM_PER_LP  2   /* LP-major blocks x (B*n) and y (B*m) */
+#define PDLPB_WARM_BASE    3   /* serving: the context's resident warm start (pdlpb_set_base_warm) */
 
 #define PDLPB_MEM_HOST     0
 #define PDLPB_MEM_DEVICE   1
@@ -107,7 +108,9 @@ typedef struct pdlpb_options {
     int32_t use_graphs;       /* 1 (default): replay each block of C iterations as one captured hipGraph */
     int32_t tile_lanes;       /* 0 = automatic; else lanes per row group of the fused SpMM kernels (1..64, power of 2) */
     int32_t tile_vec;         /* 0 = automatic; else columns per lane (1, 2 or 4) */
-    int32_t reserved[8];
+    int32_t autotune;         /* 1 (default): time tile shapes on the first block of C iterations of
+                                 a large batch and keep the fastest per kernel; 0: fixed heuristic */
+    int32_t reserved[7];
 } pdlpb_options;
 
 typedef struct pdlpb_ctx pdlpb_ctx;   /* opaque; owns all device memory of one base matrix and its batch */
@@ -189,6 +192,49 @@ int pdlpb_get_batch(pdlpb_ctx* ctx, double* X, double* Y, int32_t* status, doubl
  */
 int pdlpb_get_trace(pdlpb_ctx* ctx, int32_t j, double* x_iter, double* y_iter, double* w,
                     int32_t* restarts, int32_t* restart_log, int32_t log_cap);
+
+/*
+ * Serving: continuous batching of LPs on one resident matrix.
+ *
+ * pdlpb_serve_begin switches a context to serving with max_batch LP columns
+ * and `result_capacity` result rows.  pdlpb_submit queues LPs (one change
+ * each, as in pdlpb_set_batch) with their own tolerance and iteration budget
+ * and returns consecutive ids; it fails with PDLPB_ENOMEM when fewer than
+ * `count` result rows are free (pdlpb_release frees them).  Each
+ * pdlpb_serve_launch admits queued LPs into free columns (FIFO; the admitted
+ * LPs make their first iteration, an evaluation, at admission) and enqueues
+ * one block of C iterations for every running LP without waiting for it;
+ * pdlpb_serve_wait waits for that block and records which LPs stopped.  With
+ * the per-LP restart scope every LP follows the same iteration schedule from
+ * its own first iteration, so its result does not depend on when it was
+ * admitted or on the LPs beside it.  Launch/wait pairs of several contexts
+ * overlap on the device (each context has its own stream).
+ *
+ * pdlpb_set_base_warm keeps one warm start (x: n, y: m, primal weight w)
+ * resident on the device for PDLPB_WARM_BASE submissions.
+ */
+int pdlpb_set_base_warm(pdlpb_ctx* ctx, const double* x, const double* y, double w, int32_t mem);
+int pdlpb_serve_begin(pdlpb_ctx* ctx, int32_t result_capacity);
+int pdlpb_submit(pdlpb_ctx* ctx, int32_t count, const pdlpb_delta* deltas, int32_t warm_mode,
+                 double tol, int64_t max_iters, int32_t mem, int64_t* first_id);
+int pdlpb_serve_launch(pdlpb_ctx* ctx);
+int pdlpb_serve_wait(pdlpb_ctx* ctx, int32_t* n_running, int32_t* n_queued);
+/* Ids of LPs that stopped since the last poll (at most cap); *count receives how many. */
+int pdlpb_poll(pdlpb_ctx* ctx, int64_t* ids, int32_t cap, int32_t* count);
+/* Result of a submitted LP (as pdlpb_get); x and y are written once it has stopped. */
+int pdlpb_result(pdlpb_ctx* ctx, int64_t id, double* x, double* y, int32_t* status,
+                 double kkt[4], double* obj, int64_t* iters, int32_t mem);
+/* Free the result row of a stopped LP; its id becomes invalid. */
+int pdlpb_release(pdlpb_ctx* ctx, int64_t id);
+
+/*
+ * Tile shape of the fused product kernels for the following pdlpb_set_batch
+ * calls: `lanes` lanes (1..64, power of two) per row group, `vec` consecutive
+ * LPs (1, 2 or 4) per lane, so one group covers lanes*vec LPs of a row and a
+ * wave covers 64/lanes rows.  lanes = vec = 0 restores the automatic choice.
+ * Every shape sums each row in the same order, so results do not change.
+ */
+int pdlpb_set_tile(pdlpb_ctx* ctx, int32_t lanes, int32_t vec);
 
 /* Step size eta in use and the computed ||A||_2 (0 if eta was given). */
 int pdlpb_get_step_size(const pdlpb_ctx* ctx, double* eta, double* norm_a);

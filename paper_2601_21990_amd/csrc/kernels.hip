@@ -34,14 +34,16 @@ __device__ __forceinline__ T clampt(T v, T lo, T hi) {
 struct VarData {
     double c, lo, hi;
 };
-__device__ __forceinline__ VarData var_data(const SlotState& st, int32_t i, double c, double lo,
-                                            double hi) {
-    VarData d{c, lo, hi};
-    if (i == st.var) {
-        if (st.kind == PDLPB_SET_LO) d.lo = st.value;
-        else if (st.kind == PDLPB_SET_HI) d.hi = st.value;
+__device__ __forceinline__ VarData var_data(int32_t varkind, const double* dval, int32_t s,
+                                            int32_t i, double c, double lo, double hi) {
+    const int32_t kind = (int32_t)((uint32_t)varkind >> 28);
+    VarData d{kind == PDLPB_OBJ_UNIT ? 0.0 : c, lo, hi};
+    if (i == (varkind & VAR_MASK)) {
+        const double v = dval[s];
+        if (kind == PDLPB_SET_LO) d.lo = v;
+        else if (kind == PDLPB_SET_HI) d.hi = v;
+        else if (kind == PDLPB_OBJ_UNIT) d.c = v;
     }
-    if (st.kind == PDLPB_OBJ_UNIT) d.c = (i == st.var) ? st.value : 0.0;
     return d;
 }
 
@@ -170,13 +172,15 @@ __global__ __launch_bounds__(256) void k_primal(StepArgs<T> a) {
     const int32_t t = a.g->t0 + a.it;
 
     // operands of the epilogue, fetched before the product so their latency overlaps it
-    SlotState st[VEC];
+    SlotKey key[VEC];
+    double tau[VEC];
     T zb[VEC], z0[VEC];
 #pragma unroll
     for (int v = 0; v < VEC; ++v) {
         if (s0 + v < ncols) {
             const size_t e = (size_t)row * a.ld + s0 + v;
-            st[v] = a.st[s0 + v];
+            key[v] = a.sl.key[s0 + v];
+            tau[v] = a.sl.tau[s0 + v];
             zb[v] = a.Z[e];
             z0[v] = a.Z0[e];
         }
@@ -190,15 +194,16 @@ __global__ __launch_bounds__(256) void k_primal(StepArgs<T> a) {
     for (int v = 0; v < VEC; ++v) {
         const int32_t s = s0 + v;
         if (s >= ncols) break;
-        if (!(st[v].flags & SLOT_ACTIVE) || t > st[v].t_end) continue;
+        if (!(key[v].flags & SLOT_ACTIVE) || t > key[v].t_end) continue;
+        if (a.admit && !(key[v].flags & SLOT_NEW)) continue;
         const size_t e = (size_t)row * a.ld + s;
-        const VarData d = var_data(st[v], row, cb, lb, hb);
-        const int32_t k = t - st[v].t_anchor;
+        const VarData d = var_data(key[v].varkind, a.sl.dval, s, row, cb, lb, hb);
+        const int32_t k = t - key[v].t_anchor;
         const T x0 = z0[v];
         const T xk = (k == 0) ? x0 : T(double(k) / double(k + 1)) * zb[v] + x0 / T(k + 1);
-        const T xt = clampt<T>(xk - T(st[v].tau) * (T(d.c) + acc[v]), T(d.lo), T(d.hi));
+        const T xt = clampt<T>(xk - T(tau[v]) * (T(d.c) + acc[v]), T(d.lo), T(d.hi));
         a.Z[e] = T(2) * xt - xk;
-        if (a.eval || t == st[v].t_end) {
+        if (a.eval || t == key[v].t_end) {
             a.Zt[e] = xt;
             a.DZ[e] = xt - xk;
         }
@@ -222,13 +227,15 @@ __global__ __launch_bounds__(256) void k_dual(StepArgs<T> a) {
     if (row >= a.rows || s0 >= ncols) return;
     const int32_t t = a.g->t0 + a.it;
 
-    SlotState st[VEC];
+    SlotKey key[VEC];
+    double sig[VEC];
     T zy[VEC], z0[VEC];
 #pragma unroll
     for (int v = 0; v < VEC; ++v) {
         if (s0 + v < ncols) {
             const size_t e = (size_t)row * a.ld + s0 + v;
-            st[v] = a.st[s0 + v];
+            key[v] = a.sl.key[s0 + v];
+            sig[v] = a.sl.sigma[s0 + v];
             zy[v] = a.Z[e];
             z0[v] = a.Z0[e];
         }
@@ -242,16 +249,17 @@ __global__ __launch_bounds__(256) void k_dual(StepArgs<T> a) {
     for (int v = 0; v < VEC; ++v) {
         const int32_t s = s0 + v;
         if (s >= ncols) break;
-        if (!(st[v].flags & SLOT_ACTIVE) || t > st[v].t_end) continue;
+        if (!(key[v].flags & SLOT_ACTIVE) || t > key[v].t_end) continue;
+        if (a.admit && !(key[v].flags & SLOT_NEW)) continue;
         const size_t e = (size_t)row * a.ld + s;
-        const int32_t k = t - st[v].t_anchor;
+        const int32_t k = t - key[v].t_anchor;
         const T yk = zy[v];
         const T y0 = z0[v];
-        const T sg = T(st[v].sigma);
+        const T sg = T(sig[v]);
         const T q = yk / sg + acc[v];
         const T yt = sg * (q - clampt<T>(q, l, u));
         a.Z[e] = T(halpern_a(k)) * (T(2) * yt - yk) + y0 / T(k + 2);
-        if (a.eval || t == st[v].t_end) {
+        if (a.eval || t == key[v].t_end) {
             a.Zt[e] = yt;
             a.DZ[e] = yt - yk;
         }
@@ -282,7 +290,7 @@ __global__ __launch_bounds__(256) void k_eval(EvalArgs<T> a) {
 
     const int32_t ncols = min(a.ncols, a.g->n_cols);
     if (s < ncols) {
-        const SlotState st = a.st[s];
+        const int32_t varkind = a.sl.key[s].varkind;
         const int32_t r0 = panel * 4 * pw + wave * pw;
         const int32_t r1 = min(r0 + pw, rows);
         if (xside) {
@@ -324,7 +332,7 @@ __global__ __launch_bounds__(256) void k_eval(EvalArgs<T> a) {
                 }
                 const size_t e = (size_t)i * a.ld + s;
                 const double xt = a.Xt[e], dx = a.DX[e], x0 = a.X0[e];
-                const VarData d = var_data(st, i, a.c[i], a.xl[i], a.xu[i]);
+                const VarData d = var_data(varkind, a.sl.dval, s, i, a.c[i], a.xl[i], a.xu[i]);
                 const double rc = barrier(-d.c - g, d.lo, d.hi);        // r~ (reduced cost at y~)
                 const double rk = barrier(-d.c - (g - h), d.lo, d.hi);  // r at y^k = y~ - dy
                 const double dr = barrier(rc - rk, d.lo, d.hi);
@@ -464,14 +472,14 @@ __device__ double smoothed_weight(double w, double dx2, double dy2, const Contro
 }
 
 // restart bookkeeping of one LP: new weight and steps, cycle start, log
-__device__ void restart_slot(SlotState& st, SlotCtl& cl, int32_t* rlog, int32_t t, double eta,
-                             double wn) {
+__device__ void restart_slot(const Slots& sl, int32_t s, SlotKey& key, SlotCtl& cl, int32_t* rlog,
+                             int32_t t, double eta, double wn) {
     cl.w = wn;
-    st.tau = eta / wn;
-    st.sigma = eta * wn;
-    st.t_anchor = t + 1;
-    st.flags |= SLOT_FRESH;
-    if (cl.restarts < RESTART_LOG) rlog[cl.restarts] = t - st.t_start;
+    sl.tau[s] = eta / wn;
+    sl.sigma[s] = eta * wn;
+    key.t_anchor = t + 1;
+    key.flags |= SLOT_FRESH;
+    if (cl.restarts < RESTART_LOG) rlog[cl.restarts] = t - sl.t_start[s];
     cl.restarts += 1;
 }
 
@@ -491,7 +499,6 @@ __global__ __launch_bounds__(1024) void k_control(ControlArgs a) {
     const int32_t t = g->t0 + a.it;
     const int32_t nc = min(a.ncols, g->n_cols);
     const double eta = g->eta;
-    const double tol = g->tol;
     const double* sx = a.sums;
     const double* sy = a.sums + (size_t)NTERM * a.ld;
     int32_t my_active = 0;
@@ -503,10 +510,18 @@ __global__ __launch_bounds__(1024) void k_control(ControlArgs a) {
 
     // pass 1: stopping tests, residuals, per-LP restarts
     for (int32_t s = threadIdx.x; s < nc; s += blockDim.x) {
-        SlotState& st = a.st[s];
-        const int32_t lp = a.slot_lp[s];
+        SlotKey& st = a.sl.key[s];
+        const int32_t lp = a.sl.lp[s];
         SlotCtl& cl = a.ctl[lp];
         if (!(st.flags & SLOT_ACTIVE)) continue;
+        if (a.admit) {
+            if (!(st.flags & SLOT_NEW)) {     // already running: not evaluated in this pass
+                my_active += 1;
+                continue;
+            }
+            st.flags &= ~SLOT_NEW;
+        }
+        const double tol = cl.tol;
         const int32_t k = t - st.t_anchor;
         const bool final_now = (t >= st.t_end);
         const double dx2 = sx[0 * a.ld + s], cx = sx[1 * a.ld + s], phix = sx[2 * a.ld + s];
@@ -549,7 +564,7 @@ __global__ __launch_bounds__(1024) void k_control(ControlArgs a) {
             cl.status = status;
             cl.t_last = t_last;
             cl.k_last = t_last - st.t_anchor;
-            cl.iters = t_last - st.t_start + 1;
+            cl.iters = t_last - a.sl.t_start[s] + 1;
             st.flags = SLOT_RETIRE;
             continue;
         }
@@ -566,8 +581,8 @@ __global__ __launch_bounds__(1024) void k_control(ControlArgs a) {
             }
             st.flags &= ~SLOT_FRESH;
         } else if (a.full) {
-            if (restart_due(r, cl.r0, cl.r_prev, k, t - st.t_start, a)) {
-                restart_slot(st, cl, a.rlog + (size_t)lp * RESTART_LOG, t, eta,
+            if (restart_due(r, cl.r0, cl.r_prev, k, t - a.sl.t_start[s], a)) {
+                restart_slot(a.sl, s, st, cl, a.rlog + (size_t)lp * RESTART_LOG, t, eta,
                              smoothed_weight(w, sx[5 * a.ld + s], sy[5 * a.ld + s], a));
                 cl.r_prev = -1.0;
             } else {
@@ -609,13 +624,13 @@ __global__ __launch_bounds__(1024) void k_control(ControlArgs a) {
         __syncthreads();
         const int32_t flag = sh_flag;
         for (int32_t s = threadIdx.x; s < nc; s += blockDim.x) {
-            SlotState& st = a.st[s];
+            SlotKey& st = a.sl.key[s];
             if (!(st.flags & SLOT_ACTIVE)) continue;
-            const int32_t lp = a.slot_lp[s];
+            const int32_t lp = a.sl.lp[s];
             if (flag == 1 || (t - st.t_anchor) == 0) st.flags &= ~SLOT_FRESH;
             if (flag == 2) {
                 SlotCtl& cl = a.ctl[lp];
-                restart_slot(st, cl, a.rlog + (size_t)lp * RESTART_LOG, t, eta,
+                restart_slot(a.sl, s, st, cl, a.rlog + (size_t)lp * RESTART_LOG, t, eta,
                              smoothed_weight(cl.w, sx[5 * a.ld + s], sy[5 * a.ld + s], a));
             }
         }
@@ -632,15 +647,21 @@ __global__ __launch_bounds__(1024) void k_control(ControlArgs a) {
     const int32_t n_run = sh_n[0];
 
     // compaction plan (full evaluations): live prefix [0, n_run)
-    if (a.full) {
-        for (int32_t s = threadIdx.x; s < nc; s += blockDim.x) sh_flags[s] = a.st[s].flags;
+    if (a.admit) {
+        if (threadIdx.x == 0) {
+            g->n_retire = 0;
+            g->n_move = 0;
+            g->n_cols_next = nc;
+        }
+    } else if (a.full) {
+        for (int32_t s = threadIdx.x; s < nc; s += blockDim.x) sh_flags[s] = a.sl.key[s].flags;
         __syncthreads();
         if (threadIdx.x == 0) {
             int32_t nr = 0, nm = 0;
             int32_t mover = n_run;   // scan for running slots at or beyond n_run
             for (int32_t s = 0; s < nc; ++s) {
                 if (!(sh_flags[s] & SLOT_RETIRE)) continue;
-                const int32_t lp = a.slot_lp[s];
+                const int32_t lp = a.sl.lp[s];
                 const int32_t kl = a.ctl[lp].k_last;
                 a.retire[nr].slot = s;
                 a.retire[nr].lp = lp;
@@ -678,14 +699,14 @@ __global__ __launch_bounds__(1024) void k_control(ControlArgs a) {
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(256) void k_apply_restart(int32_t n, int32_t m, int32_t ld,
-                                                       int32_t ncols, const SlotState* st,
-                                                       const Globals* g, T* X0, const T* Xt,
-                                                       T* Y, T* Y0, const T* Yt) {
+                                                       int32_t ncols, Slots sl, const Globals* g,
+                                                       T* X0, const T* Xt, T* Y, T* Y0,
+                                                       const T* Yt) {
     const int32_t row = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (row >= n + m) return;
     const int32_t nc = min(ncols, g->n_cols);
     for (int32_t s = threadIdx.x & 63; s < nc; s += 64) {
-        if (!(st[s].flags & SLOT_FRESH)) continue;
+        if (!(sl.key[s].flags & SLOT_FRESH)) continue;
         if (row < n) {
             const size_t e = (size_t)row * ld + s;
             X0[e] = Xt[e];
@@ -713,8 +734,7 @@ struct Blocks8 {
 template <typename T>
 __global__ __launch_bounds__(256) void k_compact(int32_t n, int32_t m, int32_t ld, Blocks8<T> B,
                                                  Blocks8<T> R, const RetireEntry* retire,
-                                                 const MoveEntry* moves, SlotState* st,
-                                                 int32_t* slot_lp, Globals* g) {
+                                                 const MoveEntry* moves, Slots sl, Globals* g) {
     const int32_t nr = g->n_retire, nm = g->n_move;
     const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (row < n) {
@@ -752,8 +772,12 @@ __global__ __launch_bounds__(256) void k_compact(int32_t n, int32_t m, int32_t l
     if (blockIdx.x == 0) {
         for (int32_t q = threadIdx.x; q < nm; q += blockDim.x) {
             const MoveEntry mv = moves[q];
-            st[mv.dst] = st[mv.src];
-            slot_lp[mv.dst] = slot_lp[mv.src];
+            sl.key[mv.dst] = sl.key[mv.src];
+            sl.tau[mv.dst] = sl.tau[mv.src];
+            sl.sigma[mv.dst] = sl.sigma[mv.src];
+            sl.dval[mv.dst] = sl.dval[mv.src];
+            sl.t_start[mv.dst] = sl.t_start[mv.src];
+            sl.lp[mv.dst] = sl.lp[mv.src];
         }
         __syncthreads();
         if (threadIdx.x == 0) g->n_cols = g->n_cols_next;
@@ -764,21 +788,20 @@ __global__ __launch_bounds__(256) void k_compact(int32_t n, int32_t m, int32_t l
 // batch set-up
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ void k_init_blocks(int32_t n, int32_t m, int32_t ld, int32_t ncols,
-                              const SlotState* st, const int32_t* slot_lp, const double* xl,
-                              const double* xu, const double* xw, const double* yw, int32_t mode,
-                              T* Xbar, T* X0, T* Xt, T* DX, T* Y, T* Y0, T* Yt, T* DY) {
+__global__ void k_init_blocks(int32_t n, int32_t m, int32_t ld, int32_t ncols, Slots sl,
+                              const double* xl, const double* xu, const double* xw,
+                              const double* yw, int32_t mode, T* Xbar, T* X0, T* Xt, T* DX, T* Y,
+                              T* Y0, T* Yt, T* DY) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t nx = (int64_t)n * ld, ny = (int64_t)m * ld;
     if (idx < nx) {
         const int32_t i = (int32_t)(idx / ld), s = (int32_t)(idx % ld);
         T x = T(0);
         if (s < ncols) {
-            const SlotState q = st[s];
-            const VarData d = var_data(q, i, 0.0, xl[i], xu[i]);
+            const VarData d = var_data(sl.key[s].varkind, sl.dval, s, i, 0.0, xl[i], xu[i]);
             double w0 = 0.0;
             if (mode == PDLPB_WARM_SHARED) w0 = xw[i];
-            else if (mode == PDLPB_WARM_PER_LP) w0 = xw[(size_t)slot_lp[s] * n + i];
+            else if (mode == PDLPB_WARM_PER_LP) w0 = xw[(size_t)sl.lp[s] * n + i];
             x = T(clampd(w0, d.lo, d.hi));
         }
         Xbar[idx] = x;
@@ -791,7 +814,7 @@ __global__ void k_init_blocks(int32_t n, int32_t m, int32_t ld, int32_t ncols,
         T y = T(0);
         if (s < ncols) {
             if (mode == PDLPB_WARM_SHARED) y = T(yw[i]);
-            else if (mode == PDLPB_WARM_PER_LP) y = T(yw[(size_t)slot_lp[s] * m + i]);
+            else if (mode == PDLPB_WARM_PER_LP) y = T(yw[(size_t)sl.lp[s] * m + i]);
         }
         Y[e] = y;
         Y0[e] = y;
@@ -800,17 +823,18 @@ __global__ void k_init_blocks(int32_t n, int32_t m, int32_t ld, int32_t ncols,
     }
 }
 
-__global__ void k_begin_solve(SlotState* st, const int32_t* slot_lp, SlotCtl* ctl, int32_t ncols,
-                              int32_t max_iters, Globals* g, double tol) {
+__global__ void k_begin_solve(Slots sl, SlotCtl* ctl, int32_t ncols, int32_t max_iters, Globals* g,
+                              double tol) {
     const int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s < ncols) {
-        st[s].t_start = 0;
-        st[s].t_anchor = 0;
-        st[s].t_end = max_iters - 1;
-        SlotCtl& cl = ctl[slot_lp[s]];
+        sl.t_start[s] = 0;
+        sl.key[s].t_anchor = 0;
+        sl.key[s].t_end = max_iters - 1;
+        SlotCtl& cl = ctl[sl.lp[s]];
         cl.status = PDLPB_STATUS_RUNNING;
         cl.restarts = 0;
         cl.r_prev = -1.0;
+        cl.tol = tol;
     }
     if (s == 0) {
         g->t0 = 0;
@@ -823,6 +847,40 @@ __global__ void k_begin_solve(SlotState* st, const int32_t* slot_lp, SlotCtl* ct
         g->n_move = 0;
         g->n_cols_next = ncols;
     }
+}
+
+template <typename T>
+__global__ void k_init_columns(int32_t n, int32_t m, int32_t ld, int32_t c0, int32_t cnt, Slots sl,
+                               const double* xl, const double* xu, const double* xw,
+                               const double* yw, int32_t mode, Blocks8<T> B) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nx = (int64_t)n * cnt, ny = (int64_t)m * cnt;
+    if (idx < nx) {
+        const int32_t i = (int32_t)(idx / cnt), s = c0 + (int32_t)(idx % cnt);
+        const VarData d = var_data(sl.key[s].varkind, sl.dval, s, i, 0.0, xl[i], xu[i]);
+        const T x = T(clampd(mode == PDLPB_WARM_SHARED ? xw[i] : 0.0, d.lo, d.hi));
+        const size_t e = (size_t)i * ld + s;
+        B.b[0][e] = x;
+        B.b[1][e] = x;
+        B.b[2][e] = x;
+        B.b[3][e] = T(0);
+    } else if (idx < nx + ny) {
+        const int64_t q = idx - nx;
+        const int32_t i = (int32_t)(q / cnt), s = c0 + (int32_t)(q % cnt);
+        const T y = mode == PDLPB_WARM_SHARED ? T(yw[i]) : T(0);
+        const size_t e = (size_t)i * ld + s;
+        B.b[4][e] = y;
+        B.b[5][e] = y;
+        B.b[6][e] = y;
+        B.b[7][e] = T(0);
+    }
+}
+
+__global__ void k_admit(SlotCtl* ctl, const int32_t* rows, const SlotCtl* src, int32_t cnt,
+                        Globals* g, int32_t n_cols) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < cnt) ctl[rows[i]] = src[i];
+    if (i == 0) g->n_cols = n_cols;
 }
 
 __global__ void k_widen(const float* src, int64_t count, double* dst) {
@@ -956,49 +1014,72 @@ hipError_t launch_control(const ControlArgs& a, hipStream_t s) {
 }
 
 template <typename T>
-hipError_t launch_apply_restart(int32_t n, int32_t m, int32_t ld, int32_t ncols,
-                                const SlotState* st, const Globals* g, T* X0, const T* Xt, T* Y,
-                                T* Y0, const T* Yt, hipStream_t s) {
+hipError_t launch_apply_restart(int32_t n, int32_t m, int32_t ld, int32_t ncols, Slots sl,
+                                const Globals* g, T* X0, const T* Xt, T* Y, T* Y0, const T* Yt,
+                                hipStream_t s) {
     const int64_t rows = (int64_t)n + m;
     if (rows == 0 || ncols == 0) return hipSuccess;
     hipLaunchKernelGGL(k_apply_restart<T>, dim3((uint32_t)((rows + 3) / 4)), dim3(256), 0, s, n, m,
-                       ld, ncols, st, g, X0, Xt, Y, Y0, Yt);
+                       ld, ncols, sl, g, X0, Xt, Y, Y0, Yt);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_compact(int32_t n, int32_t m, int32_t ld, T* const* blk, T* const* res,
-                          const RetireEntry* retire, const MoveEntry* moves, SlotState* st,
-                          int32_t* slot_lp, Globals* g, hipStream_t s) {
+                          const RetireEntry* retire, const MoveEntry* moves, Slots sl, Globals* g,
+                          hipStream_t s) {
     Blocks8<T> B{}, R{};
     for (int b = 0; b < 8; ++b) B.b[b] = blk[b];
     for (int b = 0; b < 4; ++b) R.b[b] = res[b];
     const int64_t rows = (int64_t)n + m;
     const uint32_t blocks = (uint32_t)((rows + 255) / 256);
     hipLaunchKernelGGL(k_compact<T>, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, s, n, m, ld, B, R,
-                       retire, moves, st, slot_lp, g);
+                       retire, moves, sl, g);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_init_blocks(int32_t n, int32_t m, int32_t ld, int32_t ncols, const SlotState* st,
-                              const int32_t* slot_lp, const double* xl, const double* xu,
-                              const double* xw, const double* yw, int32_t mode, T* Xbar, T* X0,
-                              T* Xt, T* DX, T* Y, T* Y0, T* Yt, T* DY, hipStream_t s) {
+hipError_t launch_init_blocks(int32_t n, int32_t m, int32_t ld, int32_t ncols, Slots sl,
+                              const double* xl, const double* xu, const double* xw,
+                              const double* yw, int32_t mode, T* Xbar, T* X0, T* Xt, T* DX, T* Y,
+                              T* Y0, T* Yt, T* DY, hipStream_t s) {
     const int64_t total = (int64_t)(n + m) * ld;
     if (total == 0) return hipSuccess;
     const int64_t blocks = (total + 255) / 256;
     if (blocks > 0x7fffffff) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_init_blocks<T>, dim3((uint32_t)blocks), dim3(256), 0, s, n, m, ld, ncols,
-                       st, slot_lp, xl, xu, xw, yw, mode, Xbar, X0, Xt, DX, Y, Y0, Yt, DY);
+                       sl, xl, xu, xw, yw, mode, Xbar, X0, Xt, DX, Y, Y0, Yt, DY);
     return hipGetLastError();
 }
 
-hipError_t launch_begin_solve(SlotState* st, const int32_t* slot_lp, SlotCtl* ctl, int32_t ncols,
-                              int32_t max_iters, Globals* g, double tol, hipStream_t s) {
+hipError_t launch_begin_solve(Slots sl, SlotCtl* ctl, int32_t ncols, int32_t max_iters, Globals* g,
+                              double tol, hipStream_t s) {
     const int32_t blocks = (ncols + 255) / 256;
-    hipLaunchKernelGGL(k_begin_solve, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, s, st, slot_lp,
-                       ctl, ncols, max_iters, g, tol);
+    hipLaunchKernelGGL(k_begin_solve, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, s, sl, ctl,
+                       ncols, max_iters, g, tol);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_init_columns(int32_t n, int32_t m, int32_t ld, int32_t c0, int32_t cnt, Slots sl,
+                               const double* xl, const double* xu, const double* xw,
+                               const double* yw, int32_t mode, T* const* blk, hipStream_t s) {
+    Blocks8<T> B{};
+    for (int b = 0; b < 8; ++b) B.b[b] = blk[b];
+    const int64_t total = ((int64_t)n + m) * cnt;
+    if (total == 0) return hipSuccess;
+    const int64_t blocks = (total + 255) / 256;
+    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_init_columns<T>, dim3((uint32_t)blocks), dim3(256), 0, s, n, m, ld, c0, cnt,
+                       sl, xl, xu, xw, yw, mode, B);
+    return hipGetLastError();
+}
+
+hipError_t launch_admit(SlotCtl* ctl, const int32_t* rows, const SlotCtl* src, int32_t cnt,
+                        Globals* g, int32_t n_cols, hipStream_t s) {
+    const int32_t blocks = (cnt + 255) / 256;
+    hipLaunchKernelGGL(k_admit, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, s, ctl, rows, src, cnt,
+                       g, n_cols);
     return hipGetLastError();
 }
 
@@ -1046,28 +1127,33 @@ template hipError_t launch_dual<double>(const StepArgs<double>&, int, int, hipSt
 template hipError_t launch_dual<float>(const StepArgs<float>&, int, int, hipStream_t);
 template hipError_t launch_eval<double>(const EvalArgs<double>&, hipStream_t);
 template hipError_t launch_eval<float>(const EvalArgs<float>&, hipStream_t);
-template hipError_t launch_apply_restart<double>(int32_t, int32_t, int32_t, int32_t,
-                                                 const SlotState*, const Globals*, double*,
-                                                 const double*, double*, double*, const double*,
-                                                 hipStream_t);
-template hipError_t launch_apply_restart<float>(int32_t, int32_t, int32_t, int32_t, const SlotState*,
+template hipError_t launch_apply_restart<double>(int32_t, int32_t, int32_t, int32_t, Slots,
+                                                 const Globals*, double*, const double*, double*,
+                                                 double*, const double*, hipStream_t);
+template hipError_t launch_apply_restart<float>(int32_t, int32_t, int32_t, int32_t, Slots,
                                                 const Globals*, float*, const float*, float*,
                                                 float*, const float*, hipStream_t);
 template hipError_t launch_compact<double>(int32_t, int32_t, int32_t, double* const*,
                                            double* const*, const RetireEntry*, const MoveEntry*,
-                                           SlotState*, int32_t*, Globals*, hipStream_t);
+                                           Slots, Globals*, hipStream_t);
 template hipError_t launch_compact<float>(int32_t, int32_t, int32_t, float* const*, float* const*,
-                                          const RetireEntry*, const MoveEntry*, SlotState*,
-                                          int32_t*, Globals*, hipStream_t);
-template hipError_t launch_init_blocks<double>(int32_t, int32_t, int32_t, int32_t, const SlotState*,
-                                               const int32_t*, const double*, const double*,
-                                               const double*, const double*, int32_t, double*,
-                                               double*, double*, double*, double*, double*, double*,
-                                               double*, hipStream_t);
-template hipError_t launch_init_blocks<float>(int32_t, int32_t, int32_t, int32_t, const SlotState*,
-                                              const int32_t*, const double*, const double*,
-                                              const double*, const double*, int32_t, float*, float*,
-                                              float*, float*, float*, float*, float*, float*,
-                                              hipStream_t);
+                                          const RetireEntry*, const MoveEntry*, Slots, Globals*,
+                                          hipStream_t);
+template hipError_t launch_init_columns<double>(int32_t, int32_t, int32_t, int32_t, int32_t, Slots,
+                                                const double*, const double*, const double*,
+                                                const double*, int32_t, double* const*,
+                                                hipStream_t);
+template hipError_t launch_init_columns<float>(int32_t, int32_t, int32_t, int32_t, int32_t, Slots,
+                                               const double*, const double*, const double*,
+                                               const double*, int32_t, float* const*, hipStream_t);
+template hipError_t launch_init_blocks<double>(int32_t, int32_t, int32_t, int32_t, Slots,
+                                               const double*, const double*, const double*,
+                                               const double*, int32_t, double*, double*, double*,
+                                               double*, double*, double*, double*, double*,
+                                               hipStream_t);
+template hipError_t launch_init_blocks<float>(int32_t, int32_t, int32_t, int32_t, Slots,
+                                              const double*, const double*, const double*,
+                                              const double*, int32_t, float*, float*, float*,
+                                              float*, float*, float*, float*, float*, hipStream_t);
 
 }  // namespace pdlpb

@@ -9,8 +9,10 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <deque>
 #include <new>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "pdlpb.h"
@@ -39,6 +41,11 @@ int32_t eval_rows_per_wave(int32_t rows) {
 
 }  // namespace
 
+struct Tile {
+    int lanes = 64;     // lanes per row group
+    int vec = 1;        // consecutive LPs per lane
+};
+
 struct pdlpb_ctx {
     std::string err = "no error";
     int device = 0;
@@ -64,15 +71,18 @@ struct pdlpb_ctx {
     int32_t B = 0, ld = 0;
     int32_t n_run0 = 0;             // LPs placed in slots by set_batch (the others never run)
     int32_t live = 0;               // live column count the current launches are shaped for
-    int lanes = 64, vec = 1, wpb = 4;
+    Tile tp, td;                    // tile shapes of the primal and dual product kernels
+    int wpb = 4;
     int vec_ld = 1;                 // vector width ld is padded for
+    // tile shapes chosen by timing, per (live column shape, ld)
+    std::vector<std::pair<int64_t, std::pair<Tile, Tile>>> tuned;
     size_t cap_block_bytes = 0;     // bytes of each of the 8 dense blocks
     void* blk[8] = {};              // Xbar, X0, Xt, DX, Y, Y0, Yt, DY (row-major, stride ld)
     size_t cap_res_x = 0, cap_res_y = 0;
     void* res[4] = {};              // Rx, Rxi (B x n), Ry, Ryi (B x m): LP-major results
-    int32_t cap_slots = 0;
-    SlotState* st = nullptr;        // by slot
-    int32_t* slot_lp = nullptr;     // LP held by each slot
+    int32_t cap_slots = 0;          // slot (column) capacity
+    int32_t cap_lps = 0;            // LP rows of ctl / rlog
+    Slots sl{};                     // per-slot arrays (key, tau, sigma, dval, t_start, lp)
     SlotCtl* ctl = nullptr;         // by LP
     int32_t* rlog = nullptr;        // by LP
     RetireEntry* retire = nullptr;
@@ -94,6 +104,37 @@ struct pdlpb_ctx {
 
     // captured blocks of C iterations, one per launch shape (live column bound)
     std::vector<std::pair<int32_t, hipGraphExec_t>> graphs;
+
+    // serving (continuous batching)
+    struct Pending {
+        int32_t row;          // result row (LP index of the kernels)
+        int32_t varkind;
+        double dval, w, tol;
+        int32_t max_iters;
+        int32_t warm;         // PDLPB_WARM_NONE or PDLPB_WARM_BASE
+    };
+    bool serving = false;
+    int32_t res_cap = 0;
+    int32_t n_cols = 0;                         // live columns after the last wait
+    int32_t t0 = 0;                             // global iteration index of the next block's base
+    bool launched = false;
+    std::vector<int32_t> free_rows;
+    std::vector<int64_t> row_id;                // id held by each result row (-1 free)
+    std::unordered_map<int64_t, int32_t> id_row;
+    std::deque<Pending> queue;
+    std::deque<int64_t> completed;
+    int64_t next_id = 0;
+    double* base_x = nullptr;                   // resident warm start (n + m doubles)
+    double base_w = 0.0;
+    bool have_base = false;
+    int32_t* adm_rows = nullptr;                // admission staging (capacity columns)
+    SlotCtl* adm_ctl = nullptr;
+    std::vector<int32_t> h_adm_rows;
+    std::vector<SlotCtl> h_adm_ctl;
+    std::vector<SlotKey> h_adm_key;
+    std::vector<double> h_adm_tau, h_adm_sigma, h_adm_dval;
+    std::vector<int32_t> h_adm_tstart, h_adm_lp;
+    std::vector<RetireEntry> h_retire;
 
     // kernel timing
     bool timing = false;
@@ -153,7 +194,9 @@ void free_all(pdlpb_ctx* x) {
     for (auto e : x->ev) (void)hipEventDestroy(e);
     x->ev.clear();
     void* ptrs[] = {x->a_rp, x->a_ci, x->t_rp, x->t_ci, x->a_v64, x->t_v64, x->a_v32, x->t_v32,
-                    x->c, x->xl, x->xu, x->rl, x->ru, x->st, x->slot_lp, x->ctl, x->rlog,
+                    x->c, x->xl, x->xu, x->rl, x->ru, x->sl.key, x->sl.tau, x->sl.sigma,
+                    x->sl.dval, x->sl.t_start, x->sl.lp, x->ctl, x->rlog, x->base_x, x->adm_rows,
+                    x->adm_ctl,
                     x->retire, x->moves, x->g, x->part, x->stage, x->pow_buf};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
@@ -238,7 +281,7 @@ int compute_opnorm(pdlpb_ctx* x, double* out) {
 
 // default tile for `ncols` live columns: each row group of `lanes` lanes covers
 // lanes*vec consecutive slots; vec never exceeds the width ld was padded for
-void choose_tile(pdlpb_ctx* x, int32_t ncols) {
+Tile heuristic_tile(const pdlpb_ctx* x, int32_t ncols) {
     int vec = 1;
     if (x->fp32) vec = ncols >= 256 ? 4 : (ncols >= 128 ? 2 : 1);
     else vec = ncols >= 128 ? 2 : 1;
@@ -247,9 +290,39 @@ void choose_tile(pdlpb_ctx* x, int32_t ncols) {
     int lanes = next_pow2((ncols + vec - 1) / vec);
     if (lanes > 64) lanes = 64;
     if (x->opt.tile_lanes > 0) lanes = x->opt.tile_lanes;
-    x->vec = vec;
-    x->lanes = lanes;
+    Tile t;
+    t.lanes = lanes;
+    t.vec = vec;
+    return t;
+}
+
+void choose_tile(pdlpb_ctx* x, int32_t ncols) {
+    x->tp = x->td = heuristic_tile(x, ncols);
     x->wpb = 4;
+}
+
+// compulsory bytes of one primal launch at `ncols` columns (the size at which
+// timing tile shapes on the live solve pays for itself)
+double launch_bytes(const pdlpb_ctx* x, int32_t ncols) {
+    const double s = x->fp32 ? 4.0 : 8.0;
+    return (double)x->nnz * (s + 4) + s * ncols * ((double)x->m + 3.0 * x->n);
+}
+
+// tile shapes worth timing: widths 16..256 (not beyond the next power of two
+// above the live columns), every vector width the padding allows
+std::vector<Tile> tile_candidates(const pdlpb_ctx* x, int32_t ncols) {
+    std::vector<Tile> out;
+    const int32_t wmax = std::min<int32_t>(256, next_pow2(ncols));
+    for (int vec = 1; vec <= x->vec_ld; vec *= 2)
+        for (int32_t w = 16; w <= wmax; w *= 2) {
+            const int lanes = w / vec;
+            if (lanes < 1 || lanes > 64) continue;
+            Tile t;
+            t.lanes = lanes;
+            t.vec = vec;
+            out.push_back(t);
+        }
+    return out;
 }
 
 // launch shape for a live column count: the next power of two (at most B), so
@@ -260,7 +333,7 @@ int32_t shape_cols(const pdlpb_ctx* x, int32_t live) {
 }
 
 template <typename T>
-StepArgs<T> step_args(pdlpb_ctx* x, bool primal, int32_t it, int32_t eval) {
+StepArgs<T> step_args(pdlpb_ctx* x, bool primal, int32_t it, int32_t eval, int32_t admit = 0) {
     StepArgs<T> a{};
     T* const* b = reinterpret_cast<T* const*>(x->blk);
     const T* av = nullptr;
@@ -282,10 +355,11 @@ StepArgs<T> step_args(pdlpb_ctx* x, bool primal, int32_t it, int32_t eval) {
         a.Z = b[4]; a.Z0 = b[5]; a.Zt = b[6]; a.DZ = b[7];
         a.c = nullptr; a.lo = x->rl; a.hi = x->ru;
     }
-    a.st = x->st;
+    a.sl = x->sl;
     a.g = x->g;
     a.it = it;
     a.eval = eval;
+    a.admit = admit;
     return a;
 }
 
@@ -306,7 +380,7 @@ EvalArgs<T> eval_args(pdlpb_ctx* x) {
     a.Xt = b[2]; a.DX = b[3]; a.X0 = b[1];
     a.Yt = b[6]; a.DY = b[7]; a.Y0 = b[5];
     a.c = x->c; a.xl = x->xl; a.xu = x->xu; a.rl = x->rl; a.ru = x->ru;
-    a.st = x->st;
+    a.sl = x->sl;
     a.g = x->g;
     a.pw_x = x->pw_x; a.pw_y = x->pw_y; a.npx = x->npx; a.npy = x->npy;
     a.part_x = x->part;
@@ -314,13 +388,14 @@ EvalArgs<T> eval_args(pdlpb_ctx* x) {
     return a;
 }
 
-ControlArgs control_args(pdlpb_ctx* x, int32_t it, int32_t full, int32_t advance) {
+ControlArgs control_args(pdlpb_ctx* x, int32_t it, int32_t full, int32_t advance,
+                         int32_t admit = 0) {
     ControlArgs a{};
     a.ncols = x->live; a.ld = x->ld; a.npx = x->npx; a.npy = x->npy;
     a.part_x = x->part;
     a.part_y = x->part + (size_t)x->npx * NTERM * x->ld;
     a.sums = x->part + (size_t)(x->npx + x->npy) * NTERM * x->ld;
-    a.st = x->st; a.slot_lp = x->slot_lp; a.ctl = x->ctl; a.rlog = x->rlog;
+    a.sl = x->sl; a.ctl = x->ctl; a.rlog = x->rlog;
     a.retire = x->retire; a.moves = x->moves; a.g = x->g;
     a.it = it; a.full = full; a.advance = advance; a.block = x->opt.eval_every;
     a.batch_avg = x->opt.restart_scope == PDLPB_RESTART_BATCH_AVG;
@@ -328,6 +403,7 @@ ControlArgs control_args(pdlpb_ctx* x, int32_t it, int32_t full, int32_t advance
     a.beta_s = x->opt.beta_sufficient; a.beta_n = x->opt.beta_necessary;
     a.beta_a = x->opt.beta_artificial; a.theta = x->opt.theta; a.cross_sign = x->opt.cross_sign;
     a.infeas_tol = x->opt.infeas_tol;   // < 0: the stopping tolerance (resolved on the device)
+    a.admit = admit;
     return a;
 }
 
@@ -346,24 +422,24 @@ int timed_begin(pdlpb_ctx* x, int kind, std::vector<std::pair<int, int>>& rec) {
 
 template <typename T>
 int enqueue_iteration(pdlpb_ctx* x, int32_t it, int32_t eval,
-                      std::vector<std::pair<int, int>>* rec) {
-    StepArgs<T> p = step_args<T>(x, true, it, eval);
-    StepArgs<T> d = step_args<T>(x, false, it, eval);
+                      std::vector<std::pair<int, int>>* rec, int32_t admit = 0) {
+    StepArgs<T> p = step_args<T>(x, true, it, eval, admit);
+    StepArgs<T> d = step_args<T>(x, false, it, eval, admit);
     int idx = -1;
     if (rec) idx = timed_begin(x, 0, *rec);
-    HIP_TRY(x, launch_primal<T>(p, x->lanes, x->vec, x->stream));
+    HIP_TRY(x, launch_primal<T>(p, x->tp.lanes, x->tp.vec, x->stream));
     if (rec && idx >= 0) (void)hipEventRecord(x->ev[2 * idx + 1], x->stream);
     if (rec) idx = timed_begin(x, 1, *rec);
-    HIP_TRY(x, launch_dual<T>(d, x->lanes, x->vec, x->stream));
+    HIP_TRY(x, launch_dual<T>(d, x->td.lanes, x->td.vec, x->stream));
     if (rec && idx >= 0) (void)hipEventRecord(x->ev[2 * idx + 1], x->stream);
     return PDLPB_OK;
 }
 
 template <typename T>
 int enqueue_evaluation(pdlpb_ctx* x, int32_t it, int32_t full, int32_t advance,
-                       std::vector<std::pair<int, int>>* rec) {
+                       std::vector<std::pair<int, int>>* rec, int32_t admit = 0) {
     EvalArgs<T> e = eval_args<T>(x);
-    ControlArgs c = control_args(x, it, full, advance);
+    ControlArgs c = control_args(x, it, full, advance, admit);
     int idx = -1;
     if (rec) idx = timed_begin(x, 2, *rec);
     HIP_TRY(x, launch_eval<T>(e, x->stream));
@@ -374,10 +450,10 @@ int enqueue_evaluation(pdlpb_ctx* x, int32_t it, int32_t full, int32_t advance,
     if (full) {
         T* const* b = reinterpret_cast<T* const*>(x->blk);
         T* const* r = reinterpret_cast<T* const*>(x->res);
-        HIP_TRY(x, launch_apply_restart<T>(x->n, x->m, x->ld, x->live, x->st, x->g, b[1], b[2],
+        HIP_TRY(x, launch_apply_restart<T>(x->n, x->m, x->ld, x->live, x->sl, x->g, b[1], b[2],
                                            b[4], b[5], b[6], x->stream));
-        HIP_TRY(x, launch_compact<T>(x->n, x->m, x->ld, b, r, x->retire, x->moves, x->st,
-                                     x->slot_lp, x->g, x->stream));
+        HIP_TRY(x, launch_compact<T>(x->n, x->m, x->ld, b, r, x->retire, x->moves, x->sl, x->g,
+                                     x->stream));
     }
     if (rec && idx >= 0) (void)hipEventRecord(x->ev[2 * idx + 1], x->stream);
     return PDLPB_OK;
@@ -399,6 +475,67 @@ int enqueue_epoch(pdlpb_ctx* x, std::vector<std::pair<int, int>>* rec) {
     return PDLPB_OK;
 }
 
+// One block of C iterations that also times tile shapes: the iterations
+// between the two evaluations cycle through the candidates, every product
+// launch bracketed by events; the fastest shape is kept per kernel.  All
+// shapes produce the same bits, so the solve itself is unaffected.
+template <typename T>
+int tune_epoch(pdlpb_ctx* x) {
+    const std::vector<Tile> cand = tile_candidates(x, x->live);
+    const int32_t C = x->opt.eval_every;
+    const int nc = (int)cand.size();
+    std::vector<double> ms(2 * nc, 0.0);
+    std::vector<int> cnt(2 * nc, 0);
+    std::vector<std::pair<int, int>> rec;   // (candidate * 2 + kernel, event pair)
+    const Tile keep_p = x->tp, keep_d = x->td;
+    for (int32_t it = 1; it <= C; ++it) {
+        const bool ev = (it == 1 || it == C);
+        int c = -1;
+        if (!ev && nc > 0) {
+            c = (it - 2) % nc;
+            x->tp = x->td = cand[c];
+        } else {
+            x->tp = keep_p;
+            x->td = keep_d;
+        }
+        StepArgs<T> p = step_args<T>(x, true, it, ev ? 1 : 0);
+        StepArgs<T> d = step_args<T>(x, false, it, ev ? 1 : 0);
+        for (int kern = 0; kern < 2; ++kern) {
+            int idx = -1;
+            if (c >= 0) idx = timed_begin(x, c * 2 + kern, rec);
+            if (kern == 0) HIP_TRY(x, launch_primal<T>(p, x->tp.lanes, x->tp.vec, x->stream));
+            else HIP_TRY(x, launch_dual<T>(d, x->td.lanes, x->td.vec, x->stream));
+            if (idx >= 0) (void)hipEventRecord(x->ev[2 * idx + 1], x->stream);
+        }
+        int rc = PDLPB_OK;
+        if (it == C) rc = enqueue_evaluation<T>(x, it, 1, 1, nullptr);
+        else if (it == 1) rc = enqueue_evaluation<T>(x, it, 0, 0, nullptr);
+        if (rc) return rc;
+    }
+    HIP_TRY(x, hipStreamSynchronize(x->stream));
+    // the first sample of each candidate warms caches; average the rest
+    std::vector<int> seen(2 * nc, 0);
+    for (auto& r : rec) {
+        float e = 0.f;
+        if (hipEventElapsedTime(&e, x->ev[2 * r.second], x->ev[2 * r.second + 1]) != hipSuccess)
+            continue;
+        if (seen[r.first]++ == 0) continue;
+        ms[r.first] += e;
+        cnt[r.first] += 1;
+    }
+    int bp = -1, bd = -1;
+    for (int c = 0; c < nc; ++c) {
+        if (cnt[2 * c] && (bp < 0 || ms[2 * c] / cnt[2 * c] < ms[2 * bp] / cnt[2 * bp])) bp = c;
+        if (cnt[2 * c + 1] &&
+            (bd < 0 || ms[2 * c + 1] / cnt[2 * c + 1] < ms[2 * bd + 1] / cnt[2 * bd + 1]))
+            bd = c;
+    }
+    x->tp = bp >= 0 ? cand[bp] : keep_p;
+    x->td = bd >= 0 ? cand[bd] : keep_d;
+    x->tuned.push_back({(int64_t)x->live | ((int64_t)x->ld << 32), {x->tp, x->td}});
+    return PDLPB_OK;
+}
+
 // read the running count and the live column count back to the host
 int read_counts(pdlpb_ctx* x, int32_t* n_active, int32_t* n_cols) {
     HIP_TRY(x, hipMemcpyAsync(x->h_pinned, x->g, 4 * sizeof(int32_t), hipMemcpyDeviceToHost,
@@ -411,10 +548,9 @@ int read_counts(pdlpb_ctx* x, int32_t* n_active, int32_t* n_cols) {
 
 template <typename T>
 int run_solve(pdlpb_ctx* x, double tol, int32_t max_iters) {
-    x->live = x->n_run0;
-    choose_tile(x, shape_cols(x, x->live));
-    x->live = shape_cols(x, x->live);
-    HIP_TRY(x, launch_begin_solve(x->st, x->slot_lp, x->ctl, x->n_run0, max_iters, x->g, tol,
+    x->live = shape_cols(x, x->n_run0);
+    choose_tile(x, x->live);
+    HIP_TRY(x, launch_begin_solve(x->sl, x->ctl, x->n_run0, max_iters, x->g, tol,
                                   x->stream));
     std::vector<std::pair<int, int>> rec;
     std::vector<std::pair<int, int>>* prec = x->timing ? &rec : nullptr;
@@ -443,11 +579,27 @@ int run_solve(pdlpb_ctx* x, double tol, int32_t max_iters) {
         if (ep > max_epochs) return x->fail(PDLPB_EDEVICE, "solve did not terminate");
         // shape the launches for the live columns (compaction shrinks them)
         const int32_t shape = shape_cols(x, n_cols);
-        if (shape != x->live) {
+        bool tune_now = false;
+        if (shape != x->live || ep == 0) {
             x->live = shape;
             choose_tile(x, shape);
+            const bool fixed = x->opt.tile_lanes > 0 || x->opt.tile_vec > 0;
+            if (x->opt.autotune && !fixed && launch_bytes(x, shape) >= 32e6) {
+                const int64_t key = (int64_t)shape | ((int64_t)x->ld << 32);
+                bool hit = false;
+                for (auto& e : x->tuned)
+                    if (e.first == key) {
+                        x->tp = e.second.first;
+                        x->td = e.second.second;
+                        hit = true;
+                    }
+                tune_now = !hit && !x->timing;
+            }
         }
-        if (use_graphs) {
+        if (tune_now) {
+            rc = tune_epoch<T>(x);
+            if (rc) return rc;
+        } else if (use_graphs) {
             hipGraphExec_t exec = nullptr;
             for (auto& gr : x->graphs)
                 if (gr.first == x->live) exec = gr.second;
@@ -524,6 +676,103 @@ int copy_results(pdlpb_ctx* x, int q, int32_t first, int32_t count, double* dst,
     return PDLPB_OK;
 }
 
+// Status of an LP before it iterates: its change may be malformed or cross its bounds.
+int32_t lp_status(const pdlpb_ctx* x, const pdlpb_delta& q) {
+    if (q.kind == PDLPB_BASE) return PDLPB_STATUS_RUNNING;
+    const bool bad_value = std::isnan(q.value) || (q.kind == PDLPB_SET_LO && q.value == INFINITY) ||
+                           (q.kind == PDLPB_SET_HI && q.value == -INFINITY) ||
+                           (q.kind == PDLPB_OBJ_UNIT && !std::isfinite(q.value));
+    if (bad_value) return PDLPB_STATUS_INVALID_INPUT;
+    if (q.kind == PDLPB_SET_LO && q.value > x->h_xu[q.var]) return PDLPB_STATUS_INFEASIBLE_BOUNDS;
+    if (q.kind == PDLPB_SET_HI && q.value < x->h_xl[q.var]) return PDLPB_STATUS_INFEASIBLE_BOUNDS;
+    return PDLPB_STATUS_RUNNING;
+}
+
+// Initial primal weight without a warm start: ||c_j|| / ||b|| when both exceed 1e-10, else 1.
+double default_weight(const pdlpb_ctx* x, const pdlpb_delta& q) {
+    const double cn = q.kind == PDLPB_OBJ_UNIT ? std::fabs(q.value) : x->norm_c;
+    return (cn > 1e-10 && x->norm_b > 1e-10) ? cn / x->norm_b : 1.0;
+}
+
+// Device storage for `cols` LP columns and `lps` LP result rows (grows, reused
+// for smaller requests).  Sets vec_ld and returns the row stride ld.
+int ensure_storage(pdlpb_ctx* x, int32_t cols, int32_t lps, int32_t* ld_out) {
+    const int32_t n = x->n, m = x->m;
+    x->vec_ld = 4;
+    const Tile t0 = heuristic_tile(x, cols);
+    // pad for 4-wide vectors when the batch is large enough to be tuned
+    x->vec_ld = (x->opt.autotune && x->opt.tile_vec == 0 && launch_bytes(x, cols) >= 32e6)
+                    ? 4 : t0.vec;
+    const int32_t ld = ((cols + x->vec_ld - 1) / x->vec_ld) * x->vec_ld;
+    const size_t esz = x->fp32 ? sizeof(float) : sizeof(double);
+    const size_t rows_max = (size_t)std::max(n, m);
+    const size_t block_bytes = rows_max * (size_t)ld * esz;
+    if (block_bytes > x->cap_block_bytes) {
+        x->drop_graph();
+        for (void*& p : x->blk) x->release(p, x->cap_block_bytes);
+        x->cap_block_bytes = 0;
+        for (void*& p : x->blk) HIP_TRY(x, x->alloc(&p, block_bytes));
+        x->cap_block_bytes = block_bytes;
+    }
+    const size_t rx_bytes = (size_t)lps * n * esz, ry_bytes = (size_t)lps * m * esz;
+    if (rx_bytes > x->cap_res_x || ry_bytes > x->cap_res_y) {
+        x->drop_graph();
+        x->release(x->res[0], x->cap_res_x);
+        x->release(x->res[1], x->cap_res_x);
+        x->release(x->res[2], x->cap_res_y);
+        x->release(x->res[3], x->cap_res_y);
+        x->cap_res_x = x->cap_res_y = 0;
+        for (int q = 0; q < 2; ++q) HIP_TRY(x, x->alloc(&x->res[q], rx_bytes));
+        for (int q = 2; q < 4; ++q) HIP_TRY(x, x->alloc(&x->res[q], ry_bytes));
+        x->cap_res_x = rx_bytes;
+        x->cap_res_y = ry_bytes;
+    }
+    if (cols > x->cap_slots) {
+        x->drop_graph();
+        x->release(x->sl.key, sizeof(SlotKey) * x->cap_slots);
+        x->release(x->sl.tau, sizeof(double) * x->cap_slots);
+        x->release(x->sl.sigma, sizeof(double) * x->cap_slots);
+        x->release(x->sl.dval, sizeof(double) * x->cap_slots);
+        x->release(x->sl.t_start, sizeof(int32_t) * x->cap_slots);
+        x->release(x->sl.lp, sizeof(int32_t) * x->cap_slots);
+        x->release(x->retire, sizeof(RetireEntry) * x->cap_slots);
+        x->release(x->moves, sizeof(MoveEntry) * x->cap_slots);
+        x->release(x->adm_rows, sizeof(int32_t) * x->cap_slots);
+        x->release(x->adm_ctl, sizeof(SlotCtl) * x->cap_slots);
+        x->cap_slots = 0;
+        HIP_TRY(x, x->alloc(&x->sl.key, sizeof(SlotKey) * cols));
+        HIP_TRY(x, x->alloc(&x->sl.tau, sizeof(double) * cols));
+        HIP_TRY(x, x->alloc(&x->sl.sigma, sizeof(double) * cols));
+        HIP_TRY(x, x->alloc(&x->sl.dval, sizeof(double) * cols));
+        HIP_TRY(x, x->alloc(&x->sl.t_start, sizeof(int32_t) * cols));
+        HIP_TRY(x, x->alloc(&x->sl.lp, sizeof(int32_t) * cols));
+        HIP_TRY(x, x->alloc(&x->retire, sizeof(RetireEntry) * cols));
+        HIP_TRY(x, x->alloc(&x->moves, sizeof(MoveEntry) * cols));
+        HIP_TRY(x, x->alloc(&x->adm_rows, sizeof(int32_t) * cols));
+        HIP_TRY(x, x->alloc(&x->adm_ctl, sizeof(SlotCtl) * cols));
+        x->cap_slots = cols;
+    }
+    if (lps > x->cap_lps) {
+        x->drop_graph();
+        x->release(x->ctl, sizeof(SlotCtl) * x->cap_lps);
+        x->release(x->rlog, sizeof(int32_t) * RESTART_LOG * x->cap_lps);
+        x->cap_lps = 0;
+        HIP_TRY(x, x->alloc(&x->ctl, sizeof(SlotCtl) * lps));
+        HIP_TRY(x, x->alloc(&x->rlog, sizeof(int32_t) * RESTART_LOG * lps));
+        x->cap_lps = lps;
+    }
+    const size_t part_need = (size_t)(x->npx + x->npy + 2) * NTERM * ld;
+    if (part_need > x->cap_part) {
+        x->drop_graph();
+        x->release(x->part, x->cap_part * sizeof(double));
+        x->cap_part = 0;
+        HIP_TRY(x, x->alloc(&x->part, part_need * sizeof(double)));
+        x->cap_part = part_need;
+    }
+    *ld_out = ld;
+    return PDLPB_OK;
+}
+
 bool finite_all(const double* p, int64_t len) {
     for (int64_t i = 0; i < len; ++i)
         if (!std::isfinite(p[i])) return false;
@@ -556,6 +805,7 @@ void pdlpb_default_options(pdlpb_options* o) {
     o->use_graphs = 1;
     o->tile_lanes = 0;
     o->tile_vec = 0;
+    o->autotune = 1;
 }
 
 int pdlpb_create(pdlpb_ctx** out, int32_t m, int32_t n, int64_t nnz, const int64_t* row_ptr,
@@ -575,6 +825,7 @@ int pdlpb_create(pdlpb_ctx** out, int32_t m, int32_t n, int64_t nnz, const int64
         o = *opt;
     }
     if (m < 0 || n < 1) return bad("need m >= 0 and n >= 1");
+    if (n >= VAR_NONE) return bad("n must be below 2^28 - 1");
     if (nnz < 0 || nnz >= ((int64_t)1 << 31)) return bad("nnz must be in [0, 2^31)");
     if (!row_ptr || !c || !l || !u || (m > 0 && (!b || !sense)) ||
         (nnz > 0 && (!col_idx || !val)))
@@ -652,7 +903,7 @@ int pdlpb_create(pdlpb_ctx** out, int32_t m, int32_t n, int64_t nnz, const int64
         if (e != hipSuccess) return dev_fail(e, "hipStreamCreate");
         x->own_stream = true;
     }
-    e = hipHostMalloc((void**)&x->h_pinned, sizeof(int32_t) * 4, hipHostMallocDefault);
+    e = hipHostMalloc((void**)&x->h_pinned, sizeof(int32_t) * 16, hipHostMallocDefault);
     if (e != hipSuccess) return dev_fail(e, "hipHostMalloc");
 
     // A' in CSR (= A in CSC): counting sort by column keeps row order inside each column
@@ -751,115 +1002,52 @@ int pdlpb_set_batch(pdlpb_ctx* x, int32_t B, const pdlpb_delta* deltas, const do
         std::memcpy(d.data(), deltas, sizeof(pdlpb_delta) * B);
         if (w_warm) std::memcpy(w0.data(), w_warm, sizeof(double) * B);
     }
-    std::vector<SlotState> hs;
-    std::vector<int32_t> slot_lp;
+    std::vector<SlotKey> h_key;
+    std::vector<double> h_tau, h_sigma, h_dval;
+    std::vector<int32_t> h_lp;
     std::vector<SlotCtl> hc(B);
-    hs.reserve(B);
-    slot_lp.reserve(B);
     for (int32_t j = 0; j < B; ++j) {
         const pdlpb_delta& q = d[j];
         if (q.kind < PDLPB_BASE || q.kind > PDLPB_OBJ_UNIT)
             return x->fail(PDLPB_EINVAL, "delta kind out of range at LP " + std::to_string(j));
         if (q.kind != PDLPB_BASE && (q.var < 0 || q.var >= n))
             return x->fail(PDLPB_EINVAL, "delta var out of range at LP " + std::to_string(j));
-        SlotState s{};
+        SlotKey key{};
         SlotCtl cl{};
-        s.kind = q.kind;
-        s.var = q.kind == PDLPB_BASE ? -1 : q.var;
-        s.value = q.value;
-        int32_t status = PDLPB_STATUS_RUNNING;
-        double cn = x->norm_c;
-        if (q.kind != PDLPB_BASE) {
-            const bool bad_value = std::isnan(q.value) ||
-                                   (q.kind == PDLPB_SET_LO && q.value == INFINITY) ||
-                                   (q.kind == PDLPB_SET_HI && q.value == -INFINITY) ||
-                                   (q.kind == PDLPB_OBJ_UNIT && !std::isfinite(q.value));
-            if (bad_value) status = PDLPB_STATUS_INVALID_INPUT;
-            else if (q.kind == PDLPB_SET_LO && q.value > x->h_xu[q.var])
-                status = PDLPB_STATUS_INFEASIBLE_BOUNDS;
-            else if (q.kind == PDLPB_SET_HI && q.value < x->h_xl[q.var])
-                status = PDLPB_STATUS_INFEASIBLE_BOUNDS;
-            if (q.kind == PDLPB_OBJ_UNIT) cn = std::fabs(q.value);
-        }
-        double w = 1.0;
+        key.varkind = (q.kind == PDLPB_BASE ? VAR_NONE : q.var) | (q.kind << 28);
+        int32_t status = lp_status(x, q);
+        double w = default_weight(x, q);
         if (w_warm) {
             w = w0[j];
             if (!(w > 0.0) || !std::isfinite(w)) status = PDLPB_STATUS_INVALID_INPUT;
-        } else if (cn > 1e-10 && x->norm_b > 1e-10) {
-            w = cn / x->norm_b;
         }
         if (status != PDLPB_STATUS_RUNNING) w = 1.0;
-        s.flags = SLOT_ACTIVE;
-        s.tau = x->eta / w;
-        s.sigma = x->eta * w;
+        key.flags = SLOT_ACTIVE;
         cl.w = w;
         cl.r_prev = -1.0;
         cl.status = status;
         for (double& v : cl.kkt) v = NAN;
         cl.obj = NAN;
         if (status == PDLPB_STATUS_RUNNING) {   // running LPs fill slots [0, n_run0) in LP order
-            hs.push_back(s);
-            slot_lp.push_back(j);
+            h_key.push_back(key);
+            h_tau.push_back(x->eta / w);
+            h_sigma.push_back(x->eta * w);
+            h_dval.push_back(q.value);
+            h_lp.push_back(j);
         } else {
             cl.iters = 0;
         }
         hc[j] = cl;
     }
-    const int32_t n_run0 = (int32_t)hs.size();
+    const int32_t n_run0 = (int32_t)h_key.size();
 
     // storage (grows, reused for smaller batches)
-    x->vec_ld = 4;
-    choose_tile(x, B);
-    x->vec_ld = x->vec;
-    const int32_t ld = ((B + x->vec - 1) / x->vec) * x->vec;
+    int32_t ld = 0;
+    {
+        int rc = ensure_storage(x, B, B, &ld);
+        if (rc) return rc;
+    }
     const size_t esz = x->fp32 ? sizeof(float) : sizeof(double);
-    const size_t rows_max = (size_t)std::max(n, m);
-    const size_t block_bytes = rows_max * (size_t)ld * esz;
-    if (block_bytes > x->cap_block_bytes) {
-        x->drop_graph();
-        for (void*& p : x->blk) x->release(p, x->cap_block_bytes);
-        x->cap_block_bytes = 0;
-        for (void*& p : x->blk) HIP_TRY(x, x->alloc(&p, block_bytes));
-        x->cap_block_bytes = block_bytes;
-    }
-    const size_t rx_bytes = (size_t)B * n * esz, ry_bytes = (size_t)B * m * esz;
-    if (rx_bytes > x->cap_res_x || ry_bytes > x->cap_res_y) {
-        x->drop_graph();
-        x->release(x->res[0], x->cap_res_x);
-        x->release(x->res[1], x->cap_res_x);
-        x->release(x->res[2], x->cap_res_y);
-        x->release(x->res[3], x->cap_res_y);
-        x->cap_res_x = x->cap_res_y = 0;
-        for (int q = 0; q < 2; ++q) HIP_TRY(x, x->alloc(&x->res[q], rx_bytes));
-        for (int q = 2; q < 4; ++q) HIP_TRY(x, x->alloc(&x->res[q], ry_bytes));
-        x->cap_res_x = rx_bytes;
-        x->cap_res_y = ry_bytes;
-    }
-    if (B > x->cap_slots) {
-        x->drop_graph();
-        x->release(x->st, sizeof(SlotState) * x->cap_slots);
-        x->release(x->slot_lp, sizeof(int32_t) * x->cap_slots);
-        x->release(x->ctl, sizeof(SlotCtl) * x->cap_slots);
-        x->release(x->rlog, sizeof(int32_t) * RESTART_LOG * x->cap_slots);
-        x->release(x->retire, sizeof(RetireEntry) * x->cap_slots);
-        x->release(x->moves, sizeof(MoveEntry) * x->cap_slots);
-        x->cap_slots = 0;
-        HIP_TRY(x, x->alloc(&x->st, sizeof(SlotState) * B));
-        HIP_TRY(x, x->alloc(&x->slot_lp, sizeof(int32_t) * B));
-        HIP_TRY(x, x->alloc(&x->ctl, sizeof(SlotCtl) * B));
-        HIP_TRY(x, x->alloc(&x->rlog, sizeof(int32_t) * RESTART_LOG * B));
-        HIP_TRY(x, x->alloc(&x->retire, sizeof(RetireEntry) * B));
-        HIP_TRY(x, x->alloc(&x->moves, sizeof(MoveEntry) * B));
-        x->cap_slots = B;
-    }
-    const size_t part_need = (size_t)(x->npx + x->npy + 2) * NTERM * ld;
-    if (part_need > x->cap_part) {
-        x->drop_graph();
-        x->release(x->part, x->cap_part * sizeof(double));
-        x->cap_part = 0;
-        HIP_TRY(x, x->alloc(&x->part, part_need * sizeof(double)));
-        x->cap_part = part_need;
-    }
     x->drop_graph();   // grid shapes and slot count are baked into the captured launches
     x->B = B;
     x->ld = ld;
@@ -868,9 +1056,15 @@ int pdlpb_set_batch(pdlpb_ctx* x, int32_t B, const pdlpb_delta* deltas, const do
     x->solved = false;
 
     if (n_run0 > 0) {
-        HIP_TRY(x, hipMemcpyAsync(x->st, hs.data(), sizeof(SlotState) * n_run0,
+        HIP_TRY(x, hipMemcpyAsync(x->sl.key, h_key.data(), sizeof(SlotKey) * n_run0,
                                   hipMemcpyHostToDevice, x->stream));
-        HIP_TRY(x, hipMemcpyAsync(x->slot_lp, slot_lp.data(), sizeof(int32_t) * n_run0,
+        HIP_TRY(x, hipMemcpyAsync(x->sl.tau, h_tau.data(), sizeof(double) * n_run0,
+                                  hipMemcpyHostToDevice, x->stream));
+        HIP_TRY(x, hipMemcpyAsync(x->sl.sigma, h_sigma.data(), sizeof(double) * n_run0,
+                                  hipMemcpyHostToDevice, x->stream));
+        HIP_TRY(x, hipMemcpyAsync(x->sl.dval, h_dval.data(), sizeof(double) * n_run0,
+                                  hipMemcpyHostToDevice, x->stream));
+        HIP_TRY(x, hipMemcpyAsync(x->sl.lp, h_lp.data(), sizeof(int32_t) * n_run0,
                                   hipMemcpyHostToDevice, x->stream));
     }
     HIP_TRY(x, hipMemcpyAsync(x->ctl, hc.data(), sizeof(SlotCtl) * B, hipMemcpyHostToDevice,
@@ -907,12 +1101,12 @@ int pdlpb_set_batch(pdlpb_ctx* x, int32_t B, const pdlpb_delta* deltas, const do
     }
     if (x->fp32) {
         float* const* b = reinterpret_cast<float* const*>(x->blk);
-        HIP_TRY(x, launch_init_blocks<float>(n, m, ld, n_run0, x->st, x->slot_lp, x->xl, x->xu, xw,
+        HIP_TRY(x, launch_init_blocks<float>(n, m, ld, n_run0, x->sl, x->xl, x->xu, xw,
                                              yw, warm_mode, b[0], b[1], b[2], b[3], b[4], b[5],
                                              b[6], b[7], x->stream));
     } else {
         double* const* b = reinterpret_cast<double* const*>(x->blk);
-        HIP_TRY(x, launch_init_blocks<double>(n, m, ld, n_run0, x->st, x->slot_lp, x->xl, x->xu,
+        HIP_TRY(x, launch_init_blocks<double>(n, m, ld, n_run0, x->sl, x->xl, x->xu,
                                               xw, yw, warm_mode, b[0], b[1], b[2], b[3], b[4],
                                               b[5], b[6], b[7], x->stream));
     }
@@ -1000,6 +1194,340 @@ int pdlpb_get_trace(pdlpb_ctx* x, int32_t j, double* x_iter, double* y_iter, dou
     if (x_iter) rc = copy_results(x, 1, j, 1, x_iter, PDLPB_MEM_HOST);
     if (!rc && y_iter) rc = copy_results(x, 3, j, 1, y_iter, PDLPB_MEM_HOST);
     return rc;
+}
+
+
+// ---------------------------------------------------------------------------
+// serving: continuous batching
+// ---------------------------------------------------------------------------
+
+int pdlpb_set_base_warm(pdlpb_ctx* x, const double* xw, const double* yw, double w, int32_t mem) {
+    if (!x) return PDLPB_EINVAL;
+    if (!xw || (x->m > 0 && !yw)) return x->fail(PDLPB_EINVAL, "warm start vectors missing");
+    if (!(w > 0.0) || !std::isfinite(w)) return x->fail(PDLPB_EINVAL, "w must be positive and finite");
+    if (mem != PDLPB_MEM_HOST && mem != PDLPB_MEM_DEVICE) return x->fail(PDLPB_EINVAL, "unknown mem");
+    HIP_TRY(x, hipSetDevice(x->device));
+    if (!x->base_x) HIP_TRY(x, x->alloc(&x->base_x, sizeof(double) * ((size_t)x->n + x->m)));
+    const hipMemcpyKind kind = mem == PDLPB_MEM_DEVICE ? hipMemcpyDeviceToDevice
+                                                        : hipMemcpyHostToDevice;
+    HIP_TRY(x, hipMemcpyAsync(x->base_x, xw, sizeof(double) * x->n, kind, x->stream));
+    if (x->m)
+        HIP_TRY(x, hipMemcpyAsync(x->base_x + x->n, yw, sizeof(double) * x->m, kind, x->stream));
+    HIP_TRY(x, hipStreamSynchronize(x->stream));
+    x->base_w = w;
+    x->have_base = true;
+    return PDLPB_OK;
+}
+
+int pdlpb_serve_begin(pdlpb_ctx* x, int32_t result_capacity) {
+    if (!x) return PDLPB_EINVAL;
+    if (x->opt.restart_scope != PDLPB_RESTART_PER_LP)
+        return x->fail(PDLPB_EINVAL, "serving needs the per-LP restart scope");
+    if (result_capacity < 1 || result_capacity > (1 << 24))
+        return x->fail(PDLPB_EINVAL, "result_capacity out of range");
+    HIP_TRY(x, hipSetDevice(x->device));
+    const int32_t cols = x->opt.max_batch;
+    int32_t ld = 0;
+    int rc = ensure_storage(x, cols, result_capacity, &ld);
+    if (rc) return rc;
+    x->drop_graph();
+    x->B = cols;
+    x->ld = ld;
+    x->n_run0 = 0;
+    x->batch_set = false;
+    x->solved = false;
+    x->serving = true;
+    x->res_cap = result_capacity;
+    x->free_rows.clear();
+    for (int32_t r = result_capacity - 1; r >= 0; --r) x->free_rows.push_back(r);
+    x->row_id.assign(result_capacity, -1);
+    x->id_row.clear();
+    x->queue.clear();
+    x->completed.clear();
+    x->n_cols = 0;
+    x->t0 = 0;
+    x->launched = false;
+    x->live = 1;
+    choose_tile(x, 1);
+    Globals hg{};
+    hg.eta = x->eta;
+    hg.r_prev = -1.0;
+    HIP_TRY(x, hipMemcpy(x->g, &hg, sizeof(Globals), hipMemcpyHostToDevice));
+    return PDLPB_OK;
+}
+
+int pdlpb_submit(pdlpb_ctx* x, int32_t count, const pdlpb_delta* deltas, int32_t warm_mode,
+                 double tol, int64_t max_iters, int32_t mem, int64_t* first_id) {
+    if (!x) return PDLPB_EINVAL;
+    if (!x->serving) return x->fail(PDLPB_ESTATE, "call pdlpb_serve_begin first");
+    if (count < 1 || !deltas) return x->fail(PDLPB_EINVAL, "need count >= 1 and deltas");
+    if (warm_mode != PDLPB_WARM_NONE && warm_mode != PDLPB_WARM_BASE)
+        return x->fail(PDLPB_EINVAL, "serving takes PDLPB_WARM_NONE or PDLPB_WARM_BASE");
+    if (warm_mode == PDLPB_WARM_BASE && !x->have_base)
+        return x->fail(PDLPB_ESTATE, "no base warm start set");
+    if (!(tol >= 0.0)) return x->fail(PDLPB_EINVAL, "tol must be >= 0");
+    if (max_iters < 1 || max_iters > (1 << 30)) return x->fail(PDLPB_EINVAL, "max_iters out of range");
+    if (mem != PDLPB_MEM_HOST && mem != PDLPB_MEM_DEVICE) return x->fail(PDLPB_EINVAL, "unknown mem");
+    if ((int64_t)x->free_rows.size() < count)
+        return x->fail(PDLPB_ENOMEM, "not enough free result rows; release finished LPs");
+    std::vector<pdlpb_delta> d(count);
+    if (mem == PDLPB_MEM_DEVICE)
+        HIP_TRY(x, hipMemcpy(d.data(), deltas, sizeof(pdlpb_delta) * count, hipMemcpyDeviceToHost));
+    else
+        std::memcpy(d.data(), deltas, sizeof(pdlpb_delta) * count);
+    for (int32_t j = 0; j < count; ++j) {
+        if (d[j].kind < PDLPB_BASE || d[j].kind > PDLPB_OBJ_UNIT)
+            return x->fail(PDLPB_EINVAL, "delta kind out of range at LP " + std::to_string(j));
+        if (d[j].kind != PDLPB_BASE && (d[j].var < 0 || d[j].var >= x->n))
+            return x->fail(PDLPB_EINVAL, "delta var out of range at LP " + std::to_string(j));
+    }
+    *first_id = x->next_id;
+    const size_t esz = x->fp32 ? sizeof(float) : sizeof(double);
+    for (int32_t j = 0; j < count; ++j) {
+        const pdlpb_delta& q = d[j];
+        const int64_t id = x->next_id++;
+        const int32_t row = x->free_rows.back();
+        x->free_rows.pop_back();
+        x->row_id[row] = id;
+        x->id_row[id] = row;
+        int32_t status = lp_status(x, q);
+        double w = warm_mode == PDLPB_WARM_BASE ? x->base_w : default_weight(x, q);
+        if (status != PDLPB_STATUS_RUNNING) {
+            // settled without iterating: record the outcome and zero results
+            SlotCtl cl{};
+            cl.w = w;
+            cl.status = status;
+            for (double& v : cl.kkt) v = NAN;
+            cl.obj = NAN;
+            cl.tol = tol;
+            HIP_TRY(x, hipMemcpyAsync(x->ctl + row, &cl, sizeof(SlotCtl), hipMemcpyHostToDevice,
+                                      x->stream));
+            for (int qb = 0; qb < 4; ++qb) {
+                const size_t len = (size_t)(qb < 2 ? x->n : x->m) * esz;
+                if (len)
+                    HIP_TRY(x, hipMemsetAsync(static_cast<char*>(x->res[qb]) + (size_t)row * len, 0,
+                                              len, x->stream));
+            }
+            HIP_TRY(x, hipStreamSynchronize(x->stream));
+            x->completed.push_back(id);
+            continue;
+        }
+        pdlpb_ctx::Pending p;
+        p.row = row;
+        p.varkind = (q.kind == PDLPB_BASE ? VAR_NONE : q.var) | (q.kind << 28);
+        p.dval = q.value;
+        p.w = w;
+        p.tol = tol;
+        p.max_iters = (int32_t)max_iters;
+        p.warm = warm_mode;
+        x->queue.push_back(p);
+    }
+    return PDLPB_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// admit queued LPs into free columns and run their first iteration (t_local = 0)
+template <typename T>
+int serve_admit(pdlpb_ctx* x) {
+    const int32_t free_cols = x->B - x->n_cols;
+    const int32_t k = std::min<int32_t>(free_cols, (int32_t)x->queue.size());
+    if (k <= 0) return PDLPB_OK;
+    // a batch admitted together shares one warm-start mode (the queue is split where it changes)
+    const int32_t warm = x->queue.front().warm;
+    int32_t cnt = 0;
+    while (cnt < k && x->queue[cnt].warm == warm) ++cnt;
+    const int32_t c0 = x->n_cols;
+    x->h_adm_rows.resize(cnt);
+    x->h_adm_ctl.resize(cnt);
+    x->h_adm_key.resize(cnt);
+    x->h_adm_tau.resize(cnt);
+    x->h_adm_sigma.resize(cnt);
+    x->h_adm_dval.resize(cnt);
+    x->h_adm_tstart.resize(cnt);
+    x->h_adm_lp.resize(cnt);
+    for (int32_t j = 0; j < cnt; ++j) {
+        const pdlpb_ctx::Pending p = x->queue.front();
+        x->queue.pop_front();
+        SlotKey key{};
+        key.t_anchor = x->t0;
+        key.t_end = x->t0 + p.max_iters - 1;
+        key.varkind = p.varkind;
+        key.flags = SLOT_ACTIVE | SLOT_NEW;
+        x->h_adm_key[j] = key;
+        x->h_adm_tau[j] = x->eta / p.w;
+        x->h_adm_sigma[j] = x->eta * p.w;
+        x->h_adm_dval[j] = p.dval;
+        x->h_adm_tstart[j] = x->t0;
+        x->h_adm_lp[j] = p.row;
+        x->h_adm_rows[j] = p.row;
+        SlotCtl cl{};
+        cl.w = p.w;
+        cl.r_prev = -1.0;
+        cl.status = PDLPB_STATUS_RUNNING;
+        for (double& v : cl.kkt) v = NAN;
+        cl.obj = NAN;
+        cl.tol = p.tol;
+        x->h_adm_ctl[j] = cl;
+    }
+    const hipMemcpyKind h2d = hipMemcpyHostToDevice;
+    HIP_TRY(x, hipMemcpyAsync(x->sl.key + c0, x->h_adm_key.data(), sizeof(SlotKey) * cnt, h2d, x->stream));
+    HIP_TRY(x, hipMemcpyAsync(x->sl.tau + c0, x->h_adm_tau.data(), sizeof(double) * cnt, h2d, x->stream));
+    HIP_TRY(x, hipMemcpyAsync(x->sl.sigma + c0, x->h_adm_sigma.data(), sizeof(double) * cnt, h2d, x->stream));
+    HIP_TRY(x, hipMemcpyAsync(x->sl.dval + c0, x->h_adm_dval.data(), sizeof(double) * cnt, h2d, x->stream));
+    HIP_TRY(x, hipMemcpyAsync(x->sl.t_start + c0, x->h_adm_tstart.data(), sizeof(int32_t) * cnt, h2d, x->stream));
+    HIP_TRY(x, hipMemcpyAsync(x->sl.lp + c0, x->h_adm_lp.data(), sizeof(int32_t) * cnt, h2d, x->stream));
+    HIP_TRY(x, hipMemcpyAsync(x->adm_rows, x->h_adm_rows.data(), sizeof(int32_t) * cnt, h2d, x->stream));
+    HIP_TRY(x, hipMemcpyAsync(x->adm_ctl, x->h_adm_ctl.data(), sizeof(SlotCtl) * cnt, h2d, x->stream));
+    x->n_cols = c0 + cnt;
+    HIP_TRY(x, launch_admit(x->ctl, x->adm_rows, x->adm_ctl, cnt, x->g, x->n_cols, x->stream));
+    const double* xw = warm == PDLPB_WARM_BASE ? x->base_x : nullptr;
+    const double* yw = warm == PDLPB_WARM_BASE ? x->base_x + x->n : nullptr;
+    T* const* b = reinterpret_cast<T* const*>(x->blk);
+    HIP_TRY(x, launch_init_columns<T>(x->n, x->m, x->ld, c0, cnt, x->sl, x->xl, x->xu, xw, yw,
+                                      warm == PDLPB_WARM_BASE ? PDLPB_WARM_SHARED : PDLPB_WARM_NONE,
+                                      b, x->stream));
+    // first iteration of the admitted LPs at t = t0 (t_local = 0): a full evaluation
+    const int32_t shape = shape_cols(x, x->n_cols);
+    if (shape != x->live) {
+        x->live = shape;
+        choose_tile(x, shape);
+    }
+    int rc = enqueue_iteration<T>(x, 0, 1, nullptr, 1);
+    if (!rc) rc = enqueue_evaluation<T>(x, 0, 1, 0, nullptr, 1);
+    return rc;
+}
+
+template <typename T>
+int serve_launch(pdlpb_ctx* x) {
+    int rc = serve_admit<T>(x);
+    if (rc) return rc;
+    if (x->n_cols == 0) return PDLPB_OK;
+    const int32_t shape = shape_cols(x, x->n_cols);
+    if (shape != x->live) {
+        x->live = shape;
+        choose_tile(x, shape);
+    }
+    if (x->opt.use_graphs && !x->timing) {
+        hipGraphExec_t exec = nullptr;
+        for (auto& gr : x->graphs)
+            if (gr.first == x->live) exec = gr.second;
+        if (!exec) {
+            hipGraph_t gr = nullptr;
+            HIP_TRY(x, hipStreamBeginCapture(x->stream, hipStreamCaptureModeThreadLocal));
+            int r2 = enqueue_epoch<T>(x, nullptr);
+            hipError_t e = hipStreamEndCapture(x->stream, &gr);
+            if (r2) {
+                if (gr) (void)hipGraphDestroy(gr);
+                return r2;
+            }
+            if (e != hipSuccess) return x->hip_fail(e, "hipStreamEndCapture");
+            e = hipGraphInstantiate(&exec, gr, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(gr);
+            if (e != hipSuccess) return x->hip_fail(e, "hipGraphInstantiate");
+            x->graphs.push_back({x->live, exec});
+        }
+        HIP_TRY(x, hipGraphLaunch(exec, x->stream));
+    } else {
+        rc = enqueue_epoch<T>(x, nullptr);
+        if (rc) return rc;
+    }
+    // the stopped LPs of this block, for the host's completion list
+    HIP_TRY(x, hipMemcpyAsync(x->h_pinned, x->g, 8 * sizeof(int32_t), hipMemcpyDeviceToHost,
+                              x->stream));
+    x->launched = true;
+    return PDLPB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pdlpb_serve_launch(pdlpb_ctx* x) {
+    if (!x) return PDLPB_EINVAL;
+    if (!x->serving) return x->fail(PDLPB_ESTATE, "call pdlpb_serve_begin first");
+    if (x->launched) return x->fail(PDLPB_ESTATE, "previous block not waited for");
+    HIP_TRY(x, hipSetDevice(x->device));
+    return x->fp32 ? serve_launch<float>(x) : serve_launch<double>(x);
+}
+
+int pdlpb_serve_wait(pdlpb_ctx* x, int32_t* n_running, int32_t* n_queued) {
+    if (!x) return PDLPB_EINVAL;
+    if (!x->serving) return x->fail(PDLPB_ESTATE, "call pdlpb_serve_begin first");
+    HIP_TRY(x, hipSetDevice(x->device));
+    if (x->launched) {
+        HIP_TRY(x, hipStreamSynchronize(x->stream));
+        x->launched = false;
+        x->t0 += x->opt.eval_every;
+        const int32_t nr = x->h_pinned[4];            // Globals::n_retire
+        x->n_cols = x->h_pinned[3];                   // Globals::n_cols
+        if (nr > 0) {
+            x->h_retire.resize(nr);
+            HIP_TRY(x, hipMemcpy(x->h_retire.data(), x->retire, sizeof(RetireEntry) * nr,
+                                 hipMemcpyDeviceToHost));
+            for (const RetireEntry& e : x->h_retire) x->completed.push_back(x->row_id[e.lp]);
+        }
+    }
+    if (n_running) *n_running = x->n_cols;
+    if (n_queued) *n_queued = (int32_t)x->queue.size();
+    return PDLPB_OK;
+}
+
+int pdlpb_poll(pdlpb_ctx* x, int64_t* ids, int32_t cap, int32_t* count) {
+    if (!x || !count) return PDLPB_EINVAL;
+    int32_t c = 0;
+    while (c < cap && !x->completed.empty()) {
+        ids[c++] = x->completed.front();
+        x->completed.pop_front();
+    }
+    *count = c;
+    return PDLPB_OK;
+}
+
+int pdlpb_result(pdlpb_ctx* x, int64_t id, double* xo, double* yo, int32_t* status, double kkt[4],
+                 double* obj, int64_t* iters, int32_t mem) {
+    if (!x) return PDLPB_EINVAL;
+    auto it = x->id_row.find(id);
+    if (it == x->id_row.end()) return x->fail(PDLPB_EINVAL, "unknown or released id");
+    const int32_t row = it->second;
+    HIP_TRY(x, hipSetDevice(x->device));
+    SlotCtl cl{};
+    HIP_TRY(x, hipMemcpy(&cl, x->ctl + row, sizeof(SlotCtl), hipMemcpyDeviceToHost));
+    if (status) *status = cl.status;
+    if (kkt)
+        for (int q = 0; q < 4; ++q) kkt[q] = cl.kkt[q];
+    if (obj) *obj = cl.obj;
+    if (iters) *iters = cl.iters;
+    int rc = PDLPB_OK;
+    if (cl.status != PDLPB_STATUS_RUNNING) {
+        if (xo) rc = copy_results(x, 0, row, 1, xo, mem);
+        if (!rc && yo) rc = copy_results(x, 2, row, 1, yo, mem);
+    }
+    return rc;
+}
+
+int pdlpb_release(pdlpb_ctx* x, int64_t id) {
+    if (!x) return PDLPB_EINVAL;
+    auto it = x->id_row.find(id);
+    if (it == x->id_row.end()) return x->fail(PDLPB_EINVAL, "unknown or released id");
+    const int32_t row = it->second;
+    x->id_row.erase(it);
+    x->row_id[row] = -1;
+    x->free_rows.push_back(row);
+    return PDLPB_OK;
+}
+
+int pdlpb_set_tile(pdlpb_ctx* x, int32_t lanes, int32_t vec) {
+    if (!x) return PDLPB_EINVAL;
+    if (lanes != 0 && (lanes < 1 || lanes > 64 || (lanes & (lanes - 1))))
+        return x->fail(PDLPB_EINVAL, "lanes must be 0 or a power of two in [1, 64]");
+    if (vec != 0 && vec != 1 && vec != 2 && vec != 4)
+        return x->fail(PDLPB_EINVAL, "vec must be 0, 1, 2 or 4");
+    x->opt.tile_lanes = lanes;
+    x->opt.tile_vec = vec;
+    return PDLPB_OK;
 }
 
 int pdlpb_get_step_size(const pdlpb_ctx* x, double* eta, double* norm_a) {

@@ -13,21 +13,32 @@ namespace pdlpb {
 // kernel copies z~ into its anchor and iterate, and the next residual
 // evaluation records r(z^{n,0}) and clears the flag.  SLOT_RETIRE marks an LP
 // that has stopped and whose results still sit in its slot; the next
-// compaction copies them out and frees the slot.
-enum : int32_t { SLOT_ACTIVE = 1, SLOT_FRESH = 2, SLOT_RETIRE = 4 };
+// compaction copies them out and frees the slot.  SLOT_NEW marks an LP
+// admitted into a running batch that has not made its first iteration yet.
+enum : int32_t { SLOT_ACTIVE = 1, SLOT_FRESH = 2, SLOT_RETIRE = 4, SLOT_NEW = 8 };
 
-struct SlotState {
-    int32_t kind;      // delta kind (PDLPB_BASE .. PDLPB_OBJ_UNIT)
-    int32_t var;       // delta variable
-    double  value;     // delta value
-    double  tau;       // eta / w
-    double  sigma;     // eta * w
+// The per-slot state is stored as separate arrays so that the product kernels,
+// which read it once per column per row, load 16 + 8 bytes per column: the key
+// and the one step size they use.  The delta value is read only on the one row
+// (variable) it changes.
+struct SlotKey {
     int32_t t_anchor;  // global iteration index at which the current restart cycle began (k = t - t_anchor)
-    int32_t t_start;   // global iteration index of the LP's first iteration
     int32_t t_end;     // global iteration index of the LP's last permitted iteration
-    int32_t flags;     // SLOT_ACTIVE: still iterating; SLOT_FRESH: restarted at the last full evaluation
+    int32_t varkind;   // delta: variable | kind << 28 (PDLPB_BASE uses variable VAR_NONE)
+    int32_t flags;     // SLOT_ACTIVE / SLOT_FRESH / SLOT_RETIRE
 };
-static_assert(sizeof(SlotState) == 48, "SlotState layout");
+static_assert(sizeof(SlotKey) == 16, "SlotKey layout");
+constexpr int32_t VAR_MASK = 0x0FFFFFFF;
+constexpr int32_t VAR_NONE = 0x0FFFFFFF;   // no variable; n is limited to VAR_NONE - 1
+
+struct Slots {          // all indexed by slot
+    SlotKey* key;
+    double*  tau;       // eta / w
+    double*  sigma;     // eta * w
+    double*  dval;      // delta value
+    int32_t* t_start;   // global iteration index of the LP's first iteration
+    int32_t* lp;        // LP held by the slot
+};
 
 // ---- per-LP control data (indexed by LP, not by slot) -----------------------
 constexpr int RESTART_LOG = 64;
@@ -45,6 +56,7 @@ struct SlotCtl {
     int32_t t_last;    // global iteration index of the LP's last iteration
     int32_t k_last;    // inner index k of the LP's last iteration (Halpern weight of its last update)
     int32_t pad;
+    double  tol;       // stopping tolerance of the LP (eq:stopping)
 };
 
 // ---- compaction plan written by the control pass, executed by k_compact ------
@@ -102,10 +114,11 @@ struct StepArgs {
     const double* c;     // primal: base objective (n); dual: unused
     const double* lo;    // primal: base xl (n);  dual: row lower bounds l (m)
     const double* hi;    // primal: base xu (n);  dual: row upper bounds u (m)
-    const SlotState* st;
+    Slots sl;
     const Globals* g;
     int32_t it;          // iteration index inside the block; global t = g->t0 + it
     int32_t eval;        // 1: every running LP writes z~ and its displacement
+    int32_t admit;       // 1: only LPs flagged SLOT_NEW iterate (their first iteration)
 };
 
 template <typename T>
@@ -115,7 +128,7 @@ struct EvalArgs {
     const int32_t* t_rp; const int32_t* t_ci; const T* t_v;    // A' (n x m)
     const T *Xt, *DX, *X0, *Yt, *DY, *Y0;
     const double *c, *xl, *xu, *rl, *ru;
-    const SlotState* st;
+    Slots sl;
     const Globals* g;        // live column count
     int32_t pw_x, pw_y;      // rows per wave on the x side / y side
     int32_t npx, npy;        // row panels (4 waves each) on each side
@@ -128,8 +141,7 @@ struct ControlArgs {
     const double* part_x;
     const double* part_y;
     double* sums;            // [2*NTERM][ld] scratch written by the reduce kernel
-    SlotState* st;           // by slot
-    const int32_t* slot_lp;  // LP held by each slot
+    Slots sl;                // by slot
     SlotCtl* ctl;            // by LP
     int32_t* rlog;           // [LP][RESTART_LOG]
     RetireEntry* retire;     // compaction plan (>= B entries each)
@@ -140,6 +152,7 @@ struct ControlArgs {
     int32_t advance;         // 1: move g->t0 on by `block` after this pass
     int32_t block;           // C
     int32_t batch_avg;       // restart scope
+    int32_t admit;           // 1: first evaluation of newly admitted LPs only (no compaction)
     int32_t pw_literal;      // primal weight ratio as printed
     double beta_s, beta_n, beta_a, theta, cross_sign;
     double infeas_tol;       // eps of the infeasibility tests; < 0: the stopping tolerance; 0: off
@@ -160,17 +173,17 @@ hipError_t launch_control(const ControlArgs& a, hipStream_t s);
 // (xw: n, yw: m), 2 per LP (xw: ncols*n, yw: ncols*m, LP-major).
 // slot_lp maps slots [0, ncols) to LPs (per-LP warm starts are indexed by LP).
 template <typename T>
-hipError_t launch_init_blocks(int32_t n, int32_t m, int32_t ld, int32_t ncols,
-                              const SlotState* st, const int32_t* slot_lp, const double* xl,
-                              const double* xu, const double* xw, const double* yw, int32_t mode,
+hipError_t launch_init_blocks(int32_t n, int32_t m, int32_t ld, int32_t ncols, Slots sl,
+                              const double* xl, const double* xu, const double* xw,
+                              const double* yw, int32_t mode,
                               T* Xbar, T* X0, T* Xt, T* DX, T* Y, T* Y0, T* Yt, T* DY,
                               hipStream_t s);
 
 // Apply the restarts decided by the control pass (slots flagged SLOT_FRESH).
 template <typename T>
-hipError_t launch_apply_restart(int32_t n, int32_t m, int32_t ld, int32_t ncols,
-                                const SlotState* st, const Globals* g, T* X0, const T* Xt, T* Y,
-                                T* Y0, const T* Yt, hipStream_t s);
+hipError_t launch_apply_restart(int32_t n, int32_t m, int32_t ld, int32_t ncols, Slots sl,
+                                const Globals* g, T* X0, const T* Xt, T* Y, T* Y0, const T* Yt,
+                                hipStream_t s);
 
 // Execute the compaction plan: copy stopped LPs' z~ and last Halpern iterate
 // into the LP-major result blocks, move running LPs into freed slots.
@@ -178,12 +191,23 @@ hipError_t launch_apply_restart(int32_t n, int32_t m, int32_t ld, int32_t ncols,
 // res: Rx (B x n), Rxi (B x n), Ry (B x m), Ryi (B x m), LP-major.
 template <typename T>
 hipError_t launch_compact(int32_t n, int32_t m, int32_t ld, T* const* blk, T* const* res,
-                          const RetireEntry* retire, const MoveEntry* moves, SlotState* st,
-                          int32_t* slot_lp, Globals* g, hipStream_t s);
+                          const RetireEntry* retire, const MoveEntry* moves, Slots sl,
+                          Globals* g, hipStream_t s);
 
 // Start a solve: t_end of every live slot from the iteration budget, g->t0 = 0.
-hipError_t launch_begin_solve(SlotState* st, const int32_t* slot_lp, SlotCtl* ctl, int32_t ncols,
-                              int32_t max_iters, Globals* g, double tol, hipStream_t s);
+hipError_t launch_begin_solve(Slots sl, SlotCtl* ctl, int32_t ncols, int32_t max_iters, Globals* g,
+                              double tol, hipStream_t s);
+
+// Initialise columns [c0, c0 + cnt) of the eight blocks for newly admitted LPs
+// (warm start: mode 0 none, 1 shared vectors xw (n) / yw (m)).
+template <typename T>
+hipError_t launch_init_columns(int32_t n, int32_t m, int32_t ld, int32_t c0, int32_t cnt, Slots sl,
+                               const double* xl, const double* xu, const double* xw,
+                               const double* yw, int32_t mode, T* const* blk, hipStream_t s);
+
+// ctl[rows[i]] = src[i] for i < cnt; g->n_cols = n_cols.
+hipError_t launch_admit(SlotCtl* ctl, const int32_t* rows, const SlotCtl* src, int32_t cnt,
+                        Globals* g, int32_t n_cols, hipStream_t s);
 
 // Convert n entries of a result block to float64 (FP32 mode).
 hipError_t launch_widen(const float* src, int64_t count, double* dst, hipStream_t s);

@@ -25,7 +25,7 @@ STATUS_PRIMAL_INFEASIBLE, STATUS_DUAL_INFEASIBLE = 6, 7
 BASE, SET_LO, SET_HI, OBJ_UNIT = 0, 1, 2, 3
 FP64, MIXED32 = 0, 1
 RESTART_PER_LP, RESTART_BATCH_AVG = 0, 1
-WARM_NONE, WARM_SHARED, WARM_PER_LP = 0, 1, 2
+WARM_NONE, WARM_SHARED, WARM_PER_LP, WARM_BASE = 0, 1, 2, 3
 MEM_HOST, MEM_DEVICE = 0, 1
 
 STATUS_NAMES = {0: "RUNNING", 1: "OPTIMAL", 2: "ITERATION_LIMIT", 3: "INFEASIBLE_BOUNDS",
@@ -33,7 +33,10 @@ STATUS_NAMES = {0: "RUNNING", 1: "OPTIMAL", 2: "ITERATION_LIMIT", 3: "INFEASIBLE
                 7: "DUAL_INFEASIBLE"}
 
 EXPORTED = ["pdlpb_default_options", "pdlpb_create", "pdlpb_set_batch", "pdlpb_solve",
-            "pdlpb_get", "pdlpb_get_batch", "pdlpb_get_trace", "pdlpb_get_step_size",
+            "pdlpb_get", "pdlpb_get_batch", "pdlpb_get_trace", "pdlpb_set_tile",
+            "pdlpb_get_step_size", "pdlpb_set_base_warm", "pdlpb_serve_begin", "pdlpb_submit",
+            "pdlpb_serve_launch", "pdlpb_serve_wait", "pdlpb_poll", "pdlpb_result",
+            "pdlpb_release",
             "pdlpb_set_kernel_timing", "pdlpb_kernel_times", "pdlpb_device_bytes",
             "pdlpb_destroy", "pdlpb_last_error"]
 
@@ -52,7 +55,7 @@ class Options(C.Structure):
                 ("pw_ratio", C.c_int32), ("device", C.c_int32), ("stream", C.c_void_p),
                 ("max_batch", C.c_int32), ("use_graphs", C.c_int32),
                 ("tile_lanes", C.c_int32), ("tile_vec", C.c_int32),
-                ("reserved", C.c_int32 * 8)]
+                ("autotune", C.c_int32), ("reserved", C.c_int32 * 7)]
 
 
 class PdlpbError(RuntimeError):
@@ -78,6 +81,15 @@ def _load():
         "pdlpb_get": (C.c_int, [P, i32, P, P, i32p, dp, dp, i64p, i32]),
         "pdlpb_get_batch": (C.c_int, [P, P, P, i32p, dp, dp, i64p, i32]),
         "pdlpb_get_trace": (C.c_int, [P, i32, dp, dp, dp, i32p, i32p, i32]),
+        "pdlpb_set_tile": (C.c_int, [P, i32, i32]),
+        "pdlpb_set_base_warm": (C.c_int, [P, P, P, d, i32]),
+        "pdlpb_serve_begin": (C.c_int, [P, i32]),
+        "pdlpb_submit": (C.c_int, [P, i32, P, i32, d, i64, i32, i64p]),
+        "pdlpb_serve_launch": (C.c_int, [P]),
+        "pdlpb_serve_wait": (C.c_int, [P, i32p, i32p]),
+        "pdlpb_poll": (C.c_int, [P, i64p, i32, i32p]),
+        "pdlpb_result": (C.c_int, [P, i64, P, P, i32p, dp, dp, i64p, i32]),
+        "pdlpb_release": (C.c_int, [P, i64]),
         "pdlpb_get_step_size": (C.c_int, [P, dp, dp]),
         "pdlpb_set_kernel_timing": (C.c_int, [P, i32]),
         "pdlpb_kernel_times": (C.c_int, [P, i64p, dp]),
@@ -102,6 +114,15 @@ pdlpb_solve = lib.pdlpb_solve
 pdlpb_get = lib.pdlpb_get
 pdlpb_get_batch = lib.pdlpb_get_batch
 pdlpb_get_trace = lib.pdlpb_get_trace
+pdlpb_set_tile = lib.pdlpb_set_tile
+pdlpb_set_base_warm = lib.pdlpb_set_base_warm
+pdlpb_serve_begin = lib.pdlpb_serve_begin
+pdlpb_submit = lib.pdlpb_submit
+pdlpb_serve_launch = lib.pdlpb_serve_launch
+pdlpb_serve_wait = lib.pdlpb_serve_wait
+pdlpb_poll = lib.pdlpb_poll
+pdlpb_result = lib.pdlpb_result
+pdlpb_release = lib.pdlpb_release
 pdlpb_get_step_size = lib.pdlpb_get_step_size
 pdlpb_set_kernel_timing = lib.pdlpb_set_kernel_timing
 pdlpb_kernel_times = lib.pdlpb_kernel_times
@@ -265,6 +286,54 @@ class Context:
                                         C.byref(nr), log, log_cap))
         k = min(nr.value, log_cap)
         return dict(x_iter=x, y_iter=y, w=w.value, restarts=nr.value, restart_log=list(log[:k]))
+
+    # ---- serving (continuous batching) ----
+    def set_base_warm(self, x, y, w: float):
+        xx, yy = _f64(x, self.n), _f64(y, self.m)
+        self._check(lib.pdlpb_set_base_warm(self._h, _ptr(xx), _ptr(yy), float(w), MEM_HOST))
+
+    def serve_begin(self, result_capacity: int):
+        self._check(lib.pdlpb_serve_begin(self._h, int(result_capacity)))
+
+    def submit(self, deltas, warm_mode: int = WARM_NONE, tol: float = 1e-4,
+               max_iters: int = 100000) -> range:
+        dd = np.ascontiguousarray(deltas)
+        first = C.c_int64()
+        self._check(lib.pdlpb_submit(self._h, len(dd), _ptr(dd), int(warm_mode), float(tol),
+                                     int(max_iters), MEM_HOST, C.byref(first)))
+        return range(first.value, first.value + len(dd))
+
+    def serve_launch(self):
+        self._check(lib.pdlpb_serve_launch(self._h))
+
+    def serve_wait(self):
+        nr, nq = C.c_int32(), C.c_int32()
+        self._check(lib.pdlpb_serve_wait(self._h, C.byref(nr), C.byref(nq)))
+        return nr.value, nq.value
+
+    def poll(self, cap: int = 4096):
+        ids = np.empty(cap, dtype=np.int64)
+        cnt = C.c_int32()
+        self._check(lib.pdlpb_poll(self._h, ids.ctypes.data_as(C.POINTER(C.c_int64)), cap,
+                                   C.byref(cnt)))
+        return ids[:cnt.value].tolist()
+
+    def result(self, lp_id: int, want_x=True, want_y=True):
+        x = np.empty(self.n) if want_x else None
+        y = np.empty(self.m) if want_y else None
+        st = C.c_int32()
+        kkt = (C.c_double * 4)()
+        obj = C.c_double()
+        it = C.c_int64()
+        self._check(lib.pdlpb_result(self._h, int(lp_id), _ptr(x), _ptr(y), C.byref(st), kkt,
+                                     C.byref(obj), C.byref(it), MEM_HOST))
+        return dict(x=x, y=y, status=st.value, kkt=list(kkt), obj=obj.value, iters=it.value)
+
+    def release(self, lp_id: int):
+        self._check(lib.pdlpb_release(self._h, int(lp_id)))
+
+    def set_tile(self, lanes: int = 0, vec: int = 0):
+        self._check(lib.pdlpb_set_tile(self._h, int(lanes), int(vec)))
 
     def set_kernel_timing(self, enable: bool):
         self._check(lib.pdlpb_set_kernel_timing(self._h, int(bool(enable))))

@@ -33,7 +33,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_options_layout_matches_header():
     o = P.default_options()
-    assert o.struct_size == P.C.sizeof(P.Options) == 136
+    assert o.struct_size == P.C.sizeof(P.Options) == 136 and o.autotune == 1
     assert (o.eval_every, o.beta_sufficient, o.beta_necessary, o.beta_artificial, o.theta) == \
         (64, 0.2, 0.8, 0.36, 0.5)
     assert o.cross_sign == -1.0 and o.use_graphs == 1 and o.max_batch == 4096

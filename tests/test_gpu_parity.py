@@ -381,3 +381,20 @@ def test_tiny_lps_reach_exact_optimum(P):
             g = ctx.get(0)
         assert g["status"] == P.STATUS_OPTIMAL
         assert abs(g["obj"] - best) <= 1e-7 * (1 + abs(best)), seed
+
+
+def test_autotune_leaves_results_unchanged(P):
+    """The tile-shape timing runs inside the first block of iterations of a
+    large batch; every shape gives the same bits, so results match a run with
+    the fixed heuristic shape."""
+    inst = make_cfg3(m=20000, n=50000)
+    D = obbt_deltas(choose_vars(inst.n, 48, seed=21))
+    outs = []
+    for tune in (0, 1):
+        with make_ctx(inst, 0.05, autotune=tune) as ctx:
+            ctx.set_batch(D)
+            ctx.solve(tol=0.0, max_iters=200)
+            outs.append(ctx.get_batch())
+    np.testing.assert_array_equal(outs[0]["X"], outs[1]["X"])
+    np.testing.assert_array_equal(outs[0]["Y"], outs[1]["Y"])
+    np.testing.assert_array_equal(outs[0]["iters"], outs[1]["iters"])
