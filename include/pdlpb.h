@@ -110,7 +110,11 @@ typedef struct pdlpb_options {
     int32_t tile_vec;         /* 0 = automatic; else columns per lane (1, 2 or 4) */
     int32_t autotune;         /* 1 (default): time tile shapes on the first block of C iterations of
                                  a large batch and keep the fastest per kernel; 0: fixed heuristic */
-    int32_t reserved[7];
+    int32_t reserved_pad;     /* zero */
+    double  dual_tol;         /* eps of the dual-feasibility test of eq:stopping: < 0 (default -1) uses the
+                                 stopping tolerance; >= 0 as given.  The bound-tightening experiments of
+                                 Section 6 check dual feasibility at 1e-8 before trusting a dual bound */
+    int32_t reserved[4];
 } pdlpb_options;
 
 typedef struct pdlpb_ctx pdlpb_ctx;   /* opaque; owns all device memory of one base matrix and its batch */
@@ -192,6 +196,50 @@ int pdlpb_get_batch(pdlpb_ctx* ctx, double* X, double* Y, int32_t* status, doubl
  */
 int pdlpb_get_trace(pdlpb_ctx* ctx, int32_t j, double* x_iter, double* y_iter, double* w,
                     int32_t* restarts, int32_t* restart_log, int32_t log_cap);
+
+/*
+ * Dual objective -phi_box(r~) - phi_[l,u](y~) of every LP of the solved batch
+ * (the dual of eq:main_lp, with r~ the reduced cost of Section 4) at the point
+ * its KKT measures were taken: dual_obj (B host doubles).  For an LP whose
+ * box is finite it is a lower bound on the LP's optimum by weak duality.
+ * NaN for LPs that never iterated.  ESTATE before pdlpb_solve.
+ */
+int pdlpb_get_dual_objective(pdlpb_ctx* ctx, double* dual_obj);
+
+/*
+ * Bound tightening (Section 5.2) with the safeguards of the OBBT experiments
+ * (Section 6): every OBJ_UNIT LP j of the solved batch minimised v_j x_var
+ * (v_j = its value).  If it stopped OPTIMAL, its safe bound is
+ * (D_j - Delta_j) / v_j, with D_j its dual objective and
+ * Delta_j = eps (1 + |c_j'x~| + |D_j|): a lower bound on x_var if v_j > 0, an
+ * upper bound if v_j < 0.  lo / hi (n host doubles, written) start as the base
+ * bounds; a bound is replaced only if the new value improves it by more than
+ * min_improve (the experiments use eps = 1e-8 with pdlpb_options.dual_tol =
+ * 1e-8, and min_improve = 1e-4).  LPs are applied in batch order, each
+ * compared with the running value.  *n_changed (may be NULL) counts replacements;
+ * *infeasible (may be NULL) is 1 if some OBJ_UNIT LP stopped
+ * PDLPB_STATUS_PRIMAL_INFEASIBLE, i.e. the shared feasible set is empty.
+ * LPs that hit the iteration limit or failed give no bound.  Other change
+ * kinds are ignored.  EINVAL: NULL lo/hi, eps or min_improve negative or not
+ * finite.  ESTATE before pdlpb_solve.
+ */
+int pdlpb_obbt_tighten(pdlpb_ctx* ctx, double eps, double min_improve, double* lo, double* hi,
+                       int32_t* n_changed, int32_t* infeasible);
+
+/*
+ * Strong-branching scores (Section 5.1) of the solved batch.  gain (B host
+ * doubles, may be NULL): for a SET_LO (up) or SET_HI (down) LP that stopped
+ * OPTIMAL, max(c'x~ - parent_obj, 0); +inf if it stopped primal infeasible or
+ * its change crossed the variable's bounds; NaN otherwise and for other change
+ * kinds.  score (B host doubles, may be NULL): for each such LP, the score of
+ * its variable, (1 - mu) min(g_down, g_up) + mu max(g_down, g_up) (+inf if
+ * either gain is), with g_down / g_up the gains of the first SET_HI / SET_LO
+ * LP on that variable in batch order; NaN if either gain is NaN or the
+ * variable has no opposite branch in the batch.  mu = 1/6 is the weight of the
+ * scoring rule the paper cites.  EINVAL: parent_obj not finite, mu outside
+ * [0, 1].  ESTATE before pdlpb_solve.
+ */
+int pdlpb_branch_scores(pdlpb_ctx* ctx, double parent_obj, double mu, double* gain, double* score);
 
 /*
  * Serving: continuous batching of LPs on one resident matrix.

@@ -289,6 +289,7 @@ class Options:
     cross_sign: float = -1.0
     pw_ratio: str = "dy/dx"
     infeas_tol: Optional[float] = None   # eps of the infeasibility tests; None: tol; 0: off
+    dual_tol: Optional[float] = None     # eps of the dual-feasibility test; None: tol
 
 
 @dataclass
@@ -307,6 +308,15 @@ class Result:
     @property
     def obj(self) -> float:
         return self.kkt.obj if self.kkt is not None else float("nan")
+
+
+def _converged(kk: KKT, opt: "Options") -> bool:
+    """eq:stopping with one epsilon for the gap and primal tests and another
+    for the dual-feasibility test.  The bound-tightening experiments (Section 6,
+    OBBT results) check dual feasibility more strictly than the rest; by
+    default the two are equal, and then this is max(gap, primal, dual) <= tol."""
+    eps_d = opt.tol if opt.dual_tol is None else opt.dual_tol
+    return kk.gap <= opt.tol and kk.primal <= opt.tol and kk.dual <= eps_d
 
 
 def _infeasibility_eps(opt: "Options") -> float:
@@ -380,7 +390,7 @@ def solve(lp: LP, opt: Options = Options(), x_init=None, y_init=None,
         if (r is not None and not math.isfinite(r)) or (kk is not None and not math.isfinite(kk.rel)):
             return Result(NUMERICAL_ERROR, x_t, y_t, None, None, t + 1, restarts, w, eta,
                           kk or kkt(lp, x_t, y_t))
-        if kk is not None and kk.rel <= opt.tol:
+        if kk is not None and _converged(kk, opt):
             return Result(OPTIMAL, x_t, y_t, _halpern(k, x_t, x, x_a), _halpern(k, y_t, y, y_a),
                           t + 1, restarts, w, eta, kk)
         if full and eps_inf > 0.0:
@@ -460,7 +470,7 @@ def solve_batch_avg(lps: Sequence[LP], opt: Options = Options(), x_inits=None, y
             if (r is not None and not math.isfinite(r)) or (kk is not None and not math.isfinite(kk.rel)):
                 res[j] = Result(NUMERICAL_ERROR, x_t, y_t, None, None, t + 1, s["restarts"], s["w"],
                                 s["eta"], kk or kkt(lps[j], x_t, y_t))
-            elif kk is not None and kk.rel <= opt.tol:
+            elif kk is not None and _converged(kk, opt):
                 res[j] = Result(OPTIMAL, x_t, y_t, hx(), hy(), t + 1, s["restarts"], s["w"], s["eta"], kk)
             elif full and eps_inf > 0.0 and _infeasible_status(
                     infeasibility(lps[j], s["x"], s["y"], x_t, y_t, eps_inf)):

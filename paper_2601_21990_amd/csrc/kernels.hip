@@ -550,7 +550,7 @@ __global__ __launch_bounds__(1024) void k_control(ControlArgs a) {
         int32_t status = PDLPB_STATUS_RUNNING;
         if ((resid_here && !isfinite(r)) || (full_here && !isfinite(rel))) {
             status = PDLPB_STATUS_NUMERICAL_ERROR;
-        } else if (full_here && rel <= tol) {
+        } else if (full_here && gap <= tol && pri <= tol && dua <= (a.dual_tol < 0.0 ? tol : a.dual_tol)) {
             status = PDLPB_STATUS_OPTIMAL;
         } else if (infeas) {
             status = infeas;
@@ -559,6 +559,7 @@ __global__ __launch_bounds__(1024) void k_control(ControlArgs a) {
         }
         cl.kkt[0] = gap; cl.kkt[1] = pri; cl.kkt[2] = dua; cl.kkt[3] = rel;
         cl.obj = cx;
+        cl.dobj = -phis;
         if (status != PDLPB_STATUS_RUNNING) {
             const int32_t t_last = t < st.t_end ? t : st.t_end;
             cl.status = status;

@@ -101,6 +101,7 @@ struct pdlpb_ctx {
     bool solved = false;
     std::vector<SlotCtl> h_ctl;
     std::vector<int32_t> h_rlog;
+    std::vector<pdlpb_delta> h_delta;   // the batch's changes, by LP
 
     // captured blocks of C iterations, one per launch shape (live column bound)
     std::vector<std::pair<int32_t, hipGraphExec_t>> graphs;
@@ -403,6 +404,7 @@ ControlArgs control_args(pdlpb_ctx* x, int32_t it, int32_t full, int32_t advance
     a.beta_s = x->opt.beta_sufficient; a.beta_n = x->opt.beta_necessary;
     a.beta_a = x->opt.beta_artificial; a.theta = x->opt.theta; a.cross_sign = x->opt.cross_sign;
     a.infeas_tol = x->opt.infeas_tol;   // < 0: the stopping tolerance (resolved on the device)
+    a.dual_tol = x->opt.dual_tol;       // < 0: the stopping tolerance (resolved on the device)
     a.admit = admit;
     return a;
 }
@@ -798,6 +800,7 @@ void pdlpb_default_options(pdlpb_options* o) {
     o->step_size = 0.0;
     o->cross_sign = -1.0;
     o->infeas_tol = -1.0;
+    o->dual_tol = -1.0;
     o->pw_ratio = 0;
     o->device = 0;
     o->stream = nullptr;
@@ -840,6 +843,7 @@ int pdlpb_create(pdlpb_ctx** out, int32_t m, int32_t n, int64_t nnz, const int64
     if (!(o.step_size >= 0.0) || !std::isfinite(o.step_size)) return bad("step_size must be >= 0");
     if (o.cross_sign != -1.0 && o.cross_sign != 1.0) return bad("cross_sign must be -1 or +1");
     if (std::isnan(o.infeas_tol) || !std::isfinite(o.infeas_tol)) return bad("infeas_tol must be finite");
+    if (!std::isfinite(o.dual_tol)) return bad("dual_tol must be finite");
     if (o.max_batch < 1 || o.max_batch > MAX_BATCH) return bad("max_batch must be in [1, 4096]");
     if (o.restart_scope == PDLPB_RESTART_BATCH_AVG && o.max_batch > 1024) o.max_batch = 1024;
     if (o.tile_lanes != 0 && (o.tile_lanes < 1 || o.tile_lanes > 64 ||
@@ -1028,6 +1032,7 @@ int pdlpb_set_batch(pdlpb_ctx* x, int32_t B, const pdlpb_delta* deltas, const do
         cl.status = status;
         for (double& v : cl.kkt) v = NAN;
         cl.obj = NAN;
+        cl.dobj = NAN;
         if (status == PDLPB_STATUS_RUNNING) {   // running LPs fill slots [0, n_run0) in LP order
             h_key.push_back(key);
             h_tau.push_back(x->eta / w);
@@ -1052,6 +1057,7 @@ int pdlpb_set_batch(pdlpb_ctx* x, int32_t B, const pdlpb_delta* deltas, const do
     x->B = B;
     x->ld = ld;
     x->n_run0 = n_run0;
+    x->h_delta = d;
     x->batch_set = true;
     x->solved = false;
 
@@ -1174,6 +1180,90 @@ int pdlpb_get_batch(pdlpb_ctx* x, double* X, double* Y, int32_t* status, double*
     if (X) rc = copy_results(x, 0, 0, B, X, mem);
     if (!rc && Y) rc = copy_results(x, 2, 0, B, Y, mem);
     return rc;
+}
+
+int pdlpb_get_dual_objective(pdlpb_ctx* x, double* dual_obj) {
+    if (!x) return PDLPB_EINVAL;
+    if (!x->batch_set) return x->fail(PDLPB_ESTATE, "no batch set");
+    if (!x->solved) return x->fail(PDLPB_ESTATE, "batch not solved yet");
+    if (!dual_obj) return x->fail(PDLPB_EINVAL, "dual_obj is NULL");
+    for (int32_t j = 0; j < x->B; ++j) dual_obj[j] = x->h_ctl[j].dobj;
+    return PDLPB_OK;
+}
+
+int pdlpb_obbt_tighten(pdlpb_ctx* x, double eps, double min_improve, double* lo, double* hi,
+                       int32_t* n_changed, int32_t* infeasible) {
+    if (!x) return PDLPB_EINVAL;
+    if (!x->batch_set) return x->fail(PDLPB_ESTATE, "no batch set");
+    if (!x->solved) return x->fail(PDLPB_ESTATE, "batch not solved yet");
+    if (!lo || !hi) return x->fail(PDLPB_EINVAL, "lo or hi is NULL");
+    if (!(eps >= 0.0) || !std::isfinite(eps)) return x->fail(PDLPB_EINVAL, "eps must be finite and >= 0");
+    if (!(min_improve >= 0.0) || !std::isfinite(min_improve))
+        return x->fail(PDLPB_EINVAL, "min_improve must be finite and >= 0");
+    std::memcpy(lo, x->h_xl.data(), sizeof(double) * x->n);
+    std::memcpy(hi, x->h_xu.data(), sizeof(double) * x->n);
+    int32_t changed = 0, infeas = 0;
+    for (int32_t j = 0; j < x->B; ++j) {
+        const pdlpb_delta& q = x->h_delta[j];
+        const SlotCtl& cl = x->h_ctl[j];
+        if (q.kind != PDLPB_OBJ_UNIT || q.value == 0.0) continue;
+        if (cl.status == PDLPB_STATUS_PRIMAL_INFEASIBLE) {   // the shared feasible set is empty
+            infeas = 1;
+            continue;
+        }
+        if (cl.status != PDLPB_STATUS_OPTIMAL || !std::isfinite(cl.dobj)) continue;
+        // weak duality: value * x_var >= dobj; shift by Delta before dividing by value
+        const double delta = eps * (1.0 + std::fabs(cl.obj) + std::fabs(cl.dobj));
+        const double b = (cl.dobj - delta) / q.value;
+        const int32_t v = q.var;
+        if (q.value > 0.0 && b > lo[v] + min_improve) {
+            lo[v] = b;
+            ++changed;
+        } else if (q.value < 0.0 && b < hi[v] - min_improve) {
+            hi[v] = b;
+            ++changed;
+        }
+    }
+    if (n_changed) *n_changed = changed;
+    if (infeasible) *infeasible = infeas;
+    return PDLPB_OK;
+}
+
+int pdlpb_branch_scores(pdlpb_ctx* x, double parent_obj, double mu, double* gain, double* score) {
+    if (!x) return PDLPB_EINVAL;
+    if (!x->batch_set) return x->fail(PDLPB_ESTATE, "no batch set");
+    if (!x->solved) return x->fail(PDLPB_ESTATE, "batch not solved yet");
+    if (!std::isfinite(parent_obj)) return x->fail(PDLPB_EINVAL, "parent_obj must be finite");
+    if (!(mu >= 0.0 && mu <= 1.0)) return x->fail(PDLPB_EINVAL, "mu must lie in [0, 1]");
+    const int32_t B = x->B;
+    std::vector<double> gn(B, NAN);
+    std::unordered_map<int32_t, int32_t> first_up, first_down;
+    for (int32_t j = 0; j < B; ++j) {
+        const pdlpb_delta& q = x->h_delta[j];
+        if (q.kind != PDLPB_SET_LO && q.kind != PDLPB_SET_HI) continue;
+        const SlotCtl& cl = x->h_ctl[j];
+        if (cl.status == PDLPB_STATUS_PRIMAL_INFEASIBLE || cl.status == PDLPB_STATUS_INFEASIBLE_BOUNDS)
+            gn[j] = INFINITY;
+        else if (cl.status == PDLPB_STATUS_OPTIMAL)
+            gn[j] = std::max(cl.obj - parent_obj, 0.0);
+        auto& first = q.kind == PDLPB_SET_LO ? first_up : first_down;
+        first.emplace(q.var, j);
+    }
+    for (int32_t j = 0; j < B; ++j) {
+        if (gain) gain[j] = gn[j];
+        if (!score) continue;
+        score[j] = NAN;
+        const pdlpb_delta& q = x->h_delta[j];
+        if (q.kind != PDLPB_SET_LO && q.kind != PDLPB_SET_HI) continue;
+        const auto& other = q.kind == PDLPB_SET_LO ? first_down : first_up;
+        auto it = other.find(q.var);
+        if (it == other.end()) continue;
+        const double a = gn[j], b = gn[it->second];
+        if (std::isnan(a) || std::isnan(b)) continue;
+        const double mn = std::min(a, b), mx = std::max(a, b);
+        score[j] = std::isinf(mx) ? INFINITY : (1.0 - mu) * mn + mu * mx;
+    }
+    return PDLPB_OK;
 }
 
 int pdlpb_get_trace(pdlpb_ctx* x, int32_t j, double* x_iter, double* y_iter, double* w,
@@ -1299,6 +1389,7 @@ int pdlpb_submit(pdlpb_ctx* x, int32_t count, const pdlpb_delta* deltas, int32_t
             cl.status = status;
             for (double& v : cl.kkt) v = NAN;
             cl.obj = NAN;
+            cl.dobj = NAN;
             cl.tol = tol;
             HIP_TRY(x, hipMemcpyAsync(x->ctl + row, &cl, sizeof(SlotCtl), hipMemcpyHostToDevice,
                                       x->stream));
@@ -1369,6 +1460,7 @@ int serve_admit(pdlpb_ctx* x) {
         cl.status = PDLPB_STATUS_RUNNING;
         for (double& v : cl.kkt) v = NAN;
         cl.obj = NAN;
+        cl.dobj = NAN;
         cl.tol = p.tol;
         x->h_adm_ctl[j] = cl;
     }

@@ -50,6 +50,7 @@ struct SlotCtl {
     double  r_prev;    // previous evaluated residual of the cycle; < 0 when none
     double  kkt[4];    // gap, primal, dual, max at the LP's last evaluation
     double  obj;       // c_j' x~
+    double  dobj;      // dual objective -phi_box(r~) - phi_[l,u](y~) (eq:main_lp, dual side)
     int32_t status;    // PDLPB_STATUS_*
     int32_t iters;     // applications of T
     int32_t restarts;  // number of restarts
@@ -156,6 +157,7 @@ struct ControlArgs {
     int32_t pw_literal;      // primal weight ratio as printed
     double beta_s, beta_n, beta_a, theta, cross_sign;
     double infeas_tol;       // eps of the infeasibility tests; < 0: the stopping tolerance; 0: off
+    double dual_tol;         // eps of the dual-feasibility test; < 0: the stopping tolerance
 };
 
 // ---- launchers (kernels.hip) ---------------------------------------------------

@@ -33,7 +33,8 @@ STATUS_NAMES = {0: "RUNNING", 1: "OPTIMAL", 2: "ITERATION_LIMIT", 3: "INFEASIBLE
                 7: "DUAL_INFEASIBLE"}
 
 EXPORTED = ["pdlpb_default_options", "pdlpb_create", "pdlpb_set_batch", "pdlpb_solve",
-            "pdlpb_get", "pdlpb_get_batch", "pdlpb_get_trace", "pdlpb_set_tile",
+            "pdlpb_get", "pdlpb_get_batch", "pdlpb_get_trace", "pdlpb_get_dual_objective",
+            "pdlpb_obbt_tighten", "pdlpb_branch_scores", "pdlpb_set_tile",
             "pdlpb_get_step_size", "pdlpb_set_base_warm", "pdlpb_serve_begin", "pdlpb_submit",
             "pdlpb_serve_launch", "pdlpb_serve_wait", "pdlpb_poll", "pdlpb_result",
             "pdlpb_release",
@@ -55,7 +56,8 @@ class Options(C.Structure):
                 ("pw_ratio", C.c_int32), ("device", C.c_int32), ("stream", C.c_void_p),
                 ("max_batch", C.c_int32), ("use_graphs", C.c_int32),
                 ("tile_lanes", C.c_int32), ("tile_vec", C.c_int32),
-                ("autotune", C.c_int32), ("reserved", C.c_int32 * 7)]
+                ("autotune", C.c_int32), ("reserved_pad", C.c_int32),
+                ("dual_tol", C.c_double), ("reserved", C.c_int32 * 4)]
 
 
 class PdlpbError(RuntimeError):
@@ -81,6 +83,9 @@ def _load():
         "pdlpb_get": (C.c_int, [P, i32, P, P, i32p, dp, dp, i64p, i32]),
         "pdlpb_get_batch": (C.c_int, [P, P, P, i32p, dp, dp, i64p, i32]),
         "pdlpb_get_trace": (C.c_int, [P, i32, dp, dp, dp, i32p, i32p, i32]),
+        "pdlpb_get_dual_objective": (C.c_int, [P, dp]),
+        "pdlpb_obbt_tighten": (C.c_int, [P, d, d, dp, dp, i32p, i32p]),
+        "pdlpb_branch_scores": (C.c_int, [P, d, d, dp, dp]),
         "pdlpb_set_tile": (C.c_int, [P, i32, i32]),
         "pdlpb_set_base_warm": (C.c_int, [P, P, P, d, i32]),
         "pdlpb_serve_begin": (C.c_int, [P, i32]),
@@ -114,6 +119,9 @@ pdlpb_solve = lib.pdlpb_solve
 pdlpb_get = lib.pdlpb_get
 pdlpb_get_batch = lib.pdlpb_get_batch
 pdlpb_get_trace = lib.pdlpb_get_trace
+pdlpb_get_dual_objective = lib.pdlpb_get_dual_objective
+pdlpb_obbt_tighten = lib.pdlpb_obbt_tighten
+pdlpb_branch_scores = lib.pdlpb_branch_scores
 pdlpb_set_tile = lib.pdlpb_set_tile
 pdlpb_set_base_warm = lib.pdlpb_set_base_warm
 pdlpb_serve_begin = lib.pdlpb_serve_begin
@@ -286,6 +294,30 @@ class Context:
                                         C.byref(nr), log, log_cap))
         k = min(nr.value, log_cap)
         return dict(x_iter=x, y_iter=y, w=w.value, restarts=nr.value, restart_log=list(log[:k]))
+
+    def dual_objective(self) -> np.ndarray:
+        d = np.empty(self.B)
+        self._check(lib.pdlpb_get_dual_objective(self._h, d.ctypes.data_as(C.POINTER(C.c_double))))
+        return d
+
+    def obbt_tighten(self, eps: float = 1e-8, min_improve: float = 1e-4):
+        lo = np.empty(self.n)
+        hi = np.empty(self.n)
+        nch = C.c_int32()
+        inf = C.c_int32()
+        self._check(lib.pdlpb_obbt_tighten(self._h, float(eps), float(min_improve),
+                                           lo.ctypes.data_as(C.POINTER(C.c_double)),
+                                           hi.ctypes.data_as(C.POINTER(C.c_double)),
+                                           C.byref(nch), C.byref(inf)))
+        return dict(lo=lo, hi=hi, changed=nch.value, infeasible=bool(inf.value))
+
+    def branch_scores(self, parent_obj: float, mu: float = 1.0 / 6.0):
+        gain = np.empty(self.B)
+        score = np.empty(self.B)
+        self._check(lib.pdlpb_branch_scores(self._h, float(parent_obj), float(mu),
+                                            gain.ctypes.data_as(C.POINTER(C.c_double)),
+                                            score.ctypes.data_as(C.POINTER(C.c_double))))
+        return dict(gain=gain, score=score)
 
     # ---- serving (continuous batching) ----
     def set_base_warm(self, x, y, w: float):

@@ -37,8 +37,28 @@ def test_options_layout_matches_header():
     assert (o.eval_every, o.beta_sufficient, o.beta_necessary, o.beta_artificial, o.theta) == \
         (64, 0.2, 0.8, 0.36, 0.5)
     assert o.cross_sign == -1.0 and o.use_graphs == 1 and o.max_batch == 4096
-    assert o.infeas_tol == -1.0
+    assert o.infeas_tol == -1.0 and o.dual_tol == -1.0
     assert P.C.sizeof(P.Delta) == 16
+
+
+def test_options_offsets_match_the_c_compiler(tmp_path):
+    """The ctypes mirror of pdlpb_options has the C compiler's field offsets."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    names = [f[0] for f in P.Options._fields_]
+    src = tmp_path / "off.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "pdlpb.h"\nint main(void){\n'
+                   + "".join(f'printf("%zu\\n", offsetof(pdlpb_options, {n}));\n' for n in names)
+                   + 'printf("%zu\\n", sizeof(pdlpb_options));\nreturn 0;}\n')
+    exe = tmp_path / "off"
+    inc = os.path.join(os.path.dirname(__file__), "..", "include")
+    subprocess.run(["gcc", "-std=c99", "-I", inc, str(src), "-o", str(exe)], check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], check=True, capture_output=True,
+                                          text=True).stdout.split()]
+    want = [getattr(P.Options, n).offset for n in names] + [P.C.sizeof(P.Options)]
+    assert got == want
 
 
 def _ctx(**over):
@@ -79,6 +99,7 @@ def test_create_rejects_malformed_input(over, msg):
     (dict(tile_vec=3), "tile_vec"),
     (dict(step_size=-1.0), "step_size"),
     (dict(infeas_tol=float("nan")), "infeas_tol"),
+    (dict(dual_tol=float("inf")), "dual_tol"),
 ])
 def test_create_rejects_bad_options(opt, msg):
     with pytest.raises(P.PdlpbError) as e:

@@ -193,6 +193,20 @@ def make_cfg5(base: int = 0, m: int = 200000, n: int = 500000) -> LPInstance:
     return _finish(rng, f"cfg5_{base}", m, n, rows, cols, vals, x0, senses, 0.0, 10.0)
 
 
+def make_packing(rep: int = 0, m: int = 200, n: int = 500, k: int = 5,
+                 box=(0.0, 10.0)) -> LPInstance:
+    """Packing rows with a finite box: k nonzeros per column drawn U[0.5, 1.5],
+    all rows <=, witness x0 ~ U[0, 2].  Row capacities sit well below what the
+    box allows, so maximising a variable meets its rows before its upper bound
+    (bound tightening moves bounds on this family)."""
+    rng = np.random.default_rng(seed_for(6, rep))
+    rows, cols = _k_per_column(rng, m, n, k)
+    vals = rng.uniform(0.5, 1.5, size=rows.size)
+    x0 = rng.uniform(0.0, 2.0, size=n)
+    senses = np.full(m, ord("L"), dtype=np.uint8)
+    return _finish(rng, "packing", m, n, rows, cols, vals, x0, senses, box[0], box[1])
+
+
 # ---------------------------------------------------------------------------
 # batch specifications
 # ---------------------------------------------------------------------------
