@@ -103,12 +103,15 @@ def run_sweep(args):
     widths = [int(b) for b in args.sweep_b.split(",")]
     points = []
     tiles = [tuple(int(v) for v in t.split("x")) for t in args.sweep_tiles.split(",")]
+    caps = [int(b) for b in args.sweep_blocks.split(",")]
     eta = None
-    for prec, s_it, s_val, name in ((P.MIXED32, 4, 4, "fp32"), (P.FP64, 8, 8, "fp64")):
+    for (prec, s_it, s_val, name), cap in ((p, c) for p in (
+            (P.MIXED32, 4, 4, "fp32"), (P.FP64, 8, 8, "fp64")) for c in caps):
         if name not in args.sweep_prec.split(","):
             continue
         kw = {} if eta is None else {"step_size": eta}
-        ctx = P.Context.from_instance(inst, device=0, precision=prec, use_graphs=0, **kw)
+        ctx = P.Context.from_instance(inst, device=0, precision=prec, use_graphs=0,
+                                      max_blocks=cap, **kw)
         eta = ctx.step_size[0]
         for B in widths:
             D = obbt_deltas(choose_vars(n, max(B // 2, 1), seed=B))[:B]
@@ -126,10 +129,11 @@ def run_sweep(args):
                     q = fused_bytes(kind, m, n, nnz, B, s_val, s_it)
                     gbs = q / (avg * 1e-3) / 1e9
                     points.append({"precision": name, "B": B, "tile": f"{lanes}x{vec}",
+                                   "max_blocks": cap,
                                    "kernel": kname, "avg_us": round(avg * 1e3, 2),
                                    "bytes": int(q), "GBps": round(gbs, 1),
                                    "frac": round(gbs / HBM_PEAK_GBS, 4)})
-                    log(f"{name} B={B:4d} tile={lanes}x{vec} {kname:6s}: {avg*1e3:9.1f} us "
+                    log(f"{name} B={B:4d} tile={lanes}x{vec} cap={cap:5d} {kname:6s}: {avg*1e3:9.1f} us "
                         f"{q/1e6:9.1f} MB {gbs:8.1f} GB/s")
         ctx.close()
     best = max(points, key=lambda p: p["GBps"])
@@ -249,6 +253,8 @@ def main():
     ap.add_argument("--sweep-iters", type=int, default=65)
     ap.add_argument("--sweep-tiles", default="0x0", help="lanes x vec per point; 0x0 = automatic")
     ap.add_argument("--sweep-prec", default="fp32,fp64")
+    ap.add_argument("--sweep-blocks", default="0",
+                    help="workgroup caps of the step launches; 0 = the library default")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)

@@ -114,7 +114,9 @@ typedef struct pdlpb_options {
     double  dual_tol;         /* eps of the dual-feasibility test of eq:stopping: < 0 (default -1) uses the
                                  stopping tolerance; >= 0 as given.  The bound-tightening experiments of
                                  Section 6 check dual feasibility at 1e-8 before trusting a dual bound */
-    int32_t reserved[4];
+    int32_t max_blocks;       /* cap on the workgroups of one step launch; their waves loop over the rows.
+                                 0 (default): 2048 (eight 4-wave workgroups per compute unit) */
+    int32_t reserved[3];
 } pdlpb_options;
 
 typedef struct pdlpb_ctx pdlpb_ctx;   /* opaque; owns all device memory of one base matrix and its batch */

@@ -165,47 +165,72 @@ __global__ __launch_bounds__(256) void k_primal(StepArgs<T> a) {
     constexpr int RPW = 64 / G;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const int32_t row = (blockIdx.x * a.wpb + wave) * RPW + lane / G;
     const int32_t s0 = blockIdx.y * (G * VEC) + (lane % G) * VEC;
     const int32_t ncols = min(a.ncols, a.g->n_cols);
-    if (row >= a.rows || s0 >= ncols) return;
+    if (s0 >= ncols) return;
     const int32_t t = a.g->t0 + a.it;
 
-    // operands of the epilogue, fetched before the product so their latency overlaps it
-    SlotKey key[VEC];
-    double tau[VEC];
-    T zb[VEC], z0[VEC];
+    // per-slot operands: a lane keeps its slots for every row it visits
+    bool live[VEC], last[VEC];
+    int32_t varkind[VEC], kk[VEC];
+    T tau[VEC];
+    bool any = false;
 #pragma unroll
     for (int v = 0; v < VEC; ++v) {
+        live[v] = false;
+        last[v] = false;
+        varkind[v] = VAR_NONE;
+        kk[v] = 0;
+        tau[v] = T(0);
         if (s0 + v < ncols) {
-            const size_t e = (size_t)row * a.ld + s0 + v;
-            key[v] = a.sl.key[s0 + v];
-            tau[v] = a.sl.tau[s0 + v];
-            zb[v] = a.Z[e];
-            z0[v] = a.Z0[e];
+            const SlotKey key = a.sl.key[s0 + v];
+            live[v] = (key.flags & SLOT_ACTIVE) && t <= key.t_end &&
+                      (!a.admit || (key.flags & SLOT_NEW));
+            last[v] = (t == key.t_end);
+            varkind[v] = key.varkind;
+            kk[v] = t - key.t_anchor;
+            tau[v] = T(a.sl.tau[s0 + v]);
         }
+        any = any || live[v];
     }
-    const double cb = a.c[row], lb = a.lo[row], hb = a.hi[row];
+    if (!any) return;
+    const bool keep = a.eval != 0;
 
-    T acc[VEC];
-    row_product<T, VEC>(a.rp, a.ci, a.av, a.G, row, a.ld, s0, acc);
+    // waves stride over row groups of RPW rows; the grid may hold fewer waves than groups
+    const int32_t wstride = (int32_t)gridDim.x * a.wpb;
+    for (int32_t rw = (int32_t)blockIdx.x * a.wpb + wave; rw * RPW < a.rows; rw += wstride) {
+        const int32_t row = rw * RPW + lane / G;
+        if (row >= a.rows) continue;
+        // operands of the epilogue, fetched before the product so their latency overlaps it
+        T zb[VEC], z0[VEC];
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) {
+            if (s0 + v < ncols) {
+                const size_t e = (size_t)row * a.ld + s0 + v;
+                zb[v] = a.Z[e];
+                z0[v] = a.Z0[e];
+            }
+        }
+        const double cb = a.c[row], lb = a.lo[row], hb = a.hi[row];
+
+        T acc[VEC];
+        row_product<T, VEC>(a.rp, a.ci, a.av, a.G, row, a.ld, s0, acc);
 
 #pragma unroll
-    for (int v = 0; v < VEC; ++v) {
-        const int32_t s = s0 + v;
-        if (s >= ncols) break;
-        if (!(key[v].flags & SLOT_ACTIVE) || t > key[v].t_end) continue;
-        if (a.admit && !(key[v].flags & SLOT_NEW)) continue;
-        const size_t e = (size_t)row * a.ld + s;
-        const VarData d = var_data(key[v].varkind, a.sl.dval, s, row, cb, lb, hb);
-        const int32_t k = t - key[v].t_anchor;
-        const T x0 = z0[v];
-        const T xk = (k == 0) ? x0 : T(double(k) / double(k + 1)) * zb[v] + x0 / T(k + 1);
-        const T xt = clampt<T>(xk - T(tau[v]) * (T(d.c) + acc[v]), T(d.lo), T(d.hi));
-        a.Z[e] = T(2) * xt - xk;
-        if (a.eval || t == key[v].t_end) {
-            a.Zt[e] = xt;
-            a.DZ[e] = xt - xk;
+        for (int v = 0; v < VEC; ++v) {
+            const int32_t s = s0 + v;
+            if (!live[v]) continue;
+            const size_t e = (size_t)row * a.ld + s;
+            const VarData d = var_data(varkind[v], a.sl.dval, s, row, cb, lb, hb);
+            const int32_t k = kk[v];
+            const T x0 = z0[v];
+            const T xk = (k == 0) ? x0 : T(double(k) / double(k + 1)) * zb[v] + x0 / T(k + 1);
+            const T xt = clampt<T>(xk - tau[v] * (T(d.c) + acc[v]), T(d.lo), T(d.hi));
+            a.Z[e] = T(2) * xt - xk;
+            if (keep || last[v]) {
+                a.Zt[e] = xt;
+                a.DZ[e] = xt - xk;
+            }
         }
     }
 }
@@ -221,47 +246,68 @@ __global__ __launch_bounds__(256) void k_dual(StepArgs<T> a) {
     constexpr int RPW = 64 / G;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const int32_t row = (blockIdx.x * a.wpb + wave) * RPW + lane / G;
     const int32_t s0 = blockIdx.y * (G * VEC) + (lane % G) * VEC;
     const int32_t ncols = min(a.ncols, a.g->n_cols);
-    if (row >= a.rows || s0 >= ncols) return;
+    if (s0 >= ncols) return;
     const int32_t t = a.g->t0 + a.it;
 
-    SlotKey key[VEC];
-    double sig[VEC];
-    T zy[VEC], z0[VEC];
+    bool live[VEC], last[VEC];
+    T sig[VEC], wa[VEC], wb[VEC];
+    bool any = false;
 #pragma unroll
     for (int v = 0; v < VEC; ++v) {
+        live[v] = false;
+        last[v] = false;
+        sig[v] = T(1);
+        wa[v] = T(0);
+        wb[v] = T(1);
         if (s0 + v < ncols) {
-            const size_t e = (size_t)row * a.ld + s0 + v;
-            key[v] = a.sl.key[s0 + v];
-            sig[v] = a.sl.sigma[s0 + v];
-            zy[v] = a.Z[e];
-            z0[v] = a.Z0[e];
+            const SlotKey key = a.sl.key[s0 + v];
+            live[v] = (key.flags & SLOT_ACTIVE) && t <= key.t_end &&
+                      (!a.admit || (key.flags & SLOT_NEW));
+            last[v] = (t == key.t_end);
+            const int32_t k = t - key.t_anchor;
+            sig[v] = T(a.sl.sigma[s0 + v]);
+            wa[v] = T(halpern_a(k));
+            wb[v] = T(k + 2);
         }
+        any = any || live[v];
     }
-    const T l = T(a.lo[row]), u = T(a.hi[row]);
+    if (!any) return;
+    const bool keep = a.eval != 0;
 
-    T acc[VEC];
-    row_product<T, VEC>(a.rp, a.ci, a.av, a.G, row, a.ld, s0, acc);
+    const int32_t wstride = (int32_t)gridDim.x * a.wpb;
+    for (int32_t rw = (int32_t)blockIdx.x * a.wpb + wave; rw * RPW < a.rows; rw += wstride) {
+        const int32_t row = rw * RPW + lane / G;
+        if (row >= a.rows) continue;
+        T zy[VEC], z0[VEC];
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) {
+            if (s0 + v < ncols) {
+                const size_t e = (size_t)row * a.ld + s0 + v;
+                zy[v] = a.Z[e];
+                z0[v] = a.Z0[e];
+            }
+        }
+        const T l = T(a.lo[row]), u = T(a.hi[row]);
+
+        T acc[VEC];
+        row_product<T, VEC>(a.rp, a.ci, a.av, a.G, row, a.ld, s0, acc);
 
 #pragma unroll
-    for (int v = 0; v < VEC; ++v) {
-        const int32_t s = s0 + v;
-        if (s >= ncols) break;
-        if (!(key[v].flags & SLOT_ACTIVE) || t > key[v].t_end) continue;
-        if (a.admit && !(key[v].flags & SLOT_NEW)) continue;
-        const size_t e = (size_t)row * a.ld + s;
-        const int32_t k = t - key[v].t_anchor;
-        const T yk = zy[v];
-        const T y0 = z0[v];
-        const T sg = T(sig[v]);
-        const T q = yk / sg + acc[v];
-        const T yt = sg * (q - clampt<T>(q, l, u));
-        a.Z[e] = T(halpern_a(k)) * (T(2) * yt - yk) + y0 / T(k + 2);
-        if (a.eval || t == key[v].t_end) {
-            a.Zt[e] = yt;
-            a.DZ[e] = yt - yk;
+        for (int v = 0; v < VEC; ++v) {
+            if (!live[v]) continue;
+            const size_t e = (size_t)row * a.ld + s0 + v;
+            const T yk = zy[v];
+            const T y0 = z0[v];
+            const T sg = sig[v];
+            const T q = yk / sg + acc[v];
+            const T yt = sg * (q - clampt<T>(q, l, u));
+            a.Z[e] = wa[v] * (T(2) * yt - yk) + y0 / wb[v];
+            if (keep || last[v]) {
+                a.Zt[e] = yt;
+                a.DZ[e] = yt - yk;
+            }
         }
     }
 }
@@ -945,8 +991,14 @@ template <typename T, int G, int VEC, bool PRIMAL>
 hipError_t launch_step_gv(const StepArgs<T>& a, hipStream_t s) {
     constexpr int RPW = 64 / G;
     const int rows_per_block = a.wpb * RPW;
-    const dim3 grid((a.rows + rows_per_block - 1) / rows_per_block,
-                    (a.ncols + G * VEC - 1) / (G * VEC));
+    const uint32_t gy = (uint32_t)((a.ncols + G * VEC - 1) / (G * VEC));
+    uint32_t gx = (uint32_t)((a.rows + rows_per_block - 1) / rows_per_block);
+    if (a.max_blocks > 0 && gy > 0) {
+        // at most max_blocks workgroups in all; their waves loop over the row groups
+        const uint32_t cap = (uint32_t)max(1, a.max_blocks / (int32_t)gy);
+        gx = min(gx, cap);
+    }
+    const dim3 grid(gx, gy);
     const dim3 block(64 * a.wpb);
     if (grid.x == 0 || grid.y == 0) return hipSuccess;
     if (PRIMAL)

@@ -44,7 +44,10 @@ int32_t eval_rows_per_wave(int32_t rows) {
 struct Tile {
     int lanes = 64;     // lanes per row group
     int vec = 1;        // consecutive LPs per lane
+    int blocks = 0;     // workgroup cap of the launch (0: one wave per row group)
 };
+
+constexpr int32_t DEFAULT_MAX_BLOCKS = 2048;
 
 struct pdlpb_ctx {
     std::string err = "no error";
@@ -294,6 +297,7 @@ Tile heuristic_tile(const pdlpb_ctx* x, int32_t ncols) {
     Tile t;
     t.lanes = lanes;
     t.vec = vec;
+    t.blocks = x->opt.max_blocks > 0 ? x->opt.max_blocks : DEFAULT_MAX_BLOCKS;
     return t;
 }
 
@@ -321,6 +325,7 @@ std::vector<Tile> tile_candidates(const pdlpb_ctx* x, int32_t ncols) {
             Tile t;
             t.lanes = lanes;
             t.vec = vec;
+            t.blocks = x->opt.max_blocks > 0 ? x->opt.max_blocks : DEFAULT_MAX_BLOCKS;
             out.push_back(t);
         }
     return out;
@@ -347,6 +352,7 @@ StepArgs<T> step_args(pdlpb_ctx* x, bool primal, int32_t it, int32_t eval, int32
     a.ld = x->ld;
     a.ncols = x->live;
     a.wpb = x->wpb;
+    a.max_blocks = primal ? x->tp.blocks : x->td.blocks;
     if (primal) {
         a.G = b[4];   // Y
         a.Z = b[0]; a.Z0 = b[1]; a.Zt = b[2]; a.DZ = b[3];
@@ -844,6 +850,7 @@ int pdlpb_create(pdlpb_ctx** out, int32_t m, int32_t n, int64_t nnz, const int64
     if (o.cross_sign != -1.0 && o.cross_sign != 1.0) return bad("cross_sign must be -1 or +1");
     if (std::isnan(o.infeas_tol) || !std::isfinite(o.infeas_tol)) return bad("infeas_tol must be finite");
     if (!std::isfinite(o.dual_tol)) return bad("dual_tol must be finite");
+    if (o.max_blocks < 0) return bad("max_blocks must be >= 0");
     if (o.max_batch < 1 || o.max_batch > MAX_BATCH) return bad("max_batch must be in [1, 4096]");
     if (o.restart_scope == PDLPB_RESTART_BATCH_AVG && o.max_batch > 1024) o.max_batch = 1024;
     if (o.tile_lanes != 0 && (o.tile_lanes < 1 || o.tile_lanes > 64 ||

@@ -120,6 +120,7 @@ struct StepArgs {
     int32_t it;          // iteration index inside the block; global t = g->t0 + it
     int32_t eval;        // 1: every running LP writes z~ and its displacement
     int32_t admit;       // 1: only LPs flagged SLOT_NEW iterate (their first iteration)
+    int32_t max_blocks;  // > 0: cap on the workgroups of the launch (waves then loop over rows)
 };
 
 template <typename T>

@@ -57,7 +57,8 @@ class Options(C.Structure):
                 ("max_batch", C.c_int32), ("use_graphs", C.c_int32),
                 ("tile_lanes", C.c_int32), ("tile_vec", C.c_int32),
                 ("autotune", C.c_int32), ("reserved_pad", C.c_int32),
-                ("dual_tol", C.c_double), ("reserved", C.c_int32 * 4)]
+                ("dual_tol", C.c_double), ("max_blocks", C.c_int32),
+                ("reserved", C.c_int32 * 3)]
 
 
 class PdlpbError(RuntimeError):
