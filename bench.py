@@ -91,13 +91,17 @@ def _cpu_task(t):
 
 def run_sweep(args):
     """Fused product kernels on a large matrix (200k x 500k, 4 N(0,1) nonzeros per
-    column, the serving-stream family) at batch widths B and both precisions:
+    column, the serving-stream family; or the 20k x 50k bound-tightening matrix)
+    at batch widths B and both precisions:
     a fixed number of iterations per point, every launch bracketed by HIP events;
     achieved GB/s = compulsory bytes / average launch time (8 TB/s peak)."""
     import numpy as np
     import paper_2601_21990_amd.pdlpb as P
-    from workloads import make_cfg5, obbt_deltas, choose_vars
-    inst = make_cfg5(m=args.sweep_m, n=int(round(2.5 * args.sweep_m)))
+    from workloads import make_cfg3, make_cfg5, obbt_deltas, choose_vars
+    if args.sweep_matrix == "cfg3":
+        inst = make_cfg3()
+    else:
+        inst = make_cfg5(m=args.sweep_m, n=int(round(2.5 * args.sweep_m)))
     m, n, nnz = inst.m, inst.n, inst.nnz
     log(f"sweep instance m={m} n={n} nnz={nnz}")
     widths = [int(b) for b in args.sweep_b.split(",")]
@@ -133,13 +137,14 @@ def run_sweep(args):
                                    "kernel": kname, "avg_us": round(avg * 1e3, 2),
                                    "bytes": int(q), "GBps": round(gbs, 1),
                                    "frac": round(gbs / HBM_PEAK_GBS, 4)})
-                    log(f"{name} B={B:4d} tile={lanes}x{vec} cap={cap:5d} {kname:6s}: {avg*1e3:9.1f} us "
+                    log(f"{name} B={B:4d} tile={lanes}x{vec} cap={cap:5d} {kname:6s}: "
+                        f"{avg*1e3:9.1f} us "
                         f"{q/1e6:9.1f} MB {gbs:8.1f} GB/s")
         ctx.close()
     best = max(points, key=lambda p: p["GBps"])
     print(json.dumps({"metric": "SpMM HBM GB/s (fused product + PDHG step)", "value": best["GBps"],
                       "unit": "GB/s", "peak": HBM_PEAK_GBS, "config": {
-                          "workload": f"A {m}x{n}, nnz {nnz}, 4 N(0,1) nonzeros per column",
+                          "workload": f"A {m}x{n}, nnz {nnz}",
                           "iterations_per_point": args.sweep_iters}, "best": best,
                       "points": points}), flush=True)
 
@@ -182,7 +187,7 @@ def run_serve(args):
         inst = make_cfg5(base=b, m=m, n=n)
         ctx = P.Context.from_instance(inst, device=0, precision=prec, max_batch=args.serve_cols)
         ctx.set_batch(deltas([BASE], [0], [0.0]))
-        ctx.solve(tol=1e-6, max_iters=200000)
+        ctx.solve(tol=1e-5, max_iters=50000)
         root = ctx.get(0)
         w = ctx.get_trace(0)["w"]
         log(f"base {b}: m={m} n={n} root {P.STATUS_NAMES[root['status']]} iters={root['iters']}")
@@ -238,9 +243,136 @@ def run_serve(args):
                       "rates": lines}), flush=True)
 
 
+def run_obbt(args):
+    """Bound-tightening batch (Section 5.2) on the 20000 x 50000 family with 8
+    U[-1,1] nonzeros per column, rows of mixed sense and box [0,5]: 256 LPs
+    minimising and maximising 128 random variables, cold start.  The MIXED32
+    run (FP32 iterates and products, FP64 sums) is the measured one; an FP64
+    run of the same batch gives the objective difference per LP."""
+    import numpy as np
+    import torch
+    import paper_2601_21990_amd.pdlpb as P
+    from workloads import make_cfg3, obbt_deltas, choose_vars, seed_for
+    inst = make_cfg3()
+    D = obbt_deltas(choose_vars(inst.n, args.obbt_vars, seed_for(3, 0)))
+    B = len(D)
+    log(f"instance m={inst.m} n={inst.n} nnz={inst.nnz} B={B}")
+    dev = torch.device("cuda:0")
+    dD = torch.from_numpy(D.view(np.uint8).copy()).to(dev)
+    out = {}
+    for prec, name in ((P.MIXED32, "fp32"), (P.FP64, "fp64")):
+        ctx = P.Context.from_instance(inst, device=0, precision=prec)
+        X = torch.empty((B, inst.n), dtype=torch.float64, device=dev)
+        Y = torch.empty((B, inst.m), dtype=torch.float64, device=dev)
+        times = []
+        for rep in range(args.warmup + args.steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ctx.set_batch(dD, mem=P.MEM_DEVICE)
+            ctx.solve(tol=1e-4, max_iters=args.obbt_iters)
+            r = ctx.get_batch(X=X, Y=Y, mem=P.MEM_DEVICE)
+            torch.cuda.synchronize()
+            if rep >= args.warmup:
+                times.append(time.perf_counter() - t0)
+        ok = int(np.sum(r["status"] == P.STATUS_OPTIMAL))
+        dt = float(np.median(times))
+        out[name] = dict(ctx=ctx, res=r, x=X.cpu().numpy(), solved=ok, s=dt,
+                         lps_per_s=ok / dt)
+        log(f"{name}: {ok}/{B} optimal, median {dt*1e3:.1f} ms per batch -> {ok/dt:.1f} LPs/s, "
+            f"iters median {int(np.median(r['iters']))} max {int(np.max(r['iters']))}")
+    a, b = out["fp64"]["res"], out["fp32"]["res"]
+    both = (a["status"] == P.STATUS_OPTIMAL) & (b["status"] == P.STATUS_OPTIMAL)
+    dobj = np.abs(b["obj"] - a["obj"]) / (1.0 + np.abs(a["obj"]))
+    vars_ = D["var"]
+    xv = out["fp64"]["x"][np.arange(B), vars_]
+    at_bound = np.mean((np.abs(xv - inst.l[vars_]) < 1e-6) | (np.abs(xv - inst.u[vars_]) < 1e-6))
+    for v in out.values():
+        v["ctx"].close()
+    print(json.dumps({
+        "metric": "LPs solved/s to 1e-4 rel KKT (bound tightening, MIXED32)",
+        "value": round(out["fp32"]["lps_per_s"], 2), "unit": "LPs/s",
+        "fp64_lps_per_s": round(out["fp64"]["lps_per_s"], 2),
+        "config": {"workload": f"A {inst.m}x{inst.n}, 8 U[-1,1] nnz/col, E/L/G rows, box [0,5], "
+                               f"B={B} objectives +-e_j, cold start, tol 1e-4",
+                   "B": B, "steps": args.steps, "warmup": args.warmup},
+        "precision": {"lps_compared": int(both.sum()),
+                      "obj_rel_diff_max": float(dobj[both].max()) if both.any() else None,
+                      "obj_rel_diff_median": float(np.median(dobj[both])) if both.any() else None,
+                      "fp32_rel_kkt_max": float(np.max(b["kkt"][both, 3])) if both.any() else None},
+        "optimum_at_box_bound_fraction": round(float(at_bound), 4)}), flush=True)
+
+
+def run_mixed(args):
+    """Uneven mixed batching over eight base matrices (m = 1k ... 100k,
+    n = 2.5 m, 4..12 N(0,1) nonzeros per column, box [0,10]): each base LP is
+    solved on the GPU first; then 1000 LPs arrive as per-matrix batches of
+    2..512 (log-uniform), half bound flips of fractional root values, half
+    objectives +-e_j.  All batches are queued at once and the continuous-
+    batching loop drains them, every context replaying captured blocks of
+    iterations; LPs/s = LPs that reached 1e-4 / wall time."""
+    import numpy as np
+    import paper_2601_21990_amd.pdlpb as P
+    from paper_2601_21990_amd.serve import Server, Request
+    from workloads import make_cfg4, fsb_deltas, obbt_deltas, deltas, BASE, seed_for
+    prec = P.MIXED32 if args.mixed_prec == "fp32" else P.FP64
+    ctxs, roots = [], []
+    for i in range(8):
+        inst = make_cfg4(i)
+        ctx = P.Context.from_instance(inst, device=0, precision=prec, max_batch=512)
+        ctx.set_batch(deltas([BASE], [0], [0.0]))
+        ctx.solve(tol=1e-5, max_iters=50000)
+        root = ctx.get(0)
+        w = ctx.get_trace(0)["w"]
+        frac = root["x"] - np.floor(root["x"])
+        cand = np.nonzero((frac > 0.1) & (frac < 0.9))[0]
+        log(f"base {i}: m={inst.m} n={inst.n} nnz={inst.nnz} root "
+            f"{P.STATUS_NAMES[root['status']]} iters={root['iters']} fractional={cand.size}")
+        ctx.set_base_warm(root["x"], root["y"], w)
+        ctx.serve_begin(1024)
+        ctxs.append(ctx)
+        roots.append((root["x"], cand, inst.n))
+    rng = np.random.default_rng(seed_for(4, 999))
+    reqs, total = [], 0
+    while total < args.mixed_lps:
+        b = int(rng.integers(0, 8))
+        size = int(round(np.exp(rng.uniform(np.log(2), np.log(512))) / 2)) * 2
+        size = max(2, min(512, size, args.mixed_lps - total))
+        x, cand, n = roots[b]
+        if len(reqs) % 2 == 0 and cand.size >= size // 2:
+            v = np.sort(rng.choice(cand, size=size // 2, replace=False)).astype(np.int32)
+            d = fsb_deltas(x, v)
+        else:
+            v = np.sort(rng.choice(n, size=size // 2, replace=False)).astype(np.int32)
+            d = obbt_deltas(v)
+        reqs.append((b, d))
+        total += len(d)
+    srv = Server(ctxs, warm=True)
+    t0 = time.perf_counter()
+    for b, d in reqs:
+        srv.submit(Request(base=b, deltas=d, arrival=t0, tol=1e-4))
+    srv.drain()
+    wall = time.perf_counter() - t0
+    solved = sum(sum(1 for s in r.statuses.values() if s == P.STATUS_OPTIMAL) for r in srv.completed)
+    for c in ctxs:
+        c.close()
+    print(json.dumps({
+        "metric": "LPs solved/s to 1e-4 rel KKT (uneven mixed batches over 8 bases)",
+        "value": round(solved / wall, 2), "unit": "LPs/s",
+        "config": {"workload": "8 bases m=1k..100k, n=2.5m, 4..12 N(0,1) nnz/col, box [0,10]; "
+                               f"{total} LPs in {len(reqs)} batches of 2..512, half bound flips, "
+                               "half +-e_j objectives, warm start from each base",
+                   "precision": args.mixed_prec},
+        "lps": srv.lps_done, "optimal": solved, "wall_s": round(wall, 3)}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
-    ap.add_argument("--workload", default="fsb", choices=["fsb", "sweep", "copy", "serve"])
+    ap.add_argument("--workload", default="fsb",
+                    choices=["fsb", "sweep", "copy", "serve", "obbt", "mixed"])
+    ap.add_argument("--obbt-vars", type=int, default=128)
+    ap.add_argument("--obbt-iters", type=int, default=100000)
+    ap.add_argument("--mixed-lps", type=int, default=1000)
+    ap.add_argument("--mixed-prec", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--serve-m", type=int, default=200000)
     ap.add_argument("--serve-bases", type=int, default=4)
     ap.add_argument("--serve-prec", default="fp32", choices=["fp32", "fp64"])
@@ -253,6 +385,8 @@ def main():
     ap.add_argument("--sweep-iters", type=int, default=65)
     ap.add_argument("--sweep-tiles", default="0x0", help="lanes x vec per point; 0x0 = automatic")
     ap.add_argument("--sweep-prec", default="fp32,fp64")
+    ap.add_argument("--sweep-matrix", default="cfg5", choices=["cfg3", "cfg5"],
+                    help="cfg5: 200k x 500k (4 N(0,1) nnz/col); cfg3: 20k x 50k (8 U[-1,1] nnz/col)")
     ap.add_argument("--sweep-blocks", default="0",
                     help="workgroup caps of the step launches; 0 = the library default")
     ap.add_argument("--gpus", type=int, default=1)
@@ -277,6 +411,12 @@ def main():
         return
     if args.workload == "serve":
         run_serve(args)
+        return
+    if args.workload == "obbt":
+        run_obbt(args)
+        return
+    if args.workload == "mixed":
+        run_mixed(args)
         return
 
     import numpy as np

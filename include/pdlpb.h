@@ -115,7 +115,7 @@ typedef struct pdlpb_options {
                                  stopping tolerance; >= 0 as given.  The bound-tightening experiments of
                                  Section 6 check dual feasibility at 1e-8 before trusting a dual bound */
     int32_t max_blocks;       /* cap on the workgroups of one step launch; their waves loop over the rows.
-                                 0 (default): 2048 (eight 4-wave workgroups per compute unit) */
+                                 0 (default): 4096 (sixteen 4-wave workgroups per compute unit) */
     int32_t reserved[3];
 } pdlpb_options;
 

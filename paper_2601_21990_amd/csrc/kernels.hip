@@ -106,42 +106,106 @@ struct VecT<float, 4> {
 };
 
 // Row product of one sparse row with VEC consecutive columns of a block:
-// acc[v] = sum_k a_k * G[col_k, s0 + v], nonzeros added in CSR order.  The
-// nonzeros are taken CH at a time: their indices and values are loaded
-// together, then all CH gathers are issued before the first one is used, so a
-// row costs about two memory latencies per chunk instead of two per nonzero.
+// acc[v] = sum_k a_k * G[col_k, s0 + v], nonzeros added in CSR order.  For a
+// matrix with long rows (EW = 16) the first 16 nonzeros of every row sit in
+// an ELL head (index -1 pads short rows), whose loads do not wait for the row
+// pointers; gathers are issued CH at a time before the first one is used.
+// Entries past the head (all entries when EW = 0) come from the CSR arrays,
+// CH per trip.
 constexpr int CH = 8;
 
-template <typename T, int VEC>
-__device__ __forceinline__ void row_product(const int32_t* __restrict__ rp,
-                                            const int32_t* __restrict__ ci,
-                                            const T* __restrict__ av, const T* __restrict__ G,
-                                            int32_t row, int32_t ld, int32_t s0, T* acc) {
+template <typename T, int EW>
+struct Head {
+    int32_t j[EW];
+    T a[EW];
+};
+
+template <typename T, int EW>
+struct HeadVals;
+template <int EW>
+struct HeadVals<double, EW> {
+    __device__ static void load(const double* p, double* out) {
+        const double2* q = reinterpret_cast<const double2*>(p);
+#pragma unroll
+        for (int i = 0; i < EW / 2; ++i) {
+            const double2 w = q[i];
+            out[2 * i] = w.x;
+            out[2 * i + 1] = w.y;
+        }
+    }
+};
+template <int EW>
+struct HeadVals<float, EW> {
+    __device__ static void load(const float* p, float* out) {
+        const float4* q = reinterpret_cast<const float4*>(p);
+#pragma unroll
+        for (int i = 0; i < EW / 4; ++i) {
+            const float4 w = q[i];
+            out[4 * i] = w.x;
+            out[4 * i + 1] = w.y;
+            out[4 * i + 2] = w.z;
+            out[4 * i + 3] = w.w;
+        }
+    }
+};
+
+template <typename T, int VEC, int EW>
+__device__ __forceinline__ void row_product(const StepArgs<T>& a, int32_t row, int32_t s0,
+                                            T* acc) {
 #pragma unroll
     for (int v = 0; v < VEC; ++v) acc[v] = T(0);
-    const int32_t kb = rp[row], ke = rp[row + 1];
-    for (int32_t k0 = kb; k0 < ke; k0 += CH) {
+    const int32_t kb = a.rp[row], ke = a.rp[row + 1];
+    if constexpr (EW > 0) {
+        Head<T, EW> h;
+        const int4* q = reinterpret_cast<const int4*>(a.eci + (size_t)row * EW);
+#pragma unroll
+        for (int i = 0; i < EW / 4; ++i) {
+            const int4 w = q[i];
+            h.j[4 * i] = w.x;
+            h.j[4 * i + 1] = w.y;
+            h.j[4 * i + 2] = w.z;
+            h.j[4 * i + 3] = w.w;
+        }
+        HeadVals<T, EW>::load(a.ev + (size_t)row * EW, h.a);
+#pragma unroll
+        for (int c0 = 0; c0 < EW; c0 += CH) {
+            T g[CH][VEC];
+#pragma unroll
+            for (int u = 0; u < CH; ++u) {
+                if (h.j[c0 + u] >= 0)
+                    VecT<T, VEC>::load(a.G + (size_t)h.j[c0 + u] * a.ld + s0, g[u]);
+            }
+#pragma unroll
+            for (int u = 0; u < CH; ++u) {
+                if (h.j[c0 + u] >= 0) {
+#pragma unroll
+                    for (int v = 0; v < VEC; ++v) acc[v] = fma(h.a[c0 + u], g[u][v], acc[v]);
+                }
+            }
+        }
+    }
+    for (int32_t k0 = kb + EW; k0 < ke; k0 += CH) {
         int32_t j[CH];
-        T a[CH];
+        T w[CH];
 #pragma unroll
         for (int u = 0; u < CH; ++u) {
             j[u] = 0;
-            a[u] = T(0);
+            w[u] = T(0);
             if (k0 + u < ke) {
-                j[u] = ci[k0 + u];
-                a[u] = av[k0 + u];
+                j[u] = a.ci[k0 + u];
+                w[u] = a.av[k0 + u];
             }
         }
         T g[CH][VEC];
 #pragma unroll
         for (int u = 0; u < CH; ++u) {
-            if (k0 + u < ke) VecT<T, VEC>::load(G + (size_t)j[u] * ld + s0, g[u]);
+            if (k0 + u < ke) VecT<T, VEC>::load(a.G + (size_t)j[u] * a.ld + s0, g[u]);
         }
 #pragma unroll
         for (int u = 0; u < CH; ++u) {
             if (k0 + u < ke) {
 #pragma unroll
-                for (int v = 0; v < VEC; ++v) acc[v] = fma(a[u], g[u][v], acc[v]);
+                for (int v = 0; v < VEC; ++v) acc[v] = fma(w[u], g[u][v], acc[v]);
             }
         }
     }
@@ -160,7 +224,7 @@ __device__ __forceinline__ double halpern_a(int32_t k) { return double(k + 1) / 
 // Only Xbar is stored between iterations; x^{k+1} is rebuilt from Xbar and the
 // anchor by the next launch, which saves one block write per iteration.
 // ---------------------------------------------------------------------------
-template <typename T, int G, int VEC>
+template <typename T, int G, int VEC, int EW>
 __global__ __launch_bounds__(256) void k_primal(StepArgs<T> a) {
     constexpr int RPW = 64 / G;
     const int lane = threadIdx.x & 63;
@@ -214,7 +278,7 @@ __global__ __launch_bounds__(256) void k_primal(StepArgs<T> a) {
         const double cb = a.c[row], lb = a.lo[row], hb = a.hi[row];
 
         T acc[VEC];
-        row_product<T, VEC>(a.rp, a.ci, a.av, a.G, row, a.ld, s0, acc);
+        row_product<T, VEC, EW>(a, row, s0, acc);
 
 #pragma unroll
         for (int v = 0; v < VEC; ++v) {
@@ -241,7 +305,7 @@ __global__ __launch_bounds__(256) void k_primal(StepArgs<T> a) {
 //   y~  = sigma_j ( q - Pi_[l,u](q) )        (the printed expression in Moreau order)
 //   y^{k+1} = (k+1)/(k+2) (2 y~ - y^k) + y0/(k+2)   (eq:mainiter)
 // ---------------------------------------------------------------------------
-template <typename T, int G, int VEC>
+template <typename T, int G, int VEC, int EW>
 __global__ __launch_bounds__(256) void k_dual(StepArgs<T> a) {
     constexpr int RPW = 64 / G;
     const int lane = threadIdx.x & 63;
@@ -292,7 +356,7 @@ __global__ __launch_bounds__(256) void k_dual(StepArgs<T> a) {
         const T l = T(a.lo[row]), u = T(a.hi[row]);
 
         T acc[VEC];
-        row_product<T, VEC>(a.rp, a.ci, a.av, a.G, row, a.ld, s0, acc);
+        row_product<T, VEC, EW>(a, row, s0, acc);
 
 #pragma unroll
         for (int v = 0; v < VEC; ++v) {
@@ -987,8 +1051,8 @@ __global__ void k_fill(double* x, int32_t len, double v) {
     if (i < len) x[i] = v;
 }
 
-template <typename T, int G, int VEC, bool PRIMAL>
-hipError_t launch_step_gv(const StepArgs<T>& a, hipStream_t s) {
+template <typename T, int G, int VEC, int EW, bool PRIMAL>
+hipError_t launch_step_gve(const StepArgs<T>& a, hipStream_t s) {
     constexpr int RPW = 64 / G;
     const int rows_per_block = a.wpb * RPW;
     const uint32_t gy = (uint32_t)((a.ncols + G * VEC - 1) / (G * VEC));
@@ -1002,10 +1066,19 @@ hipError_t launch_step_gv(const StepArgs<T>& a, hipStream_t s) {
     const dim3 block(64 * a.wpb);
     if (grid.x == 0 || grid.y == 0) return hipSuccess;
     if (PRIMAL)
-        hipLaunchKernelGGL((k_primal<T, G, VEC>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((k_primal<T, G, VEC, EW>), grid, block, 0, s, a);
     else
-        hipLaunchKernelGGL((k_dual<T, G, VEC>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((k_dual<T, G, VEC, EW>), grid, block, 0, s, a);
     return hipGetLastError();
+}
+
+template <typename T, int G, int VEC, bool PRIMAL>
+hipError_t launch_step_gv(const StepArgs<T>& a, hipStream_t s) {
+    switch (a.ew) {
+        case 0: return launch_step_gve<T, G, VEC, 0, PRIMAL>(a, s);
+        case 16: return launch_step_gve<T, G, VEC, 16, PRIMAL>(a, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 template <typename T, int VEC, bool PRIMAL>

@@ -47,7 +47,7 @@ struct Tile {
     int blocks = 0;     // workgroup cap of the launch (0: one wave per row group)
 };
 
-constexpr int32_t DEFAULT_MAX_BLOCKS = 2048;
+constexpr int32_t DEFAULT_MAX_BLOCKS = 4096;
 
 struct pdlpb_ctx {
     std::string err = "no error";
@@ -63,6 +63,11 @@ struct pdlpb_ctx {
     int32_t *a_rp = nullptr, *a_ci = nullptr, *t_rp = nullptr, *t_ci = nullptr;
     double *a_v64 = nullptr, *t_v64 = nullptr;
     float *a_v32 = nullptr, *t_v32 = nullptr;
+    // ELL heads: the first ew entries of every row (index -1 pads short rows)
+    int32_t a_ew = 0, t_ew = 0;
+    int32_t *a_eci = nullptr, *t_eci = nullptr;
+    double *a_ev64 = nullptr, *t_ev64 = nullptr;
+    float *a_ev32 = nullptr, *t_ev32 = nullptr;
     double *c = nullptr, *xl = nullptr, *xu = nullptr, *rl = nullptr, *ru = nullptr;
 
     // host copies used by set_batch
@@ -198,6 +203,7 @@ void free_all(pdlpb_ctx* x) {
     for (auto e : x->ev) (void)hipEventDestroy(e);
     x->ev.clear();
     void* ptrs[] = {x->a_rp, x->a_ci, x->t_rp, x->t_ci, x->a_v64, x->t_v64, x->a_v32, x->t_v32,
+                    x->a_eci, x->t_eci, x->a_ev64, x->t_ev64, x->a_ev32, x->t_ev32,
                     x->c, x->xl, x->xu, x->rl, x->ru, x->sl.key, x->sl.tau, x->sl.sigma,
                     x->sl.dval, x->sl.t_start, x->sl.lp, x->ctl, x->rlog, x->base_x, x->adm_rows,
                     x->adm_ctl,
@@ -348,6 +354,10 @@ StepArgs<T> step_args(pdlpb_ctx* x, bool primal, int32_t it, int32_t eval, int32
     a.rp = primal ? x->t_rp : x->a_rp;
     a.ci = primal ? x->t_ci : x->a_ci;
     a.av = av;
+    a.ew = primal ? x->t_ew : x->a_ew;
+    a.eci = primal ? x->t_eci : x->a_eci;
+    if constexpr (sizeof(T) == 8) a.ev = reinterpret_cast<const T*>(primal ? x->t_ev64 : x->a_ev64);
+    else a.ev = reinterpret_cast<const T*>(primal ? x->t_ev32 : x->a_ev32);
     a.rows = primal ? x->n : x->m;
     a.ld = x->ld;
     a.ncols = x->live;
@@ -949,6 +959,38 @@ int pdlpb_create(pdlpb_ctx** out, int32_t m, int32_t n, int64_t nnz, const int64
         std::vector<float> a32(val, val + nnz), t32(h_tv.begin(), h_tv.end());
         if ((e = up(&x->a_v32, a32.data(), a32.size())) != hipSuccess) return dev_fail(e, "upload A");
         if ((e = up(&x->t_v32, t32.data(), t32.size())) != hipSuccess) return dev_fail(e, "upload A'");
+    }
+    // ELL heads of A and A' (16 wide) for a matrix where more than a tenth of
+    // the rows are longer than 8; others are walked in CSR alone
+    {
+        auto head = [&](const int32_t* rp, const int32_t* ci, const double* v, int32_t rows,
+                        int32_t* ew_out, int32_t** d_ci, double** d_v64, float** d_v32) {
+            int64_t longer = 0;
+            for (int32_t r = 0; r < rows; ++r) longer += (rp[r + 1] - rp[r]) > 8;
+            const int32_t ew = (longer * 10 > (int64_t)rows) ? 16 : 0;
+            *ew_out = ew;
+            if (ew == 0) return hipSuccess;
+            std::vector<int32_t> hci((size_t)rows * ew, -1);
+            std::vector<double> hv((size_t)rows * ew, 0.0);
+            for (int32_t r = 0; r < rows; ++r)
+                for (int32_t k = rp[r], u = 0; k < rp[r + 1] && u < ew; ++k, ++u) {
+                    hci[(size_t)r * ew + u] = ci[k];
+                    hv[(size_t)r * ew + u] = v[k];
+                }
+            hipError_t r1 = up(d_ci, hci.data(), hci.size());
+            if (r1 != hipSuccess) return r1;
+            r1 = up(d_v64, hv.data(), hv.size());
+            if (r1 != hipSuccess || !x->fp32) return r1;
+            std::vector<float> h32(hv.begin(), hv.end());
+            return up(d_v32, h32.data(), h32.size());
+        };
+        std::vector<int32_t> h_aci(col_idx, col_idx + nnz);
+        if ((e = head(h_arp.data(), h_aci.data(), val, m, &x->a_ew, &x->a_eci, &x->a_ev64,
+                      &x->a_ev32)) != hipSuccess)
+            return dev_fail(e, "upload A");
+        if ((e = head(h_trp.data(), h_tci.data(), h_tv.data(), n, &x->t_ew, &x->t_eci,
+                      &x->t_ev64, &x->t_ev32)) != hipSuccess)
+            return dev_fail(e, "upload A'");
     }
     if ((e = up(&x->c, c, (size_t)n)) != hipSuccess) return dev_fail(e, "upload c");
     if ((e = up(&x->xl, l, (size_t)n)) != hipSuccess) return dev_fail(e, "upload l");

@@ -103,6 +103,9 @@ struct StepArgs {
     const int32_t* rp;   // CSR row pointers of the matrix whose rows this kernel walks
     const int32_t* ci;   // column indices
     const T*       av;   // values
+    const int32_t* eci;  // ELL head: the first ew column indices of every row (-1 pads), rows x ew; may be null when ew = 0
+    const T*       ev;   // ELL head values (0 pads)
+    int32_t ew;          // ELL head width: 16, or 0 when the rows are walked in CSR alone
     int32_t rows;        // rows walked (n for the primal step, m for the dual step)
     int32_t ld;          // row stride of every dense block (>= ncols)
     int32_t ncols;       // columns covered by the grid (the live count g->n_cols never exceeds it)

@@ -234,7 +234,10 @@ class Context:
 
     def set_batch(self, deltas, x_warm=None, y_warm=None, w_warm=None,
                   warm_mode: Optional[int] = None, mem: int = MEM_HOST):
-        B = len(deltas)
+        if mem == MEM_HOST:
+            B = len(deltas)
+        else:                       # a device tensor holding B 16-byte records
+            B = deltas.numel() * deltas.element_size() // 16
         if mem == MEM_HOST:
             dd = np.ascontiguousarray(deltas)
             if dd.dtype.itemsize != 16:
