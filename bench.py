@@ -213,7 +213,7 @@ def run_serve(args):
                 x, cand = roots[b]
                 vars_ = np.sort(rng.choice(cand, size=size // 2, replace=False)).astype(np.int32)
                 srv.submit(Request(base=b, deltas=fsb_deltas(x, vars_), arrival=next_arrival,
-                                   tol=1e-4))
+                                   tol=1e-4, max_iters=args.serve_iters))
                 n_req += 1
                 next_arrival += rng.exponential(1.0 / rate)
             if next_arrival - t_start >= args.serve_seconds and not srv.busy():
@@ -226,7 +226,12 @@ def run_serve(args):
         lat = [r.latency for r in srv.completed]
         solved = sum(sum(1 for s in r.statuses.values() if s == P.STATUS_OPTIMAL)
                      for r in srv.completed)
+        st = np.array([v for r in srv.completed for v in r.statuses.values()], dtype=np.int64)
+        its = np.array([v for r in srv.completed for v in r.iters.values()], dtype=np.int64)
         line = {"rate_per_s": rate, "requests": n_req, "completed": len(srv.completed),
+                "statuses": np.bincount(st, minlength=8).tolist(),
+                "iters_median": int(np.median(its)) if its.size else 0,
+                "iters_max": int(its.max()) if its.size else 0,
                 "lps": srv.lps_done, "lps_optimal": solved, "wall_s": round(wall, 3),
                 "lps_per_s": round(srv.lps_done / wall, 2),
                 "p50_s": round(percentile(lat, 50), 4), "p99_s": round(percentile(lat, 99), 4)}
@@ -348,11 +353,29 @@ def run_mixed(args):
         total += len(d)
     srv = Server(ctxs, warm=True)
     t0 = time.perf_counter()
+    tagged = []
     for b, d in reqs:
-        srv.submit(Request(base=b, deltas=d, arrival=t0, tol=1e-4))
+        r = Request(base=b, deltas=d, arrival=t0, tol=1e-4, max_iters=args.mixed_iters)
+        srv.submit(r)
+        tagged.append(r)
     srv.drain()
     wall = time.perf_counter() - t0
     solved = sum(sum(1 for s in r.statuses.values() if s == P.STATUS_OPTIMAL) for r in srv.completed)
+    kinds = {}
+    for r in tagged:
+        kind = "objective" if int(r.deltas["kind"][0]) == 3 else "bound"
+        st = np.array(list(r.statuses.values()))
+        it = np.array(list(r.iters.values()))
+        e = kinds.setdefault(kind, {"lps": 0, "optimal": 0, "iters": []})
+        e["lps"] += len(st)
+        e["optimal"] += int(np.sum(st == P.STATUS_OPTIMAL))
+        e["iters"].extend(it.tolist())
+        log(f"request base={r.base} {kind} B={len(st)}: statuses {np.bincount(st, minlength=8).tolist()} "
+            f"iters median {int(np.median(it))} max {int(it.max())} latency {r.latency:.2f}s")
+    for e in kinds.values():
+        e["iters_median"] = int(np.median(e["iters"]))
+        e["iters_max"] = int(np.max(e["iters"]))
+        del e["iters"]
     for c in ctxs:
         c.close()
     print(json.dumps({
@@ -362,7 +385,8 @@ def run_mixed(args):
                                f"{total} LPs in {len(reqs)} batches of 2..512, half bound flips, "
                                "half +-e_j objectives, warm start from each base",
                    "precision": args.mixed_prec},
-        "lps": srv.lps_done, "optimal": solved, "wall_s": round(wall, 3)}), flush=True)
+        "lps": srv.lps_done, "optimal": solved, "wall_s": round(wall, 3),
+        "by_kind": kinds, "max_iters": args.mixed_iters}), flush=True)
 
 
 def main():
@@ -373,6 +397,7 @@ def main():
     ap.add_argument("--obbt-iters", type=int, default=100000)
     ap.add_argument("--mixed-lps", type=int, default=1000)
     ap.add_argument("--mixed-prec", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--mixed-iters", type=int, default=20000)
     ap.add_argument("--serve-m", type=int, default=200000)
     ap.add_argument("--serve-bases", type=int, default=4)
     ap.add_argument("--serve-prec", default="fp32", choices=["fp32", "fp64"])
@@ -380,6 +405,7 @@ def main():
     ap.add_argument("--serve-rows", type=int, default=2048)
     ap.add_argument("--serve-rates", default="1,3,10")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--serve-iters", type=int, default=20000)
     ap.add_argument("--sweep-m", type=int, default=200000)
     ap.add_argument("--sweep-b", default="1,8,32,64,128,256,512")
     ap.add_argument("--sweep-iters", type=int, default=65)

@@ -261,7 +261,11 @@ int pdlpb_branch_scores(pdlpb_ctx* ctx, double parent_obj, double mu, double* ga
  * overlap on the device (each context has its own stream).
  *
  * pdlpb_set_base_warm keeps one warm start (x: n, y: m, primal weight w)
- * resident on the device for PDLPB_WARM_BASE submissions.
+ * resident on the device for PDLPB_WARM_BASE submissions.  A bound change
+ * (SET_LO / SET_HI) starts from the base x (projected onto its box), y and w.
+ * An objective change (OBJ_UNIT) starts from the base x with y = 0 and the
+ * default weight ||c_j|| / ||b||: the base dual and weight belong to the base
+ * objective, and starting from them stalls FP32 iterates far from the optimum.
  */
 int pdlpb_set_base_warm(pdlpb_ctx* ctx, const double* x, const double* y, double w, int32_t mem);
 int pdlpb_serve_begin(pdlpb_ctx* ctx, int32_t result_capacity);

@@ -969,7 +969,7 @@ __global__ void k_init_columns(int32_t n, int32_t m, int32_t ld, int32_t c0, int
     if (idx < nx) {
         const int32_t i = (int32_t)(idx / cnt), s = c0 + (int32_t)(idx % cnt);
         const VarData d = var_data(sl.key[s].varkind, sl.dval, s, i, 0.0, xl[i], xu[i]);
-        const T x = T(clampd(mode == PDLPB_WARM_SHARED ? xw[i] : 0.0, d.lo, d.hi));
+        const T x = T(clampd(mode == PDLPB_WARM_BASE ? xw[i] : 0.0, d.lo, d.hi));
         const size_t e = (size_t)i * ld + s;
         B.b[0][e] = x;
         B.b[1][e] = x;
@@ -978,7 +978,9 @@ __global__ void k_init_columns(int32_t n, int32_t m, int32_t ld, int32_t c0, int
     } else if (idx < nx + ny) {
         const int64_t q = idx - nx;
         const int32_t i = (int32_t)(q / cnt), s = c0 + (int32_t)(q % cnt);
-        const T y = mode == PDLPB_WARM_SHARED ? T(yw[i]) : T(0);
+        // objective changes start from the base primal point with y = 0
+        const bool objective = (sl.key[s].varkind >> 28) == PDLPB_OBJ_UNIT;
+        const T y = (mode == PDLPB_WARM_BASE && !objective) ? T(yw[i]) : T(0);
         const size_t e = (size_t)i * ld + s;
         B.b[4][e] = y;
         B.b[5][e] = y;

@@ -1430,7 +1430,10 @@ int pdlpb_submit(pdlpb_ctx* x, int32_t count, const pdlpb_delta* deltas, int32_t
         x->row_id[row] = id;
         x->id_row[id] = row;
         int32_t status = lp_status(x, q);
-        double w = warm_mode == PDLPB_WARM_BASE ? x->base_w : default_weight(x, q);
+        // the base dual and weight belong to the base objective: objective changes
+        // start from the base primal point only
+        double w = (warm_mode == PDLPB_WARM_BASE && q.kind != PDLPB_OBJ_UNIT) ? x->base_w
+                                                                               : default_weight(x, q);
         if (status != PDLPB_STATUS_RUNNING) {
             // settled without iterating: record the outcome and zero results
             SlotCtl cl{};
@@ -1528,7 +1531,7 @@ int serve_admit(pdlpb_ctx* x) {
     const double* yw = warm == PDLPB_WARM_BASE ? x->base_x + x->n : nullptr;
     T* const* b = reinterpret_cast<T* const*>(x->blk);
     HIP_TRY(x, launch_init_columns<T>(x->n, x->m, x->ld, c0, cnt, x->sl, x->xl, x->xu, xw, yw,
-                                      warm == PDLPB_WARM_BASE ? PDLPB_WARM_SHARED : PDLPB_WARM_NONE,
+                                      warm,
                                       b, x->stream));
     // first iteration of the admitted LPs at t = t0 (t_local = 0): a full evaluation
     const int32_t shape = shape_cols(x, x->n_cols);

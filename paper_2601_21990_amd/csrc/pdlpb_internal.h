@@ -205,7 +205,8 @@ hipError_t launch_begin_solve(Slots sl, SlotCtl* ctl, int32_t ncols, int32_t max
                               double tol, hipStream_t s);
 
 // Initialise columns [c0, c0 + cnt) of the eight blocks for newly admitted LPs
-// (warm start: mode 0 none, 1 shared vectors xw (n) / yw (m)).
+// (warm start: PDLPB_WARM_NONE, or PDLPB_WARM_BASE from the base vectors
+// xw (n) / yw (m), where objective changes take xw and y = 0).
 template <typename T>
 hipError_t launch_init_columns(int32_t n, int32_t m, int32_t ld, int32_t c0, int32_t cnt, Slots sl,
                                const double* xl, const double* xu, const double* xw,

@@ -37,6 +37,7 @@ class Request:
     submitted: Optional[float] = None
     done: Optional[float] = None
     statuses: Dict[int, int] = field(default_factory=dict)
+    iters: Dict[int, int] = field(default_factory=dict)
 
     @property
     def latency(self) -> float:
@@ -104,6 +105,7 @@ class Server:
                     continue
                 r = self.ctx[k].result(i, want_x=self.keep_results, want_y=self.keep_results)
                 req.statuses[i] = r["status"]
+                req.iters[i] = r["iters"]
                 if self.keep_results:
                     self.results[(k, i)] = r
                 self.ctx[k].release(i)

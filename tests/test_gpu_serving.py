@@ -161,3 +161,28 @@ def test_server_loop_overlaps_bases(P, base):
     finally:
         for c in ctxs:
             c.close()
+
+
+def test_objective_change_warm_base_starts_from_base_primal(P, base):
+    """An objective change admitted with the base warm start begins at the
+    base primal point with y = 0 and the default weight, i.e. exactly the
+    batch solve warm-started per LP that way."""
+    inst, lp, eta, root = base
+    D = obbt_deltas(choose_vars(inst.n, 4, seed=7))
+    B = len(D)
+    with make_ctx(inst, eta) as ctx:
+        # no weights given: each LP takes the default ||c_j|| / ||b||
+        ctx.set_batch(D, x_warm=np.tile(root.x, B), y_warm=np.zeros(B * inst.m),
+                      warm_mode=P.WARM_PER_LP)
+        ctx.solve(tol=1e-5, max_iters=20000)
+        ref = ctx.get_batch()
+    with make_ctx(inst, eta) as ctx:
+        ctx.set_base_warm(root.x, root.y, root.w)
+        ctx.serve_begin(16)
+        ids = ctx.submit(D, P.WARM_BASE, 1e-5, 20000)
+        got = _serve_until_done(P, ctx, list(ids))
+    for j, i in enumerate(ids):
+        assert got[i]["status"] == ref["status"][j] == P.STATUS_OPTIMAL
+        assert got[i]["iters"] == ref["iters"][j]
+        np.testing.assert_array_equal(got[i]["x"], ref["X"][j])
+        np.testing.assert_array_equal(got[i]["y"], ref["Y"][j])
