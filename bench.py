@@ -11,8 +11,12 @@ every LP to 1e-4 relative KKT in FP64, copy the solutions to device buffers.
 
 Reported: LPs solved per second (value), the same LPs solved one at a time
 by the same library (plain PDHG, B = 1), the dominant kernel's achieved HBM
-bandwidth against 8 TB/s (HIP events on the library's stream), and the FP64
-reference solver timed on the host cores on a bounded sample.
+bandwidth against 8 TB/s (HIP events on the library's stream; its measured
+HBM traffic from a committed counter summary when that was taken on the same
+kernel sources), the fused product kernels' GB/s at a 200k x 500k shape whose
+blocks exceed the caches, and the FP64 reference solver timed on the host
+cores on a bounded sample.  Other workloads: --workload obbt | mixed | serve |
+sweep | copy | pmc-summary.
 """
 from __future__ import annotations
 
@@ -44,6 +48,103 @@ def fused_bytes(kind, m, n, nnz, B, s_val, s_it):
     if kind == 0:
         return nnz * (s_val + 4) + 4 * (n + 1) + s_it * B * (m + 3 * n)
     return nnz * (s_val + 4) + 4 * (m + 1) + s_it * B * (n + 3 * m)
+
+
+def kernel_source_sha() -> str:
+    """SHA-256 of the library sources that decide what the kernels move (the
+    kernels, their argument layout and the launch shapes)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "pdlpb_internal.h", "pdlpb.cpp"):
+        with open(os.path.join(ROOT, "paper_2601_21990_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(name, kernel):
+    """HBM bytes per launch of `kernel` from a committed counter summary, or
+    None when the summary is missing or was taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    if d.get("kernels_sha256") != kernel_source_sha() or d.get("kernel") != kernel:
+        return None
+    return d["bytes_per_launch"]
+
+
+def run_pmc_summary(args):
+    """Per-dispatch HBM traffic of one kernel from two rocprofv3 --pmc runs of
+    the same command (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch), over the
+    dispatches of the chosen solves (a solve starts at a k_begin_solve
+    dispatch), scaled by what the same counters read for a 1 GiB device copy
+    (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  Writes a JSON summary keyed by the
+    hash of the kernel sources it was taken on."""
+    import csv
+    import glob
+    solves = {int(v) for v in args.pmc_solves.split(",")}
+
+    def per_dispatch(d, counter):
+        f = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)[0]
+        rows = sorted(csv.DictReader(open(f)), key=lambda r: int(r["Dispatch_Id"]))
+        vals, solve = [], 0
+        for r in rows:
+            name = r["Kernel_Name"]
+            if "k_begin_solve" in name:
+                solve += 1
+            if r["Counter_Name"] == counter and args.pmc_kernel in name and solve in solves:
+                vals.append(float(r["Counter_Value"]))
+        return vals
+
+    fetch = per_dispatch(args.pmc_fetch, "FETCH_SIZE")
+    write = per_dispatch(args.pmc_write, "WRITE_SIZE")
+    if not fetch or len(fetch) != len(write):
+        raise SystemExit(f"dispatch counts differ or are empty: {len(fetch)} vs {len(write)}")
+    f_kib = sum(fetch) / len(fetch)
+    w_kib = sum(write) / len(write)
+    out = {"kernel": args.pmc_kernel, "solves": sorted(solves), "dispatches": len(fetch),
+           "fetch_kib_per_dispatch": round(f_kib, 2), "write_kib_per_dispatch": round(w_kib, 2),
+           "fetch_factor": 2.0, "write_factor": 1.0,
+           "bytes_per_launch": int(round((2.0 * f_kib + 1.0 * w_kib) * 1024)),
+           "kernels_sha256": kernel_source_sha(), "command": args.pmc_command}
+    with open(args.pmc_out, "w") as fh:
+        json.dump(out, fh, indent=1)
+        fh.write("\n")
+    print(json.dumps(out), flush=True)
+
+
+def spmm_leg():
+    """The fused product kernels at the 200k x 500k shape (4 N(0,1) nonzeros
+    per column, the serving-stream family), FP64, B = 512, default launch
+    shapes, 65 iterations with every launch bracketed by HIP events: achieved
+    GB/s = compulsory bytes / average launch time.  The blocks (≈2 GB each)
+    exceed the 256 MB last-level cache, so this is the HBM point."""
+    import paper_2601_21990_amd.pdlpb as P
+    from workloads import make_cfg5, obbt_deltas, choose_vars
+    inst = make_cfg5()
+    m, n, nnz = inst.m, inst.n, inst.nnz
+    B = 512
+    ctx = P.Context.from_instance(inst, device=0)
+    ctx.set_batch(obbt_deltas(choose_vars(n, B // 2, seed=B)))
+    ctx.set_kernel_timing(True)
+    ctx.solve(tol=0.0, max_iters=65)
+    cnt, ms = ctx.kernel_times()
+    cols = ctx.kernel_columns()
+    ctx.set_kernel_timing(False)
+    ctx.close()
+    out = {"workload": f"A {m}x{n} (nnz {nnz}), FP64, B={B}, 65 iterations"}
+    for kind, name in ((0, "primal"), (1, "dual")):
+        nl = max(cnt[kind], 1)
+        q0 = fused_bytes(kind, m, n, nnz, 0, 8, 8)
+        q = q0 + (fused_bytes(kind, m, n, nnz, 1, 8, 8) - q0) * cols[kind] / nl
+        avg = ms[kind] / nl
+        gbs = q / (avg * 1e-3) / 1e9
+        out[name] = {"achieved": round(gbs, 1), "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+                     "bytes_per_launch": int(q), "avg_launch_us": round(avg * 1e3, 2),
+                     "launches": int(cnt[kind])}
+        log(f"spmm {name}: {avg*1e3:.1f} us per launch, {gbs:.1f} GB/s")
+    return out
 
 
 def cpu_sample(n_lps, workers):
@@ -392,7 +493,14 @@ def run_mixed(args):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--workload", default="fsb",
-                    choices=["fsb", "sweep", "copy", "serve", "obbt", "mixed"])
+                    choices=["fsb", "sweep", "copy", "serve", "obbt", "mixed", "pmc-summary"])
+    ap.add_argument("--pmc-fetch", help="rocprofv3 output folder of the FETCH_SIZE run")
+    ap.add_argument("--pmc-write", help="rocprofv3 output folder of the WRITE_SIZE run")
+    ap.add_argument("--pmc-kernel", default="k_dual")
+    ap.add_argument("--pmc-solves", default="2,3,4",
+                    help="1-based solves (k_begin_solve dispatches) whose launches count")
+    ap.add_argument("--pmc-out", default=None)
+    ap.add_argument("--pmc-command", default="")
     ap.add_argument("--obbt-vars", type=int, default=128)
     ap.add_argument("--obbt-iters", type=int, default=100000)
     ap.add_argument("--mixed-lps", type=int, default=1000)
@@ -419,7 +527,9 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-lps", type=int, default=128)
+    ap.add_argument("--cpu-lps", type=int, default=256)
+    ap.add_argument("--no-spmm", action="store_true",
+                    help="skip the 200k x 500k product-kernel point")
     ap.add_argument("--plain-lps", type=int, default=64, help="LPs of the batch solved one at a time")
     ap.add_argument("--graphs", type=int, default=1)
     args = ap.parse_args()
@@ -437,6 +547,9 @@ def main():
         return
     if args.workload == "serve":
         run_serve(args)
+        return
+    if args.workload == "pmc-summary":
+        run_pmc_summary(args)
         return
     if args.workload == "obbt":
         run_obbt(args)
@@ -517,18 +630,27 @@ def main():
     torch.cuda.synchronize()
     event_dt = time.perf_counter() - t1
     counts, total_ms = ctx.kernel_times()
+    cols = ctx.kernel_columns()
     ctx.set_kernel_timing(False)
     log(f"event-timed pass: {event_dt:.4f}s")
 
-    # roofline of the dominant kernel
+    # roofline of the dominant kernel: algorithmic bytes are affine in the live
+    # column count of a launch, so their sum over the timed launches follows from
+    # the launch count and the summed live columns
     names = ["primal: A'Y + primal step", "dual: A Xbar + dual step", "evaluation", "control"]
     dom = 0 if total_ms[0] >= total_ms[1] else 1
-    avg_ms = total_ms[dom] / max(counts[dom], 1)
-    q = fused_bytes(dom, m, n, nnz, B, 8, 8)
+    nl = max(counts[dom], 1)
+    avg_ms = total_ms[dom] / nl
+    q0 = fused_bytes(dom, m, n, nnz, 0, 8, 8)
+    q1 = fused_bytes(dom, m, n, nnz, 1, 8, 8) - q0
+    q = (q0 * counts[dom] + q1 * cols[dom]) / nl
     achieved = q / (avg_ms * 1e-3) / 1e9
+    traffic = measured_traffic("fsb_cfg2_b64_fp64_dual_traffic.json", "k_dual") if dom == 1 else None
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
-                "kernel": names[dom], "bytes_per_launch": int(q),
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
+                "traffic": traffic, "kernel": names[dom], "bytes_per_launch": int(q),
+                "full_width_bytes": int(fused_bytes(dom, m, n, nnz, B, 8, 8)),
+                "mean_live_columns": round(cols[dom] / nl, 2),
                 "avg_launch_us": round(avg_ms * 1e3, 3), "launches": int(counts[dom])}
     kernel_us = {names[k]: round(total_ms[k] / max(counts[k], 1) * 1e3, 3) for k in range(4)}
 
@@ -564,6 +686,7 @@ def main():
         log(f"cpu: {cpu['value']} LPs/s")
 
     ctx.close()
+    spmm = None if args.no_spmm else spmm_leg()
     line = {
         "metric": METRIC,
         "value": round(value, 2),
@@ -589,6 +712,7 @@ def main():
                   "max": int(out["iters"].max())},
         "kernel_avg_us": kernel_us,
         "roofline": roofline,
+        "spmm_hbm": spmm,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

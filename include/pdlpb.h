@@ -115,8 +115,13 @@ typedef struct pdlpb_options {
                                  stopping tolerance; >= 0 as given.  The bound-tightening experiments of
                                  Section 6 check dual feasibility at 1e-8 before trusting a dual bound */
     int32_t max_blocks;       /* cap on the workgroups of one step launch; their waves loop over the rows.
-                                 0 (default): 4096 (sixteen 4-wave workgroups per compute unit) */
-    int32_t reserved[3];
+                                 0 (default): 16384 (64 4-wave workgroups per compute unit) */
+    int32_t scaling;          /* diagonal preconditioning of A at create: 0 (default) none; 1 ten Ruiz
+                                 equilibration passes then one Pock-Chambolle pass (alpha = 1).  The
+                                 solver then works on D_r A D_c (the stopping and infeasibility tests
+                                 measure the scaled LP); changes, warm starts and results stay in the
+                                 caller's coordinates */
+    int32_t reserved[2];
 } pdlpb_options;
 
 typedef struct pdlpb_ctx pdlpb_ctx;   /* opaque; owns all device memory of one base matrix and its batch */
@@ -290,6 +295,14 @@ int pdlpb_release(pdlpb_ctx* ctx, int64_t id);
  */
 int pdlpb_set_tile(pdlpb_ctx* ctx, int32_t lanes, int32_t vec);
 
+/*
+ * The diagonal scaling in use (pdlpb_options.scaling): dr (m host doubles) and
+ * dc (n host doubles) with the solver's matrix D_r A D_c; all ones without
+ * scaling.  Either pointer may be NULL.  Problem scaling is one of the
+ * enhancements of the first-order method the paper builds on (Section 2).
+ */
+int pdlpb_get_scaling(const pdlpb_ctx* ctx, double* dr, double* dc);
+
 /* Step size eta in use and the computed ||A||_2 (0 if eta was given). */
 int pdlpb_get_step_size(const pdlpb_ctx* ctx, double* eta, double* norm_a);
 
@@ -303,6 +316,15 @@ int pdlpb_get_step_size(const pdlpb_ctx* ctx, double* eta, double* norm_a);
  */
 int pdlpb_set_kernel_timing(pdlpb_ctx* ctx, int32_t enable);
 int pdlpb_kernel_times(pdlpb_ctx* ctx, int64_t counts[4], double total_ms[4]);
+
+/*
+ * For the same launches: the live LP columns each launch processed, summed
+ * per kind (the live count is read back at every evaluation; within a block
+ * of C iterations it does not change).  Algorithmic bytes of the product
+ * kernels are affine in the column count, so with the launch count this gives
+ * their exact sum.  EINVAL for a NULL cols.
+ */
+int pdlpb_kernel_columns(pdlpb_ctx* ctx, int64_t cols[4]);
 
 /* Bytes of device memory held by the context. */
 int64_t pdlpb_device_bytes(const pdlpb_ctx* ctx);

@@ -996,6 +996,17 @@ __global__ void k_admit(SlotCtl* ctl, const int32_t* rows, const SlotCtl* src, i
     if (i == 0) g->n_cols = n_cols;
 }
 
+// v[k] *= d[k % period] (or /=): maps LP-major blocks and shared vectors
+// between the caller's coordinates and the scaled LP's
+__global__ void k_rescale(double* v, const double* d, int64_t count, int32_t period,
+                          int32_t divide) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < count) {
+        const double f = d[k % period];
+        v[k] = divide ? v[k] / f : v[k] * f;
+    }
+}
+
 __global__ void k_widen(const float* src, int64_t count, double* dst) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < count) dst[i] = (double)src[i];
@@ -1208,6 +1219,16 @@ hipError_t launch_admit(SlotCtl* ctl, const int32_t* rows, const SlotCtl* src, i
     const int32_t blocks = (cnt + 255) / 256;
     hipLaunchKernelGGL(k_admit, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, s, ctl, rows, src, cnt,
                        g, n_cols);
+    return hipGetLastError();
+}
+
+hipError_t launch_rescale(double* v, const double* d, int64_t count, int32_t period,
+                          int32_t divide, hipStream_t s) {
+    if (count == 0 || period == 0) return hipSuccess;
+    const int64_t blocks = (count + 255) / 256;
+    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_rescale, dim3((uint32_t)blocks), dim3(256), 0, s, v, d, count, period,
+                       divide);
     return hipGetLastError();
 }
 

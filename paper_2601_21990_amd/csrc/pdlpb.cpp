@@ -47,7 +47,7 @@ struct Tile {
     int blocks = 0;     // workgroup cap of the launch (0: one wave per row group)
 };
 
-constexpr int32_t DEFAULT_MAX_BLOCKS = 4096;
+constexpr int32_t DEFAULT_MAX_BLOCKS = 16384;
 
 struct pdlpb_ctx {
     std::string err = "no error";
@@ -70,8 +70,12 @@ struct pdlpb_ctx {
     float *a_ev32 = nullptr, *t_ev32 = nullptr;
     double *c = nullptr, *xl = nullptr, *xu = nullptr, *rl = nullptr, *ru = nullptr;
 
-    // host copies used by set_batch
+    // host copies used by set_batch (the caller's bounds, before any scaling)
     std::vector<double> h_xl, h_xu;
+    // diagonal scaling: the solver works on D_r A D_c (all ones when off)
+    bool scaled = false;
+    std::vector<double> h_dr, h_dc;
+    double *d_dr = nullptr, *d_dc = nullptr;
     double norm_c = 0.0, norm_b = 0.0;
     double eta = 0.0, norm_a = 0.0;
 
@@ -149,6 +153,9 @@ struct pdlpb_ctx {
     bool timing = false;
     int64_t t_counts[4] = {0, 0, 0, 0};
     double t_ms[4] = {0, 0, 0, 0};
+    int64_t t_cols[4] = {0, 0, 0, 0};   // live LP columns summed over the timed launches
+    int32_t cur_cols = 0;               // live LP columns of the launches being enqueued
+    std::vector<int32_t> rec_cols;      // cur_cols at each timed launch (by event pair)
     std::vector<hipEvent_t> ev;
 
     int64_t dev_bytes = 0;
@@ -203,7 +210,8 @@ void free_all(pdlpb_ctx* x) {
     for (auto e : x->ev) (void)hipEventDestroy(e);
     x->ev.clear();
     void* ptrs[] = {x->a_rp, x->a_ci, x->t_rp, x->t_ci, x->a_v64, x->t_v64, x->a_v32, x->t_v32,
-                    x->a_eci, x->t_eci, x->a_ev64, x->t_ev64, x->a_ev32, x->t_ev32,
+                    x->a_eci, x->t_eci, x->a_ev64, x->t_ev64, x->a_ev32, x->t_ev32, x->d_dr,
+                    x->d_dc,
                     x->c, x->xl, x->xu, x->rl, x->ru, x->sl.key, x->sl.tau, x->sl.sigma,
                     x->sl.dval, x->sl.t_start, x->sl.lp, x->ctl, x->rlog, x->base_x, x->adm_rows,
                     x->adm_ctl,
@@ -289,15 +297,17 @@ int compute_opnorm(pdlpb_ctx* x, double* out) {
     return PDLPB_OK;
 }
 
-// default tile for `ncols` live columns: each row group of `lanes` lanes covers
-// lanes*vec consecutive slots; vec never exceeds the width ld was padded for
+// default tile for `ncols` live columns: a row group covers W = lanes * vec
+// consecutive slots with W = 64 (fewer when the batch is narrower), 2 FP64 or
+// 4 FP32 slots per lane once the batch is that wide -- the fastest shape of
+// the 200k x 500k sweeps at B = 64 ... 512 in both precisions; vec never
+// exceeds the width ld was padded for
 Tile heuristic_tile(const pdlpb_ctx* x, int32_t ncols) {
-    int vec = 1;
-    if (x->fp32) vec = ncols >= 256 ? 4 : (ncols >= 128 ? 2 : 1);
-    else vec = ncols >= 128 ? 2 : 1;
+    const int32_t w = std::min<int32_t>(64, next_pow2(ncols > 0 ? ncols : 1));
+    int vec = w >= 64 ? (x->fp32 ? 4 : 2) : 1;
     if (x->opt.tile_vec > 0) vec = x->opt.tile_vec;
     if (vec > x->vec_ld) vec = x->vec_ld;
-    int lanes = next_pow2((ncols + vec - 1) / vec);
+    int lanes = std::max(1, (int)(w / vec));
     if (lanes > 64) lanes = 64;
     if (x->opt.tile_lanes > 0) lanes = x->opt.tile_lanes;
     Tile t;
@@ -430,10 +440,14 @@ int timed_begin(pdlpb_ctx* x, int kind, std::vector<std::pair<int, int>>& rec) {
     const int idx = (int)rec.size();
     while ((int)x->ev.size() < 2 * (idx + 1)) {
         hipEvent_t e;
-        if (hipEventCreate(&e) != hipSuccess) return -1;
+        // timing only: no system-scope fence, so the events neither flush the
+        // caches nor slow the launches they bracket
+        if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return -1;
         x->ev.push_back(e);
     }
     rec.push_back({kind, idx});
+    if ((int)x->rec_cols.size() <= idx) x->rec_cols.resize(idx + 1);
+    x->rec_cols[idx] = x->cur_cols;
     (void)hipEventRecord(x->ev[2 * idx], x->stream);
     return idx;
 }
@@ -579,11 +593,13 @@ int run_solve(pdlpb_ctx* x, double tol, int32_t max_iters) {
                 hipSuccess) {
                 x->t_counts[r.first] += 1;
                 x->t_ms[r.first] += ms;
+                x->t_cols[r.first] += x->rec_cols[r.second];
             }
         }
         rec.clear();
     };
     // prologue: t = 0 is a full evaluation
+    x->cur_cols = x->n_run0;
     int rc = enqueue_iteration<T>(x, 0, 1, prec);
     if (!rc) rc = enqueue_evaluation<T>(x, 0, 1, 0, prec);
     if (rc) return rc;
@@ -597,6 +613,7 @@ int run_solve(pdlpb_ctx* x, double tol, int32_t max_iters) {
         if (ep > max_epochs) return x->fail(PDLPB_EDEVICE, "solve did not terminate");
         // shape the launches for the live columns (compaction shrinks them)
         const int32_t shape = shape_cols(x, n_cols);
+        x->cur_cols = n_cols;
         bool tune_now = false;
         if (shape != x->live || ep == 0) {
             x->live = shape;
@@ -676,6 +693,29 @@ int copy_results(pdlpb_ctx* x, int q, int32_t first, int32_t count, double* dst,
     if (cnt == 0) return PDLPB_OK;
     const hipMemcpyKind kind = mem == PDLPB_MEM_DEVICE ? hipMemcpyDeviceToDevice
                                                         : hipMemcpyDeviceToHost;
+    if (x->scaled) {
+        // back to the caller's coordinates: x = dc x^, y = dr y^
+        const double* d = q < 2 ? x->d_dc : x->d_dr;
+        double* buf = dst;
+        if (mem != PDLPB_MEM_DEVICE) {
+            int rc = ensure_stage(x, (size_t)cnt);
+            if (rc) return rc;
+            buf = x->stage;
+        }
+        if (x->fp32) {
+            const float* src = static_cast<const float*>(x->res[q]) + (size_t)first * rows;
+            HIP_TRY(x, launch_widen(src, cnt, buf, x->stream));
+        } else {
+            const double* src = static_cast<const double*>(x->res[q]) + (size_t)first * rows;
+            HIP_TRY(x, hipMemcpyAsync(buf, src, cnt * sizeof(double), hipMemcpyDeviceToDevice,
+                                      x->stream));
+        }
+        HIP_TRY(x, launch_rescale(buf, d, cnt, (int32_t)rows, 0, x->stream));
+        if (buf != dst)
+            HIP_TRY(x, hipMemcpyAsync(dst, buf, cnt * sizeof(double), kind, x->stream));
+        HIP_TRY(x, hipStreamSynchronize(x->stream));
+        return PDLPB_OK;
+    }
     if (x->fp32) {
         const float* src = static_cast<const float*>(x->res[q]) + (size_t)first * rows;
         if (mem == PDLPB_MEM_DEVICE) {
@@ -704,6 +744,56 @@ int32_t lp_status(const pdlpb_ctx* x, const pdlpb_delta& q) {
     if (q.kind == PDLPB_SET_LO && q.value > x->h_xu[q.var]) return PDLPB_STATUS_INFEASIBLE_BOUNDS;
     if (q.kind == PDLPB_SET_HI && q.value < x->h_xl[q.var]) return PDLPB_STATUS_INFEASIBLE_BOUNDS;
     return PDLPB_STATUS_RUNNING;
+}
+
+// Diagonal scaling of A (pdlpb_options.scaling = 1): `iters` Ruiz passes, each
+// dividing every row and column of the current D_r A D_c by the square root
+// of its infinity norm (both from the same pass's matrix), then one
+// Pock-Chambolle pass with alpha = 1 (square roots of the row and column
+// 1-norms).  Empty rows and columns keep the factor 1.
+void compute_scaling(int32_t m, int32_t n, const int64_t* rp, const int32_t* ci,
+                     const double* v, int iters, std::vector<double>& dr,
+                     std::vector<double>& dc) {
+    dr.assign(m, 1.0);
+    dc.assign(n, 1.0);
+    std::vector<double> rs(m), cs(n);
+    auto scaled = [&](int32_t i, int64_t k) { return std::fabs((dr[i] * v[k]) * dc[ci[k]]); };
+    for (int it = 0; it < iters; ++it) {
+        std::fill(rs.begin(), rs.end(), 0.0);
+        std::fill(cs.begin(), cs.end(), 0.0);
+        for (int32_t i = 0; i < m; ++i)
+            for (int64_t k = rp[i]; k < rp[i + 1]; ++k) {
+                const double a = scaled(i, k);
+                rs[i] = std::max(rs[i], a);
+                cs[ci[k]] = std::max(cs[ci[k]], a);
+            }
+        for (int32_t i = 0; i < m; ++i)
+            if (rs[i] > 0.0) dr[i] = dr[i] * (1.0 / std::sqrt(rs[i]));
+        for (int32_t j = 0; j < n; ++j)
+            if (cs[j] > 0.0) dc[j] = dc[j] * (1.0 / std::sqrt(cs[j]));
+    }
+    std::fill(rs.begin(), rs.end(), 0.0);
+    std::fill(cs.begin(), cs.end(), 0.0);
+    for (int32_t i = 0; i < m; ++i)
+        for (int64_t k = rp[i]; k < rp[i + 1]; ++k) {
+            const double a = scaled(i, k);
+            rs[i] += a;
+            cs[ci[k]] += a;
+        }
+    for (int32_t i = 0; i < m; ++i)
+        if (rs[i] > 0.0) dr[i] = dr[i] * (1.0 / std::sqrt(rs[i]));
+    for (int32_t j = 0; j < n; ++j)
+        if (cs[j] > 0.0) dc[j] = dc[j] * (1.0 / std::sqrt(cs[j]));
+}
+
+// A change of the caller's LP expressed on the scaled one: a bound on x_var
+// becomes value / dc[var], the objective value * e_var becomes value * dc[var].
+pdlpb_delta scaled_delta(const pdlpb_ctx* x, const pdlpb_delta& q) {
+    pdlpb_delta r = q;
+    if (!x->scaled || q.kind == PDLPB_BASE) return r;
+    if (q.kind == PDLPB_OBJ_UNIT) r.value = q.value * x->h_dc[q.var];
+    else r.value = q.value / x->h_dc[q.var];
+    return r;
 }
 
 // Initial primal weight without a warm start: ||c_j|| / ||b|| when both exceed 1e-10, else 1.
@@ -861,6 +951,7 @@ int pdlpb_create(pdlpb_ctx** out, int32_t m, int32_t n, int64_t nnz, const int64
     if (std::isnan(o.infeas_tol) || !std::isfinite(o.infeas_tol)) return bad("infeas_tol must be finite");
     if (!std::isfinite(o.dual_tol)) return bad("dual_tol must be finite");
     if (o.max_blocks < 0) return bad("max_blocks must be >= 0");
+    if (o.scaling != 0 && o.scaling != 1) return bad("scaling must be 0 or 1");
     if (o.max_batch < 1 || o.max_batch > MAX_BATCH) return bad("max_batch must be in [1, 4096]");
     if (o.restart_scope == PDLPB_RESTART_BATCH_AVG && o.max_batch > 1024) o.max_batch = 1024;
     if (o.tile_lanes != 0 && (o.tile_lanes < 1 || o.tile_lanes > 64 ||
@@ -926,6 +1017,42 @@ int pdlpb_create(pdlpb_ctx** out, int32_t m, int32_t n, int64_t nnz, const int64
     }
     e = hipHostMalloc((void**)&x->h_pinned, sizeof(int32_t) * 16, hipHostMallocDefault);
     if (e != hipSuccess) return dev_fail(e, "hipHostMalloc");
+
+    // diagonal scaling: from here on A, c, the row bounds and the variable bounds
+    // are the scaled LP's (the host copies of the caller's bounds stay as given)
+    const double* l_in = l;
+    const double* u_in = u;
+    std::vector<double> s_val, s_c, s_l, s_u, s_b;
+    if (o.scaling == 1) {
+        compute_scaling(m, n, row_ptr, col_idx, val, 10, x->h_dr, x->h_dc);
+        x->scaled = true;
+        s_val.resize((size_t)nnz);
+        for (int32_t i = 0; i < m; ++i)
+            for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k)
+                s_val[k] = (x->h_dr[i] * val[k]) * x->h_dc[col_idx[k]];
+        s_c.resize(n);
+        s_l.resize(n);
+        s_u.resize(n);
+        for (int32_t j = 0; j < n; ++j) {
+            s_c[j] = x->h_dc[j] * c[j];
+            s_l[j] = l[j] / x->h_dc[j];
+            s_u[j] = u[j] / x->h_dc[j];
+        }
+        s_b.resize(m);
+        for (int32_t i = 0; i < m; ++i) {
+            rl[i] = x->h_dr[i] * rl[i];
+            ru[i] = x->h_dr[i] * ru[i];
+            s_b[i] = x->h_dr[i] * b[i];
+        }
+        val = s_val.data();
+        c = s_c.data();
+        l = s_l.data();
+        u = s_u.data();
+        b = s_b.data();
+    } else {
+        x->h_dr.assign(m, 1.0);
+        x->h_dc.assign(n, 1.0);
+    }
 
     // A' in CSR (= A in CSC): counting sort by column keeps row order inside each column
     std::vector<int32_t> h_arp(m + 1), h_trp(n + 1, 0), h_tci(nnz);
@@ -999,8 +1126,12 @@ int pdlpb_create(pdlpb_ctx** out, int32_t m, int32_t n, int64_t nnz, const int64
     if ((e = up(&x->ru, ru.data(), (size_t)m)) != hipSuccess) return dev_fail(e, "upload rows");
     if ((e = x->alloc(&x->g, sizeof(Globals))) != hipSuccess) return dev_fail(e, "alloc");
 
-    x->h_xl.assign(l, l + n);
-    x->h_xu.assign(u, u + n);
+    x->h_xl.assign(l_in, l_in + n);
+    x->h_xu.assign(u_in, u_in + n);
+    if (x->scaled) {
+        if ((e = up(&x->d_dr, x->h_dr.data(), (size_t)m)) != hipSuccess) return dev_fail(e, "upload");
+        if ((e = up(&x->d_dc, x->h_dc.data(), (size_t)n)) != hipSuccess) return dev_fail(e, "upload");
+    }
     double sc = 0.0, sb = 0.0;
     for (int32_t j = 0; j < n; ++j) sc += c[j] * c[j];
     for (int32_t i = 0; i < m; ++i) sb += b[i] * b[i];
@@ -1069,7 +1200,7 @@ int pdlpb_set_batch(pdlpb_ctx* x, int32_t B, const pdlpb_delta* deltas, const do
         SlotCtl cl{};
         key.varkind = (q.kind == PDLPB_BASE ? VAR_NONE : q.var) | (q.kind << 28);
         int32_t status = lp_status(x, q);
-        double w = default_weight(x, q);
+        double w = default_weight(x, scaled_delta(x, q));
         if (w_warm) {
             w = w0[j];
             if (!(w > 0.0) || !std::isfinite(w)) status = PDLPB_STATUS_INVALID_INPUT;
@@ -1086,7 +1217,7 @@ int pdlpb_set_batch(pdlpb_ctx* x, int32_t B, const pdlpb_delta* deltas, const do
             h_key.push_back(key);
             h_tau.push_back(x->eta / w);
             h_sigma.push_back(x->eta * w);
-            h_dval.push_back(q.value);
+            h_dval.push_back(scaled_delta(x, q).value);
             h_lp.push_back(j);
         } else {
             cl.iters = 0;
@@ -1139,9 +1270,22 @@ int pdlpb_set_batch(pdlpb_ctx* x, int32_t B, const pdlpb_delta* deltas, const do
     if (warm_mode != PDLPB_WARM_NONE) {
         const size_t nx = warm_mode == PDLPB_WARM_SHARED ? (size_t)n : (size_t)n * B;
         const size_t ny = warm_mode == PDLPB_WARM_SHARED ? (size_t)m : (size_t)m * B;
-        if (mem == PDLPB_MEM_DEVICE) {
+        if (mem == PDLPB_MEM_DEVICE && !x->scaled) {
             xw = x_warm;
             yw = y_warm;
+        } else if (mem == PDLPB_MEM_DEVICE) {
+            // the caller's vectors mapped to the scaled LP: x / dc, y / dr
+            int rc = ensure_stage(x, nx + ny);
+            if (rc) return rc;
+            HIP_TRY(x, hipMemcpyAsync(x->stage, x_warm, nx * sizeof(double),
+                                      hipMemcpyDeviceToDevice, x->stream));
+            if (ny)
+                HIP_TRY(x, hipMemcpyAsync(x->stage + nx, y_warm, ny * sizeof(double),
+                                          hipMemcpyDeviceToDevice, x->stream));
+            HIP_TRY(x, launch_rescale(x->stage, x->d_dc, (int64_t)nx, n, 1, x->stream));
+            HIP_TRY(x, launch_rescale(x->stage + nx, x->d_dr, (int64_t)ny, m, 1, x->stream));
+            xw = x->stage;
+            yw = x->stage + nx;
         } else {
             int rc = ensure_stage(x, nx + ny);
             if (rc) return rc;
@@ -1150,6 +1294,10 @@ int pdlpb_set_batch(pdlpb_ctx* x, int32_t B, const pdlpb_delta* deltas, const do
             if (ny)
                 HIP_TRY(x, hipMemcpyAsync(x->stage + nx, y_warm, ny * sizeof(double),
                                           hipMemcpyHostToDevice, x->stream));
+            if (x->scaled) {
+                HIP_TRY(x, launch_rescale(x->stage, x->d_dc, (int64_t)nx, n, 1, x->stream));
+                HIP_TRY(x, launch_rescale(x->stage + nx, x->d_dr, (int64_t)ny, m, 1, x->stream));
+            }
             xw = x->stage;
             yw = x->stage + nx;
         }
@@ -1352,6 +1500,10 @@ int pdlpb_set_base_warm(pdlpb_ctx* x, const double* xw, const double* yw, double
     HIP_TRY(x, hipMemcpyAsync(x->base_x, xw, sizeof(double) * x->n, kind, x->stream));
     if (x->m)
         HIP_TRY(x, hipMemcpyAsync(x->base_x + x->n, yw, sizeof(double) * x->m, kind, x->stream));
+    if (x->scaled) {
+        HIP_TRY(x, launch_rescale(x->base_x, x->d_dc, x->n, x->n, 1, x->stream));
+        HIP_TRY(x, launch_rescale(x->base_x + x->n, x->d_dr, x->m, x->m, 1, x->stream));
+    }
     HIP_TRY(x, hipStreamSynchronize(x->stream));
     x->base_w = w;
     x->have_base = true;
@@ -1433,7 +1585,7 @@ int pdlpb_submit(pdlpb_ctx* x, int32_t count, const pdlpb_delta* deltas, int32_t
         // the base dual and weight belong to the base objective: objective changes
         // start from the base primal point only
         double w = (warm_mode == PDLPB_WARM_BASE && q.kind != PDLPB_OBJ_UNIT) ? x->base_w
-                                                                               : default_weight(x, q);
+                                                                               : default_weight(x, scaled_delta(x, q));
         if (status != PDLPB_STATUS_RUNNING) {
             // settled without iterating: record the outcome and zero results
             SlotCtl cl{};
@@ -1458,7 +1610,7 @@ int pdlpb_submit(pdlpb_ctx* x, int32_t count, const pdlpb_delta* deltas, int32_t
         pdlpb_ctx::Pending p;
         p.row = row;
         p.varkind = (q.kind == PDLPB_BASE ? VAR_NONE : q.var) | (q.kind << 28);
-        p.dval = q.value;
+        p.dval = scaled_delta(x, q).value;
         p.w = w;
         p.tol = tol;
         p.max_iters = (int32_t)max_iters;
@@ -1681,13 +1833,28 @@ int pdlpb_get_step_size(const pdlpb_ctx* x, double* eta, double* norm_a) {
     return PDLPB_OK;
 }
 
+int pdlpb_get_scaling(const pdlpb_ctx* x, double* dr, double* dc) {
+    if (!x) return PDLPB_EINVAL;
+    if (dr) std::copy(x->h_dr.begin(), x->h_dr.end(), dr);
+    if (dc) std::copy(x->h_dc.begin(), x->h_dc.end(), dc);
+    return PDLPB_OK;
+}
+
 int pdlpb_set_kernel_timing(pdlpb_ctx* x, int32_t enable) {
     if (!x) return PDLPB_EINVAL;
     x->timing = enable != 0;
     for (int q = 0; q < 4; ++q) {
         x->t_counts[q] = 0;
         x->t_ms[q] = 0.0;
+        x->t_cols[q] = 0;
     }
+    return PDLPB_OK;
+}
+
+int pdlpb_kernel_columns(pdlpb_ctx* x, int64_t cols[4]) {
+    if (!x) return PDLPB_EINVAL;
+    if (!cols) return x->fail(PDLPB_EINVAL, "cols is NULL");
+    for (int q = 0; q < 4; ++q) cols[q] = x->t_cols[q];
     return PDLPB_OK;
 }
 

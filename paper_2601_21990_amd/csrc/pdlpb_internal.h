@@ -219,6 +219,10 @@ hipError_t launch_admit(SlotCtl* ctl, const int32_t* rows, const SlotCtl* src, i
 // Convert n entries of a result block to float64 (FP32 mode).
 hipError_t launch_widen(const float* src, int64_t count, double* dst, hipStream_t s);
 
+// v[k] *= d[k % period], or v[k] /= d[k % period] when divide != 0.
+hipError_t launch_rescale(double* v, const double* d, int64_t count, int32_t period,
+                          int32_t divide, hipStream_t s);
+
 // Power iteration building blocks (float64, one vector).
 hipError_t launch_spmv(const int32_t* rp, const int32_t* ci, const double* v, int32_t rows,
                        const double* x, double* y, hipStream_t s);

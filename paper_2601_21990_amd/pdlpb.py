@@ -35,10 +35,12 @@ STATUS_NAMES = {0: "RUNNING", 1: "OPTIMAL", 2: "ITERATION_LIMIT", 3: "INFEASIBLE
 EXPORTED = ["pdlpb_default_options", "pdlpb_create", "pdlpb_set_batch", "pdlpb_solve",
             "pdlpb_get", "pdlpb_get_batch", "pdlpb_get_trace", "pdlpb_get_dual_objective",
             "pdlpb_obbt_tighten", "pdlpb_branch_scores", "pdlpb_set_tile",
-            "pdlpb_get_step_size", "pdlpb_set_base_warm", "pdlpb_serve_begin", "pdlpb_submit",
+            "pdlpb_get_step_size", "pdlpb_get_scaling", "pdlpb_set_base_warm",
+            "pdlpb_serve_begin", "pdlpb_submit",
             "pdlpb_serve_launch", "pdlpb_serve_wait", "pdlpb_poll", "pdlpb_result",
             "pdlpb_release",
-            "pdlpb_set_kernel_timing", "pdlpb_kernel_times", "pdlpb_device_bytes",
+            "pdlpb_set_kernel_timing", "pdlpb_kernel_times", "pdlpb_kernel_columns",
+            "pdlpb_device_bytes",
             "pdlpb_destroy", "pdlpb_last_error"]
 
 
@@ -58,7 +60,7 @@ class Options(C.Structure):
                 ("tile_lanes", C.c_int32), ("tile_vec", C.c_int32),
                 ("autotune", C.c_int32), ("reserved_pad", C.c_int32),
                 ("dual_tol", C.c_double), ("max_blocks", C.c_int32),
-                ("reserved", C.c_int32 * 3)]
+                ("scaling", C.c_int32), ("reserved", C.c_int32 * 2)]
 
 
 class PdlpbError(RuntimeError):
@@ -97,8 +99,10 @@ def _load():
         "pdlpb_result": (C.c_int, [P, i64, P, P, i32p, dp, dp, i64p, i32]),
         "pdlpb_release": (C.c_int, [P, i64]),
         "pdlpb_get_step_size": (C.c_int, [P, dp, dp]),
+        "pdlpb_get_scaling": (C.c_int, [P, dp, dp]),
         "pdlpb_set_kernel_timing": (C.c_int, [P, i32]),
         "pdlpb_kernel_times": (C.c_int, [P, i64p, dp]),
+        "pdlpb_kernel_columns": (C.c_int, [P, i64p]),
         "pdlpb_device_bytes": (C.c_int64, [P]),
         "pdlpb_destroy": (None, [P]),
         "pdlpb_last_error": (C.c_char_p, [P]),
@@ -133,8 +137,10 @@ pdlpb_poll = lib.pdlpb_poll
 pdlpb_result = lib.pdlpb_result
 pdlpb_release = lib.pdlpb_release
 pdlpb_get_step_size = lib.pdlpb_get_step_size
+pdlpb_get_scaling = lib.pdlpb_get_scaling
 pdlpb_set_kernel_timing = lib.pdlpb_set_kernel_timing
 pdlpb_kernel_times = lib.pdlpb_kernel_times
+pdlpb_kernel_columns = lib.pdlpb_kernel_columns
 pdlpb_device_bytes = lib.pdlpb_device_bytes
 pdlpb_destroy = lib.pdlpb_destroy
 pdlpb_last_error = lib.pdlpb_last_error
@@ -227,6 +233,12 @@ class Context:
         eta, na = C.c_double(), C.c_double()
         self._check(lib.pdlpb_get_step_size(self._h, C.byref(eta), C.byref(na)))
         return eta.value, na.value
+
+    def scaling(self):
+        dr, dc = np.empty(self.m), np.empty(self.n)
+        self._check(lib.pdlpb_get_scaling(self._h, dr.ctypes.data_as(C.POINTER(C.c_double)),
+                                          dc.ctypes.data_as(C.POINTER(C.c_double))))
+        return dr, dc
 
     @property
     def device_bytes(self) -> int:
@@ -379,3 +391,8 @@ class Context:
         ms = (C.c_double * 4)()
         self._check(lib.pdlpb_kernel_times(self._h, cnt, ms))
         return list(cnt), list(ms)
+
+    def kernel_columns(self):
+        cols = (C.c_int64 * 4)()
+        self._check(lib.pdlpb_kernel_columns(self._h, cols))
+        return list(cols)

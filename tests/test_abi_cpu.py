@@ -100,6 +100,8 @@ def test_create_rejects_malformed_input(over, msg):
     (dict(step_size=-1.0), "step_size"),
     (dict(infeas_tol=float("nan")), "infeas_tol"),
     (dict(dual_tol=float("inf")), "dual_tol"),
+    (dict(scaling=2), "scaling"),
+    (dict(max_blocks=-1), "max_blocks"),
 ])
 def test_create_rejects_bad_options(opt, msg):
     with pytest.raises(P.PdlpbError) as e:

@@ -193,6 +193,20 @@ def make_cfg5(base: int = 0, m: int = 200000, n: int = 500000) -> LPInstance:
     return _finish(rng, f"cfg5_{base}", m, n, rows, cols, vals, x0, senses, 0.0, 10.0)
 
 
+def make_badly_scaled(rep: int = 0, m: int = 200, n: int = 500) -> LPInstance:
+    """The 2000 x 5000 family at a smaller size with rows multiplied by
+    10^U[-3, 3] (their right-hand sides with them) and objective entries by
+    10^U[-2, 2]: the same feasible set, entries spread over twelve decades."""
+    inst = make_cfg2(rep, m=m, n=n)
+    rng = np.random.default_rng(seed_for(7, rep))
+    rs = 10.0 ** rng.uniform(-3.0, 3.0, size=m)
+    cs = 10.0 ** rng.uniform(-2.0, 2.0, size=n)
+    rows = np.repeat(np.arange(m), np.diff(inst.row_ptr))
+    return LPInstance(m=m, n=n, row_ptr=inst.row_ptr, col_idx=inst.col_idx,
+                      val=inst.val * rs[rows], c=inst.c * cs, b=inst.b * rs, sense=inst.sense,
+                      l=inst.l, u=inst.u, x0=inst.x0, name="badly_scaled")
+
+
 def make_packing(rep: int = 0, m: int = 200, n: int = 500, k: int = 5,
                  box=(0.0, 10.0)) -> LPInstance:
     """Packing rows with a finite box: k nonzeros per column drawn U[0.5, 1.5],
