@@ -193,6 +193,57 @@ def make_cfg5(base: int = 0, m: int = 200000, n: int = 500000) -> LPInstance:
     return _finish(rng, f"cfg5_{base}", m, n, rows, cols, vals, x0, senses, 0.0, 10.0)
 
 
+def make_setcover(rep: int = 0, m: int = 2000, n: int = 4000, k: int = 8) -> LPInstance:
+    """Set-covering LP relaxation: min c'x, every row covered (sum over its
+    columns >= 1), 0 <= x <= 1.  Each row holds k distinct random columns with
+    coefficient 1; costs c ~ U{1..100}.  x = 1 is feasible."""
+    rng = np.random.default_rng(seed_for(8, rep))
+    cols = np.stack([rng.choice(n, size=k, replace=False) for _ in range(m)]).ravel()
+    rows = np.repeat(np.arange(m), k)
+    row_ptr, col_idx, val = _coo_to_csr(m, rows.astype(np.int64), cols.astype(np.int64),
+                                        np.ones(m * k))
+    c = rng.integers(1, 101, size=n).astype(np.float64)
+    return LPInstance(m=m, n=n, row_ptr=row_ptr, col_idx=col_idx, val=val, c=c,
+                      b=np.ones(m), sense=np.full(m, ord("G"), dtype=np.uint8),
+                      l=np.zeros(n), u=np.ones(n), x0=np.ones(n), name="setcover")
+
+
+def make_facility(rep: int = 0, F: int = 100, C: int = 1000, k: int = 10) -> LPInstance:
+    """Capacitated facility-location LP relaxation on random points in the unit
+    square: facilities i with opening cost f_i ~ U[50, 150] (variables y_i,
+    first F columns), customers j with demand d_j ~ U[5, 35] served by their k
+    nearest facilities (variables x_ij, cost = distance * 100 * d_j).  Rows:
+    sum_i x_ij = 1 for every customer (E); x_ij - y_i <= 0 for every pair (L);
+    sum_j d_j x_ij - s_i y_i <= 0 for every facility (L), with s_i = U[1.05, 2]
+    times the load the even split below puts on i.  Bounds [0, 1].  Opening
+    every facility and splitting each customer evenly over its k facilities is
+    feasible."""
+    rng = np.random.default_rng(seed_for(9, rep))
+    fp = rng.random((F, 2))
+    cp = rng.random((C, 2))
+    dist = np.linalg.norm(cp[:, None, :] - fp[None, :, :], axis=2)
+    near = np.argsort(dist, axis=1)[:, :k]                  # C x k facility indices
+    dem = rng.uniform(5.0, 35.0, size=C)
+    n = F + C * k
+    m = C + C * k + F
+    pair = np.arange(C * k)
+    xcol = F + pair                                          # column of x_ij
+    cust = np.repeat(np.arange(C), k)
+    fac = near.ravel()
+    load = np.bincount(fac, weights=dem[cust] / k, minlength=F)
+    cap = np.where(load > 0, load * rng.uniform(1.05, 2.0, size=F), 1.0)
+    rows = np.concatenate([cust, C + pair, C + pair, C + C * k + fac, C + C * k + np.arange(F)])
+    cols = np.concatenate([xcol, xcol, fac, xcol, np.arange(F)])
+    vals = np.concatenate([np.ones(C * k), np.ones(C * k), -np.ones(C * k), dem[cust], -cap])
+    row_ptr, col_idx, val = _coo_to_csr(m, rows.astype(np.int64), cols.astype(np.int64), vals)
+    c = np.concatenate([rng.uniform(50.0, 150.0, size=F), 100.0 * dist[cust, fac] * dem[cust]])
+    b = np.concatenate([np.ones(C), np.zeros(C * k + F)])
+    sense = np.concatenate([np.full(C, ord("E")), np.full(C * k + F, ord("L"))]).astype(np.uint8)
+    x0 = np.concatenate([np.ones(F), np.full(C * k, 1.0 / k)])
+    return LPInstance(m=m, n=n, row_ptr=row_ptr, col_idx=col_idx, val=val, c=c, b=b,
+                      sense=sense, l=np.zeros(n), u=np.ones(n), x0=x0, name="facility")
+
+
 def make_badly_scaled(rep: int = 0, m: int = 200, n: int = 500) -> LPInstance:
     """The 2000 x 5000 family at a smaller size with rows multiplied by
     10^U[-3, 3] (their right-hand sides with them) and objective entries by
