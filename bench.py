@@ -140,11 +140,60 @@ def spmm_leg():
         q = q0 + (fused_bytes(kind, m, n, nnz, 1, 8, 8) - q0) * cols[kind] / nl
         avg = ms[kind] / nl
         gbs = q / (avg * 1e-3) / 1e9
+        kname = "k_primal" if kind == 0 else "k_dual"
         out[name] = {"achieved": round(gbs, 1), "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(f"spmm_200kx500k_b512_fp64_{kname}_traffic.json",
+                                                 kname),
                      "bytes_per_launch": int(q), "avg_launch_us": round(avg * 1e3, 2),
                      "launches": int(cnt[kind])}
         log(f"spmm {name}: {avg*1e3:.1f} us per launch, {gbs:.1f} GB/s")
     return out
+
+
+def _solve_index(rows):
+    """Solve index (1-based) of every dispatch, in dispatch order: a solve
+    starts at its k_begin_solve dispatch."""
+    idx, cur = [], 0
+    for r in rows:
+        if "k_begin_solve" in r["Kernel_Name"]:
+            cur += 1
+        idx.append(cur)
+    return idx
+
+
+def run_trace_summary(args):
+    """Markdown summary of a rocprofv3 --kernel-trace --stats run: the overall
+    per-kernel statistics and the average duration of each kernel over the
+    dispatches of the chosen solves (the benchmark's event-timed steps)."""
+    import csv
+    import glob
+    d = args.trace_dir
+    stats = glob.glob(os.path.join(d, "**", "*kernel_stats.csv"), recursive=True)[0]
+    trace = glob.glob(os.path.join(d, "**", "*kernel_trace.csv"), recursive=True)[0]
+    rows = sorted(csv.DictReader(open(trace)), key=lambda r: int(r["Dispatch_Id"]))
+    sel = {int(v) for v in args.trace_solves.split(",")}
+    per = {}
+    for r, k in zip(rows, _solve_index(rows)):
+        if k not in sel:
+            continue
+        name = r["Kernel_Name"].split("(")[0].split("::")[-1].split("<")[0]
+        e = per.setdefault(name, [0, 0])
+        e[0] += 1
+        e[1] += int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+    lines = [f"# {args.trace_title}", "", "Command:", "", "```", args.trace_command, "```", "",
+             "## rocprofv3 kernel statistics (whole process)", "",
+             "| kernel | calls | total ms | average us | % |", "|---|---|---|---|---|"]
+    for r in list(csv.DictReader(open(stats)))[: args.trace_top]:
+        lines.append(f"| {r['Name'][:60]} | {r['Calls']} | {int(r['TotalDurationNs']) / 1e6:.3f} | "
+                     f"{float(r['AverageNs']) / 1e3:.3f} | {float(r['Percentage']):.2f} |")
+    lines += ["", f"## Dispatches of solves {sorted(sel)} only", "",
+              "| kernel | dispatches | average us |", "|---|---|---|"]
+    for name, (cnt, ns) in sorted(per.items(), key=lambda kv: -kv[1][1]):
+        lines.append(f"| {name} | {cnt} | {ns / cnt / 1e3:.3f} |")
+    text = "\n".join(lines) + "\n"
+    with open(args.trace_out, "w") as fh:
+        fh.write(text)
+    print(text)
 
 
 def cpu_sample(n_lps, workers):
@@ -558,7 +607,13 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--workload", default="fsb",
                     choices=["fsb", "sweep", "copy", "serve", "obbt", "mixed", "structured",
-                             "pmc-summary"])
+                             "pmc-summary", "trace-summary"])
+    ap.add_argument("--trace-dir", help="rocprofv3 --kernel-trace --stats output folder")
+    ap.add_argument("--trace-solves", default="6,7,8")
+    ap.add_argument("--trace-out", default=None)
+    ap.add_argument("--trace-title", default="kernel trace")
+    ap.add_argument("--trace-command", default="")
+    ap.add_argument("--trace-top", type=int, default=16)
     ap.add_argument("--pmc-fetch", help="rocprofv3 output folder of the FETCH_SIZE run")
     ap.add_argument("--pmc-write", help="rocprofv3 output folder of the WRITE_SIZE run")
     ap.add_argument("--pmc-kernel", default="k_dual")
@@ -595,6 +650,8 @@ def main():
     ap.add_argument("--cpu-lps", type=int, default=256)
     ap.add_argument("--no-spmm", action="store_true",
                     help="skip the 200k x 500k product-kernel point")
+    ap.add_argument("--tile-lanes", type=int, default=0, help="fixed lanes per row group (0: auto)")
+    ap.add_argument("--tile-vec", type=int, default=0, help="fixed LPs per lane (0: auto)")
     ap.add_argument("--plain-lps", type=int, default=64, help="LPs of the batch solved one at a time")
     ap.add_argument("--graphs", type=int, default=1)
     args = ap.parse_args()
@@ -615,6 +672,9 @@ def main():
         return
     if args.workload == "structured":
         run_structured(args)
+        return
+    if args.workload == "trace-summary":
+        run_trace_summary(args)
         return
     if args.workload == "pmc-summary":
         run_pmc_summary(args)
