@@ -698,7 +698,7 @@ def main():
     m, n, nnz = inst.m, inst.n, inst.nnz
     log(f"instance m={m} n={n} nnz={nnz}")
 
-    opts = dict(device=0, use_graphs=args.graphs)
+    opts = dict(device=0, use_graphs=args.graphs, tile_lanes=args.tile_lanes, tile_vec=args.tile_vec)
     ctx = P.Context.from_instance(inst, **opts)
     eta, norm_a = ctx.step_size
     log(f"eta={eta:.6g} ||A||={norm_a:.6g}")

@@ -399,7 +399,15 @@ __global__ __launch_bounds__(256) void k_eval(EvalArgs<T> a) {
     for (int q = 0; q < NTERM; ++q) acc[q] = 0.0;
 
     const int32_t ncols = min(a.ncols, a.g->n_cols);
+    // between full evaluations only LPs at the start of a restart cycle (their
+    // residual r(z^{n,0})) or at their last iteration read these sums
+    bool need = false;
     if (s < ncols) {
+        const SlotKey key = a.sl.key[s];
+        const int32_t t = a.g->t0 + a.it;
+        need = a.full || t == key.t_anchor || t >= key.t_end;
+    }
+    if (need) {
         const int32_t varkind = a.sl.key[s].varkind;
         const int32_t r0 = panel * 4 * pw + wave * pw;
         const int32_t r1 = min(r0 + pw, rows);
@@ -667,9 +675,11 @@ __global__ __launch_bounds__(1024) void k_control(ControlArgs a) {
         } else if (final_now) {
             status = PDLPB_STATUS_ITERATION_LIMIT;
         }
-        cl.kkt[0] = gap; cl.kkt[1] = pri; cl.kkt[2] = dua; cl.kkt[3] = rel;
-        cl.obj = cx;
-        cl.dobj = -phis;
+        if (a.full || k == 0 || final_now) {   // the evaluation computed this LP's sums
+            cl.kkt[0] = gap; cl.kkt[1] = pri; cl.kkt[2] = dua; cl.kkt[3] = rel;
+            cl.obj = cx;
+            cl.dobj = -phis;
+        }
         if (status != PDLPB_STATUS_RUNNING) {
             const int32_t t_last = t < st.t_end ? t : st.t_end;
             cl.status = status;

@@ -307,7 +307,10 @@ Tile heuristic_tile(const pdlpb_ctx* x, int32_t ncols) {
     int vec = w >= 64 ? (x->fp32 ? 4 : 2) : 1;
     if (x->opt.tile_vec > 0) vec = x->opt.tile_vec;
     if (vec > x->vec_ld) vec = x->vec_ld;
-    int lanes = std::max(1, (int)(w / vec));
+    // at least 8 lanes per row group: a narrow batch (few live LPs) still spreads
+    // its rows over many waves (the idle lanes return at once), which is what
+    // keeps the latency-bound iterations of a shrinking batch short
+    int lanes = std::max(8, (int)(w / vec));
     if (lanes > 64) lanes = 64;
     if (x->opt.tile_lanes > 0) lanes = x->opt.tile_lanes;
     Tile t;
@@ -391,8 +394,10 @@ StepArgs<T> step_args(pdlpb_ctx* x, bool primal, int32_t it, int32_t eval, int32
 }
 
 template <typename T>
-EvalArgs<T> eval_args(pdlpb_ctx* x) {
+EvalArgs<T> eval_args(pdlpb_ctx* x, int32_t it, int32_t full) {
     EvalArgs<T> a{};
+    a.it = it;
+    a.full = full;
     T* const* b = reinterpret_cast<T* const*>(x->blk);
     a.n = x->n; a.m = x->m; a.ld = x->ld; a.ncols = x->live;
     a.a_rp = x->a_rp; a.a_ci = x->a_ci;
@@ -470,7 +475,7 @@ int enqueue_iteration(pdlpb_ctx* x, int32_t it, int32_t eval,
 template <typename T>
 int enqueue_evaluation(pdlpb_ctx* x, int32_t it, int32_t full, int32_t advance,
                        std::vector<std::pair<int, int>>* rec, int32_t admit = 0) {
-    EvalArgs<T> e = eval_args<T>(x);
+    EvalArgs<T> e = eval_args<T>(x, it, full);
     ControlArgs c = control_args(x, it, full, advance, admit);
     int idx = -1;
     if (rec) idx = timed_begin(x, 2, *rec);

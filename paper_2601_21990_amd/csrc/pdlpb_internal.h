@@ -139,6 +139,9 @@ struct EvalArgs {
     int32_t npx, npy;        // row panels (4 waves each) on each side
     double* part_x;          // [NTERM][ld][npx]
     double* part_y;          // [NTERM][ld][npy]
+    int32_t it;              // iteration index inside the block; global t = g->t0 + it
+    int32_t full;            // 1: every running LP's sums; 0: only LPs at the start of a
+                             // restart cycle (k = 0) or at their last iteration need them
 };
 
 struct ControlArgs {
