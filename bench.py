@@ -320,8 +320,9 @@ def run_copy(args):
 
 def run_serve(args):
     """Serving stream: four resident base LPs (the 200k x 500k family by
-    default, FP32 products with FP64 sums), each with its root solution kept
-    on the device as warm start.  Requests arrive as a Poisson process; each
+    default, FP64; --serve-prec fp32 for FP32 iterates with FP64 sums, which
+    cannot certify the infeasible branches of this family, see the design
+    notes), each with its root solution kept on the device as warm start.  Requests arrive as a Poisson process; each
     is a strong-branching batch of 2..512 LPs (log-uniform, even) on a random
     base.  The loop admits requests as columns and result rows free up and
     reports p50 / p99 latency and LPs/s per arrival rate."""
@@ -628,7 +629,7 @@ def main():
     ap.add_argument("--mixed-iters", type=int, default=20000)
     ap.add_argument("--serve-m", type=int, default=200000)
     ap.add_argument("--serve-bases", type=int, default=4)
-    ap.add_argument("--serve-prec", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--serve-prec", default="fp64", choices=["fp32", "fp64"])
     ap.add_argument("--serve-cols", type=int, default=1024)
     ap.add_argument("--serve-rows", type=int, default=2048)
     ap.add_argument("--serve-rates", default="1,3,10")
