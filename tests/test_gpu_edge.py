@@ -1,0 +1,83 @@
+"""Degenerate shapes through the C ABI against the oracle: no rows at all,
+only free rows (the box-only closed form), empty rows and columns, a matrix
+without nonzeros, and one-variable LPs."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle as O
+from tests.gpu_common import rel_err, ITER_RTOL
+from workloads import deltas, BASE, SET_LO, SET_HI, OBJ_UNIT
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2601_21990_amd.pdlpb as P
+    return P
+
+
+def _ctx(P, A, b, sense, c, l, u, **kw):
+    A = sp.csr_matrix(A)
+    return P.Context(A.shape[0], A.shape[1], A.indptr.astype(np.int64), A.indices.astype(np.int32),
+                     A.data, c, b, np.frombuffer(sense.encode(), dtype=np.uint8), l, u, **kw)
+
+
+def _oracle_lp(A, b, sense, c, l, u):
+    A = sp.csr_matrix(A)
+    return O.from_arrays(A.shape[0], A.shape[1], A.indptr, A.indices, A.data, c, b,
+                         np.frombuffer(sense.encode(), dtype=np.uint8), l, u)
+
+
+CASES = {
+    "no_rows": (np.zeros((0, 3)), np.zeros(0), "", [1.0, -2.0, 0.5], [0.0, -1.0, 2.0],
+                [4.0, 3.0, 5.0]),
+    "free_rows": ([[1.0, 2.0, 0.0], [0.0, 1.0, -1.0]], [3.0, 1.0], "NN", [1.0, -2.0, 0.5],
+                  [0.0, -1.0, 2.0], [4.0, 3.0, 5.0]),
+    "empty_row_and_column": ([[1.0, 0.0, 1.0, 0.0], [0.0, 0.0, 0.0, 0.0], [2.0, 0.0, -1.0, 0.0]],
+                             [2.0, 0.0, 1.0], "ELG", [1.0, 3.0, 1.0, -1.0],
+                             [0.0, 0.0, 0.0, 0.0], [5.0, 5.0, 5.0, 2.0]),
+    "no_nonzeros": (np.zeros((2, 3)), [0.0, 1.0], "EL", [2.0, -1.0, 0.0], [0.0, 0.0, -1.0],
+                    [1.0, 1.0, 1.0]),
+    "one_variable": ([[2.0]], [3.0], "L", [-1.0], [0.0], [10.0]),
+}
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+@pytest.mark.parametrize("K", [1, 50])
+def test_degenerate_shapes_match_oracle(P, name, K):
+    """Fixed iteration counts below the first full evaluation after t = 0: these
+    LPs reach their optima exactly, and with tol = 0 the rounding of a full
+    evaluation's sums (zero or not) would decide where each side stops."""
+    A, b, sense, c, l, u = CASES[name]
+    lp = _oracle_lp(A, b, sense, c, l, u)
+    eta = O.step_size(lp.A)
+    n = lp.n
+    D = deltas([BASE, SET_LO, SET_HI, OBJ_UNIT], [0, n - 1, 0, n - 1], [0.0, 0.5, 0.5, -1.0])
+    with _ctx(P, A, b, sense, c, l, u, step_size=eta) as ctx:
+        ctx.set_batch(D)
+        ctx.solve(tol=0.0, max_iters=K)
+        got = [ctx.get(j) for j in range(len(D))]
+    for j, d in enumerate(D):
+        lpj = O.apply_delta(lp, int(d["kind"]), int(d["var"]), float(d["value"]))
+        r = O.solve(lpj, O.Options(tol=0.0, max_iters=K, step_size=eta))
+        assert got[j]["status"] == r.status and got[j]["iters"] == r.iters, (name, j)
+        assert rel_err(got[j]["x"], r.x) <= ITER_RTOL, (name, j)
+        if lp.m:
+            assert rel_err(got[j]["y"], r.y) <= ITER_RTOL, (name, j)
+
+
+def test_box_only_closed_form(P):
+    """Free rows only: each x_j ends at the bound its cost sign selects and y = 0."""
+    A, b, sense, c, l, u = CASES["free_rows"]
+    with _ctx(P, A, b, sense, c, l, u) as ctx:
+        ctx.set_batch(deltas([BASE], [0], [0.0]))
+        ctx.solve(tol=1e-10, max_iters=10000)
+        r = ctx.get(0)
+    c, l, u = map(np.asarray, (c, l, u))
+    want = np.where(c > 0, l, np.where(c < 0, u, np.clip(0.0, l, u)))
+    assert r["status"] == P.STATUS_OPTIMAL
+    np.testing.assert_allclose(r["x"], want, atol=1e-9)
+    np.testing.assert_array_equal(r["y"], np.zeros(2))
+    assert r["obj"] == pytest.approx(float(c @ want), abs=1e-9)
