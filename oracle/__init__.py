@@ -10,12 +10,21 @@ Only the test suite, the smoke check and the benchmark's CPU-baseline leg may
 import this package.  It shares no code with the GPU library (kernels, headers,
 helpers or constants), and the GPU library never calls it.
 
+Also: `oracle.mip` (safe bound-tightening bounds and strong-branching scores
+from per-LP results, Sections 5.1, 5.2 and the OBBT experiments of Section 6)
+and `oracle.scaling` (diagonal preconditioning in front of the same solver,
+the problem scaling named in Section 2).
+
 Pins: every function is checked in the CPU test suite against closed forms,
 brute-force vertex enumeration, an independent LP solver (HiGHS via scipy),
 first-order optimality of the proximal steps, firm nonexpansiveness, and
-KKT/complementary-slackness invariants.  Parity unpinned: iterate trajectories
-and iteration counts (the paper prints none), and the values of the restart
-constants beta_s, beta_n, beta_a, theta (named, not valued, in the paper).
+KKT/complementary-slackness invariants; the scaling against its own closed
+forms (a diagonal matrix equilibrated in one pass, the Pock-Chambolle bound
+||D_r A D_c|| <= 1) and objective invariance; the MIP outputs against exact
+variable ranges and child optima from vertex enumeration and HiGHS.  Parity
+unpinned: iterate trajectories and iteration counts (the paper prints none),
+and the values of the restart constants beta_s, beta_n, beta_a, theta (named,
+not valued, in the paper).
 """
 from .lp import LP, row_bounds, from_arrays, from_instance, apply_delta, BASE, SET_LO, SET_HI, OBJ_UNIT
 from .pdhg import (Options, Result, KKT, solve, solve_batch_avg, pdhg_operator,
