@@ -158,7 +158,9 @@ int pdlpb_create(pdlpb_ctx** out, int32_t m, int32_t n, int64_t nnz,
  * one whose change is not a number gets PDLPB_STATUS_INVALID_INPUT; neither
  * is iterated and neither affects the others.  A kind outside 0..3 or a var
  * outside [0, n) fails the call with PDLPB_EINVAL.  Device storage grows to
- * the largest B seen and is reused for smaller batches.
+ * the largest B seen and is reused for smaller batches.  A batch ends any
+ * serving session on the context (its queued requests and results are
+ * dropped; pdlpb_serve_begin starts a new one).
  */
 int pdlpb_set_batch(pdlpb_ctx* ctx, int32_t B, const pdlpb_delta* deltas,
                     const double* x_warm, const double* y_warm, const double* w_warm,

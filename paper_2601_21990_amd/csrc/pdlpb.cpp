@@ -1239,6 +1239,12 @@ int pdlpb_set_batch(pdlpb_ctx* x, int32_t B, const pdlpb_delta* deltas, const do
     }
     const size_t esz = x->fp32 ? sizeof(float) : sizeof(double);
     x->drop_graph();   // grid shapes and slot count are baked into the captured launches
+    // a batch ends any serving session: its queue, ids and results are dropped
+    x->serving = false;
+    x->queue.clear();
+    x->completed.clear();
+    x->id_row.clear();
+    x->free_rows.clear();
     x->B = B;
     x->ld = ld;
     x->n_run0 = n_run0;

@@ -186,3 +186,21 @@ def test_objective_change_warm_base_starts_from_base_primal(P, base):
         assert got[i]["iters"] == ref["iters"][j]
         np.testing.assert_array_equal(got[i]["x"], ref["X"][j])
         np.testing.assert_array_equal(got[i]["y"], ref["Y"][j])
+
+
+def test_batch_after_serving_ends_the_session(P, base):
+    inst, lp, eta, root = base
+    r1, _, _ = _requests(inst, root)
+    with make_ctx(inst, eta) as ctx:
+        ctx.serve_begin(16)
+        ctx.submit(r1[:2], P.WARM_NONE, 1e-4, 20000)
+        ctx.set_batch(r1[:2])
+        ctx.solve(tol=1e-4, max_iters=20000)
+        assert np.all(ctx.get_batch(want_x=False, want_y=False)["status"] == P.STATUS_OPTIMAL)
+        with pytest.raises(P.PdlpbError) as e:
+            ctx.serve_launch()
+        assert e.value.code == P.ESTATE
+        ctx.serve_begin(16)                        # a new session works again
+        ids = ctx.submit(r1[:2], P.WARM_NONE, 1e-4, 20000)
+        got = _serve_until_done(P, ctx, list(ids))
+        assert all(g["status"] == P.STATUS_OPTIMAL for g in got.values())
