@@ -336,7 +336,8 @@ def run_serve(args):
     ctxs, roots = [], []
     for b in range(args.serve_bases):
         inst = make_cfg5(base=b, m=m, n=n)
-        ctx = P.Context.from_instance(inst, device=0, precision=prec, max_batch=args.serve_cols)
+        ctx = P.Context.from_instance(inst, device=0, precision=prec, max_batch=args.serve_cols,
+                                      eval_every=args.serve_eval)
         ctx.set_batch(deltas([BASE], [0], [0.0]))
         ctx.solve(tol=1e-5, max_iters=50000)
         root = ctx.get(0)
@@ -395,6 +396,7 @@ def run_serve(args):
                                              f"(4 N(0,1) nnz/col), requests of 2..512 "
                                              f"strong-branching LPs, warm start, tol 1e-4",
                                  "precision": args.serve_prec, "columns": args.serve_cols,
+                                 "eval_every": args.serve_eval,
                                  "result_rows": args.serve_rows},
                       "rates": lines}), flush=True)
 
@@ -458,19 +460,13 @@ def run_obbt(args):
         "optimum_at_box_bound_fraction": round(float(at_bound), 4)}), flush=True)
 
 
-def run_mixed(args):
-    """Uneven mixed batching over eight base matrices (m = 1k ... 100k,
-    n = 2.5 m, 4..12 N(0,1) nonzeros per column, box [0,10]): each base LP is
-    solved on the GPU first; then 1000 LPs arrive as per-matrix batches of
-    2..512 (log-uniform), half bound flips of fractional root values, half
-    objectives +-e_j.  All batches are queued at once and the continuous-
-    batching loop drains them, every context replaying captured blocks of
-    iterations; LPs/s = LPs that reached 1e-4 / wall time."""
+def _mixed_pass(args, prec):
+    """One pass of the mixed workload at one precision; returns the wall time,
+    the requests (statuses, iterations, objectives per LP) and the base info."""
     import numpy as np
     import paper_2601_21990_amd.pdlpb as P
     from paper_2601_21990_amd.serve import Server, Request
     from workloads import make_cfg4, fsb_deltas, obbt_deltas, deltas, BASE, seed_for
-    prec = P.MIXED32 if args.mixed_prec == "fp32" else P.FP64
     ctxs, roots = [], []
     for i in range(8):
         inst = make_cfg4(i)
@@ -487,21 +483,26 @@ def run_mixed(args):
         ctx.serve_begin(1024)
         ctxs.append(ctx)
         roots.append((root["x"], cand, inst.n))
-    rng = np.random.default_rng(seed_for(4, 999))
-    reqs, total = [], 0
-    while total < args.mixed_lps:
-        b = int(rng.integers(0, 8))
-        size = int(round(np.exp(rng.uniform(np.log(2), np.log(512))) / 2)) * 2
-        size = max(2, min(512, size, args.mixed_lps - total))
-        x, cand, n = roots[b]
-        if len(reqs) % 2 == 0 and cand.size >= size // 2:
-            v = np.sort(rng.choice(cand, size=size // 2, replace=False)).astype(np.int32)
-            d = fsb_deltas(x, v)
-        else:
-            v = np.sort(rng.choice(n, size=size // 2, replace=False)).astype(np.int32)
-            d = obbt_deltas(v)
-        reqs.append((b, d))
-        total += len(d)
+    # the request stream depends on the seed and, for bound flips, on each
+    # base's fractional root values; the FP64 pass reuses the FP32 pass's stream
+    reqs = getattr(args, "_mixed_reqs", None)
+    if reqs is None:
+        rng = np.random.default_rng(seed_for(4, 999))
+        reqs, total = [], 0
+        while total < args.mixed_lps:
+            b = int(rng.integers(0, 8))
+            size = int(round(np.exp(rng.uniform(np.log(2), np.log(512))) / 2)) * 2
+            size = max(2, min(512, size, args.mixed_lps - total))
+            x, cand, n = roots[b]
+            if len(reqs) % 2 == 0 and cand.size >= size // 2:
+                v = np.sort(rng.choice(cand, size=size // 2, replace=False)).astype(np.int32)
+                d = fsb_deltas(x, v)
+            else:
+                v = np.sort(rng.choice(n, size=size // 2, replace=False)).astype(np.int32)
+                d = obbt_deltas(v)
+            reqs.append((b, d))
+            total += len(d)
+        args._mixed_reqs = reqs
     srv = Server(ctxs, warm=True)
     t0 = time.perf_counter()
     tagged = []
@@ -511,12 +512,31 @@ def run_mixed(args):
         tagged.append(r)
     srv.drain()
     wall = time.perf_counter() - t0
-    solved = sum(sum(1 for s in r.statuses.values() if s == P.STATUS_OPTIMAL) for r in srv.completed)
+    for c in ctxs:
+        c.close()
+    return wall, tagged
+
+
+def run_mixed(args):
+    """Uneven mixed batching over eight base matrices (m = 1k ... 100k,
+    n = 2.5 m, 4..12 N(0,1) nonzeros per column, box [0,10]): each base LP is
+    solved on the GPU first; then 1000 LPs arrive as per-matrix batches of
+    2..512 (log-uniform), half bound flips of fractional root values, half
+    objectives +-e_j.  All batches are queued at once and the continuous-
+    batching loop drains them, every context replaying captured blocks of
+    iterations; LPs/s = LPs that reached 1e-4 / wall time.  The measured pass
+    uses FP32 iterates with FP64 sums (--mixed-prec); an FP64 pass of the same
+    requests gives the precision statement (objective difference per LP)."""
+    import numpy as np
+    import paper_2601_21990_amd.pdlpb as P
+    prec = P.MIXED32 if args.mixed_prec == "fp32" else P.FP64
+    wall, tagged = _mixed_pass(args, prec)
+    solved = sum(sum(1 for s in r.statuses.values() if s == P.STATUS_OPTIMAL) for r in tagged)
     kinds = {}
     for r in tagged:
         kind = "objective" if int(r.deltas["kind"][0]) == 3 else "bound"
-        st = np.array(list(r.statuses.values()))
-        it = np.array(list(r.iters.values()))
+        st = np.array([r.statuses[i] for i in r.ids])
+        it = np.array([r.iters[i] for i in r.ids])
         e = kinds.setdefault(kind, {"lps": 0, "optimal": 0, "iters": []})
         e["lps"] += len(st)
         e["optimal"] += int(np.sum(st == P.STATUS_OPTIMAL))
@@ -527,17 +547,32 @@ def run_mixed(args):
         e["iters_median"] = int(np.median(e["iters"]))
         e["iters_max"] = int(np.max(e["iters"]))
         del e["iters"]
-    for c in ctxs:
-        c.close()
+    precision = None
+    if prec == P.MIXED32 and not args.no_precision:
+        wall64, tagged64 = _mixed_pass(args, P.FP64)
+        d, both = [], 0
+        for r32, r64 in zip(tagged, tagged64):
+            for i32, i64 in zip(r32.ids, r64.ids):
+                if r32.statuses[i32] == P.STATUS_OPTIMAL and r64.statuses[i64] == P.STATUS_OPTIMAL:
+                    o32, o64 = r32.objs[i32], r64.objs[i64]
+                    d.append(abs(o32 - o64) / (1.0 + abs(o64)))
+        solved64 = sum(sum(1 for s in r.statuses.values() if s == P.STATUS_OPTIMAL)
+                       for r in tagged64)
+        precision = {"lps_compared": len(d), "obj_rel_diff_max": float(np.max(d)),
+                     "obj_rel_diff_median": float(np.median(d)),
+                     "fp64_lps_per_s": round(solved64 / wall64, 2)}
+        log(f"precision: {json.dumps(precision)}")
     print(json.dumps({
         "metric": "LPs solved/s to 1e-4 rel KKT (uneven mixed batches over 8 bases)",
         "value": round(solved / wall, 2), "unit": "LPs/s",
         "config": {"workload": "8 bases m=1k..100k, n=2.5m, 4..12 N(0,1) nnz/col, box [0,10]; "
-                               f"{total} LPs in {len(reqs)} batches of 2..512, half bound flips, "
-                               "half +-e_j objectives, warm start from each base",
+                               f"{sum(len(r.ids) for r in tagged)} LPs in {len(tagged)} batches "
+                               "of 2..512, half bound flips, half +-e_j objectives, warm start "
+                               "from each base",
                    "precision": args.mixed_prec},
-        "lps": srv.lps_done, "optimal": solved, "wall_s": round(wall, 3),
-        "by_kind": kinds, "max_iters": args.mixed_iters}), flush=True)
+        "lps": sum(len(r.ids) for r in tagged), "optimal": solved, "wall_s": round(wall, 3),
+        "by_kind": kinds, "max_iters": args.mixed_iters, "precision_statement": precision}),
+        flush=True)
 
 
 def run_structured(args):
@@ -627,6 +662,14 @@ def main():
     ap.add_argument("--mixed-lps", type=int, default=1000)
     ap.add_argument("--mixed-prec", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--mixed-iters", type=int, default=20000)
+    ap.add_argument("--no-precision", action="store_true",
+                    help="mixed: skip the FP64 pass of the precision statement")
+    ap.add_argument("--serve-eval", type=int, default=16,
+                    help="serve: iterations between evaluations (the block length)")
+    ap.add_argument("--eval-every", type=int, default=16,
+                    help="fsb: iterations between evaluations of the batch")
+    ap.add_argument("--plain-eval-every", type=int, default=64,
+                    help="fsb: iterations between evaluations of the one-LP-at-a-time leg")
     ap.add_argument("--serve-m", type=int, default=200000)
     ap.add_argument("--serve-bases", type=int, default=4)
     ap.add_argument("--serve-prec", default="fp64", choices=["fp32", "fp64"])
@@ -699,8 +742,11 @@ def main():
     m, n, nnz = inst.m, inst.n, inst.nnz
     log(f"instance m={m} n={n} nnz={nnz}")
 
-    opts = dict(device=0, use_graphs=args.graphs, tile_lanes=args.tile_lanes, tile_vec=args.tile_vec)
+    opts = dict(device=0, use_graphs=args.graphs, tile_lanes=args.tile_lanes, tile_vec=args.tile_vec,
+                eval_every=args.eval_every)
     ctx = P.Context.from_instance(inst, **opts)
+    # the one-LP-at-a-time leg runs at the evaluation interval that suits one LP best
+    ctx_plain = P.Context.from_instance(inst, **{**opts, "eval_every": args.plain_eval_every})
     eta, norm_a = ctx.step_size
     log(f"eta={eta:.6g} ||A||={norm_a:.6g}")
 
@@ -784,7 +830,15 @@ def main():
     kernel_us = {names[k]: round(total_ms[k] / max(counts[k], 1) * 1e3, 3) for k in range(4)}
 
     # plain PDHG: the same LPs one at a time (B = 1) with the same library
+    ctx.close()
+    ctx = ctx_plain
     np_plain = min(args.plain_lps, B)
+    for j in range(min(2, np_plain)):          # untimed: graphs for B = 1
+        rc = P.lib.pdlpb_set_batch(ctx._h, 1, d_deltas.data_ptr() + 16 * j, d_x.data_ptr(),
+                                   d_y.data_ptr(), d_w.data_ptr(), P.WARM_SHARED, P.MEM_DEVICE)
+        ctx._check(rc)
+        ctx.B = 1
+        ctx.solve(tol=1e-4, max_iters=100000)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     plain_solved = 0
@@ -811,7 +865,8 @@ def main():
         cpu = {"value": round(cs / cdt, 2), "unit": "LPs/s", "cores": workers, "kind": "oracle",
                "sample": f"{args.cpu_lps} strong-branching LPs of the same 2000x5000 family, "
                          f"warm-started from the reference solver's own root solve, "
-                         f"one LP per process task; {cs} solved in {cdt:.2f}s"}
+                         f"one LP per process task, evaluation interval 64 (its default); "
+                         f"{cs} solved in {cdt:.2f}s"}
         log(f"cpu: {cpu['value']} LPs/s")
 
     ctx.close()
@@ -832,9 +887,11 @@ def main():
         "config": {"workload": "strong-branching batch: A 2000x5000 (5 N(0,1) nnz/col), 1000 E + "
                                "1000 L rows, box [0,10], B=64 bound changes on 32 fractional "
                                "variables, warm start from the root LP, FP64, tol 1e-4 rel KKT",
-                   "m": m, "n": n, "nnz": nnz, "B": B, "tol": 1e-4},
+                   "m": m, "n": n, "nnz": nnz, "B": B, "tol": 1e-4,
+                   "eval_every": args.eval_every},
         "plain": {"value": round(plain_value, 2), "unit": "LPs/s", "lps": np_plain,
-                  "iters_median": int(np.median(plain_iters))},
+                  "iters_median": int(np.median(plain_iters)),
+                  "eval_every": args.plain_eval_every},
         "batched_vs_plain": round(value / plain_value, 3) if plain_value > 0 else None,
         "event_timed_pass_s": round(event_dt, 4),
         "iters": {"min": int(out["iters"].min()), "median": int(np.median(out["iters"])),

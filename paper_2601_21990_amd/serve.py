@@ -38,6 +38,7 @@ class Request:
     done: Optional[float] = None
     statuses: Dict[int, int] = field(default_factory=dict)
     iters: Dict[int, int] = field(default_factory=dict)
+    objs: Dict[int, float] = field(default_factory=dict)
 
     @property
     def latency(self) -> float:
@@ -106,6 +107,7 @@ class Server:
                 r = self.ctx[k].result(i, want_x=self.keep_results, want_y=self.keep_results)
                 req.statuses[i] = r["status"]
                 req.iters[i] = r["iters"]
+                req.objs[i] = r["obj"]
                 if self.keep_results:
                     self.results[(k, i)] = r
                 self.ctx[k].release(i)

@@ -81,22 +81,25 @@ def _cfg2_ctx(P, inst, eta, base, D, **kw):
     return ctx
 
 
+@pytest.mark.parametrize("C", [64, 16])
 @pytest.mark.parametrize("K", [1, 65, 200])
-def test_cfg2_batch_fixed_iterations(P, K):
+def test_cfg2_batch_fixed_iterations(P, K, C):
     inst, lp, eta, base, D = cfg2_setup()
-    with _cfg2_ctx(P, inst, eta, base, D) as ctx:
+    with _cfg2_ctx(P, inst, eta, base, D, eval_every=C) as ctx:
         ctx.solve(tol=0.0, max_iters=K)
         res = [(ctx.get(j), ctx.get_trace(j)) for j in range(len(D))]
     worst = 0.0
     for j, d in enumerate(D):
-        ores = oracle_run(lp_for(lp, d), eta, 0.0, K, base.x, base.y, base.w)
-        worst = max(worst, assert_trajectory_match(*res[j], ores, what=f"LP {j} K={K}"))
-    print(f"cfg2 K={K}: worst rel err {worst:.2e}")
+        ores = oracle_run(lp_for(lp, d), eta, 0.0, K, base.x, base.y, base.w, eval_every=C)
+        worst = max(worst, assert_trajectory_match(*res[j], ores, what=f"LP {j} K={K} C={C}"))
+    print(f"cfg2 K={K} C={C}: worst rel err {worst:.2e}")
 
 
-def test_cfg2_batch_converged(P):
+# C = 16 is the evaluation interval the strong-branching benchmark runs with
+@pytest.mark.parametrize("C", [64, 16])
+def test_cfg2_batch_converged(P, C):
     inst, lp, eta, base, D = cfg2_setup()
-    with _cfg2_ctx(P, inst, eta, base, D) as ctx:
+    with _cfg2_ctx(P, inst, eta, base, D, eval_every=C) as ctx:
         ctx.solve(tol=1e-4, max_iters=100000)
         out = ctx.get_batch()
         traces = [ctx.get_trace(j) for j in range(len(D))]
@@ -105,7 +108,8 @@ def test_cfg2_batch_converged(P):
     assert np.all(out["kkt"][opt, 3] <= 1e-4)
     same_traj = 0
     for j, d in enumerate(D):
-        ores = oracle_run(lp_for(lp, d), eta, 1e-4, 100000, base.x, base.y, base.w)
+        ores = oracle_run(lp_for(lp, d), eta, 1e-4, 100000, base.x, base.y, base.w,
+                          eval_every=C)
         assert out["status"][j] == ores.status, (j, out["status"][j], ores.status)
         if ores.status == O.OPTIMAL:
             assert abs(out["obj"][j] - ores.obj) <= 4e-4 * (1 + abs(ores.obj)), j
