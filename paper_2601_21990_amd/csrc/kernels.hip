@@ -119,6 +119,8 @@ struct Head {
     int32_t j[EW];
     T a[EW];
 };
+template <typename T>
+struct Head<T, 0> {};
 
 template <typename T, int EW>
 struct HeadVals;
@@ -149,42 +151,73 @@ struct HeadVals<float, EW> {
     }
 };
 
+// Everything one row of a step needs before its gathers: the row's CSR range
+// and ELL head, the streamed block entries of the lane's slots and the row's
+// base data.  None of it depends on the batch state, so a wave issues the
+// loads of its first row together with those of the batch and slot state.
 template <typename T, int VEC, int EW>
-__device__ __forceinline__ void row_product(const StepArgs<T>& a, int32_t row, int32_t s0,
-                                            T* acc) {
+struct RowOps {
+    int32_t kb, ke;
+    T z[VEC], z0[VEC];
+    double c, lo, hi;
+    Head<T, EW> h;
+};
+
+template <typename T, int VEC, int EW, bool PRIMAL>
+__device__ __forceinline__ void load_row(const StepArgs<T>& a, int32_t row, int32_t s0,
+                                         RowOps<T, VEC, EW>& op) {
+    op.kb = a.rp[row];
+    op.ke = a.rp[row + 1];
 #pragma unroll
-    for (int v = 0; v < VEC; ++v) acc[v] = T(0);
-    const int32_t kb = a.rp[row], ke = a.rp[row + 1];
+    for (int v = 0; v < VEC; ++v) {
+        if (s0 + v < a.ncols) {
+            const size_t e = (size_t)row * a.ld + s0 + v;
+            op.z[v] = a.Z[e];
+            op.z0[v] = a.Z0[e];
+        }
+    }
+    op.c = PRIMAL ? a.c[row] : 0.0;
+    op.lo = a.lo[row];
+    op.hi = a.hi[row];
     if constexpr (EW > 0) {
-        Head<T, EW> h;
         const int4* q = reinterpret_cast<const int4*>(a.eci + (size_t)row * EW);
 #pragma unroll
         for (int i = 0; i < EW / 4; ++i) {
             const int4 w = q[i];
-            h.j[4 * i] = w.x;
-            h.j[4 * i + 1] = w.y;
-            h.j[4 * i + 2] = w.z;
-            h.j[4 * i + 3] = w.w;
+            op.h.j[4 * i] = w.x;
+            op.h.j[4 * i + 1] = w.y;
+            op.h.j[4 * i + 2] = w.z;
+            op.h.j[4 * i + 3] = w.w;
         }
-        HeadVals<T, EW>::load(a.ev + (size_t)row * EW, h.a);
+        HeadVals<T, EW>::load(a.ev + (size_t)row * EW, op.h.a);
+    }
+}
+
+template <typename T, int VEC, int EW>
+__device__ __forceinline__ void row_product(const StepArgs<T>& a, const RowOps<T, VEC, EW>& op,
+                                            int32_t s0, T* acc) {
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) acc[v] = T(0);
+    if constexpr (EW > 0) {
 #pragma unroll
         for (int c0 = 0; c0 < EW; c0 += CH) {
             T g[CH][VEC];
 #pragma unroll
             for (int u = 0; u < CH; ++u) {
-                if (h.j[c0 + u] >= 0)
-                    VecT<T, VEC>::load(a.G + (size_t)h.j[c0 + u] * a.ld + s0, g[u]);
+                if (op.h.j[c0 + u] >= 0)
+                    VecT<T, VEC>::load(a.G + (size_t)op.h.j[c0 + u] * a.ld + s0, g[u]);
             }
 #pragma unroll
             for (int u = 0; u < CH; ++u) {
-                if (h.j[c0 + u] >= 0) {
+                if (op.h.j[c0 + u] >= 0) {
 #pragma unroll
-                    for (int v = 0; v < VEC; ++v) acc[v] = fma(h.a[c0 + u], g[u][v], acc[v]);
+                    for (int v = 0; v < VEC; ++v) acc[v] = fma(op.h.a[c0 + u], g[u][v], acc[v]);
                 }
             }
         }
     }
-    for (int32_t k0 = kb + EW; k0 < ke; k0 += CH) {
+    const int32_t ke = op.ke;
+    for (int32_t k0 = op.kb + EW; k0 < ke; k0 += CH) {
         int32_t j[CH];
         T w[CH];
 #pragma unroll
@@ -214,6 +247,23 @@ __device__ __forceinline__ void row_product(const StepArgs<T>& a, int32_t row, i
 // Halpern weights of eq:mainiter for inner index k: (k+1)/(k+2) and 1/(k+2).
 __device__ __forceinline__ double halpern_a(int32_t k) { return double(k + 1) / double(k + 2); }
 
+// Makes the kernel arguments that the first round of loads uses resident in
+// scalar registers at entry, so they arrive in one batch instead of in the
+// order the branches below would request them.
+template <typename T>
+__device__ __forceinline__ void fetch_args(const StepArgs<T>& a, const double* slot_step) {
+    asm volatile("" ::"s"(a.rows), "s"(a.ncols), "s"(a.ld), "s"(a.wpb), "s"(a.it), "s"(a.g),
+                 "s"(a.sl.key), "s"(slot_step), "s"(a.rp), "s"(a.Z), "s"(a.Z0), "s"(a.lo),
+                 "s"(a.hi), "s"(a.eci), "s"(a.ev));
+}
+
+// Both step kernels start the same way.  A lane covers VEC slots from s0 of the
+// rows RPW = 64/G apart that its wave visits; waves stride over row groups (the
+// grid may hold fewer waves than groups).  The live column count, the lane's
+// slot keys and step sizes, and the first row's operands are loaded in one
+// round; only then do lanes past the live count, or whose slots all rest,
+// leave.  Bounds on the host-side column count keep every load in the blocks.
+
 // ---------------------------------------------------------------------------
 // Primal step fused with G = A'Y (Section 5, eq:main-iterate, first line):
 //   x^k  = x0                               if k == 0
@@ -229,11 +279,34 @@ __global__ __launch_bounds__(256) void k_primal(StepArgs<T> a) {
     constexpr int RPW = 64 / G;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
+    fetch_args(a, a.sl.tau);
     const int32_t s0 = blockIdx.y * (G * VEC) + (lane % G) * VEC;
-    const int32_t ncols = min(a.ncols, a.g->n_cols);
-    if (s0 >= ncols) return;
-    const int32_t t = a.g->t0 + a.it;
+    int32_t rw = (int32_t)blockIdx.x * a.wpb + wave;
+    if (s0 >= a.ncols || rw * RPW >= a.rows) return;
+    const int32_t wstride = (int32_t)gridDim.x * a.wpb;
 
+    // one round of loads: batch state, slot state, first row (the batch state is
+    // read through vector loads, which queue in order with the others)
+    const __attribute__((address_space(1))) Globals* gv =
+        (const __attribute__((address_space(1))) Globals*)a.g;
+    asm volatile("" : "+v"(gv));
+    const int32_t gcols = gv->n_cols;
+    const int32_t t = gv->t0 + a.it;
+    SlotKey key[VEC];
+    double tau_d[VEC];
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) {
+        if (s0 + v < a.ncols) {
+            key[v] = a.sl.key[s0 + v];
+            tau_d[v] = a.sl.tau[s0 + v];
+        }
+    }
+    int32_t row = rw * RPW + lane / G;
+    RowOps<T, VEC, EW> op;
+    if (row < a.rows) load_row<T, VEC, EW, true>(a, row, s0, op);
+
+    const int32_t ncols = min(a.ncols, gcols);
+    if (s0 >= ncols) return;
     // per-slot operands: a lane keeps its slots for every row it visits
     bool live[VEC], last[VEC];
     int32_t varkind[VEC], kk[VEC];
@@ -247,48 +320,30 @@ __global__ __launch_bounds__(256) void k_primal(StepArgs<T> a) {
         kk[v] = 0;
         tau[v] = T(0);
         if (s0 + v < ncols) {
-            const SlotKey key = a.sl.key[s0 + v];
-            live[v] = (key.flags & SLOT_ACTIVE) && t <= key.t_end &&
-                      (!a.admit || (key.flags & SLOT_NEW));
-            last[v] = (t == key.t_end);
-            varkind[v] = key.varkind;
-            kk[v] = t - key.t_anchor;
-            tau[v] = T(a.sl.tau[s0 + v]);
+            live[v] = (key[v].flags & SLOT_ACTIVE) && t <= key[v].t_end &&
+                      (!a.admit || (key[v].flags & SLOT_NEW));
+            last[v] = (t == key[v].t_end);
+            varkind[v] = key[v].varkind;
+            kk[v] = t - key[v].t_anchor;
+            tau[v] = T(tau_d[v]);
         }
         any = any || live[v];
     }
     if (!any) return;
     const bool keep = a.eval != 0;
 
-    // waves stride over row groups of RPW rows; the grid may hold fewer waves than groups
-    const int32_t wstride = (int32_t)gridDim.x * a.wpb;
-    for (int32_t rw = (int32_t)blockIdx.x * a.wpb + wave; rw * RPW < a.rows; rw += wstride) {
-        const int32_t row = rw * RPW + lane / G;
-        if (row >= a.rows) continue;
-        // operands of the epilogue, fetched before the product so their latency overlaps it
-        T zb[VEC], z0[VEC];
-#pragma unroll
-        for (int v = 0; v < VEC; ++v) {
-            if (s0 + v < ncols) {
-                const size_t e = (size_t)row * a.ld + s0 + v;
-                zb[v] = a.Z[e];
-                z0[v] = a.Z0[e];
-            }
-        }
-        const double cb = a.c[row], lb = a.lo[row], hb = a.hi[row];
-
+    auto step = [&](int32_t r, const RowOps<T, VEC, EW>& o) {
         T acc[VEC];
-        row_product<T, VEC, EW>(a, row, s0, acc);
-
+        row_product<T, VEC, EW>(a, o, s0, acc);
 #pragma unroll
         for (int v = 0; v < VEC; ++v) {
             const int32_t s = s0 + v;
             if (!live[v]) continue;
-            const size_t e = (size_t)row * a.ld + s;
-            const VarData d = var_data(varkind[v], a.sl.dval, s, row, cb, lb, hb);
+            const size_t e = (size_t)r * a.ld + s;
+            const VarData d = var_data(varkind[v], a.sl.dval, s, r, o.c, o.lo, o.hi);
             const int32_t k = kk[v];
-            const T x0 = z0[v];
-            const T xk = (k == 0) ? x0 : T(double(k) / double(k + 1)) * zb[v] + x0 / T(k + 1);
+            const T x0 = o.z0[v];
+            const T xk = (k == 0) ? x0 : T(double(k) / double(k + 1)) * o.z[v] + x0 / T(k + 1);
             const T xt = clampt<T>(xk - tau[v] * (T(d.c) + acc[v]), T(d.lo), T(d.hi));
             a.Z[e] = T(2) * xt - xk;
             if (keep || last[v]) {
@@ -296,6 +351,14 @@ __global__ __launch_bounds__(256) void k_primal(StepArgs<T> a) {
                 a.DZ[e] = xt - xk;
             }
         }
+    };
+    if (row < a.rows) step(row, op);
+    for (rw += wstride; rw * RPW < a.rows; rw += wstride) {
+        row = rw * RPW + lane / G;
+        if (row >= a.rows) continue;
+        RowOps<T, VEC, EW> o;
+        load_row<T, VEC, EW, true>(a, row, s0, o);
+        step(row, o);
     }
 }
 
@@ -310,11 +373,34 @@ __global__ __launch_bounds__(256) void k_dual(StepArgs<T> a) {
     constexpr int RPW = 64 / G;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
+    fetch_args(a, a.sl.sigma);
     const int32_t s0 = blockIdx.y * (G * VEC) + (lane % G) * VEC;
-    const int32_t ncols = min(a.ncols, a.g->n_cols);
-    if (s0 >= ncols) return;
-    const int32_t t = a.g->t0 + a.it;
+    int32_t rw = (int32_t)blockIdx.x * a.wpb + wave;
+    if (s0 >= a.ncols || rw * RPW >= a.rows) return;
+    const int32_t wstride = (int32_t)gridDim.x * a.wpb;
 
+    // one round of loads: batch state, slot state, first row (the batch state is
+    // read through vector loads, which queue in order with the others)
+    const __attribute__((address_space(1))) Globals* gv =
+        (const __attribute__((address_space(1))) Globals*)a.g;
+    asm volatile("" : "+v"(gv));
+    const int32_t gcols = gv->n_cols;
+    const int32_t t = gv->t0 + a.it;
+    SlotKey key[VEC];
+    double sig_d[VEC];
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) {
+        if (s0 + v < a.ncols) {
+            key[v] = a.sl.key[s0 + v];
+            sig_d[v] = a.sl.sigma[s0 + v];
+        }
+    }
+    int32_t row = rw * RPW + lane / G;
+    RowOps<T, VEC, EW> op;
+    if (row < a.rows) load_row<T, VEC, EW, false>(a, row, s0, op);
+
+    const int32_t ncols = min(a.ncols, gcols);
+    if (s0 >= ncols) return;
     bool live[VEC], last[VEC];
     T sig[VEC], wa[VEC], wb[VEC];
     bool any = false;
@@ -326,12 +412,11 @@ __global__ __launch_bounds__(256) void k_dual(StepArgs<T> a) {
         wa[v] = T(0);
         wb[v] = T(1);
         if (s0 + v < ncols) {
-            const SlotKey key = a.sl.key[s0 + v];
-            live[v] = (key.flags & SLOT_ACTIVE) && t <= key.t_end &&
-                      (!a.admit || (key.flags & SLOT_NEW));
-            last[v] = (t == key.t_end);
-            const int32_t k = t - key.t_anchor;
-            sig[v] = T(a.sl.sigma[s0 + v]);
+            live[v] = (key[v].flags & SLOT_ACTIVE) && t <= key[v].t_end &&
+                      (!a.admit || (key[v].flags & SLOT_NEW));
+            last[v] = (t == key[v].t_end);
+            const int32_t k = t - key[v].t_anchor;
+            sig[v] = T(sig_d[v]);
             wa[v] = T(halpern_a(k));
             wb[v] = T(k + 2);
         }
@@ -340,30 +425,16 @@ __global__ __launch_bounds__(256) void k_dual(StepArgs<T> a) {
     if (!any) return;
     const bool keep = a.eval != 0;
 
-    const int32_t wstride = (int32_t)gridDim.x * a.wpb;
-    for (int32_t rw = (int32_t)blockIdx.x * a.wpb + wave; rw * RPW < a.rows; rw += wstride) {
-        const int32_t row = rw * RPW + lane / G;
-        if (row >= a.rows) continue;
-        T zy[VEC], z0[VEC];
-#pragma unroll
-        for (int v = 0; v < VEC; ++v) {
-            if (s0 + v < ncols) {
-                const size_t e = (size_t)row * a.ld + s0 + v;
-                zy[v] = a.Z[e];
-                z0[v] = a.Z0[e];
-            }
-        }
-        const T l = T(a.lo[row]), u = T(a.hi[row]);
-
+    auto step = [&](int32_t r, const RowOps<T, VEC, EW>& o) {
+        const T l = T(o.lo), u = T(o.hi);
         T acc[VEC];
-        row_product<T, VEC, EW>(a, row, s0, acc);
-
+        row_product<T, VEC, EW>(a, o, s0, acc);
 #pragma unroll
         for (int v = 0; v < VEC; ++v) {
             if (!live[v]) continue;
-            const size_t e = (size_t)row * a.ld + s0 + v;
-            const T yk = zy[v];
-            const T y0 = z0[v];
+            const size_t e = (size_t)r * a.ld + s0 + v;
+            const T yk = o.z[v];
+            const T y0 = o.z0[v];
             const T sg = sig[v];
             const T q = yk / sg + acc[v];
             const T yt = sg * (q - clampt<T>(q, l, u));
@@ -373,6 +444,14 @@ __global__ __launch_bounds__(256) void k_dual(StepArgs<T> a) {
                 a.DZ[e] = yt - yk;
             }
         }
+    };
+    if (row < a.rows) step(row, op);
+    for (rw += wstride; rw * RPW < a.rows; rw += wstride) {
+        row = rw * RPW + lane / G;
+        if (row >= a.rows) continue;
+        RowOps<T, VEC, EW> o;
+        load_row<T, VEC, EW, false>(a, row, s0, o);
+        step(row, o);
     }
 }
 
