@@ -401,6 +401,32 @@ def run_serve(args):
                       "rates": lines}), flush=True)
 
 
+def _plain_leg(ctx, dD, X, Y, n_lps, max_iters):
+    """The first n_lps LPs of a batch solved one at a time (B = 1) by the same
+    context, cold start, after two untimed ones; LPs/s of those solved."""
+    import torch
+    import paper_2601_21990_amd.pdlpb as P
+    n_lps = min(n_lps, dD.numel() // 16)
+
+    def one(j):
+        ctx.set_batch(dD[16 * j:16 * (j + 1)], mem=P.MEM_DEVICE)
+        ctx.solve(tol=1e-4, max_iters=max_iters)
+        r = ctx.get_batch(X=X[0:1], Y=Y[0:1], mem=P.MEM_DEVICE)
+        return int(r["status"][0] == P.STATUS_OPTIMAL), int(r["iters"][0])
+
+    for j in range(min(2, n_lps)):
+        one(j)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = [one(j) for j in range(n_lps)]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    solved = sum(r[0] for r in res)
+    log(f"plain: {n_lps} LPs one at a time in {dt:.3f}s -> {solved / dt:.1f} LPs/s")
+    return {"value": round(solved / dt, 2), "unit": "LPs/s", "lps": n_lps,
+            "iters_median": int(sorted(r[1] for r in res)[n_lps // 2])}
+
+
 def run_obbt(args):
     """Bound-tightening batch (Section 5.2) on the 20000 x 50000 family with 8
     U[-1,1] nonzeros per column, rows of mixed sense and box [0,5]: 256 LPs
@@ -438,18 +464,23 @@ def run_obbt(args):
                          lps_per_s=ok / dt)
         log(f"{name}: {ok}/{B} optimal, median {dt*1e3:.1f} ms per batch -> {ok/dt:.1f} LPs/s, "
             f"iters median {int(np.median(r['iters']))} max {int(np.max(r['iters']))}")
+        if name == "fp32":
+            out["plain"] = _plain_leg(ctx, dD, X, Y, args.plain_lps, args.obbt_iters)
     a, b = out["fp64"]["res"], out["fp32"]["res"]
     both = (a["status"] == P.STATUS_OPTIMAL) & (b["status"] == P.STATUS_OPTIMAL)
     dobj = np.abs(b["obj"] - a["obj"]) / (1.0 + np.abs(a["obj"]))
     vars_ = D["var"]
     xv = out["fp64"]["x"][np.arange(B), vars_]
     at_bound = np.mean((np.abs(xv - inst.l[vars_]) < 1e-6) | (np.abs(xv - inst.u[vars_]) < 1e-6))
-    for v in out.values():
-        v["ctx"].close()
+    for k in ("fp32", "fp64"):
+        out[k]["ctx"].close()
     print(json.dumps({
         "metric": "LPs solved/s to 1e-4 rel KKT (bound tightening, MIXED32)",
         "value": round(out["fp32"]["lps_per_s"], 2), "unit": "LPs/s",
         "fp64_lps_per_s": round(out["fp64"]["lps_per_s"], 2),
+        "plain": out["plain"],
+        "batched_vs_plain": round(out["fp32"]["lps_per_s"] / out["plain"]["value"], 3)
+        if out["plain"]["value"] > 0 else None,
         "config": {"workload": f"A {inst.m}x{inst.n}, 8 U[-1,1] nnz/col, E/L/G rows, box [0,5], "
                                f"B={B} objectives +-e_j, cold start, tol 1e-4",
                    "B": B, "steps": args.steps, "warmup": args.warmup},
@@ -512,9 +543,35 @@ def _mixed_pass(args, prec):
         tagged.append(r)
     srv.drain()
     wall = time.perf_counter() - t0
+    plain = None
+    if getattr(args, "_mixed_plain", False):
+        # the same loop fed one LP at a time: plain_lps LPs spread evenly over
+        # the requests (both kinds, every base), after two untimed ones
+        per = -(-args.plain_lps // len(reqs))
+        sample = []
+        for b, d in reqs:
+            for j in np.linspace(0, len(d) - 1, min(per, len(d))).astype(int):
+                sample.append((b, d[j:j + 1]))
+        sample = sample[:args.plain_lps]
+
+        def one(b, d):
+            r = Request(base=b, deltas=d, arrival=time.perf_counter(), tol=1e-4,
+                        max_iters=args.mixed_iters)
+            srv.submit(r)
+            srv.drain()
+            return r
+
+        for b, d in sample[:2]:
+            one(b, d)
+        t1 = time.perf_counter()
+        done = [one(b, d) for b, d in sample]
+        pdt = time.perf_counter() - t1
+        ok = sum(1 for r in done for st in r.statuses.values() if st == P.STATUS_OPTIMAL)
+        plain = {"value": round(ok / pdt, 2), "unit": "LPs/s", "lps": len(sample)}
+        log(f"plain: {len(sample)} LPs one at a time in {pdt:.3f}s -> {ok / pdt:.1f} LPs/s")
     for c in ctxs:
         c.close()
-    return wall, tagged
+    return wall, tagged, plain
 
 
 def run_mixed(args):
@@ -530,7 +587,9 @@ def run_mixed(args):
     import numpy as np
     import paper_2601_21990_amd.pdlpb as P
     prec = P.MIXED32 if args.mixed_prec == "fp32" else P.FP64
-    wall, tagged = _mixed_pass(args, prec)
+    args._mixed_plain = True
+    wall, tagged, plain = _mixed_pass(args, prec)
+    args._mixed_plain = False
     solved = sum(sum(1 for s in r.statuses.values() if s == P.STATUS_OPTIMAL) for r in tagged)
     kinds = {}
     for r in tagged:
@@ -549,7 +608,7 @@ def run_mixed(args):
         del e["iters"]
     precision = None
     if prec == P.MIXED32 and not args.no_precision:
-        wall64, tagged64 = _mixed_pass(args, P.FP64)
+        wall64, tagged64, _ = _mixed_pass(args, P.FP64)
         d, both = [], 0
         for r32, r64 in zip(tagged, tagged64):
             for i32, i64 in zip(r32.ids, r64.ids):
@@ -570,6 +629,9 @@ def run_mixed(args):
                                "of 2..512, half bound flips, half +-e_j objectives, warm start "
                                "from each base",
                    "precision": args.mixed_prec},
+        "plain": plain,
+        "batched_vs_plain": round(solved / wall / plain["value"], 3) if plain and plain["value"] > 0
+        else None,
         "lps": sum(len(r.ids) for r in tagged), "optimal": solved, "wall_s": round(wall, 3),
         "by_kind": kinds, "max_iters": args.mixed_iters, "precision_statement": precision}),
         flush=True)
