@@ -330,7 +330,11 @@ __global__ __launch_bounds__(256) void k_primal(StepArgs<T> a) {
         any = any || live[v];
     }
     if (!any) return;
-    const bool keep = a.eval != 0;
+    // z~ and the displacement are stored for the evaluation that reads them
+    bool keep[VEC];
+#pragma unroll
+    for (int v = 0; v < VEC; ++v)
+        keep[v] = last[v] || a.eval == 2 || (a.eval == 1 && kk[v] == 0);
 
     auto step = [&](int32_t r, const RowOps<T, VEC, EW>& o) {
         T acc[VEC];
@@ -346,7 +350,7 @@ __global__ __launch_bounds__(256) void k_primal(StepArgs<T> a) {
             const T xk = (k == 0) ? x0 : T(double(k) / double(k + 1)) * o.z[v] + x0 / T(k + 1);
             const T xt = clampt<T>(xk - tau[v] * (T(d.c) + acc[v]), T(d.lo), T(d.hi));
             a.Z[e] = T(2) * xt - xk;
-            if (keep || last[v]) {
+            if (keep[v]) {
                 a.Zt[e] = xt;
                 a.DZ[e] = xt - xk;
             }
@@ -401,21 +405,22 @@ __global__ __launch_bounds__(256) void k_dual(StepArgs<T> a) {
 
     const int32_t ncols = min(a.ncols, gcols);
     if (s0 >= ncols) return;
-    bool live[VEC], last[VEC];
+    bool live[VEC], keep[VEC];
     T sig[VEC], wa[VEC], wb[VEC];
     bool any = false;
 #pragma unroll
     for (int v = 0; v < VEC; ++v) {
         live[v] = false;
-        last[v] = false;
+        keep[v] = false;
         sig[v] = T(1);
         wa[v] = T(0);
         wb[v] = T(1);
         if (s0 + v < ncols) {
             live[v] = (key[v].flags & SLOT_ACTIVE) && t <= key[v].t_end &&
                       (!a.admit || (key[v].flags & SLOT_NEW));
-            last[v] = (t == key[v].t_end);
             const int32_t k = t - key[v].t_anchor;
+            // y~ and the displacement are stored for the evaluation that reads them
+            keep[v] = t == key[v].t_end || a.eval == 2 || (a.eval == 1 && k == 0);
             sig[v] = T(sig_d[v]);
             wa[v] = T(halpern_a(k));
             wb[v] = T(k + 2);
@@ -423,7 +428,6 @@ __global__ __launch_bounds__(256) void k_dual(StepArgs<T> a) {
         any = any || live[v];
     }
     if (!any) return;
-    const bool keep = a.eval != 0;
 
     auto step = [&](int32_t r, const RowOps<T, VEC, EW>& o) {
         const T l = T(o.lo), u = T(o.hi);
@@ -439,7 +443,7 @@ __global__ __launch_bounds__(256) void k_dual(StepArgs<T> a) {
             const T q = yk / sg + acc[v];
             const T yt = sg * (q - clampt<T>(q, l, u));
             a.Z[e] = wa[v] * (T(2) * yt - yk) + y0 / wb[v];
-            if (keep || last[v]) {
+            if (keep[v]) {
                 a.Zt[e] = yt;
                 a.DZ[e] = yt - yk;
             }
@@ -477,6 +481,8 @@ __global__ __launch_bounds__(256) void k_eval(EvalArgs<T> a) {
 #pragma unroll
     for (int q = 0; q < NTERM; ++q) acc[q] = 0.0;
 
+    // an evaluation of fresh cycles with none to evaluate (the last full one found none)
+    if (!a.full && a.g->quiet) return;
     const int32_t ncols = min(a.ncols, a.g->n_cols);
     // between full evaluations only LPs at the start of a restart cycle (their
     // residual r(z^{n,0})) or at their last iteration read these sums
@@ -490,11 +496,18 @@ __global__ __launch_bounds__(256) void k_eval(EvalArgs<T> a) {
         const int32_t varkind = a.sl.key[s].varkind;
         const int32_t r0 = panel * 4 * pw + wave * pw;
         const int32_t r1 = min(r0 + pw, rows);
+        // each row's own operands are loaded before its product and the next
+        // row's pointers during it, so a row costs one chain of dependent loads
         if (xside) {
+            int32_t kb_next = r0 < r1 ? a.t_rp[r0] : 0;
             for (int32_t i = r0; i < r1; ++i) {
                 // (A' y~)_i, (A' dy)_i and (A' Pi_B[l,u](dy))_i over the rows of column i
                 double g = 0.0, h = 0.0, pdy = 0.0;
-                const int32_t kb = a.t_rp[i], ke = a.t_rp[i + 1];
+                const int32_t kb = kb_next, ke = a.t_rp[i + 1];
+                kb_next = ke;
+                const size_t e = (size_t)i * a.ld + s;
+                const double xt = a.Xt[e], dx = a.DX[e], x0 = a.X0[e];
+                const double ci = a.c[i], xli = a.xl[i], xui = a.xu[i];
                 for (int32_t k0 = kb; k0 < ke; k0 += CH) {
                     int32_t jj[CH];
                     double vv[CH];
@@ -527,9 +540,7 @@ __global__ __launch_bounds__(256) void k_eval(EvalArgs<T> a) {
                         }
                     }
                 }
-                const size_t e = (size_t)i * a.ld + s;
-                const double xt = a.Xt[e], dx = a.DX[e], x0 = a.X0[e];
-                const VarData d = var_data(varkind, a.sl.dval, s, i, a.c[i], a.xl[i], a.xu[i]);
+                const VarData d = var_data(varkind, a.sl.dval, s, i, ci, xli, xui);
                 const double rc = barrier(-d.c - g, d.lo, d.hi);        // r~ (reduced cost at y~)
                 const double rk = barrier(-d.c - (g - h), d.lo, d.hi);  // r at y^k = y~ - dy
                 const double dr = barrier(rc - rk, d.lo, d.hi);
@@ -549,9 +560,14 @@ __global__ __launch_bounds__(256) void k_eval(EvalArgs<T> a) {
                 acc[9] += rx * rx;
             }
         } else {
+            int32_t kb_next = r0 < r1 ? a.a_rp[r0] : 0;
             for (int32_t i = r0; i < r1; ++i) {
                 double ax = 0.0, adx = 0.0;                       // (A x~)_i, (A dx)_i
-                const int32_t kb = a.a_rp[i], ke = a.a_rp[i + 1];
+                const int32_t kb = kb_next, ke = a.a_rp[i + 1];
+                kb_next = ke;
+                const size_t e = (size_t)i * a.ld + s;
+                const double yt = a.Yt[e], dy = a.DY[e], y0 = a.Y0[e];
+                const double l = a.rl[i], u = a.ru[i];
                 for (int32_t k0 = kb; k0 < ke; k0 += CH) {
                     int32_t jj[CH];
                     double vv[CH];
@@ -581,9 +597,6 @@ __global__ __launch_bounds__(256) void k_eval(EvalArgs<T> a) {
                         }
                     }
                 }
-                const size_t e = (size_t)i * a.ld + s;
-                const double yt = a.Yt[e], dy = a.DY[e], y0 = a.Y0[e];
-                const double l = a.rl[i], u = a.ru[i];
                 const double pres = ax - clampd(ax, l, u);
                 const double ea = yt - y0;
                 const double ra = adx - recession(adx, l, u);
@@ -602,18 +615,18 @@ __global__ __launch_bounds__(256) void k_eval(EvalArgs<T> a) {
     for (int q = 0; q < NTERM; ++q) red[wave][q][lane] = acc[q];
     __syncthreads();
     if (wave == 0 && s < ncols) {
-        // layout [term][slot][panel]: the reduction reads each (term, slot) row of panels contiguously
-        const int32_t np = xside ? a.npx : a.npy;
-        double* out = (xside ? a.part_x : a.part_y) + (size_t)s * np + panel;
+        // layout [panel][term][slot]: a block writes its panel's sums as whole
+        // rows of consecutive slots (one full cache line per 16 FP64 slots)
+        double* out = (xside ? a.part_x : a.part_y) + (size_t)panel * NTERM * a.ld + s;
 #pragma unroll
         for (int q = 0; q < NTERM; ++q) {
             const double v = ((red[0][q][lane] + red[1][q][lane]) + red[2][q][lane]) + red[3][q][lane];
-            out[(size_t)q * a.ld * np] = v;
+            out[(size_t)q * a.ld] = v;
         }
     }
 }
 
-// sums[q][s] = sum over panels of part[q][s][panel]; q < NTERM: x side, else y side.
+// sums[q][s] = sum over panels of part[panel][q][s]; q < NTERM: x side, else y side.
 // One wave per (term, slot): lane l adds panels l, l+64, ... in order, then a
 // butterfly over the 64 lanes (every lane ends with the same bits, since each
 // level adds the same pair in either order).  The tree depends on the panel
@@ -622,13 +635,15 @@ __global__ __launch_bounds__(256) void k_reduce(ControlArgs a) {
     const int32_t lane = threadIdx.x & 63;
     const int32_t pair = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (pair >= 2 * NTERM * a.ncols) return;
+    if (!a.full && !a.admit && a.g->quiet) return;
     const int32_t q = pair / a.ncols, s = pair % a.ncols;
     const bool xside = q < NTERM;
     const int32_t qq = xside ? q : q - NTERM;
     const int32_t np = xside ? a.npx : a.npy;
-    const double* p = (xside ? a.part_x : a.part_y) + ((size_t)qq * a.ld + s) * np;
+    const double* p = (xside ? a.part_x : a.part_y) + (size_t)qq * a.ld + s;
+    const size_t stride = (size_t)NTERM * a.ld;
     double acc = 0.0;
-    for (int32_t i = lane; i < np; i += 64) acc += p[i];
+    for (int32_t i = lane; i < np; i += 64) acc += p[(size_t)i * stride];
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
     if (lane == 0) a.sums[(size_t)q * a.ld + s] = acc;
@@ -693,6 +708,7 @@ __global__ __launch_bounds__(1024) void k_control(ControlArgs a) {
     __shared__ int32_t sh_flags[MAX_BATCH];
     __shared__ int32_t sh_flag;
     Globals* g = a.g;
+    if (!a.full && !a.admit && g->quiet) return;
     const int32_t t = g->t0 + a.it;
     const int32_t nc = min(a.ncols, g->n_cols);
     const double eta = g->eta;
@@ -705,6 +721,7 @@ __global__ __launch_bounds__(1024) void k_control(ControlArgs a) {
     }
     __syncthreads();
 
+    int32_t my_fresh = 0;   // running LPs that the next evaluation of fresh cycles reads
     // pass 1: stopping tests, residuals, per-LP restarts
     for (int32_t s = threadIdx.x; s < nc; s += blockDim.x) {
         SlotKey& st = a.sl.key[s];
@@ -789,6 +806,7 @@ __global__ __launch_bounds__(1024) void k_control(ControlArgs a) {
                 cl.r_prev = r;
             }
         }
+        if ((st.flags & SLOT_FRESH) || st.t_end <= t + 1) my_fresh += 1;
     }
 
     // batch-average scope: mean residual over running LPs, shared decision
@@ -845,6 +863,17 @@ __global__ __launch_bounds__(1024) void k_control(ControlArgs a) {
         __syncthreads();
     }
     const int32_t n_run = sh_n[0];
+    // a full pass decides whether the next evaluation of fresh cycles has work
+    // (never skipped under the batch-average scope or after admissions)
+    __syncthreads();
+    sh_n[threadIdx.x] = my_fresh;
+    __syncthreads();
+    for (int32_t w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int32_t)threadIdx.x < w) sh_n[threadIdx.x] += sh_n[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && (a.full || a.admit))
+        g->quiet = (a.full && !a.admit && !a.batch_avg && sh_n[0] == 0) ? 1 : 0;
 
     // compaction plan (full evaluations): live prefix [0, n_run)
     if (a.admit) {
@@ -1046,6 +1075,7 @@ __global__ void k_begin_solve(Slots sl, SlotCtl* ctl, int32_t ncols, int32_t max
         g->n_retire = 0;
         g->n_move = 0;
         g->n_cols_next = ncols;
+        g->quiet = 0;
     }
 }
 
@@ -1082,7 +1112,10 @@ __global__ void k_admit(SlotCtl* ctl, const int32_t* rows, const SlotCtl* src, i
                         Globals* g, int32_t n_cols) {
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < cnt) ctl[rows[i]] = src[i];
-    if (i == 0) g->n_cols = n_cols;
+    if (i == 0) {
+        g->n_cols = n_cols;
+        g->quiet = 0;
+    }
 }
 
 // v[k] *= d[k % period] (or /=): maps LP-major blocks and shared vectors

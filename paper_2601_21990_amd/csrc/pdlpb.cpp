@@ -502,7 +502,8 @@ template <typename T>
 int enqueue_epoch(pdlpb_ctx* x, std::vector<std::pair<int, int>>* rec) {
     const int32_t C = x->opt.eval_every;
     for (int32_t it = 1; it <= C; ++it) {
-        const int32_t ev = (it == 1 || it == C) ? 1 : 0;
+        // z~ stored by every LP before the full evaluation, by fresh cycles before the first
+        const int32_t ev = it == C ? 2 : (it == 1 ? 1 : 0);
         int rc = enqueue_iteration<T>(x, it, ev, rec);
         if (rc) return rc;
         if (it == C) rc = enqueue_evaluation<T>(x, it, 1, 1, rec);
@@ -535,8 +536,9 @@ int tune_epoch(pdlpb_ctx* x) {
             x->tp = keep_p;
             x->td = keep_d;
         }
-        StepArgs<T> p = step_args<T>(x, true, it, ev ? 1 : 0);
-        StepArgs<T> d = step_args<T>(x, false, it, ev ? 1 : 0);
+        const int32_t lev = it == C ? 2 : (it == 1 ? 1 : 0);
+        StepArgs<T> p = step_args<T>(x, true, it, lev);
+        StepArgs<T> d = step_args<T>(x, false, it, lev);
         for (int kern = 0; kern < 2; ++kern) {
             int idx = -1;
             if (c >= 0) idx = timed_begin(x, c * 2 + kern, rec);
@@ -605,7 +607,7 @@ int run_solve(pdlpb_ctx* x, double tol, int32_t max_iters) {
     };
     // prologue: t = 0 is a full evaluation
     x->cur_cols = x->n_run0;
-    int rc = enqueue_iteration<T>(x, 0, 1, prec);
+    int rc = enqueue_iteration<T>(x, 0, 2, prec);
     if (!rc) rc = enqueue_evaluation<T>(x, 0, 1, 0, prec);
     if (rc) return rc;
     int32_t n_active = 0, n_cols = 0;
@@ -1702,7 +1704,7 @@ int serve_admit(pdlpb_ctx* x) {
         x->live = shape;
         choose_tile(x, shape);
     }
-    int rc = enqueue_iteration<T>(x, 0, 1, nullptr, 1);
+    int rc = enqueue_iteration<T>(x, 0, 2, nullptr, 1);
     if (!rc) rc = enqueue_evaluation<T>(x, 0, 1, 0, nullptr, 1);
     return rc;
 }

@@ -82,7 +82,8 @@ struct Globals {
     int32_t n_retire;    // compaction plan: stopped LPs to copy out
     int32_t n_move;      //   running LPs to move into freed slots
     int32_t n_cols_next; //   live columns after the compaction
-    int32_t pad;
+    int32_t quiet;       // 1: the next evaluation that is not full has no LP to evaluate (no
+                         //    running LP starts a restart cycle or reaches its last iteration)
     double  tol;
     double  eta;
     double  r0;          // BATCH_AVG shared r(z^{n,0})
@@ -121,7 +122,8 @@ struct StepArgs {
     Slots sl;
     const Globals* g;
     int32_t it;          // iteration index inside the block; global t = g->t0 + it
-    int32_t eval;        // 1: every running LP writes z~ and its displacement
+    int32_t eval;        // 2: every running LP writes z~ and its displacement; 1: only the LPs
+                         //    that the following evaluation of fresh cycles reads; 0: none
     int32_t admit;       // 1: only LPs flagged SLOT_NEW iterate (their first iteration)
     int32_t max_blocks;  // > 0: cap on the workgroups of the launch (waves then loop over rows)
 };
