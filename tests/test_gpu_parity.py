@@ -81,8 +81,10 @@ def _cfg2_ctx(P, inst, eta, base, D, **kw):
     return ctx
 
 
+# K = C + 2: the limit falls on the first iteration after a full evaluation, so the
+# evaluation of fresh cycles there must run although no LP starts a cycle
 @pytest.mark.parametrize("C", [64, 16])
-@pytest.mark.parametrize("K", [1, 65, 200])
+@pytest.mark.parametrize("K", [1, 18, 65, 66, 200])
 def test_cfg2_batch_fixed_iterations(P, K, C):
     inst, lp, eta, base, D = cfg2_setup()
     with _cfg2_ctx(P, inst, eta, base, D, eval_every=C) as ctx:
