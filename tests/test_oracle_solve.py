@@ -200,3 +200,90 @@ def test_batch_avg_converges_each_lp():
     longest = max(res, key=lambda r: r.iters)
     for r in res:
         assert set(r.restarts) == {t for t in longest.restarts if t < r.iters - 1}
+
+
+# ---------------------------------------------------------------------------
+# Worst-case rate of the Halpern iteration: with anchor weight 1/(k+2) and a
+# nonexpansive map R, ||z^k - R z^k|| <= 2 ||z^0 - z*|| / (k+1) for every fixed
+# point z* (Lieder, Optim. Lett. 2021).  Here R = 2T - I, nonexpansive in the
+# metric M of the residual because T is firmly nonexpansive there, so the
+# residual r(z^k) = ||T z^k - z^k||_M is at most ||z^0 - z*||_M / (k+1).  The
+# bound holds along the oracle's own iterate trajectory once restarts, the
+# stopping test and the infeasibility tests are switched off.
+# ---------------------------------------------------------------------------
+
+def _no_restarts(K, eta):
+    return O.Options(tol=0.0, max_iters=K, beta_s=0.0, beta_n=0.0, beta_a=1e12,
+                     infeas_tol=0.0, step_size=eta)
+
+
+def _rate_setup(inst, seed):
+    """eta, w, a start z^0 (zero, or random in the box and the barrier cone)
+    and ||z^0 - z*||_M with z* the oracle's point converged to 1e-12."""
+    lp = O.from_instance(inst)
+    eta = O.step_size(lp.A)
+    w = O.initial_primal_weight(lp)
+    ref = O.solve(lp, O.Options(tol=1e-12, max_iters=400000, step_size=eta))
+    assert ref.status == O.OPTIMAL
+    if seed is None:
+        x0, y0 = O.proj_box(np.zeros(lp.n), lp.xl, lp.xu), np.zeros(lp.m)
+    else:
+        rng = np.random.default_rng(seed)
+        x0 = O.proj_box(rng.uniform(-1.0, 4.0, lp.n), lp.xl, lp.xu)
+        y0 = O.proj_barrier_cone(rng.normal(size=lp.m), lp.l, lp.u)
+    dist = O.fixed_point_residual(lp, x0, y0, ref.x, ref.y, w, eta)
+    return lp, eta, w, x0, y0, dist
+
+
+@pytest.mark.parametrize("start", [None, 101])
+@pytest.mark.parametrize("inst", [make_tiny(s, m=4, n=7, senses="ELG", box=(0.0, 3.0))
+                                  for s in range(3)] + [make_cfg1()],
+                         ids=["tiny0", "tiny1", "tiny2", "cfg1"])
+def test_halpern_rate_bound_along_the_trajectory(inst, start):
+    lp, eta, w, x0, y0, dist = _rate_setup(inst, start)
+    for K in (1, 2, 3, 5, 10, 30, 100, 300, 1000, 3000):
+        res = O.solve(lp, _no_restarts(K, eta), x_init=x0, y_init=y0, w_init=w)
+        assert res.iters == K and not res.restarts
+        xt, yt = O.pdhg_operator(lp, res.x_iter, res.y_iter, eta / w, eta * w)
+        r = O.fixed_point_residual(lp, res.x_iter, res.y_iter, xt, yt, w, eta)
+        assert r <= dist / (K + 1) * (1 + 1e-6) + 1e-12, (K, r, dist / (K + 1))
+
+
+def _worst_ratio(lp, eta, w, x0, y0, dist, update, K=3000):
+    """max over k of r(z^k) (k+1) / ||z^0 - z*||_M for an iteration given by `update`."""
+    x, y = x0.copy(), y0.copy()
+    worst = 0.0
+    for k in range(K):
+        xt, yt = O.pdhg_operator(lp, x, y, eta / w, eta * w)
+        worst = max(worst, O.fixed_point_residual(lp, x, y, xt, yt, w, eta) * (k + 1) / dist)
+        x, y = update(k, x, y, xt, yt, x0, y0)
+    return worst
+
+
+def _halpern(k, z, z0):
+    return (k + 1) / (k + 2) * z + z0 / (k + 2)
+
+
+# plausible mistakes in the iteration, each planted in a copy of it built from
+# the oracle's operator: the bound is violated, so the check above has teeth
+_MISTAKES = {
+    "not reflected": lambda k, x, y, xt, yt, x0, y0: (_halpern(k, xt, x0), _halpern(k, yt, y0)),
+    "dual not reflected": lambda k, x, y, xt, yt, x0, y0: (_halpern(k, 2 * xt - x, x0),
+                                                           _halpern(k, yt, y0)),
+    "dual anchor sign": lambda k, x, y, xt, yt, x0, y0: (_halpern(k, 2 * xt - x, x0),
+                                                         _halpern(k, 2 * yt - y, -y0)),
+    "no anchor": lambda k, x, y, xt, yt, x0, y0: (2 * xt - x, 2 * yt - y),
+    "anchor at z^k": lambda k, x, y, xt, yt, x0, y0: (_halpern(k, 2 * xt - x, x),
+                                                      _halpern(k, 2 * yt - y, y)),
+}
+
+
+@pytest.mark.parametrize("mistake", sorted(_MISTAKES))
+@pytest.mark.parametrize("seed", [1, 2])
+def test_halpern_rate_bound_catches_planted_mistakes(seed, mistake):
+    inst = make_tiny(seed, m=4, n=7, senses="ELG", box=(0.0, 3.0))
+    args = _rate_setup(inst, 100 + seed)
+    good = _worst_ratio(*args, lambda k, x, y, xt, yt, x0, y0: (_halpern(k, 2 * xt - x, x0),
+                                                                _halpern(k, 2 * yt - y, y0)))
+    assert good <= 1.0
+    assert _worst_ratio(*args, _MISTAKES[mistake]) > 1.05
