@@ -1,7 +1,8 @@
 """Parity at the largest size, in the launch configuration the benchmark
 times: A 200000 x 500000 (4 N(0,1) nonzeros per column), FP64, B = 512
-bound-tightening LPs, default launch shapes, 65 iterations (one full
-evaluation with its restart tests).  The oracle recomputes a sample of the
+bound-tightening LPs, default options (the tile autotuner times its candidate
+shapes on the first block of iterations, as in the benchmark), 65 iterations
+(one full evaluation with its restart tests).  The oracle recomputes a sample of the
 LPs one at a time with its own step size; every LP of the batch must also be
 finite and still running or stopped with a valid status."""
 import numpy as np
@@ -27,7 +28,7 @@ def test_largest_size_sampled_lps_match_oracle(P):
     lp = O.from_instance(inst)
     eta = O.step_size(lp.A)
     D = obbt_deltas(choose_vars(inst.n, 256, seed=512))
-    with make_ctx(inst, eta, autotune=0) as ctx:
+    with make_ctx(inst, eta) as ctx:
         ctx.set_batch(D)
         ctx.solve(tol=0.0, max_iters=K)
         st = ctx.get_batch(want_x=False, want_y=False)
