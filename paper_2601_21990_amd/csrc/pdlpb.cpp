@@ -48,6 +48,8 @@ struct Tile {
 };
 
 constexpr int32_t DEFAULT_MAX_BLOCKS = 16384;
+constexpr int64_t RUN_AHEAD_AFTER = 8;      // blocks of a solve before replays run ahead of the host
+constexpr double RUN_AHEAD_BYTES = 32e6;    // ... and only while one launch moves less than this
 
 struct pdlpb_ctx {
     std::string err = "no error";
@@ -157,6 +159,7 @@ struct pdlpb_ctx {
     int32_t cur_cols = 0;               // live LP columns of the launches being enqueued
     std::vector<int32_t> rec_cols;      // cur_cols at each timed launch (by event pair)
     std::vector<hipEvent_t> ev;
+    hipEvent_t cnt_ev[2] = {nullptr, nullptr};   // live counts copied to h_pinned[8 + 4 s]
 
     int64_t dev_bytes = 0;
 
@@ -209,6 +212,11 @@ void free_all(pdlpb_ctx* x) {
     x->drop_graph();
     for (auto e : x->ev) (void)hipEventDestroy(e);
     x->ev.clear();
+    for (auto& e : x->cnt_ev)
+        if (e) {
+            (void)hipEventDestroy(e);
+            e = nullptr;
+        }
     void* ptrs[] = {x->a_rp, x->a_ci, x->t_rp, x->t_ci, x->a_v64, x->t_v64, x->a_v32, x->t_v32,
                     x->a_eci, x->t_eci, x->a_ev64, x->t_ev64, x->a_ev32, x->t_ev32, x->d_dr,
                     x->d_dc,
@@ -576,6 +584,24 @@ int tune_epoch(pdlpb_ctx* x) {
 }
 
 // read the running count and the live column count back to the host
+// Queue a copy of the live counts into pinned slot s (0 or 1) and mark it;
+// wait_counts reads them once the copy has landed.
+int enqueue_counts(pdlpb_ctx* x, int s) {
+    if (!x->cnt_ev[s])
+        HIP_TRY(x, hipEventCreateWithFlags(&x->cnt_ev[s], hipEventDisableTiming));
+    HIP_TRY(x, hipMemcpyAsync(x->h_pinned + 8 + 4 * s, x->g, 4 * sizeof(int32_t),
+                              hipMemcpyDeviceToHost, x->stream));
+    HIP_TRY(x, hipEventRecord(x->cnt_ev[s], x->stream));
+    return PDLPB_OK;
+}
+
+int wait_counts(pdlpb_ctx* x, int s, int32_t* n_active, int32_t* n_cols) {
+    HIP_TRY(x, hipEventSynchronize(x->cnt_ev[s]));
+    *n_active = x->h_pinned[8 + 4 * s + 1];   // Globals::n_active
+    *n_cols = x->h_pinned[8 + 4 * s + 3];     // Globals::n_cols
+    return PDLPB_OK;
+}
+
 int read_counts(pdlpb_ctx* x, int32_t* n_active, int32_t* n_cols) {
     HIP_TRY(x, hipMemcpyAsync(x->h_pinned, x->g, 4 * sizeof(int32_t), hipMemcpyDeviceToHost,
                               x->stream));
@@ -616,8 +642,17 @@ int run_solve(pdlpb_ctx* x, double tol, int32_t max_iters) {
     if (prec) harvest();
     const bool use_graphs = x->opt.use_graphs && !x->timing;
     const int64_t max_epochs = (int64_t)max_iters / x->opt.eval_every + 2;
+    // Replayed blocks of a long solve run one ahead of the host: block e+1 is
+    // queued before the host waits for the counts of block e, so the device
+    // does not idle while the host reads them and decides the next launch
+    // shape.  A block queued after every LP has stopped launches kernels that
+    // find no live column, which costs little only when the launches are small
+    // (latency-bound), and pays off only over many blocks.
+    bool in_flight = false;   // a block whose counts have not been read
+    int in_slot = 0, next_slot = 0;
+    int64_t launched = 0;
     for (int64_t ep = 0; n_active > 0; ++ep) {
-        if (ep > max_epochs) return x->fail(PDLPB_EDEVICE, "solve did not terminate");
+        if (launched > max_epochs + 1) return x->fail(PDLPB_EDEVICE, "solve did not terminate");
         // shape the launches for the live columns (compaction shrinks them)
         const int32_t shape = shape_cols(x, n_cols);
         x->cur_cols = n_cols;
@@ -638,6 +673,16 @@ int run_solve(pdlpb_ctx* x, double tol, int32_t max_iters) {
                 tune_now = !hit && !x->timing;
             }
         }
+        const bool ahead = use_graphs && !tune_now && launched >= RUN_AHEAD_AFTER &&
+                           launch_bytes(x, x->live) < RUN_AHEAD_BYTES;
+        if (in_flight && !ahead) {
+            // a synchronous block follows: read the counts of the block ahead first
+            rc = wait_counts(x, in_slot, &n_active, &n_cols);
+            if (rc) return rc;
+            in_flight = false;
+            continue;
+        }
+        ++launched;
         if (tune_now) {
             rc = tune_epoch<T>(x);
             if (rc) return rc;
@@ -661,6 +706,18 @@ int run_solve(pdlpb_ctx* x, double tol, int32_t max_iters) {
                 x->graphs.push_back({x->live, exec});
             }
             HIP_TRY(x, hipGraphLaunch(exec, x->stream));
+            if (ahead) {
+                rc = enqueue_counts(x, next_slot);
+                if (rc) return rc;
+                if (in_flight) {
+                    rc = wait_counts(x, in_slot, &n_active, &n_cols);
+                    if (rc) return rc;
+                }
+                in_flight = true;
+                in_slot = next_slot;
+                next_slot ^= 1;
+                continue;
+            }
         } else {
             rc = enqueue_epoch<T>(x, prec);
             if (rc) return rc;
