@@ -651,6 +651,15 @@ int run_solve(pdlpb_ctx* x, double tol, int32_t max_iters) {
     bool in_flight = false;   // a block whose counts have not been read
     int in_slot = 0, next_slot = 0;
     int64_t launched = 0;
+    // no block outlives the call: other entry points write device state with
+    // copies that do not wait for the context's (non-blocking) stream
+    struct Drain {
+        pdlpb_ctx* x;
+        const bool* f;
+        ~Drain() {
+            if (*f) (void)hipStreamSynchronize(x->stream);
+        }
+    } drain{x, &in_flight};
     for (int64_t ep = 0; n_active > 0; ++ep) {
         if (launched > max_epochs + 1) return x->fail(PDLPB_EDEVICE, "solve did not terminate");
         // shape the launches for the live columns (compaction shrinks them)

@@ -204,3 +204,27 @@ def test_batch_after_serving_ends_the_session(P, base):
         ids = ctx.submit(r1[:2], P.WARM_NONE, 1e-4, 20000)
         got = _serve_until_done(P, ctx, list(ids))
         assert all(g["status"] == P.STATUS_OPTIMAL for g in got.values())
+
+
+def test_serving_right_after_a_long_solve(P, base):
+    """A solve of many blocks (its replays run ahead of the host) returns with
+    nothing left running: a serving session opened at once on the same context
+    gives the same bits as one on a fresh context."""
+    inst, lp, eta, root = base
+    r1, _, _ = _requests(inst, root)
+    with make_ctx(inst, eta, eval_every=4) as ctx:
+        ctx.serve_begin(16)
+        ids = ctx.submit(r1, P.WARM_NONE, 1e-6, 20000)
+        ref = _serve_until_done(P, ctx, list(ids))
+    with make_ctx(inst, eta, eval_every=4) as ctx:
+        ctx.set_batch(r1)
+        ctx.solve(tol=1e-9, max_iters=2000)     # hundreds of blocks of 4 iterations
+        st = ctx.get_batch(want_x=False, want_y=False)
+        assert np.all(st["iters"] > 4 * 8)
+        ctx.serve_begin(16)
+        ids2 = ctx.submit(r1, P.WARM_NONE, 1e-6, 20000)
+        got = _serve_until_done(P, ctx, list(ids2))
+    for i, i2 in zip(ids, ids2):
+        assert got[i2]["iters"] == ref[i]["iters"]
+        np.testing.assert_array_equal(got[i2]["x"], ref[i]["x"])
+        np.testing.assert_array_equal(got[i2]["y"], ref[i]["y"])
