@@ -81,3 +81,42 @@ def test_box_only_closed_form(P):
     np.testing.assert_allclose(r["x"], want, atol=1e-9)
     np.testing.assert_array_equal(r["y"], np.zeros(2))
     assert r["obj"] == pytest.approx(float(c @ want), abs=1e-9)
+
+
+def test_maximum_batch_width(P):
+    """B = 4096, the largest batch a context accepts by default: 128 distinct
+    bound-tightening LPs, each placed 32 times at scattered positions.  Every
+    copy of an LP carries the same bits (its arithmetic does not depend on
+    its slot or on the batch), a sample matches the oracle's trajectory over a
+    full evaluation, and one LP more is rejected."""
+    from tests.gpu_common import make_ctx, lp_for, assert_trajectory_match
+    from workloads import make_cfg2, obbt_deltas, choose_vars
+    inst = make_cfg2(m=200, n=500)
+    lp = O.from_instance(inst)
+    eta = O.step_size(lp.A)
+    U = obbt_deltas(choose_vars(inst.n, 64, seed=7))          # 128 distinct LPs
+    perm = np.random.default_rng(7).permutation(4096)
+    D = np.tile(U, 32)[perm]                                    # copy c of LP u at perm^-1
+    K = 65
+    with make_ctx(inst, eta) as ctx:
+        assert ctx.options.max_batch == 4096
+        ctx.set_batch(D)
+        ctx.solve(tol=0.0, max_iters=K)
+        out = ctx.get_batch()
+        sample = {}
+        for u in (0, 63, 64, 127):
+            j = int(np.nonzero(perm % 128 == u)[0][0])
+            sample[u] = (ctx.get(j), ctx.get_trace(j))
+        with pytest.raises(P.PdlpbError) as e:
+            ctx.set_batch(np.tile(U, 33)[:4097])
+        assert e.value.code == P.EINVAL
+    assert np.all(out["iters"] == K)
+    src = perm % 128
+    for u in range(128):
+        rows = np.nonzero(src == u)[0]
+        assert rows.size == 32
+        for q in ("X", "Y"):
+            assert np.array_equal(out[q][rows], np.broadcast_to(out[q][rows[0]], out[q][rows].shape))
+    for u, (res, tr) in sample.items():
+        ores = O.solve(lp_for(lp, U[u]), O.Options(tol=0.0, max_iters=K, step_size=eta))
+        assert_trajectory_match(res, tr, ores, what=f"LP {u}")
