@@ -735,6 +735,8 @@ def main():
                     help="serve: iterations between evaluations (the block length)")
     ap.add_argument("--eval-every", type=int, default=16,
                     help="fsb: iterations between evaluations of the batch")
+    ap.add_argument("--fsb-vars", type=int, default=32,
+                    help="fsb: branching candidates (the batch holds two LPs per candidate)")
     ap.add_argument("--plain-eval-every", type=int, default=64,
                     help="fsb: iterations between evaluations of the one-LP-at-a-time leg")
     ap.add_argument("--serve-m", type=int, default=200000)
@@ -823,7 +825,7 @@ def main():
     root = ctx.get(0)
     root_w = ctx.get_trace(0)["w"]
     log(f"root: status={P.STATUS_NAMES[root['status']]} iters={root['iters']} obj={root['obj']:.6f}")
-    vars_ = choose_fractional(root["x"], 32, seed_for(2, 0))
+    vars_ = choose_fractional(root["x"], args.fsb_vars, seed_for(2, 0))
     D = fsb_deltas(root["x"], vars_)
     B = len(D)
 
@@ -954,7 +956,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "strong-branching batch: A 2000x5000 (5 N(0,1) nnz/col), 1000 E + "
-                               "1000 L rows, box [0,10], B=64 bound changes on 32 fractional "
+                               f"1000 L rows, box [0,10], B={B} bound changes on {B // 2} fractional "
                                "variables, warm start from the root LP, FP64, tol 1e-4 rel KKT",
                    "m": m, "n": n, "nnz": nnz, "B": B, "tol": 1e-4,
                    "eval_every": args.eval_every},
