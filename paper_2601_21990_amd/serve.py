@@ -12,7 +12,10 @@ of its LPs have stopped; its latency is completion time minus arrival time.
 Admission by memory footprint: a context holds `max_batch` LP columns and
 `result_capacity` result rows, both allocated when serving begins; LPs beyond
 the free columns wait in the library's FIFO queue, and a request whose LPs do
-not fit the free result rows waits in this loop until rows are released.
+not fit the free result rows waits in this loop until rows are released.  The
+requests of one base enter the library in arrival order: one that does not fit
+holds back the later ones of its base, so a large request is not overtaken
+indefinitely by small ones.
 """
 from __future__ import annotations
 
@@ -56,20 +59,17 @@ class Server:
         self.completed: List[Request] = []
         self.lps_done = 0
 
-    @staticmethod
-    def footprint_bytes(ctx: P.Context, fp32: bool) -> int:
-        """Device bytes one LP column costs while it runs: eight iterate blocks
-        (n or m entries each) plus its four result rows."""
-        s = 4 if fp32 else 8
-        return s * (4 * (ctx.n + ctx.m) + 2 * (ctx.n + ctx.m))
-
     def submit(self, req: Request) -> None:
         self.waiting.append(req)
         self._admit_waiting()
 
     def _admit_waiting(self) -> None:
         still = []
+        blocked = set()           # bases whose oldest waiting request did not fit
         for req in self.waiting:
+            if req.base in blocked:
+                still.append(req)
+                continue
             ctx = self.ctx[req.base]
             try:
                 ids = ctx.submit(req.deltas, P.WARM_BASE if self.warm else P.WARM_NONE,
@@ -77,6 +77,7 @@ class Server:
             except P.PdlpbError as e:
                 if e.code != P.ENOMEM:
                     raise
+                blocked.add(req.base)
                 still.append(req)
                 continue
             req.ids = list(ids)
