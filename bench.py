@@ -6,8 +6,10 @@ constraint matrix with 5 N(0,1) nonzeros per column, 1000 equality and 1000
 <= rows, box [0,10], c ~ N(0,1).  The root LP is solved on the GPU (outside
 the timed region); 32 variables with fractional parts in [0.1, 0.9] give a
 batch of B = 64 bound-changed LPs, each warm-started from the root solution.
-One step = set the batch from device-resident deltas and warm start, solve
-every LP to 1e-4 relative KKT in FP64, copy the solutions to device buffers.
+Ten independent draws of the 32 candidates are staged; step i solves draw
+i mod 10.  One step = set the batch from device-resident deltas and warm
+start, solve every LP to 1e-4 relative KKT in FP64, copy the solutions to
+device buffers.
 
 Reported: LPs solved per second (value), the same LPs solved one at a time
 by the same library (plain PDHG, B = 1), the dominant kernel's achieved HBM
@@ -733,10 +735,12 @@ def main():
                     help="mixed: skip the FP64 pass of the precision statement")
     ap.add_argument("--serve-eval", type=int, default=16,
                     help="serve: iterations between evaluations (the block length)")
-    ap.add_argument("--eval-every", type=int, default=16,
+    ap.add_argument("--eval-every", type=int, default=32,
                     help="fsb: iterations between evaluations of the batch")
     ap.add_argument("--fsb-vars", type=int, default=32,
                     help="fsb: branching candidates (the batch holds two LPs per candidate)")
+    ap.add_argument("--fsb-draws", type=int, default=10,
+                    help="fsb: independent draws of the candidates; step i solves draw i mod R")
     ap.add_argument("--plain-eval-every", type=int, default=64,
                     help="fsb: iterations between evaluations of the one-LP-at-a-time leg")
     ap.add_argument("--serve-m", type=int, default=200000)
@@ -825,12 +829,16 @@ def main():
     root = ctx.get(0)
     root_w = ctx.get_trace(0)["w"]
     log(f"root: status={P.STATUS_NAMES[root['status']]} iters={root['iters']} obj={root['obj']:.6f}")
-    vars_ = choose_fractional(root["x"], args.fsb_vars, seed_for(2, 0))
-    D = fsb_deltas(root["x"], vars_)
-    B = len(D)
+    # one batch per draw of branching candidates from the root's fractional
+    # variables; step i solves draw i mod R, so the rate describes the family of
+    # batches rather than the luck of one draw (the batch time is set by its
+    # slowest LP, often an infeasible branch)
+    draws = [fsb_deltas(root["x"], choose_fractional(root["x"], args.fsb_vars, seed_for(2, r)))
+             for r in range(args.fsb_draws)]
+    B = len(draws[0])
 
     # inputs resident in HBM before the timed region
-    d_deltas = torch.from_numpy(D.view(np.uint8).copy()).to(dev)
+    d_draws = [torch.from_numpy(D.view(np.uint8).copy()).to(dev) for D in draws]
     d_x = torch.from_numpy(root["x"]).to(dev)
     d_y = torch.from_numpy(root["y"]).to(dev)
     d_w = torch.full((B,), root_w, dtype=torch.float64, device=dev)
@@ -838,9 +846,9 @@ def main():
     d_Y = torch.empty((B, m), dtype=torch.float64, device=dev)
     torch.cuda.synchronize()
 
-    def step():
-        rc = P.lib.pdlpb_set_batch(ctx._h, B, d_deltas.data_ptr(), d_x.data_ptr(), d_y.data_ptr(),
-                                   d_w.data_ptr(), P.WARM_SHARED, P.MEM_DEVICE)
+    def step(i):
+        rc = P.lib.pdlpb_set_batch(ctx._h, B, d_draws[i % len(d_draws)].data_ptr(), d_x.data_ptr(),
+                                   d_y.data_ptr(), d_w.data_ptr(), P.WARM_SHARED, P.MEM_DEVICE)
         ctx._check(rc)
         ctx.B = B
         ctx.solve(tol=1e-4, max_iters=100000)
@@ -848,7 +856,7 @@ def main():
 
     out = None
     for i in range(max(args.warmup, 1)):
-        out = step()
+        out = step(i)
     log(f"warmup done: iters min/median/max = {out['iters'].min()}/{int(np.median(out['iters']))}/"
         f"{out['iters'].max()}, statuses {np.bincount(out['status'], minlength=6).tolist()}")
 
@@ -856,9 +864,12 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     solved = 0
+    iters, slowest = [], []
     for i in range(args.steps):
-        out = step()
+        out = step(i)
         solved += int(np.sum(out["status"] == P.STATUS_OPTIMAL))
+        iters.append(out["iters"])
+        slowest.append(int(out["iters"].max()))
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     value = solved / dt
@@ -870,7 +881,7 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     for i in range(args.steps):
-        step()
+        step(i)
     torch.cuda.synchronize()
     event_dt = time.perf_counter() - t1
     counts, total_ms = ctx.kernel_times()
@@ -903,9 +914,14 @@ def main():
     # plain PDHG: the same LPs one at a time (B = 1) with the same library
     ctx.close()
     ctx = ctx_plain
-    np_plain = min(args.plain_lps, B)
+    # LP j of the sample is LP j // R of draw j mod R
+    np_plain = min(args.plain_lps, B * len(d_draws))
+
+    def plain_ptr(j):
+        return d_draws[j % len(d_draws)].data_ptr() + 16 * (j // len(d_draws))
+
     for j in range(min(2, np_plain)):          # untimed: graphs for B = 1
-        rc = P.lib.pdlpb_set_batch(ctx._h, 1, d_deltas.data_ptr() + 16 * j, d_x.data_ptr(),
+        rc = P.lib.pdlpb_set_batch(ctx._h, 1, plain_ptr(j), d_x.data_ptr(),
                                    d_y.data_ptr(), d_w.data_ptr(), P.WARM_SHARED, P.MEM_DEVICE)
         ctx._check(rc)
         ctx.B = 1
@@ -915,7 +931,7 @@ def main():
     plain_solved = 0
     plain_iters = []
     for j in range(np_plain):
-        rc = P.lib.pdlpb_set_batch(ctx._h, 1, d_deltas.data_ptr() + 16 * j, d_x.data_ptr(),
+        rc = P.lib.pdlpb_set_batch(ctx._h, 1, plain_ptr(j), d_x.data_ptr(),
                                    d_y.data_ptr(), d_w.data_ptr(), P.WARM_SHARED, P.MEM_DEVICE)
         ctx._check(rc)
         ctx.B = 1
@@ -957,16 +973,19 @@ def main():
         "data": "synthetic",
         "config": {"workload": "strong-branching batch: A 2000x5000 (5 N(0,1) nnz/col), 1000 E + "
                                f"1000 L rows, box [0,10], B={B} bound changes on {B // 2} fractional "
-                               "variables, warm start from the root LP, FP64, tol 1e-4 rel KKT",
-                   "m": m, "n": n, "nnz": nnz, "B": B, "tol": 1e-4,
+                               "variables, warm start from the root LP, FP64, tol 1e-4 rel KKT; "
+                               f"step i solves draw i mod {len(d_draws)} of the candidates",
+                   "m": m, "n": n, "nnz": nnz, "B": B, "tol": 1e-4, "draws": len(d_draws),
                    "eval_every": args.eval_every},
         "plain": {"value": round(plain_value, 2), "unit": "LPs/s", "lps": np_plain,
                   "iters_median": int(np.median(plain_iters)),
                   "eval_every": args.plain_eval_every},
         "batched_vs_plain": round(value / plain_value, 3) if plain_value > 0 else None,
         "event_timed_pass_s": round(event_dt, 4),
-        "iters": {"min": int(out["iters"].min()), "median": int(np.median(out["iters"])),
-                  "max": int(out["iters"].max())},
+        "iters": {"min": int(np.min(np.concatenate(iters))),
+                  "median": int(np.median(np.concatenate(iters))),
+                  "max": int(np.max(np.concatenate(iters))),
+                  "slowest_per_batch_median": int(np.median(slowest))},
         "kernel_avg_us": kernel_us,
         "roofline": roofline,
         "spmm_hbm": spmm,

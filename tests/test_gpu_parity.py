@@ -81,10 +81,11 @@ def _cfg2_ctx(P, inst, eta, base, D, **kw):
     return ctx
 
 
-# K = C + 2: the limit falls on the first iteration after a full evaluation, so the
-# evaluation of fresh cycles there must run although no LP starts a cycle
-@pytest.mark.parametrize("C", [64, 16])
-@pytest.mark.parametrize("K", [1, 18, 65, 66, 200])
+# K = C + 2 (18, 34, 66): the limit falls on the first iteration after a full
+# evaluation, so the evaluation of fresh cycles there must run although no LP
+# starts a cycle
+@pytest.mark.parametrize("C", [64, 32, 16])
+@pytest.mark.parametrize("K", [1, 18, 34, 65, 66, 200])
 def test_cfg2_batch_fixed_iterations(P, K, C):
     inst, lp, eta, base, D = cfg2_setup()
     with _cfg2_ctx(P, inst, eta, base, D, eval_every=C) as ctx:
@@ -97,8 +98,9 @@ def test_cfg2_batch_fixed_iterations(P, K, C):
     print(f"cfg2 K={K} C={C}: worst rel err {worst:.2e}")
 
 
-# C = 16 is the evaluation interval the strong-branching benchmark runs with
-@pytest.mark.parametrize("C", [64, 16])
+# C = 32 is the evaluation interval the strong-branching benchmark runs with, 16 the
+# one serving runs with
+@pytest.mark.parametrize("C", [64, 32, 16])
 def test_cfg2_batch_converged(P, C):
     inst, lp, eta, base, D = cfg2_setup()
     with _cfg2_ctx(P, inst, eta, base, D, eval_every=C) as ctx:
