@@ -255,6 +255,11 @@ def run_sweep(args):
     import numpy as np
     import paper_2601_21990_amd.pdlpb as P
     from workloads import make_cfg3, make_cfg5, obbt_deltas, choose_vars
+    # a solve replays whole blocks of C = 64 iterations: with any other count the
+    # launches past the LPs' last iteration find no live column, and averaging
+    # them in would overstate the rate of the ones that work
+    if (args.sweep_iters - 1) % 64 != 0:
+        raise SystemExit("--sweep-iters must be 64 k + 1 (65, 129, ...)")
     if args.sweep_matrix == "cfg3":
         inst = make_cfg3()
     else:

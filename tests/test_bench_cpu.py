@@ -115,3 +115,9 @@ def test_trace_summary_averages_the_chosen_solves(tmp_path):
     assert "| k_dual | 2 | 5.000 |" in text          # (4000 + 6000) ns / 2
     assert "| k_primal | 1 | 3.000 |" in text
     assert "| k_dual | 3 | 0.015 | 5.000 | 75.00 |" in text
+
+
+def test_sweep_refuses_iteration_counts_that_leave_dead_launches():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--workload", "sweep",
+                        "--sweep-iters", "33"], capture_output=True, text=True, timeout=300)
+    assert r.returncode != 0 and "64 k + 1" in r.stderr
