@@ -918,6 +918,22 @@ def main():
                 "avg_launch_us": round(avg_ms * 1e3, 3), "launches": int(counts[dom])}
     kernel_us = {names[k]: round(total_ms[k] / max(counts[k], 1) * 1e3, 3) for k in range(4)}
 
+    # the same steps with the inputs in host memory and the results copied back
+    # to it (the boundary accepts either): the rate including the host transfers
+    w_host = np.full(B, root_w)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    host_solved = 0
+    for i in range(args.steps):
+        ctx.set_batch(draws[i % len(draws)], x_warm=root["x"], y_warm=root["y"], w_warm=w_host)
+        ctx.solve(tol=1e-4, max_iters=100000)
+        r = ctx.get_batch()
+        host_solved += int(np.sum(r["status"] == P.STATUS_OPTIMAL))
+    host_dt = time.perf_counter() - t3
+    host_io = {"value": round(host_solved / host_dt, 2), "unit": "LPs/s",
+               "note": "inputs from and results (x~, y~ per LP) to host memory"}
+    log(f"host I/O: {args.steps} steps in {host_dt:.4f}s -> {host_io['value']} LPs/s")
+
     # plain PDHG: the same LPs one at a time (B = 1) with the same library
     ctx.close()
     ctx = ctx_plain
@@ -989,6 +1005,7 @@ def main():
                   "eval_every": args.plain_eval_every},
         "batched_vs_plain": round(value / plain_value, 3) if plain_value > 0 else None,
         "event_timed_pass_s": round(event_dt, 4),
+        "host_io": host_io,
         "iters": {"min": int(np.min(np.concatenate(iters))),
                   "median": int(np.median(np.concatenate(iters))),
                   "max": int(np.max(np.concatenate(iters))),
