@@ -174,8 +174,11 @@ int pdlpb_set_batch(pdlpb_ctx* ctx, int32_t B, const pdlpb_delta* deltas,
  * (ITERATION_LIMIT), or fails (NUMERICAL_ERROR).
  * tol >= 0, max_iters >= 1.  All control (restarts, primal weights, statuses)
  * runs on the GPU; the host only checks once per C iterations whether any LP
- * is still running.  Returns PDLPB_ESTATE if no batch is set or it was
- * already solved.
+ * is still running (in a long solve of small launches the device runs one
+ * block of C iterations ahead of that check; a block that finds every LP
+ * stopped does nothing).  The call returns once every LP has stopped, with no
+ * work of its own left on the context's stream.  Returns PDLPB_ESTATE if no
+ * batch is set or it was already solved.
  */
 int pdlpb_solve(pdlpb_ctx* ctx, double tol, int64_t max_iters);
 
