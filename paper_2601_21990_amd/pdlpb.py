@@ -10,6 +10,7 @@ missing, importing this module raises.
 from __future__ import annotations
 
 import ctypes as C
+import importlib.util
 import os
 from typing import Optional
 
@@ -69,10 +70,26 @@ class PdlpbError(RuntimeError):
         self.code = code
 
 
+def _share_torch_runtime():
+    """When PyTorch is installed, load the HIP runtime it bundles before this
+    library, so that the library binds to it and the process holds one runtime
+    whichever of the two is used first: with two runtimes in one process the
+    one that starts second finds no GPU."""
+    spec = importlib.util.find_spec("torch")
+    if spec is None or not spec.origin:
+        return
+    libdir = os.path.join(os.path.dirname(spec.origin), "lib")
+    for name in ("libhsa-runtime64.so", "libamdhip64.so"):
+        path = os.path.join(libdir, name)
+        if os.path.exists(path):
+            C.CDLL(path, mode=C.RTLD_GLOBAL)
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
                           "(hipcc --offload-arch=gfx950); there is no fallback path")
+    _share_torch_runtime()
     lib = C.CDLL(LIB_PATH)
     P = C.c_void_p
     d, i32, i64 = C.c_double, C.c_int32, C.c_int64

@@ -406,3 +406,36 @@ def test_autotune_leaves_results_unchanged(P):
     np.testing.assert_array_equal(outs[0]["X"], outs[1]["X"])
     np.testing.assert_array_equal(outs[0]["Y"], outs[1]["Y"])
     np.testing.assert_array_equal(outs[0]["iters"], outs[1]["iters"])
+
+
+def test_caller_stream_and_device_buffers(P):
+    """A context on a stream the caller owns (a torch stream of default
+    priority), inputs and outputs in device memory: the batch gives the same
+    bits as on the context's own stream, and a torch operation queued on the
+    caller's stream right after get_batch sees the finished results."""
+    import torch
+    inst, lp, eta, base, D = cfg2_setup()
+    with make_ctx(inst, eta, eval_every=32) as ctx:
+        ctx.set_batch(D, x_warm=base.x, y_warm=base.y, w_warm=np.full(len(D), base.w))
+        ctx.solve(tol=1e-4, max_iters=100000)
+        ref = ctx.get_batch()
+    s = torch.cuda.Stream()
+    dev = torch.device("cuda:0")
+    with torch.cuda.stream(s):
+        with make_ctx(inst, eta, eval_every=32, stream=s.cuda_stream) as ctx:
+            dD = torch.from_numpy(D.view(np.uint8).copy()).to(dev)
+            dx = torch.from_numpy(base.x).to(dev)
+            dy = torch.from_numpy(base.y).to(dev)
+            dw = torch.full((len(D),), base.w, dtype=torch.float64, device=dev)
+            ctx.set_batch(dD, x_warm=dx, y_warm=dy, w_warm=dw, mem=P.MEM_DEVICE)
+            ctx.solve(tol=1e-4, max_iters=100000)
+            X = torch.empty((len(D), inst.n), dtype=torch.float64, device=dev)
+            Y = torch.empty((len(D), inst.m), dtype=torch.float64, device=dev)
+            out = ctx.get_batch(X=X, Y=Y, mem=P.MEM_DEVICE)
+            row_sums = X.sum(dim=1)               # queued on the caller's stream
+    s.synchronize()
+    np.testing.assert_array_equal(out["status"], ref["status"])
+    np.testing.assert_array_equal(out["iters"], ref["iters"])
+    np.testing.assert_array_equal(X.cpu().numpy(), ref["X"])
+    np.testing.assert_array_equal(Y.cpu().numpy(), ref["Y"])
+    np.testing.assert_allclose(row_sums.cpu().numpy(), ref["X"].sum(axis=1), rtol=1e-12)
