@@ -871,9 +871,11 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     solved = 0
-    iters, slowest = [], []
+    iters, slowest, step_s = [], [], []
     for i in range(args.steps):
-        out = step(i)
+        ts = time.perf_counter()
+        out = step(i)                      # ends with the statuses read back to the host
+        step_s.append(time.perf_counter() - ts)
         solved += int(np.sum(out["status"] == P.STATUS_OPTIMAL))
         iters.append(out["iters"])
         slowest.append(int(out["iters"].max()))
@@ -1004,6 +1006,8 @@ def main():
                   "iters_median": int(np.median(plain_iters)),
                   "eval_every": args.plain_eval_every},
         "batched_vs_plain": round(value / plain_value, 3) if plain_value > 0 else None,
+        "step_ms": {"min": round(min(step_s) * 1e3, 3), "median": round(float(np.median(step_s)) * 1e3, 3),
+                    "max": round(max(step_s) * 1e3, 3)},
         "event_timed_pass_s": round(event_dt, 4),
         "host_io": host_io,
         "iters": {"min": int(np.min(np.concatenate(iters))),
