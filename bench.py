@@ -748,6 +748,8 @@ def main():
                     help="fsb: branching candidates (the batch holds two LPs per candidate)")
     ap.add_argument("--fsb-draws", type=int, default=10,
                     help="fsb: independent draws of the candidates; step i solves draw i mod R")
+    ap.add_argument("--plain-tile-lanes", type=int, default=0,
+                    help="fsb: fixed lanes per row for the one-LP-at-a-time leg (0: the library's choice)")
     ap.add_argument("--plain-eval-every", type=int, default=64,
                     help="fsb: iterations between evaluations of the one-LP-at-a-time leg")
     ap.add_argument("--serve-m", type=int, default=200000)
@@ -826,7 +828,10 @@ def main():
                 eval_every=args.eval_every)
     ctx = P.Context.from_instance(inst, **opts)
     # the one-LP-at-a-time leg runs at the evaluation interval that suits one LP best
-    ctx_plain = P.Context.from_instance(inst, **{**opts, "eval_every": args.plain_eval_every})
+    popts = {**opts, "eval_every": args.plain_eval_every}
+    if args.plain_tile_lanes:
+        popts.update(tile_lanes=args.plain_tile_lanes, tile_vec=1)
+    ctx_plain = P.Context.from_instance(inst, **popts)
     eta, norm_a = ctx.step_size
     log(f"eta={eta:.6g} ||A||={norm_a:.6g}")
 
