@@ -24,7 +24,7 @@ from typing import Optional, Tuple
 import numpy as np
 import scipy.sparse as sp
 
-from .lp import LP, BASE, SET_LO, SET_HI, OBJ_UNIT
+from .lp import LP, SET_LO, SET_HI, OBJ_UNIT
 from .pdhg import Options, Result, solve
 
 RUIZ_ITERS = 10

@@ -7,7 +7,7 @@ import functools
 import numpy as np
 
 import oracle as O
-from workloads import (make_cfg1, make_cfg2, choose_fractional, fsb_deltas, seed_for)
+from workloads import make_cfg2, choose_fractional, fsb_deltas, seed_for
 
 ITER_RTOL = 1e-9          # relative error on iterates after a fixed iteration count (FP64)
 

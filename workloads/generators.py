@@ -19,7 +19,7 @@ Every generator draws from ``numpy.random.default_rng`` (PCG64) seeded with
 from __future__ import annotations
 
 from dataclasses import dataclass, field
-from typing import Dict, List, Optional
+from typing import Dict, List
 
 import numpy as np
 
