@@ -228,3 +228,26 @@ def test_serving_right_after_a_long_solve(P, base):
         assert got[i2]["iters"] == ref[i]["iters"]
         np.testing.assert_array_equal(got[i2]["x"], ref[i]["x"])
         np.testing.assert_array_equal(got[i2]["y"], ref[i]["y"])
+
+
+def test_serve_matches_batch_solve_mixed32(P, base):
+    """The same property with FP32 iterates and FP64 sums: an LP served through
+    admission carries the bits it has when its request is solved as a batch."""
+    inst, lp, eta, root = base
+    r1, _, r3 = _requests(inst, root)
+    with make_ctx(inst, eta, precision=P.MIXED32) as ctx:
+        ctx.set_batch(r3)
+        ctx.solve(tol=1e-4, max_iters=20000)
+        ref = ctx.get_batch()
+    with make_ctx(inst, eta, precision=P.MIXED32) as ctx:
+        ctx.serve_begin(32)
+        ctx.submit(r1, P.WARM_NONE, 1e-4, 20000)        # running when r3 arrives
+        ctx.serve_launch()
+        ctx.serve_wait()
+        ids = ctx.submit(r3, P.WARM_NONE, 1e-4, 20000)
+        got = _serve_until_done(P, ctx, list(ids))
+    for j, i in enumerate(ids):
+        assert got[i]["status"] == ref["status"][j]
+        assert got[i]["iters"] == ref["iters"][j]
+        np.testing.assert_array_equal(got[i]["x"], ref["X"][j])
+        np.testing.assert_array_equal(got[i]["y"], ref["Y"][j])
