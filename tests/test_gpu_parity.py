@@ -329,15 +329,17 @@ def test_mixed32_error_statement(P):
         assert k.rel <= 2e-3, (j, k)
 
 
-def test_batch_avg_matches_oracle(P):
+@pytest.mark.parametrize("C", [64, 32])
+def test_batch_avg_matches_oracle(P, C):
     inst = make_cfg2(m=200, n=500)
     lp = O.from_instance(inst)
     eta = O.step_size(lp.A)
     D = obbt_deltas(choose_vars(lp.n, 4, seed=13))
     lps = [lp_for(lp, d) for d in D]
     for tol, K in [(0.0, 400), (1e-5, 100000)]:
-        ores = O.solve_batch_avg(lps, O.Options(tol=tol, max_iters=K, step_size=eta))
-        with make_ctx(inst, eta, restart_scope=P.RESTART_BATCH_AVG) as ctx:
+        ores = O.solve_batch_avg(lps, O.Options(tol=tol, max_iters=K, step_size=eta,
+                                                eval_every=C))
+        with make_ctx(inst, eta, restart_scope=P.RESTART_BATCH_AVG, eval_every=C) as ctx:
             ctx.set_batch(D)
             ctx.solve(tol=tol, max_iters=K)
             for j in range(len(D)):
@@ -345,9 +347,11 @@ def test_batch_avg_matches_oracle(P):
                                         rtol=1e-8, what=f"avg tol={tol} LP {j}")
 
 
-def test_infeasible_and_unbounded_lps_detected(P):
+@pytest.mark.parametrize("C", [64, 32])
+def test_infeasible_and_unbounded_lps_detected(P, C):
     """Section 4 infeasibility tests on the GPU: an infeasible box-constrained
-    LP and an unbounded LP, each in a batch with a feasible neighbour."""
+    LP and an unbounded LP, each in a batch with a feasible neighbour; the
+    statuses and the iteration at which each LP stops equal the oracle's."""
     import scipy.sparse as sp
     from workloads.generators import LPInstance
     # rows: x0 + x1 = 5 (E), x0 - x1 <= 3 (L); box [0, 1]^2 (infeasible) / [0, 4]^2 (feasible)
@@ -357,23 +361,33 @@ def test_infeasible_and_unbounded_lps_detected(P):
                           val=A.data, c=np.array([1.0, -1.0]), b=np.array([5.0, 3.0]),
                           sense=np.frombuffer(b"EL", dtype=np.uint8), l=np.zeros(2),
                           u=np.full(2, hi), x0=np.zeros(2))
-    with make_ctx(inst(4.0)) as ctx:
-        ctx.set_batch(deltas([SET_HI, BASE], [0, 0], [0.5, 0.0]))   # x0 <= 0.5 -> x1 >= 4.5 > 4
+    base_lp = O.from_instance(inst(4.0))
+    eta = O.step_size(base_lp.A)
+    D = deltas([SET_HI, BASE], [0, 0], [0.5, 0.0])                 # x0 <= 0.5 -> x1 >= 4.5 > 4
+    with make_ctx(inst(4.0), eta, eval_every=C) as ctx:
+        ctx.set_batch(D)
         ctx.solve(tol=1e-8, max_iters=200000)
         out = ctx.get_batch()
     assert list(out["status"]) == [P.STATUS_PRIMAL_INFEASIBLE, P.STATUS_OPTIMAL]
-    lp = O.apply_delta(O.from_instance(inst(4.0)), SET_HI, 0, 0.5)
-    assert O.solve(lp, O.Options(tol=1e-8, max_iters=200000)).status == O.PRIMAL_INFEASIBLE
+    for j, d in enumerate(D):
+        r = oracle_run(lp_for(base_lp, d), eta, 1e-8, 200000, eval_every=C)
+        assert (out["status"][j], out["iters"][j]) == (r.status, r.iters), (j, C)
     # unbounded: min -x0 s.t. x0 - x1 = 0, x >= 0 with no upper bounds
     B1 = sp.csr_matrix(np.array([[1.0, -1.0]]))
     unb = LPInstance(m=1, n=2, row_ptr=B1.indptr.astype(np.int64), col_idx=B1.indices, val=B1.data,
                      c=np.array([-1.0, 0.0]), b=np.zeros(1), sense=np.frombuffer(b"E", np.uint8),
                      l=np.zeros(2), u=np.full(2, np.inf), x0=np.zeros(2))
-    with make_ctx(unb) as ctx:
-        ctx.set_batch(deltas([BASE, OBJ_UNIT], [0, 1], [0.0, 1.0]))   # min -x0 (unbounded), min x1
+    unb_lp = O.from_instance(unb)
+    eta = O.step_size(unb_lp.A)
+    D = deltas([BASE, OBJ_UNIT], [0, 1], [0.0, 1.0])                # min -x0 (unbounded), min x1
+    with make_ctx(unb, eta, eval_every=C) as ctx:
+        ctx.set_batch(D)
         ctx.solve(tol=1e-8, max_iters=200000)
         out = ctx.get_batch()
     assert list(out["status"]) == [P.STATUS_DUAL_INFEASIBLE, P.STATUS_OPTIMAL]
+    for j, d in enumerate(D):
+        r = oracle_run(lp_for(unb_lp, d), eta, 1e-8, 200000, eval_every=C)
+        assert (out["status"][j], out["iters"][j]) == (r.status, r.iters), (j, C)
 
 
 def test_tiny_lps_reach_exact_optimum(P):
