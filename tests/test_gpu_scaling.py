@@ -56,15 +56,16 @@ def test_fixed_iterations_match_oracle(P, setup, K):
         assert rel_err(got[j]["x"], x) <= ITER_RTOL and rel_err(got[j]["y"], y) <= ITER_RTOL, j
 
 
-def test_converged_match_oracle(P, setup):
+@pytest.mark.parametrize("C", [64, 32])
+def test_converged_match_oracle(P, setup, C):
     inst, lp, dr, dc, eta, root, xr, yr, D = setup
-    with make_ctx(inst, eta, scaling=1) as ctx:
+    with make_ctx(inst, eta, scaling=1, eval_every=C) as ctx:
         ctx.set_batch(D, x_warm=xr, y_warm=yr, w_warm=np.full(len(D), root.w))
         ctx.solve(tol=1e-4, max_iters=50000)
         got = ctx.get_batch()
     for j, d in enumerate(D):
         r, x, y = S.solve_scaled(lp_for(lp, d), O.Options(tol=1e-4, max_iters=50000,
-                                                          step_size=eta),
+                                                          step_size=eta, eval_every=C),
                                  dr, dc, x_init=xr, y_init=yr, w_init=root.w)
         assert got["status"][j] == r.status and got["iters"][j] == r.iters, j
         assert rel_err(got["X"][j], x) <= 1e-8, j
