@@ -23,9 +23,13 @@ forms (a diagonal matrix equilibrated in one pass, the Pock-Chambolle bound
 ||D_r A D_c|| <= 1) and objective invariance; the MIP outputs against exact
 variable ranges and child optima from vertex enumeration and HiGHS; the
 iterate trajectory without restarts against the worst-case rate bound of the
-Halpern iteration.  Parity unpinned: the exact trajectories with restarts and
-the iteration counts (the paper prints none), and the values of the restart
-constants beta_s, beta_n, beta_a, theta (named, not valued, in the paper).
+Halpern iteration; restarted trajectories (fixed weight) against what firm
+nonexpansiveness fixes across a restart: each cycle starts no farther from a
+solution than the first, its first residual is at most the one that fired the
+restart, and the rate bound holds from its own start.  Parity unpinned: the
+exact restart times and iteration counts (the paper prints none), and the
+values of the restart constants beta_s, beta_n, beta_a, theta (named, not
+valued, in the paper).
 """
 from .lp import LP, row_bounds, from_arrays, from_instance, apply_delta, BASE, SET_LO, SET_HI, OBJ_UNIT
 from .pdhg import (Options, Result, KKT, solve, solve_batch_avg, pdhg_operator,

@@ -1,8 +1,8 @@
 """End-to-end pins of the reference solver: the converged objective against
 exact optima (vertex enumeration, box closed form, hand-solved LPs, HiGHS),
 KKT and complementary-slackness invariants at every returned point, the
-strong-branching / bound-tightening semantics of Section 5, statuses, and the
-batched restart scope."""
+strong-branching / bound-tightening semantics of Section 5, statuses, the
+batched restart scope, and the Halpern rate bound with and without restarts."""
 import json
 import math
 import os
@@ -287,3 +287,148 @@ def test_halpern_rate_bound_catches_planted_mistakes(seed, mistake):
                                                                 _halpern(k, 2 * yt - y, y0)))
     assert good <= 1.0
     assert _worst_ratio(*args, _MISTAKES[mistake]) > 1.05
+
+
+# ---------------------------------------------------------------------------
+# Restarted trajectories (Section 4, Restarts).  With theta = 0 the smoothed
+# weight equals the old one, so T and the metric M stay the same across
+# restarts, and with z* a fixed point three facts follow from T being firmly
+# nonexpansive in M:
+#   (i)   every cycle starts no farther from z* than the first one does
+#         (||T z - z*|| <= ||z - z*||, and a Halpern iterate is a convex
+#         combination of R z^k and its anchor, both inside that ball);
+#   (ii)  a new cycle's first residual is at most the residual that fired the
+#         restart (||T(T z) - T z|| <= ||T z - z||);
+#   (iii) inside each cycle the Halpern bound above holds from that cycle's
+#         own start.
+# Checked on cycles whose start is farther from z* than 1e-7 of the first,
+# above the accuracy of the converged reference point and of rounding.
+# ---------------------------------------------------------------------------
+
+def _restart_opts(K, eta, C):
+    return O.Options(tol=0.0, max_iters=K, eval_every=C, theta=0.0, infeas_tol=0.0, step_size=eta)
+
+
+def _residual(lp, eta, w, x, y):
+    xt, yt = O.pdhg_operator(lp, x, y, eta / w, eta * w)
+    return O.fixed_point_residual(lp, x, y, xt, yt, w, eta)
+
+
+def _oracle_cycles(lp, eta, w, x0, y0, C, K, js=(1, 2, 3, 5, 8, 13, 21, 34, 55)):
+    """Cycles of the oracle's restarted run of K iterations, read from shorter
+    runs of the same solve: max_iters = t + 1 returns T(z^t), which is the next
+    cycle's start when t fired a restart, and max_iters = t returns z^t."""
+    run = lambda KK: O.solve(lp, _restart_opts(KK, eta, C), x_init=x0, y_init=y0, w_init=w)
+    ts = run(K).restarts
+    cycles = []
+    for n, b in enumerate([0] + [t + 1 for t in ts]):
+        if n == 0:
+            start = (x0, y0)
+        else:
+            r = run(b)
+            assert r.restarts == ts[:n - 1]
+            start = (r.x, r.y)
+        end = ts[n] if n < len(ts) else K - 1
+        samples = [(0, _residual(lp, eta, w, *start))]
+        for j in js:
+            if b + j <= end:
+                r = run(b + j)
+                samples.append((j, _residual(lp, eta, w, r.x_iter, r.y_iter)))
+        trig = None
+        if n < len(ts):
+            r = run(ts[n])
+            trig = _residual(lp, eta, w, r.x_iter, r.y_iter)
+        cycles.append(dict(start=start, trig=trig, samples=samples))
+    return cycles
+
+
+def _restart_ratios(lp, eta, w, ref, cycles, floor=1e-7):
+    """Worst ratios of (i), (ii), (iii) over the cycles above the floor (each
+    at most 1 when the facts hold) and the number of cycles checked."""
+    dist = lambda z: O.fixed_point_residual(lp, z[0], z[1], ref.x, ref.y, w, eta)
+    d0 = dist(cycles[0]["start"])
+    out = {"start": 0.0, "first residual": 0.0, "rate": 0.0}
+    checked = 0
+    for n, c in enumerate(cycles):
+        dn = dist(c["start"])
+        if dn < floor * d0:
+            break
+        checked += 1
+        out["start"] = max(out["start"], dn / d0)
+        if n:
+            out["first residual"] = max(out["first residual"],
+                                        c["samples"][0][1] / cycles[n - 1]["trig"])
+        for j, r in c["samples"]:
+            out["rate"] = max(out["rate"], r * (j + 1) / dn)
+    return out, checked
+
+
+def _setup_with_star(inst, seed):
+    lp, eta, w, x0, y0, _ = _rate_setup(inst, seed)
+    ref = O.solve(lp, O.Options(tol=1e-12, max_iters=400000, step_size=eta))
+    return lp, eta, w, x0, y0, ref
+
+
+@pytest.mark.parametrize("C", [16, 64])
+@pytest.mark.parametrize("start", [None, 101])
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_restarted_trajectory_bounds(seed, start, C):
+    inst = make_tiny(seed, m=4, n=7, senses="ELG", box=(0.0, 3.0))
+    lp, eta, w, x0, y0, ref = _setup_with_star(inst, start)
+    cycles = _oracle_cycles(lp, eta, w, x0, y0, C, K=1000)
+    ratios, checked = _restart_ratios(lp, eta, w, ref, cycles)
+    assert checked >= 4, checked
+    for name, v in ratios.items():
+        assert v <= 1.0 + 1e-6, (name, v)
+
+
+def _restarted_copy(lp, eta, w, x0, y0, C, K, mistake=None):
+    """A copy of the restarted iteration built from the oracle's operator,
+    residual and restart test, with a mistake planted in the restart."""
+    x, y, xa, ya = x0, y0, x0, y0
+    k, r0, r_prev = 0, None, None
+    cycles = [dict(start=(x, y), trig=None, samples=[])]
+    restarts = []
+    for t in range(K):
+        xt, yt = O.pdhg_operator(lp, x, y, eta / w, eta * w)
+        full = t % C == 0
+        r = O.fixed_point_residual(lp, x, y, xt, yt, w, eta)
+        cycles[-1]["samples"].append((k if mistake != "k not reset" else len(cycles[-1]["samples"]), r))
+        if k == 0:
+            r0 = r
+        elif full and O.restart_due(r, r0, r_prev, k, t, 0.2, 0.8, 0.36):
+            cycles[-1]["trig"] = r
+            restarts.append(t)
+            if mistake == "restart to the anchor":
+                x, y = xa, ya
+            elif mistake == "anchor kept":
+                x, y = xt, yt
+            else:
+                x, y, xa, ya = xt, yt, xt, yt
+            cycles.append(dict(start=(x, y), trig=None, samples=[]))
+            k = k + 1 if mistake == "k not reset" else 0
+            r_prev = None
+            continue
+        if full or k == 0:
+            r_prev = r
+        x = (k + 1) / (k + 2) * (2 * xt - x) + xa / (k + 2)
+        y = (k + 1) / (k + 2) * (2 * yt - y) + ya / (k + 2)
+        k += 1
+    return cycles, restarts
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_restarted_trajectory_bounds_catch_planted_mistakes(seed):
+    inst = make_tiny(seed, m=4, n=7, senses="ELG", box=(0.0, 3.0))
+    lp, eta, w, x0, y0, ref = _setup_with_star(inst, 100 + seed)
+    K, C = 1500, 16
+    cycles, restarts = _restarted_copy(lp, eta, w, x0, y0, C, K)
+    # the copy restarts where the oracle does, and meets the bounds
+    assert restarts == O.solve(lp, _restart_opts(K, eta, C), x_init=x0, y_init=y0,
+                               w_init=w).restarts
+    ratios, _ = _restart_ratios(lp, eta, w, ref, cycles)
+    assert max(ratios.values()) <= 1.0 + 1e-6, ratios
+    for mistake in ("restart to the anchor", "anchor kept", "k not reset"):
+        cycles, _ = _restarted_copy(lp, eta, w, x0, y0, C, K, mistake)
+        ratios, _ = _restart_ratios(lp, eta, w, ref, cycles)
+        assert max(ratios.values()) > 1.5, (mistake, ratios)
