@@ -1,6 +1,7 @@
 """Degenerate shapes through the C ABI against the oracle: no rows at all,
 only free rows (the box-only closed form), empty rows and columns, a matrix
-without nonzeros, and one-variable LPs."""
+without nonzeros, one-variable LPs, the widest batch, and free and half-bounded
+variables in an LP of several tiles."""
 import numpy as np
 import pytest
 import scipy.sparse as sp
@@ -120,3 +121,34 @@ def test_maximum_batch_width(P):
     for u, (res, tr) in sample.items():
         ores = O.solve(lp_for(lp, U[u]), O.Options(tol=0.0, max_iters=K, step_size=eta))
         assert_trajectory_match(res, tr, ores, what=f"LP {u}")
+
+
+@pytest.mark.parametrize("K", [1, 65, 300])
+def test_infinite_bounds_several_tiles(P, K):
+    """Free, lower-only and upper-only variables in a 200 x 500 LP (several row
+    tiles, nine LPs for a ragged slot tile): the projections, reduced costs and
+    support functions at infinite bounds give the oracle's iterates, statuses
+    and restart iterations after K iterations."""
+    import dataclasses
+    from tests.gpu_common import lp_for, oracle_run, assert_trajectory_match
+    from workloads import make_cfg2
+    inst = make_cfg2(m=200, n=500)
+    kind = np.random.default_rng(7).integers(0, 4, size=inst.n)   # box, free, [l, inf), (-inf, u]
+    l, u = inst.l.copy(), inst.u.copy()
+    l[kind == 1], u[kind == 1] = -np.inf, np.inf
+    u[kind == 2] = np.inf
+    l[kind == 3] = -np.inf
+    inst = dataclasses.replace(inst, l=l, u=u)
+    lp = O.from_instance(inst)
+    eta = O.step_size(lp.A)
+    free, lower, upper = (int(np.flatnonzero(kind == k)[0]) for k in (1, 2, 3))
+    D = deltas([BASE, SET_LO, SET_HI, SET_HI, SET_LO, OBJ_UNIT, OBJ_UNIT, SET_LO, SET_HI],
+               [0, free, free, lower, upper, free, lower, lower, upper],
+               [0.0, -1.0, 2.0, 5.0, 3.0, 1.0, -1.0, 1.0, 8.0])
+    with P.Context.from_instance(inst, step_size=float(eta)) as ctx:
+        ctx.set_batch(D)
+        ctx.solve(tol=0.0, max_iters=K)
+        got = [(ctx.get(j), ctx.get_trace(j)) for j in range(len(D))]
+    for j, d in enumerate(D):
+        ores = oracle_run(lp_for(lp, d), eta, 0.0, K)
+        assert_trajectory_match(*got[j], ores, what=f"LP {j} K={K}")
