@@ -453,3 +453,29 @@ def test_caller_stream_and_device_buffers(P):
     np.testing.assert_array_equal(X.cpu().numpy(), ref["X"])
     np.testing.assert_array_equal(Y.cpu().numpy(), ref["Y"])
     np.testing.assert_allclose(row_sums.cpu().numpy(), ref["X"].sum(axis=1), rtol=1e-12)
+
+
+@pytest.mark.parametrize("K", [1, 66, 200])
+def test_per_lp_warm_starts(P, K):
+    """Each LP starts from its own primal point (partly outside the box, which
+    the start projects onto), its own dual point and its own primal weight; the
+    iterates, statuses and restart iterations after K iterations equal the
+    oracle's started the same way."""
+    inst = make_cfg2(m=200, n=500)
+    lp = O.from_instance(inst)
+    eta = O.step_size(lp.A)
+    rng = np.random.default_rng(11)
+    B = 7
+    D = obbt_deltas(choose_vars(inst.n, 3, seed=5))[:B - 1]
+    D = np.concatenate([deltas([BASE], [0], [0.0]), D])
+    X0 = rng.uniform(-2.0, 12.0, size=(B, inst.n))          # box [0, 10]
+    Y0 = rng.normal(size=(B, inst.m))
+    W0 = np.exp(rng.uniform(np.log(0.1), np.log(10.0), size=B))
+    with make_ctx(inst, eta) as ctx:
+        ctx.set_batch(D, x_warm=X0.ravel(), y_warm=Y0.ravel(), w_warm=W0,
+                      warm_mode=P.WARM_PER_LP)
+        ctx.solve(tol=0.0, max_iters=K)
+        res = [(ctx.get(j), ctx.get_trace(j)) for j in range(B)]
+    for j, d in enumerate(D):
+        ores = oracle_run(lp_for(lp, d), eta, 0.0, K, X0[j], Y0[j], W0[j])
+        assert_trajectory_match(*res[j], ores, what=f"LP {j} K={K}")
