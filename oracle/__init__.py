@@ -23,8 +23,8 @@ forms (a diagonal matrix equilibrated in one pass, the Pock-Chambolle bound
 ||D_r A D_c|| <= 1) and objective invariance; the MIP outputs against exact
 variable ranges and child optima from vertex enumeration and HiGHS; the
 iterate trajectory without restarts against the worst-case rate bound of the
-Halpern iteration; restarted trajectories (fixed weight) against what firm
-nonexpansiveness fixes across a restart: each cycle starts no farther from a
+Halpern iteration; restarted trajectories (fixed weight, per LP and under the
+batch-average scope) against what firm nonexpansiveness fixes across a restart: each cycle starts no farther from a
 solution than the first, its first residual is at most the one that fired the
 restart, and the rate bound holds from its own start.  Parity unpinned: the
 exact restart times and iteration counts (the paper prints none), and the

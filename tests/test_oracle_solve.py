@@ -314,11 +314,11 @@ def _residual(lp, eta, w, x, y):
     return O.fixed_point_residual(lp, x, y, xt, yt, w, eta)
 
 
-def _oracle_cycles(lp, eta, w, x0, y0, C, K, js=(1, 2, 3, 5, 8, 13, 21, 34, 55)):
-    """Cycles of the oracle's restarted run of K iterations, read from shorter
-    runs of the same solve: max_iters = t + 1 returns T(z^t), which is the next
-    cycle's start when t fired a restart, and max_iters = t returns z^t."""
-    run = lambda KK: O.solve(lp, _restart_opts(KK, eta, C), x_init=x0, y_init=y0, w_init=w)
+def _oracle_cycles(lp, eta, w, x0, y0, K, run, js=(1, 2, 3, 5, 8, 13, 21, 34, 55)):
+    """Cycles of one LP's restarted run of K iterations, read from shorter runs
+    of the same solve (`run(max_iters)` returns that LP's result):
+    max_iters = t + 1 returns T(z^t), which is the next cycle's start when t
+    fired a restart, and max_iters = t returns z^t."""
     ts = run(K).restarts
     cycles = []
     for n, b in enumerate([0] + [t + 1 for t in ts]):
@@ -375,11 +375,35 @@ def _setup_with_star(inst, seed):
 def test_restarted_trajectory_bounds(seed, start, C):
     inst = make_tiny(seed, m=4, n=7, senses="ELG", box=(0.0, 3.0))
     lp, eta, w, x0, y0, ref = _setup_with_star(inst, start)
-    cycles = _oracle_cycles(lp, eta, w, x0, y0, C, K=1000)
+    run = lambda KK: O.solve(lp, _restart_opts(KK, eta, C), x_init=x0, y_init=y0, w_init=w)
+    cycles = _oracle_cycles(lp, eta, w, x0, y0, 1000, run)
     ratios, checked = _restart_ratios(lp, eta, w, ref, cycles)
     assert checked >= 4, checked
     for name, v in ratios.items():
         assert v <= 1.0 + 1e-6, (name, v)
+
+
+@pytest.mark.parametrize("C", [16, 64])
+def test_restarted_trajectory_bounds_batch_average(C):
+    """The same facts for every LP of a batch under the batch-average scope,
+    where the mean residual decides when all LPs restart together."""
+    import functools
+    lps = [O.from_instance(make_tiny(s, m=4, n=7, senses="ELG", box=(0.0, 3.0))) for s in range(3)]
+    eta = min(O.step_size(lp.A) for lp in lps)
+    ws = [O.initial_primal_weight(lp) for lp in lps]
+    rng = np.random.default_rng(5)
+    x0s = [O.proj_box(rng.uniform(-1.0, 4.0, lp.n), lp.xl, lp.xu) for lp in lps]
+    y0s = [O.proj_barrier_cone(rng.normal(size=lp.m), lp.l, lp.u) for lp in lps]
+    runs = functools.lru_cache(maxsize=None)(
+        lambda KK: O.solve_batch_avg(lps, _restart_opts(KK, eta, C), x0s, y0s, ws))
+    for j, lp in enumerate(lps):
+        ref = O.solve(lp, O.Options(tol=1e-12, max_iters=400000, step_size=eta))
+        assert ref.status == O.OPTIMAL
+        cycles = _oracle_cycles(lp, eta, ws[j], x0s[j], y0s[j], 1000, lambda KK: runs(KK)[j])
+        ratios, checked = _restart_ratios(lp, eta, ws[j], ref, cycles)
+        assert checked >= 3, (j, checked)
+        for name, v in ratios.items():
+            assert v <= 1.0 + 1e-6, (j, name, v)
 
 
 def _restarted_copy(lp, eta, w, x0, y0, C, K, mistake=None):
