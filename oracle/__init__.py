@@ -24,9 +24,10 @@ forms (a diagonal matrix equilibrated in one pass, the Pock-Chambolle bound
 variable ranges and child optima from vertex enumeration and HiGHS; the
 iterate trajectory without restarts against the worst-case rate bound of the
 Halpern iteration; restarted trajectories (fixed weight, per LP and under the
-batch-average scope) against what firm nonexpansiveness fixes across a restart: each cycle starts no farther from a
-solution than the first, its first residual is at most the one that fired the
-restart, and the rate bound holds from its own start.  Parity unpinned: the
+batch-average scope) against what firm nonexpansiveness fixes across a
+restart: each cycle starts no farther from a solution than the first, its
+first residual is at most the one that fired the restart, and the rate bound
+holds from its own start.  Parity unpinned: the
 exact restart times and iteration counts (the paper prints none), and the
 values of the restart constants beta_s, beta_n, beta_a, theta (named, not
 valued, in the paper).
