@@ -4,7 +4,9 @@ A 20000 x 50000 with 8 U[-1,1] nonzeros per column, E/L/G rows, box [0,5];
 iterates and products with FP64 sums against the FP64 run of the same batch,
 and every FP32 point re-measured by the oracle's FP64 KKT, both against A
 itself and against A rounded to FP32 (the matrix the FP32 run multiplies by),
-which separates the data rounding from the iteration's own error."""
+which separates the data rounding from the iteration's own error.  At a
+smaller size, the mixed-mode iterates after a fixed number of iterations
+against the FP64 oracle, within the growth of FP32 rounding."""
 import numpy as np
 import pytest
 import scipy.sparse as sp
@@ -49,3 +51,32 @@ def test_mixed32_precision_statement_full_size(P):
           f"(vs FP32-rounded A: max {max(rel32):.2e})")
     assert err[both].max() <= 1e-3
     assert max(rel) <= 2e-3 and max(rel32) <= 2e-3
+
+
+@pytest.mark.parametrize("K", [1, 2, 8, 32, 64])
+def test_mixed32_fixed_iterations_within_rounding_growth(P, K):
+    """The mixed mode runs the oracle's iteration: after K iterations its
+    iterates differ from the FP64 oracle's by at most 4 (K + 1) u relative,
+    u = 2^-24.  Each iteration rounds to FP32 at most four times what it feeds
+    forward (the primal and dual points of T, the Halpern combination, and A
+    itself), and the reflected step is nonexpansive, so these errors add up
+    without growing.  K <= 64 keeps every decision (stopping, infeasibility,
+    restart) out of the run: with tol = 0 the only full evaluation is at
+    t = 0, so statuses, counts and restart logs must also agree exactly."""
+    from tests.gpu_common import oracle_run, rel_err
+    inst = make_cfg3(m=2000, n=5000)
+    lp = O.from_instance(inst)
+    eta = O.step_size(lp.A)
+    D = obbt_deltas(choose_vars(lp.n, 4, seed=12))
+    with make_ctx(inst, eta, precision=P.MIXED32) as ctx:
+        ctx.set_batch(D)
+        ctx.solve(tol=0.0, max_iters=K)
+        res = [(ctx.get(j), ctx.get_trace(j)) for j in range(len(D))]
+    bound = 4 * (K + 1) * 2.0 ** -24
+    for j, d in enumerate(D):
+        o = oracle_run(lp_for(lp, d), eta, 0.0, K)
+        g, tr = res[j]
+        assert (g["status"], g["iters"], tr["restart_log"]) == (o.status, o.iters, o.restarts[:64])
+        errs = (rel_err(g["x"], o.x), rel_err(g["y"], o.y), rel_err(tr["x_iter"], o.x_iter),
+                rel_err(tr["y_iter"], o.y_iter))
+        assert max(errs) <= bound, (j, K, errs, bound)
