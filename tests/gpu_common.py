@@ -10,6 +10,13 @@ import oracle as O
 from workloads import make_cfg2, choose_fractional, fsb_deltas, seed_for
 
 ITER_RTOL = 1e-9          # relative error on iterates after a fixed iteration count (FP64)
+# The KKT measures of eq:stopping are ratios of norms of the iterates; iterates
+# within ITER_RTOL move them by at most ITER_RTOL times norm ratios such as
+# ||A|| ||x|| / (1 + ||Ax||), which stay below 100 on these workloads.
+KKT_ATOL = 1e-7
+# |c'x_gpu - c'x_ref| <= ||c|| ||x|| ITER_RTOL, and ||c|| ||x|| / (1 + |c'x|)
+# stays below 1000 on these workloads
+OBJ_RTOL = 1e-6
 
 
 def rel_err(a, b) -> float:
@@ -56,6 +63,15 @@ def assert_trajectory_match(gpu_res, gpu_trace, ores, rtol=ITER_RTOL, what=""):
     ex = rel_err(gpu_res["x"], ores.x)
     ey = rel_err(gpu_res["y"], ores.y)
     assert ex <= rtol and ey <= rtol, (what, ex, ey)
+    if ores.kkt is not None and "kkt" in gpu_res:
+        ref = (ores.kkt.gap, ores.kkt.primal, ores.kkt.dual, ores.kkt.rel)
+        for name, a, b in zip(("gap", "primal", "dual", "max"), gpu_res["kkt"], ref):
+            if np.isfinite(b):
+                assert abs(a - b) <= KKT_ATOL, (what, name, a, b)
+            else:
+                assert a == b or (np.isnan(a) and np.isnan(b)), (what, name, a, b)
+        assert abs(gpu_res["obj"] - ores.kkt.obj) <= OBJ_RTOL * (1 + abs(ores.kkt.obj)), \
+            (what, "obj", gpu_res["obj"], ores.kkt.obj)
     if ores.x_iter is not None:
         exi = rel_err(gpu_trace["x_iter"], ores.x_iter)
         eyi = rel_err(gpu_trace["y_iter"], ores.y_iter)
