@@ -129,3 +129,30 @@ def test_initial_primal_weight():
 def test_opnorm_when_constant_vector_is_in_null_space():
     A = sp.csr_matrix(np.array([[1.0, -1.0], [2.0, -2.0]]))
     assert math.isclose(O.opnorm(A), np.linalg.norm(A.toarray(), 2), rel_tol=1e-12)
+
+
+def _log_imbalance(w, dx, dy, eta=0.7):
+    """log of the ratio of the two diagonal terms of the residual metric,
+    (w/eta) ||dx||^2 against ||dy||^2 / (eta w)."""
+    return math.log((w / eta) * dx * dx) - math.log(dy * dy / (eta * w))
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_primal_weight_update_balances_the_metric(seed):
+    """The weight update (Section 4) exists to balance the primal and dual
+    parts of the residual metric: with the ratio ||dy|| / ||dx|| (reading R2),
+    smoothing with theta shrinks their log-imbalance by the factor 1 - theta,
+    and theta = 1 balances them exactly.  The printed ratio ||dx|| / ||dy||, or
+    the two smoothing weights swapped, breaks this."""
+    rng = np.random.default_rng(seed)
+    dx, dy = np.exp(rng.uniform(-3, 3, size=2))
+    w0 = float(np.exp(rng.uniform(-3, 3)))
+    before = _log_imbalance(w0, dx, dy)
+    for theta in (0.0, 0.3, 0.5, 1.0):
+        after = _log_imbalance(O.smoothed_primal_weight(dx, dy, w0, theta), dx, dy)
+        assert math.isclose(after, (1.0 - theta) * before, rel_tol=1e-9, abs_tol=1e-9)
+    # planted mistakes, on the CPU: the printed ratio, and the weights swapped
+    printed = _log_imbalance(O.smoothed_primal_weight(dx, dy, w0, 1.0, ratio="dx/dy"), dx, dy)
+    assert abs(printed) > 1e-3
+    swapped = w0 ** 0.3 * (dy / dx) ** 0.7                 # theta applied to the old weight
+    assert not math.isclose(_log_imbalance(swapped, dx, dy), 0.7 * before, rel_tol=1e-6)
