@@ -3,7 +3,8 @@
 Each operator is checked against an independent statement of what it must
 be: a scalar minimisation for the proximal steps, a brute-force nearest point
 for the projections, a hand-solved primal-dual pair for the fixed point of T,
-and HiGHS duals for strong duality of the support-function dual.
+and HiGHS duals for strong duality of the support-function dual, HiGHS optima
+for its weak duality.
 """
 import json
 import math
@@ -214,3 +215,34 @@ def test_apply_delta_kinds():
     ob = O.apply_delta(lp, O.OBJ_UNIT, 1, -1.0)
     assert ob.c[1] == -1.0 and np.count_nonzero(ob.c) == 1
     assert O.apply_delta(lp, O.BASE, 0, 0.0).c is lp.c
+
+
+
+def _dual_value(lp, y, flip_aty=False):
+    """The dual objective as the oracle's KKT reports it; with flip_aty, the
+    same with the sign of A'y in the reduced cost flipped (a planted mistake)."""
+    if not flip_aty:
+        return O.kkt(lp, O.proj_box(np.zeros(lp.n), lp.xl, lp.xu), y).dual_obj
+    r = O.proj_barrier_cone(-lp.c + lp.A.T @ y, lp.xl, lp.xu)
+    return -(O.support(r, lp.xl, lp.xu) + O.support(y, lp.l, lp.u))
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_dual_objective_is_a_lower_bound(seed):
+    """Weak duality: with a finite box, the dual objective at ANY dual point of
+    the barrier cone is at most the LP optimum (HiGHS), and it reaches it at the
+    optimal duals (checked above).  The sign of A'y flipped in the reduced cost,
+    planted on the CPU, exceeds the optimum."""
+    from workloads import make_tiny
+    lp = O.from_instance(make_tiny(seed, m=4, n=7, senses="ELG", box=(0.0, 3.0)))
+    opt, _, _ = highs(lp)
+    rng = np.random.default_rng(seed)
+    worst = -np.inf
+    worst_planted = -np.inf
+    for scale in (0.1, 1.0, 10.0, 100.0):
+        for _ in range(100):
+            y = O.proj_barrier_cone(rng.normal(scale=scale, size=lp.m), lp.l, lp.u)
+            worst = max(worst, _dual_value(lp, y) - opt)
+            worst_planted = max(worst_planted, _dual_value(lp, y, flip_aty=True) - opt)
+    assert worst <= 1e-9 * (1 + abs(opt)), worst
+    assert worst_planted > 1e-3, worst_planted
