@@ -80,3 +80,32 @@ def test_mixed32_fixed_iterations_within_rounding_growth(P, K):
         errs = (rel_err(g["x"], o.x), rel_err(g["y"], o.y), rel_err(tr["x_iter"], o.x_iter),
                 rel_err(tr["y_iter"], o.y_iter))
         assert max(errs) <= bound, (j, K, errs, bound)
+
+
+def test_mixed32_bound_tightening_batch_sampled_fixed_iterations(P):
+    """The bound-tightening batch as the benchmark runs it (A 20000 x 50000,
+    256 LPs, FP32 iterates, default options with the tile autotuner) after 64
+    iterations: every LP is still running with 64 iterations, and sampled LPs
+    recomputed one at a time by the FP64 oracle agree within 4 (K + 1) u, the
+    bound of the fixed-iteration test above."""
+    from tests.gpu_common import oracle_run, rel_err
+    inst = make_cfg3()
+    lp = O.from_instance(inst)
+    eta = O.step_size(lp.A)
+    D = obbt_deltas(choose_vars(inst.n, 128, seed_for(3, 0)))
+    K = 64
+    sample = [0, 127, 128, 255]
+    with make_ctx(inst, eta, precision=P.MIXED32) as ctx:
+        ctx.set_batch(D)
+        ctx.solve(tol=0.0, max_iters=K)
+        st = ctx.get_batch(want_x=False, want_y=False)
+        res = {j: (ctx.get(j), ctx.get_trace(j)) for j in sample}
+    assert np.all(st["iters"] == K) and np.all(st["status"] == P.STATUS_ITERATION_LIMIT)
+    bound = 4 * (K + 1) * 2.0 ** -24
+    for j in sample:
+        o = oracle_run(lp_for(lp, D[j]), eta, 0.0, K)
+        g, tr = res[j]
+        errs = (rel_err(g["x"], o.x), rel_err(g["y"], o.y), rel_err(tr["x_iter"], o.x_iter),
+                rel_err(tr["y_iter"], o.y_iter))
+        print(f"LP {j}: {max(errs):.2e} (bound {bound:.2e})")
+        assert max(errs) <= bound, (j, errs, bound)
