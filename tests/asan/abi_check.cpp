@@ -1,4 +1,4 @@
-// C ABI driver for host-side AddressSanitizer builds.  Without arguments: input
+// C ABI test program for host-side AddressSanitizer builds.  Without arguments: input
 // validation of pdlpb_create, every entry point with a NULL context, and (when
 // no device is present) the device-failure path.  With --device: one context
 // through solve, getters, bound tightening, branching scores, device-pointer

@@ -1,8 +1,8 @@
 """The library's host code under AddressSanitizer (host side only; device code
-is built as usual): a driver linked with the library sources checks the input
+is built as usual): a test program linked with the library sources checks the input
 validation of pdlpb_create, every entry point with a NULL context and, on a
 machine without a GPU, the failure path of a well-formed create.  Any memory
-error or leak in that code fails the driver's exit status.  The same driver
+error or leak in that code fails the program's exit status.  The same program
 with --device runs a context through every entry point on a GPU."""
 import os
 import shutil
@@ -17,13 +17,13 @@ HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 
 @pytest.mark.skipif(not os.path.exists(HIPCC), reason="hipcc not installed")
 def test_abi_host_code_under_address_sanitizer(tmp_path):
-    exe = tmp_path / "abi_driver"
+    exe = tmp_path / "abi_check"
     cmd = [HIPCC, "-O1", "-g", "--offload-arch=gfx950", "-std=c++17",
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
            "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fno-omit-frame-pointer",
            "-fno-gpu-rdc", "-I" + os.path.join(ROOT, "include"), "-I" + CSRC, "-x", "hip",
            os.path.join(CSRC, "kernels.hip"), os.path.join(CSRC, "pdlpb.cpp"),
-           os.path.join(ROOT, "tests", "asan", "abi_driver.cpp"), "-o", str(exe)]
+           os.path.join(ROOT, "tests", "asan", "abi_check.cpp"), "-o", str(exe)]
     b = subprocess.run(cmd, capture_output=True, text=True, timeout=600)
     assert b.returncode == 0, b.stderr[-3000:]
     # allocations the ROCm runtime keeps until exit are not the library's
