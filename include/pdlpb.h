@@ -285,10 +285,16 @@ int pdlpb_serve_launch(pdlpb_ctx* ctx);
 int pdlpb_serve_wait(pdlpb_ctx* ctx, int32_t* n_running, int32_t* n_queued);
 /* Ids of LPs that stopped since the last poll (at most cap); *count receives how many. */
 int pdlpb_poll(pdlpb_ctx* ctx, int64_t* ids, int32_t cap, int32_t* count);
-/* Result of a submitted LP (as pdlpb_get); x and y are written once it has stopped. */
+/*
+ * Result of a submitted LP (as pdlpb_get).  Until the LP has stopped (its id
+ * was returned by pdlpb_poll, or it settled at submission) the call reports
+ * status PDLPB_STATUS_RUNNING, kkt and obj NaN and iters 0, and writes
+ * neither x nor y.  EINVAL for an unknown or released id.
+ */
 int pdlpb_result(pdlpb_ctx* ctx, int64_t id, double* x, double* y, int32_t* status,
                  double kkt[4], double* obj, int64_t* iters, int32_t mem);
-/* Free the result row of a stopped LP; its id becomes invalid. */
+/* Free the result row of a stopped LP; its id becomes invalid.  PDLPB_ESTATE
+ * while the LP is queued or running (its row is still in use). */
 int pdlpb_release(pdlpb_ctx* ctx, int64_t id);
 
 /*
@@ -333,6 +339,12 @@ int pdlpb_kernel_columns(pdlpb_ctx* ctx, int64_t cols[4]);
 
 /* Bytes of device memory held by the context. */
 int64_t pdlpb_device_bytes(const pdlpb_ctx* ctx);
+
+/* Number of blocks of C iterations captured as graphs over the context's life.
+ * A captured block is replayed for every later batch or serving round with the
+ * same launch shape (live column bound, row stride, tile shapes), and is
+ * captured again only when the context's storage is reallocated. */
+int64_t pdlpb_graph_captures(const pdlpb_ctx* ctx);
 
 /* Release every device buffer and the context.  NULL is a no-op. */
 void pdlpb_destroy(pdlpb_ctx* ctx);

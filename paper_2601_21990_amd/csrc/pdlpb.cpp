@@ -90,7 +90,7 @@ struct pdlpb_ctx {
     int vec_ld = 1;                 // vector width ld is padded for
     // tile shapes chosen by timing, per (live column shape, ld)
     std::vector<std::pair<int64_t, std::pair<Tile, Tile>>> tuned;
-    size_t cap_block_bytes = 0;     // bytes of each of the 8 dense blocks
+    size_t cap_block_bytes = 0;     // bytes of each of the 8 dense blocks per row (ld * element size)
     void* blk[8] = {};              // Xbar, X0, Xt, DX, Y, Y0, Yt, DY (row-major, stride ld)
     size_t cap_res_x = 0, cap_res_y = 0;
     void* res[4] = {};              // Rx, Rxi (B x n), Ry, Ryi (B x m): LP-major results
@@ -117,8 +117,20 @@ struct pdlpb_ctx {
     std::vector<int32_t> h_rlog;
     std::vector<pdlpb_delta> h_delta;   // the batch's changes, by LP
 
-    // captured blocks of C iterations, one per launch shape (live column bound)
-    std::vector<std::pair<int32_t, hipGraphExec_t>> graphs;
+    // captured blocks of C iterations, one per launch configuration; every
+    // argument a captured launch holds by value is in the key or is a pointer
+    // into storage that only ensure_storage replaces (and it drops the cache)
+    struct GraphKey {
+        int32_t live, ld, wpb;
+        int32_t tp_lanes, tp_vec, tp_blocks, td_lanes, td_vec, td_blocks;
+        bool operator==(const GraphKey& o) const {
+            return live == o.live && ld == o.ld && wpb == o.wpb && tp_lanes == o.tp_lanes &&
+                   tp_vec == o.tp_vec && tp_blocks == o.tp_blocks && td_lanes == o.td_lanes &&
+                   td_vec == o.td_vec && td_blocks == o.td_blocks;
+        }
+    };
+    std::vector<std::pair<GraphKey, hipGraphExec_t>> graphs;
+    int64_t graph_captures = 0;     // graphs captured and instantiated over the context's life
 
     // serving (continuous batching)
     struct Pending {
@@ -135,6 +147,8 @@ struct pdlpb_ctx {
     bool launched = false;
     std::vector<int32_t> free_rows;
     std::vector<int64_t> row_id;                // id held by each result row (-1 free)
+    enum : int8_t { ROW_FREE = 0, ROW_QUEUED = 1, ROW_RUNNING = 2, ROW_STOPPED = 3 };
+    std::vector<int8_t> row_state;              // where the LP of each result row stands
     std::unordered_map<int64_t, int32_t> id_row;
     std::deque<Pending> queue;
     std::deque<int64_t> completed;
@@ -194,6 +208,9 @@ struct pdlpb_ctx {
     void drop_graph() {
         for (auto& gr : graphs) (void)hipGraphExecDestroy(gr.second);
         graphs.clear();
+    }
+    GraphKey graph_key() const {
+        return GraphKey{live, ld, wpb, tp.lanes, tp.vec, tp.blocks, td.lanes, td.vec, td.blocks};
     }
 };
 
@@ -521,6 +538,44 @@ int enqueue_epoch(pdlpb_ctx* x, std::vector<std::pair<int, int>>* rec) {
     return PDLPB_OK;
 }
 
+// Launch one block of C iterations as a captured graph: the graph of the
+// current launch configuration is reused across batches and serving rounds,
+// and captured on first use.  The cache is bounded; past the bound it starts
+// over.
+constexpr size_t MAX_GRAPHS = 64;
+
+template <typename T>
+int replay_epoch(pdlpb_ctx* x) {
+    const pdlpb_ctx::GraphKey key = x->graph_key();
+    hipGraphExec_t exec = nullptr;
+    for (auto& gr : x->graphs)
+        if (gr.first == key) exec = gr.second;
+    if (!exec) {
+        if (x->graphs.size() >= MAX_GRAPHS) {
+            // a replay of another graph may still be queued: graphs are only
+            // destroyed once the stream has drained
+            HIP_TRY(x, hipStreamSynchronize(x->stream));
+            x->drop_graph();
+        }
+        hipGraph_t gr = nullptr;
+        HIP_TRY(x, hipStreamBeginCapture(x->stream, hipStreamCaptureModeThreadLocal));
+        int r2 = enqueue_epoch<T>(x, nullptr);
+        hipError_t e = hipStreamEndCapture(x->stream, &gr);
+        if (r2) {
+            if (gr) (void)hipGraphDestroy(gr);
+            return r2;
+        }
+        if (e != hipSuccess) return x->hip_fail(e, "hipStreamEndCapture");
+        e = hipGraphInstantiate(&exec, gr, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(gr);
+        if (e != hipSuccess) return x->hip_fail(e, "hipGraphInstantiate");
+        x->graphs.push_back({key, exec});
+        x->graph_captures += 1;
+    }
+    HIP_TRY(x, hipGraphLaunch(exec, x->stream));
+    return PDLPB_OK;
+}
+
 // One block of C iterations that also times tile shapes: the iterations
 // between the two evaluations cycle through the candidates, every product
 // launch bracketed by events; the fastest shape is kept per kernel.  All
@@ -696,25 +751,8 @@ int run_solve(pdlpb_ctx* x, double tol, int32_t max_iters) {
             rc = tune_epoch<T>(x);
             if (rc) return rc;
         } else if (use_graphs) {
-            hipGraphExec_t exec = nullptr;
-            for (auto& gr : x->graphs)
-                if (gr.first == x->live) exec = gr.second;
-            if (!exec) {
-                hipGraph_t gr = nullptr;
-                HIP_TRY(x, hipStreamBeginCapture(x->stream, hipStreamCaptureModeThreadLocal));
-                int r2 = enqueue_epoch<T>(x, nullptr);
-                hipError_t e = hipStreamEndCapture(x->stream, &gr);
-                if (r2) {
-                    if (gr) (void)hipGraphDestroy(gr);
-                    return r2;
-                }
-                if (e != hipSuccess) return x->hip_fail(e, "hipStreamEndCapture");
-                e = hipGraphInstantiate(&exec, gr, nullptr, nullptr, 0);
-                (void)hipGraphDestroy(gr);
-                if (e != hipSuccess) return x->hip_fail(e, "hipGraphInstantiate");
-                x->graphs.push_back({x->live, exec});
-            }
-            HIP_TRY(x, hipGraphLaunch(exec, x->stream));
+            rc = replay_epoch<T>(x);
+            if (rc) return rc;
             if (ahead) {
                 rc = enqueue_counts(x, next_slot);
                 if (rc) return rc;
@@ -886,14 +924,17 @@ int ensure_storage(pdlpb_ctx* x, int32_t cols, int32_t lps, int32_t* ld_out) {
                     ? 4 : t0.vec;
     const int32_t ld = ((cols + x->vec_ld - 1) / x->vec_ld) * x->vec_ld;
     const size_t esz = x->fp32 ? sizeof(float) : sizeof(double);
-    const size_t rows_max = (size_t)std::max(n, m);
-    const size_t block_bytes = rows_max * (size_t)ld * esz;
-    if (block_bytes > x->cap_block_bytes) {
+    // blocks 0-3 hold x rows (n), blocks 4-7 y rows (m); capacity is kept as
+    // bytes per row so both kinds grow together
+    const size_t row_bytes = (size_t)ld * esz;
+    if (row_bytes > x->cap_block_bytes) {
         x->drop_graph();
-        for (void*& p : x->blk) x->release(p, x->cap_block_bytes);
+        for (int q = 0; q < 8; ++q)
+            x->release(x->blk[q], (size_t)(q < 4 ? n : m) * x->cap_block_bytes);
         x->cap_block_bytes = 0;
-        for (void*& p : x->blk) HIP_TRY(x, x->alloc(&p, block_bytes));
-        x->cap_block_bytes = block_bytes;
+        for (int q = 0; q < 8; ++q)
+            HIP_TRY(x, x->alloc(&x->blk[q], (size_t)(q < 4 ? n : m) * row_bytes));
+        x->cap_block_bytes = row_bytes;
     }
     const size_t rx_bytes = (size_t)lps * n * esz, ry_bytes = (size_t)lps * m * esz;
     if (rx_bytes > x->cap_res_x || ry_bytes > x->cap_res_y) {
@@ -1306,7 +1347,8 @@ int pdlpb_set_batch(pdlpb_ctx* x, int32_t B, const pdlpb_delta* deltas, const do
         if (rc) return rc;
     }
     const size_t esz = x->fp32 ? sizeof(float) : sizeof(double);
-    x->drop_graph();   // grid shapes and slot count are baked into the captured launches
+    // captured graphs stay valid: their keys hold the launch shapes, and
+    // ensure_storage drops them when it moves a buffer
     // a batch ends any serving session: its queue, ids and results are dropped
     x->serving = false;
     x->queue.clear();
@@ -1600,7 +1642,6 @@ int pdlpb_serve_begin(pdlpb_ctx* x, int32_t result_capacity) {
     int32_t ld = 0;
     int rc = ensure_storage(x, cols, result_capacity, &ld);
     if (rc) return rc;
-    x->drop_graph();
     x->B = cols;
     x->ld = ld;
     x->n_run0 = 0;
@@ -1611,6 +1652,7 @@ int pdlpb_serve_begin(pdlpb_ctx* x, int32_t result_capacity) {
     x->free_rows.clear();
     for (int32_t r = result_capacity - 1; r >= 0; --r) x->free_rows.push_back(r);
     x->row_id.assign(result_capacity, -1);
+    x->row_state.assign(result_capacity, pdlpb_ctx::ROW_FREE);
     x->id_row.clear();
     x->queue.clear();
     x->completed.clear();
@@ -1683,9 +1725,11 @@ int pdlpb_submit(pdlpb_ctx* x, int32_t count, const pdlpb_delta* deltas, int32_t
                                               len, x->stream));
             }
             HIP_TRY(x, hipStreamSynchronize(x->stream));
+            x->row_state[row] = pdlpb_ctx::ROW_STOPPED;
             x->completed.push_back(id);
             continue;
         }
+        x->row_state[row] = pdlpb_ctx::ROW_QUEUED;
         pdlpb_ctx::Pending p;
         p.row = row;
         p.varkind = (q.kind == PDLPB_BASE ? VAR_NONE : q.var) | (q.kind << 28);
@@ -1737,6 +1781,7 @@ int serve_admit(pdlpb_ctx* x) {
         x->h_adm_tstart[j] = x->t0;
         x->h_adm_lp[j] = p.row;
         x->h_adm_rows[j] = p.row;
+        x->row_state[p.row] = pdlpb_ctx::ROW_RUNNING;
         SlotCtl cl{};
         cl.w = p.w;
         cl.r_prev = -1.0;
@@ -1786,25 +1831,8 @@ int serve_launch(pdlpb_ctx* x) {
         choose_tile(x, shape);
     }
     if (x->opt.use_graphs && !x->timing) {
-        hipGraphExec_t exec = nullptr;
-        for (auto& gr : x->graphs)
-            if (gr.first == x->live) exec = gr.second;
-        if (!exec) {
-            hipGraph_t gr = nullptr;
-            HIP_TRY(x, hipStreamBeginCapture(x->stream, hipStreamCaptureModeThreadLocal));
-            int r2 = enqueue_epoch<T>(x, nullptr);
-            hipError_t e = hipStreamEndCapture(x->stream, &gr);
-            if (r2) {
-                if (gr) (void)hipGraphDestroy(gr);
-                return r2;
-            }
-            if (e != hipSuccess) return x->hip_fail(e, "hipStreamEndCapture");
-            e = hipGraphInstantiate(&exec, gr, nullptr, nullptr, 0);
-            (void)hipGraphDestroy(gr);
-            if (e != hipSuccess) return x->hip_fail(e, "hipGraphInstantiate");
-            x->graphs.push_back({x->live, exec});
-        }
-        HIP_TRY(x, hipGraphLaunch(exec, x->stream));
+        rc = replay_epoch<T>(x);
+        if (rc) return rc;
     } else {
         rc = enqueue_epoch<T>(x, nullptr);
         if (rc) return rc;
@@ -1842,7 +1870,10 @@ int pdlpb_serve_wait(pdlpb_ctx* x, int32_t* n_running, int32_t* n_queued) {
             x->h_retire.resize(nr);
             HIP_TRY(x, hipMemcpy(x->h_retire.data(), x->retire, sizeof(RetireEntry) * nr,
                                  hipMemcpyDeviceToHost));
-            for (const RetireEntry& e : x->h_retire) x->completed.push_back(x->row_id[e.lp]);
+            for (const RetireEntry& e : x->h_retire) {
+                x->row_state[e.lp] = pdlpb_ctx::ROW_STOPPED;
+                x->completed.push_back(x->row_id[e.lp]);
+            }
         }
     }
     if (n_running) *n_running = x->n_cols;
@@ -1864,9 +1895,20 @@ int pdlpb_poll(pdlpb_ctx* x, int64_t* ids, int32_t cap, int32_t* count) {
 int pdlpb_result(pdlpb_ctx* x, int64_t id, double* xo, double* yo, int32_t* status, double kkt[4],
                  double* obj, int64_t* iters, int32_t mem) {
     if (!x) return PDLPB_EINVAL;
+    if (mem != PDLPB_MEM_HOST && mem != PDLPB_MEM_DEVICE) return x->fail(PDLPB_EINVAL, "unknown mem");
     auto it = x->id_row.find(id);
     if (it == x->id_row.end()) return x->fail(PDLPB_EINVAL, "unknown or released id");
     const int32_t row = it->second;
+    if (x->row_state[row] != pdlpb_ctx::ROW_STOPPED) {
+        // queued or running: the row may still hold another LP's data or be
+        // written by the device, so nothing is read from it
+        if (status) *status = PDLPB_STATUS_RUNNING;
+        if (kkt)
+            for (int q = 0; q < 4; ++q) kkt[q] = NAN;
+        if (obj) *obj = NAN;
+        if (iters) *iters = 0;
+        return PDLPB_OK;
+    }
     HIP_TRY(x, hipSetDevice(x->device));
     SlotCtl cl{};
     HIP_TRY(x, hipMemcpy(&cl, x->ctl + row, sizeof(SlotCtl), hipMemcpyDeviceToHost));
@@ -1876,10 +1918,8 @@ int pdlpb_result(pdlpb_ctx* x, int64_t id, double* xo, double* yo, int32_t* stat
     if (obj) *obj = cl.obj;
     if (iters) *iters = cl.iters;
     int rc = PDLPB_OK;
-    if (cl.status != PDLPB_STATUS_RUNNING) {
-        if (xo) rc = copy_results(x, 0, row, 1, xo, mem);
-        if (!rc && yo) rc = copy_results(x, 2, row, 1, yo, mem);
-    }
+    if (xo) rc = copy_results(x, 0, row, 1, xo, mem);
+    if (!rc && yo) rc = copy_results(x, 2, row, 1, yo, mem);
     return rc;
 }
 
@@ -1888,8 +1928,11 @@ int pdlpb_release(pdlpb_ctx* x, int64_t id) {
     auto it = x->id_row.find(id);
     if (it == x->id_row.end()) return x->fail(PDLPB_EINVAL, "unknown or released id");
     const int32_t row = it->second;
+    if (x->row_state[row] != pdlpb_ctx::ROW_STOPPED)
+        return x->fail(PDLPB_ESTATE, "LP has not stopped; only a stopped LP's row can be released");
     x->id_row.erase(it);
     x->row_id[row] = -1;
+    x->row_state[row] = pdlpb_ctx::ROW_FREE;
     x->free_rows.push_back(row);
     return PDLPB_OK;
 }
@@ -1947,6 +1990,8 @@ int pdlpb_kernel_times(pdlpb_ctx* x, int64_t counts[4], double total_ms[4]) {
 }
 
 int64_t pdlpb_device_bytes(const pdlpb_ctx* x) { return x ? x->dev_bytes : 0; }
+
+int64_t pdlpb_graph_captures(const pdlpb_ctx* x) { return x ? x->graph_captures : 0; }
 
 void pdlpb_destroy(pdlpb_ctx* x) { free_all(x); }
 

@@ -41,7 +41,7 @@ EXPORTED = ["pdlpb_default_options", "pdlpb_create", "pdlpb_set_batch", "pdlpb_s
             "pdlpb_serve_launch", "pdlpb_serve_wait", "pdlpb_poll", "pdlpb_result",
             "pdlpb_release",
             "pdlpb_set_kernel_timing", "pdlpb_kernel_times", "pdlpb_kernel_columns",
-            "pdlpb_device_bytes",
+            "pdlpb_device_bytes", "pdlpb_graph_captures",
             "pdlpb_destroy", "pdlpb_last_error"]
 
 
@@ -121,6 +121,7 @@ def _load():
         "pdlpb_kernel_times": (C.c_int, [P, i64p, dp]),
         "pdlpb_kernel_columns": (C.c_int, [P, i64p]),
         "pdlpb_device_bytes": (C.c_int64, [P]),
+        "pdlpb_graph_captures": (C.c_int64, [P]),
         "pdlpb_destroy": (None, [P]),
         "pdlpb_last_error": (C.c_char_p, [P]),
     }
@@ -159,6 +160,7 @@ pdlpb_set_kernel_timing = lib.pdlpb_set_kernel_timing
 pdlpb_kernel_times = lib.pdlpb_kernel_times
 pdlpb_kernel_columns = lib.pdlpb_kernel_columns
 pdlpb_device_bytes = lib.pdlpb_device_bytes
+pdlpb_graph_captures = lib.pdlpb_graph_captures
 pdlpb_destroy = lib.pdlpb_destroy
 pdlpb_last_error = lib.pdlpb_last_error
 
@@ -260,6 +262,10 @@ class Context:
     @property
     def device_bytes(self) -> int:
         return int(lib.pdlpb_device_bytes(self._h))
+
+    @property
+    def graph_captures(self) -> int:
+        return int(lib.pdlpb_graph_captures(self._h))
 
     def set_batch(self, deltas, x_warm=None, y_warm=None, w_warm=None,
                   warm_mode: Optional[int] = None, mem: int = MEM_HOST):
