@@ -27,10 +27,22 @@ Halpern iteration; restarted trajectories (fixed weight, per LP and under the
 batch-average scope) against what firm nonexpansiveness fixes across a
 restart: each cycle starts no farther from a solution than the first, its
 first residual is at most the one that fired the restart, and the rate bound
-holds from its own start.  Parity unpinned: the
-exact restart times and iteration counts (the paper prints none), and the
-values of the restart constants beta_s, beta_n, beta_a, theta (named, not
-valued, in the paper).
+holds from its own start; the whole restarted trajectory against the scale
+covariance of the LP (objective times alpha, box and rows times beta: the
+iterates scale by beta and alpha exactly when the primal weight scales by
+alpha / beta), which pins the form of the initial primal weight and the ratio
+of the weight update.
+
+Parity unpinned (readings no independent source fixes):
+  * the exact restart times and iteration counts (the paper prints none);
+  * the values of the restart constants beta_s, beta_n, beta_a, theta (named,
+    not valued, in the paper);
+  * the constant factor of the initial primal weight ||c|| / ||b|| and its
+    fallback 1 below 1e-10 (the paper does not state w0; scale covariance
+    fixes its form only up to a constant factor);
+  * the strong-branching score weight mu = 1/6 of oracle.mip (the paper says
+    only that the children's objectives determine the score; the value is
+    the rule of the study it cites).
 """
 from .lp import LP, row_bounds, from_arrays, from_instance, apply_delta, BASE, SET_LO, SET_HI, OBJ_UNIT
 from .pdhg import (Options, Result, KKT, solve, solve_batch_avg, pdhg_operator,

@@ -22,6 +22,12 @@ Readings (the paper leaves these open):
     or a branch whose new bound crosses the other bound).  The score
     combines them as (1 - mu) min + mu max with mu = 1/6, the weighting of the
     cited strong-branching study.
+
+Pins: the bounds against exact variable ranges (vertex enumeration, HiGHS),
+the gains against child optima.  Parity unpinned: the value mu = 1/6 (the
+paper only says the children's objectives determine the score); the tests
+pin the form of the score (a weighted mean of the smaller and the larger
+gain), not the weight.
 """
 from __future__ import annotations
 

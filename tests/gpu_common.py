@@ -24,6 +24,26 @@ def rel_err(a, b) -> float:
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1.0))
 
 
+def elem_err(a, b) -> float:
+    """Largest coordinate error, each relative to its own reference value:
+    max_i |a_i - b_i| / max(|b_i|, 1).  The norm-relative error can hide one
+    wrong coordinate of a long vector; this cannot."""
+    a, b = np.asarray(a, dtype=np.float64), np.asarray(b, dtype=np.float64)
+    if a.size == 0:
+        return 0.0
+    return float(np.max(np.abs(a - b) / np.maximum(np.abs(b), 1.0)))
+
+
+def assert_iterates_match(pairs, rtol=ITER_RTOL, what=""):
+    """Every (gpu, reference) vector pair agrees per LP in norm and per coordinate."""
+    worst = 0.0
+    for name, g, o in pairs:
+        en, ee = rel_err(g, o), elem_err(g, o)
+        assert en <= rtol and ee <= rtol, (what, name, en, ee)
+        worst = max(worst, en, ee)
+    return worst
+
+
 def lp_for(base_lp, delta):
     return O.apply_delta(base_lp, int(delta["kind"]), int(delta["var"]), float(delta["value"]))
 
@@ -63,6 +83,8 @@ def assert_trajectory_match(gpu_res, gpu_trace, ores, rtol=ITER_RTOL, what=""):
     ex = rel_err(gpu_res["x"], ores.x)
     ey = rel_err(gpu_res["y"], ores.y)
     assert ex <= rtol and ey <= rtol, (what, ex, ey)
+    # per coordinate as well: z~ (the returned point)
+    assert_iterates_match((("x~", gpu_res["x"], ores.x), ("y~", gpu_res["y"], ores.y)), rtol, what)
     if ores.kkt is not None and "kkt" in gpu_res:
         ref = (ores.kkt.gap, ores.kkt.primal, ores.kkt.dual, ores.kkt.rel)
         for name, a, b in zip(("gap", "primal", "dual", "max"), gpu_res["kkt"], ref):
@@ -73,7 +95,7 @@ def assert_trajectory_match(gpu_res, gpu_trace, ores, rtol=ITER_RTOL, what=""):
         assert abs(gpu_res["obj"] - ores.kkt.obj) <= OBJ_RTOL * (1 + abs(ores.kkt.obj)), \
             (what, "obj", gpu_res["obj"], ores.kkt.obj)
     if ores.x_iter is not None:
-        exi = rel_err(gpu_trace["x_iter"], ores.x_iter)
-        eyi = rel_err(gpu_trace["y_iter"], ores.y_iter)
-        assert exi <= rtol and eyi <= rtol, (what, exi, eyi)
+        # the Halpern iterate z^{k+1}, in norm and per coordinate
+        assert_iterates_match((("x_iter", gpu_trace["x_iter"], ores.x_iter),
+                               ("y_iter", gpu_trace["y_iter"], ores.y_iter)), rtol, what)
     return max(ex, ey)

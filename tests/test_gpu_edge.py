@@ -7,7 +7,7 @@ import pytest
 import scipy.sparse as sp
 
 import oracle as O
-from tests.gpu_common import rel_err, ITER_RTOL
+from tests.gpu_common import rel_err, elem_err, ITER_RTOL
 from workloads import deltas, BASE, SET_LO, SET_HI, OBJ_UNIT
 
 pytestmark = pytest.mark.gpu
@@ -65,8 +65,10 @@ def test_degenerate_shapes_match_oracle(P, name, K):
         r = O.solve(lpj, O.Options(tol=0.0, max_iters=K, step_size=eta))
         assert got[j]["status"] == r.status and got[j]["iters"] == r.iters, (name, j)
         assert rel_err(got[j]["x"], r.x) <= ITER_RTOL, (name, j)
+        assert elem_err(got[j]["x"], r.x) <= ITER_RTOL, (name, j)
         if lp.m:
             assert rel_err(got[j]["y"], r.y) <= ITER_RTOL, (name, j)
+            assert elem_err(got[j]["y"], r.y) <= ITER_RTOL, (name, j)
 
 
 def test_box_only_closed_form(P):

@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 
 import oracle as O
-from tests.gpu_common import (ITER_RTOL, rel_err, lp_for, make_ctx, cfg2_setup, oracle_run,
+from tests.gpu_common import (ITER_RTOL, rel_err, elem_err, lp_for, make_ctx, cfg2_setup, oracle_run,
                               assert_trajectory_match)
 from workloads import (make_cfg1, make_cfg2, make_cfg3, make_tiny, obbt_deltas, choose_vars,
                        deltas, BASE, SET_LO, SET_HI, OBJ_UNIT)
@@ -120,6 +120,7 @@ def test_cfg2_batch_converged(P, C):
         if out["iters"][j] == ores.iters and traces[j]["restart_log"] == ores.restarts:
             same_traj += 1
             assert rel_err(out["X"][j], ores.x) <= ITER_RTOL
+            assert elem_err(out["X"][j], ores.x) <= ITER_RTOL
     # identical trajectories are expected for every LP (no restart test near a tie)
     assert same_traj == len(D)
 
@@ -479,3 +480,35 @@ def test_per_lp_warm_starts(P, K):
     for j, d in enumerate(D):
         ores = oracle_run(lp_for(lp, d), eta, 0.0, K, X0[j], Y0[j], W0[j])
         assert_trajectory_match(*res[j], ores, what=f"LP {j} K={K}")
+
+
+def test_graphs_are_reused_across_batches(P):
+    """Blocks of C iterations captured for one batch are replayed for later
+    batches of the same launch shape instead of being captured again, and the
+    replays give the bits of the first solve; B = 1 batches solved one after
+    another share one set of graphs too."""
+    inst, lp, eta, base, D = cfg2_setup()
+    with _cfg2_ctx(P, inst, eta, base, D, eval_every=32) as ctx:
+        ctx.solve(tol=1e-4, max_iters=100000)
+        first = ctx.get_batch()
+        n1 = ctx.graph_captures
+        assert n1 >= 1
+        for _ in range(3):
+            ctx.set_batch(D, x_warm=base.x, y_warm=base.y, w_warm=np.full(len(D), base.w))
+            ctx.solve(tol=1e-4, max_iters=100000)
+            again = ctx.get_batch()
+            np.testing.assert_array_equal(again["iters"], first["iters"])
+            np.testing.assert_array_equal(again["X"], first["X"])
+            np.testing.assert_array_equal(again["Y"], first["Y"])
+        assert ctx.graph_captures == n1
+        ones = []
+        for j in range(6):
+            ctx.set_batch(D[j:j + 1], x_warm=base.x, y_warm=base.y, w_warm=np.full(1, base.w))
+            ctx.solve(tol=1e-4, max_iters=100000)
+            ones.append(ctx.get_batch())
+            if j == 0:
+                n2 = ctx.graph_captures
+        assert ctx.graph_captures == n2
+        for j, o in enumerate(ones):
+            assert o["iters"][0] == first["iters"][j]
+            np.testing.assert_array_equal(o["X"][0], first["X"][j])

@@ -40,17 +40,27 @@ def test_mixed32_precision_statement_full_size(P):
     err = np.abs(b["obj"] - a["obj"]) / (1 + np.abs(a["obj"]))
     A32 = sp.csr_matrix((inst.val.astype(np.float32).astype(np.float64), inst.col_idx,
                          inst.row_ptr), shape=(inst.m, inst.n))
-    rel, rel32 = [], []
+    rel, rel32, dev = [], [], []
     for j in np.nonzero(both)[0][::8]:
         lpj = lp_for(lp, D[j])
         rel.append(O.kkt(lpj, b["X"][j], b["Y"][j]).rel)
         lpj32 = O.LP(A=A32, c=lpj.c, l=lpj.l, u=lpj.u, xl=lpj.xl, xu=lpj.xu, b=lpj.b)
         rel32.append(O.kkt(lpj32, b["X"][j], b["Y"][j]).rel)
+        dev.append(float(b["kkt"][j, 3]))
+    gap_dev = max(abs(r - d) for r, d in zip(rel32, dev))
     print(f"MIXED32 vs FP64 objective over {both.sum()} LPs: max {err[both].max():.2e} "
           f"median {np.median(err[both]):.2e}; oracle KKT of FP32 points: max {max(rel):.2e} "
-          f"(vs FP32-rounded A: max {max(rel32):.2e})")
+          f"median {np.median(rel):.2e} (vs FP32-rounded A: max {max(rel32):.2e}; "
+          f"|oracle - device| max {gap_dev:.2e})")
     assert err[both].max() <= 1e-3
-    assert max(rel) <= 2e-3 and max(rel32) <= 2e-3
+    # Against the FP32-rounded A, the matrix the FP32 run multiplies by, the oracle
+    # measures what the device's FP64 sums measured: the same number up to
+    # summation order, and within the stopping tolerance.
+    assert gap_dev <= 1e-9
+    assert max(rel32) <= 1e-4 * (1 + 1e-6)
+    # Against A itself the measure also carries the rounding of A's entries
+    # (relative 6e-8), amplified by the norms of the iterates.
+    assert max(rel) <= 2e-3
 
 
 @pytest.mark.parametrize("K", [1, 2, 8, 32, 64])

@@ -7,7 +7,7 @@ import pytest
 
 import oracle as O
 from oracle import scaling as S
-from tests.gpu_common import make_ctx, lp_for, rel_err, ITER_RTOL
+from tests.gpu_common import make_ctx, lp_for, rel_err, elem_err, ITER_RTOL
 from workloads import make_badly_scaled, choose_fractional, fsb_deltas, obbt_deltas, choose_vars
 
 pytestmark = pytest.mark.gpu
@@ -54,6 +54,7 @@ def test_fixed_iterations_match_oracle(P, setup, K):
                                  dr, dc, x_init=xr, y_init=yr, w_init=root.w)
         assert got[j]["iters"] == r.iters == K
         assert rel_err(got[j]["x"], x) <= ITER_RTOL and rel_err(got[j]["y"], y) <= ITER_RTOL, j
+        assert elem_err(got[j]["x"], x) <= ITER_RTOL and elem_err(got[j]["y"], y) <= ITER_RTOL, j
 
 
 @pytest.mark.parametrize("C", [64, 32])
@@ -69,6 +70,7 @@ def test_converged_match_oracle(P, setup, C):
                                  dr, dc, x_init=xr, y_init=yr, w_init=root.w)
         assert got["status"][j] == r.status and got["iters"][j] == r.iters, j
         assert rel_err(got["X"][j], x) <= 1e-8, j
+        assert elem_err(got["X"][j], x) <= 1e-8, j
         assert got["obj"][j] == pytest.approx(r.obj, rel=1e-9, abs=1e-9)
 
 

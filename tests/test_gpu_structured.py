@@ -7,7 +7,7 @@ import pytest
 
 import oracle as O
 from oracle import scaling as S
-from tests.gpu_common import make_ctx, lp_for, rel_err
+from tests.gpu_common import make_ctx, lp_for, rel_err, elem_err
 from workloads import make_setcover, make_facility, choose_fractional, fsb_deltas
 
 pytestmark = pytest.mark.gpu
@@ -48,3 +48,4 @@ def test_strong_branching_matches_oracle(P, family):
                                  dr, dc, x_init=xr, y_init=yr, w_init=root.w)
         assert got["status"][j] == r.status and got["iters"][j] == r.iters, (family, j)
         assert rel_err(got["X"][j], x) <= 1e-8, (family, j)
+        assert elem_err(got["X"][j], x) <= 1e-8, (family, j)
