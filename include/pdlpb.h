@@ -38,6 +38,7 @@
 #ifndef PDLPB_H
 #define PDLPB_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -122,6 +123,21 @@ typedef struct pdlpb_options {
                                  measure the scaled LP); changes, warm starts and results stay in the
                                  caller's coordinates */
     int32_t reserved[2];
+    /* Device memory of the context.  Both NULL (default): hipMalloc / hipFree.
+       Otherwise both set: every device buffer the context holds comes from
+       dev_alloc(bytes, alloc_user), which returns a pointer on the context's
+       device aligned to at least 256 bytes, or NULL (the call that needed it
+       then fails with PDLPB_ENOMEM), and goes back through
+       dev_free(ptr, bytes, alloc_user) with the size it was requested with.
+       The context synchronises its stream before each dev_free, so memory
+       handed back is no longer in use.  A caching allocator (such as
+       PyTorch's) can back a context this way.  Buffers are requested by
+       pdlpb_create, by calls whose batch outgrows the storage (set_batch,
+       serve_begin, estimate_batch) and by result copies that need staging;
+       they are returned when storage is replaced and by pdlpb_destroy. */
+    void* (*dev_alloc)(size_t bytes, void* alloc_user);
+    void  (*dev_free)(void* ptr, size_t bytes, void* alloc_user);
+    void*  alloc_user;
 } pdlpb_options;
 
 typedef struct pdlpb_ctx pdlpb_ctx;   /* opaque; owns all device memory of one base matrix and its batch */
@@ -296,6 +312,24 @@ int pdlpb_result(pdlpb_ctx* ctx, int64_t id, double* x, double* y, int32_t* stat
 /* Free the result row of a stopped LP; its id becomes invalid.  PDLPB_ESTATE
  * while the LP is queued or running (its row is still in use). */
 int pdlpb_release(pdlpb_ctx* ctx, int64_t id);
+
+/*
+ * Batch width estimate (Section 5, "Matrix-matrix products and optimal batch
+ * size"): the paper times ten products A X and ten products A'Y at several
+ * batch widths before a MIP solve and takes the width that maximises the
+ * matrix-vector products per second.  For each widths[i] this runs `reps`
+ * fused primal steps (A'Y) and `reps` fused dual steps (A Xbar) of the
+ * context's own kernels on a batch of widths[i] copies of the base LP (after
+ * one untimed pair), timed with HIP events on the context's stream.  ms
+ * (count host doubles, may be NULL) receives the elapsed milliseconds per
+ * width; *best (may be NULL) the width with the most column products per
+ * second, 2 reps widths[i] / ms[i] (the first of equal ones).  The call
+ * replaces the context's batch: a batch set before it, its results and any
+ * serving session end.  Storage grows to the largest width.  EINVAL: NULL
+ * widths, count < 1, reps outside [1, 1000], a width outside [1, max_batch].
+ */
+int pdlpb_estimate_batch(pdlpb_ctx* ctx, const int32_t* widths, int32_t count, int32_t reps,
+                         double* ms, int32_t* best);
 
 /*
  * Tile shape of the fused product kernels for the following pdlpb_set_batch

@@ -880,23 +880,33 @@ __global__ __launch_bounds__(1024) void k_control(ControlArgs a) {
         if (threadIdx.x == 0) {
             g->n_retire = 0;
             g->n_move = 0;
+            g->n_fresh = 0;
             g->n_cols_next = nc;
         }
     } else if (a.full) {
         for (int32_t s = threadIdx.x; s < nc; s += blockDim.x) sh_flags[s] = a.sl.key[s].flags;
         __syncthreads();
         if (threadIdx.x == 0) {
-            int32_t nr = 0, nm = 0;
+            int32_t nr = 0, nm = 0, nf = 0;
             int32_t mover = n_run;   // scan for running slots at or beyond n_run
             for (int32_t s = 0; s < nc; ++s) {
-                if (!(sh_flags[s] & SLOT_RETIRE)) continue;
+                const int32_t fl = sh_flags[s];
+                if (!(fl & SLOT_RETIRE)) {
+                    // restarted LPs that keep their slot; those beyond n_run restart
+                    // as they move
+                    if ((fl & SLOT_ACTIVE) && (fl & SLOT_FRESH) && s < n_run) a.fresh[nf++] = s;
+                    continue;
+                }
                 const int32_t lp = a.sl.lp[s];
                 const int32_t kl = a.ctl[lp].k_last;
-                a.retire[nr].slot = s;
-                a.retire[nr].lp = lp;
-                a.retire[nr].kp2 = kl + 2;
-                a.retire[nr].a = double(kl + 1) / double(kl + 2);
-                nr += 1;
+                RetireEntry re;
+                re.slot = s;
+                re.lp = lp;
+                re.kp2 = kl + 2;
+                re.src = -1;
+                re.a = double(kl + 1) / double(kl + 2);
+                re.src_fresh = 0;
+                re.pad = 0;
                 if (s < n_run) {
                     // the running slots at or beyond n_run are exactly as many as the
                     // stopped slots below it; the bound only guards that count
@@ -905,12 +915,16 @@ __global__ __launch_bounds__(1024) void k_control(ControlArgs a) {
                         a.moves[nm].src = mover;
                         a.moves[nm].dst = s;
                         nm += 1;
+                        re.src = mover;
+                        re.src_fresh = (sh_flags[mover] & SLOT_FRESH) ? 1 : 0;
                         ++mover;
                     }
                 }
+                a.retire[nr++] = re;
             }
             g->n_retire = nr;
             g->n_move = nm;
+            g->n_fresh = nf;
             g->n_cols_next = n_run;
         }
     }
@@ -921,39 +935,22 @@ __global__ __launch_bounds__(1024) void k_control(ControlArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// Restart (Section 4, Restarts): for every LP restarted by the control pass,
-// the anchor and the iterate become z~ of the evaluation: X0 = Xt, Y0 = Y = Yt.
-// (Xbar needs no update: at k = 0 the primal step reads the anchor only.)
-// Rows [0, n) are x rows, [n, n+m) y rows; 4 rows per block, lanes over slots.
-// ---------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(256) void k_apply_restart(int32_t n, int32_t m, int32_t ld,
-                                                       int32_t ncols, Slots sl, const Globals* g,
-                                                       T* X0, const T* Xt, T* Y, T* Y0,
-                                                       const T* Yt) {
-    const int32_t row = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (row >= n + m) return;
-    const int32_t nc = min(ncols, g->n_cols);
-    for (int32_t s = threadIdx.x & 63; s < nc; s += 64) {
-        if (!(sl.key[s].flags & SLOT_FRESH)) continue;
-        if (row < n) {
-            const size_t e = (size_t)row * ld + s;
-            X0[e] = Xt[e];
-        } else {
-            const size_t e = (size_t)(row - n) * ld + s;
-            const T v = Yt[e];
-            Y0[e] = v;
-            Y[e] = v;
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Compaction (Section 5, stopping criteria: stopped LPs leave the iterate
-// blocks so that kernel sizes shrink).  One thread per row of the blocks
-// (x rows, then y rows): first the stopped LPs' z~ and last Halpern iterate
-// are copied to the LP-major result blocks, then the running LPs listed in
-// the plan move into the freed slots.  Block 0 also moves their slot states.
+// Plan of a full evaluation (Section 4, restarts; Section 5, per-LP stop and
+// compaction), one launch:
+//   - restarted LPs that stay in place: anchor and dual iterate become z~
+//     (X0 = Xt, Y0 = Y = Yt; Xbar needs no update, since at k = 0 the primal
+//     step reads the anchor only);
+//   - stopped LPs: z~ and the last Halpern iterate are copied to the LP-major
+//     result blocks;
+//   - a running LP beyond the new column count moves into the slot of a
+//     stopped one, after that slot's results are copied out (the same thread
+//     reads the old column and then writes the new one), taking a restart
+//     decided at this evaluation on the way.
+// A workgroup owns TR consecutive rows (x rows first, then y rows) and 64
+// plan entries, one per lane; its four waves take every fourth row.  Reads
+// and writes of the row-major blocks run along slots; the results pass
+// through LDS so that each LP's TR values of a result block are written as
+// one contiguous segment.  TR * sizeof(T) = 256 bytes.
 // ---------------------------------------------------------------------------
 template <typename T>
 struct Blocks8 {
@@ -963,44 +960,88 @@ struct Blocks8 {
 template <typename T>
 __global__ __launch_bounds__(256) void k_compact(int32_t n, int32_t m, int32_t ld, Blocks8<T> B,
                                                  Blocks8<T> R, const RetireEntry* retire,
-                                                 const MoveEntry* moves, Slots sl, Globals* g) {
-    const int32_t nr = g->n_retire, nm = g->n_move;
-    const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (row < n) {
-        const size_t base = (size_t)row * ld;
-        T* Xbar = B.b[0];
-        T* X0 = B.b[1];
-        T* Xt = B.b[2];
-        for (int32_t q = 0; q < nr; ++q) {
-            const RetireEntry e = retire[q];
-            const size_t f = base + e.slot;
-            R.b[0][(size_t)e.lp * n + row] = Xt[f];
-            R.b[1][(size_t)e.lp * n + row] =
-                T(e.a * (double)Xbar[f] + (double)X0[f] / (double)e.kp2);
-        }
-        for (int32_t q = 0; q < nm; ++q) {
-            const MoveEntry mv = moves[q];
-#pragma unroll
-            for (int b = 0; b < 4; ++b) B.b[b][base + mv.dst] = B.b[b][base + mv.src];
-        }
-    } else if (row < (int64_t)n + m) {
-        const int64_t i = row - n;
-        const size_t base = (size_t)i * ld;
-        for (int32_t q = 0; q < nr; ++q) {
-            const RetireEntry e = retire[q];
-            const size_t f = base + e.slot;
-            R.b[2][(size_t)e.lp * m + i] = B.b[6][f];    // y~
-            R.b[3][(size_t)e.lp * m + i] = B.b[4][f];    // Halpern iterate y^{k+1}
-        }
-        for (int32_t q = 0; q < nm; ++q) {
-            const MoveEntry mv = moves[q];
-#pragma unroll
-            for (int b = 4; b < 8; ++b) B.b[b][base + mv.dst] = B.b[b][base + mv.src];
+                                                 const MoveEntry* moves, const int32_t* fresh,
+                                                 Slots sl, Globals* g) {
+    constexpr int TR = 256 / (int)sizeof(T);
+    __shared__ T res_t[64][TR + 1];   // z~ of each entry's LP, rows of the tile
+    __shared__ T res_h[64][TR + 1];   // its last Halpern iterate
+    const int32_t nr = g->n_retire, nf = g->n_fresh, nm = g->n_move;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int32_t q0 = (int32_t)blockIdx.y * 64;
+    const int32_t q = q0 + lane;                          // this lane's plan entry
+    const int32_t tiles_x = (n + TR - 1) / TR;
+    const bool xside = (int32_t)blockIdx.x < tiles_x;
+    const int32_t r0 = (xside ? (int32_t)blockIdx.x : (int32_t)blockIdx.x - tiles_x) * TR;
+    const int32_t rows = xside ? n : m;
+    const int32_t rcount = min(TR, rows - r0);
+
+    if (q < nf) {
+        const int32_t s = fresh[q];
+        for (int32_t rr = wave; rr < rcount; rr += 4) {
+            const size_t e = (size_t)(r0 + rr) * ld + s;
+            if (xside) {
+                B.b[1][e] = B.b[2][e];
+            } else {
+                const T v = B.b[6][e];
+                B.b[5][e] = v;
+                B.b[4][e] = v;
+            }
         }
     }
-    if (blockIdx.x == 0) {
-        for (int32_t q = threadIdx.x; q < nm; q += blockDim.x) {
-            const MoveEntry mv = moves[q];
+    if (q0 < nr) {
+        if (q < nr) {
+            const RetireEntry re = retire[q];
+            for (int32_t rr = wave; rr < rcount; rr += 4) {
+                const size_t base = (size_t)(r0 + rr) * ld;
+                const size_t e = base + re.slot;
+                if (xside) {
+                    const T xb = B.b[0][e], x0 = B.b[1][e], xt = B.b[2][e];
+                    res_t[lane][rr] = xt;
+                    res_h[lane][rr] = T(re.a * (double)xb + (double)x0 / (double)re.kp2);
+                } else {
+                    res_t[lane][rr] = B.b[6][e];   // y~
+                    res_h[lane][rr] = B.b[4][e];   // Halpern iterate y^{k+1}
+                }
+                if (re.src >= 0) {
+                    const size_t f = base + re.src;
+                    if (xside) {
+                        const T v0 = B.b[0][f], v2 = B.b[2][f], v3 = B.b[3][f];
+                        const T v1 = re.src_fresh ? v2 : B.b[1][f];
+                        B.b[0][e] = v0;
+                        B.b[1][e] = v1;
+                        B.b[2][e] = v2;
+                        B.b[3][e] = v3;
+                    } else {
+                        const T v6 = B.b[6][f], v7 = B.b[7][f];
+                        const T v4 = re.src_fresh ? v6 : B.b[4][f];
+                        const T v5 = re.src_fresh ? v6 : B.b[5][f];
+                        B.b[4][e] = v4;
+                        B.b[5][e] = v5;
+                        B.b[6][e] = v6;
+                        B.b[7][e] = v7;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        // transposed write: each entry's rows of the tile as one contiguous run
+        const int32_t nq = min(64, nr - q0);
+        T* rt = xside ? R.b[0] : R.b[2];
+        T* rh = xside ? R.b[1] : R.b[3];
+        for (int32_t idx = threadIdx.x; idx < nq * TR; idx += 256) {
+            const int32_t qq = idx / TR, rr = idx % TR;
+            if (rr >= rcount) continue;
+            const int32_t lp = retire[q0 + qq].lp;
+            const size_t o = (size_t)lp * rows + r0 + rr;
+            rt[o] = res_t[qq][rr];
+            rh[o] = res_h[qq][rr];
+        }
+    }
+    if (blockIdx.x == 0 && blockIdx.y == 0) {
+        // slot state of the moved LPs; no other workgroup of this launch reads it
+        for (int32_t k = threadIdx.x; k < nm; k += blockDim.x) {
+            const MoveEntry mv = moves[k];
             sl.key[mv.dst] = sl.key[mv.src];
             sl.tau[mv.dst] = sl.tau[mv.src];
             sl.sigma[mv.dst] = sl.sigma[mv.src];
@@ -1074,6 +1115,7 @@ __global__ void k_begin_solve(Slots sl, SlotCtl* ctl, int32_t ncols, int32_t max
         g->n_cols = ncols;
         g->n_retire = 0;
         g->n_move = 0;
+        g->n_fresh = 0;
         g->n_cols_next = ncols;
         g->quiet = 0;
     }
@@ -1275,27 +1317,19 @@ hipError_t launch_control(const ControlArgs& a, hipStream_t s) {
 }
 
 template <typename T>
-hipError_t launch_apply_restart(int32_t n, int32_t m, int32_t ld, int32_t ncols, Slots sl,
-                                const Globals* g, T* X0, const T* Xt, T* Y, T* Y0, const T* Yt,
-                                hipStream_t s) {
-    const int64_t rows = (int64_t)n + m;
-    if (rows == 0 || ncols == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_apply_restart<T>, dim3((uint32_t)((rows + 3) / 4)), dim3(256), 0, s, n, m,
-                       ld, ncols, sl, g, X0, Xt, Y, Y0, Yt);
-    return hipGetLastError();
-}
-
-template <typename T>
-hipError_t launch_compact(int32_t n, int32_t m, int32_t ld, T* const* blk, T* const* res,
-                          const RetireEntry* retire, const MoveEntry* moves, Slots sl, Globals* g,
-                          hipStream_t s) {
+hipError_t launch_compact(int32_t n, int32_t m, int32_t ld, int32_t ncols, T* const* blk,
+                          T* const* res, const RetireEntry* retire, const MoveEntry* moves,
+                          const int32_t* fresh, Slots sl, Globals* g, hipStream_t s) {
+    constexpr int TR = 256 / (int)sizeof(T);
     Blocks8<T> B{}, R{};
     for (int b = 0; b < 8; ++b) B.b[b] = blk[b];
     for (int b = 0; b < 4; ++b) R.b[b] = res[b];
-    const int64_t rows = (int64_t)n + m;
-    const uint32_t blocks = (uint32_t)((rows + 255) / 256);
-    hipLaunchKernelGGL(k_compact<T>, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, s, n, m, ld, B, R,
-                       retire, moves, sl, g);
+    const int64_t tiles = ((int64_t)n + TR - 1) / TR + ((int64_t)m + TR - 1) / TR;
+    const int64_t chunks = ((int64_t)ncols + 63) / 64;
+    if (tiles > 0x7fffffff) return hipErrorInvalidValue;
+    const dim3 grid((uint32_t)(tiles > 0 ? tiles : 1), (uint32_t)(chunks > 0 ? chunks : 1));
+    hipLaunchKernelGGL(k_compact<T>, grid, dim3(256), 0, s, n, m, ld, B, R, retire, moves, fresh,
+                       sl, g);
     return hipGetLastError();
 }
 
@@ -1398,18 +1432,12 @@ template hipError_t launch_dual<double>(const StepArgs<double>&, int, int, hipSt
 template hipError_t launch_dual<float>(const StepArgs<float>&, int, int, hipStream_t);
 template hipError_t launch_eval<double>(const EvalArgs<double>&, hipStream_t);
 template hipError_t launch_eval<float>(const EvalArgs<float>&, hipStream_t);
-template hipError_t launch_apply_restart<double>(int32_t, int32_t, int32_t, int32_t, Slots,
-                                                 const Globals*, double*, const double*, double*,
-                                                 double*, const double*, hipStream_t);
-template hipError_t launch_apply_restart<float>(int32_t, int32_t, int32_t, int32_t, Slots,
-                                                const Globals*, float*, const float*, float*,
-                                                float*, const float*, hipStream_t);
-template hipError_t launch_compact<double>(int32_t, int32_t, int32_t, double* const*,
+template hipError_t launch_compact<double>(int32_t, int32_t, int32_t, int32_t, double* const*,
                                            double* const*, const RetireEntry*, const MoveEntry*,
-                                           Slots, Globals*, hipStream_t);
-template hipError_t launch_compact<float>(int32_t, int32_t, int32_t, float* const*, float* const*,
-                                          const RetireEntry*, const MoveEntry*, Slots, Globals*,
-                                          hipStream_t);
+                                           const int32_t*, Slots, Globals*, hipStream_t);
+template hipError_t launch_compact<float>(int32_t, int32_t, int32_t, int32_t, float* const*,
+                                          float* const*, const RetireEntry*, const MoveEntry*,
+                                          const int32_t*, Slots, Globals*, hipStream_t);
 template hipError_t launch_init_columns<double>(int32_t, int32_t, int32_t, int32_t, int32_t, Slots,
                                                 const double*, const double*, const double*,
                                                 const double*, int32_t, double* const*,

@@ -101,6 +101,7 @@ struct pdlpb_ctx {
     int32_t* rlog = nullptr;        // by LP
     RetireEntry* retire = nullptr;
     MoveEntry* moves = nullptr;
+    int32_t* fresh = nullptr;       // restarted slots that stay in place (compaction plan)
     Globals* g = nullptr;
     size_t cap_part = 0;            // doubles in part (x and y) + sums
     double* part = nullptr;
@@ -184,25 +185,43 @@ struct pdlpb_ctx {
     }
     int hip_fail(hipError_t e, const char* what) {
         err = std::string(what) + ": " + hipGetErrorString(e);
-        return PDLPB_EDEVICE;
+        return e == hipErrorOutOfMemory ? PDLPB_ENOMEM : PDLPB_EDEVICE;
     }
+    // every live device buffer and its size (the free callback takes the size)
+    std::unordered_map<void*, size_t> dev_sizes;
     template <typename P>
     hipError_t alloc(P** p, size_t bytes) {
         if (bytes == 0) bytes = 256;
         void* q = nullptr;
-        hipError_t e = hipMalloc(&q, bytes);
-        if (e == hipSuccess) {
-            *p = static_cast<P*>(q);
-            dev_bytes += (int64_t)bytes;
+        if (opt.dev_alloc) {
+            q = opt.dev_alloc(bytes, opt.alloc_user);
+            if (!q) return hipErrorOutOfMemory;
+        } else {
+            hipError_t e = hipMalloc(&q, bytes);
+            if (e != hipSuccess) return e;
         }
-        return e;
+        dev_sizes[q] = bytes;
+        dev_bytes += (int64_t)bytes;
+        *p = static_cast<P*>(q);
+        return hipSuccess;
+    }
+    void free_raw(void* q) {
+        auto it = dev_sizes.find(q);
+        const size_t bytes = it != dev_sizes.end() ? it->second : 0;
+        if (it != dev_sizes.end()) dev_sizes.erase(it);
+        dev_bytes -= (int64_t)bytes;
+        if (opt.dev_free) {
+            // a caller's allocator may hand the memory out again at once: no
+            // work of this context may still use it
+            if (stream) (void)hipStreamSynchronize(stream);
+            opt.dev_free(q, bytes, opt.alloc_user);
+        } else {
+            (void)hipFree(q);
+        }
     }
     template <typename P>
-    void release(P*& p, size_t bytes) {
-        if (p) {
-            (void)hipFree((void*)p);
-            dev_bytes -= (int64_t)(bytes == 0 ? 256 : bytes);
-        }
+    void release(P*& p, size_t /*bytes*/) {
+        if (p) free_raw((void*)p);
         p = nullptr;
     }
     void drop_graph() {
@@ -234,25 +253,11 @@ void free_all(pdlpb_ctx* x) {
             (void)hipEventDestroy(e);
             e = nullptr;
         }
-    void* ptrs[] = {x->a_rp, x->a_ci, x->t_rp, x->t_ci, x->a_v64, x->t_v64, x->a_v32, x->t_v32,
-                    x->a_eci, x->t_eci, x->a_ev64, x->t_ev64, x->a_ev32, x->t_ev32, x->d_dr,
-                    x->d_dc,
-                    x->c, x->xl, x->xu, x->rl, x->ru, x->sl.key, x->sl.tau, x->sl.sigma,
-                    x->sl.dval, x->sl.t_start, x->sl.lp, x->ctl, x->rlog, x->base_x, x->adm_rows,
-                    x->adm_ctl,
-                    x->retire, x->moves, x->g, x->part, x->stage, x->pow_buf};
-    for (void* p : ptrs)
-        if (p) (void)hipFree(p);
-    for (void*& p : x->blk)
-        if (p) {
-            (void)hipFree(p);
-            p = nullptr;
-        }
-    for (void*& p : x->res)
-        if (p) {
-            (void)hipFree(p);
-            p = nullptr;
-        }
+    // every device buffer, whichever allocator it came from
+    std::vector<void*> live;
+    live.reserve(x->dev_sizes.size());
+    for (auto& kv : x->dev_sizes) live.push_back(kv.first);
+    for (void* p : live) x->free_raw(p);
     if (x->h_pinned) (void)hipHostFree(x->h_pinned);
     if (x->own_stream && x->stream) (void)hipStreamDestroy(x->stream);
     delete x;
@@ -453,7 +458,7 @@ ControlArgs control_args(pdlpb_ctx* x, int32_t it, int32_t full, int32_t advance
     a.part_y = x->part + (size_t)x->npx * NTERM * x->ld;
     a.sums = x->part + (size_t)(x->npx + x->npy) * NTERM * x->ld;
     a.sl = x->sl; a.ctl = x->ctl; a.rlog = x->rlog;
-    a.retire = x->retire; a.moves = x->moves; a.g = x->g;
+    a.retire = x->retire; a.moves = x->moves; a.fresh = x->fresh; a.g = x->g;
     a.it = it; a.full = full; a.advance = advance; a.block = x->opt.eval_every;
     a.batch_avg = x->opt.restart_scope == PDLPB_RESTART_BATCH_AVG;
     a.pw_literal = x->opt.pw_ratio == 1;
@@ -512,10 +517,8 @@ int enqueue_evaluation(pdlpb_ctx* x, int32_t it, int32_t full, int32_t advance,
     if (full) {
         T* const* b = reinterpret_cast<T* const*>(x->blk);
         T* const* r = reinterpret_cast<T* const*>(x->res);
-        HIP_TRY(x, launch_apply_restart<T>(x->n, x->m, x->ld, x->live, x->sl, x->g, b[1], b[2],
-                                           b[4], b[5], b[6], x->stream));
-        HIP_TRY(x, launch_compact<T>(x->n, x->m, x->ld, b, r, x->retire, x->moves, x->sl, x->g,
-                                     x->stream));
+        HIP_TRY(x, launch_compact<T>(x->n, x->m, x->ld, x->live, b, r, x->retire, x->moves,
+                                     x->fresh, x->sl, x->g, x->stream));
     }
     if (rec && idx >= 0) (void)hipEventRecord(x->ev[2 * idx + 1], x->stream);
     return PDLPB_OK;
@@ -959,6 +962,7 @@ int ensure_storage(pdlpb_ctx* x, int32_t cols, int32_t lps, int32_t* ld_out) {
         x->release(x->sl.lp, sizeof(int32_t) * x->cap_slots);
         x->release(x->retire, sizeof(RetireEntry) * x->cap_slots);
         x->release(x->moves, sizeof(MoveEntry) * x->cap_slots);
+        x->release(x->fresh, sizeof(int32_t) * x->cap_slots);
         x->release(x->adm_rows, sizeof(int32_t) * x->cap_slots);
         x->release(x->adm_ctl, sizeof(SlotCtl) * x->cap_slots);
         x->cap_slots = 0;
@@ -970,6 +974,7 @@ int ensure_storage(pdlpb_ctx* x, int32_t cols, int32_t lps, int32_t* ld_out) {
         HIP_TRY(x, x->alloc(&x->sl.lp, sizeof(int32_t) * cols));
         HIP_TRY(x, x->alloc(&x->retire, sizeof(RetireEntry) * cols));
         HIP_TRY(x, x->alloc(&x->moves, sizeof(MoveEntry) * cols));
+        HIP_TRY(x, x->alloc(&x->fresh, sizeof(int32_t) * cols));
         HIP_TRY(x, x->alloc(&x->adm_rows, sizeof(int32_t) * cols));
         HIP_TRY(x, x->alloc(&x->adm_ctl, sizeof(SlotCtl) * cols));
         x->cap_slots = cols;
@@ -1073,6 +1078,8 @@ int pdlpb_create(pdlpb_ctx** out, int32_t m, int32_t n, int64_t nnz, const int64
         return bad("tile_lanes must be 0 or a power of two in [1, 64]");
     if (o.tile_vec != 0 && o.tile_vec != 1 && o.tile_vec != 2 && o.tile_vec != 4)
         return bad("tile_vec must be 0, 1, 2 or 4");
+    if ((o.dev_alloc == nullptr) != (o.dev_free == nullptr))
+        return bad("dev_alloc and dev_free must both be set or both be NULL");
     // CSR structure
     if (row_ptr[0] != 0) return bad("row_ptr[0] must be 0");
     for (int32_t i = 0; i < m; ++i) {
@@ -1934,6 +1941,125 @@ int pdlpb_release(pdlpb_ctx* x, int64_t id) {
     x->row_id[row] = -1;
     x->row_state[row] = pdlpb_ctx::ROW_FREE;
     x->free_rows.push_back(row);
+    return PDLPB_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Fused product launches at each width of `widths` on a batch of copies of the
+// base LP; ms[i] receives the elapsed time of `reps` primal and `reps` dual
+// launches after one untimed pair.
+template <typename T>
+int estimate_widths(pdlpb_ctx* x, const int32_t* widths, int32_t count, int32_t reps,
+                    double* ms) {
+    int32_t wmax = 1;
+    for (int32_t i = 0; i < count; ++i) wmax = std::max(wmax, widths[i]);
+    HIP_TRY(x, hipStreamSynchronize(x->stream));
+    int32_t ld = 0;
+    int rc = ensure_storage(x, wmax, 1, &ld);
+    if (rc) return rc;
+    // the call replaces the batch: any batch or serving session ends
+    x->serving = false;
+    x->launched = false;
+    x->queue.clear();
+    x->completed.clear();
+    x->id_row.clear();
+    x->free_rows.clear();
+    x->batch_set = false;
+    x->solved = false;
+    x->B = wmax;
+    x->ld = ld;
+    x->n_run0 = 0;
+    std::vector<SlotKey> key(wmax);
+    std::vector<double> step(wmax, x->eta), zero(wmax, 0.0);
+    std::vector<int32_t> lp(wmax), t0(wmax, 0);
+    for (int32_t s = 0; s < wmax; ++s) {
+        key[s].t_anchor = 0;
+        key[s].t_end = 1 << 30;
+        key[s].varkind = VAR_NONE;
+        key[s].flags = SLOT_ACTIVE;
+        lp[s] = s;
+    }
+    const hipMemcpyKind h2d = hipMemcpyHostToDevice;
+    HIP_TRY(x, hipMemcpyAsync(x->sl.key, key.data(), sizeof(SlotKey) * wmax, h2d, x->stream));
+    HIP_TRY(x, hipMemcpyAsync(x->sl.tau, step.data(), sizeof(double) * wmax, h2d, x->stream));
+    HIP_TRY(x, hipMemcpyAsync(x->sl.sigma, step.data(), sizeof(double) * wmax, h2d, x->stream));
+    HIP_TRY(x, hipMemcpyAsync(x->sl.dval, zero.data(), sizeof(double) * wmax, h2d, x->stream));
+    HIP_TRY(x, hipMemcpyAsync(x->sl.t_start, t0.data(), sizeof(int32_t) * wmax, h2d, x->stream));
+    HIP_TRY(x, hipMemcpyAsync(x->sl.lp, lp.data(), sizeof(int32_t) * wmax, h2d, x->stream));
+    Globals hg{};
+    hg.n_cols = wmax;
+    hg.n_active = wmax;
+    hg.n_cols_next = wmax;
+    hg.eta = x->eta;
+    hg.r_prev = -1.0;
+    HIP_TRY(x, hipMemcpyAsync(x->g, &hg, sizeof(Globals), h2d, x->stream));
+    T* const* b = reinterpret_cast<T* const*>(x->blk);
+    HIP_TRY(x, launch_init_blocks<T>(x->n, x->m, ld, wmax, x->sl, x->xl, x->xu, nullptr, nullptr,
+                                     PDLPB_WARM_NONE, b[0], b[1], b[2], b[3], b[4], b[5], b[6],
+                                     b[7], x->stream));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(x, hipEventCreateWithFlags(&e0, hipEventDisableSystemFence));
+    hipError_t he = hipEventCreateWithFlags(&e1, hipEventDisableSystemFence);
+    if (he != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return x->hip_fail(he, "hipEventCreate");
+    }
+    struct Ev {
+        hipEvent_t a, b;
+        ~Ev() {
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+        }
+    } guard{e0, e1};
+    for (int32_t i = 0; i < count; ++i) {
+        x->live = widths[i];
+        choose_tile(x, widths[i]);
+        const StepArgs<T> p = step_args<T>(x, true, 1, 0);
+        const StepArgs<T> d = step_args<T>(x, false, 1, 0);
+        HIP_TRY(x, launch_primal<T>(p, x->tp.lanes, x->tp.vec, x->stream));
+        HIP_TRY(x, launch_dual<T>(d, x->td.lanes, x->td.vec, x->stream));
+        HIP_TRY(x, hipEventRecord(e0, x->stream));
+        for (int32_t r = 0; r < reps; ++r) {
+            HIP_TRY(x, launch_primal<T>(p, x->tp.lanes, x->tp.vec, x->stream));
+            HIP_TRY(x, launch_dual<T>(d, x->td.lanes, x->td.vec, x->stream));
+        }
+        HIP_TRY(x, hipEventRecord(e1, x->stream));
+        HIP_TRY(x, hipEventSynchronize(e1));
+        float el = 0.f;
+        HIP_TRY(x, hipEventElapsedTime(&el, e0, e1));
+        ms[i] = (double)el;
+    }
+    HIP_TRY(x, hipStreamSynchronize(x->stream));
+    return PDLPB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pdlpb_estimate_batch(pdlpb_ctx* x, const int32_t* widths, int32_t count, int32_t reps,
+                         double* ms, int32_t* best) {
+    if (!x) return PDLPB_EINVAL;
+    if (!widths || count < 1) return x->fail(PDLPB_EINVAL, "need widths and count >= 1");
+    if (reps < 1 || reps > 1000) return x->fail(PDLPB_EINVAL, "reps must be in [1, 1000]");
+    for (int32_t i = 0; i < count; ++i)
+        if (widths[i] < 1 || widths[i] > x->opt.max_batch)
+            return x->fail(PDLPB_EINVAL, "width outside [1, max_batch]");
+    HIP_TRY(x, hipSetDevice(x->device));
+    std::vector<double> t(count, 0.0);
+    const int rc = x->fp32 ? estimate_widths<float>(x, widths, count, reps, t.data())
+                           : estimate_widths<double>(x, widths, count, reps, t.data());
+    if (rc) return rc;
+    // the width with the most column products per second (the paper's optimum)
+    int32_t bi = 0;
+    for (int32_t i = 1; i < count; ++i)
+        if ((double)widths[i] / t[i] > (double)widths[bi] / t[bi]) bi = i;
+    if (ms)
+        for (int32_t i = 0; i < count; ++i) ms[i] = t[i];
+    if (best) *best = widths[bi];
     return PDLPB_OK;
 }
 

@@ -9,8 +9,8 @@
 namespace pdlpb {
 
 // ---- per-slot state read by the fused step kernels ------------------------
-// SLOT_FRESH marks an LP restarted by the last full evaluation: the restart
-// kernel copies z~ into its anchor and iterate, and the next residual
+// SLOT_FRESH marks an LP restarted by the last full evaluation: the plan of
+// that evaluation copies z~ into its anchor and iterate, and the next residual
 // evaluation records r(z^{n,0}) and clears the flag.  SLOT_RETIRE marks an LP
 // that has stopped and whose results still sit in its slot; the next
 // compaction copies them out and frees the slot.  SLOT_NEW marks an LP
@@ -65,9 +65,14 @@ struct RetireEntry {
     int32_t slot;      // slot whose LP has stopped
     int32_t lp;        // that LP
     int32_t kp2;       // k_last + 2
-    int32_t pad;
+    int32_t src;       // running slot beyond the new column count that moves into this
+                       // slot once its results are copied out; -1 when none does
     double  a;         // (k_last + 1) / (k_last + 2)
+    int32_t src_fresh; // 1: the moving LP restarted at this evaluation, so its anchor
+                       // and dual iterate are its z~ (the move applies the restart)
+    int32_t pad;
 };
+static_assert(sizeof(RetireEntry) == 32, "RetireEntry layout");
 struct MoveEntry {
     int32_t src;       // running slot beyond the new column count
     int32_t dst;       // freed slot below it
@@ -84,6 +89,9 @@ struct Globals {
     int32_t n_cols_next; //   live columns after the compaction
     int32_t quiet;       // 1: the next evaluation that is not full has no LP to evaluate (no
                          //    running LP starts a restart cycle or reaches its last iteration)
+    int32_t n_fresh;     // compaction plan: running LPs below n_cols_next that restarted at
+                         //    this evaluation (their anchor and dual iterate become z~)
+    int32_t pad;
     double  tol;
     double  eta;
     double  r0;          // BATCH_AVG shared r(z^{n,0})
@@ -156,6 +164,7 @@ struct ControlArgs {
     int32_t* rlog;           // [LP][RESTART_LOG]
     RetireEntry* retire;     // compaction plan (>= B entries each)
     MoveEntry* moves;
+    int32_t* fresh;          // slots of restarted LPs that stay in place
     Globals* g;
     int32_t it;              // iteration index inside the block
     int32_t full;            // 1: KKT and restart tests (t mod C == 0); 0: residual of fresh cycles only
@@ -190,20 +199,17 @@ hipError_t launch_init_blocks(int32_t n, int32_t m, int32_t ld, int32_t ncols, S
                               T* Xbar, T* X0, T* Xt, T* DX, T* Y, T* Y0, T* Yt, T* DY,
                               hipStream_t s);
 
-// Apply the restarts decided by the control pass (slots flagged SLOT_FRESH).
-template <typename T>
-hipError_t launch_apply_restart(int32_t n, int32_t m, int32_t ld, int32_t ncols, Slots sl,
-                                const Globals* g, T* X0, const T* Xt, T* Y, T* Y0, const T* Yt,
-                                hipStream_t s);
-
-// Execute the compaction plan: copy stopped LPs' z~ and last Halpern iterate
-// into the LP-major result blocks, move running LPs into freed slots.
+// Execute the plan of a full evaluation in one launch: restarted LPs take z~
+// as anchor and dual iterate (Section 4, restarts), stopped LPs' z~ and last
+// Halpern iterate are copied into the LP-major result blocks, and running LPs
+// beyond the new column count move into the freed slots.  ncols bounds the
+// plan's entries (the live column count of the launches).
 // blk: Xbar, X0, Xt, DX, Y, Y0, Yt, DY (row-major, stride ld).
 // res: Rx (B x n), Rxi (B x n), Ry (B x m), Ryi (B x m), LP-major.
 template <typename T>
-hipError_t launch_compact(int32_t n, int32_t m, int32_t ld, T* const* blk, T* const* res,
-                          const RetireEntry* retire, const MoveEntry* moves, Slots sl,
-                          Globals* g, hipStream_t s);
+hipError_t launch_compact(int32_t n, int32_t m, int32_t ld, int32_t ncols, T* const* blk,
+                          T* const* res, const RetireEntry* retire, const MoveEntry* moves,
+                          const int32_t* fresh, Slots sl, Globals* g, hipStream_t s);
 
 // Start a solve: t_end of every live slot from the iteration budget, g->t0 = 0.
 hipError_t launch_begin_solve(Slots sl, SlotCtl* ctl, int32_t ncols, int32_t max_iters, Globals* g,

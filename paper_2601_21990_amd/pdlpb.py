@@ -41,7 +41,7 @@ EXPORTED = ["pdlpb_default_options", "pdlpb_create", "pdlpb_set_batch", "pdlpb_s
             "pdlpb_serve_launch", "pdlpb_serve_wait", "pdlpb_poll", "pdlpb_result",
             "pdlpb_release",
             "pdlpb_set_kernel_timing", "pdlpb_kernel_times", "pdlpb_kernel_columns",
-            "pdlpb_device_bytes", "pdlpb_graph_captures",
+            "pdlpb_device_bytes", "pdlpb_graph_captures", "pdlpb_estimate_batch",
             "pdlpb_destroy", "pdlpb_last_error"]
 
 
@@ -61,7 +61,9 @@ class Options(C.Structure):
                 ("tile_lanes", C.c_int32), ("tile_vec", C.c_int32),
                 ("autotune", C.c_int32), ("reserved_pad", C.c_int32),
                 ("dual_tol", C.c_double), ("max_blocks", C.c_int32),
-                ("scaling", C.c_int32), ("reserved", C.c_int32 * 2)]
+                ("scaling", C.c_int32), ("reserved", C.c_int32 * 2),
+                ("dev_alloc", C.c_void_p), ("dev_free", C.c_void_p),
+                ("alloc_user", C.c_void_p)]
 
 
 class PdlpbError(RuntimeError):
@@ -122,6 +124,7 @@ def _load():
         "pdlpb_kernel_columns": (C.c_int, [P, i64p]),
         "pdlpb_device_bytes": (C.c_int64, [P]),
         "pdlpb_graph_captures": (C.c_int64, [P]),
+        "pdlpb_estimate_batch": (C.c_int, [P, i32p, i32, i32, dp, i32p]),
         "pdlpb_destroy": (None, [P]),
         "pdlpb_last_error": (C.c_char_p, [P]),
     }
@@ -161,8 +164,50 @@ pdlpb_kernel_times = lib.pdlpb_kernel_times
 pdlpb_kernel_columns = lib.pdlpb_kernel_columns
 pdlpb_device_bytes = lib.pdlpb_device_bytes
 pdlpb_graph_captures = lib.pdlpb_graph_captures
+pdlpb_estimate_batch = lib.pdlpb_estimate_batch
 pdlpb_destroy = lib.pdlpb_destroy
 pdlpb_last_error = lib.pdlpb_last_error
+
+
+# device-memory callbacks of pdlpb_options (dev_alloc, dev_free)
+DEV_ALLOC = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+DEV_FREE = C.CFUNCTYPE(None, C.c_void_p, C.c_size_t, C.c_void_p)
+
+
+class TorchAllocator:
+    """pdlpb_options.dev_alloc / dev_free backed by PyTorch's caching allocator
+    on one device.  Keep the object alive as long as the context (Context does
+    when it is passed as ``allocator=``).  Counts requests and returns."""
+
+    def __init__(self, device: int = 0):
+        import torch
+        self._torch = torch
+        self.device = int(device)
+        self.live = {}
+        self.allocs = 0
+        self.frees = 0
+
+        def _alloc(nbytes, _user):
+            try:
+                p = self._torch.cuda.caching_allocator_alloc(int(nbytes), device=self.device)
+            except RuntimeError:
+                return None
+            self.live[int(p)] = int(nbytes)
+            self.allocs += 1
+            return int(p)
+
+        def _free(ptr, nbytes, _user):
+            self.live.pop(int(ptr), None)
+            self.frees += 1
+            self._torch.cuda.caching_allocator_delete(int(ptr))
+
+        self.c_alloc = DEV_ALLOC(_alloc)
+        self.c_free = DEV_FREE(_free)
+
+    def install(self, opts: Options) -> None:
+        opts.dev_alloc = C.cast(self.c_alloc, C.c_void_p).value
+        opts.dev_free = C.cast(self.c_free, C.c_void_p).value
+        opts.alloc_user = None
 
 
 def default_options(**kw) -> Options:
@@ -203,8 +248,11 @@ class Context:
     """One constraint matrix on the GPU and its current batch of LPs."""
 
     def __init__(self, m, n, row_ptr, col_idx, val, c, b, sense, l, u,
-                 options: Optional[Options] = None, **opt_kw):
+                 options: Optional[Options] = None, allocator=None, **opt_kw):
         opts = options if options is not None else default_options(**opt_kw)
+        self._allocator = allocator          # its callbacks must outlive the context
+        if allocator is not None:
+            allocator.install(opts)
         self.m, self.n = int(m), int(n)
         rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
         ci = np.ascontiguousarray(col_idx, dtype=np.int32)
@@ -402,6 +450,17 @@ class Context:
 
     def release(self, lp_id: int):
         self._check(lib.pdlpb_release(self._h, int(lp_id)))
+
+    def estimate_batch(self, widths, reps: int = 10):
+        w = np.ascontiguousarray(widths, dtype=np.int32)
+        ms = np.empty(w.size)
+        best = C.c_int32()
+        self._check(lib.pdlpb_estimate_batch(self._h, w.ctypes.data_as(C.POINTER(C.c_int32)),
+                                             int(w.size), int(reps),
+                                             ms.ctypes.data_as(C.POINTER(C.c_double)),
+                                             C.byref(best)))
+        self.B = 0
+        return best.value, ms
 
     def set_tile(self, lanes: int = 0, vec: int = 0):
         self._check(lib.pdlpb_set_tile(self._h, int(lanes), int(vec)))

@@ -33,7 +33,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_options_layout_matches_header():
     o = P.default_options()
-    assert o.struct_size == P.C.sizeof(P.Options) == 136 and o.autotune == 1
+    assert o.struct_size == P.C.sizeof(P.Options) == 160 and o.autotune == 1
     assert (o.eval_every, o.beta_sufficient, o.beta_necessary, o.beta_artificial, o.theta) == \
         (64, 0.2, 0.8, 0.36, 0.5)
     assert o.cross_sign == -1.0 and o.use_graphs == 1 and o.max_batch == 4096
@@ -102,6 +102,8 @@ def test_create_rejects_malformed_input(over, msg):
     (dict(dual_tol=float("inf")), "dual_tol"),
     (dict(scaling=2), "scaling"),
     (dict(max_blocks=-1), "max_blocks"),
+    (dict(dev_alloc=1), "dev_alloc and dev_free"),
+    (dict(dev_free=1), "dev_alloc and dev_free"),
 ])
 def test_create_rejects_bad_options(opt, msg):
     with pytest.raises(P.PdlpbError) as e:
@@ -129,4 +131,5 @@ def test_null_context_calls_are_rejected():
     assert P.lib.pdlpb_solve(None, 1e-4, 10) == P.EINVAL
     assert P.lib.pdlpb_set_batch(None, 1, None, None, None, None, 0, 0) == P.EINVAL
     assert P.lib.pdlpb_device_bytes(None) == 0
+    assert P.lib.pdlpb_estimate_batch(None, None, 0, 10, None, None) == P.EINVAL
     P.lib.pdlpb_destroy(None)
