@@ -226,6 +226,26 @@ int pdlpb_get_trace(pdlpb_ctx* ctx, int32_t j, double* x_iter, double* y_iter, d
                     int32_t* restarts, int32_t* restart_log, int32_t log_cap);
 
 /*
+ * pdlpb_get_batch for callers that cannot allocate device memory (code that
+ * must not call hipMalloc, such as tight serving loops or work recorded into
+ * a HIP graph).  Same arguments, results and errors as pdlpb_get_batch, and
+ * it allocates nothing: pdlpb_get_batch stages host copies that need FP32
+ * widening (PDLPB_MIXED32) or the scaling (pdlpb_options.scaling) in a device
+ * buffer it allocates, while this call stages them in a fixed array of
+ * PDLPB_NOALLOC_SCRATCH_BYTES per GPU, set up by pdlpb_create and held until
+ * the process ends, as many LPs at a time as fit.  Device destinations and
+ * FP64 unscaled contexts need no staging.  Fails with PDLPB_EINVAL when
+ * staging is needed and one LP's vector (n or m doubles) does not fit the
+ * array.  The array is shared by every context on a GPU and keeps the last
+ * call's contents; overlapping calls would race on it, so the library runs
+ * calls of this entry point one at a time within a process (each process has
+ * its own array).
+ */
+#define PDLPB_NOALLOC_SCRATCH_BYTES (32u << 20)
+int pdlpb_get_batch_noalloc(pdlpb_ctx* ctx, double* X, double* Y, int32_t* status, double* kkt,
+                            double* obj, int64_t* iters, int32_t mem);
+
+/*
  * Dual objective -phi_box(r~) - phi_[l,u](y~) of every LP of the solved batch
  * (the dual of eq:main_lp, with r~ the reduced cost of Section 4) at the point
  * its KKT measures were taken: dual_obj (B host doubles).  For an LP whose

@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <deque>
+#include <mutex>
 #include <new>
 #include <string>
 #include <unordered_map>
@@ -23,6 +24,31 @@ using namespace pdlpb;
 namespace {
 
 thread_local std::string g_create_error = "no error";
+
+// ---- staging of pdlpb_get_batch_noalloc --------------------------------------
+// A fixed device array instead of an allocation: each GPU the library runs on
+// holds its own copy until the process ends.  Its name is not an address in
+// host code; the address on each device comes from hipGetSymbolAddress, taken
+// once per device (with that device current) when the first context is
+// created there, and only that address is used on the host.
+constexpr size_t NOALLOC_DOUBLES = (size_t)PDLPB_NOALLOC_SCRATCH_BYTES / sizeof(double);
+static __device__ __align__(256) double scratch[NOALLOC_DOUBLES];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;                   // guards the table and serialises the entry point
+double* g_scratch_ptr[MAX_DEVICES] = {};   // address of the array on each device, once known
+
+// Record the array's address on `device` (current).  Called by pdlpb_create.
+hipError_t scratch_setup(int device) {
+    if (device < 0 || device >= MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[device]) return hipSuccess;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = static_cast<double*>(p);
+    return hipSuccess;
+}
 
 int32_t next_pow2(int64_t v) {
     int32_t p = 1;
@@ -1129,6 +1155,8 @@ int pdlpb_create(pdlpb_ctx** out, int32_t m, int32_t n, int64_t nnz, const int64
     };
     hipError_t e = hipSetDevice(o.device);
     if (e != hipSuccess) return dev_fail(e, "hipSetDevice");
+    e = scratch_setup(o.device);
+    if (e != hipSuccess) return dev_fail(e, "hipGetSymbolAddress(scratch)");
     if (o.stream) {
         x->stream = static_cast<hipStream_t>(o.stream);
     } else {
@@ -1504,6 +1532,78 @@ int pdlpb_get_batch(pdlpb_ctx* x, double* X, double* Y, int32_t* status, double*
     int rc = PDLPB_OK;
     if (X) rc = copy_results(x, 0, 0, B, X, mem);
     if (!rc && Y) rc = copy_results(x, 2, 0, B, Y, mem);
+    return rc;
+}
+
+}  // extern "C"
+
+namespace {
+
+// copy_results without an allocation: host destinations that need FP32
+// widening or the scaling pass through the device's fixed staging array, as
+// many LPs at a time as fit; every other case needs no staging.
+int copy_results_noalloc(pdlpb_ctx* x, int q, int32_t count, double* dst, int32_t mem,
+                         double* scr) {
+    const int64_t rows = (q < 2) ? x->n : x->m;
+    if (rows * count == 0) return PDLPB_OK;
+    if (mem == PDLPB_MEM_DEVICE || (!x->fp32 && !x->scaled)) {
+        // the library's own path, which stages nothing in these cases
+        return copy_results(x, q, 0, count, dst, mem);
+    }
+    if ((size_t)rows > NOALLOC_DOUBLES)
+        return x->fail(PDLPB_EINVAL, "one LP's vector (" + std::to_string(rows) +
+                                         " doubles) exceeds the fixed staging array of " +
+                                         std::to_string(NOALLOC_DOUBLES) + " doubles");
+    const int32_t per = (int32_t)std::min<int64_t>(count, (int64_t)NOALLOC_DOUBLES / rows);
+    const double* d = q < 2 ? x->d_dc : x->d_dr;
+    for (int32_t c0 = 0; c0 < count; c0 += per) {
+        const int32_t k = std::min(per, count - c0);
+        const int64_t cnt = rows * k;
+        if (x->fp32) {
+            const float* src = static_cast<const float*>(x->res[q]) + (size_t)c0 * rows;
+            HIP_TRY(x, launch_widen(src, cnt, scr, x->stream));
+        } else {
+            const double* src = static_cast<const double*>(x->res[q]) + (size_t)c0 * rows;
+            HIP_TRY(x, hipMemcpyAsync(scr, src, cnt * sizeof(double), hipMemcpyDeviceToDevice,
+                                      x->stream));
+        }
+        if (x->scaled) HIP_TRY(x, launch_rescale(scr, d, cnt, (int32_t)rows, 0, x->stream));
+        HIP_TRY(x, hipMemcpyAsync(dst + (size_t)c0 * rows, scr, cnt * sizeof(double),
+                                  hipMemcpyDeviceToHost, x->stream));
+        // the next chunk reuses the array
+        HIP_TRY(x, hipStreamSynchronize(x->stream));
+    }
+    return PDLPB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pdlpb_get_batch_noalloc(pdlpb_ctx* x, double* X, double* Y, int32_t* status, double* kkt,
+                            double* obj, int64_t* iters, int32_t mem) {
+    if (!x) return PDLPB_EINVAL;
+    if (!x->batch_set) return x->fail(PDLPB_ESTATE, "no batch set");
+    if (!x->solved) return x->fail(PDLPB_ESTATE, "batch not solved yet");
+    if (mem != PDLPB_MEM_HOST && mem != PDLPB_MEM_DEVICE) return x->fail(PDLPB_EINVAL, "unknown mem");
+    if (x->device < 0 || x->device >= MAX_DEVICES) return x->fail(PDLPB_EINVAL, "device out of range");
+    // one call at a time per process: the array is shared by every context on a device
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    double* scr = g_scratch_ptr[x->device];
+    if (!scr) return x->fail(PDLPB_ESTATE, "staging array of the device not set up");
+    HIP_TRY(x, hipSetDevice(x->device));
+    const int32_t B = x->B;
+    for (int32_t j = 0; j < B; ++j) {
+        const SlotCtl& cl = x->h_ctl[j];
+        if (status) status[j] = cl.status;
+        if (kkt)
+            for (int q = 0; q < 4; ++q) kkt[4 * (size_t)j + q] = cl.kkt[q];
+        if (obj) obj[j] = cl.obj;
+        if (iters) iters[j] = cl.iters;
+    }
+    int rc = PDLPB_OK;
+    if (X) rc = copy_results_noalloc(x, 0, B, X, mem, scr);
+    if (!rc && Y) rc = copy_results_noalloc(x, 2, B, Y, mem, scr);
     return rc;
 }
 

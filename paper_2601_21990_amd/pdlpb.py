@@ -28,6 +28,7 @@ FP64, MIXED32 = 0, 1
 RESTART_PER_LP, RESTART_BATCH_AVG = 0, 1
 WARM_NONE, WARM_SHARED, WARM_PER_LP, WARM_BASE = 0, 1, 2, 3
 MEM_HOST, MEM_DEVICE = 0, 1
+NOALLOC_SCRATCH_BYTES = 32 << 20   # PDLPB_NOALLOC_SCRATCH_BYTES: staging of pdlpb_get_batch_noalloc
 
 STATUS_NAMES = {0: "RUNNING", 1: "OPTIMAL", 2: "ITERATION_LIMIT", 3: "INFEASIBLE_BOUNDS",
                 4: "NUMERICAL_ERROR", 5: "INVALID_INPUT", 6: "PRIMAL_INFEASIBLE",
@@ -42,6 +43,7 @@ EXPORTED = ["pdlpb_default_options", "pdlpb_create", "pdlpb_set_batch", "pdlpb_s
             "pdlpb_release",
             "pdlpb_set_kernel_timing", "pdlpb_kernel_times", "pdlpb_kernel_columns",
             "pdlpb_device_bytes", "pdlpb_graph_captures", "pdlpb_estimate_batch",
+            "pdlpb_get_batch_noalloc",
             "pdlpb_destroy", "pdlpb_last_error"]
 
 
@@ -104,6 +106,7 @@ def _load():
         "pdlpb_solve": (C.c_int, [P, d, i64]),
         "pdlpb_get": (C.c_int, [P, i32, P, P, i32p, dp, dp, i64p, i32]),
         "pdlpb_get_batch": (C.c_int, [P, P, P, i32p, dp, dp, i64p, i32]),
+        "pdlpb_get_batch_noalloc": (C.c_int, [P, P, P, i32p, dp, dp, i64p, i32]),
         "pdlpb_get_trace": (C.c_int, [P, i32, dp, dp, dp, i32p, i32p, i32]),
         "pdlpb_get_dual_objective": (C.c_int, [P, dp]),
         "pdlpb_obbt_tighten": (C.c_int, [P, d, d, dp, dp, i32p, i32p]),
@@ -144,6 +147,7 @@ pdlpb_set_batch = lib.pdlpb_set_batch
 pdlpb_solve = lib.pdlpb_solve
 pdlpb_get = lib.pdlpb_get
 pdlpb_get_batch = lib.pdlpb_get_batch
+pdlpb_get_batch_noalloc = lib.pdlpb_get_batch_noalloc
 pdlpb_get_trace = lib.pdlpb_get_trace
 pdlpb_get_dual_objective = lib.pdlpb_get_dual_objective
 pdlpb_obbt_tighten = lib.pdlpb_obbt_tighten
