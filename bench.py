@@ -1,24 +1,27 @@
 #!/usr/bin/env python3
 """Throughput benchmark of the batched PDHG library on one MI355X.
 
-Default workload (strong branching, Section 5.1 of the paper): a 2000 x 5000
-constraint matrix with 5 N(0,1) nonzeros per column, 1000 equality and 1000
-<= rows, box [0,10], c ~ N(0,1).  The root LP is solved on the GPU (outside
-the timed region); 32 variables with fractional parts in [0.1, 0.9] give a
-batch of B = 64 bound-changed LPs, each warm-started from the root solution.
-Ten independent draws of the 32 candidates are staged; step i solves draw
-i mod 10.  One step = set the batch from device-resident deltas and warm
-start, solve every LP to 1e-4 relative KKT in FP64, copy the solutions to
-device buffers.
+Default line (strong branching, Section 5.1, on the largest single-GPU shape):
+a 200k x 500k base LP with 4 N(0,1) nonzeros per column, rows of mixed sense,
+box [0,10], c ~ N(0,1) (the serving-stream family).  The root LP is solved on
+the GPU (outside the timed region); 256 variables with fractional parts in
+[0.1, 0.9] give a batch of B = 512 bound-changed LPs, each warm-started from
+the root solution.  Ten draws of the candidates are staged in HBM; step i
+solves draw i mod 10.  One step = set the batch from device-resident deltas
+and warm start, solve every LP to 1e-4 relative KKT in FP64, copy x~ and y~ of
+every LP to device buffers.
 
-Reported: LPs solved per second (value), the same LPs solved one at a time
-by the same library (plain PDHG, B = 1), the dominant kernel's achieved HBM
-bandwidth against 8 TB/s (HIP events on the library's stream; its measured
-HBM traffic from a committed counter summary when that was taken on the same
-kernel sources), the fused product kernels' GB/s at a 200k x 500k shape whose
-blocks exceed the caches, and the FP64 reference solver timed on the host
-cores on a bounded sample.  Other workloads: --workload obbt | mixed | serve |
-sweep | copy | pmc-summary.
+Reported beside it: the same LPs one at a time by the same library (plain
+PDHG, B = 1, sampled), the dominant kernel's achieved HBM bandwidth against
+8 TB/s (HIP events on the library's stream) and its measured traffic from a
+committed counter summary taken on the same kernel sources, the fused product
+kernels at B = 512 on the same matrix, the serving loop over four resident
+bases at two Poisson rates (p50 / p99 latency, LPs/s), the 20000 x 50000
+bound-tightening batch (FP32 iterates with FP64 sums, its FP64 run and the
+objective difference), the 2000 x 5000 strong-branching batch, and the FP64
+reference solver timed on the host cores on a sample of the same LPs.  Single
+workloads: --workload fsb2 | obbt | mixed | serve | structured | sweep | copy |
+trace-summary | pmc-summary.
 """
 from __future__ import annotations
 
@@ -330,6 +333,11 @@ def run_copy(args):
 
 
 def run_serve(args):
+    print(json.dumps(serve_leg(args, [float(r) for r in args.serve_rates.split(",")],
+                               args.serve_seconds)), flush=True)
+
+
+def serve_leg(args, rates, seconds):
     """Serving stream: four resident base LPs (the 200k x 500k family by
     default, FP64; --serve-prec fp32 for FP32 iterates with FP64 sums, which
     cannot certify the infeasible branches of this family, see the design
@@ -362,14 +370,14 @@ def run_serve(args):
         roots.append((root["x"], cand))
     rng = np.random.default_rng(2601021990 + 5000)
     lines = []
-    for rate in [float(r) for r in args.serve_rates.split(",")]:
+    for rate in rates:
         srv = Server(ctxs, warm=True)
         t_start = time.perf_counter()
         next_arrival = t_start + rng.exponential(1.0 / rate)
         n_req = 0
         while True:
             now = time.perf_counter()
-            while next_arrival <= now and next_arrival - t_start < args.serve_seconds:
+            while next_arrival <= now and next_arrival - t_start < seconds:
                 b = int(rng.integers(0, len(ctxs)))
                 size = int(round(np.exp(rng.uniform(np.log(2), np.log(512))) / 2)) * 2
                 size = max(2, min(512, size))
@@ -379,7 +387,7 @@ def run_serve(args):
                                    tol=1e-4, max_iters=args.serve_iters))
                 n_req += 1
                 next_arrival += rng.exponential(1.0 / rate)
-            if next_arrival - t_start >= args.serve_seconds and not srv.busy():
+            if next_arrival - t_start >= seconds and not srv.busy():
                 break
             if srv.busy():
                 srv.step()
@@ -402,14 +410,14 @@ def run_serve(args):
         lines.append(line)
     for c in ctxs:
         c.close()
-    print(json.dumps({"metric": "serving p50/p99 latency and LPs/s",
-                      "config": {"workload": f"{args.serve_bases} resident bases A {m}x{n} "
-                                             f"(4 N(0,1) nnz/col), requests of 2..512 "
-                                             f"strong-branching LPs, warm start, tol 1e-4",
-                                 "precision": args.serve_prec, "columns": args.serve_cols,
-                                 "eval_every": args.serve_eval,
-                                 "result_rows": args.serve_rows},
-                      "rates": lines}), flush=True)
+    return {"metric": "serving p50/p99 latency and LPs/s",
+            "config": {"workload": f"{args.serve_bases} resident bases A {m}x{n} "
+                                   f"(4 N(0,1) nnz/col), Poisson requests of 2..512 "
+                                   f"strong-branching LPs, warm start, tol 1e-4",
+                       "precision": args.serve_prec, "columns": args.serve_cols,
+                       "eval_every": args.serve_eval, "result_rows": args.serve_rows,
+                       "seconds_per_rate": seconds},
+            "rates": lines}
 
 
 def _plain_leg(ctx, dD, X, Y, n_lps, max_iters):
@@ -439,6 +447,10 @@ def _plain_leg(ctx, dD, X, Y, n_lps, max_iters):
 
 
 def run_obbt(args):
+    print(json.dumps(obbt_leg(args, args.steps, args.warmup)), flush=True)
+
+
+def obbt_leg(args, steps, warmup):
     """Bound-tightening batch (Section 5.2) on the 20000 x 50000 family with 8
     U[-1,1] nonzeros per column, rows of mixed sense and box [0,5]: 256 LPs
     minimising and maximising 128 random variables, cold start.  The MIXED32
@@ -460,14 +472,14 @@ def run_obbt(args):
         X = torch.empty((B, inst.n), dtype=torch.float64, device=dev)
         Y = torch.empty((B, inst.m), dtype=torch.float64, device=dev)
         times = []
-        for rep in range(args.warmup + args.steps):
+        for rep in range(warmup + steps):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             ctx.set_batch(dD, mem=P.MEM_DEVICE)
             ctx.solve(tol=1e-4, max_iters=args.obbt_iters)
             r = ctx.get_batch(X=X, Y=Y, mem=P.MEM_DEVICE)
             torch.cuda.synchronize()
-            if rep >= args.warmup:
+            if rep >= warmup:
                 times.append(time.perf_counter() - t0)
         ok = int(np.sum(r["status"] == P.STATUS_OPTIMAL))
         dt = float(np.median(times))
@@ -485,7 +497,7 @@ def run_obbt(args):
     at_bound = np.mean((np.abs(xv - inst.l[vars_]) < 1e-6) | (np.abs(xv - inst.u[vars_]) < 1e-6))
     for k in ("fp32", "fp64"):
         out[k]["ctx"].close()
-    print(json.dumps({
+    return {
         "metric": "LPs solved/s to 1e-4 rel KKT (bound tightening, MIXED32)",
         "value": round(out["fp32"]["lps_per_s"], 2), "unit": "LPs/s",
         "fp64_lps_per_s": round(out["fp64"]["lps_per_s"], 2),
@@ -494,12 +506,12 @@ def run_obbt(args):
         if out["plain"]["value"] > 0 else None,
         "config": {"workload": f"A {inst.m}x{inst.n}, 8 U[-1,1] nnz/col, E/L/G rows, box [0,5], "
                                f"B={B} objectives +-e_j, cold start, tol 1e-4",
-                   "B": B, "steps": args.steps, "warmup": args.warmup},
+                   "B": B, "steps": steps, "warmup": warmup},
         "precision": {"lps_compared": int(both.sum()),
                       "obj_rel_diff_max": float(dobj[both].max()) if both.any() else None,
                       "obj_rel_diff_median": float(np.median(dobj[both])) if both.any() else None,
                       "fp32_rel_kkt_max": float(np.max(b["kkt"][both, 3])) if both.any() else None},
-        "optimum_at_box_bound_fraction": round(float(at_bound), 4)}), flush=True)
+        "optimum_at_box_bound_fraction": round(float(at_bound), 4)}
 
 
 def _mixed_pass(args, prec):
@@ -714,103 +726,280 @@ def run_structured(args):
                       "families": out}), flush=True)
 
 
-def main():
-    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
-    ap.add_argument("--workload", default="fsb",
-                    choices=["fsb", "sweep", "copy", "serve", "obbt", "mixed", "structured",
-                             "pmc-summary", "trace-summary"])
-    ap.add_argument("--trace-dir", help="rocprofv3 --kernel-trace --stats output folder")
-    ap.add_argument("--trace-solves", default="6,7,8")
-    ap.add_argument("--trace-out", default=None)
-    ap.add_argument("--trace-title", default="kernel trace")
-    ap.add_argument("--trace-command", default="")
-    ap.add_argument("--trace-top", type=int, default=16)
-    ap.add_argument("--pmc-fetch", help="rocprofv3 output folder of the FETCH_SIZE run")
-    ap.add_argument("--pmc-write", help="rocprofv3 output folder of the WRITE_SIZE run")
-    ap.add_argument("--pmc-kernel", default="k_dual")
-    ap.add_argument("--pmc-solves", default="2,3,4",
-                    help="1-based solves (k_begin_solve dispatches) whose launches count")
-    ap.add_argument("--pmc-out", default=None)
-    ap.add_argument("--pmc-command", default="")
-    ap.add_argument("--obbt-vars", type=int, default=128)
-    ap.add_argument("--obbt-iters", type=int, default=100000)
-    ap.add_argument("--mixed-lps", type=int, default=1000)
-    ap.add_argument("--mixed-prec", default="fp32", choices=["fp32", "fp64"])
-    ap.add_argument("--mixed-iters", type=int, default=20000)
-    ap.add_argument("--no-precision", action="store_true",
-                    help="mixed: skip the FP64 pass of the precision statement")
-    ap.add_argument("--serve-eval", type=int, default=16,
-                    help="serve: iterations between evaluations (the block length)")
-    ap.add_argument("--eval-every", type=int, default=32,
-                    help="fsb: iterations between evaluations of the batch")
-    ap.add_argument("--fsb-vars", type=int, default=32,
-                    help="fsb: branching candidates (the batch holds two LPs per candidate)")
-    ap.add_argument("--fsb-draws", type=int, default=10,
-                    help="fsb: independent draws of the candidates; step i solves draw i mod R")
-    ap.add_argument("--plain-tile-lanes", type=int, default=0,
-                    help="fsb: fixed lanes per row for the one-LP-at-a-time leg (0: the library's choice)")
-    ap.add_argument("--plain-eval-every", type=int, default=64,
-                    help="fsb: iterations between evaluations of the one-LP-at-a-time leg")
-    ap.add_argument("--serve-m", type=int, default=200000)
-    ap.add_argument("--serve-bases", type=int, default=4)
-    ap.add_argument("--serve-prec", default="fp64", choices=["fp32", "fp64"])
-    ap.add_argument("--serve-cols", type=int, default=1024)
-    ap.add_argument("--serve-rows", type=int, default=2048)
-    ap.add_argument("--serve-rates", default="1,3,10")
-    ap.add_argument("--serve-seconds", type=float, default=10.0)
-    ap.add_argument("--serve-iters", type=int, default=20000)
-    ap.add_argument("--sweep-m", type=int, default=200000)
-    ap.add_argument("--sweep-b", default="1,8,32,64,128,256,512")
-    ap.add_argument("--sweep-iters", type=int, default=65)
-    ap.add_argument("--sweep-tiles", default="0x0", help="lanes x vec per point; 0x0 = automatic")
-    ap.add_argument("--sweep-prec", default="fp32,fp64")
-    ap.add_argument("--sweep-matrix", default="cfg5", choices=["cfg3", "cfg5"],
-                    help="cfg5: 200k x 500k (4 N(0,1) nnz/col); cfg3: 20k x 50k (8 U[-1,1] nnz/col)")
-    ap.add_argument("--sweep-blocks", default="0",
-                    help="workgroup caps of the step launches; 0 = the library default")
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-lps", type=int, default=256)
-    ap.add_argument("--no-spmm", action="store_true",
-                    help="skip the 200k x 500k product-kernel point")
-    ap.add_argument("--tile-lanes", type=int, default=0, help="fixed lanes per row group (0: auto)")
-    ap.add_argument("--tile-vec", type=int, default=0, help="fixed LPs per lane (0: auto)")
-    ap.add_argument("--plain-lps", type=int, default=64, help="LPs of the batch solved one at a time")
-    ap.add_argument("--graphs", type=int, default=1)
-    args = ap.parse_args()
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only; the batch shards by LP columns with no "
-              "communication, so N GPUs give N independent copies of this measurement",
-              file=sys.stderr)
-        sys.exit(2)
+def cpu_workers():
+    """Worker processes for the reference solver: the CPUs this process may
+    run on, at most 16 (the host share of one GPU on the measurement boxes)."""
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    return max(1, min(16, avail))
 
-    if args.workload == "sweep":
-        run_sweep(args)
-        return
-    if args.workload == "copy":
-        run_copy(args)
-        return
-    if args.workload == "serve":
-        run_serve(args)
-        return
-    if args.workload == "structured":
-        run_structured(args)
-        return
-    if args.workload == "trace-summary":
-        run_trace_summary(args)
-        return
-    if args.workload == "pmc-summary":
-        run_pmc_summary(args)
-        return
-    if args.workload == "obbt":
-        run_obbt(args)
-        return
-    if args.workload == "mixed":
-        run_mixed(args)
-        return
 
+_CPU5 = {}
+
+
+def _cpu5_init(eta, C, x, y, w):
+    from threadpoolctl import threadpool_limits
+    threadpool_limits(1)          # one thread per worker process
+    import oracle as O
+    from workloads import make_cfg5
+    _CPU5["lp"] = O.from_instance(make_cfg5(base=0))
+    _CPU5.update(eta=eta, C=C, x=x, y=y, w=w)
+
+
+def _cpu5_task(t):
+    import oracle as O
+    lpj = O.apply_delta(_CPU5["lp"], *t)
+    r = O.solve(lpj, O.Options(tol=1e-4, step_size=_CPU5["eta"], eval_every=_CPU5["C"],
+                               max_iters=100000),
+                x_init=_CPU5["x"], y_init=_CPU5["y"], w_init=_CPU5["w"])
+    return r.status, r.iters
+
+
+def cpu_baseline_cfg5(sample, eta, C, root, w, workers):
+    """The FP64 reference solver on the host cores, one LP per task, on LPs of
+    the GPU batch: the same changes, the same warm start (the GPU's root
+    solution), step size and evaluation interval."""
+    import numpy as np
+    from concurrent.futures import ProcessPoolExecutor
+    import oracle as O
+    tasks = [(int(d["kind"]), int(d["var"]), float(d["value"])) for d in sample]
+    with ProcessPoolExecutor(max_workers=workers, initializer=_cpu5_init,
+                             initargs=(eta, C, root["x"], root["y"], w)) as ex:
+        # the workers build the matrix before the clock starts
+        list(ex.map(_cpu5_noop, range(workers), chunksize=1))
+        t0 = time.perf_counter()
+        res = list(ex.map(_cpu5_task, tasks, chunksize=1))
+        dt = time.perf_counter() - t0
+    solved = sum(1 for st, _ in res if st == O.OPTIMAL)
+    iters = [it for _, it in res]
+    return solved, dt, int(np.median(iters))
+
+
+def _cpu5_noop(_):
+    time.sleep(0.2)
+    return 0
+
+
+def headline(args):
+    """Strong branching on the 200k x 500k family (the largest single-GPU
+    shape): B = 512 bound changes on 256 fractional variables of the GPU's root
+    solution, warm start from it, FP64, draws cycled over the steps."""
+    import numpy as np
+    log("importing torch")
+    import torch
+    import paper_2601_21990_amd.pdlpb as P
+    from workloads import make_cfg5, choose_fractional, fsb_deltas, seed_for, deltas, BASE
+
+    dev = torch.device("cuda:0")
+    torch.cuda.init()
+    inst = make_cfg5(base=0)
+    m, n, nnz = inst.m, inst.n, inst.nnz
+    C = args.cfg5_eval
+    log(f"instance m={m} n={n} nnz={nnz}")
+    opts = dict(device=0, use_graphs=args.graphs, eval_every=C, max_batch=2 * args.cfg5_vars)
+    ctx = P.Context.from_instance(inst, **opts)
+    eta, norm_a = ctx.step_size
+    log(f"eta={eta:.6g} ||A||={norm_a:.6g}")
+    t0 = time.perf_counter()
+    ctx.set_batch(deltas([BASE], [0], [0.0]))
+    ctx.solve(tol=1e-6, max_iters=200000)
+    root = ctx.get(0)
+    root_w = ctx.get_trace(0)["w"]
+    log(f"root: status={P.STATUS_NAMES[root['status']]} iters={root['iters']} "
+        f"obj={root['obj']:.6f} in {time.perf_counter() - t0:.2f}s")
+    draws = [fsb_deltas(root["x"], choose_fractional(root["x"], args.cfg5_vars, seed_for(5, 100 + r)))
+             for r in range(args.fsb_draws)]
+    B = len(draws[0])
+    d_draws = [torch.from_numpy(D.view(np.uint8).copy()).to(dev) for D in draws]
+    d_x = torch.from_numpy(root["x"]).to(dev)
+    d_y = torch.from_numpy(root["y"]).to(dev)
+    d_w = torch.full((B,), root_w, dtype=torch.float64, device=dev)
+    d_X = torch.empty((B, n), dtype=torch.float64, device=dev)
+    d_Y = torch.empty((B, m), dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+
+    def step(i):
+        rc = P.lib.pdlpb_set_batch(ctx._h, B, d_draws[i % len(d_draws)].data_ptr(), d_x.data_ptr(),
+                                   d_y.data_ptr(), d_w.data_ptr(), P.WARM_SHARED, P.MEM_DEVICE)
+        ctx._check(rc)
+        ctx.B = B
+        ctx.solve(tol=1e-4, max_iters=100000)
+        return ctx.get_batch(X=d_X, Y=d_Y, mem=P.MEM_DEVICE)
+
+    out = None
+    for i in range(max(args.warmup, 1)):
+        out = step(i)
+    log(f"warmup done: iters min/median/max = {out['iters'].min()}/{int(np.median(out['iters']))}/"
+        f"{out['iters'].max()}, statuses {np.bincount(out['status'], minlength=8).tolist()}")
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    solved = 0
+    iters, slowest, step_s, statuses = [], [], [], np.zeros(8, dtype=np.int64)
+    for i in range(args.steps):
+        ts = time.perf_counter()
+        out = step(i)                      # ends with the statuses read back to the host
+        step_s.append(time.perf_counter() - ts)
+        solved += int(np.sum(out["status"] == P.STATUS_OPTIMAL))
+        statuses += np.bincount(out["status"], minlength=8)
+        iters.append(out["iters"])
+        slowest.append(int(out["iters"].max()))
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    value = solved / dt
+    log(f"timed: {args.steps} steps in {dt:.4f}s, {solved} LPs solved -> {value:.1f} LPs/s")
+
+    # the same steps with every fused launch bracketed by HIP events on the
+    # library's stream (eager launches): per-kernel durations for the roofline
+    ctx.set_kernel_timing(True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for i in range(args.steps):
+        step(i)
+    torch.cuda.synchronize()
+    event_dt = time.perf_counter() - t1
+    counts, total_ms = ctx.kernel_times()
+    cols = ctx.kernel_columns()
+    ctx.set_kernel_timing(False)
+    log(f"event-timed pass: {event_dt:.4f}s")
+    names = ["primal: A'Y + primal step", "dual: A Xbar + dual step", "evaluation",
+             "control, restarts and compaction"]
+    dom = 0 if total_ms[0] >= total_ms[1] else 1
+    nl = max(counts[dom], 1)
+    avg_ms = total_ms[dom] / nl
+    q0 = fused_bytes(dom, m, n, nnz, 0, 8, 8)
+    q1 = fused_bytes(dom, m, n, nnz, 1, 8, 8) - q0
+    q = (q0 * counts[dom] + q1 * cols[dom]) / nl
+    achieved = q / (avg_ms * 1e-3) / 1e9
+    kname = "k_primal" if dom == 0 else "k_dual"
+    traffic = measured_traffic(f"fsb_200kx500k_b512_fp64_{kname}_traffic.json", kname)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
+                "traffic": traffic,
+                "traffic_GBps": round(traffic / (avg_ms * 1e-3) / 1e9, 2) if traffic else None,
+                "kernel": names[dom], "bytes_per_launch": int(q),
+                "full_width_bytes": int(fused_bytes(dom, m, n, nnz, B, 8, 8)),
+                "mean_live_columns": round(cols[dom] / nl, 2),
+                "avg_launch_us": round(avg_ms * 1e3, 3), "launches": int(counts[dom])}
+    kernel_ms = {names[k]: {"launches": int(counts[k]), "total_ms": round(total_ms[k], 3),
+                            "avg_us": round(total_ms[k] / max(counts[k], 1) * 1e3, 2)}
+                 for k in range(4)}
+
+    # with host-memory inputs and outputs (every LP's x~ and y~ copied back)
+    w_host = np.full(B, root_w)
+    n_host = min(3, args.steps)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    host_solved = 0
+    for i in range(n_host):
+        ctx.set_batch(draws[i % len(draws)], x_warm=root["x"], y_warm=root["y"], w_warm=w_host)
+        ctx.solve(tol=1e-4, max_iters=100000)
+        r = ctx.get_batch()
+        host_solved += int(np.sum(r["status"] == P.STATUS_OPTIMAL))
+    host_dt = time.perf_counter() - t3
+    host_io = {"value": round(host_solved / host_dt, 2), "unit": "LPs/s", "steps": n_host,
+               "note": "inputs from and results (x~, y~ per LP, 2.9 GB) to host memory"}
+    log(f"host I/O: {n_host} steps in {host_dt:.4f}s -> {host_io['value']} LPs/s")
+    ctx.close()
+
+    # plain PDHG: a sample of the same LPs one at a time (B = 1), same library
+    ctx_p = P.Context.from_instance(inst, device=0, use_graphs=args.graphs,
+                                    eval_every=args.cfg5_plain_eval, max_batch=1, step_size=eta)
+    n_plain = min(args.plain_lps, B * len(draws))
+    picks = [(j % len(draws), (j * 37) % B) for j in range(n_plain)]
+    sample = np.concatenate([draws[r][k:k + 1] for r, k in picks])
+
+    def plain_ptr(j):
+        r, k = picks[j]
+        return d_draws[r].data_ptr() + 16 * k
+
+    def one(j):
+        rc = P.lib.pdlpb_set_batch(ctx_p._h, 1, plain_ptr(j), d_x.data_ptr(), d_y.data_ptr(),
+                                   d_w.data_ptr(), P.WARM_SHARED, P.MEM_DEVICE)
+        ctx_p._check(rc)
+        ctx_p.B = 1
+        ctx_p.solve(tol=1e-4, max_iters=100000)
+        return ctx_p.get_batch(X=d_X, Y=d_Y, mem=P.MEM_DEVICE)
+
+    for j in range(min(2, n_plain)):
+        one(j)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    plain_solved, plain_iters, plain_s = 0, [], []
+    for j in range(n_plain):
+        tj = time.perf_counter()
+        o = one(j)
+        plain_s.append(time.perf_counter() - tj)
+        plain_solved += int(o["status"][0] == P.STATUS_OPTIMAL)
+        plain_iters.append(int(o["iters"][0]))
+    torch.cuda.synchronize()
+    plain_dt = time.perf_counter() - t2
+    plain_value = plain_solved / plain_dt
+    log(f"plain: {n_plain} LPs in {plain_dt:.4f}s -> {plain_value:.1f} LPs/s")
+    ctx_p.close()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        workers = cpu_workers()
+        log(f"cpu baseline: reference solver, {n_plain} LPs on {workers} processes")
+        cs, cdt, cmed = cpu_baseline_cfg5(sample, eta, C, root, root_w, workers)
+        cpu = {"value": round(cs / cdt, 3), "unit": "LPs/s", "cores": workers, "kind": "oracle",
+               "host_cpu_count": os.cpu_count(),
+               "sample": f"the {n_plain} LPs of the one-at-a-time leg (drawn across the "
+                         f"{len(draws)} draws), same changes, warm start, step size and "
+                         f"evaluation interval ({C}); one LP per process task; {cs} solved in "
+                         f"{cdt:.2f}s, median {cmed} iterations"}
+        log(f"cpu: {cpu['value']} LPs/s")
+
+    it_all = np.concatenate(iters)
+    return {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "LPs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(dt / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"strong-branching batch on the 200k x 500k family: A {m}x{n} "
+                               f"(4 N(0,1) nnz/col, E/L/G rows), box [0,10], B={B} bound changes "
+                               f"on {B // 2} fractional variables of the root LP, warm start from "
+                               f"it, FP64, tol 1e-4 rel KKT; step i solves draw i mod "
+                               f"{len(draws)} of the candidates",
+                   "m": m, "n": n, "nnz": nnz, "B": B, "tol": 1e-4, "draws": len(draws),
+                   "eval_every": C, "root_iters": int(root["iters"])},
+        "plain": {"value": round(plain_value, 2), "unit": "LPs/s", "lps": n_plain,
+                  "iters_median": int(np.median(plain_iters)), "eval_every": args.cfg5_plain_eval,
+                  "ms_per_lp_median": round(float(np.median(plain_s)) * 1e3, 3)},
+        "batched_vs_plain": round(value / plain_value, 3) if plain_value > 0 else None,
+        "step_ms": {"min": round(min(step_s) * 1e3, 3),
+                    "median": round(float(np.median(step_s)) * 1e3, 3),
+                    "max": round(max(step_s) * 1e3, 3)},
+        "statuses": statuses.tolist(),
+        "event_timed_pass_s": round(event_dt, 4),
+        "host_io": host_io,
+        "iters": {"min": int(it_all.min()), "median": int(np.median(it_all)),
+                  "max": int(it_all.max()), "slowest_per_batch_median": int(np.median(slowest))},
+        "kernels": kernel_ms,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+
+
+
+def fsb2_leg(args, with_cpu=False):
+    """Strong-branching batch on the 2000 x 5000 family (5 N(0,1) nonzeros per
+    column, 1000 E + 1000 L rows, box [0,10]): B = 64 bound changes on 32
+    fractional variables of the GPU's root solution, warm start from it, FP64,
+    ten draws of the candidates cycled over the steps; the same LPs one at a
+    time; the dual step's roofline; optionally the reference solver on the
+    host cores (its own root solve)."""
     import numpy as np
     log("importing torch")
     import torch
@@ -974,11 +1163,12 @@ def main():
     log(f"plain: {np_plain} LPs in {plain_dt:.4f}s -> {plain_value:.1f} LPs/s")
 
     cpu = None
-    if not args.no_cpu_baseline:
-        workers = max(1, min(16, os.cpu_count() or 1))
+    if with_cpu and not args.no_cpu_baseline:
+        workers = cpu_workers()
         log(f"cpu baseline: reference solver, {args.cpu_lps} LPs on {workers} processes")
         cs, cdt = cpu_sample(args.cpu_lps, workers)
         cpu = {"value": round(cs / cdt, 2), "unit": "LPs/s", "cores": workers, "kind": "oracle",
+               "host_cpu_count": os.cpu_count(),
                "sample": f"{args.cpu_lps} strong-branching LPs of the same 2000x5000 family, "
                          f"warm-started from the reference solver's own root solve, "
                          f"one LP per process task, evaluation interval 64 (its default); "
@@ -986,7 +1176,6 @@ def main():
         log(f"cpu: {cpu['value']} LPs/s")
 
     ctx.close()
-    spmm = None if args.no_spmm else spmm_leg()
     line = {
         "metric": METRIC,
         "value": round(value, 2),
@@ -1020,9 +1209,138 @@ def main():
                   "slowest_per_batch_median": int(np.median(slowest))},
         "kernel_avg_us": kernel_us,
         "roofline": roofline,
-        "spmm_hbm": spmm,
         "cpu_baseline": cpu,
     }
+    return line
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--workload", default="line",
+                    choices=["line", "fsb2", "sweep", "copy", "serve", "obbt", "mixed",
+                             "structured", "pmc-summary", "trace-summary"])
+    ap.add_argument("--trace-dir", help="rocprofv3 --kernel-trace --stats output folder")
+    ap.add_argument("--trace-solves", default="6,7,8")
+    ap.add_argument("--trace-out", default=None)
+    ap.add_argument("--trace-title", default="kernel trace")
+    ap.add_argument("--trace-command", default="")
+    ap.add_argument("--trace-top", type=int, default=16)
+    ap.add_argument("--pmc-fetch", help="rocprofv3 output folder of the FETCH_SIZE run")
+    ap.add_argument("--pmc-write", help="rocprofv3 output folder of the WRITE_SIZE run")
+    ap.add_argument("--pmc-kernel", default="k_dual")
+    ap.add_argument("--pmc-solves", default="2,3,4",
+                    help="1-based solves (k_begin_solve dispatches) whose launches count")
+    ap.add_argument("--pmc-out", default=None)
+    ap.add_argument("--pmc-command", default="")
+    ap.add_argument("--obbt-vars", type=int, default=128)
+    ap.add_argument("--obbt-iters", type=int, default=100000)
+    ap.add_argument("--mixed-lps", type=int, default=1000)
+    ap.add_argument("--mixed-prec", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--mixed-iters", type=int, default=20000)
+    ap.add_argument("--no-precision", action="store_true",
+                    help="mixed: skip the FP64 pass of the precision statement")
+    ap.add_argument("--serve-eval", type=int, default=16,
+                    help="serve: iterations between evaluations (the block length)")
+    ap.add_argument("--eval-every", type=int, default=32,
+                    help="fsb: iterations between evaluations of the batch")
+    ap.add_argument("--fsb-vars", type=int, default=32,
+                    help="fsb: branching candidates (the batch holds two LPs per candidate)")
+    ap.add_argument("--fsb-draws", type=int, default=10,
+                    help="fsb: independent draws of the candidates; step i solves draw i mod R")
+    ap.add_argument("--plain-tile-lanes", type=int, default=0,
+                    help="fsb: fixed lanes per row for the one-LP-at-a-time leg (0: the library's choice)")
+    ap.add_argument("--plain-eval-every", type=int, default=64,
+                    help="fsb: iterations between evaluations of the one-LP-at-a-time leg")
+    ap.add_argument("--serve-m", type=int, default=200000)
+    ap.add_argument("--serve-bases", type=int, default=4)
+    ap.add_argument("--serve-prec", default="fp64", choices=["fp32", "fp64"])
+    ap.add_argument("--serve-cols", type=int, default=1024)
+    ap.add_argument("--serve-rows", type=int, default=2048)
+    ap.add_argument("--serve-rates", default="1,3,10")
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--serve-iters", type=int, default=20000)
+    ap.add_argument("--sweep-m", type=int, default=200000)
+    ap.add_argument("--sweep-b", default="1,8,32,64,128,256,512")
+    ap.add_argument("--sweep-iters", type=int, default=65)
+    ap.add_argument("--sweep-tiles", default="0x0", help="lanes x vec per point; 0x0 = automatic")
+    ap.add_argument("--sweep-prec", default="fp32,fp64")
+    ap.add_argument("--sweep-matrix", default="cfg5", choices=["cfg3", "cfg5"],
+                    help="cfg5: 200k x 500k (4 N(0,1) nnz/col); cfg3: 20k x 50k (8 U[-1,1] nnz/col)")
+    ap.add_argument("--sweep-blocks", default="0",
+                    help="workgroup caps of the step launches; 0 = the library default")
+    ap.add_argument("--cfg5-vars", type=int, default=256,
+                    help="default line: branching candidates on the 200k x 500k base (B = 2x)")
+    ap.add_argument("--cfg5-eval", type=int, default=16,
+                    help="default line: iterations between evaluations of the batch")
+    ap.add_argument("--cfg5-plain-eval", type=int, default=16,
+                    help="default line: iterations between evaluations of the one-at-a-time leg")
+    ap.add_argument("--line-serve-rates", default="10,100",
+                    help="default line: Poisson request rates of the serving sub-object")
+    ap.add_argument("--line-serve-seconds", type=float, default=5.0)
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-obbt", action="store_true")
+    ap.add_argument("--no-fsb2", action="store_true")
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-lps", type=int, default=256)
+    ap.add_argument("--no-spmm", action="store_true",
+                    help="skip the 200k x 500k product-kernel point")
+    ap.add_argument("--tile-lanes", type=int, default=0, help="fixed lanes per row group (0: auto)")
+    ap.add_argument("--tile-vec", type=int, default=0, help="fixed LPs per lane (0: auto)")
+    ap.add_argument("--plain-lps", type=int, default=64, help="LPs of the batch solved one at a time")
+    ap.add_argument("--graphs", type=int, default=1)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU only; the batch shards by LP columns with no "
+              "communication, so N GPUs give N independent copies of this measurement",
+              file=sys.stderr)
+        sys.exit(2)
+
+    if args.workload == "sweep":
+        run_sweep(args)
+        return
+    if args.workload == "copy":
+        run_copy(args)
+        return
+    if args.workload == "serve":
+        run_serve(args)
+        return
+    if args.workload == "structured":
+        run_structured(args)
+        return
+    if args.workload == "trace-summary":
+        run_trace_summary(args)
+        return
+    if args.workload == "pmc-summary":
+        run_pmc_summary(args)
+        return
+    if args.workload == "obbt":
+        run_obbt(args)
+        return
+    if args.workload == "mixed":
+        run_mixed(args)
+        return
+    if args.workload == "fsb2":
+        print(json.dumps(fsb2_leg(args, with_cpu=True)), flush=True)
+        return
+
+    # the default line: the 200k x 500k strong-branching batch, then the other
+    # workloads of the metric as sub-objects (each after its own warmup)
+    line = headline(args)
+    if not args.no_spmm:
+        line["spmm_hbm"] = spmm_leg()
+    if not args.no_serving:
+        rates = [float(r) for r in args.line_serve_rates.split(",")]
+        line["serving"] = serve_leg(args, rates, args.line_serve_seconds)
+    if not args.no_obbt:
+        line["bound_tightening_20kx50k"] = obbt_leg(args, steps=5, warmup=2)
+    if not args.no_fsb2:
+        sub = fsb2_leg(args, with_cpu=False)
+        line["strong_branching_2kx5k"] = {k: sub[k] for k in (
+            "value", "unit", "config", "plain", "batched_vs_plain", "step_ms", "iters",
+            "roofline")}
     print(json.dumps(line), flush=True)
 
 

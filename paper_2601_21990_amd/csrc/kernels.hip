@@ -467,6 +467,62 @@ __global__ __launch_bounds__(256) void k_dual(StepArgs<T> a) {
 // are added in wave order.  The panel size depends on the row count only, so
 // each LP's sums do not depend on the batch around it.
 // ---------------------------------------------------------------------------
+// Operands of one evaluation row (x side: a column of A; y side: a row of A)
+// for one LP slot, and the row's contribution to the evaluation sums.
+struct XRow {
+    double xt, dx, x0, c, lo, hi;
+};
+struct YRow {
+    double yt, dy, y0, l, u;
+};
+template <typename T>
+__device__ __forceinline__ XRow load_xrow(const EvalArgs<T>& a, int32_t i, int32_t s) {
+    const size_t e = (size_t)i * a.ld + s;
+    return XRow{(double)a.Xt[e], (double)a.DX[e], (double)a.X0[e], a.c[i], a.xl[i], a.xu[i]};
+}
+template <typename T>
+__device__ __forceinline__ YRow load_yrow(const EvalArgs<T>& a, int32_t i, int32_t s) {
+    const size_t e = (size_t)i * a.ld + s;
+    return YRow{(double)a.Yt[e], (double)a.DY[e], (double)a.Y0[e], a.rl[i], a.ru[i]};
+}
+// x side of column i: g = (A' y~)_i, h = (A' dy)_i, pdy = (A' Pi_B[l,u](dy))_i
+__device__ __forceinline__ void finish_xrow(const XRow& r, double g, double h, double pdy,
+                                            int32_t varkind, const double* dval, int32_t s,
+                                            int32_t i, double* acc) {
+    const VarData d = var_data(varkind, dval, s, i, r.c, r.lo, r.hi);
+    const double rc = barrier(-d.c - g, d.lo, d.hi);        // r~ (reduced cost at y~)
+    const double rk = barrier(-d.c - (g - h), d.lo, d.hi);  // r at y^k = y~ - dy
+    const double dr = barrier(rc - rk, d.lo, d.hi);
+    const double dres = d.c + g + rc;
+    const double ea = r.xt - r.x0;
+    const double pr = pdy + dr;
+    const double rx = r.dx - recession(r.dx, d.lo, d.hi);
+    acc[0] += r.dx * r.dx;
+    acc[1] += d.c * r.xt;
+    acc[2] += support1(rc, d.lo, d.hi);
+    acc[3] += dres * dres;
+    acc[4] += d.c * d.c;
+    acc[5] += ea * ea;
+    acc[6] += support1(dr, d.lo, d.hi);
+    acc[7] += pr * pr;
+    acc[8] += d.c * r.dx;
+    acc[9] += rx * rx;
+}
+// y side of row i: ax = (A x~)_i, adx = (A dx)_i
+__device__ __forceinline__ void finish_yrow(const YRow& r, double ax, double adx, double* acc) {
+    const double pres = ax - clampd(ax, r.l, r.u);
+    const double ea = r.yt - r.y0;
+    const double ra = adx - recession(adx, r.l, r.u);
+    acc[0] += r.dy * r.dy;
+    acc[1] += r.dy * adx;
+    acc[2] += support1(r.yt, r.l, r.u);
+    acc[3] += pres * pres;
+    acc[4] += ax * ax;
+    acc[5] += ea * ea;
+    acc[6] += support1(barrier(r.dy, r.l, r.u), r.l, r.u);
+    acc[7] += ra * ra;
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_eval(EvalArgs<T> a) {
     __shared__ double red[4][NTERM][64];
@@ -496,119 +552,118 @@ __global__ __launch_bounds__(256) void k_eval(EvalArgs<T> a) {
         const int32_t varkind = a.sl.key[s].varkind;
         const int32_t r0 = panel * 4 * pw + wave * pw;
         const int32_t r1 = min(r0 + pw, rows);
-        // each row's own operands are loaded before its product and the next
-        // row's pointers during it, so a row costs one chain of dependent loads
-        if (xside) {
-            int32_t kb_next = r0 < r1 ? a.t_rp[r0] : 0;
-            for (int32_t i = r0; i < r1; ++i) {
-                // (A' y~)_i, (A' dy)_i and (A' Pi_B[l,u](dy))_i over the rows of column i
-                double g = 0.0, h = 0.0, pdy = 0.0;
-                const int32_t kb = kb_next, ke = a.t_rp[i + 1];
-                kb_next = ke;
-                const size_t e = (size_t)i * a.ld + s;
-                const double xt = a.Xt[e], dx = a.DX[e], x0 = a.X0[e];
-                const double ci = a.c[i], xli = a.xl[i], xui = a.xu[i];
-                for (int32_t k0 = kb; k0 < ke; k0 += CH) {
-                    int32_t jj[CH];
-                    double vv[CH];
+        // The wave walks the nonzeros of its rows as one stream, CH at a time,
+        // so the gathers of short rows are in flight together; each row's
+        // products still add its nonzeros in CSR order and the rows' terms
+        // are added in row order, exactly as a row-by-row walk would.  Row
+        // operands are loaded one row ahead.
+        if (xside && r0 < r1) {
+            const int32_t kbeg = a.t_rp[r0], kend = a.t_rp[r1];
+            int32_t i = r0;
+            int32_t ke = a.t_rp[r0 + 1];
+            XRow cur = load_xrow(a, r0, s), nxt{};
+            int32_t ke_n = 0;
+            if (r0 + 1 < r1) {
+                nxt = load_xrow(a, r0 + 1, s);
+                ke_n = a.t_rp[r0 + 2];
+            }
+            double g = 0.0, h = 0.0, pdy = 0.0;
+            auto advance = [&]() {
+                finish_xrow(cur, g, h, pdy, varkind, a.sl.dval, s, i, acc);
+                g = h = pdy = 0.0;
+                ++i;
+                cur = nxt;
+                ke = ke_n;
+                if (i + 1 < r1) {
+                    nxt = load_xrow(a, i + 1, s);
+                    ke_n = a.t_rp[i + 2];
+                }
+            };
+            for (int32_t k0 = kbeg; k0 < kend; k0 += CH) {
+                int32_t jj[CH];
+                double vv[CH], yv[CH], dv[CH], lv[CH], uv[CH];
 #pragma unroll
-                    for (int u = 0; u < CH; ++u) {
-                        jj[u] = 0;
-                        vv[u] = 0.0;
-                        if (k0 + u < ke) {
-                            jj[u] = a.t_ci[k0 + u];
-                            vv[u] = (double)a.t_v[k0 + u];
-                        }
-                    }
-                    double yv[CH], dv[CH], lv[CH], uv[CH];
-#pragma unroll
-                    for (int u = 0; u < CH; ++u) {
-                        if (k0 + u < ke) {
-                            const size_t f = (size_t)jj[u] * a.ld + s;
-                            yv[u] = (double)a.Yt[f];
-                            dv[u] = (double)a.DY[f];
-                            lv[u] = a.rl[jj[u]];
-                            uv[u] = a.ru[jj[u]];
-                        }
-                    }
-#pragma unroll
-                    for (int u = 0; u < CH; ++u) {
-                        if (k0 + u < ke) {
-                            g = fma(vv[u], yv[u], g);
-                            h = fma(vv[u], dv[u], h);
-                            pdy = fma(vv[u], barrier(dv[u], lv[u], uv[u]), pdy);
-                        }
+                for (int u = 0; u < CH; ++u) {
+                    jj[u] = 0;
+                    vv[u] = 0.0;
+                    if (k0 + u < kend) {
+                        jj[u] = a.t_ci[k0 + u];
+                        vv[u] = (double)a.t_v[k0 + u];
                     }
                 }
-                const VarData d = var_data(varkind, a.sl.dval, s, i, ci, xli, xui);
-                const double rc = barrier(-d.c - g, d.lo, d.hi);        // r~ (reduced cost at y~)
-                const double rk = barrier(-d.c - (g - h), d.lo, d.hi);  // r at y^k = y~ - dy
-                const double dr = barrier(rc - rk, d.lo, d.hi);
-                const double dres = d.c + g + rc;
-                const double ea = xt - x0;
-                const double pr = pdy + dr;
-                const double rx = dx - recession(dx, d.lo, d.hi);
-                acc[0] += dx * dx;
-                acc[1] += d.c * xt;
-                acc[2] += support1(rc, d.lo, d.hi);
-                acc[3] += dres * dres;
-                acc[4] += d.c * d.c;
-                acc[5] += ea * ea;
-                acc[6] += support1(dr, d.lo, d.hi);
-                acc[7] += pr * pr;
-                acc[8] += d.c * dx;
-                acc[9] += rx * rx;
-            }
-        } else {
-            int32_t kb_next = r0 < r1 ? a.a_rp[r0] : 0;
-            for (int32_t i = r0; i < r1; ++i) {
-                double ax = 0.0, adx = 0.0;                       // (A x~)_i, (A dx)_i
-                const int32_t kb = kb_next, ke = a.a_rp[i + 1];
-                kb_next = ke;
-                const size_t e = (size_t)i * a.ld + s;
-                const double yt = a.Yt[e], dy = a.DY[e], y0 = a.Y0[e];
-                const double l = a.rl[i], u = a.ru[i];
-                for (int32_t k0 = kb; k0 < ke; k0 += CH) {
-                    int32_t jj[CH];
-                    double vv[CH];
 #pragma unroll
-                    for (int u = 0; u < CH; ++u) {
-                        jj[u] = 0;
-                        vv[u] = 0.0;
-                        if (k0 + u < ke) {
-                            jj[u] = a.a_ci[k0 + u];
-                            vv[u] = (double)a.a_v[k0 + u];
-                        }
-                    }
-                    double xv[CH], dv[CH];
-#pragma unroll
-                    for (int u = 0; u < CH; ++u) {
-                        if (k0 + u < ke) {
-                            const size_t f = (size_t)jj[u] * a.ld + s;
-                            xv[u] = (double)a.Xt[f];
-                            dv[u] = (double)a.DX[f];
-                        }
-                    }
-#pragma unroll
-                    for (int u = 0; u < CH; ++u) {
-                        if (k0 + u < ke) {
-                            ax = fma(vv[u], xv[u], ax);
-                            adx = fma(vv[u], dv[u], adx);
-                        }
+                for (int u = 0; u < CH; ++u) {
+                    if (k0 + u < kend) {
+                        const size_t f = (size_t)jj[u] * a.ld + s;
+                        yv[u] = (double)a.Yt[f];
+                        dv[u] = (double)a.DY[f];
+                        lv[u] = a.rl[jj[u]];
+                        uv[u] = a.ru[jj[u]];
                     }
                 }
-                const double pres = ax - clampd(ax, l, u);
-                const double ea = yt - y0;
-                const double ra = adx - recession(adx, l, u);
-                acc[0] += dy * dy;
-                acc[1] += dy * adx;
-                acc[2] += support1(yt, l, u);
-                acc[3] += pres * pres;
-                acc[4] += ax * ax;
-                acc[5] += ea * ea;
-                acc[6] += support1(barrier(dy, l, u), l, u);
-                acc[7] += ra * ra;
+#pragma unroll
+                for (int u = 0; u < CH; ++u) {
+                    if (k0 + u < kend) {
+                        while (k0 + u >= ke) advance();
+                        g = fma(vv[u], yv[u], g);
+                        h = fma(vv[u], dv[u], h);
+                        pdy = fma(vv[u], barrier(dv[u], lv[u], uv[u]), pdy);
+                    }
+                }
             }
+            while (i < r1) advance();
+        } else if (r0 < r1) {
+            const int32_t kbeg = a.a_rp[r0], kend = a.a_rp[r1];
+            int32_t i = r0;
+            int32_t ke = a.a_rp[r0 + 1];
+            YRow cur = load_yrow(a, r0, s), nxt{};
+            int32_t ke_n = 0;
+            if (r0 + 1 < r1) {
+                nxt = load_yrow(a, r0 + 1, s);
+                ke_n = a.a_rp[r0 + 2];
+            }
+            double ax = 0.0, adx = 0.0;                       // (A x~)_i, (A dx)_i
+            auto advance = [&]() {
+                finish_yrow(cur, ax, adx, acc);
+                ax = adx = 0.0;
+                ++i;
+                cur = nxt;
+                ke = ke_n;
+                if (i + 1 < r1) {
+                    nxt = load_yrow(a, i + 1, s);
+                    ke_n = a.a_rp[i + 2];
+                }
+            };
+            for (int32_t k0 = kbeg; k0 < kend; k0 += CH) {
+                int32_t jj[CH];
+                double vv[CH], xv[CH], dv[CH];
+#pragma unroll
+                for (int u = 0; u < CH; ++u) {
+                    jj[u] = 0;
+                    vv[u] = 0.0;
+                    if (k0 + u < kend) {
+                        jj[u] = a.a_ci[k0 + u];
+                        vv[u] = (double)a.a_v[k0 + u];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < CH; ++u) {
+                    if (k0 + u < kend) {
+                        const size_t f = (size_t)jj[u] * a.ld + s;
+                        xv[u] = (double)a.Xt[f];
+                        dv[u] = (double)a.DX[f];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < CH; ++u) {
+                    if (k0 + u < kend) {
+                        while (k0 + u >= ke) advance();
+                        ax = fma(vv[u], xv[u], ax);
+                        adx = fma(vv[u], dv[u], adx);
+                    }
+                }
+            }
+            while (i < r1) advance();
         }
     }
 #pragma unroll

@@ -25,6 +25,12 @@ def test_more_than_one_gpu_is_refused():
     assert "one GPU" in r.stderr and r.stdout == ""
 
 
+def test_cpu_workers_stay_within_the_host_share():
+    w = bench.cpu_workers()
+    assert 1 <= w <= 16
+    assert w <= (os.cpu_count() or 1)
+
+
 def test_fused_bytes_hand_count():
     # m = 2 rows, n = 3 columns, 4 nonzeros, B = 2 LPs, 8-byte values and iterates
     m, n, nnz, B = 2, 3, 4, 2
