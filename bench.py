@@ -341,10 +341,17 @@ def serve_leg(args, rates, seconds):
     """Serving stream: four resident base LPs (the 200k x 500k family by
     default, FP64; --serve-prec fp32 for FP32 iterates with FP64 sums, which
     cannot certify the infeasible branches of this family, see the design
-    notes), each with its root solution kept on the device as warm start.  Requests arrive as a Poisson process; each
-    is a strong-branching batch of 2..512 LPs (log-uniform, even) on a random
-    base.  The loop admits requests as columns and result rows free up and
-    reports p50 / p99 latency and LPs/s per arrival rate."""
+    notes), each with its root solution kept on the device as warm start.
+    Requests arrive as a Poisson process for `seconds`; each is a
+    strong-branching batch of 2..512 LPs (log-uniform, even) on a random base.
+    The loop admits requests whole, in arrival order, when their device-memory
+    footprint fits one budget for all bases (--serve-budget-gb), serves the
+    bases whose blocks finish first, and reports p50 / p99 latency, the time
+    requests waited for admission and LPs/s per arrival rate.  Above capacity
+    the queue grows; after the arrivals stop the loop drains for at most
+    --serve-drain-s seconds, and the requests still unfinished are counted
+    (their latency is at least their age, so p99 over the completed ones is
+    then a lower bound, flagged `censored`)."""
     import numpy as np
     import paper_2601_21990_amd.pdlpb as P
     from paper_2601_21990_amd.serve import Server, Request, percentile
@@ -355,8 +362,9 @@ def serve_leg(args, rates, seconds):
     ctxs, roots = [], []
     for b in range(args.serve_bases):
         inst = make_cfg5(base=b, m=m, n=n)
+        alloc = P.TorchAllocator(0) if args.serve_torch_alloc else None
         ctx = P.Context.from_instance(inst, device=0, precision=prec, max_batch=args.serve_cols,
-                                      eval_every=args.serve_eval)
+                                      eval_every=args.serve_eval, allocator=alloc)
         ctx.set_batch(deltas([BASE], [0], [0.0]))
         ctx.solve(tol=1e-5, max_iters=50000)
         root = ctx.get(0)
@@ -368,13 +376,22 @@ def serve_leg(args, rates, seconds):
         ctx.serve_begin(args.serve_rows)
         ctxs.append(ctx)
         roots.append((root["x"], cand))
+    if args.serve_budget_gb > 0:
+        budget = int(args.serve_budget_gb * (1 << 30))
+    elif args.serve_budget_gb < 0:
+        # a share of the device's memory
+        import torch
+        budget = int(-args.serve_budget_gb * torch.cuda.get_device_properties(0).total_memory)
+    else:
+        budget = None
     rng = np.random.default_rng(2601021990 + 5000)
     lines = []
     for rate in rates:
-        srv = Server(ctxs, warm=True)
+        srv = Server(ctxs, warm=True, budget_bytes=budget)
         t_start = time.perf_counter()
         next_arrival = t_start + rng.exponential(1.0 / rate)
-        n_req = 0
+        n_req, offered = 0, 0
+        submitted = []
         while True:
             now = time.perf_counter()
             while next_arrival <= now and next_arrival - t_start < seconds:
@@ -383,29 +400,46 @@ def serve_leg(args, rates, seconds):
                 size = max(2, min(512, size))
                 x, cand = roots[b]
                 vars_ = np.sort(rng.choice(cand, size=size // 2, replace=False)).astype(np.int32)
-                srv.submit(Request(base=b, deltas=fsb_deltas(x, vars_), arrival=next_arrival,
-                                   tol=1e-4, max_iters=args.serve_iters))
+                r = Request(base=b, deltas=fsb_deltas(x, vars_), arrival=next_arrival,
+                            tol=1e-4, max_iters=args.serve_iters)
+                srv.submit(r)
+                submitted.append(r)
                 n_req += 1
+                offered += size
                 next_arrival += rng.exponential(1.0 / rate)
-            if next_arrival - t_start >= seconds and not srv.busy():
+            arrivals_over = next_arrival - t_start >= seconds
+            if arrivals_over and (not srv.busy() or now - t_start > seconds + args.serve_drain_s):
                 break
             if srv.busy():
                 srv.step()
             else:
                 time.sleep(max(0.0, min(next_arrival - time.perf_counter(), 0.01)))
         wall = time.perf_counter() - t_start
-        lat = [r.latency for r in srv.completed]
-        solved = sum(sum(1 for s in r.statuses.values() if s == P.STATUS_OPTIMAL)
-                     for r in srv.completed)
-        st = np.array([v for r in srv.completed for v in r.statuses.values()], dtype=np.int64)
-        its = np.array([v for r in srv.completed for v in r.iters.values()], dtype=np.int64)
-        line = {"rate_per_s": rate, "requests": n_req, "completed": len(srv.completed),
-                "statuses": np.bincount(st, minlength=8).tolist(),
+        unfinished = [r for r in submitted if r.done is None]
+        # the loop ends here: requests never admitted are dropped, and the LPs
+        # already in the library finish untimed
+        srv.fifo.clear()
+        srv.drain()
+        done = [r for r in submitted if r.done is not None and r.done - t_start <= wall]
+        lat = [r.latency for r in done]
+        waits = [r.wait for r in done]
+        solved = sum(sum(1 for s in r.statuses.values() if s == P.STATUS_OPTIMAL) for r in done)
+        lps = sum(len(r.ids) for r in done)
+        st = np.array([v for r in done for v in r.statuses.values()], dtype=np.int64)
+        its = np.array([v for r in done for v in r.iters.values()], dtype=np.int64)
+        line = {"rate_per_s": rate, "requests": n_req, "completed": len(done),
+                "unfinished": len(unfinished), "censored": bool(unfinished),
+                "offered_lps_per_s": round(offered / seconds, 1),
+                "statuses": np.bincount(st, minlength=8).tolist() if st.size else [],
                 "iters_median": int(np.median(its)) if its.size else 0,
                 "iters_max": int(its.max()) if its.size else 0,
-                "lps": srv.lps_done, "lps_optimal": solved, "wall_s": round(wall, 3),
-                "lps_per_s": round(srv.lps_done / wall, 2),
-                "p50_s": round(percentile(lat, 50), 4), "p99_s": round(percentile(lat, 99), 4)}
+                "lps": lps, "lps_optimal": solved, "wall_s": round(wall, 3),
+                "lps_per_s": round(lps / wall, 2),
+                "p50_s": round(percentile(lat, 50), 4), "p99_s": round(percentile(lat, 99), 4),
+                "admission_wait_p50_s": round(percentile(waits, 50), 4),
+                "admission_wait_p99_s": round(percentile(waits, 99), 4),
+                "peak_footprint_gib": round(srv.peak_bytes / (1 << 30), 2),
+                "deferred_admissions": srv.blocked_on_budget, "trims": srv.trims}
         log(json.dumps(line))
         lines.append(line)
     for c in ctxs:
@@ -414,9 +448,12 @@ def serve_leg(args, rates, seconds):
             "config": {"workload": f"{args.serve_bases} resident bases A {m}x{n} "
                                    f"(4 N(0,1) nnz/col), Poisson requests of 2..512 "
                                    f"strong-branching LPs, warm start, tol 1e-4",
-                       "precision": args.serve_prec, "columns": args.serve_cols,
+                       "precision": args.serve_prec, "max_columns_per_base": args.serve_cols,
                        "eval_every": args.serve_eval, "result_rows": args.serve_rows,
-                       "seconds_per_rate": seconds},
+                       "budget_gib": round(budget / (1 << 30), 2) if budget else None,
+                       "torch_allocator": bool(args.serve_torch_alloc),
+                       "seconds_per_rate": seconds,
+                       "drain_cap_s": args.serve_drain_s},
             "rates": lines}
 
 
@@ -1259,6 +1296,13 @@ def main():
     ap.add_argument("--serve-rates", default="1,3,10")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-iters", type=int, default=20000)
+    ap.add_argument("--serve-budget-gb", type=float, default=-0.75,
+                    help="serve: device-memory budget of all bases: GiB if > 0, a fraction of "
+                         "the device's memory if < 0, none if 0")
+    ap.add_argument("--serve-torch-alloc", action="store_true",
+                    help="serve: the contexts' device memory from PyTorch's caching allocator")
+    ap.add_argument("--serve-drain-s", type=float, default=20.0,
+                    help="serve: longest drain after the arrivals stop")
     ap.add_argument("--sweep-m", type=int, default=200000)
     ap.add_argument("--sweep-b", default="1,8,32,64,128,256,512")
     ap.add_argument("--sweep-iters", type=int, default=65)

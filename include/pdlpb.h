@@ -292,19 +292,29 @@ int pdlpb_branch_scores(pdlpb_ctx* ctx, double parent_obj, double mu, double* ga
 /*
  * Serving: continuous batching of LPs on one resident matrix.
  *
- * pdlpb_serve_begin switches a context to serving with max_batch LP columns
- * and `result_capacity` result rows.  pdlpb_submit queues LPs (one change
- * each, as in pdlpb_set_batch) with their own tolerance and iteration budget
- * and returns consecutive ids; it fails with PDLPB_ENOMEM when fewer than
- * `count` result rows are free (pdlpb_release frees them).  Each
- * pdlpb_serve_launch admits queued LPs into free columns (FIFO; the admitted
- * LPs make their first iteration, an evaluation, at admission) and enqueues
- * one block of C iterations for every running LP without waiting for it;
- * pdlpb_serve_wait waits for that block and records which LPs stopped.  With
- * the per-LP restart scope every LP follows the same iteration schedule from
- * its own first iteration, so its result does not depend on when it was
+ * pdlpb_serve_begin switches a context to serving with at most max_batch LP
+ * columns and at most `result_capacity` result rows.  pdlpb_submit queues LPs
+ * (one change each, as in pdlpb_set_batch) with their own tolerance and
+ * iteration budget and returns consecutive ids; it fails with PDLPB_ENOMEM
+ * when fewer than `count` result rows are free (pdlpb_release frees them).
+ * Each pdlpb_serve_launch admits queued LPs into free columns (FIFO; the
+ * admitted LPs make their first iteration, an evaluation, at admission) and
+ * enqueues one block of C iterations for every running LP without waiting for
+ * it; pdlpb_serve_wait waits for that block and records which LPs stopped.
+ * With the per-LP restart scope every LP follows the same iteration schedule
+ * from its own first iteration, so its result does not depend on when it was
  * admitted or on the LPs beside it.  Launch/wait pairs of several contexts
  * overlap on the device (each context has its own stream).
+ *
+ * Device storage follows the admitted work: a session starts with one column
+ * and one result row, and pdlpb_serve_launch grows both (to the next power of
+ * two, within the limits above) so that every running and queued LP has a
+ * column and every row in use exists, moving the running LPs' columns into
+ * the new storage.  pdlpb_serve_footprint tells a caller the device bytes the
+ * context will hold once `extra` more LPs are submitted, so that a loop over
+ * several contexts can admit a request only when its footprint fits one
+ * device-memory budget; pdlpb_serve_trim shrinks the storage to what the LPs
+ * still queued, running or holding result rows need.
  *
  * pdlpb_set_base_warm keeps one warm start (x: n, y: m, primal weight w)
  * resident on the device for PDLPB_WARM_BASE submissions.  A bound change
@@ -332,6 +342,26 @@ int pdlpb_result(pdlpb_ctx* ctx, int64_t id, double* x, double* y, int32_t* stat
 /* Free the result row of a stopped LP; its id becomes invalid.  PDLPB_ESTATE
  * while the LP is queued or running (its row is still in use). */
 int pdlpb_release(pdlpb_ctx* ctx, int64_t id);
+/*
+ * 1 when no block of the session is in flight or the last one launched has
+ * finished on the device (pdlpb_serve_wait will not block), 0 while it still
+ * runs, a negative error code on a device error.  Never blocks, so a loop can
+ * serve the contexts whose blocks finish first.
+ */
+int pdlpb_serve_ready(pdlpb_ctx* ctx);
+/*
+ * *bytes = device bytes the context will hold (pdlpb_device_bytes: matrix,
+ * base vectors, warm start and batch storage) once `extra` (>= 0) more LPs
+ * are submitted and admitted, with the storage grown as pdlpb_serve_launch
+ * grows it.  With extra = 0: what its running and queued LPs will hold.
+ */
+int pdlpb_serve_footprint(pdlpb_ctx* ctx, int32_t extra, int64_t* bytes);
+/*
+ * Shrink the session's storage to the next power of two at or above what its
+ * running and queued LPs (columns) and its rows in use need, keeping their
+ * data.  PDLPB_ESTATE while a block is in flight.
+ */
+int pdlpb_serve_trim(pdlpb_ctx* ctx);
 
 /*
  * Batch width estimate (Section 5, "Matrix-matrix products and optimal batch

@@ -176,6 +176,10 @@ struct pdlpb_ctx {
     std::vector<int64_t> row_id;                // id held by each result row (-1 free)
     enum : int8_t { ROW_FREE = 0, ROW_QUEUED = 1, ROW_RUNNING = 2, ROW_STOPPED = 3 };
     std::vector<int8_t> row_state;              // where the LP of each result row stands
+    std::vector<int8_t> row_settled;            // 1: the LP settled at submission (never on the device)
+    std::vector<SlotCtl> settled_ctl;           // its outcome, by row
+    int32_t row_hi = 0;                         // rows [0, row_hi) hold every row in use
+    hipEvent_t serve_ev = nullptr;              // end of the block in flight
     std::unordered_map<int64_t, int32_t> id_row;
     std::deque<Pending> queue;
     std::deque<int64_t> completed;
@@ -279,6 +283,7 @@ void free_all(pdlpb_ctx* x) {
             (void)hipEventDestroy(e);
             e = nullptr;
         }
+    if (x->serve_ev) (void)hipEventDestroy(x->serve_ev);
     // every device buffer, whichever allocator it came from
     std::vector<void*> live;
     live.reserve(x->dev_sizes.size());
@@ -942,16 +947,28 @@ double default_weight(const pdlpb_ctx* x, const pdlpb_delta& q) {
     return (cn > 1e-10 && x->norm_b > 1e-10) ? cn / x->norm_b : 1.0;
 }
 
+// Vector width the row stride of a `cols`-column storage is padded for: 4 when
+// the launches are large enough to be tuned over every shape, else the width
+// the default tile uses.
+int32_t vec_for(const pdlpb_ctx* x, int32_t cols) {
+    if (x->opt.autotune && x->opt.tile_vec == 0 && launch_bytes(x, cols) >= 32e6) return 4;
+    const int32_t w = std::min<int32_t>(64, next_pow2(cols > 0 ? cols : 1));
+    int32_t vec = w >= 64 ? (x->fp32 ? 4 : 2) : 1;
+    if (x->opt.tile_vec > 0) vec = x->opt.tile_vec;
+    return vec;
+}
+int32_t ld_for(const pdlpb_ctx* x, int32_t cols) {
+    const int32_t v = vec_for(x, cols);
+    return ((cols + v - 1) / v) * v;
+}
+
 // Device storage for `cols` LP columns and `lps` LP result rows (grows, reused
 // for smaller requests).  Sets vec_ld and returns the row stride ld.
 int ensure_storage(pdlpb_ctx* x, int32_t cols, int32_t lps, int32_t* ld_out) {
     const int32_t n = x->n, m = x->m;
-    x->vec_ld = 4;
-    const Tile t0 = heuristic_tile(x, cols);
     // pad for 4-wide vectors when the batch is large enough to be tuned
-    x->vec_ld = (x->opt.autotune && x->opt.tile_vec == 0 && launch_bytes(x, cols) >= 32e6)
-                    ? 4 : t0.vec;
-    const int32_t ld = ((cols + x->vec_ld - 1) / x->vec_ld) * x->vec_ld;
+    x->vec_ld = vec_for(x, cols);
+    const int32_t ld = ld_for(x, cols);
     const size_t esz = x->fp32 ? sizeof(float) : sizeof(double);
     // blocks 0-3 hold x rows (n), blocks 4-7 y rows (m); capacity is kept as
     // bytes per row so both kinds grow together
@@ -1024,6 +1041,164 @@ int ensure_storage(pdlpb_ctx* x, int32_t cols, int32_t lps, int32_t* ld_out) {
     }
     *ld_out = ld;
     return PDLPB_OK;
+}
+
+// Device bytes of an allocation of `bytes` (the allocator rounds zero up).
+int64_t alloc_bytes(size_t bytes) { return (int64_t)(bytes == 0 ? 256 : bytes); }
+
+// Device bytes of the batch storage for `cols` columns (stride ld) and `rows`
+// result rows: the eight iterate blocks, the per-slot arrays, the compaction
+// plan and admission staging, the evaluation partial sums, the four result
+// blocks and the per-LP control rows.  Mirrors resize_storage.
+int64_t storage_bytes(const pdlpb_ctx* x, int32_t cols, int32_t rows) {
+    const size_t esz = x->fp32 ? sizeof(float) : sizeof(double);
+    const int32_t ld = ld_for(x, cols);
+    int64_t b = 0;
+    for (int q = 0; q < 8; ++q) b += alloc_bytes((size_t)(q < 4 ? x->n : x->m) * ld * esz);
+    const size_t per_slot[] = {sizeof(SlotKey), sizeof(double), sizeof(double), sizeof(double),
+                               sizeof(int32_t), sizeof(int32_t), sizeof(RetireEntry),
+                               sizeof(MoveEntry), sizeof(int32_t), sizeof(int32_t),
+                               sizeof(SlotCtl)};
+    for (size_t e : per_slot) b += alloc_bytes(e * cols);
+    b += alloc_bytes((size_t)(x->npx + x->npy + 2) * NTERM * ld * sizeof(double));
+    for (int q = 0; q < 4; ++q) b += alloc_bytes((size_t)rows * (q < 2 ? x->n : x->m) * esz);
+    b += alloc_bytes(sizeof(SlotCtl) * rows);
+    b += alloc_bytes(sizeof(int32_t) * RESTART_LOG * rows);
+    return b;
+}
+
+// Bytes currently held by the batch storage.
+int64_t held_storage_bytes(const pdlpb_ctx* x) {
+    int64_t b = 0;
+    const void* ptrs[] = {x->blk[0], x->blk[1], x->blk[2], x->blk[3], x->blk[4], x->blk[5],
+                          x->blk[6], x->blk[7], x->sl.key, x->sl.tau, x->sl.sigma, x->sl.dval,
+                          x->sl.t_start, x->sl.lp, x->retire, x->moves, x->fresh, x->adm_rows,
+                          x->adm_ctl, x->part, x->res[0], x->res[1], x->res[2], x->res[3],
+                          x->ctl, x->rlog};
+    for (const void* p : ptrs) {
+        auto it = x->dev_sizes.find(const_cast<void*>(p));
+        if (p && it != x->dev_sizes.end()) b += (int64_t)it->second;
+    }
+    return b;
+}
+
+// Serving storage: `cols` columns and `rows` result rows, keeping the first
+// `keep_cols` columns of every block and slot array and the first
+// min(rows, old rows) result and control rows.  New buffers are allocated and
+// filled on the context's stream before the old ones go.
+int resize_storage(pdlpb_ctx* x, int32_t cols, int32_t rows, int32_t keep_cols) {
+    const int32_t n = x->n, m = x->m;
+    const size_t esz = x->fp32 ? sizeof(float) : sizeof(double);
+    const int32_t old_cols = x->cap_slots, old_ld = x->ld, old_rows = x->cap_lps;
+    keep_cols = std::min(keep_cols, std::min(old_cols, cols));
+    const int32_t keep_rows = std::min(old_rows, rows);
+    HIP_TRY(x, hipStreamSynchronize(x->stream));
+    x->drop_graph();
+    if (cols != old_cols || x->blk[0] == nullptr) {
+        const int32_t ld = ld_for(x, cols);
+        x->vec_ld = vec_for(x, cols);
+        void* nb[8] = {};
+        for (int q = 0; q < 8; ++q) {
+            const int32_t r = q < 4 ? n : m;
+            HIP_TRY(x, x->alloc(&nb[q], (size_t)r * ld * esz));
+            if (keep_cols > 0 && r > 0 && x->blk[q])
+                HIP_TRY(x, hipMemcpy2DAsync(nb[q], (size_t)ld * esz, x->blk[q], (size_t)old_ld * esz,
+                                            (size_t)keep_cols * esz, (size_t)r,
+                                            hipMemcpyDeviceToDevice, x->stream));
+        }
+        auto regrow = [&](auto*& p, size_t elem, bool copy) -> int {
+            using E = std::remove_pointer_t<std::remove_reference_t<decltype(p)>>;
+            E* q = nullptr;
+            HIP_TRY(x, x->alloc(&q, elem * (size_t)cols));
+            if (copy && keep_cols > 0 && p)
+                HIP_TRY(x, hipMemcpyAsync(q, p, elem * (size_t)keep_cols, hipMemcpyDeviceToDevice,
+                                          x->stream));
+            HIP_TRY(x, hipStreamSynchronize(x->stream));
+            x->release(p, 0);
+            p = q;
+            return PDLPB_OK;
+        };
+        int rc = PDLPB_OK;
+        if (!rc) rc = regrow(x->sl.key, sizeof(SlotKey), true);
+        if (!rc) rc = regrow(x->sl.tau, sizeof(double), true);
+        if (!rc) rc = regrow(x->sl.sigma, sizeof(double), true);
+        if (!rc) rc = regrow(x->sl.dval, sizeof(double), true);
+        if (!rc) rc = regrow(x->sl.t_start, sizeof(int32_t), true);
+        if (!rc) rc = regrow(x->sl.lp, sizeof(int32_t), true);
+        if (!rc) rc = regrow(x->retire, sizeof(RetireEntry), false);
+        if (!rc) rc = regrow(x->moves, sizeof(MoveEntry), false);
+        if (!rc) rc = regrow(x->fresh, sizeof(int32_t), false);
+        if (!rc) rc = regrow(x->adm_rows, sizeof(int32_t), false);
+        if (!rc) rc = regrow(x->adm_ctl, sizeof(SlotCtl), false);
+        if (rc) return rc;
+        double* np_ = nullptr;
+        const size_t part_need = (size_t)(x->npx + x->npy + 2) * NTERM * ld;
+        HIP_TRY(x, x->alloc(&np_, part_need * sizeof(double)));
+        HIP_TRY(x, hipStreamSynchronize(x->stream));
+        for (int q = 0; q < 8; ++q) {
+            void* old = x->blk[q];
+            x->release(old, 0);
+            x->blk[q] = nb[q];
+        }
+        x->release(x->part, 0);
+        x->part = np_;
+        x->cap_part = part_need;
+        x->cap_slots = cols;
+        x->cap_block_bytes = (size_t)ld * esz;
+        x->ld = ld;
+    }
+    if (rows != old_rows || x->ctl == nullptr) {
+        void* nr[4] = {};
+        for (int q = 0; q < 4; ++q) {
+            const size_t len = (size_t)(q < 2 ? n : m) * esz;
+            HIP_TRY(x, x->alloc(&nr[q], len * rows));
+            if (keep_rows > 0 && len > 0 && x->res[q])
+                HIP_TRY(x, hipMemcpyAsync(nr[q], x->res[q], len * keep_rows,
+                                          hipMemcpyDeviceToDevice, x->stream));
+        }
+        SlotCtl* nc = nullptr;
+        int32_t* nl = nullptr;
+        HIP_TRY(x, x->alloc(&nc, sizeof(SlotCtl) * rows));
+        HIP_TRY(x, x->alloc(&nl, sizeof(int32_t) * RESTART_LOG * rows));
+        if (keep_rows > 0 && x->ctl) {
+            HIP_TRY(x, hipMemcpyAsync(nc, x->ctl, sizeof(SlotCtl) * keep_rows,
+                                      hipMemcpyDeviceToDevice, x->stream));
+            HIP_TRY(x, hipMemcpyAsync(nl, x->rlog, sizeof(int32_t) * RESTART_LOG * keep_rows,
+                                      hipMemcpyDeviceToDevice, x->stream));
+        }
+        HIP_TRY(x, hipStreamSynchronize(x->stream));
+        for (int q = 0; q < 4; ++q) {
+            x->release(x->res[q], 0);
+            x->res[q] = nr[q];
+        }
+        x->release(x->ctl, 0);
+        x->release(x->rlog, 0);
+        x->ctl = nc;
+        x->rlog = nl;
+        x->cap_res_x = (size_t)rows * n * esz;
+        x->cap_res_y = (size_t)rows * m * esz;
+        x->cap_lps = rows;
+    }
+    x->B = cols;
+    return PDLPB_OK;
+}
+
+// Serving capacity targets: the next power of two at or above the need, within
+// the session's limits (columns: max_batch; rows: result_capacity).
+int32_t grow_target(int32_t have, int32_t need, int32_t limit) {
+    if (need <= have) return have;
+    return std::min(limit, std::max(need, next_pow2(need)));
+}
+
+// Columns and result rows the session needs once `extra` more LPs are
+// submitted: every running and queued LP a column (up to max_batch), every row
+// in use (rows are handed out from the free list in order) a result row.
+void serve_need(const pdlpb_ctx* x, int32_t extra, int32_t* cols, int32_t* rows) {
+    *cols = std::min<int64_t>(x->opt.max_batch, (int64_t)x->n_cols + (int64_t)x->queue.size() + extra);
+    int32_t hi = x->row_hi;
+    const int32_t nf = (int32_t)x->free_rows.size();
+    for (int32_t k = 0; k < extra && k < nf; ++k) hi = std::max(hi, x->free_rows[nf - 1 - k] + 1);
+    *rows = hi;
 }
 
 bool finite_all(const double* p, int64_t len) {
@@ -1324,6 +1499,11 @@ int pdlpb_set_batch(pdlpb_ctx* x, int32_t B, const pdlpb_delta* deltas, const do
     if (warm_mode != PDLPB_WARM_NONE && (!x_warm || (x->m > 0 && !y_warm)))
         return x->fail(PDLPB_EINVAL, "warm start vectors missing");
     HIP_TRY(x, hipSetDevice(x->device));
+    if (x->launched) {
+        // a serving block still in flight ends before its storage is reused
+        HIP_TRY(x, hipStreamSynchronize(x->stream));
+        x->launched = false;
+    }
     const int32_t n = x->n, m = x->m;
 
     std::vector<pdlpb_delta> d(B);
@@ -1745,12 +1925,12 @@ int pdlpb_serve_begin(pdlpb_ctx* x, int32_t result_capacity) {
     if (result_capacity < 1 || result_capacity > (1 << 24))
         return x->fail(PDLPB_EINVAL, "result_capacity out of range");
     HIP_TRY(x, hipSetDevice(x->device));
-    const int32_t cols = x->opt.max_batch;
-    int32_t ld = 0;
-    int rc = ensure_storage(x, cols, result_capacity, &ld);
+    HIP_TRY(x, hipStreamSynchronize(x->stream));
+    // storage starts at one column and one result row and grows with the LPs
+    // submitted (pdlpb_serve_footprint, pdlpb_serve_trim)
+    x->n_cols = 0;
+    int rc = resize_storage(x, 1, 1, 0);
     if (rc) return rc;
-    x->B = cols;
-    x->ld = ld;
     x->n_run0 = 0;
     x->batch_set = false;
     x->solved = false;
@@ -1760,6 +1940,9 @@ int pdlpb_serve_begin(pdlpb_ctx* x, int32_t result_capacity) {
     for (int32_t r = result_capacity - 1; r >= 0; --r) x->free_rows.push_back(r);
     x->row_id.assign(result_capacity, -1);
     x->row_state.assign(result_capacity, pdlpb_ctx::ROW_FREE);
+    x->row_settled.assign(result_capacity, 0);
+    x->settled_ctl.assign(result_capacity, SlotCtl{});
+    x->row_hi = 0;
     x->id_row.clear();
     x->queue.clear();
     x->completed.clear();
@@ -1801,7 +1984,6 @@ int pdlpb_submit(pdlpb_ctx* x, int32_t count, const pdlpb_delta* deltas, int32_t
             return x->fail(PDLPB_EINVAL, "delta var out of range at LP " + std::to_string(j));
     }
     *first_id = x->next_id;
-    const size_t esz = x->fp32 ? sizeof(float) : sizeof(double);
     for (int32_t j = 0; j < count; ++j) {
         const pdlpb_delta& q = d[j];
         const int64_t id = x->next_id++;
@@ -1814,8 +1996,9 @@ int pdlpb_submit(pdlpb_ctx* x, int32_t count, const pdlpb_delta* deltas, int32_t
         // start from the base primal point only
         double w = (warm_mode == PDLPB_WARM_BASE && q.kind != PDLPB_OBJ_UNIT) ? x->base_w
                                                                                : default_weight(x, scaled_delta(x, q));
+        x->row_hi = std::max(x->row_hi, row + 1);
         if (status != PDLPB_STATUS_RUNNING) {
-            // settled without iterating: record the outcome and zero results
+            // settled without iterating: the outcome stays on the host (x = y = 0)
             SlotCtl cl{};
             cl.w = w;
             cl.status = status;
@@ -1823,19 +2006,13 @@ int pdlpb_submit(pdlpb_ctx* x, int32_t count, const pdlpb_delta* deltas, int32_t
             cl.obj = NAN;
             cl.dobj = NAN;
             cl.tol = tol;
-            HIP_TRY(x, hipMemcpyAsync(x->ctl + row, &cl, sizeof(SlotCtl), hipMemcpyHostToDevice,
-                                      x->stream));
-            for (int qb = 0; qb < 4; ++qb) {
-                const size_t len = (size_t)(qb < 2 ? x->n : x->m) * esz;
-                if (len)
-                    HIP_TRY(x, hipMemsetAsync(static_cast<char*>(x->res[qb]) + (size_t)row * len, 0,
-                                              len, x->stream));
-            }
-            HIP_TRY(x, hipStreamSynchronize(x->stream));
+            x->settled_ctl[row] = cl;
+            x->row_settled[row] = 1;
             x->row_state[row] = pdlpb_ctx::ROW_STOPPED;
             x->completed.push_back(id);
             continue;
         }
+        x->row_settled[row] = 0;
         x->row_state[row] = pdlpb_ctx::ROW_QUEUED;
         pdlpb_ctx::Pending p;
         p.row = row;
@@ -1929,6 +2106,15 @@ int serve_admit(pdlpb_ctx* x) {
 
 template <typename T>
 int serve_launch(pdlpb_ctx* x) {
+    // storage for every running and queued LP (no block is in flight here)
+    int32_t need_cols = 0, need_rows = 0;
+    serve_need(x, 0, &need_cols, &need_rows);
+    const int32_t cols = grow_target(x->B, need_cols, x->opt.max_batch);
+    const int32_t rows = grow_target(x->cap_lps, need_rows, x->res_cap);
+    if (cols != x->B || rows != x->cap_lps) {
+        const int rc0 = resize_storage(x, cols, rows, x->n_cols);
+        if (rc0) return rc0;
+    }
     int rc = serve_admit<T>(x);
     if (rc) return rc;
     if (x->n_cols == 0) return PDLPB_OK;
@@ -1947,6 +2133,8 @@ int serve_launch(pdlpb_ctx* x) {
     // the stopped LPs of this block, for the host's completion list
     HIP_TRY(x, hipMemcpyAsync(x->h_pinned, x->g, 8 * sizeof(int32_t), hipMemcpyDeviceToHost,
                               x->stream));
+    if (!x->serve_ev) HIP_TRY(x, hipEventCreateWithFlags(&x->serve_ev, hipEventDisableTiming));
+    HIP_TRY(x, hipEventRecord(x->serve_ev, x->stream));
     x->launched = true;
     return PDLPB_OK;
 }
@@ -2018,12 +2206,26 @@ int pdlpb_result(pdlpb_ctx* x, int64_t id, double* xo, double* yo, int32_t* stat
     }
     HIP_TRY(x, hipSetDevice(x->device));
     SlotCtl cl{};
-    HIP_TRY(x, hipMemcpy(&cl, x->ctl + row, sizeof(SlotCtl), hipMemcpyDeviceToHost));
+    const bool settled = x->row_settled[row] != 0;
+    if (settled) cl = x->settled_ctl[row];
+    else HIP_TRY(x, hipMemcpy(&cl, x->ctl + row, sizeof(SlotCtl), hipMemcpyDeviceToHost));
     if (status) *status = cl.status;
     if (kkt)
         for (int q = 0; q < 4; ++q) kkt[q] = cl.kkt[q];
     if (obj) *obj = cl.obj;
     if (iters) *iters = cl.iters;
+    if (settled) {
+        // an LP that never iterated reports x = 0, y = 0
+        for (int q = 0; q < 2; ++q) {
+            double* d = q == 0 ? xo : yo;
+            const size_t len = sizeof(double) * (size_t)(q == 0 ? x->n : x->m);
+            if (!d || len == 0) continue;
+            if (mem == PDLPB_MEM_DEVICE) HIP_TRY(x, hipMemsetAsync(d, 0, len, x->stream));
+            else std::memset(d, 0, len);
+        }
+        HIP_TRY(x, hipStreamSynchronize(x->stream));
+        return PDLPB_OK;
+    }
     int rc = PDLPB_OK;
     if (xo) rc = copy_results(x, 0, row, 1, xo, mem);
     if (!rc && yo) rc = copy_results(x, 2, row, 1, yo, mem);
@@ -2040,8 +2242,45 @@ int pdlpb_release(pdlpb_ctx* x, int64_t id) {
     x->id_row.erase(it);
     x->row_id[row] = -1;
     x->row_state[row] = pdlpb_ctx::ROW_FREE;
+    x->row_settled[row] = 0;
     x->free_rows.push_back(row);
+    while (x->row_hi > 0 && x->row_state[x->row_hi - 1] == pdlpb_ctx::ROW_FREE) --x->row_hi;
     return PDLPB_OK;
+}
+
+int pdlpb_serve_ready(pdlpb_ctx* x) {
+    if (!x) return PDLPB_EINVAL;
+    if (!x->serving) return x->fail(PDLPB_ESTATE, "call pdlpb_serve_begin first");
+    if (!x->launched || !x->serve_ev) return 1;
+    const hipError_t e = hipEventQuery(x->serve_ev);
+    if (e == hipSuccess) return 1;
+    if (e == hipErrorNotReady) return 0;
+    return x->hip_fail(e, "hipEventQuery");
+}
+
+int pdlpb_serve_footprint(pdlpb_ctx* x, int32_t extra, int64_t* bytes) {
+    if (!x || !bytes) return PDLPB_EINVAL;
+    if (!x->serving) return x->fail(PDLPB_ESTATE, "call pdlpb_serve_begin first");
+    if (extra < 0) return x->fail(PDLPB_EINVAL, "extra must be >= 0");
+    int32_t need_cols = 0, need_rows = 0;
+    serve_need(x, extra, &need_cols, &need_rows);
+    const int32_t cols = grow_target(x->B, need_cols, x->opt.max_batch);
+    const int32_t rows = grow_target(x->cap_lps, need_rows, x->res_cap);
+    *bytes = x->dev_bytes - held_storage_bytes(x) + storage_bytes(x, cols, rows);
+    return PDLPB_OK;
+}
+
+int pdlpb_serve_trim(pdlpb_ctx* x) {
+    if (!x) return PDLPB_EINVAL;
+    if (!x->serving) return x->fail(PDLPB_ESTATE, "call pdlpb_serve_begin first");
+    if (x->launched) return x->fail(PDLPB_ESTATE, "a block is in flight; call pdlpb_serve_wait first");
+    HIP_TRY(x, hipSetDevice(x->device));
+    int32_t need_cols = 0, need_rows = 0;
+    serve_need(x, 0, &need_cols, &need_rows);
+    const int32_t cols = std::min(x->opt.max_batch, next_pow2(std::max(need_cols, 1)));
+    const int32_t rows = std::min(x->res_cap, next_pow2(std::max(need_rows, 1)));
+    if (cols >= x->B && rows >= x->cap_lps) return PDLPB_OK;
+    return resize_storage(x, std::min(cols, x->B), std::min(rows, x->cap_lps), x->n_cols);
 }
 
 }  // extern "C"

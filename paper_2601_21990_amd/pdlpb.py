@@ -43,7 +43,8 @@ EXPORTED = ["pdlpb_default_options", "pdlpb_create", "pdlpb_set_batch", "pdlpb_s
             "pdlpb_release",
             "pdlpb_set_kernel_timing", "pdlpb_kernel_times", "pdlpb_kernel_columns",
             "pdlpb_device_bytes", "pdlpb_graph_captures", "pdlpb_estimate_batch",
-            "pdlpb_get_batch_noalloc",
+            "pdlpb_get_batch_noalloc", "pdlpb_serve_ready", "pdlpb_serve_footprint",
+            "pdlpb_serve_trim",
             "pdlpb_destroy", "pdlpb_last_error"]
 
 
@@ -120,6 +121,9 @@ def _load():
         "pdlpb_poll": (C.c_int, [P, i64p, i32, i32p]),
         "pdlpb_result": (C.c_int, [P, i64, P, P, i32p, dp, dp, i64p, i32]),
         "pdlpb_release": (C.c_int, [P, i64]),
+        "pdlpb_serve_ready": (C.c_int, [P]),
+        "pdlpb_serve_footprint": (C.c_int, [P, i32, i64p]),
+        "pdlpb_serve_trim": (C.c_int, [P]),
         "pdlpb_get_step_size": (C.c_int, [P, dp, dp]),
         "pdlpb_get_scaling": (C.c_int, [P, dp, dp]),
         "pdlpb_set_kernel_timing": (C.c_int, [P, i32]),
@@ -161,6 +165,9 @@ pdlpb_serve_wait = lib.pdlpb_serve_wait
 pdlpb_poll = lib.pdlpb_poll
 pdlpb_result = lib.pdlpb_result
 pdlpb_release = lib.pdlpb_release
+pdlpb_serve_ready = lib.pdlpb_serve_ready
+pdlpb_serve_footprint = lib.pdlpb_serve_footprint
+pdlpb_serve_trim = lib.pdlpb_serve_trim
 pdlpb_get_step_size = lib.pdlpb_get_step_size
 pdlpb_get_scaling = lib.pdlpb_get_scaling
 pdlpb_set_kernel_timing = lib.pdlpb_set_kernel_timing
@@ -454,6 +461,20 @@ class Context:
 
     def release(self, lp_id: int):
         self._check(lib.pdlpb_release(self._h, int(lp_id)))
+
+    def serve_ready(self) -> bool:
+        rc = lib.pdlpb_serve_ready(self._h)
+        if rc < 0:
+            self._check(rc)
+        return rc == 1
+
+    def serve_footprint(self, extra: int = 0) -> int:
+        b = C.c_int64()
+        self._check(lib.pdlpb_serve_footprint(self._h, int(extra), C.byref(b)))
+        return b.value
+
+    def serve_trim(self):
+        self._check(lib.pdlpb_serve_trim(self._h))
 
     def estimate_batch(self, widths, reps: int = 10):
         w = np.ascontiguousarray(widths, dtype=np.int32)
