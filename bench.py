@@ -78,6 +78,49 @@ def measured_traffic(name, kernel):
     return d["bytes_per_launch"]
 
 
+def run_pmc_table(args):
+    """Markdown table of L2-to-memory (EA) traffic per kernel from rocprofv3
+    --pmc runs: every folder of --pmc-table (label=DIR, comma separated) holds
+    one run; counters of the same label are merged, and each kernel's mean per
+    dispatch is reported with the bytes the request-size counters give:
+    read = 32 RDREQ_32B + 64 RDREQ_64B + 128 RDREQ_128B, write = 64 WRREQ_64B
+    + 32 (WRREQ - WRREQ_64B) (on a 1 GiB copy these read exactly 1 GiB each)."""
+    import csv
+    import glob
+    runs = {}
+    for item in args.pmc_table.split(","):
+        label, d = item.split("=", 1)
+        f = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)[0]
+        per = runs.setdefault(label, {})
+        for r in csv.DictReader(open(f)):
+            name = r["Kernel_Name"]
+            k = next((k for k in ("k_primal", "k_dual", "k_eval", "k_compact", "copyBuffer")
+                      if k in name), None)
+            if k is None:
+                continue
+            per.setdefault(k, {}).setdefault(r["Counter_Name"], []).append(
+                float(r["Counter_Value"]))
+    lines = ["| run | kernel | dispatches | read GB | write GB | 128 B reads | 64 B reads | "
+             "32 B reads | L2 hits | L2 misses |", "|---|---|---|---|---|---|---|---|---|---|"]
+    for label, per in runs.items():
+        for k, cs in sorted(per.items()):
+            def mean(c):
+                v = cs.get(c + "_sum") or cs.get(c)
+                return sum(v) / len(v) if v else None
+            r32, r64, r128 = (mean(f"TCC_EA0_RDREQ_{b}") for b in ("32B", "64B", "128B"))
+            wr, wr64 = mean("TCC_EA0_WRREQ"), mean("TCC_EA0_WRREQ_64B")
+            rd = None if r128 is None else 32 * (r32 or 0) + 64 * (r64 or 0) + 128 * r128
+            wb = None if wr is None else 64 * wr64 + 32 * (wr - wr64)
+            n = max(len(v) for v in cs.values())
+
+            def f(v, scale=1e9, nd=3):
+                return "-" if v is None else f"{v / scale:.{nd}f}"
+            lines.append(f"| {label} | {k} | {n} | {f(rd)} | {f(wb)} | {f(r128, 1e6, 2)}M | "
+                         f"{f(r64, 1e6, 2)}M | {f(r32, 1e6, 2)}M | {f(mean('TCC_HIT'), 1e6, 2)}M | "
+                         f"{f(mean('TCC_MISS'), 1e6, 2)}M |")
+    print("\n".join(lines))
+
+
 def run_pmc_summary(args):
     """Per-dispatch HBM traffic of one kernel from two rocprofv3 --pmc runs of
     the same command (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch), over the
@@ -362,7 +405,7 @@ def serve_leg(args, rates, seconds):
     ctxs, roots = [], []
     for b in range(args.serve_bases):
         inst = make_cfg5(base=b, m=m, n=n)
-        alloc = P.TorchAllocator(0) if args.serve_torch_alloc else None
+        alloc = None if args.serve_hip_alloc else P.TorchAllocator(0)
         ctx = P.Context.from_instance(inst, device=0, precision=prec, max_batch=args.serve_cols,
                                       eval_every=args.serve_eval, allocator=alloc)
         ctx.set_batch(deltas([BASE], [0], [0.0]))
@@ -451,7 +494,7 @@ def serve_leg(args, rates, seconds):
                        "precision": args.serve_prec, "max_columns_per_base": args.serve_cols,
                        "eval_every": args.serve_eval, "result_rows": args.serve_rows,
                        "budget_gib": round(budget / (1 << 30), 2) if budget else None,
-                       "torch_allocator": bool(args.serve_torch_alloc),
+                       "torch_allocator": not args.serve_hip_alloc,
                        "seconds_per_rate": seconds,
                        "drain_cap_s": args.serve_drain_s},
             "rates": lines}
@@ -1255,7 +1298,7 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--workload", default="line",
                     choices=["line", "fsb2", "sweep", "copy", "serve", "obbt", "mixed",
-                             "structured", "pmc-summary", "trace-summary"])
+                             "structured", "pmc-summary", "pmc-table", "trace-summary"])
     ap.add_argument("--trace-dir", help="rocprofv3 --kernel-trace --stats output folder")
     ap.add_argument("--trace-solves", default="6,7,8")
     ap.add_argument("--trace-out", default=None)
@@ -1269,6 +1312,7 @@ def main():
                     help="1-based solves (k_begin_solve dispatches) whose launches count")
     ap.add_argument("--pmc-out", default=None)
     ap.add_argument("--pmc-command", default="")
+    ap.add_argument("--pmc-table", help="pmc-table: label=DIR,... of rocprofv3 --pmc runs")
     ap.add_argument("--obbt-vars", type=int, default=128)
     ap.add_argument("--obbt-iters", type=int, default=100000)
     ap.add_argument("--mixed-lps", type=int, default=1000)
@@ -1299,8 +1343,9 @@ def main():
     ap.add_argument("--serve-budget-gb", type=float, default=-0.75,
                     help="serve: device-memory budget of all bases: GiB if > 0, a fraction of "
                          "the device's memory if < 0, none if 0")
-    ap.add_argument("--serve-torch-alloc", action="store_true",
-                    help="serve: the contexts' device memory from PyTorch's caching allocator")
+    ap.add_argument("--serve-hip-alloc", action="store_true",
+                    help="serve: the contexts' device memory from hipMalloc instead of PyTorch's "
+                         "caching allocator (growing and trimming storage then allocates anew)")
     ap.add_argument("--serve-drain-s", type=float, default=20.0,
                     help="serve: longest drain after the arrivals stop")
     ap.add_argument("--sweep-m", type=int, default=200000)
@@ -1359,6 +1404,9 @@ def main():
         return
     if args.workload == "pmc-summary":
         run_pmc_summary(args)
+        return
+    if args.workload == "pmc-table":
+        run_pmc_table(args)
         return
     if args.workload == "obbt":
         run_obbt(args)

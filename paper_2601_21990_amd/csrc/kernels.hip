@@ -485,10 +485,14 @@ __device__ __forceinline__ YRow load_yrow(const EvalArgs<T>& a, int32_t i, int32
     const size_t e = (size_t)i * a.ld + s;
     return YRow{(double)a.Yt[e], (double)a.DY[e], (double)a.Y0[e], a.rl[i], a.ru[i]};
 }
-// x side of column i: g = (A' y~)_i, h = (A' dy)_i, pdy = (A' Pi_B[l,u](dy))_i
+// x side of column i: g = (A' y~)_i, h = (A' dy)_i, pdy = (A' Pi_B[l,u](dy))_i.
+// tv receives the row's terms; callers add them to the running sums.  No
+// product here is fused into a later addition, so every kernel that adds the
+// same terms in the same order gets the same sums.
 __device__ __forceinline__ void finish_xrow(const XRow& r, double g, double h, double pdy,
                                             int32_t varkind, const double* dval, int32_t s,
-                                            int32_t i, double* acc) {
+                                            int32_t i, double* tv) {
+#pragma clang fp contract(off)
     const VarData d = var_data(varkind, dval, s, i, r.c, r.lo, r.hi);
     const double rc = barrier(-d.c - g, d.lo, d.hi);        // r~ (reduced cost at y~)
     const double rk = barrier(-d.c - (g - h), d.lo, d.hi);  // r at y^k = y~ - dy
@@ -497,30 +501,33 @@ __device__ __forceinline__ void finish_xrow(const XRow& r, double g, double h, d
     const double ea = r.xt - r.x0;
     const double pr = pdy + dr;
     const double rx = r.dx - recession(r.dx, d.lo, d.hi);
-    acc[0] += r.dx * r.dx;
-    acc[1] += d.c * r.xt;
-    acc[2] += support1(rc, d.lo, d.hi);
-    acc[3] += dres * dres;
-    acc[4] += d.c * d.c;
-    acc[5] += ea * ea;
-    acc[6] += support1(dr, d.lo, d.hi);
-    acc[7] += pr * pr;
-    acc[8] += d.c * r.dx;
-    acc[9] += rx * rx;
+    tv[0] = r.dx * r.dx;
+    tv[1] = d.c * r.xt;
+    tv[2] = support1(rc, d.lo, d.hi);
+    tv[3] = dres * dres;
+    tv[4] = d.c * d.c;
+    tv[5] = ea * ea;
+    tv[6] = support1(dr, d.lo, d.hi);
+    tv[7] = pr * pr;
+    tv[8] = d.c * r.dx;
+    tv[9] = rx * rx;
 }
-// y side of row i: ax = (A x~)_i, adx = (A dx)_i
-__device__ __forceinline__ void finish_yrow(const YRow& r, double ax, double adx, double* acc) {
+// y side of row i: ax = (A x~)_i, adx = (A dx)_i; tv as above (terms 8, 9 zero)
+__device__ __forceinline__ void finish_yrow(const YRow& r, double ax, double adx, double* tv) {
+#pragma clang fp contract(off)
     const double pres = ax - clampd(ax, r.l, r.u);
     const double ea = r.yt - r.y0;
     const double ra = adx - recession(adx, r.l, r.u);
-    acc[0] += r.dy * r.dy;
-    acc[1] += r.dy * adx;
-    acc[2] += support1(r.yt, r.l, r.u);
-    acc[3] += pres * pres;
-    acc[4] += ax * ax;
-    acc[5] += ea * ea;
-    acc[6] += support1(barrier(r.dy, r.l, r.u), r.l, r.u);
-    acc[7] += ra * ra;
+    tv[0] = r.dy * r.dy;
+    tv[1] = r.dy * adx;
+    tv[2] = support1(r.yt, r.l, r.u);
+    tv[3] = pres * pres;
+    tv[4] = ax * ax;
+    tv[5] = ea * ea;
+    tv[6] = support1(barrier(r.dy, r.l, r.u), r.l, r.u);
+    tv[7] = ra * ra;
+    tv[8] = 0.0;
+    tv[9] = 0.0;
 }
 
 template <typename T>
@@ -569,7 +576,10 @@ __global__ __launch_bounds__(256) void k_eval(EvalArgs<T> a) {
             }
             double g = 0.0, h = 0.0, pdy = 0.0;
             auto advance = [&]() {
-                finish_xrow(cur, g, h, pdy, varkind, a.sl.dval, s, i, acc);
+                double tv[NTERM];
+                finish_xrow(cur, g, h, pdy, varkind, a.sl.dval, s, i, tv);
+#pragma unroll
+                for (int q = 0; q < NTERM; ++q) acc[q] += tv[q];
                 g = h = pdy = 0.0;
                 ++i;
                 cur = nxt;
@@ -624,7 +634,10 @@ __global__ __launch_bounds__(256) void k_eval(EvalArgs<T> a) {
             }
             double ax = 0.0, adx = 0.0;                       // (A x~)_i, (A dx)_i
             auto advance = [&]() {
-                finish_yrow(cur, ax, adx, acc);
+                double tv[NTERM];
+                finish_yrow(cur, ax, adx, tv);
+#pragma unroll
+                for (int q = 0; q < NTERM; ++q) acc[q] += tv[q];
                 ax = adx = 0.0;
                 ++i;
                 cur = nxt;
@@ -678,6 +691,90 @@ __global__ __launch_bounds__(256) void k_eval(EvalArgs<T> a) {
             const double v = ((red[0][q][lane] + red[1][q][lane]) + red[2][q][lane]) + red[3][q][lane];
             out[(size_t)q * a.ld] = v;
         }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Evaluation for narrow batches: the same sums as k_eval, bit for bit, with
+// the lanes spread over rows instead of slots.  A block owns one panel and one
+// slot (blockIdx.y); wave w owns the same rows [p0 + w*pw, p0 + (w+1)*pw) as in
+// k_eval.  Its lanes take 64 consecutive rows at a time and compute each row's
+// products (CSR order) and terms in parallel; lane q then adds term q of those
+// rows in row order, continuing the wave's running sum, so every addition of
+// k_eval happens in the same order.  The four wave sums are combined as there.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_eval_narrow(EvalArgs<T> a) {
+    __shared__ double terms[4][64][NTERM + 1];
+    __shared__ double red[4][NTERM];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int32_t s = blockIdx.y;
+    const bool xside = (int32_t)blockIdx.x < a.npx;
+    const int32_t panel = xside ? blockIdx.x : blockIdx.x - a.npx;
+    const int32_t pw = xside ? a.pw_x : a.pw_y;
+    const int32_t rows = xside ? a.n : a.m;
+
+    if (!a.full && a.g->quiet) return;
+    const int32_t ncols = min(a.ncols, a.g->n_cols);
+    if (s >= ncols) return;
+    const SlotKey key = a.sl.key[s];
+    const int32_t t = a.g->t0 + a.it;
+    if (!(a.full || t == key.t_anchor || t >= key.t_end)) return;
+    const int32_t varkind = key.varkind;
+    const int32_t r0 = panel * 4 * pw + wave * pw;
+    const int32_t r1 = min(r0 + pw, rows);
+    double acc = 0.0;                      // lane q < NTERM: the wave's running sum of term q
+    // every wave makes the same number of trips (pw is the same for all four),
+    // so the block's barriers match even where a wave's rows run out
+    for (int32_t off = 0; off < pw; off += 64) {
+        const int32_t rb = r0 + off;
+        const int32_t i = rb + lane;
+        if (i < r1) {
+            double tq[NTERM];
+            if (xside) {
+                const XRow r = load_xrow(a, i, s);
+                double g = 0.0, h = 0.0, pdy = 0.0;
+                const int32_t kb = a.t_rp[i], ke = a.t_rp[i + 1];
+                for (int32_t k = kb; k < ke; ++k) {
+                    const int32_t j = a.t_ci[k];
+                    const double v = (double)a.t_v[k];
+                    const size_t f = (size_t)j * a.ld + s;
+                    const double yv = (double)a.Yt[f], dv = (double)a.DY[f];
+                    g = fma(v, yv, g);
+                    h = fma(v, dv, h);
+                    pdy = fma(v, barrier(dv, a.rl[j], a.ru[j]), pdy);
+                }
+                finish_xrow(r, g, h, pdy, varkind, a.sl.dval, s, i, tq);
+            } else {
+                const YRow r = load_yrow(a, i, s);
+                double ax = 0.0, adx = 0.0;
+                const int32_t kb = a.a_rp[i], ke = a.a_rp[i + 1];
+                for (int32_t k = kb; k < ke; ++k) {
+                    const int32_t j = a.a_ci[k];
+                    const double v = (double)a.a_v[k];
+                    const size_t f = (size_t)j * a.ld + s;
+                    ax = fma(v, (double)a.Xt[f], ax);
+                    adx = fma(v, (double)a.DX[f], adx);
+                }
+                finish_yrow(r, ax, adx, tq);
+            }
+#pragma unroll
+            for (int q = 0; q < NTERM; ++q) terms[wave][lane][q] = tq[q];
+        }
+        __syncthreads();
+        if (lane < NTERM) {
+            const int32_t cnt = min(64, r1 - rb);
+            for (int32_t j = 0; j < cnt; ++j) acc += terms[wave][j][lane];
+        }
+        __syncthreads();
+    }
+    if (lane < NTERM) red[wave][lane] = acc;
+    __syncthreads();
+    if (wave == 0 && lane < NTERM) {
+        double* out = (xside ? a.part_x : a.part_y) + (size_t)panel * NTERM * a.ld + s;
+        const double v = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+        out[(size_t)lane * a.ld] = v;
     }
 }
 
@@ -1350,8 +1447,17 @@ hipError_t launch_dual(const StepArgs<T>& a, int lanes, int vec, hipStream_t s) 
     return launch_step<T, false>(a, lanes, vec, s);
 }
 
+// batches this narrow use k_eval_narrow (rows across the lanes)
+constexpr int32_t EVAL_NARROW_COLS = 16;
+
 template <typename T>
 hipError_t launch_eval(const EvalArgs<T>& a, hipStream_t s) {
+    if (a.ncols <= EVAL_NARROW_COLS) {
+        const dim3 grid(a.npx + a.npy, a.ncols);
+        if (grid.x == 0 || grid.y == 0) return hipSuccess;
+        hipLaunchKernelGGL(k_eval_narrow<T>, grid, dim3(256), 0, s, a);
+        return hipGetLastError();
+    }
     const dim3 grid(a.npx + a.npy, (a.ncols + 63) / 64);
     if (grid.x == 0 || grid.y == 0) return hipSuccess;
     hipLaunchKernelGGL(k_eval<T>, grid, dim3(256), 0, s, a);
