@@ -945,7 +945,7 @@ def headline(args):
     ctx.set_kernel_timing(False)
     log(f"event-timed pass: {event_dt:.4f}s")
     names = ["primal: A'Y + primal step", "dual: A Xbar + dual step", "evaluation",
-             "control, restarts and compaction"]
+             "control, restarts and compaction", "persistent tail"]
     dom = 0 if total_ms[0] >= total_ms[1] else 1
     nl = max(counts[dom], 1)
     avg_ms = total_ms[dom] / nl
@@ -965,7 +965,7 @@ def headline(args):
                 "avg_launch_us": round(avg_ms * 1e3, 3), "launches": int(counts[dom])}
     kernel_ms = {names[k]: {"launches": int(counts[k]), "total_ms": round(total_ms[k], 3),
                             "avg_us": round(total_ms[k] / max(counts[k], 1) * 1e3, 2)}
-                 for k in range(4)}
+                 for k in range(5)}
 
     # with host-memory inputs and outputs (every LP's x~ and y~ copied back)
     w_host = np.full(B, root_w)
@@ -1174,7 +1174,8 @@ def fsb2_leg(args, with_cpu=False):
     # roofline of the dominant kernel: algorithmic bytes are affine in the live
     # column count of a launch, so their sum over the timed launches follows from
     # the launch count and the summed live columns
-    names = ["primal: A'Y + primal step", "dual: A Xbar + dual step", "evaluation", "control"]
+    names = ["primal: A'Y + primal step", "dual: A Xbar + dual step", "evaluation", "control",
+             "persistent tail"]
     dom = 0 if total_ms[0] >= total_ms[1] else 1
     nl = max(counts[dom], 1)
     avg_ms = total_ms[dom] / nl
@@ -1191,7 +1192,7 @@ def fsb2_leg(args, with_cpu=False):
                 "full_width_bytes": int(fused_bytes(dom, m, n, nnz, B, 8, 8)),
                 "mean_live_columns": round(cols[dom] / nl, 2),
                 "avg_launch_us": round(avg_ms * 1e3, 3), "launches": int(counts[dom])}
-    kernel_us = {names[k]: round(total_ms[k] / max(counts[k], 1) * 1e3, 3) for k in range(4)}
+    kernel_us = {names[k]: round(total_ms[k] / max(counts[k], 1) * 1e3, 3) for k in range(5)}
 
     # the same steps with the inputs in host memory and the results copied back
     # to it (the boundary accepts either): the rate including the host transfers

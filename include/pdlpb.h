@@ -122,7 +122,12 @@ typedef struct pdlpb_options {
                                  solver then works on D_r A D_c (the stopping and infeasibility tests
                                  measure the scaled LP); changes, warm starts and results stay in the
                                  caller's coordinates */
-    int32_t reserved[2];
+    int32_t tail_cols;        /* persistent tail: once at most this many LPs of a batch still run
+                                 (0, the default, disables), on a matrix of at most 65536 nonzeros and
+                                 with the per-LP restart scope, pdlpb_solve finishes them in one
+                                 launch with one workgroup per LP, which computes the same bits as
+                                 the batched kernels (Section 5: the LPs left once most have stopped) */
+    int32_t reserved;
     /* Device memory of the context.  Both NULL (default): hipMalloc / hipFree.
        Otherwise both set: every device buffer the context holds comes from
        dev_alloc(bytes, alloc_user), which returns a pointer on the context's
@@ -405,12 +410,12 @@ int pdlpb_get_step_size(const pdlpb_ctx* ctx, double* eta, double* norm_a);
  * Kernel timing.  While enabled, pdlpb_solve runs without graph replay and
  * brackets every launch of the fused SpMM kernels with HIP events on the
  * context's stream.  pdlpb_kernel_times reports, per kind
- * (0: A'Y + primal step, 1: A X + dual step, 2: evaluation, 3: control),
- * the number of launches and their summed duration in milliseconds since the
- * last reset.
+ * (0: A'Y + primal step, 1: A X + dual step, 2: evaluation, 3: control,
+ * restarts and compaction, 4: persistent tail), the number of launches and
+ * their summed duration in milliseconds since the last reset.
  */
 int pdlpb_set_kernel_timing(pdlpb_ctx* ctx, int32_t enable);
-int pdlpb_kernel_times(pdlpb_ctx* ctx, int64_t counts[4], double total_ms[4]);
+int pdlpb_kernel_times(pdlpb_ctx* ctx, int64_t counts[5], double total_ms[5]);
 
 /*
  * For the same launches: the live LP columns each launch processed, summed
@@ -419,7 +424,7 @@ int pdlpb_kernel_times(pdlpb_ctx* ctx, int64_t counts[4], double total_ms[4]);
  * kernels are affine in the column count, so with the launch count this gives
  * their exact sum.  EINVAL for a NULL cols.
  */
-int pdlpb_kernel_columns(pdlpb_ctx* ctx, int64_t cols[4]);
+int pdlpb_kernel_columns(pdlpb_ctx* ctx, int64_t cols[5]);
 
 /* Bytes of device memory held by the context. */
 int64_t pdlpb_device_bytes(const pdlpb_ctx* ctx);

@@ -54,6 +54,12 @@ __device__ __forceinline__ double barrier(double v, double lo, double hi) {
     if (isinf(hi) && hi > 0.0) v = fmin(v, 0.0);
     return v;
 }
+// The same projection from the row's code (1: lo = -inf, 2: hi = +inf).
+__device__ __forceinline__ double barrier_code(double v, int32_t code) {
+    if (code & 1) v = fmax(v, 0.0);
+    if (code & 2) v = fmin(v, 0.0);
+    return v;
+}
 // Projection onto the recession cone of [lo, hi] (Section 4, infeasibility
 // detection): free if both ends are infinite, >= 0 if only hi = +inf, <= 0 if
 // only lo = -inf, 0 if both are finite.
@@ -244,6 +250,38 @@ __device__ __forceinline__ void row_product(const StepArgs<T>& a, const RowOps<T
     }
 }
 
+// The per-coordinate updates of one iteration, shared by every kernel that
+// iterates, so that each computes the same bits.  No product is fused into a
+// later addition.
+// Primal (eq:main-iterate, first line; eq:mainiter): x^k rebuilt from the
+// stored reflection z and the anchor x0, x~ = Pi_[lo,hi](x^k - tau (c + g)),
+// reflection 2 x~ - x^k.
+template <typename T>
+__device__ __forceinline__ void primal_point(int32_t k, T z, T x0, T tau, double c, double lo,
+                                             double hi, T g, T& xk, T& xt, T& xbar) {
+#pragma clang fp contract(off)
+    xk = (k == 0) ? x0 : T(double(k) / double(k + 1)) * z + x0 / T(k + 1);
+    xt = clampt<T>(xk - tau * (T(c) + g), T(lo), T(hi));
+    xbar = T(2) * xt - xk;
+}
+// Dual (eq:main-iterate, second line, Moreau form; eq:mainiter): q = y^k / sigma + v,
+// y~ = sigma (q - Pi_[l,u](q)), y^{k+1} = wa (2 y~ - y^k) + y0 / wb.
+template <typename T>
+__device__ __forceinline__ void dual_point(T yk, T y0, T sg, T wa, T wb, T l, T u, T v, T& yt,
+                                           T& ynext) {
+#pragma clang fp contract(off)
+    const T q = yk / sg + v;
+    yt = sg * (q - clampt<T>(q, l, u));
+    ynext = wa * (T(2) * yt - yk) + y0 / wb;
+}
+// Last Halpern iterate of a stopped LP, rebuilt from its reflection and anchor:
+// a xbar + x0 / kp2 with a = (k+1)/(k+2), kp2 = k + 2 of its last iteration.
+template <typename T>
+__device__ __forceinline__ T halpern_last(double a, int32_t kp2, T xbar, T x0) {
+#pragma clang fp contract(off)
+    return T(a * (double)xbar + (double)x0 / (double)kp2);
+}
+
 // Halpern weights of eq:mainiter for inner index k: (k+1)/(k+2) and 1/(k+2).
 __device__ __forceinline__ double halpern_a(int32_t k) { return double(k + 1) / double(k + 2); }
 
@@ -346,10 +384,9 @@ __global__ __launch_bounds__(256) void k_primal(StepArgs<T> a) {
             const size_t e = (size_t)r * a.ld + s;
             const VarData d = var_data(varkind[v], a.sl.dval, s, r, o.c, o.lo, o.hi);
             const int32_t k = kk[v];
-            const T x0 = o.z0[v];
-            const T xk = (k == 0) ? x0 : T(double(k) / double(k + 1)) * o.z[v] + x0 / T(k + 1);
-            const T xt = clampt<T>(xk - tau[v] * (T(d.c) + acc[v]), T(d.lo), T(d.hi));
-            a.Z[e] = T(2) * xt - xk;
+            T xk, xt, xbar;
+            primal_point<T>(k, o.z[v], o.z0[v], tau[v], d.c, d.lo, d.hi, acc[v], xk, xt, xbar);
+            a.Z[e] = xbar;
             if (keep[v]) {
                 a.Zt[e] = xt;
                 a.DZ[e] = xt - xk;
@@ -438,11 +475,9 @@ __global__ __launch_bounds__(256) void k_dual(StepArgs<T> a) {
             if (!live[v]) continue;
             const size_t e = (size_t)r * a.ld + s0 + v;
             const T yk = o.z[v];
-            const T y0 = o.z0[v];
-            const T sg = sig[v];
-            const T q = yk / sg + acc[v];
-            const T yt = sg * (q - clampt<T>(q, l, u));
-            a.Z[e] = wa[v] * (T(2) * yt - yk) + y0 / wb[v];
+            T yt, yn;
+            dual_point<T>(yk, o.z0[v], sig[v], wa[v], wb[v], l, u, acc[v], yt, yn);
+            a.Z[e] = yn;
             if (keep[v]) {
                 a.Zt[e] = yt;
                 a.DZ[e] = yt - yk;
@@ -591,7 +626,8 @@ __global__ __launch_bounds__(256) void k_eval(EvalArgs<T> a) {
             };
             for (int32_t k0 = kbeg; k0 < kend; k0 += CH) {
                 int32_t jj[CH];
-                double vv[CH], yv[CH], dv[CH], lv[CH], uv[CH];
+                double vv[CH], yv[CH], dv[CH];
+                int32_t cd[CH];
 #pragma unroll
                 for (int u = 0; u < CH; ++u) {
                     jj[u] = 0;
@@ -607,8 +643,7 @@ __global__ __launch_bounds__(256) void k_eval(EvalArgs<T> a) {
                         const size_t f = (size_t)jj[u] * a.ld + s;
                         yv[u] = (double)a.Yt[f];
                         dv[u] = (double)a.DY[f];
-                        lv[u] = a.rl[jj[u]];
-                        uv[u] = a.ru[jj[u]];
+                        cd[u] = a.rcode[jj[u]];
                     }
                 }
 #pragma unroll
@@ -617,7 +652,7 @@ __global__ __launch_bounds__(256) void k_eval(EvalArgs<T> a) {
                         while (k0 + u >= ke) advance();
                         g = fma(vv[u], yv[u], g);
                         h = fma(vv[u], dv[u], h);
-                        pdy = fma(vv[u], barrier(dv[u], lv[u], uv[u]), pdy);
+                        pdy = fma(vv[u], barrier_code(dv[u], cd[u]), pdy);
                     }
                 }
             }
@@ -807,6 +842,7 @@ __global__ __launch_bounds__(256) void k_reduce(ControlArgs a) {
 // ---------------------------------------------------------------------------
 __device__ bool restart_due(double r, double r0, double r_prev, int32_t k, int32_t t,
                             const ControlArgs& a) {
+#pragma clang fp contract(off)
     if (r <= a.beta_s * r0) return true;
     if (r_prev >= 0.0 && r <= a.beta_n * r0 && r > r_prev) return true;
     if ((double)k > a.beta_a * (double)t) return true;
@@ -817,6 +853,7 @@ __device__ bool restart_due(double r, double r0, double r_prev, int32_t k, int32
 // on the displacement sums of one LP: returns the status, or 0.
 __device__ int32_t infeasible(const double* sx, const double* sy, int32_t ld, int32_t s,
                               double eps) {
+#pragma clang fp contract(off)
     const double phi = sx[6 * ld + s] + sy[6 * ld + s];     // phi_[l,u](dy) + phi_box(dr)
     if (phi < 0.0 && sqrt(sx[7 * ld + s]) <= eps * fabs(phi)) return PDLPB_STATUS_PRIMAL_INFEASIBLE;
     const double cdx = sx[8 * ld + s];
@@ -827,6 +864,7 @@ __device__ int32_t infeasible(const double* sx, const double* sy, int32_t ld, in
 
 // new primal weight by exponential smoothing (Section 4), d from the anchor displacement
 __device__ double smoothed_weight(double w, double dx2, double dy2, const ControlArgs& a) {
+#pragma clang fp contract(off)
     const double dxn = sqrt(dx2), dyn = sqrt(dy2);
     const double num = a.pw_literal ? dxn : dyn;
     const double den = a.pw_literal ? dyn : dxn;
@@ -845,6 +883,90 @@ __device__ void restart_slot(const Slots& sl, int32_t s, SlotKey& key, SlotCtl& 
     key.flags |= SLOT_FRESH;
     if (cl.restarts < RESTART_LOG) rlog[cl.restarts] = t - sl.t_start[s];
     cl.restarts += 1;
+}
+
+// Tests of one running LP at an evaluation (Section 4): the fixed-point
+// residual, the stopping measures of eq:stopping, the infeasibility tests, the
+// iteration limit and, with the per-LP restart scope, the restart rules and the
+// primal-weight update.  sx / sy hold the LP's evaluation sums at
+// [q * ld + s].  Returns 1 when the LP stopped (its status is recorded and its
+// slot marked for retirement), else 0; *r_out and *resid_out give the residual
+// and whether it was taken, for the batch-average scope.  No product is fused
+// into a later addition, so every kernel calling this computes the same bits.
+__device__ int32_t control_slot(const ControlArgs& a, bool full, int32_t s, SlotKey& st,
+                                SlotCtl& cl, int32_t* rlog, const double* sx, const double* sy,
+                                int32_t ld, int32_t t, double eta, bool per_lp, double* r_out,
+                                bool* resid_out) {
+#pragma clang fp contract(off)
+    // sx, sy point at the slot's sums: term q at [q * ld]
+    const double tol = cl.tol;
+    const int32_t k = t - st.t_anchor;
+    const bool final_now = (t >= st.t_end);
+    const double dx2 = sx[0 * ld], cx = sx[1 * ld], phix = sx[2 * ld];
+    const double dres2 = sx[3 * ld], c2 = sx[4 * ld];
+    const double dy2 = sy[0 * ld], cross = sy[1 * ld], phiy = sy[2 * ld];
+    const double pres2 = sy[3 * ld], ax2 = sy[4 * ld];
+    const double w = cl.w;
+    // fixed-point residual r(z) = ||T(z) - z||_M (eq:residual, cross-term sign per option)
+    const double q2 = (w / eta) * dx2 + (1.0 / (eta * w)) * dy2 + 2.0 * a.cross_sign * cross;
+    const double r = isfinite(q2) ? sqrt(fmax(q2, 0.0)) : NAN;
+    // stopping measures (eq:stopping)
+    const double phis = phix + phiy;
+    const double gap = isfinite(phis) ? fabs(cx + phis) / (1.0 + fabs(cx) + fabs(phis)) : INFINITY;
+    const double pri = sqrt(pres2) / (1.0 + sqrt(ax2));
+    const double dua = sqrt(dres2) / (1.0 + sqrt(c2));
+    double rel = fmax(gap, fmax(pri, dua));
+    if (isnan(gap) || isnan(pri) || isnan(dua)) rel = NAN;
+    // an LP that ran out of budget before this evaluation is evaluated at its final z~
+    const bool at_eval = (t <= st.t_end);
+    const bool full_here = full && at_eval;
+    const bool resid_here = at_eval && (full || k == 0);
+    // order of the tests: NaN, stopping, infeasibility, iteration limit
+    const double eps_inf = a.infeas_tol < 0.0 ? tol : a.infeas_tol;
+    const int32_t infeas = (full_here && eps_inf > 0.0) ? infeasible(sx, sy, ld, 0, eps_inf) : 0;
+    int32_t status = PDLPB_STATUS_RUNNING;
+    if ((resid_here && !isfinite(r)) || (full_here && !isfinite(rel))) {
+        status = PDLPB_STATUS_NUMERICAL_ERROR;
+    } else if (full_here && gap <= tol && pri <= tol && dua <= (a.dual_tol < 0.0 ? tol : a.dual_tol)) {
+        status = PDLPB_STATUS_OPTIMAL;
+    } else if (infeas) {
+        status = infeas;
+    } else if (final_now) {
+        status = PDLPB_STATUS_ITERATION_LIMIT;
+    }
+    if (full || k == 0 || final_now) {   // the evaluation computed this LP's sums
+        cl.kkt[0] = gap; cl.kkt[1] = pri; cl.kkt[2] = dua; cl.kkt[3] = rel;
+        cl.obj = cx;
+        cl.dobj = -phis;
+    }
+    *r_out = r;
+    *resid_out = resid_here;
+    if (status != PDLPB_STATUS_RUNNING) {
+        const int32_t t_last = t < st.t_end ? t : st.t_end;
+        cl.status = status;
+        cl.t_last = t_last;
+        cl.k_last = t_last - st.t_anchor;
+        cl.iters = t_last - a.sl.t_start[s] + 1;
+        st.flags = SLOT_RETIRE;
+        return 1;
+    }
+    if (!per_lp) return 0;
+    if (k == 0) {
+        if (resid_here) {
+            cl.r0 = r;
+            cl.r_prev = r;
+        }
+        st.flags &= ~SLOT_FRESH;
+    } else if (full) {
+        if (restart_due(r, cl.r0, cl.r_prev, k, t - a.sl.t_start[s], a)) {
+            restart_slot(a.sl, s, st, cl, rlog, t, eta,
+                         smoothed_weight(w, sx[5 * ld], sy[5 * ld], a));
+            cl.r_prev = -1.0;
+        } else {
+            cl.r_prev = r;
+        }
+    }
+    return 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -887,76 +1009,15 @@ __global__ __launch_bounds__(1024) void k_control(ControlArgs a) {
             }
             st.flags &= ~SLOT_NEW;
         }
-        const double tol = cl.tol;
-        const int32_t k = t - st.t_anchor;
-        const bool final_now = (t >= st.t_end);
-        const double dx2 = sx[0 * a.ld + s], cx = sx[1 * a.ld + s], phix = sx[2 * a.ld + s];
-        const double dres2 = sx[3 * a.ld + s], c2 = sx[4 * a.ld + s];
-        const double dy2 = sy[0 * a.ld + s], cross = sy[1 * a.ld + s], phiy = sy[2 * a.ld + s];
-        const double pres2 = sy[3 * a.ld + s], ax2 = sy[4 * a.ld + s];
-        const double w = cl.w;
-        // fixed-point residual r(z) = ||T(z) - z||_M (eq:residual, cross-term sign per option)
-        const double q2 = (w / eta) * dx2 + (1.0 / (eta * w)) * dy2 + 2.0 * a.cross_sign * cross;
-        const double r = isfinite(q2) ? sqrt(fmax(q2, 0.0)) : NAN;
-        // stopping measures (eq:stopping)
-        const double phis = phix + phiy;
-        const double gap = isfinite(phis) ? fabs(cx + phis) / (1.0 + fabs(cx) + fabs(phis)) : INFINITY;
-        const double pri = sqrt(pres2) / (1.0 + sqrt(ax2));
-        const double dua = sqrt(dres2) / (1.0 + sqrt(c2));
-        double rel = fmax(gap, fmax(pri, dua));
-        if (isnan(gap) || isnan(pri) || isnan(dua)) rel = NAN;
-        // an LP that ran out of budget before this launch is evaluated at its final z~
-        const bool at_eval = (t <= st.t_end);
-        const bool full_here = a.full && at_eval;
-        const bool resid_here = at_eval && (a.full || k == 0);
-        // order of the tests: NaN, stopping, infeasibility, iteration limit
-        const double eps_inf = a.infeas_tol < 0.0 ? tol : a.infeas_tol;
-        const int32_t infeas =
-            (full_here && eps_inf > 0.0) ? infeasible(sx, sy, a.ld, s, eps_inf) : 0;
-        int32_t status = PDLPB_STATUS_RUNNING;
-        if ((resid_here && !isfinite(r)) || (full_here && !isfinite(rel))) {
-            status = PDLPB_STATUS_NUMERICAL_ERROR;
-        } else if (full_here && gap <= tol && pri <= tol && dua <= (a.dual_tol < 0.0 ? tol : a.dual_tol)) {
-            status = PDLPB_STATUS_OPTIMAL;
-        } else if (infeas) {
-            status = infeas;
-        } else if (final_now) {
-            status = PDLPB_STATUS_ITERATION_LIMIT;
-        }
-        if (a.full || k == 0 || final_now) {   // the evaluation computed this LP's sums
-            cl.kkt[0] = gap; cl.kkt[1] = pri; cl.kkt[2] = dua; cl.kkt[3] = rel;
-            cl.obj = cx;
-            cl.dobj = -phis;
-        }
-        if (status != PDLPB_STATUS_RUNNING) {
-            const int32_t t_last = t < st.t_end ? t : st.t_end;
-            cl.status = status;
-            cl.t_last = t_last;
-            cl.k_last = t_last - st.t_anchor;
-            cl.iters = t_last - a.sl.t_start[s] + 1;
-            st.flags = SLOT_RETIRE;
+        double r = 0.0;
+        bool resid_here = false;
+        if (control_slot(a, a.full != 0, s, st, cl, a.rlog + (size_t)lp * RESTART_LOG, sx + s,
+                          sy + s, a.ld, t, eta, !a.batch_avg, &r, &resid_here))
             continue;
-        }
         my_active += 1;
-        if (a.batch_avg) {
-            if (resid_here) {            // indexed by LP: the average adds LPs in LP order
-                sh_r[lp] = r;
-                sh_n[lp] = 1;
-            }
-        } else if (k == 0) {
-            if (resid_here) {
-                cl.r0 = r;
-                cl.r_prev = r;
-            }
-            st.flags &= ~SLOT_FRESH;
-        } else if (a.full) {
-            if (restart_due(r, cl.r0, cl.r_prev, k, t - a.sl.t_start[s], a)) {
-                restart_slot(a.sl, s, st, cl, a.rlog + (size_t)lp * RESTART_LOG, t, eta,
-                             smoothed_weight(w, sx[5 * a.ld + s], sy[5 * a.ld + s], a));
-                cl.r_prev = -1.0;
-            } else {
-                cl.r_prev = r;
-            }
+        if (a.batch_avg && resid_here) {   // indexed by LP: the average adds LPs in LP order
+            sh_r[lp] = r;
+            sh_n[lp] = 1;
         }
         if ((st.flags & SLOT_FRESH) || st.t_end <= t + 1) my_fresh += 1;
     }
@@ -1150,7 +1211,7 @@ __global__ __launch_bounds__(256) void k_compact(int32_t n, int32_t m, int32_t l
                 if (xside) {
                     const T xb = B.b[0][e], x0 = B.b[1][e], xt = B.b[2][e];
                     res_t[lane][rr] = xt;
-                    res_h[lane][rr] = T(re.a * (double)xb + (double)x0 / (double)re.kp2);
+                    res_h[lane][rr] = halpern_last<T>(re.a, re.kp2, xb, x0);
                 } else {
                     res_t[lane][rr] = B.b[6][e];   // y~
                     res_h[lane][rr] = B.b[4][e];   // Halpern iterate y^{k+1}
@@ -1203,6 +1264,251 @@ __global__ __launch_bounds__(256) void k_compact(int32_t n, int32_t m, int32_t l
         }
         __syncthreads();
         if (threadIdx.x == 0) g->n_cols = g->n_cols_next;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Persistent tail (Section 5: the LPs still running once most of a batch has
+// stopped).  One workgroup of 1024 threads owns one running LP and runs its
+// remaining iterations, evaluations, restarts and stop inside one launch, so a
+// narrow tail pays no launch boundaries.  It follows the batched schedule
+// exactly: blocks of C iterations from the next block base t0; an evaluation
+// of a fresh restart cycle (or of a last iteration) after the first iteration
+// of a block, a full evaluation after the last.  The LP's column is copied to
+// contiguous vectors first.  Every quantity is computed as the batched kernels
+// compute it -- the same row products in CSR order, the same coordinate
+// updates, the same evaluation chains of pw rows per wave, panel sums
+// ((c0 + c1) + c2) + c3, lane-strided panel sums and butterfly, and the same
+// control -- so the LP's results are those of the batched path, bit for bit.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct TailVec {
+    T *xb, *x0, *xt, *dx, *y, *y0, *yt, *dy;
+};
+
+// One side of an evaluation: chain sums (chain c = 4 panel + wave, rows
+// [c pw, (c + 1) pw)), panel values, then the 64-lane reduction of term q
+// into sums[q].  Waves take 64 / pw chains at once when pw < 64.
+template <typename T>
+__device__ void tail_eval_side(const TailArgs<T>& a, const TailVec<T>& v, int32_t s,
+                               int32_t varkind, bool xside, double* chain, double* panel,
+                               double* sums, double (*terms)[NTERM + 1], int lane, int wave,
+                               int tid) {
+    constexpr int NW = TAIL_THREADS / 64;
+    const int32_t np = xside ? a.npx : a.npy;
+    const int32_t pw = xside ? a.pw_x : a.pw_y;
+    const int32_t rows = xside ? a.n : a.m;
+    const int32_t nchains = 4 * np;
+    const int32_t per = pw < 64 ? pw : 64;        // rows of one chain in one trip
+    const int32_t G = 64 / per;                   // chains of a wave in one trip
+    const int32_t trips = pw < 64 ? 1 : pw / 64;
+    const int32_t npair = G * NTERM;
+    for (int32_t cb = 0; cb < nchains; cb += NW * G) {
+        const int32_t c0 = cb + wave * G;
+        double acc[3] = {0.0, 0.0, 0.0};          // pairs lane, lane + 64, lane + 128
+        for (int32_t tr = 0; tr < trips; ++tr) {
+            const int32_t c = c0 + lane / per;
+            const int32_t i = c * pw + tr * 64 + lane % per;
+            const int32_t r1 = min((c + 1) * pw, rows);
+            if (c < nchains && i < r1) {
+                double tq[NTERM];
+                if (xside) {
+                    const XRow r{(double)v.xt[i], (double)v.dx[i], (double)v.x0[i], a.c[i], a.xl[i],
+                                 a.xu[i]};
+                    double g = 0.0, h = 0.0, pdy = 0.0;
+                    for (int32_t k = a.t_rp[i]; k < a.t_rp[i + 1]; ++k) {
+                        const int32_t j = a.t_ci[k];
+                        const double w = (double)a.t_v[k];
+                        const double yv = (double)v.yt[j], dv = (double)v.dy[j];
+                        g = fma(w, yv, g);
+                        h = fma(w, dv, h);
+                        pdy = fma(w, barrier(dv, a.rl[j], a.ru[j]), pdy);
+                    }
+                    finish_xrow(r, g, h, pdy, varkind, a.sl.dval, s, i, tq);
+                } else {
+                    const YRow r{(double)v.yt[i], (double)v.dy[i], (double)v.y0[i], a.rl[i], a.ru[i]};
+                    double ax = 0.0, adx = 0.0;
+                    for (int32_t k = a.a_rp[i]; k < a.a_rp[i + 1]; ++k) {
+                        const int32_t j = a.a_ci[k];
+                        const double w = (double)a.a_v[k];
+                        ax = fma(w, (double)v.xt[j], ax);
+                        adx = fma(w, (double)v.dx[j], adx);
+                    }
+                    finish_yrow(r, ax, adx, tq);
+                }
+#pragma unroll
+                for (int q = 0; q < NTERM; ++q) terms[wave * 64 + lane][q] = tq[q];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int pi = 0; pi < 3; ++pi) {
+                const int32_t pair = lane + 64 * pi;
+                if (pair < npair) {
+                    const int32_t cl = pair / NTERM, q = pair % NTERM;
+                    const int32_t c2 = c0 + cl;
+                    if (c2 < nchains) {
+                        const int32_t rb = c2 * pw + tr * 64;
+                        const int32_t cnt = min(per, min((c2 + 1) * pw, rows) - rb);
+                        for (int32_t jj = 0; jj < cnt; ++jj) acc[pi] += terms[wave * 64 + cl * per + jj][q];
+                    }
+                }
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int pi = 0; pi < 3; ++pi) {
+            const int32_t pair = lane + 64 * pi;
+            if (pair < npair) {
+                const int32_t c2 = c0 + pair / NTERM;
+                if (c2 < nchains) chain[(size_t)c2 * NTERM + pair % NTERM] = acc[pi];
+            }
+        }
+    }
+    __syncthreads();
+    // panel values, term-major: panel[q np + p]
+    for (int32_t idx = tid; idx < np * NTERM; idx += TAIL_THREADS) {
+        const int32_t p = idx / NTERM, q = idx % NTERM;
+        const double* cc = chain + (size_t)4 * p * NTERM + q;
+        panel[(size_t)q * np + p] = ((cc[0] + cc[NTERM]) + cc[2 * NTERM]) + cc[3 * NTERM];
+    }
+    __syncthreads();
+    // term q: lane l adds panels l, l + 64, ... in order, then a butterfly
+    for (int32_t q = wave; q < NTERM; q += NW) {
+        double acc = 0.0;
+        for (int32_t i = lane; i < np; i += 64) acc += panel[(size_t)q * np + i];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+        if (lane == 0) sums[q] = acc;
+    }
+    __syncthreads();
+}
+
+template <typename T>
+__global__ __launch_bounds__(TAIL_THREADS) void k_tail(TailArgs<T> a) {
+    __shared__ double terms[TAIL_THREADS][NTERM + 1];
+    __shared__ int32_t sh_stop;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int tid = threadIdx.x;
+    const int32_t s = blockIdx.x;
+    if (s >= a.ncols) return;
+    SlotKey* keyp = a.sl.key + s;
+    if (!(keyp->flags & SLOT_ACTIVE)) return;
+    const int32_t n = a.n, m = a.m, ld = a.ld;
+    TailVec<T> v;
+    v.xb = a.work + (size_t)s * (4 * (size_t)n + 4 * (size_t)m);
+    v.x0 = v.xb + n;
+    v.xt = v.x0 + n;
+    v.dx = v.xt + n;
+    v.y = v.dx + n;
+    v.y0 = v.y + m;
+    v.yt = v.y0 + m;
+    v.dy = v.yt + m;
+    for (int32_t i = tid; i < n; i += TAIL_THREADS) {
+        const size_t e = (size_t)i * ld + s;
+        v.xb[i] = a.blk[0][e];
+        v.x0[i] = a.blk[1][e];
+        v.xt[i] = a.blk[2][e];
+        v.dx[i] = a.blk[3][e];
+    }
+    for (int32_t i = tid; i < m; i += TAIL_THREADS) {
+        const size_t e = (size_t)i * ld + s;
+        v.y[i] = a.blk[4][e];
+        v.y0[i] = a.blk[5][e];
+        v.yt[i] = a.blk[6][e];
+        v.dy[i] = a.blk[7][e];
+    }
+    double* ws = a.wsum + (size_t)s * tail_sum_doubles(a.npx, a.npy);
+    double* chain_x = ws;
+    double* chain_y = chain_x + (size_t)4 * a.npx * NTERM;
+    double* panel_x = chain_y + (size_t)4 * a.npy * NTERM;
+    double* panel_y = panel_x + (size_t)a.npx * NTERM;
+    double* sums = panel_y + (size_t)a.npy * NTERM;   // x side [0, NTERM), y side [NTERM, 2 NTERM)
+    const double eta = a.g->eta;
+    int32_t t0 = a.g->t0;
+    const int32_t lp = a.sl.lp[s];
+    __syncthreads();
+    for (;;) {
+        bool stopped = false;
+        for (int32_t it = 1; it <= a.C && !stopped; ++it) {
+            const int32_t t = t0 + it;
+            const SlotKey key = *keyp;
+            const int32_t k = t - key.t_anchor;
+            if ((key.flags & SLOT_ACTIVE) && t <= key.t_end) {
+                // the evaluation after this iteration reads z~ and the displacement
+                const bool keep = t == key.t_end || it == a.C || (it == 1 && k == 0);
+                const T tau = T(a.sl.tau[s]);
+                for (int32_t i = tid; i < n; i += TAIL_THREADS) {
+                    T acc = T(0);
+                    for (int32_t q = a.t_rp[i]; q < a.t_rp[i + 1]; ++q)
+                        acc = fma(a.t_v[q], v.y[a.t_ci[q]], acc);
+                    const VarData d = var_data(key.varkind, a.sl.dval, s, i, a.c[i], a.xl[i], a.xu[i]);
+                    T xk, xt, xbar;
+                    primal_point<T>(k, v.xb[i], v.x0[i], tau, d.c, d.lo, d.hi, acc, xk, xt, xbar);
+                    v.xb[i] = xbar;
+                    if (keep) {
+                        v.xt[i] = xt;
+                        v.dx[i] = xt - xk;
+                    }
+                }
+                __syncthreads();
+                const T sg = T(a.sl.sigma[s]);
+                const T wa = T(halpern_a(k)), wb = T(k + 2);
+                for (int32_t i = tid; i < m; i += TAIL_THREADS) {
+                    T acc = T(0);
+                    for (int32_t q = a.a_rp[i]; q < a.a_rp[i + 1]; ++q)
+                        acc = fma(a.a_v[q], v.xb[a.a_ci[q]], acc);
+                    const T yk = v.y[i];
+                    T yt, yn;
+                    dual_point<T>(yk, v.y0[i], sg, wa, wb, T(a.rl[i]), T(a.ru[i]), acc, yt, yn);
+                    v.y[i] = yn;
+                    if (keep) {
+                        v.yt[i] = yt;
+                        v.dy[i] = yt - yk;
+                    }
+                }
+                __syncthreads();
+            }
+            if (it != 1 && it != a.C) continue;
+            const bool full = it == a.C;
+            // between full evaluations only a fresh cycle or a last iteration is evaluated
+            if (!(full || t == key.t_anchor || t >= key.t_end)) continue;
+            tail_eval_side<T>(a, v, s, key.varkind, true, chain_x, panel_x, sums, terms, lane, wave, tid);
+            tail_eval_side<T>(a, v, s, key.varkind, false, chain_y, panel_y, sums + NTERM, terms, lane,
+                              wave, tid);
+            if (tid == 0) {
+                double r = 0.0;
+                bool rh = false;
+                sh_stop = control_slot(a.ca, full, s, *keyp, a.ctl[lp],
+                                       a.rlog + (size_t)lp * RESTART_LOG, sums, sums + NTERM, 1, t,
+                                       eta, true, &r, &rh);
+            }
+            __syncthreads();
+            stopped = sh_stop != 0;
+            if (full && !stopped && (keyp->flags & SLOT_FRESH)) {
+                // restart: anchor and dual iterate become z~ (Section 4)
+                for (int32_t i = tid; i < n; i += TAIL_THREADS) v.x0[i] = v.xt[i];
+                for (int32_t i = tid; i < m; i += TAIL_THREADS) {
+                    const T yt = v.yt[i];
+                    v.y0[i] = yt;
+                    v.y[i] = yt;
+                }
+                __syncthreads();
+            }
+        }
+        if (stopped) break;
+        t0 += a.C;
+    }
+    // results: z~ and the last Halpern iterate (as the compaction copies them)
+    const int32_t kl = a.ctl[lp].k_last;
+    const double ha = double(kl + 1) / double(kl + 2);
+    for (int32_t i = tid; i < n; i += TAIL_THREADS) {
+        a.res[0][(size_t)lp * n + i] = v.xt[i];
+        a.res[1][(size_t)lp * n + i] = halpern_last<T>(ha, kl + 2, v.xb[i], v.x0[i]);
+    }
+    for (int32_t i = tid; i < m; i += TAIL_THREADS) {
+        a.res[2][(size_t)lp * m + i] = v.yt[i];
+        a.res[3][(size_t)lp * m + i] = v.y[i];
     }
 }
 
@@ -1464,6 +1770,13 @@ hipError_t launch_eval(const EvalArgs<T>& a, hipStream_t s) {
     return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_tail(const TailArgs<T>& a, hipStream_t s) {
+    if (a.ncols <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_tail<T>, dim3(a.ncols), dim3(TAIL_THREADS), 0, s, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_reduce(const ControlArgs& a, hipStream_t s) {
     const int64_t pairs = (int64_t)2 * NTERM * a.ncols;
     if (pairs == 0) return hipSuccess;
@@ -1591,6 +1904,8 @@ template hipError_t launch_primal<double>(const StepArgs<double>&, int, int, hip
 template hipError_t launch_primal<float>(const StepArgs<float>&, int, int, hipStream_t);
 template hipError_t launch_dual<double>(const StepArgs<double>&, int, int, hipStream_t);
 template hipError_t launch_dual<float>(const StepArgs<float>&, int, int, hipStream_t);
+template hipError_t launch_tail<double>(const TailArgs<double>&, hipStream_t);
+template hipError_t launch_tail<float>(const TailArgs<float>&, hipStream_t);
 template hipError_t launch_eval<double>(const EvalArgs<double>&, hipStream_t);
 template hipError_t launch_eval<float>(const EvalArgs<float>&, hipStream_t);
 template hipError_t launch_compact<double>(int32_t, int32_t, int32_t, int32_t, double* const*,

@@ -97,6 +97,7 @@ struct pdlpb_ctx {
     double *a_ev64 = nullptr, *t_ev64 = nullptr;
     float *a_ev32 = nullptr, *t_ev32 = nullptr;
     double *c = nullptr, *xl = nullptr, *xu = nullptr, *rl = nullptr, *ru = nullptr;
+    int8_t* rcode = nullptr;        // per row: 1 if l = -inf, | 2 if u = +inf
 
     // host copies used by set_batch (the caller's bounds, before any scaling)
     std::vector<double> h_xl, h_xu;
@@ -135,6 +136,9 @@ struct pdlpb_ctx {
     size_t cap_stage = 0;
     double* stage = nullptr;        // staging for warm starts and results
     double* pow_buf = nullptr;      // power iteration scratch
+    void* tail_work = nullptr;      // persistent tail: contiguous iterates of each LP
+    double* tail_sum = nullptr;     //   and its evaluation chain and panel sums
+    int32_t tail_cap = 0;           //   LPs the two buffers hold
     int32_t* h_pinned = nullptr;    // n_active read-back
 
     // state
@@ -198,9 +202,9 @@ struct pdlpb_ctx {
 
     // kernel timing
     bool timing = false;
-    int64_t t_counts[4] = {0, 0, 0, 0};
-    double t_ms[4] = {0, 0, 0, 0};
-    int64_t t_cols[4] = {0, 0, 0, 0};   // live LP columns summed over the timed launches
+    int64_t t_counts[5] = {0, 0, 0, 0, 0};
+    double t_ms[5] = {0, 0, 0, 0, 0};
+    int64_t t_cols[5] = {0, 0, 0, 0, 0};   // live LP columns summed over the timed launches
     int32_t cur_cols = 0;               // live LP columns of the launches being enqueued
     std::vector<int32_t> rec_cols;      // cur_cols at each timed launch (by event pair)
     std::vector<hipEvent_t> ev;
@@ -473,6 +477,7 @@ EvalArgs<T> eval_args(pdlpb_ctx* x, int32_t it, int32_t full) {
     a.Xt = b[2]; a.DX = b[3]; a.X0 = b[1];
     a.Yt = b[6]; a.DY = b[7]; a.Y0 = b[5];
     a.c = x->c; a.xl = x->xl; a.xu = x->xu; a.rl = x->rl; a.ru = x->ru;
+    a.rcode = x->rcode;
     a.sl = x->sl;
     a.g = x->g;
     a.pw_x = x->pw_x; a.pw_y = x->pw_y; a.npx = x->npx; a.npy = x->npy;
@@ -700,6 +705,57 @@ int read_counts(pdlpb_ctx* x, int32_t* n_active, int32_t* n_cols) {
     return PDLPB_OK;
 }
 
+// largest matrix whose LPs the persistent tail iterates with one workgroup each
+constexpr int64_t TAIL_MAX_NNZ = 65536;
+
+bool tail_applies(const pdlpb_ctx* x, int32_t n_cols) {
+    return x->opt.tail_cols > 0 && n_cols > 0 && n_cols <= x->opt.tail_cols &&
+           x->nnz <= TAIL_MAX_NNZ && x->opt.restart_scope == PDLPB_RESTART_PER_LP && !x->serving;
+}
+
+// Finish the running LPs of slots [0, n_cols) with the persistent tail kernel
+// (one workgroup each), from the next block base on the device.
+template <typename T>
+int run_tail(pdlpb_ctx* x, int32_t n_cols, std::vector<std::pair<int, int>>* rec) {
+    const size_t esz = sizeof(T);
+    if (n_cols > x->tail_cap) {
+        x->release(x->tail_work, 0);
+        x->release(x->tail_sum, 0);
+        x->tail_cap = 0;
+        const int32_t cap = x->opt.tail_cols;
+        HIP_TRY(x, x->alloc(&x->tail_work, (size_t)cap * (4 * (size_t)x->n + 4 * (size_t)x->m) * esz));
+        HIP_TRY(x, x->alloc(&x->tail_sum, (size_t)cap * tail_sum_doubles(x->npx, x->npy) * sizeof(double)));
+        x->tail_cap = cap;
+    }
+    TailArgs<T> a{};
+    a.n = x->n; a.m = x->m; a.ld = x->ld; a.C = x->opt.eval_every; a.ncols = n_cols;
+    a.a_rp = x->a_rp; a.a_ci = x->a_ci; a.t_rp = x->t_rp; a.t_ci = x->t_ci;
+    if constexpr (sizeof(T) == 8) {
+        a.a_v = reinterpret_cast<const T*>(x->a_v64);
+        a.t_v = reinterpret_cast<const T*>(x->t_v64);
+    } else {
+        a.a_v = reinterpret_cast<const T*>(x->a_v32);
+        a.t_v = reinterpret_cast<const T*>(x->t_v32);
+    }
+    for (int b = 0; b < 8; ++b) a.blk[b] = static_cast<T*>(x->blk[b]);
+    for (int b = 0; b < 4; ++b) a.res[b] = static_cast<T*>(x->res[b]);
+    a.c = x->c; a.xl = x->xl; a.xu = x->xu; a.rl = x->rl; a.ru = x->ru;
+    a.sl = x->sl; a.ctl = x->ctl; a.rlog = x->rlog; a.g = x->g;
+    a.ca = control_args(x, 0, 1, 0);
+    a.pw_x = x->pw_x; a.pw_y = x->pw_y; a.npx = x->npx; a.npy = x->npy;
+    a.work = static_cast<T*>(x->tail_work);
+    a.wsum = x->tail_sum;
+    int idx = -1;
+    if (rec) {
+        x->cur_cols = n_cols;
+        idx = timed_begin(x, 4, *rec);
+    }
+    HIP_TRY(x, launch_tail<T>(a, x->stream));
+    if (rec && idx >= 0) (void)hipEventRecord(x->ev[2 * idx + 1], x->stream);
+    HIP_TRY(x, hipStreamSynchronize(x->stream));
+    return PDLPB_OK;
+}
+
 template <typename T>
 int run_solve(pdlpb_ctx* x, double tol, int32_t max_iters) {
     x->live = shape_cols(x, x->n_run0);
@@ -751,6 +807,20 @@ int run_solve(pdlpb_ctx* x, double tol, int32_t max_iters) {
     } drain{x, &in_flight};
     for (int64_t ep = 0; n_active > 0; ++ep) {
         if (launched > max_epochs + 1) return x->fail(PDLPB_EDEVICE, "solve did not terminate");
+        if (tail_applies(x, n_cols)) {
+            if (in_flight) {
+                // the counts of the block running ahead decide first
+                rc = wait_counts(x, in_slot, &n_active, &n_cols);
+                if (rc) return rc;
+                in_flight = false;
+                continue;
+            }
+            // the few LPs left run to their stop in one launch
+            rc = run_tail<T>(x, n_cols, prec);
+            if (rc) return rc;
+            if (prec) harvest();
+            return PDLPB_OK;
+        }
         // shape the launches for the live columns (compaction shrinks them)
         const int32_t shape = shape_cols(x, n_cols);
         x->cur_cols = n_cols;
@@ -1235,6 +1305,7 @@ void pdlpb_default_options(pdlpb_options* o) {
     o->tile_lanes = 0;
     o->tile_vec = 0;
     o->autotune = 1;
+    o->tail_cols = 0;
 }
 
 int pdlpb_create(pdlpb_ctx** out, int32_t m, int32_t n, int64_t nnz, const int64_t* row_ptr,
@@ -1279,6 +1350,7 @@ int pdlpb_create(pdlpb_ctx** out, int32_t m, int32_t n, int64_t nnz, const int64
         return bad("tile_lanes must be 0 or a power of two in [1, 64]");
     if (o.tile_vec != 0 && o.tile_vec != 1 && o.tile_vec != 2 && o.tile_vec != 4)
         return bad("tile_vec must be 0, 1, 2 or 4");
+    if (o.tail_cols < 0 || o.tail_cols > 64) return bad("tail_cols must be in [0, 64]");
     if ((o.dev_alloc == nullptr) != (o.dev_free == nullptr))
         return bad("dev_alloc and dev_free must both be set or both be NULL");
     // CSR structure
@@ -1448,6 +1520,13 @@ int pdlpb_create(pdlpb_ctx** out, int32_t m, int32_t n, int64_t nnz, const int64
     if ((e = up(&x->xu, u, (size_t)n)) != hipSuccess) return dev_fail(e, "upload u");
     if ((e = up(&x->rl, rl.data(), (size_t)m)) != hipSuccess) return dev_fail(e, "upload rows");
     if ((e = up(&x->ru, ru.data(), (size_t)m)) != hipSuccess) return dev_fail(e, "upload rows");
+    {
+        std::vector<int8_t> code(m);
+        for (int32_t i = 0; i < m; ++i)
+            code[i] = (int8_t)((std::isinf(rl[i]) && rl[i] < 0 ? 1 : 0) |
+                               (std::isinf(ru[i]) && ru[i] > 0 ? 2 : 0));
+        if ((e = up(&x->rcode, code.data(), (size_t)m)) != hipSuccess) return dev_fail(e, "upload rows");
+    }
     if ((e = x->alloc(&x->g, sizeof(Globals))) != hipSuccess) return dev_fail(e, "alloc");
 
     x->h_xl.assign(l_in, l_in + n);
@@ -2430,7 +2509,7 @@ int pdlpb_get_scaling(const pdlpb_ctx* x, double* dr, double* dc) {
 int pdlpb_set_kernel_timing(pdlpb_ctx* x, int32_t enable) {
     if (!x) return PDLPB_EINVAL;
     x->timing = enable != 0;
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < 5; ++q) {
         x->t_counts[q] = 0;
         x->t_ms[q] = 0.0;
         x->t_cols[q] = 0;
@@ -2438,16 +2517,16 @@ int pdlpb_set_kernel_timing(pdlpb_ctx* x, int32_t enable) {
     return PDLPB_OK;
 }
 
-int pdlpb_kernel_columns(pdlpb_ctx* x, int64_t cols[4]) {
+int pdlpb_kernel_columns(pdlpb_ctx* x, int64_t cols[5]) {
     if (!x) return PDLPB_EINVAL;
     if (!cols) return x->fail(PDLPB_EINVAL, "cols is NULL");
-    for (int q = 0; q < 4; ++q) cols[q] = x->t_cols[q];
+    for (int q = 0; q < 5; ++q) cols[q] = x->t_cols[q];
     return PDLPB_OK;
 }
 
-int pdlpb_kernel_times(pdlpb_ctx* x, int64_t counts[4], double total_ms[4]) {
+int pdlpb_kernel_times(pdlpb_ctx* x, int64_t counts[5], double total_ms[5]) {
     if (!x) return PDLPB_EINVAL;
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < 5; ++q) {
         if (counts) counts[q] = x->t_counts[q];
         if (total_ms) total_ms[q] = x->t_ms[q];
     }

@@ -143,6 +143,7 @@ struct EvalArgs {
     const int32_t* t_rp; const int32_t* t_ci; const T* t_v;    // A' (n x m)
     const T *Xt, *DX, *X0, *Yt, *DY, *Y0;
     const double *c, *xl, *xu, *rl, *ru;
+    const int8_t* rcode;     // per row of A: 1 if its lower bound is -inf, | 2 if its upper is +inf
     Slots sl;
     const Globals* g;        // live column count
     int32_t pw_x, pw_y;      // rows per wave on the x side / y side
@@ -178,6 +179,32 @@ struct ControlArgs {
     double dual_tol;         // eps of the dual-feasibility test; < 0: the stopping tolerance
 };
 
+// Persistent tail: one workgroup per running LP iterates it to its stop.
+constexpr int32_t TAIL_THREADS = 512;
+
+template <typename T>
+struct TailArgs {
+    int32_t n, m, ld, C;
+    int32_t ncols;             // workgroups: slots [0, ncols)
+    const int32_t* a_rp; const int32_t* a_ci; const T* a_v;    // A (m x n)
+    const int32_t* t_rp; const int32_t* t_ci; const T* t_v;    // A' (n x m)
+    T* blk[8];                 // Xbar, X0, Xt, DX, Y, Y0, Yt, DY (row-major, stride ld)
+    T* res[4];                 // Rx, Rxi (B x n), Ry, Ryi (B x m): LP-major results
+    const double *c, *xl, *xu, *rl, *ru;
+    Slots sl;
+    SlotCtl* ctl;
+    int32_t* rlog;
+    const Globals* g;          // t0 (base of the next block of C iterations) and eta
+    ControlArgs ca;            // stopping, infeasibility and restart parameters
+    int32_t pw_x, pw_y, npx, npy;
+    T* work;                   // per workgroup: Xbar, X0, Xt, DX (n each), Y, Y0, Yt, DY (m each)
+    double* wsum;              // per workgroup: tail_sum_doubles(npx, npy) doubles
+};
+__host__ __device__ inline size_t tail_sum_doubles(int32_t npx, int32_t npy) {
+    // chain sums (4 per panel), panel values, the evaluation sums
+    return (size_t)(4 * (npx + npy) + (npx + npy) + 2) * NTERM;
+}
+
 // ---- launchers (kernels.hip) ---------------------------------------------------
 // Each returns hipSuccess or the launch error.
 template <typename T>
@@ -188,6 +215,12 @@ template <typename T>
 hipError_t launch_eval(const EvalArgs<T>& a, hipStream_t s);
 hipError_t launch_reduce(const ControlArgs& a, hipStream_t s);
 hipError_t launch_control(const ControlArgs& a, hipStream_t s);
+// Iterate every running LP of slots [0, ncols) to its stop with one workgroup
+// each, computing the same bits as the batched kernels (same products in CSR
+// order, same evaluation chains and reduction trees, same control), and copy
+// its results to the result blocks.
+template <typename T>
+hipError_t launch_tail(const TailArgs<T>& a, hipStream_t s);
 
 // Fill the dense blocks of a new batch.  Warm vectors: mode 0 none, 1 shared
 // (xw: n, yw: m), 2 per LP (xw: ncols*n, yw: ncols*m, LP-major).

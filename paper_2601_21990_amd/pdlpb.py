@@ -64,7 +64,7 @@ class Options(C.Structure):
                 ("tile_lanes", C.c_int32), ("tile_vec", C.c_int32),
                 ("autotune", C.c_int32), ("reserved_pad", C.c_int32),
                 ("dual_tol", C.c_double), ("max_blocks", C.c_int32),
-                ("scaling", C.c_int32), ("reserved", C.c_int32 * 2),
+                ("scaling", C.c_int32), ("tail_cols", C.c_int32), ("reserved", C.c_int32),
                 ("dev_alloc", C.c_void_p), ("dev_free", C.c_void_p),
                 ("alloc_user", C.c_void_p)]
 
@@ -494,12 +494,12 @@ class Context:
         self._check(lib.pdlpb_set_kernel_timing(self._h, int(bool(enable))))
 
     def kernel_times(self):
-        cnt = (C.c_int64 * 4)()
-        ms = (C.c_double * 4)()
+        cnt = (C.c_int64 * 5)()
+        ms = (C.c_double * 5)()
         self._check(lib.pdlpb_kernel_times(self._h, cnt, ms))
         return list(cnt), list(ms)
 
     def kernel_columns(self):
-        cols = (C.c_int64 * 4)()
+        cols = (C.c_int64 * 5)()
         self._check(lib.pdlpb_kernel_columns(self._h, cols))
         return list(cols)
