@@ -1092,7 +1092,8 @@ def fsb2_leg(args, with_cpu=False):
     m, n, nnz = inst.m, inst.n, inst.nnz
     log(f"instance m={m} n={n} nnz={nnz}")
 
-    opts = dict(device=0, use_graphs=args.graphs, tile_lanes=args.tile_lanes, tile_vec=args.tile_vec,
+    opts = dict(device=0, use_graphs=args.graphs, tail_cols=args.tail_cols,
+                tile_lanes=args.tile_lanes, tile_vec=args.tile_vec,
                 eval_every=args.eval_every)
     ctx = P.Context.from_instance(inst, **opts)
     # the one-LP-at-a-time leg runs at the evaluation interval that suits one LP best
@@ -1370,6 +1371,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-obbt", action="store_true")
     ap.add_argument("--no-fsb2", action="store_true")
+    ap.add_argument("--tail-cols", type=int, default=0,
+                    help="persistent tail once at most this many LPs of a batch run (0: off)")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)

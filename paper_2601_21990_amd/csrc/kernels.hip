@@ -1383,10 +1383,36 @@ __device__ void tail_eval_side(const TailArgs<T>& a, const TailVec<T>& v, int32_
     __syncthreads();
 }
 
+// One row's product with a vector held in LDS, in CSR order: the first eight
+// entries from the 8-wide ELL copy (no wait for the row pointers), the rest of
+// a longer row from the CSR arrays.
+template <typename T>
+__device__ __forceinline__ T tail_row(const int32_t* eci, const T* ev, const int32_t* rp,
+                                      const int32_t* ci, const T* av, int32_t i, const T* sv) {
+    int32_t j[8];
+    T w[8];
+    const int4* q = reinterpret_cast<const int4*>(eci + (size_t)i * 8);
+    const int4 j0 = q[0], j1 = q[1];
+    j[0] = j0.x; j[1] = j0.y; j[2] = j0.z; j[3] = j0.w;
+    j[4] = j1.x; j[5] = j1.y; j[6] = j1.z; j[7] = j1.w;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) w[u] = ev[(size_t)i * 8 + u];
+    T acc = T(0);
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+        if (j[u] >= 0) acc = fma(w[u], sv[j[u]], acc);
+    if (j[7] >= 0) {
+        const int32_t ke = rp[i + 1];
+        for (int32_t k = rp[i] + 8; k < ke; ++k) acc = fma(av[k], sv[ci[k]], acc);
+    }
+    return acc;
+}
+
 template <typename T>
 __global__ __launch_bounds__(TAIL_THREADS) void k_tail(TailArgs<T> a) {
     __shared__ double terms[TAIL_THREADS][NTERM + 1];
     __shared__ int32_t sh_stop;
+    extern __shared__ double tail_lds[];   // Xbar (n) and Y (m), the vectors the products gather
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int tid = threadIdx.x;
@@ -1396,12 +1422,13 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(TailArgs<T> a) {
     if (!(keyp->flags & SLOT_ACTIVE)) return;
     const int32_t n = a.n, m = a.m, ld = a.ld;
     TailVec<T> v;
-    v.xb = a.work + (size_t)s * (4 * (size_t)n + 4 * (size_t)m);
-    v.x0 = v.xb + n;
+    T* const wbase = a.work + (size_t)s * (4 * (size_t)n + 4 * (size_t)m);
+    v.xb = reinterpret_cast<T*>(tail_lds);
+    v.x0 = wbase + n;
     v.xt = v.x0 + n;
     v.dx = v.xt + n;
-    v.y = v.dx + n;
-    v.y0 = v.y + m;
+    v.y = v.xb + n;
+    v.y0 = v.dx + n + m;
     v.yt = v.y0 + m;
     v.dy = v.yt + m;
     for (int32_t i = tid; i < n; i += TAIL_THREADS) {
@@ -1439,9 +1466,7 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(TailArgs<T> a) {
                 const bool keep = t == key.t_end || it == a.C || (it == 1 && k == 0);
                 const T tau = T(a.sl.tau[s]);
                 for (int32_t i = tid; i < n; i += TAIL_THREADS) {
-                    T acc = T(0);
-                    for (int32_t q = a.t_rp[i]; q < a.t_rp[i + 1]; ++q)
-                        acc = fma(a.t_v[q], v.y[a.t_ci[q]], acc);
+                    const T acc = tail_row<T>(a.t_e8ci, a.t_e8v, a.t_rp, a.t_ci, a.t_v, i, v.y);
                     const VarData d = var_data(key.varkind, a.sl.dval, s, i, a.c[i], a.xl[i], a.xu[i]);
                     T xk, xt, xbar;
                     primal_point<T>(k, v.xb[i], v.x0[i], tau, d.c, d.lo, d.hi, acc, xk, xt, xbar);
@@ -1455,9 +1480,7 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(TailArgs<T> a) {
                 const T sg = T(a.sl.sigma[s]);
                 const T wa = T(halpern_a(k)), wb = T(k + 2);
                 for (int32_t i = tid; i < m; i += TAIL_THREADS) {
-                    T acc = T(0);
-                    for (int32_t q = a.a_rp[i]; q < a.a_rp[i + 1]; ++q)
-                        acc = fma(a.a_v[q], v.xb[a.a_ci[q]], acc);
+                    const T acc = tail_row<T>(a.a_e8ci, a.a_e8v, a.a_rp, a.a_ci, a.a_v, i, v.xb);
                     const T yk = v.y[i];
                     T yt, yn;
                     dual_point<T>(yk, v.y0[i], sg, wa, wb, T(a.rl[i]), T(a.ru[i]), acc, yt, yn);
@@ -1771,9 +1794,9 @@ hipError_t launch_eval(const EvalArgs<T>& a, hipStream_t s) {
 }
 
 template <typename T>
-hipError_t launch_tail(const TailArgs<T>& a, hipStream_t s) {
+hipError_t launch_tail(const TailArgs<T>& a, size_t dyn_lds, hipStream_t s) {
     if (a.ncols <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_tail<T>, dim3(a.ncols), dim3(TAIL_THREADS), 0, s, a);
+    hipLaunchKernelGGL(k_tail<T>, dim3(a.ncols), dim3(TAIL_THREADS), dyn_lds, s, a);
     return hipGetLastError();
 }
 
@@ -1904,8 +1927,8 @@ template hipError_t launch_primal<double>(const StepArgs<double>&, int, int, hip
 template hipError_t launch_primal<float>(const StepArgs<float>&, int, int, hipStream_t);
 template hipError_t launch_dual<double>(const StepArgs<double>&, int, int, hipStream_t);
 template hipError_t launch_dual<float>(const StepArgs<float>&, int, int, hipStream_t);
-template hipError_t launch_tail<double>(const TailArgs<double>&, hipStream_t);
-template hipError_t launch_tail<float>(const TailArgs<float>&, hipStream_t);
+template hipError_t launch_tail<double>(const TailArgs<double>&, size_t, hipStream_t);
+template hipError_t launch_tail<float>(const TailArgs<float>&, size_t, hipStream_t);
 template hipError_t launch_eval<double>(const EvalArgs<double>&, hipStream_t);
 template hipError_t launch_eval<float>(const EvalArgs<float>&, hipStream_t);
 template hipError_t launch_compact<double>(int32_t, int32_t, int32_t, int32_t, double* const*,

@@ -74,6 +74,8 @@ struct Tile {
 };
 
 constexpr int32_t DEFAULT_MAX_BLOCKS = 16384;
+// largest matrix whose LPs the persistent tail iterates with one workgroup each
+constexpr int64_t TAIL_MAX_NNZ = 65536;
 constexpr int64_t RUN_AHEAD_AFTER = 8;      // blocks of a solve before replays run ahead of the host
 constexpr double RUN_AHEAD_BYTES = 32e6;    // ... and only while one launch moves less than this
 
@@ -136,6 +138,10 @@ struct pdlpb_ctx {
     size_t cap_stage = 0;
     double* stage = nullptr;        // staging for warm starts and results
     double* pow_buf = nullptr;      // power iteration scratch
+    int32_t *a_e8ci = nullptr, *t_e8ci = nullptr;   // persistent tail: first 8 entries of
+    double *a_e8v64 = nullptr, *t_e8v64 = nullptr;   //   every row of A and A' (small
+    float *a_e8v32 = nullptr, *t_e8v32 = nullptr;    //   matrices only; index -1 pads)
+    int64_t lds_max = 0;            // LDS bytes a workgroup may hold on the device
     void* tail_work = nullptr;      // persistent tail: contiguous iterates of each LP
     double* tail_sum = nullptr;     //   and its evaluation chain and panel sums
     int32_t tail_cap = 0;           //   LPs the two buffers hold
@@ -705,12 +711,15 @@ int read_counts(pdlpb_ctx* x, int32_t* n_active, int32_t* n_cols) {
     return PDLPB_OK;
 }
 
-// largest matrix whose LPs the persistent tail iterates with one workgroup each
-constexpr int64_t TAIL_MAX_NNZ = 65536;
+// LDS the tail kernel needs beyond its static arrays: Xbar and Y of its LP
+size_t tail_dyn_lds(const pdlpb_ctx* x) {
+    return ((size_t)x->n + (size_t)x->m) * (x->fp32 ? sizeof(float) : sizeof(double));
+}
 
 bool tail_applies(const pdlpb_ctx* x, int32_t n_cols) {
     return x->opt.tail_cols > 0 && n_cols > 0 && n_cols <= x->opt.tail_cols &&
-           x->nnz <= TAIL_MAX_NNZ && x->opt.restart_scope == PDLPB_RESTART_PER_LP && !x->serving;
+           x->nnz <= TAIL_MAX_NNZ && x->opt.restart_scope == PDLPB_RESTART_PER_LP &&
+           !x->serving && x->a_e8ci && (int64_t)(tail_dyn_lds(x) + TAIL_STATIC_LDS) <= x->lds_max;
 }
 
 // Finish the running LPs of slots [0, n_cols) with the persistent tail kernel
@@ -733,10 +742,16 @@ int run_tail(pdlpb_ctx* x, int32_t n_cols, std::vector<std::pair<int, int>>* rec
     if constexpr (sizeof(T) == 8) {
         a.a_v = reinterpret_cast<const T*>(x->a_v64);
         a.t_v = reinterpret_cast<const T*>(x->t_v64);
+        a.a_e8v = reinterpret_cast<const T*>(x->a_e8v64);
+        a.t_e8v = reinterpret_cast<const T*>(x->t_e8v64);
     } else {
         a.a_v = reinterpret_cast<const T*>(x->a_v32);
         a.t_v = reinterpret_cast<const T*>(x->t_v32);
+        a.a_e8v = reinterpret_cast<const T*>(x->a_e8v32);
+        a.t_e8v = reinterpret_cast<const T*>(x->t_e8v32);
     }
+    a.a_e8ci = x->a_e8ci;
+    a.t_e8ci = x->t_e8ci;
     for (int b = 0; b < 8; ++b) a.blk[b] = static_cast<T*>(x->blk[b]);
     for (int b = 0; b < 4; ++b) a.res[b] = static_cast<T*>(x->res[b]);
     a.c = x->c; a.xl = x->xl; a.xu = x->xu; a.rl = x->rl; a.ru = x->ru;
@@ -750,7 +765,7 @@ int run_tail(pdlpb_ctx* x, int32_t n_cols, std::vector<std::pair<int, int>>* rec
         x->cur_cols = n_cols;
         idx = timed_begin(x, 4, *rec);
     }
-    HIP_TRY(x, launch_tail<T>(a, x->stream));
+    HIP_TRY(x, launch_tail<T>(a, tail_dyn_lds(x), x->stream));
     if (rec && idx >= 0) (void)hipEventRecord(x->ev[2 * idx + 1], x->stream);
     HIP_TRY(x, hipStreamSynchronize(x->stream));
     return PDLPB_OK;
@@ -1404,6 +1419,12 @@ int pdlpb_create(pdlpb_ctx** out, int32_t m, int32_t n, int64_t nnz, const int64
     if (e != hipSuccess) return dev_fail(e, "hipSetDevice");
     e = scratch_setup(o.device);
     if (e != hipSuccess) return dev_fail(e, "hipGetSymbolAddress(scratch)");
+    {
+        int lds = 0;
+        e = hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, o.device);
+        if (e != hipSuccess) return dev_fail(e, "hipDeviceGetAttribute");
+        x->lds_max = lds;
+    }
     if (o.stream) {
         x->stream = static_cast<hipStream_t>(o.stream);
     } else {
@@ -1487,11 +1508,15 @@ int pdlpb_create(pdlpb_ctx** out, int32_t m, int32_t n, int64_t nnz, const int64
     // the rows are longer than 8; others are walked in CSR alone
     {
         auto head = [&](const int32_t* rp, const int32_t* ci, const double* v, int32_t rows,
-                        int32_t* ew_out, int32_t** d_ci, double** d_v64, float** d_v32) {
-            int64_t longer = 0;
-            for (int32_t r = 0; r < rows; ++r) longer += (rp[r + 1] - rp[r]) > 8;
-            const int32_t ew = (longer * 10 > (int64_t)rows) ? 16 : 0;
-            *ew_out = ew;
+                        int32_t* ew_out, int32_t** d_ci, double** d_v64, float** d_v32,
+                        int32_t width) {
+            int32_t ew = width;
+            if (ew == 0) {
+                int64_t longer = 0;
+                for (int32_t r = 0; r < rows; ++r) longer += (rp[r + 1] - rp[r]) > 8;
+                ew = (longer * 10 > (int64_t)rows) ? 16 : 0;
+            }
+            if (ew_out) *ew_out = ew;
             if (ew == 0) return hipSuccess;
             std::vector<int32_t> hci((size_t)rows * ew, -1);
             std::vector<double> hv((size_t)rows * ew, 0.0);
@@ -1509,11 +1534,20 @@ int pdlpb_create(pdlpb_ctx** out, int32_t m, int32_t n, int64_t nnz, const int64
         };
         std::vector<int32_t> h_aci(col_idx, col_idx + nnz);
         if ((e = head(h_arp.data(), h_aci.data(), val, m, &x->a_ew, &x->a_eci, &x->a_ev64,
-                      &x->a_ev32)) != hipSuccess)
+                      &x->a_ev32, 0)) != hipSuccess)
             return dev_fail(e, "upload A");
         if ((e = head(h_trp.data(), h_tci.data(), h_tv.data(), n, &x->t_ew, &x->t_eci,
-                      &x->t_ev64, &x->t_ev32)) != hipSuccess)
+                      &x->t_ev64, &x->t_ev32, 0)) != hipSuccess)
             return dev_fail(e, "upload A'");
+        // 8-wide copies for the persistent tail (small matrices only)
+        if (nnz <= TAIL_MAX_NNZ && m > 0) {
+            if ((e = head(h_arp.data(), h_aci.data(), val, m, nullptr, &x->a_e8ci, &x->a_e8v64,
+                          &x->a_e8v32, 8)) != hipSuccess)
+                return dev_fail(e, "upload A");
+            if ((e = head(h_trp.data(), h_tci.data(), h_tv.data(), n, nullptr, &x->t_e8ci,
+                          &x->t_e8v64, &x->t_e8v32, 8)) != hipSuccess)
+                return dev_fail(e, "upload A'");
+        }
     }
     if ((e = up(&x->c, c, (size_t)n)) != hipSuccess) return dev_fail(e, "upload c");
     if ((e = up(&x->xl, l, (size_t)n)) != hipSuccess) return dev_fail(e, "upload l");

@@ -188,6 +188,8 @@ struct TailArgs {
     int32_t ncols;             // workgroups: slots [0, ncols)
     const int32_t* a_rp; const int32_t* a_ci; const T* a_v;    // A (m x n)
     const int32_t* t_rp; const int32_t* t_ci; const T* t_v;    // A' (n x m)
+    const int32_t* a_e8ci; const T* a_e8v;   // the first 8 entries of every row of A (-1 pads)
+    const int32_t* t_e8ci; const T* t_e8v;   // ... and of A'
     T* blk[8];                 // Xbar, X0, Xt, DX, Y, Y0, Yt, DY (row-major, stride ld)
     T* res[4];                 // Rx, Rxi (B x n), Ry, Ryi (B x m): LP-major results
     const double *c, *xl, *xu, *rl, *ru;
@@ -197,9 +199,12 @@ struct TailArgs {
     const Globals* g;          // t0 (base of the next block of C iterations) and eta
     ControlArgs ca;            // stopping, infeasibility and restart parameters
     int32_t pw_x, pw_y, npx, npy;
-    T* work;                   // per workgroup: Xbar, X0, Xt, DX (n each), Y, Y0, Yt, DY (m each)
+    T* work;                   // per workgroup: Xbar, X0, Xt, DX (n each), Y, Y0, Yt, DY (m each);
+                               // Xbar and Y themselves live in LDS while the LP runs
     double* wsum;              // per workgroup: tail_sum_doubles(npx, npy) doubles
 };
+// LDS of the tail kernel: its evaluation terms (static) and Xbar, Y (dynamic)
+constexpr size_t TAIL_STATIC_LDS = (size_t)TAIL_THREADS * (NTERM + 1) * sizeof(double) + 64;
 __host__ __device__ inline size_t tail_sum_doubles(int32_t npx, int32_t npy) {
     // chain sums (4 per panel), panel values, the evaluation sums
     return (size_t)(4 * (npx + npy) + (npx + npy) + 2) * NTERM;
@@ -220,7 +225,7 @@ hipError_t launch_control(const ControlArgs& a, hipStream_t s);
 // order, same evaluation chains and reduction trees, same control), and copy
 // its results to the result blocks.
 template <typename T>
-hipError_t launch_tail(const TailArgs<T>& a, hipStream_t s);
+hipError_t launch_tail(const TailArgs<T>& a, size_t dyn_lds, hipStream_t s);
 
 // Fill the dense blocks of a new batch.  Warm vectors: mode 0 none, 1 shared
 // (xw: n, yw: m), 2 per LP (xw: ncols*n, yw: ncols*m, LP-major).
