@@ -1088,7 +1088,7 @@ def fsb2_leg(args, with_cpu=False):
 
     dev = torch.device("cuda:0")
     torch.cuda.init()
-    inst = make_cfg2()
+    inst = make_cfg2(m=args.fsb2_m, n=args.fsb2_m * 5 // 2)
     m, n, nnz = inst.m, inst.n, inst.nnz
     log(f"instance m={m} n={n} nnz={nnz}")
 
@@ -1271,8 +1271,8 @@ def fsb2_leg(args, with_cpu=False):
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "strong-branching batch: A 2000x5000 (5 N(0,1) nnz/col), 1000 E + "
-                               f"1000 L rows, box [0,10], B={B} bound changes on {B // 2} fractional "
+        "config": {"workload": f"strong-branching batch: A {m}x{n} (5 N(0,1) nnz/col), {m // 2} E + "
+                               f"{m - m // 2} L rows, box [0,10], B={B} bound changes on {B // 2} fractional "
                                "variables, warm start from the root LP, FP64, tol 1e-4 rel KKT; "
                                f"step i solves draw i mod {len(d_draws)} of the candidates",
                    "m": m, "n": n, "nnz": nnz, "B": B, "tol": 1e-4, "draws": len(d_draws),
@@ -1371,6 +1371,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-obbt", action="store_true")
     ap.add_argument("--no-fsb2", action="store_true")
+    ap.add_argument("--fsb2-m", type=int, default=2000,
+                    help="rows of the strong-branching family's matrix (n = 2.5 m; 2000 is the benchmark's)")
     ap.add_argument("--tail-cols", type=int, default=0,
                     help="persistent tail once at most this many LPs of a batch run (0: off)")
     ap.add_argument("--gpus", type=int, default=1)

@@ -1385,23 +1385,45 @@ __device__ void tail_eval_side(const TailArgs<T>& a, const TailVec<T>& v, int32_
 
 // One row's product with a vector held in LDS, in CSR order: the first eight
 // entries from the 8-wide ELL copy (no wait for the row pointers), the rest of
-// a longer row from the CSR arrays.
+// a longer row from the CSR arrays.  A thread takes TAIL_ROWS rows at a time
+// and issues all of their ELL loads before the first gather, so that several
+// rows' loads are in flight in each of the workgroup's few waves.
+constexpr int TAIL_ROWS = 2;
+
 template <typename T>
-__device__ __forceinline__ T tail_row(const int32_t* eci, const T* ev, const int32_t* rp,
-                                      const int32_t* ci, const T* av, int32_t i, const T* sv) {
+struct TailEll {
     int32_t j[8];
     T w[8];
+};
+
+template <typename T>
+__device__ __forceinline__ void tail_ell_load(const int32_t* eci, const T* ev, int32_t i,
+                                              TailEll<T>& r) {
     const int4* q = reinterpret_cast<const int4*>(eci + (size_t)i * 8);
     const int4 j0 = q[0], j1 = q[1];
-    j[0] = j0.x; j[1] = j0.y; j[2] = j0.z; j[3] = j0.w;
-    j[4] = j1.x; j[5] = j1.y; j[6] = j1.z; j[7] = j1.w;
-#pragma unroll
-    for (int u = 0; u < 8; ++u) w[u] = ev[(size_t)i * 8 + u];
+    r.j[0] = j0.x; r.j[1] = j0.y; r.j[2] = j0.z; r.j[3] = j0.w;
+    r.j[4] = j1.x; r.j[5] = j1.y; r.j[6] = j1.z; r.j[7] = j1.w;
+    HeadVals<T, 8>::load(ev + (size_t)i * 8, r.w);
+}
+
+// The ELL part: padding entries (index -1) leave the sum as it is.
+template <typename T>
+__device__ __forceinline__ T tail_ell_dot(const TailEll<T>& r, const T* sv) {
     T acc = T(0);
 #pragma unroll
-    for (int u = 0; u < 8; ++u)
-        if (j[u] >= 0) acc = fma(w[u], sv[j[u]], acc);
-    if (j[7] >= 0) {
+    for (int u = 0; u < 8; ++u) {
+        const T g = sv[r.j[u] < 0 ? 0 : r.j[u]];
+        const T f = fma(r.w[u], g, acc);
+        acc = r.j[u] >= 0 ? f : acc;
+    }
+    return acc;
+}
+
+// Entries past the first eight, in CSR order.
+template <typename T>
+__device__ __forceinline__ T tail_rest(const TailEll<T>& r, const int32_t* rp, const int32_t* ci,
+                                       const T* av, int32_t i, const T* sv, T acc) {
+    if (r.j[7] >= 0) {
         const int32_t ke = rp[i + 1];
         for (int32_t k = rp[i] + 8; k < ke; ++k) acc = fma(av[k], sv[ci[k]], acc);
     }
@@ -1465,29 +1487,68 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(TailArgs<T> a) {
                 // the evaluation after this iteration reads z~ and the displacement
                 const bool keep = t == key.t_end || it == a.C || (it == 1 && k == 0);
                 const T tau = T(a.sl.tau[s]);
-                for (int32_t i = tid; i < n; i += TAIL_THREADS) {
-                    const T acc = tail_row<T>(a.t_e8ci, a.t_e8v, a.t_rp, a.t_ci, a.t_v, i, v.y);
-                    const VarData d = var_data(key.varkind, a.sl.dval, s, i, a.c[i], a.xl[i], a.xu[i]);
-                    T xk, xt, xbar;
-                    primal_point<T>(k, v.xb[i], v.x0[i], tau, d.c, d.lo, d.hi, acc, xk, xt, xbar);
-                    v.xb[i] = xbar;
-                    if (keep) {
-                        v.xt[i] = xt;
-                        v.dx[i] = xt - xk;
+                for (int32_t i0 = tid; i0 < n; i0 += TAIL_ROWS * TAIL_THREADS) {
+                    TailEll<T> e[TAIL_ROWS];
+                    T acc[TAIL_ROWS], x0v[TAIL_ROWS];
+                    double cv[TAIL_ROWS], lv[TAIL_ROWS], hv[TAIL_ROWS];
+#pragma unroll
+                    for (int r = 0; r < TAIL_ROWS; ++r) {
+                        const int32_t i = min(i0 + r * TAIL_THREADS, n - 1);   // past n: row n-1, unused
+                        tail_ell_load<T>(a.t_e8ci, a.t_e8v, i, e[r]);
+                        cv[r] = a.c[i];
+                        lv[r] = a.xl[i];
+                        hv[r] = a.xu[i];
+                        x0v[r] = v.x0[i];
+                    }
+#pragma unroll
+                    for (int r = 0; r < TAIL_ROWS; ++r) acc[r] = tail_ell_dot<T>(e[r], v.y);
+#pragma unroll
+                    for (int r = 0; r < TAIL_ROWS; ++r) {
+                        const int32_t i = i0 + r * TAIL_THREADS;
+                        if (i < n) {
+                            const T pr = tail_rest<T>(e[r], a.t_rp, a.t_ci, a.t_v, i, v.y, acc[r]);
+                            const VarData d = var_data(key.varkind, a.sl.dval, s, i, cv[r], lv[r], hv[r]);
+                            T xk, xt, xbar;
+                            primal_point<T>(k, v.xb[i], x0v[r], tau, d.c, d.lo, d.hi, pr, xk, xt, xbar);
+                            v.xb[i] = xbar;
+                            if (keep) {
+                                v.xt[i] = xt;
+                                v.dx[i] = xt - xk;
+                            }
+                        }
                     }
                 }
                 __syncthreads();
                 const T sg = T(a.sl.sigma[s]);
                 const T wa = T(halpern_a(k)), wb = T(k + 2);
-                for (int32_t i = tid; i < m; i += TAIL_THREADS) {
-                    const T acc = tail_row<T>(a.a_e8ci, a.a_e8v, a.a_rp, a.a_ci, a.a_v, i, v.xb);
-                    const T yk = v.y[i];
-                    T yt, yn;
-                    dual_point<T>(yk, v.y0[i], sg, wa, wb, T(a.rl[i]), T(a.ru[i]), acc, yt, yn);
-                    v.y[i] = yn;
-                    if (keep) {
-                        v.yt[i] = yt;
-                        v.dy[i] = yt - yk;
+                for (int32_t i0 = tid; i0 < m; i0 += TAIL_ROWS * TAIL_THREADS) {
+                    TailEll<T> e[TAIL_ROWS];
+                    T acc[TAIL_ROWS], y0v[TAIL_ROWS];
+                    double lv[TAIL_ROWS], hv[TAIL_ROWS];
+#pragma unroll
+                    for (int r = 0; r < TAIL_ROWS; ++r) {
+                        const int32_t i = min(i0 + r * TAIL_THREADS, m - 1);   // past m: row m-1, unused
+                        tail_ell_load<T>(a.a_e8ci, a.a_e8v, i, e[r]);
+                        lv[r] = a.rl[i];
+                        hv[r] = a.ru[i];
+                        y0v[r] = v.y0[i];
+                    }
+#pragma unroll
+                    for (int r = 0; r < TAIL_ROWS; ++r) acc[r] = tail_ell_dot<T>(e[r], v.xb);
+#pragma unroll
+                    for (int r = 0; r < TAIL_ROWS; ++r) {
+                        const int32_t i = i0 + r * TAIL_THREADS;
+                        if (i < m) {
+                            const T pr = tail_rest<T>(e[r], a.a_rp, a.a_ci, a.a_v, i, v.xb, acc[r]);
+                            const T yk = v.y[i];
+                            T yt, yn;
+                            dual_point<T>(yk, y0v[r], sg, wa, wb, T(lv[r]), T(hv[r]), pr, yt, yn);
+                            v.y[i] = yn;
+                            if (keep) {
+                                v.yt[i] = yt;
+                                v.dy[i] = yt - yk;
+                            }
+                        }
                     }
                 }
                 __syncthreads();
