@@ -228,7 +228,8 @@ def run_trace_summary(args):
     for r, k in zip(rows, _solve_index(rows)):
         if k not in sel:
             continue
-        name = r["Kernel_Name"].split("(")[0].split("::")[-1].split("<")[0]
+        name = r["Kernel_Name"].replace("(anonymous namespace)::", "").split("(")[0]
+        name = name.split("<")[0].split("::")[-1]
         e = per.setdefault(name, [0, 0])
         e[0] += 1
         e[1] += int(r["End_Timestamp"]) - int(r["Start_Timestamp"])

@@ -744,9 +744,16 @@ __global__ __launch_bounds__(256) void k_eval_narrow(EvalArgs<T> a) {
     __shared__ double red[4][NTERM];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const int32_t s = blockIdx.y;
-    const bool xside = (int32_t)blockIdx.x < a.npx;
-    const int32_t panel = xside ? blockIdx.x : blockIdx.x - a.npx;
+    // Workgroups go to the eight XCDs round robin (workgroup w to XCD w mod 8).
+    // Numbering panel p's column c as 8 (ncols floor(p / 8) + c) + p mod 8 puts
+    // every column of a panel on one XCD, one after another, so that they read
+    // the panel's matrix rows and gathered lines from that XCD's L2.
+    const int32_t w8 = (int32_t)(blockIdx.x & 7), q8 = (int32_t)(blockIdx.x >> 3);
+    const int32_t s = q8 % a.ncols;
+    const int32_t pidx = (q8 / a.ncols) * 8 + w8;
+    if (pidx >= a.npx + a.npy) return;
+    const bool xside = pidx < a.npx;
+    const int32_t panel = xside ? pidx : pidx - a.npx;
     const int32_t pw = xside ? a.pw_x : a.pw_y;
     const int32_t rows = xside ? a.n : a.m;
 
@@ -1843,9 +1850,9 @@ constexpr int32_t EVAL_NARROW_COLS = 16;
 template <typename T>
 hipError_t launch_eval(const EvalArgs<T>& a, hipStream_t s) {
     if (a.ncols <= EVAL_NARROW_COLS) {
-        const dim3 grid(a.npx + a.npy, a.ncols);
-        if (grid.x == 0 || grid.y == 0) return hipSuccess;
-        hipLaunchKernelGGL(k_eval_narrow<T>, grid, dim3(256), 0, s, a);
+        const int64_t groups = ((int64_t)a.npx + a.npy + 7) / 8 * 8 * a.ncols;
+        if (groups <= 0) return hipSuccess;
+        hipLaunchKernelGGL(k_eval_narrow<T>, dim3((uint32_t)groups), dim3(256), 0, s, a);
         return hipGetLastError();
     }
     const dim3 grid(a.npx + a.npy, (a.ncols + 63) / 64);
