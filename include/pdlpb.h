@@ -126,7 +126,10 @@ typedef struct pdlpb_options {
                                  (0, the default, disables), on a matrix of at most 65536 nonzeros and
                                  with the per-LP restart scope, pdlpb_solve finishes them in one
                                  launch with one workgroup per LP, which computes the same bits as
-                                 the batched kernels (Section 5: the LPs left once most have stopped) */
+                                 the batched kernels (Section 5: the LPs left once most have stopped).
+                                 One CU then streams the whole matrix every iteration: it is faster
+                                 than the batched kernels only on matrices of a few thousand
+                                 nonzeros, so it is left to the caller */
     int32_t reserved;
     /* Device memory of the context.  Both NULL (default): hipMalloc / hipFree.
        Otherwise both set: every device buffer the context holds comes from

@@ -1276,13 +1276,15 @@ __global__ __launch_bounds__(256) void k_compact(int32_t n, int32_t m, int32_t l
 
 // ---------------------------------------------------------------------------
 // Persistent tail (Section 5: the LPs still running once most of a batch has
-// stopped).  One workgroup of 1024 threads owns one running LP and runs its
-// remaining iterations, evaluations, restarts and stop inside one launch, so a
-// narrow tail pays no launch boundaries.  It follows the batched schedule
-// exactly: blocks of C iterations from the next block base t0; an evaluation
-// of a fresh restart cycle (or of a last iteration) after the first iteration
-// of a block, a full evaluation after the last.  The LP's column is copied to
-// contiguous vectors first.  Every quantity is computed as the batched kernels
+// stopped).  One workgroup of TAIL_THREADS threads owns one running LP and
+// runs its remaining iterations, evaluations, restarts and stop inside one
+// launch, so a narrow tail pays no launch boundaries.  It follows the batched
+// schedule exactly: blocks of C iterations from the next block base t0; an
+// evaluation of a fresh restart cycle (or of a last iteration) after the first
+// iteration of a block, a full evaluation after the last.  The LP's column is
+// copied to contiguous vectors first (the two that the products gather, X-bar
+// and Y, into LDS).  One CU streams the whole matrix every iteration, so the
+// tail pays only for small matrices (a few thousand nonzeros).  Every quantity is computed as the batched kernels
 // compute it -- the same row products in CSR order, the same coordinate
 // updates, the same evaluation chains of pw rows per wave, panel sums
 // ((c0 + c1) + c2) + c3, lane-strided panel sums and butterfly, and the same
