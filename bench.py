@@ -1185,7 +1185,8 @@ def fsb2_leg(args, with_cpu=False):
     q1 = fused_bytes(dom, m, n, nnz, 1, 8, 8) - q0
     q = (q0 * counts[dom] + q1 * cols[dom]) / nl
     achieved = q / (avg_ms * 1e-3) / 1e9
-    traffic = measured_traffic("fsb_cfg2_b64_fp64_dual_traffic.json", "k_dual") if dom == 1 else None
+    kname = "k_primal" if dom == 0 else "k_dual"
+    traffic = measured_traffic(f"fsb_2000x5000_b64_fp64_{kname}_traffic.json", kname)
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
                 "traffic": traffic,
