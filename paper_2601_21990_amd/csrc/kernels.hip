@@ -510,15 +510,30 @@ struct XRow {
 struct YRow {
     double yt, dy, y0, l, u;
 };
+// A row's operands as loaded, in the storage type of the blocks: a row fetched
+// ahead is widened only when its terms are formed, so that its loads stay in
+// flight behind the gathers of the current row.
 template <typename T>
-__device__ __forceinline__ XRow load_xrow(const EvalArgs<T>& a, int32_t i, int32_t s) {
+struct XRowIn {
+    T xt, dx, x0;
+    double c, lo, hi;
+    __device__ XRow wide() const { return XRow{(double)xt, (double)dx, (double)x0, c, lo, hi}; }
+};
+template <typename T>
+struct YRowIn {
+    T yt, dy, y0;
+    double l, u;
+    __device__ YRow wide() const { return YRow{(double)yt, (double)dy, (double)y0, l, u}; }
+};
+template <typename T>
+__device__ __forceinline__ XRowIn<T> load_xrow(const EvalArgs<T>& a, int32_t i, int32_t s) {
     const size_t e = (size_t)i * a.ld + s;
-    return XRow{(double)a.Xt[e], (double)a.DX[e], (double)a.X0[e], a.c[i], a.xl[i], a.xu[i]};
+    return XRowIn<T>{a.Xt[e], a.DX[e], a.X0[e], a.c[i], a.xl[i], a.xu[i]};
 }
 template <typename T>
-__device__ __forceinline__ YRow load_yrow(const EvalArgs<T>& a, int32_t i, int32_t s) {
+__device__ __forceinline__ YRowIn<T> load_yrow(const EvalArgs<T>& a, int32_t i, int32_t s) {
     const size_t e = (size_t)i * a.ld + s;
-    return YRow{(double)a.Yt[e], (double)a.DY[e], (double)a.Y0[e], a.rl[i], a.ru[i]};
+    return YRowIn<T>{a.Yt[e], a.DY[e], a.Y0[e], a.rl[i], a.ru[i]};
 }
 // x side of column i: g = (A' y~)_i, h = (A' dy)_i, pdy = (A' Pi_B[l,u](dy))_i.
 // tv receives the row's terms; callers add them to the running sums.  No
@@ -603,7 +618,7 @@ __global__ __launch_bounds__(256) void k_eval(EvalArgs<T> a) {
             const int32_t kbeg = a.t_rp[r0], kend = a.t_rp[r1];
             int32_t i = r0;
             int32_t ke = a.t_rp[r0 + 1];
-            XRow cur = load_xrow(a, r0, s), nxt{};
+            XRowIn<T> cur = load_xrow(a, r0, s), nxt{};
             int32_t ke_n = 0;
             if (r0 + 1 < r1) {
                 nxt = load_xrow(a, r0 + 1, s);
@@ -612,7 +627,7 @@ __global__ __launch_bounds__(256) void k_eval(EvalArgs<T> a) {
             double g = 0.0, h = 0.0, pdy = 0.0;
             auto advance = [&]() {
                 double tv[NTERM];
-                finish_xrow(cur, g, h, pdy, varkind, a.sl.dval, s, i, tv);
+                finish_xrow(cur.wide(), g, h, pdy, varkind, a.sl.dval, s, i, tv);
 #pragma unroll
                 for (int q = 0; q < NTERM; ++q) acc[q] += tv[q];
                 g = h = pdy = 0.0;
@@ -625,24 +640,26 @@ __global__ __launch_bounds__(256) void k_eval(EvalArgs<T> a) {
                 }
             };
             for (int32_t k0 = kbeg; k0 < kend; k0 += CH) {
+                // loads in the storage type; the widening to double waits
+                // until every gather of the chunk has been issued
                 int32_t jj[CH];
-                double vv[CH], yv[CH], dv[CH];
+                T vv[CH], yv[CH], dv[CH];
                 int32_t cd[CH];
 #pragma unroll
                 for (int u = 0; u < CH; ++u) {
                     jj[u] = 0;
-                    vv[u] = 0.0;
+                    vv[u] = T(0);
                     if (k0 + u < kend) {
                         jj[u] = a.t_ci[k0 + u];
-                        vv[u] = (double)a.t_v[k0 + u];
+                        vv[u] = a.t_v[k0 + u];
                     }
                 }
 #pragma unroll
                 for (int u = 0; u < CH; ++u) {
                     if (k0 + u < kend) {
                         const size_t f = (size_t)jj[u] * a.ld + s;
-                        yv[u] = (double)a.Yt[f];
-                        dv[u] = (double)a.DY[f];
+                        yv[u] = a.Yt[f];
+                        dv[u] = a.DY[f];
                         cd[u] = a.rcode[jj[u]];
                     }
                 }
@@ -650,9 +667,10 @@ __global__ __launch_bounds__(256) void k_eval(EvalArgs<T> a) {
                 for (int u = 0; u < CH; ++u) {
                     if (k0 + u < kend) {
                         while (k0 + u >= ke) advance();
-                        g = fma(vv[u], yv[u], g);
-                        h = fma(vv[u], dv[u], h);
-                        pdy = fma(vv[u], barrier_code(dv[u], cd[u]), pdy);
+                        const double w = (double)vv[u], d = (double)dv[u];
+                        g = fma(w, (double)yv[u], g);
+                        h = fma(w, d, h);
+                        pdy = fma(w, barrier_code(d, cd[u]), pdy);
                     }
                 }
             }
@@ -661,7 +679,7 @@ __global__ __launch_bounds__(256) void k_eval(EvalArgs<T> a) {
             const int32_t kbeg = a.a_rp[r0], kend = a.a_rp[r1];
             int32_t i = r0;
             int32_t ke = a.a_rp[r0 + 1];
-            YRow cur = load_yrow(a, r0, s), nxt{};
+            YRowIn<T> cur = load_yrow(a, r0, s), nxt{};
             int32_t ke_n = 0;
             if (r0 + 1 < r1) {
                 nxt = load_yrow(a, r0 + 1, s);
@@ -670,7 +688,7 @@ __global__ __launch_bounds__(256) void k_eval(EvalArgs<T> a) {
             double ax = 0.0, adx = 0.0;                       // (A x~)_i, (A dx)_i
             auto advance = [&]() {
                 double tv[NTERM];
-                finish_yrow(cur, ax, adx, tv);
+                finish_yrow(cur.wide(), ax, adx, tv);
 #pragma unroll
                 for (int q = 0; q < NTERM; ++q) acc[q] += tv[q];
                 ax = adx = 0.0;
@@ -684,30 +702,31 @@ __global__ __launch_bounds__(256) void k_eval(EvalArgs<T> a) {
             };
             for (int32_t k0 = kbeg; k0 < kend; k0 += CH) {
                 int32_t jj[CH];
-                double vv[CH], xv[CH], dv[CH];
+                T vv[CH], xv[CH], dv[CH];
 #pragma unroll
                 for (int u = 0; u < CH; ++u) {
                     jj[u] = 0;
-                    vv[u] = 0.0;
+                    vv[u] = T(0);
                     if (k0 + u < kend) {
                         jj[u] = a.a_ci[k0 + u];
-                        vv[u] = (double)a.a_v[k0 + u];
+                        vv[u] = a.a_v[k0 + u];
                     }
                 }
 #pragma unroll
                 for (int u = 0; u < CH; ++u) {
                     if (k0 + u < kend) {
                         const size_t f = (size_t)jj[u] * a.ld + s;
-                        xv[u] = (double)a.Xt[f];
-                        dv[u] = (double)a.DX[f];
+                        xv[u] = a.Xt[f];
+                        dv[u] = a.DX[f];
                     }
                 }
 #pragma unroll
                 for (int u = 0; u < CH; ++u) {
                     if (k0 + u < kend) {
                         while (k0 + u >= ke) advance();
-                        ax = fma(vv[u], xv[u], ax);
-                        adx = fma(vv[u], dv[u], adx);
+                        const double w = (double)vv[u];
+                        ax = fma(w, (double)xv[u], ax);
+                        adx = fma(w, (double)dv[u], adx);
                     }
                 }
             }
@@ -775,7 +794,7 @@ __global__ __launch_bounds__(256) void k_eval_narrow(EvalArgs<T> a) {
         if (i < r1) {
             double tq[NTERM];
             if (xside) {
-                const XRow r = load_xrow(a, i, s);
+                const XRow r = load_xrow(a, i, s).wide();
                 double g = 0.0, h = 0.0, pdy = 0.0;
                 const int32_t kb = a.t_rp[i], ke = a.t_rp[i + 1];
                 for (int32_t k = kb; k < ke; ++k) {
@@ -789,7 +808,7 @@ __global__ __launch_bounds__(256) void k_eval_narrow(EvalArgs<T> a) {
                 }
                 finish_xrow(r, g, h, pdy, varkind, a.sl.dval, s, i, tq);
             } else {
-                const YRow r = load_yrow(a, i, s);
+                const YRow r = load_yrow(a, i, s).wide();
                 double ax = 0.0, adx = 0.0;
                 const int32_t kb = a.a_rp[i], ke = a.a_rp[i + 1];
                 for (int32_t k = kb; k < ke; ++k) {
