@@ -757,6 +757,8 @@ __global__ __launch_bounds__(256) void k_eval(EvalArgs<T> a) {
 // rows in row order, continuing the wave's running sum, so every addition of
 // k_eval happens in the same order.  The four wave sums are combined as there.
 // ---------------------------------------------------------------------------
+constexpr int NCH = 4;   // nonzeros of a row loaded together by k_eval_narrow
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_eval_narrow(EvalArgs<T> a) {
     __shared__ double terms[4][64][NTERM + 1];
@@ -794,31 +796,77 @@ __global__ __launch_bounds__(256) void k_eval_narrow(EvalArgs<T> a) {
         if (i < r1) {
             double tq[NTERM];
             if (xside) {
-                const XRow r = load_xrow(a, i, s).wide();
+                const XRowIn<T> r = load_xrow(a, i, s);
                 double g = 0.0, h = 0.0, pdy = 0.0;
                 const int32_t kb = a.t_rp[i], ke = a.t_rp[i + 1];
-                for (int32_t k = kb; k < ke; ++k) {
-                    const int32_t j = a.t_ci[k];
-                    const double v = (double)a.t_v[k];
-                    const size_t f = (size_t)j * a.ld + s;
-                    const double yv = (double)a.Yt[f], dv = (double)a.DY[f];
-                    g = fma(v, yv, g);
-                    h = fma(v, dv, h);
-                    pdy = fma(v, barrier(dv, a.rl[j], a.ru[j]), pdy);
+                // NCH nonzeros at a time: their indices, then their gathers, are
+                // in flight together; the sums still add them in CSR order
+                for (int32_t k0 = kb; k0 < ke; k0 += NCH) {
+                    int32_t jj[NCH], cd[NCH];
+                    T vv[NCH], yv[NCH], dv[NCH];
+#pragma unroll
+                    for (int u = 0; u < NCH; ++u) {
+                        jj[u] = 0;
+                        vv[u] = T(0);
+                        if (k0 + u < ke) {
+                            jj[u] = a.t_ci[k0 + u];
+                            vv[u] = a.t_v[k0 + u];
+                        }
+                    }
+#pragma unroll
+                    for (int u = 0; u < NCH; ++u) {
+                        if (k0 + u < ke) {
+                            const size_t f = (size_t)jj[u] * a.ld + s;
+                            yv[u] = a.Yt[f];
+                            dv[u] = a.DY[f];
+                            cd[u] = a.rcode[jj[u]];
+                        }
+                    }
+#pragma unroll
+                    for (int u = 0; u < NCH; ++u) {
+                        if (k0 + u < ke) {
+                            const double w = (double)vv[u], d = (double)dv[u];
+                            g = fma(w, (double)yv[u], g);
+                            h = fma(w, d, h);
+                            pdy = fma(w, barrier_code(d, cd[u]), pdy);
+                        }
+                    }
                 }
-                finish_xrow(r, g, h, pdy, varkind, a.sl.dval, s, i, tq);
+                finish_xrow(r.wide(), g, h, pdy, varkind, a.sl.dval, s, i, tq);
             } else {
-                const YRow r = load_yrow(a, i, s).wide();
+                const YRowIn<T> r = load_yrow(a, i, s);
                 double ax = 0.0, adx = 0.0;
                 const int32_t kb = a.a_rp[i], ke = a.a_rp[i + 1];
-                for (int32_t k = kb; k < ke; ++k) {
-                    const int32_t j = a.a_ci[k];
-                    const double v = (double)a.a_v[k];
-                    const size_t f = (size_t)j * a.ld + s;
-                    ax = fma(v, (double)a.Xt[f], ax);
-                    adx = fma(v, (double)a.DX[f], adx);
+                for (int32_t k0 = kb; k0 < ke; k0 += NCH) {
+                    int32_t jj[NCH];
+                    T vv[NCH], xv[NCH], dv[NCH];
+#pragma unroll
+                    for (int u = 0; u < NCH; ++u) {
+                        jj[u] = 0;
+                        vv[u] = T(0);
+                        if (k0 + u < ke) {
+                            jj[u] = a.a_ci[k0 + u];
+                            vv[u] = a.a_v[k0 + u];
+                        }
+                    }
+#pragma unroll
+                    for (int u = 0; u < NCH; ++u) {
+                        if (k0 + u < ke) {
+                            const size_t f = (size_t)jj[u] * a.ld + s;
+                            xv[u] = a.Xt[f];
+                            dv[u] = a.DX[f];
+                        }
+                    }
+#pragma unroll
+                    for (int u = 0; u < NCH; ++u) {
+                        if (k0 + u < ke) {
+                            const double w = (double)vv[u];
+                            ax = fma(w, (double)xv[u], ax);
+                            adx = fma(w, (double)dv[u], adx);
+                        }
+                    }
                 }
-                finish_yrow(r, ax, adx, tq);
+                finish_yrow(r.wide(), ax, adx, tq);
             }
 #pragma unroll
             for (int q = 0; q < NTERM; ++q) terms[wave][lane][q] = tq[q];
