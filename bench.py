@@ -84,7 +84,11 @@ def run_pmc_table(args):
     one run; counters of the same label are merged, and each kernel's mean per
     dispatch is reported with the bytes the request-size counters give:
     read = 32 RDREQ_32B + 64 RDREQ_64B + 128 RDREQ_128B, write = 64 WRREQ_64B
-    + 32 (WRREQ - WRREQ_64B) (on a 1 GiB copy these read exactly 1 GiB each)."""
+    + 32 (WRREQ - WRREQ_64B) (on a 1 GiB copy these read exactly 1 GiB each).
+    The means are over the dispatches that read at least 1 MB (a kernel with
+    nothing to do, such as an evaluation of no restart cycle, returns at once
+    and would dilute the mean); the runs of one label are the same program, so
+    dispatch i of every run is the same launch."""
     import csv
     import glob
     runs = {}
@@ -92,7 +96,7 @@ def run_pmc_table(args):
         label, d = item.split("=", 1)
         f = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)[0]
         per = runs.setdefault(label, {})
-        for r in csv.DictReader(open(f)):
+        for r in sorted(csv.DictReader(open(f)), key=lambda r: int(r["Dispatch_Id"])):
             name = r["Kernel_Name"]
             k = next((k for k in ("k_primal", "k_dual", "k_eval", "k_compact", "copyBuffer")
                       if k in name), None)
@@ -100,22 +104,35 @@ def run_pmc_table(args):
                 continue
             per.setdefault(k, {}).setdefault(r["Counter_Name"], []).append(
                 float(r["Counter_Value"]))
-    lines = ["| run | kernel | dispatches | read GB | write GB | 128 B reads | 64 B reads | "
+    lines = ["| run | kernel | dispatches (counted) | read GB | write GB | 128 B reads | 64 B reads | "
              "32 B reads | L2 hits | L2 misses |", "|---|---|---|---|---|---|---|---|---|---|"]
     for label, per in runs.items():
         for k, cs in sorted(per.items()):
+            def col(c):
+                return cs.get(c + "_sum") or cs.get(c)
+            r128s, r64s, r32s = (col(f"TCC_EA0_RDREQ_{b}") for b in ("128B", "64B", "32B"))
+            n = max(len(v) for v in cs.values())
+            keep = list(range(n))
+            if r128s:
+                per_read = [128 * r128s[i] + 64 * (r64s[i] if r64s else 0) +
+                            32 * (r32s[i] if r32s else 0) for i in range(len(r128s))]
+                keep = [i for i, b in enumerate(per_read) if b >= 1e6] or keep
+
             def mean(c):
-                v = cs.get(c + "_sum") or cs.get(c)
-                return sum(v) / len(v) if v else None
+                v = col(c)
+                if not v:
+                    return None
+                sel = [v[i] for i in keep if i < len(v)] if len(v) == n else v
+                return sum(sel) / len(sel)
             r32, r64, r128 = (mean(f"TCC_EA0_RDREQ_{b}") for b in ("32B", "64B", "128B"))
             wr, wr64 = mean("TCC_EA0_WRREQ"), mean("TCC_EA0_WRREQ_64B")
             rd = None if r128 is None else 32 * (r32 or 0) + 64 * (r64 or 0) + 128 * r128
             wb = None if wr is None else 64 * wr64 + 32 * (wr - wr64)
-            n = max(len(v) for v in cs.values())
+            counted = f"{n} ({len(keep)})"
 
             def f(v, scale=1e9, nd=3):
                 return "-" if v is None else f"{v / scale:.{nd}f}"
-            lines.append(f"| {label} | {k} | {n} | {f(rd)} | {f(wb)} | {f(r128, 1e6, 2)}M | "
+            lines.append(f"| {label} | {k} | {counted} | {f(rd)} | {f(wb)} | {f(r128, 1e6, 2)}M | "
                          f"{f(r64, 1e6, 2)}M | {f(r32, 1e6, 2)}M | {f(mean('TCC_HIT'), 1e6, 2)}M | "
                          f"{f(mean('TCC_MISS'), 1e6, 2)}M |")
     print("\n".join(lines))
