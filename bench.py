@@ -907,7 +907,8 @@ def headline(args):
     root_w = ctx.get_trace(0)["w"]
     log(f"root: status={P.STATUS_NAMES[root['status']]} iters={root['iters']} "
         f"obj={root['obj']:.6f} in {time.perf_counter() - t0:.2f}s")
-    draws = [fsb_deltas(root["x"], choose_fractional(root["x"], args.cfg5_vars, seed_for(5, 100 + r)))
+    draws = [fsb_deltas(root["x"], choose_fractional(root["x"], args.cfg5_vars,
+                                                     seed_for(5, args.cfg5_draw_seed + r)))
              for r in range(args.fsb_draws)]
     B = len(draws[0])
     d_draws = [torch.from_numpy(D.view(np.uint8).copy()).to(dev) for D in draws]
@@ -1379,11 +1380,14 @@ def main():
                     help="workgroup caps of the step launches; 0 = the library default")
     ap.add_argument("--cfg5-vars", type=int, default=256,
                     help="default line: branching candidates on the 200k x 500k base (B = 2x)")
-    ap.add_argument("--cfg5-eval", type=int, default=16,
+    ap.add_argument("--cfg5-eval", type=int, default=24,
                     help="default line: iterations between evaluations of the batch")
+    ap.add_argument("--cfg5-draw-seed", type=int, default=100,
+                    help="default line: first seed offset of the candidate draws (other offsets "
+                         "give independent draws, e.g. to choose the evaluation interval on)")
     ap.add_argument("--cfg5-cpu-lps", type=int, default=512,
                     help="default line: LPs of draw 0 solved by the reference solver on the host")
-    ap.add_argument("--cfg5-plain-eval", type=int, default=16,
+    ap.add_argument("--cfg5-plain-eval", type=int, default=8,
                     help="default line: iterations between evaluations of the one-at-a-time leg")
     ap.add_argument("--line-serve-rates", default="10,100",
                     help="default line: Poisson request rates of the serving sub-object")
