@@ -1041,14 +1041,16 @@ def headline(args):
     cpu = None
     if not args.no_cpu_baseline:
         workers = cpu_workers()
-        n_cpu = min(args.cfg5_cpu_lps, B)
+        cpu_lps = np.concatenate(draws)[:args.cfg5_cpu_lps]
+        n_cpu = len(cpu_lps)
         log(f"cpu baseline: reference solver, {n_cpu} LPs on {workers} processes")
-        cs, cdt, cmed = cpu_baseline_cfg5(draws[0][:n_cpu], eta, C, root, root_w, workers)
+        cs, cdt, cmed = cpu_baseline_cfg5(cpu_lps, eta, C, root, root_w, workers)
         cpu = {"value": round(cs / cdt, 3), "unit": "LPs/s", "cores": workers, "kind": "oracle",
                "host_cpu_count": os.cpu_count(),
-               "sample": f"the first {n_cpu} LPs of draw 0 (the batch of step 0), same "
-                         f"changes, warm start, step size and evaluation interval ({C}); one LP "
-                         f"per process task; {cs} solved in {cdt:.2f}s, median {cmed} iterations"}
+               "sample": f"the {n_cpu} LPs of the first {-(-n_cpu // B)} draws (the batches of "
+                         f"the first steps), same changes, warm start, step size and evaluation "
+                         f"interval ({C}); one LP per process task; {cs} solved in {cdt:.2f}s, "
+                         f"median {cmed} iterations"}
         log(f"cpu: {cpu['value']} LPs/s")
 
     it_all = np.concatenate(iters)
@@ -1385,8 +1387,9 @@ def main():
     ap.add_argument("--cfg5-draw-seed", type=int, default=100,
                     help="default line: first seed offset of the candidate draws (other offsets "
                          "give independent draws, e.g. to choose the evaluation interval on)")
-    ap.add_argument("--cfg5-cpu-lps", type=int, default=512,
-                    help="default line: LPs of draw 0 solved by the reference solver on the host")
+    ap.add_argument("--cfg5-cpu-lps", type=int, default=1024,
+                    help="default line: LPs of the first draws solved by the reference solver "
+                         "on the host")
     ap.add_argument("--cfg5-plain-eval", type=int, default=8,
                     help="default line: iterations between evaluations of the one-at-a-time leg")
     ap.add_argument("--line-serve-rates", default="10,100",
