@@ -98,9 +98,9 @@ def test_cfg2_batch_fixed_iterations(P, K, C):
     print(f"cfg2 K={K} C={C}: worst rel err {worst:.2e}")
 
 
-# C = 32 is the evaluation interval the strong-branching benchmark runs with, 16 the
-# one serving runs with
-@pytest.mark.parametrize("C", [64, 32, 16])
+# C = 32 is the evaluation interval the 2000 x 5000 strong-branching batch runs
+# with, 24 the 200k x 500k line's, 16 serving's and 8 the line's one-at-a-time leg's
+@pytest.mark.parametrize("C", [64, 32, 24, 16, 8])
 def test_cfg2_batch_converged(P, C):
     inst, lp, eta, base, D = cfg2_setup()
     with _cfg2_ctx(P, inst, eta, base, D, eval_every=C) as ctx:
