@@ -59,8 +59,10 @@ def test_mixed32_precision_statement_full_size(P):
     assert gap_dev <= 1e-9
     assert max(rel32) <= 1e-4 * (1 + 1e-6)
     # Against A itself the measure also carries the rounding of A's entries
-    # (relative 6e-8), amplified by the norms of the iterates.
-    assert max(rel) <= 2e-3
+    # (relative 6e-8), amplified by the norms of the iterates; on this batch the
+    # points still meet the tolerance against A (measured max 3.5e-5), so the
+    # FP32 LPs counted as solved are solved for the LP as given.
+    assert max(rel) <= 1e-4
 
 
 @pytest.mark.parametrize("K", [1, 2, 8, 32, 64])
