@@ -121,6 +121,13 @@ struct pdlpb_ctx {
     std::vector<std::pair<int64_t, std::pair<Tile, Tile>>> tuned;
     size_t cap_block_bytes = 0;     // bytes of each of the 8 dense blocks per row (ld * element size)
     void* blk[8] = {};              // Xbar, X0, Xt, DX, Y, Y0, Yt, DY (row-major, stride ld)
+    // Narrow storage: once at most NARROW_LD columns of a wide batch still run,
+    // run_solve copies them into blocks of stride NARROW_LD and works there
+    // until it returns (blk and ld point at them meanwhile).
+    void* nblk[8] = {};             // the narrow blocks (allocated on first use)
+    void* wblk[8] = {};             // the batch's own blocks while narrow storage is in use
+    int32_t wld = 0;                // and their stride
+    bool narrow = false;
     size_t cap_res_x = 0, cap_res_y = 0;
     void* res[4] = {};              // Rx, Rxi (B x n), Ry, Ryi (B x m): LP-major results
     int32_t cap_slots = 0;          // slot (column) capacity
@@ -158,12 +165,12 @@ struct pdlpb_ctx {
     // argument a captured launch holds by value is in the key or is a pointer
     // into storage that only ensure_storage replaces (and it drops the cache)
     struct GraphKey {
-        int32_t live, ld, wpb;
+        int32_t live, ld, wpb, narrow;
         int32_t tp_lanes, tp_vec, tp_blocks, td_lanes, td_vec, td_blocks;
         bool operator==(const GraphKey& o) const {
-            return live == o.live && ld == o.ld && wpb == o.wpb && tp_lanes == o.tp_lanes &&
-                   tp_vec == o.tp_vec && tp_blocks == o.tp_blocks && td_lanes == o.td_lanes &&
-                   td_vec == o.td_vec && td_blocks == o.td_blocks;
+            return live == o.live && ld == o.ld && wpb == o.wpb && narrow == o.narrow &&
+                   tp_lanes == o.tp_lanes && tp_vec == o.tp_vec && tp_blocks == o.tp_blocks &&
+                   td_lanes == o.td_lanes && td_vec == o.td_vec && td_blocks == o.td_blocks;
         }
     };
     std::vector<std::pair<GraphKey, hipGraphExec_t>> graphs;
@@ -269,7 +276,8 @@ struct pdlpb_ctx {
         graphs.clear();
     }
     GraphKey graph_key() const {
-        return GraphKey{live, ld, wpb, tp.lanes, tp.vec, tp.blocks, td.lanes, td.vec, td.blocks};
+        return GraphKey{live,     ld,       wpb,      narrow ? 1 : 0, tp.lanes, tp.vec,
+                        tp.blocks, td.lanes, td.vec,   td.blocks};
     }
 };
 
@@ -771,6 +779,60 @@ int run_tail(pdlpb_ctx* x, int32_t n_cols, std::vector<std::pair<int, int>>* rec
     return PDLPB_OK;
 }
 
+// Narrow storage.  In the batch's blocks the live columns of a row sit at
+// stride ld, so once few LPs run every gathered segment and every streamed row
+// lies in its own ld-wide row: at 200k x 500k, 8 running LPs cost 67 / 55 us
+// per primal / dual launch in blocks of stride 512 and 48 / 46 us in blocks of
+// stride 8.  Once at most NARROW_LD columns of a batch at least four times as
+// wide still run, and its blocks exceed the last-level cache, run_solve copies
+// those columns into blocks of stride NARROW_LD and works there until it
+// returns.  Every kernel takes the stride
+// as an argument and every LP's arithmetic is independent of it, so results
+// do not change.
+constexpr int32_t NARROW_LD = 16;
+constexpr double NARROW_MIN_BLOCK_BYTES = 256e6;   // one block pair (x rows + y rows)
+
+bool narrow_applies(const pdlpb_ctx* x, int32_t n_cols) {
+    // blocks that the caches hold gain nothing from the copy
+    const double esz = x->fp32 ? 4.0 : 8.0;
+    const double row_bytes = ((double)x->n + (double)x->m) * esz;
+    return !x->serving && !x->narrow && n_cols > 0 && n_cols <= NARROW_LD &&
+           x->ld >= 4 * NARROW_LD && NARROW_LD % x->vec_ld == 0 &&
+           row_bytes * x->ld >= NARROW_MIN_BLOCK_BYTES;
+}
+
+int enter_narrow(pdlpb_ctx* x) {
+    const size_t esz = x->fp32 ? sizeof(float) : sizeof(double);
+    const size_t pitch = (size_t)NARROW_LD * esz;
+    for (int q = 0; q < 8; ++q) {
+        const int32_t rows = q < 4 ? x->n : x->m;
+        if (!x->nblk[q]) HIP_TRY(x, x->alloc(&x->nblk[q], (size_t)rows * pitch));
+        if (rows > 0)
+            HIP_TRY(x, hipMemcpy2DAsync(x->nblk[q], pitch, x->blk[q], (size_t)x->ld * esz, pitch,
+                                        (size_t)rows, hipMemcpyDeviceToDevice, x->stream));
+    }
+    for (int q = 0; q < 8; ++q) {
+        x->wblk[q] = x->blk[q];
+        x->blk[q] = x->nblk[q];
+    }
+    x->wld = x->ld;
+    x->ld = NARROW_LD;
+    x->narrow = true;
+    return PDLPB_OK;
+}
+
+void leave_narrow(pdlpb_ctx* x) {
+    if (!x->narrow) return;
+    for (int q = 0; q < 8; ++q) x->blk[q] = x->wblk[q];
+    x->ld = x->wld;
+    x->narrow = false;
+}
+
+void free_narrow(pdlpb_ctx* x) {
+    leave_narrow(x);
+    for (int q = 0; q < 8; ++q) x->release(x->nblk[q], 0);
+}
+
 template <typename T>
 int run_solve(pdlpb_ctx* x, double tol, int32_t max_iters) {
     x->live = shape_cols(x, x->n_run0);
@@ -820,6 +882,12 @@ int run_solve(pdlpb_ctx* x, double tol, int32_t max_iters) {
             if (*f) (void)hipStreamSynchronize(x->stream);
         }
     } drain{x, &in_flight};
+    // the batch's own blocks again when the call returns (the work queued on
+    // the narrow ones stays ordered before anything later on the stream)
+    struct Wide {
+        pdlpb_ctx* x;
+        ~Wide() { leave_narrow(x); }
+    } wide{x};
     for (int64_t ep = 0; n_active > 0; ++ep) {
         if (launched > max_epochs + 1) return x->fail(PDLPB_EDEVICE, "solve did not terminate");
         if (tail_applies(x, n_cols)) {
@@ -835,6 +903,17 @@ int run_solve(pdlpb_ctx* x, double tol, int32_t max_iters) {
             if (rc) return rc;
             if (prec) harvest();
             return PDLPB_OK;
+        }
+        if (narrow_applies(x, n_cols)) {
+            if (in_flight) {
+                rc = wait_counts(x, in_slot, &n_active, &n_cols);
+                if (rc) return rc;
+                in_flight = false;
+                continue;
+            }
+            rc = enter_narrow(x);
+            if (rc) return rc;
+            x->live = -1;   // shape the launches (and their graphs) for the new stride
         }
         // shape the launches for the live columns (compaction shrinks them)
         const int32_t shape = shape_cols(x, n_cols);
@@ -2039,6 +2118,9 @@ int pdlpb_serve_begin(pdlpb_ctx* x, int32_t result_capacity) {
         return x->fail(PDLPB_EINVAL, "result_capacity out of range");
     HIP_TRY(x, hipSetDevice(x->device));
     HIP_TRY(x, hipStreamSynchronize(x->stream));
+    // a session holds only what its LPs need: no narrow copies of a batch
+    x->drop_graph();
+    free_narrow(x);
     // storage starts at one column and one result row and grows with the LPs
     // submitted (pdlpb_serve_footprint, pdlpb_serve_trim)
     x->n_cols = 0;

@@ -53,7 +53,8 @@ def test_strong_branching_line_sampled_lps_match_oracle(P):
     """Draw 0 of the benchmark line: the first LP of the batch, the LP at the
     three-quarter point of the iteration counts and the slowest LP follow the
     oracle's trajectories from the same root (statuses, iteration counts,
-    restart logs, iterates and KKT measures).
+    restart logs, iterates and KKT measures), and solved alone they give the
+    batch's bits (the batch's last LPs run in narrow storage).
 
     Per coordinate the iterates are compared on the scale max(|o_i|, rms(o), 1)
     (elem_scale): after hundreds of iterations on duals whose entries are in
@@ -78,6 +79,19 @@ def test_strong_branching_line_sampled_lps_match_oracle(P):
         order = np.argsort(st["iters"], kind="stable")
         sample = sorted({0, int(order[3 * len(order) // 4]), int(order[-1])})
         res = {j: (ctx.get(j), ctx.get_trace(j)) for j in sample}
+    # the same LPs alone (one column, never moved to narrow storage): the same
+    # bits as in the batch, whose last LPs ran in blocks of stride 16
+    with P.Context.from_instance(inst, eval_every=C, max_batch=1, step_size=eta) as one:
+        for j in sample:
+            one.set_batch(D[j:j + 1], x_warm=root["x"], y_warm=root["y"], w_warm=np.full(1, w))
+            one.solve(tol=1e-4, max_iters=100000)
+            g, tr = one.get(0), one.get_trace(0)
+            assert g["status"] == res[j][0]["status"] and g["iters"] == res[j][0]["iters"], j
+            assert tr["restart_log"] == res[j][1]["restart_log"], j
+            for key in ("x", "y"):
+                assert np.array_equal(g[key], res[j][0][key]), (j, key)
+            for key in ("x_iter", "y_iter"):
+                assert np.array_equal(tr[key], res[j][1][key]), (j, key)
     ok = np.isin(st["status"], [P.STATUS_OPTIMAL, P.STATUS_PRIMAL_INFEASIBLE])
     assert np.all(ok), np.bincount(st["status"])
     assert np.all(st["kkt"][st["status"] == P.STATUS_OPTIMAL, 3] <= 1e-4)
