@@ -1343,7 +1343,7 @@ def main():
     ap.add_argument("--mixed-iters", type=int, default=20000)
     ap.add_argument("--no-precision", action="store_true",
                     help="mixed: skip the FP64 pass of the precision statement")
-    ap.add_argument("--serve-eval", type=int, default=16,
+    ap.add_argument("--serve-eval", type=int, default=8,
                     help="serve: iterations between evaluations (the block length)")
     ap.add_argument("--eval-every", type=int, default=32,
                     help="fsb: iterations between evaluations of the batch")
@@ -1358,7 +1358,7 @@ def main():
     ap.add_argument("--serve-m", type=int, default=200000)
     ap.add_argument("--serve-bases", type=int, default=4)
     ap.add_argument("--serve-prec", default="fp64", choices=["fp32", "fp64"])
-    ap.add_argument("--serve-cols", type=int, default=1024)
+    ap.add_argument("--serve-cols", type=int, default=256)
     ap.add_argument("--serve-rows", type=int, default=2048)
     ap.add_argument("--serve-rates", default="1,3,10")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
