@@ -880,6 +880,58 @@ def _cpu5_noop(_):
     return 0
 
 
+def mixed32_line(args, inst, eta, C, draws, d_draws, d_x, d_y, d_w, d_X, d_Y, fp64_by_draw):
+    """The line's first draws again with FP32 iterates and products (FP64
+    sums), from the same root and step size: LPs/s and the objective
+    difference against the FP64 steps.  FP32 iterates cannot certify the
+    infeasible branches of this family (the rounding of y~ swamps the
+    displacement the test reads), so the FP32 run stops at an iteration cap
+    and those LPs are reported, not counted."""
+    import numpy as np
+    import torch
+    import paper_2601_21990_amd.pdlpb as P
+    B = len(draws[0])
+    ctx = P.Context.from_instance(inst, device=0, use_graphs=args.graphs, eval_every=C,
+                                  max_batch=B, step_size=eta, precision=P.MIXED32)
+    cap = args.cfg5_mixed_iters
+
+    def step(i):
+        rc = P.lib.pdlpb_set_batch(ctx._h, B, d_draws[i].data_ptr(), d_x.data_ptr(),
+                                   d_y.data_ptr(), d_w.data_ptr(), P.WARM_SHARED, P.MEM_DEVICE)
+        ctx._check(rc)
+        ctx.B = B
+        ctx.solve(tol=1e-4, max_iters=cap)
+        return ctx.get_batch(X=d_X, Y=d_Y, mem=P.MEM_DEVICE)
+
+    nd = len(fp64_by_draw)
+    step(0)                                # warm-up (graphs, tile choice)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    outs = [step(i) for i in range(nd)]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ctx.close()
+    diffs, solved, capped, st_all = [], 0, 0, np.zeros(8, dtype=np.int64)
+    for (st64, obj64), o in zip(fp64_by_draw, outs):
+        both = (st64 == P.STATUS_OPTIMAL) & (o["status"] == P.STATUS_OPTIMAL)
+        diffs.append(np.abs(o["obj"][both] - obj64[both]) / (1.0 + np.abs(obj64[both])))
+        solved += int(np.sum(o["status"] == P.STATUS_OPTIMAL))
+        capped += int(np.sum(o["status"] == P.STATUS_ITERATION_LIMIT))
+        st_all += np.bincount(o["status"], minlength=8)
+    d = np.concatenate(diffs) if diffs else np.zeros(0)
+    res = {"value": round(solved / dt, 2), "unit": "LPs/s", "draws": nd,
+           "lps_compared": int(d.size),
+           "obj_rel_diff_max": float(d.max()) if d.size else None,
+           "obj_rel_diff_median": float(np.median(d)) if d.size else None,
+           "statuses": st_all.tolist(), "iteration_cap": cap, "capped": capped,
+           "note": "FP32 iterates and products with FP64 sums, same draws, root and step size as "
+                   "the FP64 steps; LPs at the iteration cap are the infeasible branches FP32 "
+                   "cannot certify"}
+    log(f"mixed32: {nd} draws in {dt:.3f}s, {solved} solved -> {res['value']} LPs/s; objective "
+        f"difference max {res['obj_rel_diff_max']}, {capped} at the iteration cap")
+    return res
+
+
 def headline(args):
     """Strong branching on the 200k x 500k family (the largest single-GPU
     shape): B = 512 bound changes on 256 fractional variables of the GPU's root
@@ -937,6 +989,7 @@ def headline(args):
     t0 = time.perf_counter()
     solved = 0
     iters, slowest, step_s, statuses = [], [], [], np.zeros(8, dtype=np.int64)
+    fp64_by_draw = []                      # (statuses, objectives) of the first draws
     for i in range(args.steps):
         ts = time.perf_counter()
         out = step(i)                      # ends with the statuses read back to the host
@@ -945,6 +998,8 @@ def headline(args):
         statuses += np.bincount(out["status"], minlength=8)
         iters.append(out["iters"])
         slowest.append(int(out["iters"].max()))
+        if i < len(draws) and len(fp64_by_draw) < args.cfg5_mixed_draws:
+            fp64_by_draw.append((out["status"].copy(), out["obj"].copy()))
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     value = solved / dt
@@ -1002,6 +1057,9 @@ def headline(args):
                "note": "inputs from and results (x~, y~ per LP, 2.9 GB) to host memory"}
     log(f"host I/O: {n_host} steps in {host_dt:.4f}s -> {host_io['value']} LPs/s")
     ctx.close()
+
+    mixed = mixed32_line(args, inst, eta, C, draws, d_draws, d_x, d_y, d_w, d_X, d_Y,
+                         fp64_by_draw) if fp64_by_draw else None
 
     # plain PDHG: a sample of the same LPs one at a time (B = 1), same library
     ctx_p = P.Context.from_instance(inst, device=0, use_graphs=args.graphs,
@@ -1088,6 +1146,7 @@ def headline(args):
                   "max": int(it_all.max()), "slowest_per_batch_median": int(np.median(slowest))},
         "kernels": kernel_ms,
         "roofline": roofline,
+        "mixed32": mixed,
         "cpu_baseline": cpu,
     }
 
@@ -1387,6 +1446,10 @@ def main():
     ap.add_argument("--cfg5-draw-seed", type=int, default=100,
                     help="default line: first seed offset of the candidate draws (other offsets "
                          "give independent draws, e.g. to choose the evaluation interval on)")
+    ap.add_argument("--cfg5-mixed-draws", type=int, default=3,
+                    help="default line: draws solved again with FP32 iterates (0: none)")
+    ap.add_argument("--cfg5-mixed-iters", type=int, default=3000,
+                    help="default line: iteration cap of the FP32-iterate run")
     ap.add_argument("--cfg5-cpu-lps", type=int, default=1024,
                     help="default line: LPs of the first draws solved by the reference solver "
                          "on the host")

@@ -49,7 +49,52 @@ def test_largest_size_sampled_lps_match_oracle(P):
         assert_trajectory_match(*res[j], ores, what=f"LP {j}")
 
 
-def test_strong_branching_line_sampled_lps_match_oracle(P):
+@pytest.fixture(scope="module")
+def line_root(P):
+    """The line's base LP solved on the GPU (FP64, C = 24) and draw 0 of its
+    candidates."""
+    inst = make_cfg5(base=0)
+    lp = O.from_instance(inst)
+    with P.Context.from_instance(inst, eval_every=24, max_batch=1) as ctx:
+        eta, _ = ctx.step_size
+        ctx.set_batch(deltas([BASE], [0], [0.0]))
+        ctx.solve(tol=1e-6, max_iters=200000)
+        root = ctx.get(0)
+        w = ctx.get_trace(0)["w"]
+    assert root["status"] == P.STATUS_OPTIMAL
+    D = fsb_deltas(root["x"], choose_fractional(root["x"], 256, seed_for(5, 100)))
+    return inst, lp, eta, root, w, D
+
+
+def test_mixed32_line_points_meet_tolerance_against_a(P, line_root):
+    """Draw 0 of the line with FP32 iterates and products (FP64 sums): every
+    LP it reports optimal has an FP64 twin within 1e-7 in objective, and the
+    oracle measures a sample of its points within the tolerance against the
+    true A (the FP32 run multiplies by A rounded to FP32)."""
+    inst, lp, eta, root, w, D = line_root
+    res = {}
+    for prec in (P.FP64, P.MIXED32):
+        with P.Context.from_instance(inst, eval_every=24, max_batch=512, step_size=eta,
+                                     precision=prec) as ctx:
+            ctx.set_batch(D, x_warm=root["x"], y_warm=root["y"], w_warm=np.full(len(D), w))
+            ctx.solve(tol=1e-4, max_iters=3000)
+            res[prec] = ctx.get_batch()
+    a, b = res[P.FP64], res[P.MIXED32]
+    both = (a["status"] == P.STATUS_OPTIMAL) & (b["status"] == P.STATUS_OPTIMAL)
+    assert both.sum() >= len(D) - 4
+    err = np.abs(b["obj"][both] - a["obj"][both]) / (1 + np.abs(a["obj"][both]))
+    rel = []
+    order = np.argsort(b["iters"], kind="stable")
+    for j in [int(order[k]) for k in np.linspace(0, len(order) - 1, 8).astype(int)]:
+        if b["status"][j] == P.STATUS_OPTIMAL:
+            rel.append(O.kkt(lp_for(lp, D[j]), b["X"][j], b["Y"][j]).rel)
+    print(f"MIXED32 line: objective difference max {err.max():.2e}; oracle KKT of FP32 points "
+          f"against A: max {max(rel):.2e} over {len(rel)} LPs")
+    assert err.max() <= 1e-7
+    assert rel and max(rel) <= 1e-4
+
+
+def test_strong_branching_line_sampled_lps_match_oracle(P, line_root):
     """Draw 0 of the benchmark line: the first LP of the batch, the LP at the
     three-quarter point of the iteration counts and the slowest LP follow the
     oracle's trajectories from the same root (statuses, iteration counts,
@@ -61,18 +106,10 @@ def test_strong_branching_line_sampled_lps_match_oracle(P):
     the thousands (rms 1765 for the slowest LP), a dual entry near zero carries
     the rounding of the terms mixed into it, e.g. 4.1e-9 on an entry of 0.58,
     2.3e-12 of the vector's scale; the norm-relative check stays at 1e-9."""
-    inst = make_cfg5(base=0)
-    lp = O.from_instance(inst)
+    inst, lp, eta, root, w, D = line_root
     C = 24
-    with P.Context.from_instance(inst, eval_every=C, max_batch=512) as ctx:
-        eta, _ = ctx.step_size
-        ctx.set_batch(deltas([BASE], [0], [0.0]))
-        ctx.solve(tol=1e-6, max_iters=200000)
-        root = ctx.get(0)
-        w = ctx.get_trace(0)["w"]
-        assert root["status"] == P.STATUS_OPTIMAL
-        D = fsb_deltas(root["x"], choose_fractional(root["x"], 256, seed_for(5, 100)))
-        assert len(D) == 512
+    assert len(D) == 512
+    with P.Context.from_instance(inst, eval_every=C, max_batch=512, step_size=eta) as ctx:
         ctx.set_batch(D, x_warm=root["x"], y_warm=root["y"], w_warm=np.full(len(D), w))
         ctx.solve(tol=1e-4, max_iters=100000)
         st = ctx.get_batch(want_x=False, want_y=False)
