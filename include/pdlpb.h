@@ -429,13 +429,19 @@ int pdlpb_kernel_times(pdlpb_ctx* ctx, int64_t counts[5], double total_ms[5]);
  */
 int pdlpb_kernel_columns(pdlpb_ctx* ctx, int64_t cols[5]);
 
-/* Bytes of device memory held by the context. */
+/* Bytes of device memory held by the context.  Besides the matrix, base
+ * vectors, batch storage and results, a context that has solved a batch whose
+ * eight blocks exceed the last-level cache (n + m rows at its stride, at least
+ * 256 MB per pair of blocks) keeps eight blocks of 16 columns, (n + m) * 16 *
+ * element size * 4 bytes, where a batch's last LPs finish (Section 5: the LPs
+ * left once most have stopped); pdlpb_serve_begin releases them. */
 int64_t pdlpb_device_bytes(const pdlpb_ctx* ctx);
 
 /* Number of blocks of C iterations captured as graphs over the context's life.
  * A captured block is replayed for every later batch or serving round with the
- * same launch shape (live column bound, row stride, tile shapes), and is
- * captured again only when the context's storage is reallocated. */
+ * same launch shape (live column bound, row stride, tile shapes, batch or
+ * 16-column storage), and is captured again only when the context's storage is
+ * reallocated. */
 int64_t pdlpb_graph_captures(const pdlpb_ctx* ctx);
 
 /* Release every device buffer and the context.  NULL is a no-op. */
