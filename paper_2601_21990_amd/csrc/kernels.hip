@@ -1678,8 +1678,7 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(TailArgs<T> a) {
 template <typename T>
 __global__ void k_init_blocks(int32_t n, int32_t m, int32_t ld, int32_t ncols, Slots sl,
                               const double* xl, const double* xu, const double* xw,
-                              const double* yw, int32_t mode, T* Xbar, T* X0, T* Xt, T* DX, T* Y,
-                              T* Y0, T* Yt, T* DY) {
+                              const double* yw, int32_t mode, T* Xbar, T* X0, T* Y, T* Y0) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t nx = (int64_t)n * ld, ny = (int64_t)m * ld;
     if (idx < nx) {
@@ -1694,8 +1693,6 @@ __global__ void k_init_blocks(int32_t n, int32_t m, int32_t ld, int32_t ncols, S
         }
         Xbar[idx] = x;
         X0[idx] = x;
-        Xt[idx] = x;
-        DX[idx] = T(0);
     } else if (idx < nx + ny) {
         const int64_t e = idx - nx;
         const int32_t i = (int32_t)(e / ld), s = (int32_t)(e % ld);
@@ -1706,8 +1703,6 @@ __global__ void k_init_blocks(int32_t n, int32_t m, int32_t ld, int32_t ncols, S
         }
         Y[e] = y;
         Y0[e] = y;
-        Yt[e] = y;
-        DY[e] = T(0);
     }
 }
 
@@ -1970,14 +1965,14 @@ hipError_t launch_compact(int32_t n, int32_t m, int32_t ld, int32_t ncols, T* co
 template <typename T>
 hipError_t launch_init_blocks(int32_t n, int32_t m, int32_t ld, int32_t ncols, Slots sl,
                               const double* xl, const double* xu, const double* xw,
-                              const double* yw, int32_t mode, T* Xbar, T* X0, T* Xt, T* DX, T* Y,
-                              T* Y0, T* Yt, T* DY, hipStream_t s) {
+                              const double* yw, int32_t mode, T* Xbar, T* X0, T* Y, T* Y0,
+                              hipStream_t s) {
     const int64_t total = (int64_t)(n + m) * ld;
     if (total == 0) return hipSuccess;
     const int64_t blocks = (total + 255) / 256;
     if (blocks > 0x7fffffff) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_init_blocks<T>, dim3((uint32_t)blocks), dim3(256), 0, s, n, m, ld, ncols,
-                       sl, xl, xu, xw, yw, mode, Xbar, X0, Xt, DX, Y, Y0, Yt, DY);
+                       sl, xl, xu, xw, yw, mode, Xbar, X0, Y, Y0);
     return hipGetLastError();
 }
 
@@ -2084,11 +2079,10 @@ template hipError_t launch_init_columns<float>(int32_t, int32_t, int32_t, int32_
 template hipError_t launch_init_blocks<double>(int32_t, int32_t, int32_t, int32_t, Slots,
                                                const double*, const double*, const double*,
                                                const double*, int32_t, double*, double*, double*,
-                                               double*, double*, double*, double*, double*,
-                                               hipStream_t);
+                                               double*, hipStream_t);
 template hipError_t launch_init_blocks<float>(int32_t, int32_t, int32_t, int32_t, Slots,
                                               const double*, const double*, const double*,
                                               const double*, int32_t, float*, float*, float*,
-                                              float*, float*, float*, float*, float*, hipStream_t);
+                                              float*, hipStream_t);
 
 }  // namespace pdlpb

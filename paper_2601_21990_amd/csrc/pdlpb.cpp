@@ -1833,13 +1833,12 @@ int pdlpb_set_batch(pdlpb_ctx* x, int32_t B, const pdlpb_delta* deltas, const do
     if (x->fp32) {
         float* const* b = reinterpret_cast<float* const*>(x->blk);
         HIP_TRY(x, launch_init_blocks<float>(n, m, ld, n_run0, x->sl, x->xl, x->xu, xw,
-                                             yw, warm_mode, b[0], b[1], b[2], b[3], b[4], b[5],
-                                             b[6], b[7], x->stream));
+                                             yw, warm_mode, b[0], b[1], b[4], b[5], x->stream));
     } else {
         double* const* b = reinterpret_cast<double* const*>(x->blk);
         HIP_TRY(x, launch_init_blocks<double>(n, m, ld, n_run0, x->sl, x->xl, x->xu,
-                                              xw, yw, warm_mode, b[0], b[1], b[2], b[3], b[4],
-                                              b[5], b[6], b[7], x->stream));
+                                              xw, yw, warm_mode, b[0], b[1], b[4], b[5],
+                                              x->stream));
     }
     // host staging must outlive the copies
     HIP_TRY(x, hipStreamSynchronize(x->stream));
@@ -2532,8 +2531,7 @@ int estimate_widths(pdlpb_ctx* x, const int32_t* widths, int32_t count, int32_t 
     HIP_TRY(x, hipMemcpyAsync(x->g, &hg, sizeof(Globals), h2d, x->stream));
     T* const* b = reinterpret_cast<T* const*>(x->blk);
     HIP_TRY(x, launch_init_blocks<T>(x->n, x->m, ld, wmax, x->sl, x->xl, x->xu, nullptr, nullptr,
-                                     PDLPB_WARM_NONE, b[0], b[1], b[2], b[3], b[4], b[5], b[6],
-                                     b[7], x->stream));
+                                     PDLPB_WARM_NONE, b[0], b[1], b[4], b[5], x->stream));
     hipEvent_t e0 = nullptr, e1 = nullptr;
     HIP_TRY(x, hipEventCreateWithFlags(&e0, hipEventDisableSystemFence));
     hipError_t he = hipEventCreateWithFlags(&e1, hipEventDisableSystemFence);

@@ -227,14 +227,17 @@ hipError_t launch_control(const ControlArgs& a, hipStream_t s);
 template <typename T>
 hipError_t launch_tail(const TailArgs<T>& a, size_t dyn_lds, hipStream_t s);
 
-// Fill the dense blocks of a new batch.  Warm vectors: mode 0 none, 1 shared
-// (xw: n, yw: m), 2 per LP (xw: ncols*n, yw: ncols*m, LP-major).
-// slot_lp maps slots [0, ncols) to LPs (per-LP warm starts are indexed by LP).
+// Fill the iterate blocks of a new batch (Xbar = X0 = the projected warm x,
+// Y = Y0 = the warm y).  Warm vectors: mode 0 none, 1 shared (xw: n, yw: m),
+// 2 per LP (xw: ncols*n, yw: ncols*m, LP-major); slot_lp maps slots
+// [0, ncols) to LPs (per-LP warm starts are indexed by LP).  The evaluation
+// blocks (X~, dX, Y~, dY) are left as they are: a solve starts with a full
+// evaluation, whose iteration writes them for every LP before anything reads
+// them.
 template <typename T>
 hipError_t launch_init_blocks(int32_t n, int32_t m, int32_t ld, int32_t ncols, Slots sl,
                               const double* xl, const double* xu, const double* xw,
-                              const double* yw, int32_t mode,
-                              T* Xbar, T* X0, T* Xt, T* DX, T* Y, T* Y0, T* Yt, T* DY,
+                              const double* yw, int32_t mode, T* Xbar, T* X0, T* Y, T* Y0,
                               hipStream_t s);
 
 // Execute the plan of a full evaluation in one launch: restarted LPs take z~
