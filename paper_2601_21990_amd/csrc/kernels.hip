@@ -1291,22 +1291,21 @@ __global__ __launch_bounds__(256) void k_compact(int32_t n, int32_t m, int32_t l
                     res_h[lane][rr] = B.b[4][e];   // Halpern iterate y^{k+1}
                 }
                 if (re.src >= 0) {
+                    // a moving LP takes its iterate and anchor along (z~ as both
+                    // when it restarted at this evaluation); its z~ and
+                    // displacement are written again by the iteration before any
+                    // later evaluation reads them
                     const size_t f = base + re.src;
                     if (xside) {
-                        const T v0 = B.b[0][f], v2 = B.b[2][f], v3 = B.b[3][f];
-                        const T v1 = re.src_fresh ? v2 : B.b[1][f];
+                        const T v0 = B.b[0][f];
+                        const T v1 = re.src_fresh ? B.b[2][f] : B.b[1][f];
                         B.b[0][e] = v0;
                         B.b[1][e] = v1;
-                        B.b[2][e] = v2;
-                        B.b[3][e] = v3;
                     } else {
-                        const T v6 = B.b[6][f], v7 = B.b[7][f];
-                        const T v4 = re.src_fresh ? v6 : B.b[4][f];
-                        const T v5 = re.src_fresh ? v6 : B.b[5][f];
+                        const T v4 = re.src_fresh ? B.b[6][f] : B.b[4][f];
+                        const T v5 = re.src_fresh ? v4 : B.b[5][f];
                         B.b[4][e] = v4;
                         B.b[5][e] = v5;
-                        B.b[6][e] = v6;
-                        B.b[7][e] = v7;
                     }
                 }
             }
