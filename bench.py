@@ -837,34 +837,34 @@ def cpu_workers():
 _CPU5 = {}
 
 
-def _cpu5_init(eta, C, x, y, w):
+def _cpu5_init(eta, C, S, x, y, w):
     from threadpoolctl import threadpool_limits
     threadpool_limits(1)          # one thread per worker process
     import oracle as O
     from workloads import make_cfg5
     _CPU5["lp"] = O.from_instance(make_cfg5(base=0))
-    _CPU5.update(eta=eta, C=C, x=x, y=y, w=w)
+    _CPU5.update(eta=eta, C=C, S=S, x=x, y=y, w=w)
 
 
 def _cpu5_task(t):
     import oracle as O
     lpj = O.apply_delta(_CPU5["lp"], *t)
     r = O.solve(lpj, O.Options(tol=1e-4, step_size=_CPU5["eta"], eval_every=_CPU5["C"],
-                               max_iters=100000),
+                               stop_every=_CPU5["S"], max_iters=100000),
                 x_init=_CPU5["x"], y_init=_CPU5["y"], w_init=_CPU5["w"])
     return r.status, r.iters
 
 
-def cpu_baseline_cfg5(sample, eta, C, root, w, workers):
+def cpu_baseline_cfg5(sample, eta, C, S, root, w, workers):
     """The FP64 reference solver on the host cores, one LP per task, on LPs of
     the GPU batch: the same changes, the same warm start (the GPU's root
-    solution), step size and evaluation interval."""
+    solution), step size, evaluation interval and stopping tests."""
     import numpy as np
     from concurrent.futures import ProcessPoolExecutor
     import oracle as O
     tasks = [(int(d["kind"]), int(d["var"]), float(d["value"])) for d in sample]
     with ProcessPoolExecutor(max_workers=workers, initializer=_cpu5_init,
-                             initargs=(eta, C, root["x"], root["y"], w)) as ex:
+                             initargs=(eta, C, S, root["x"], root["y"], w)) as ex:
         # the workers build the matrix before the clock starts
         list(ex.map(_cpu5_noop, range(workers), chunksize=1))
         t0 = time.perf_counter()
@@ -892,7 +892,8 @@ def mixed32_line(args, inst, eta, C, draws, d_draws, d_x, d_y, d_w, d_X, d_Y, fp
     import paper_2601_21990_amd.pdlpb as P
     B = len(draws[0])
     ctx = P.Context.from_instance(inst, device=0, use_graphs=args.graphs, eval_every=C,
-                                  max_batch=B, step_size=eta, precision=P.MIXED32)
+                                  stop_every=args.cfg5_stop_every, max_batch=B, step_size=eta,
+                                  precision=P.MIXED32)
     cap = args.cfg5_mixed_iters
 
     def step(i):
@@ -948,15 +949,19 @@ def headline(args):
     m, n, nnz = inst.m, inst.n, inst.nnz
     C = args.cfg5_eval
     log(f"instance m={m} n={n} nnz={nnz}")
-    opts = dict(device=0, use_graphs=args.graphs, eval_every=C, max_batch=2 * args.cfg5_vars)
+    # the root LP (the MIP's relaxation) is solved once, at the evaluation
+    # interval alone, so the candidates do not depend on the batch's options
+    with P.Context.from_instance(inst, device=0, eval_every=C, max_batch=1) as ctx_root:
+        eta, norm_a = ctx_root.step_size
+        log(f"eta={eta:.6g} ||A||={norm_a:.6g}")
+        t0 = time.perf_counter()
+        ctx_root.set_batch(deltas([BASE], [0], [0.0]))
+        ctx_root.solve(tol=1e-6, max_iters=200000)
+        root = ctx_root.get(0)
+        root_w = ctx_root.get_trace(0)["w"]
+    opts = dict(device=0, use_graphs=args.graphs, eval_every=C, max_batch=2 * args.cfg5_vars,
+                stop_every=args.cfg5_stop_every, step_size=eta)
     ctx = P.Context.from_instance(inst, **opts)
-    eta, norm_a = ctx.step_size
-    log(f"eta={eta:.6g} ||A||={norm_a:.6g}")
-    t0 = time.perf_counter()
-    ctx.set_batch(deltas([BASE], [0], [0.0]))
-    ctx.solve(tol=1e-6, max_iters=200000)
-    root = ctx.get(0)
-    root_w = ctx.get_trace(0)["w"]
     log(f"root: status={P.STATUS_NAMES[root['status']]} iters={root['iters']} "
         f"obj={root['obj']:.6f} in {time.perf_counter() - t0:.2f}s")
     draws = [fsb_deltas(root["x"], choose_fractional(root["x"], args.cfg5_vars,
@@ -1102,12 +1107,14 @@ def headline(args):
         cpu_lps = np.concatenate(draws)[:args.cfg5_cpu_lps]
         n_cpu = len(cpu_lps)
         log(f"cpu baseline: reference solver, {n_cpu} LPs on {workers} processes")
-        cs, cdt, cmed = cpu_baseline_cfg5(cpu_lps, eta, C, root, root_w, workers)
+        cs, cdt, cmed = cpu_baseline_cfg5(cpu_lps, eta, C, args.cfg5_stop_every, root, root_w,
+                                          workers)
         cpu = {"value": round(cs / cdt, 3), "unit": "LPs/s", "cores": workers, "kind": "oracle",
                "host_cpu_count": os.cpu_count(),
                "sample": f"the {n_cpu} LPs of the first {-(-n_cpu // B)} draws (the batches of "
-                         f"the first steps), same changes, warm start, step size and evaluation "
-                         f"interval ({C}); one LP per process task; {cs} solved in {cdt:.2f}s, "
+                         f"the first steps), same changes, warm start, step size, evaluation "
+                         f"interval ({C}) and stopping tests (every {args.cfg5_stop_every}); one "
+                         f"LP per process task; {cs} solved in {cdt:.2f}s, "
                          f"median {cmed} iterations"}
         log(f"cpu: {cpu['value']} LPs/s")
 
@@ -1131,7 +1138,8 @@ def headline(args):
                                f"it, FP64, tol 1e-4 rel KKT; step i solves draw i mod "
                                f"{len(draws)} of the candidates",
                    "m": m, "n": n, "nnz": nnz, "B": B, "tol": 1e-4, "draws": len(draws),
-                   "eval_every": C, "root_iters": int(root["iters"])},
+                   "eval_every": C, "stop_every": args.cfg5_stop_every,
+                   "root_iters": int(root["iters"])},
         "plain": {"value": round(plain_value, 2), "unit": "LPs/s", "lps": n_plain,
                   "iters_median": int(np.median(plain_iters)), "eval_every": args.cfg5_plain_eval,
                   "ms_per_lp_median": round(float(np.median(plain_s)) * 1e3, 3)},
@@ -1443,6 +1451,9 @@ def main():
                     help="default line: branching candidates on the 200k x 500k base (B = 2x)")
     ap.add_argument("--cfg5-eval", type=int, default=24,
                     help="default line: iterations between evaluations of the batch")
+    ap.add_argument("--cfg5-stop-every", type=int, default=12,
+                    help="default line: stopping tests every S iterations between evaluations "
+                         "(0: off)")
     ap.add_argument("--cfg5-draw-seed", type=int, default=100,
                     help="default line: first seed offset of the candidate draws (other offsets "
                          "give independent draws, e.g. to choose the evaluation interval on)")

@@ -130,7 +130,13 @@ typedef struct pdlpb_options {
                                  One CU then streams the whole matrix every iteration: it is faster
                                  than the batched kernels only on matrices of a few thousand
                                  nonzeros, so it is left to the caller */
-    int32_t reserved;
+    int32_t stop_every;       /* S: the stopping test (eq:stopping at z~) also runs every S
+                                 iterations between the evaluations of eval_every (Section 4 leaves
+                                 the schedule open); it tests nothing else, so the iterates are
+                                 those of the run without it and LPs only stop sooner.  0 (the
+                                 default) or eval_every: off; otherwise a divisor >= 2 of
+                                 eval_every.  Per-LP restart scope, pdlpb_solve only (ignored by
+                                 the serving calls). */
     /* Device memory of the context.  Both NULL (default): hipMalloc / hipFree.
        Otherwise both set: every device buffer the context holds comes from
        dev_alloc(bytes, alloc_user), which returns a pointer on the context's

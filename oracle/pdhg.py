@@ -290,6 +290,9 @@ class Options:
     pw_ratio: str = "dy/dx"
     infeas_tol: Optional[float] = None   # eps of the infeasibility tests; None: tol; 0: off
     dual_tol: Optional[float] = None     # eps of the dual-feasibility test; None: tol
+    # S: stopping tests also at t mod S == 0 between the evaluations above
+    # (0: off; S >= 2 dividing C; per-LP restart scope only)
+    stop_every: int = 0
 
 
 @dataclass
@@ -308,6 +311,18 @@ class Result:
     @property
     def obj(self) -> float:
         return self.kkt.obj if self.kkt is not None else float("nan")
+
+
+def _stop_every(opt: "Options") -> int:
+    """The interval S of the extra stopping tests, 0 when off; S must be at
+    least 2 and divide C (so they never fall on t = 0 mod C or on the first
+    iteration of a restart cycle)."""
+    S = int(opt.stop_every)
+    if S == 0 or S == opt.eval_every:
+        return 0
+    if S < 2 or opt.eval_every % S != 0:
+        raise ValueError("stop_every must be 0 or a divisor >= 2 of eval_every")
+    return S
 
 
 def _converged(kk: KKT, opt: "Options") -> bool:
@@ -357,7 +372,12 @@ def solve(lp: LP, opt: Options = Options(), x_init=None, y_init=None,
         point, PRIMAL_INFEASIBLE / DUAL_INFEASIBLE when the infeasibility tests
         pass there (after the stopping test), and ITERATION_LIMIT after
         max_iters applications of T; in every case it returns z~ of its last
-        iteration.
+        iteration;
+      * with stop_every = S, the stopping test (eq:stopping at z~, and the NaN
+        check) also runs at every t with t mod S == 0 between those evaluation
+        points; nothing else happens there (no residual, no restart or
+        infeasibility test), so the iterates are those of the run without it
+        and the LP only stops sooner.
     """
     n, m = lp.n, lp.m
     if np.any(lp.xl > lp.xu):
@@ -376,6 +396,7 @@ def solve(lp: LP, opt: Options = Options(), x_init=None, y_init=None,
     r_prev = None
     restarts: List[int] = []
     C = opt.eval_every
+    S = _stop_every(opt)
     eps_inf = _infeasibility_eps(opt)
 
     while True:
@@ -385,7 +406,7 @@ def solve(lp: LP, opt: Options = Options(), x_init=None, y_init=None,
         evaluate = full or k == 0
         r = fixed_point_residual(lp, x, y, x_t, y_t, w, eta, opt.cross_sign) if evaluate else None
         kk = None
-        if full:
+        if full or (S and t % S == 0):
             kk = kkt(lp, x_t, y_t)
         if (r is not None and not math.isfinite(r)) or (kk is not None and not math.isfinite(kk.rel)):
             return Result(NUMERICAL_ERROR, x_t, y_t, None, None, t + 1, restarts, w, eta,
@@ -429,7 +450,11 @@ def solve_batch_avg(lps: Sequence[LP], opt: Options = Options(), x_inits=None, y
     the average residual over the batch, and when they fire all LPs restart
     together, each smoothing its own weight.  The paper does not say which LPs
     enter the average once some have stopped; reading: the LPs still running
-    after this evaluation's stopping tests."""
+    after this evaluation's stopping tests.  The extra stopping tests of
+    stop_every belong to the per-LP scope only (an LP leaving between two
+    evaluations would change the average the others restart on)."""
+    if _stop_every(opt):
+        raise ValueError("stop_every applies to the per-LP restart scope only")
     N = len(lps)
     res: List[Optional[Result]] = [None] * N
     state = []

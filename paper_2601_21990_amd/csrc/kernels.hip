@@ -896,7 +896,7 @@ __global__ __launch_bounds__(256) void k_reduce(ControlArgs a) {
     const int32_t lane = threadIdx.x & 63;
     const int32_t pair = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (pair >= 2 * NTERM * a.ncols) return;
-    if (!a.full && !a.admit && a.g->quiet) return;
+    if (!a.full && !a.admit && !a.stop_only && a.g->quiet) return;
     const int32_t q = pair / a.ncols, s = pair % a.ncols;
     const bool xside = q < NTERM;
     const int32_t qq = xside ? q : q - NTERM;
@@ -967,10 +967,10 @@ __device__ void restart_slot(const Slots& sl, int32_t s, SlotKey& key, SlotCtl& 
 // slot marked for retirement), else 0; *r_out and *resid_out give the residual
 // and whether it was taken, for the batch-average scope.  No product is fused
 // into a later addition, so every kernel calling this computes the same bits.
-__device__ int32_t control_slot(const ControlArgs& a, bool full, int32_t s, SlotKey& st,
-                                SlotCtl& cl, int32_t* rlog, const double* sx, const double* sy,
-                                int32_t ld, int32_t t, double eta, bool per_lp, double* r_out,
-                                bool* resid_out) {
+__device__ int32_t control_slot(const ControlArgs& a, bool full, bool stop, int32_t s,
+                                SlotKey& st, SlotCtl& cl, int32_t* rlog, const double* sx,
+                                const double* sy, int32_t ld, int32_t t, double eta, bool per_lp,
+                                double* r_out, bool* resid_out) {
 #pragma clang fp contract(off)
     // sx, sy point at the slot's sums: term q at [q * ld]
     const double tol = cl.tol;
@@ -994,21 +994,23 @@ __device__ int32_t control_slot(const ControlArgs& a, bool full, int32_t s, Slot
     // an LP that ran out of budget before this evaluation is evaluated at its final z~
     const bool at_eval = (t <= st.t_end);
     const bool full_here = full && at_eval;
+    // the stopping test runs at full evaluations and at the stopping tests in between
+    const bool test_here = (full || stop) && at_eval;
     const bool resid_here = at_eval && (full || k == 0);
     // order of the tests: NaN, stopping, infeasibility, iteration limit
     const double eps_inf = a.infeas_tol < 0.0 ? tol : a.infeas_tol;
     const int32_t infeas = (full_here && eps_inf > 0.0) ? infeasible(sx, sy, ld, 0, eps_inf) : 0;
     int32_t status = PDLPB_STATUS_RUNNING;
-    if ((resid_here && !isfinite(r)) || (full_here && !isfinite(rel))) {
+    if ((resid_here && !isfinite(r)) || (test_here && !isfinite(rel))) {
         status = PDLPB_STATUS_NUMERICAL_ERROR;
-    } else if (full_here && gap <= tol && pri <= tol && dua <= (a.dual_tol < 0.0 ? tol : a.dual_tol)) {
+    } else if (test_here && gap <= tol && pri <= tol && dua <= (a.dual_tol < 0.0 ? tol : a.dual_tol)) {
         status = PDLPB_STATUS_OPTIMAL;
     } else if (infeas) {
         status = infeas;
     } else if (final_now) {
         status = PDLPB_STATUS_ITERATION_LIMIT;
     }
-    if (full || k == 0 || final_now) {   // the evaluation computed this LP's sums
+    if (full || stop || k == 0 || final_now) {   // the evaluation computed this LP's sums
         cl.kkt[0] = gap; cl.kkt[1] = pri; cl.kkt[2] = dua; cl.kkt[3] = rel;
         cl.obj = cx;
         cl.dobj = -phis;
@@ -1056,7 +1058,7 @@ __global__ __launch_bounds__(1024) void k_control(ControlArgs a) {
     __shared__ int32_t sh_flags[MAX_BATCH];
     __shared__ int32_t sh_flag;
     Globals* g = a.g;
-    if (!a.full && !a.admit && g->quiet) return;
+    if (!a.full && !a.admit && !a.stop_only && g->quiet) return;
     const int32_t t = g->t0 + a.it;
     const int32_t nc = min(a.ncols, g->n_cols);
     const double eta = g->eta;
@@ -1085,8 +1087,9 @@ __global__ __launch_bounds__(1024) void k_control(ControlArgs a) {
         }
         double r = 0.0;
         bool resid_here = false;
-        if (control_slot(a, a.full != 0, s, st, cl, a.rlog + (size_t)lp * RESTART_LOG, sx + s,
-                          sy + s, a.ld, t, eta, !a.batch_avg, &r, &resid_here))
+        if (control_slot(a, a.full != 0, a.stop_only != 0, s, st, cl,
+                         a.rlog + (size_t)lp * RESTART_LOG, sx + s, sy + s, a.ld, t, eta,
+                         !a.batch_avg, &r, &resid_here))
             continue;
         my_active += 1;
         if (a.batch_avg && resid_here) {   // indexed by LP: the average adds LPs in LP order
@@ -1162,7 +1165,7 @@ __global__ __launch_bounds__(1024) void k_control(ControlArgs a) {
     if (threadIdx.x == 0 && (a.full || a.admit))
         g->quiet = (a.full && !a.admit && !a.batch_avg && sh_n[0] == 0) ? 1 : 0;
 
-    // compaction plan (full evaluations): live prefix [0, n_run)
+    // compaction plan (full evaluations and stopping tests): live prefix [0, n_run)
     if (a.admit) {
         if (threadIdx.x == 0) {
             g->n_retire = 0;
@@ -1170,7 +1173,7 @@ __global__ __launch_bounds__(1024) void k_control(ControlArgs a) {
             g->n_fresh = 0;
             g->n_cols_next = nc;
         }
-    } else if (a.full) {
+    } else if (a.full || a.stop_only) {
         for (int32_t s = threadIdx.x; s < nc; s += blockDim.x) sh_flags[s] = a.sl.key[s].flags;
         __syncthreads();
         if (threadIdx.x == 0) {
@@ -1558,9 +1561,10 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(TailArgs<T> a) {
             const int32_t t = t0 + it;
             const SlotKey key = *keyp;
             const int32_t k = t - key.t_anchor;
+            const bool stop_it = a.S > 0 && it % a.S == 0 && it != a.C;
             if ((key.flags & SLOT_ACTIVE) && t <= key.t_end) {
                 // the evaluation after this iteration reads z~ and the displacement
-                const bool keep = t == key.t_end || it == a.C || (it == 1 && k == 0);
+                const bool keep = t == key.t_end || it == a.C || (it == 1 && k == 0) || stop_it;
                 const T tau = T(a.sl.tau[s]);
                 for (int32_t i0 = tid; i0 < n; i0 += TAIL_ROWS * TAIL_THREADS) {
                     TailEll<T> e[TAIL_ROWS];
@@ -1628,17 +1632,18 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(TailArgs<T> a) {
                 }
                 __syncthreads();
             }
-            if (it != 1 && it != a.C) continue;
+            if (it != 1 && it != a.C && !stop_it) continue;
             const bool full = it == a.C;
-            // between full evaluations only a fresh cycle or a last iteration is evaluated
-            if (!(full || t == key.t_anchor || t >= key.t_end)) continue;
+            // between full evaluations only a fresh cycle, a stopping test or a last
+            // iteration is evaluated
+            if (!(full || stop_it || t == key.t_anchor || t >= key.t_end)) continue;
             tail_eval_side<T>(a, v, s, key.varkind, true, chain_x, panel_x, sums, terms, lane, wave, tid);
             tail_eval_side<T>(a, v, s, key.varkind, false, chain_y, panel_y, sums + NTERM, terms, lane,
                               wave, tid);
             if (tid == 0) {
                 double r = 0.0;
                 bool rh = false;
-                sh_stop = control_slot(a.ca, full, s, *keyp, a.ctl[lp],
+                sh_stop = control_slot(a.ca, full, stop_it, s, *keyp, a.ctl[lp],
                                        a.rlog + (size_t)lp * RESTART_LOG, sums, sums + NTERM, 1, t,
                                        eta, true, &r, &rh);
             }

@@ -554,9 +554,12 @@ int enqueue_iteration(pdlpb_ctx* x, int32_t it, int32_t eval,
 
 template <typename T>
 int enqueue_evaluation(pdlpb_ctx* x, int32_t it, int32_t full, int32_t advance,
-                       std::vector<std::pair<int, int>>* rec, int32_t admit = 0) {
-    EvalArgs<T> e = eval_args<T>(x, it, full);
+                       std::vector<std::pair<int, int>>* rec, int32_t admit = 0,
+                       int32_t stop = 0) {
+    // a stopping test alone needs the sums of every running LP, as a full evaluation does
+    EvalArgs<T> e = eval_args<T>(x, it, full || stop);
     ControlArgs c = control_args(x, it, full, advance, admit);
+    c.stop_only = stop;
     int idx = -1;
     if (rec) idx = timed_begin(x, 2, *rec);
     HIP_TRY(x, launch_eval<T>(e, x->stream));
@@ -564,7 +567,7 @@ int enqueue_evaluation(pdlpb_ctx* x, int32_t it, int32_t full, int32_t advance,
     if (rec) idx = timed_begin(x, 3, *rec);
     HIP_TRY(x, launch_reduce(c, x->stream));
     HIP_TRY(x, launch_control(c, x->stream));
-    if (full) {
+    if (full || stop) {
         T* const* b = reinterpret_cast<T* const*>(x->blk);
         T* const* r = reinterpret_cast<T* const*>(x->res);
         HIP_TRY(x, launch_compact<T>(x->n, x->m, x->ld, x->live, b, r, x->retire, x->moves,
@@ -574,17 +577,34 @@ int enqueue_evaluation(pdlpb_ctx* x, int32_t it, int32_t full, int32_t advance,
     return PDLPB_OK;
 }
 
+// Interval S of the stopping tests between full evaluations (option
+// stop_every), 0 when they are off: per-LP restart scope and batches only.
+// S >= 2 divides C, so a stopping test never falls on the first iteration of a
+// block (the fresh-cycle evaluation) or on its last (the full one).
+int32_t stop_interval(const pdlpb_ctx* x) {
+    const int32_t S = x->opt.stop_every, C = x->opt.eval_every;
+    if (S <= 0 || S >= C || x->serving || x->opt.restart_scope != PDLPB_RESTART_PER_LP) return 0;
+    return S;
+}
+bool stop_at(const pdlpb_ctx* x, int32_t it) {
+    const int32_t S = stop_interval(x);
+    return S > 0 && it % S == 0 && it != x->opt.eval_every;
+}
+
 // one block of C iterations: t = t0+1 .. t0+C; residual of fresh cycles at the
-// first, full evaluation (KKT, restarts) at the last
+// first, stopping tests every S, full evaluation (KKT, restarts) at the last
 template <typename T>
 int enqueue_epoch(pdlpb_ctx* x, std::vector<std::pair<int, int>>* rec) {
     const int32_t C = x->opt.eval_every;
     for (int32_t it = 1; it <= C; ++it) {
-        // z~ stored by every LP before the full evaluation, by fresh cycles before the first
-        const int32_t ev = it == C ? 2 : (it == 1 ? 1 : 0);
+        // z~ stored by every LP before the full evaluation and the stopping
+        // tests, by fresh cycles before the first
+        const bool stop = stop_at(x, it);
+        const int32_t ev = (it == C || stop) ? 2 : (it == 1 ? 1 : 0);
         int rc = enqueue_iteration<T>(x, it, ev, rec);
         if (rc) return rc;
         if (it == C) rc = enqueue_evaluation<T>(x, it, 1, 1, rec);
+        else if (stop) rc = enqueue_evaluation<T>(x, it, 0, 0, rec, 0, 1);
         else if (it == 1) rc = enqueue_evaluation<T>(x, it, 0, 0, rec);
         if (rc) return rc;
     }
@@ -643,7 +663,8 @@ int tune_epoch(pdlpb_ctx* x) {
     std::vector<std::pair<int, int>> rec;   // (candidate * 2 + kernel, event pair)
     const Tile keep_p = x->tp, keep_d = x->td;
     for (int32_t it = 1; it <= C; ++it) {
-        const bool ev = (it == 1 || it == C);
+        const bool stop = stop_at(x, it);
+        const bool ev = (it == 1 || it == C || stop);
         int c = -1;
         if (!ev && nc > 0) {
             c = (it - 2) % nc;
@@ -652,7 +673,7 @@ int tune_epoch(pdlpb_ctx* x) {
             x->tp = keep_p;
             x->td = keep_d;
         }
-        const int32_t lev = it == C ? 2 : (it == 1 ? 1 : 0);
+        const int32_t lev = (it == C || stop) ? 2 : (it == 1 ? 1 : 0);
         StepArgs<T> p = step_args<T>(x, true, it, lev);
         StepArgs<T> d = step_args<T>(x, false, it, lev);
         for (int kern = 0; kern < 2; ++kern) {
@@ -664,6 +685,7 @@ int tune_epoch(pdlpb_ctx* x) {
         }
         int rc = PDLPB_OK;
         if (it == C) rc = enqueue_evaluation<T>(x, it, 1, 1, nullptr);
+        else if (stop) rc = enqueue_evaluation<T>(x, it, 0, 0, nullptr, 0, 1);
         else if (it == 1) rc = enqueue_evaluation<T>(x, it, 0, 0, nullptr);
         if (rc) return rc;
     }
@@ -746,6 +768,7 @@ int run_tail(pdlpb_ctx* x, int32_t n_cols, std::vector<std::pair<int, int>>* rec
     }
     TailArgs<T> a{};
     a.n = x->n; a.m = x->m; a.ld = x->ld; a.C = x->opt.eval_every; a.ncols = n_cols;
+    a.S = stop_interval(x);
     a.a_rp = x->a_rp; a.a_ci = x->a_ci; a.t_rp = x->t_rp; a.t_ci = x->t_ci;
     if constexpr (sizeof(T) == 8) {
         a.a_v = reinterpret_cast<const T*>(x->a_v64);
@@ -1445,6 +1468,9 @@ int pdlpb_create(pdlpb_ctx** out, int32_t m, int32_t n, int64_t nnz, const int64
     if (o.tile_vec != 0 && o.tile_vec != 1 && o.tile_vec != 2 && o.tile_vec != 4)
         return bad("tile_vec must be 0, 1, 2 or 4");
     if (o.tail_cols < 0 || o.tail_cols > 64) return bad("tail_cols must be in [0, 64]");
+    if (o.stop_every != 0 && o.stop_every != o.eval_every &&
+        (o.stop_every < 2 || o.eval_every % o.stop_every != 0))
+        return bad("stop_every must be 0 or a divisor >= 2 of eval_every");
     if ((o.dev_alloc == nullptr) != (o.dev_free == nullptr))
         return bad("dev_alloc and dev_free must both be set or both be NULL");
     // CSR structure

@@ -169,6 +169,7 @@ struct ControlArgs {
     Globals* g;
     int32_t it;              // iteration index inside the block
     int32_t full;            // 1: KKT and restart tests (t mod C == 0); 0: residual of fresh cycles only
+    int32_t stop_only;       // 1 (with full = 0): the stopping test alone, at every LP (t mod S == 0)
     int32_t advance;         // 1: move g->t0 on by `block` after this pass
     int32_t block;           // C
     int32_t batch_avg;       // restart scope
@@ -185,6 +186,7 @@ constexpr int32_t TAIL_THREADS = 512;
 template <typename T>
 struct TailArgs {
     int32_t n, m, ld, C;
+    int32_t S;                 // stopping tests also every S iterations of a block (0: off)
     int32_t ncols;             // workgroups: slots [0, ncols)
     const int32_t* a_rp; const int32_t* a_ci; const T* a_v;    // A (m x n)
     const int32_t* t_rp; const int32_t* t_ci; const T* t_v;    // A' (n x m)

@@ -104,6 +104,9 @@ def test_create_rejects_malformed_input(over, msg):
     (dict(max_blocks=-1), "max_blocks"),
     (dict(dev_alloc=1), "dev_alloc and dev_free"),
     (dict(dev_free=1), "dev_alloc and dev_free"),
+    (dict(eval_every=24, stop_every=1), "stop_every"),
+    (dict(eval_every=24, stop_every=5), "stop_every"),
+    (dict(eval_every=24, stop_every=48), "stop_every"),
 ])
 def test_create_rejects_bad_options(opt, msg):
     with pytest.raises(P.PdlpbError) as e:

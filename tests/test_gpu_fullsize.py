@@ -6,7 +6,8 @@ column), FP64, B = 512.
   iterations (one full evaluation with its restart tests).
 * The strong-branching batch of the benchmark line, converged: the base LP
   solved on the GPU, 512 bound changes on 256 fractional variables of its
-  root, warm start from it, C = 24, tolerance 1e-4.
+  root, warm start from it, C = 24 with stopping tests every 12 iterations,
+  tolerance 1e-4.
 
 The oracle recomputes a sample of the LPs one at a time with the same step
 size and start; every LP of the batch must also be finite and still running
@@ -74,8 +75,8 @@ def test_mixed32_line_points_meet_tolerance_against_a(P, line_root):
     inst, lp, eta, root, w, D = line_root
     res = {}
     for prec in (P.FP64, P.MIXED32):
-        with P.Context.from_instance(inst, eval_every=24, max_batch=512, step_size=eta,
-                                     precision=prec) as ctx:
+        with P.Context.from_instance(inst, eval_every=24, stop_every=12, max_batch=512,
+                                     step_size=eta, precision=prec) as ctx:
             ctx.set_batch(D, x_warm=root["x"], y_warm=root["y"], w_warm=np.full(len(D), w))
             ctx.solve(tol=1e-4, max_iters=3000)
             res[prec] = ctx.get_batch()
@@ -107,9 +108,10 @@ def test_strong_branching_line_sampled_lps_match_oracle(P, line_root):
     the rounding of the terms mixed into it, e.g. 4.1e-9 on an entry of 0.58,
     2.3e-12 of the vector's scale; the norm-relative check stays at 1e-9."""
     inst, lp, eta, root, w, D = line_root
-    C = 24
+    C, S = 24, 12
     assert len(D) == 512
-    with P.Context.from_instance(inst, eval_every=C, max_batch=512, step_size=eta) as ctx:
+    with P.Context.from_instance(inst, eval_every=C, stop_every=S, max_batch=512,
+                                 step_size=eta) as ctx:
         ctx.set_batch(D, x_warm=root["x"], y_warm=root["y"], w_warm=np.full(len(D), w))
         ctx.solve(tol=1e-4, max_iters=100000)
         st = ctx.get_batch(want_x=False, want_y=False)
@@ -118,7 +120,8 @@ def test_strong_branching_line_sampled_lps_match_oracle(P, line_root):
         res = {j: (ctx.get(j), ctx.get_trace(j)) for j in sample}
     # the same LPs alone (one column, never moved to narrow storage): the same
     # bits as in the batch, whose last LPs ran in blocks of stride 16
-    with P.Context.from_instance(inst, eval_every=C, max_batch=1, step_size=eta) as one:
+    with P.Context.from_instance(inst, eval_every=C, stop_every=S, max_batch=1,
+                                 step_size=eta) as one:
         for j in sample:
             one.set_batch(D[j:j + 1], x_warm=root["x"], y_warm=root["y"], w_warm=np.full(1, w))
             one.solve(tol=1e-4, max_iters=100000)
@@ -134,6 +137,6 @@ def test_strong_branching_line_sampled_lps_match_oracle(P, line_root):
     assert np.all(st["kkt"][st["status"] == P.STATUS_OPTIMAL, 3] <= 1e-4)
     for j in sample:
         ores = oracle_run(lp_for(lp, D[j]), eta, 1e-4, 100000, root["x"], root["y"], w,
-                          eval_every=C)
+                          eval_every=C, stop_every=S)
         print("LP", j, "iters", res[j][0]["iters"], "restarts", res[j][1]["restart_log"][:8])
         assert_trajectory_match(*res[j], ores, what=f"line LP {j}", floor="rms")

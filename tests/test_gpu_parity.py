@@ -125,6 +125,32 @@ def test_cfg2_batch_converged(P, C):
     assert same_traj == len(D)
 
 
+@pytest.mark.parametrize("C, S", [(32, 8), (24, 8), (24, 4)])
+def test_cfg2_batch_converged_with_stop_tests(P, C, S):
+    """Stopping tests every S iterations between the full evaluations: the
+    batch (restart tests, compaction and moves now also at the stopping tests)
+    follows the oracle run with the same schedule, LP by LP: statuses,
+    iteration counts, restart logs and iterates; and no LP stops later than
+    without the tests."""
+    inst, lp, eta, base, D = cfg2_setup()
+    outs = {}
+    for stop in (0, S):
+        with _cfg2_ctx(P, inst, eta, base, D, eval_every=C, stop_every=stop) as ctx:
+            ctx.solve(tol=1e-4, max_iters=100000)
+            out = ctx.get_batch()
+            out["traces"] = [ctx.get_trace(j) for j in range(len(D))]
+            outs[stop] = out
+    out = outs[S]
+    assert np.all(out["iters"] <= outs[0]["iters"])
+    assert np.any(out["iters"] < outs[0]["iters"])
+    for j, d in enumerate(D):
+        ores = oracle_run(lp_for(lp, d), eta, 1e-4, 100000, base.x, base.y, base.w,
+                          eval_every=C, stop_every=S)
+        g = {"status": out["status"][j], "iters": out["iters"][j], "x": out["X"][j],
+             "y": out["Y"][j], "kkt": out["kkt"][j], "obj": out["obj"][j]}
+        assert_trajectory_match(g, out["traces"][j], ores, what=(C, S, j))
+
+
 def test_batched_equals_independent(P):
     """Each LP's result does not depend on the batch around it: bitwise equal
     alone (B = 1), in a small batch, and in the full batch."""

@@ -45,14 +45,17 @@ def _same(a, b):
         assert ta["w"] == tb["w"] and ta["restart_log"] == tb["restart_log"]
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_tail_equals_batched_kernels_converged(P, prec):
+@pytest.mark.parametrize("prec, stop", [("fp64", 0), ("fp32", 0), ("fp64", 8)])
+def test_tail_equals_batched_kernels_converged(P, prec, stop):
     """The 2000 x 5000 strong-branching batch (64 LPs, warm start, one
-    infeasible branch in the family): the last LPs finish in the tail."""
+    infeasible branch in the family): the last LPs finish in the tail; with
+    stop = 8 both also run stopping tests between the full evaluations."""
     inst, lp, eta, base, D = cfg2_setup()
     precision = P.MIXED32 if prec == "fp32" else P.FP64
-    a = _run(P, inst, eta, D, 1e-4, 100000, 8, warm=base, precision=precision, eval_every=32)
-    b = _run(P, inst, eta, D, 1e-4, 100000, 0, warm=base, precision=precision, eval_every=32)
+    a = _run(P, inst, eta, D, 1e-4, 100000, 8, warm=base, precision=precision, eval_every=32,
+             stop_every=stop)
+    b = _run(P, inst, eta, D, 1e-4, 100000, 0, warm=base, precision=precision, eval_every=32,
+             stop_every=stop)
     assert a["tail_launches"] == 1 and b["tail_launches"] == 0
     _same(a, b)
 
