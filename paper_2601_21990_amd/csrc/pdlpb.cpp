@@ -591,6 +591,8 @@ bool stop_at(const pdlpb_ctx* x, int32_t it) {
     return S > 0 && it % S == 0 && it != x->opt.eval_every;
 }
 
+int read_counts(pdlpb_ctx* x, int32_t* n_active, int32_t* n_cols);
+
 // one block of C iterations: t = t0+1 .. t0+C; residual of fresh cycles at the
 // first, stopping tests every S, full evaluation (KKT, restarts) at the last
 template <typename T>
@@ -603,9 +605,21 @@ int enqueue_epoch(pdlpb_ctx* x, std::vector<std::pair<int, int>>* rec) {
         const int32_t ev = (it == C || stop) ? 2 : (it == 1 ? 1 : 0);
         int rc = enqueue_iteration<T>(x, it, ev, rec);
         if (rc) return rc;
-        if (it == C) rc = enqueue_evaluation<T>(x, it, 1, 1, rec);
-        else if (stop) rc = enqueue_evaluation<T>(x, it, 0, 0, rec, 0, 1);
-        else if (it == 1) rc = enqueue_evaluation<T>(x, it, 0, 0, rec);
+        if (it == C) {
+            rc = enqueue_evaluation<T>(x, it, 1, 1, rec);
+        } else if (stop) {
+            rc = enqueue_evaluation<T>(x, it, 0, 0, rec, 0, 1);
+            // timed launches record the live columns they run on, and after a
+            // stopping test the device may hold fewer (eager timing only: the
+            // host waits for the count; a captured block never does)
+            if (!rc && rec) {
+                int32_t n_active = 0, n_cols = 0;
+                rc = read_counts(x, &n_active, &n_cols);
+                if (!rc) x->cur_cols = n_cols;
+            }
+        } else if (it == 1) {
+            rc = enqueue_evaluation<T>(x, it, 0, 0, rec);
+        }
         if (rc) return rc;
     }
     return PDLPB_OK;
