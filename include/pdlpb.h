@@ -111,7 +111,19 @@ typedef struct pdlpb_options {
     int32_t tile_vec;         /* 0 = automatic; else columns per lane (1, 2 or 4) */
     int32_t autotune;         /* 1 (default): time tile shapes on the first block of C iterations of
                                  a large batch and keep the fastest per kernel; 0: fixed heuristic */
-    int32_t reserved_pad;     /* zero */
+    int32_t shared_start;     /* first iteration of a batch whose running LPs all start from one point
+                                 (PDLPB_WARM_NONE or PDLPB_WARM_SHARED), the objective changes with
+                                 one primal weight and the other LPs with one primal weight
+                                 (Section 5: the LPs differ from a common LP in one variable): it is
+                                 made once for the common LP (and once for it with objective 0 when
+                                 the batch holds objective changes) and per LP only at its variable
+                                 and the rows of A through it; the evaluation at t = 0 likewise; the
+                                 dense blocks are then written only for the LPs still running.  The
+                                 results are those of the full-width path, bit for bit.  0 (default):
+                                 when the batch's blocks hold at least 8 MB; 1: whenever the batch
+                                 qualifies; -1: never.  A change qualifies when its variable's
+                                 column has at most 64 nonzeros and the rows through it at most
+                                 4095 in all */
     double  dual_tol;         /* eps of the dual-feasibility test of eq:stopping: < 0 (default -1) uses the
                                  stopping tolerance; >= 0 as given.  The bound-tightening experiments of
                                  Section 6 check dual feasibility at 1e-8 before trusting a dual bound */

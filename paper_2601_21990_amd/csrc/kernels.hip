@@ -1845,6 +1845,526 @@ __global__ void k_fill(double* x, int32_t len, double v) {
     if (i < len) x[i] = v;
 }
 
+// ---------------------------------------------------------------------------
+// Shared start (Section 5: the LPs of a strong-branching or bound-tightening
+// batch each change one variable of a common LP).  When every running LP
+// starts from the same point, with the same step sizes as the other LPs of its
+// base LP, T(z^0) of an LP
+// differs from that of its base LP -- the common LP, or for an objective
+// change the common LP with objective 0 -- only at its variable v (x^0 for a
+// bound change; x~, x-bar, dx) and at the rows of A through v (y~, y^1, dy).
+// Its evaluation terms at t = 0 then differ only on x rows that are v or
+// share a row of A with v and on y rows through v, and a chain of rows
+// (evaluation panel unit) without such a row sums to its base LP's value.
+// These kernels make the first iteration of each base LP once, of each LP
+// only at those coordinates, the terms and chain sums of each base LP once,
+// and each LP's chains only where it differs.  Products, coordinate updates,
+// terms and sums are those of the step and evaluation kernels, in the same
+// order, so every LP's panel sums are the bits k_eval computes from its
+// blocks.  After the control pass the blocks are written only for the LPs
+// that still run, at their slots after the compaction, and the stopped LPs'
+// results go straight to the result blocks.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ int32_t sp_class(const SharedArgs<T>& a, int32_t varkind) {
+    return ((uint32_t)varkind >> 28) == (uint32_t)PDLPB_OBJ_UNIT ? a.cls_obj : a.cls_bound;
+}
+// delta key of base LP K (no variable)
+template <typename T>
+__device__ __forceinline__ int32_t sp_base_key(const SharedArgs<T>& a, int32_t K) {
+    return VAR_NONE | (a.cls_kind[K] << 28);
+}
+// y^0 as the blocks hold it
+template <typename T>
+__device__ __forceinline__ T sp_y0(const SharedArgs<T>& a, int32_t r) {
+    return a.yw ? T(a.yw[r]) : T(0);
+}
+
+// x^0 on the base box and, per base LP, x~, x-bar and dx of the first step:
+// one thread per variable, (A'y^0)_i summed in CSR order from 0 as the primal
+// step kernel sums it.
+template <typename T>
+__global__ __launch_bounds__(256) void k_sp_primal(SharedArgs<T> a) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    const double lo = a.xl[i], hi = a.xu[i];
+    const T x0 = T(clampd(a.xw ? a.xw[i] : 0.0, lo, hi));
+    T g = T(0);
+    for (int32_t k = a.t_rp[i]; k < a.t_rp[i + 1]; ++k) g = fma(a.t_v[k], sp_y0(a, a.t_ci[k]), g);
+    a.x0[i] = x0;
+    for (int32_t K = 0; K < a.ncls; ++K) {
+        const VarData d = var_data(sp_base_key(a, K), nullptr, 0, i, a.c[i], lo, hi);
+        T xk, xt, xbar;
+        primal_point<T>(0, T(0), x0, T(a.tau[K]), d.c, d.lo, d.hi, g, xk, xt, xbar);
+        const size_t e = (size_t)K * a.n + i;
+        a.xt[e] = xt;
+        a.xbar[e] = xbar;
+        a.dx[e] = xt - xk;
+    }
+}
+
+// y^0 and, per base LP, y~, y^1 and dy of the first step: one thread per row.
+template <typename T>
+__global__ __launch_bounds__(256) void k_sp_dual(SharedArgs<T> a) {
+    const int32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= a.m) return;
+    const T y0 = sp_y0(a, r);
+    const T l = T(a.rl[r]), u = T(a.ru[r]);
+    a.y0[r] = y0;
+    for (int32_t K = 0; K < a.ncls; ++K) {
+        const T* xb = a.xbar + (size_t)K * a.n;
+        T v = T(0);
+        for (int32_t k = a.a_rp[r]; k < a.a_rp[r + 1]; ++k) v = fma(a.a_v[k], xb[a.a_ci[k]], v);
+        T yt, yn;
+        dual_point<T>(y0, y0, T(a.sigma[K]), T(halpern_a(0)), T(2), l, u, v, yt, yn);
+        const size_t e = (size_t)K * a.m + r;
+        a.yt[e] = yt;
+        a.yn[e] = yn;
+        a.dy[e] = yt - y0;
+    }
+}
+
+// The first step of each LP where it differs from its base LP: x at its
+// variable v (its own box and objective entry), then y at the rows of A
+// through v, whose products read its own x-bar at v.  One wave per slot.
+template <typename T>
+__global__ __launch_bounds__(256) void k_sp_side(SharedArgs<T> a) {
+    const int lane = threadIdx.x & 63;
+    const int32_t s = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (s >= a.nslots) return;
+    const int32_t vk = a.sl.key[s].varkind;
+    const int32_t v = vk & VAR_MASK;
+    if (v == VAR_NONE) return;
+    const int32_t K = sp_class(a, vk);
+    T* side = a.side + (size_t)s * SP_SIDE;
+    const VarData d0 = var_data(vk, a.sl.dval, s, v, 0.0, a.xl[v], a.xu[v]);
+    const T x0 = T(clampd(a.xw ? a.xw[v] : 0.0, d0.lo, d0.hi));
+    const int32_t kb = a.t_rp[v];
+    const int32_t nv = min(a.t_rp[v + 1] - kb, SP_MAX_COL);
+    T g = T(0);
+    for (int32_t k = kb; k < a.t_rp[v + 1]; ++k) g = fma(a.t_v[k], sp_y0(a, a.t_ci[k]), g);
+    const VarData d = var_data(vk, a.sl.dval, s, v, a.c[v], a.xl[v], a.xu[v]);
+    T xk, xt, xbar;
+    primal_point<T>(0, T(0), x0, T(a.tau[K]), d.c, d.lo, d.hi, g, xk, xt, xbar);
+    if (lane == 0) {
+        side[0] = x0;
+        side[1] = xt;
+        side[2] = xbar;
+        side[3] = xt - xk;
+    }
+    const T* xb = a.xbar + (size_t)K * a.n;
+    for (int32_t q = lane; q < nv; q += 64) {
+        const int32_t r = a.t_ci[kb + q];
+        T p = T(0);
+        for (int32_t k = a.a_rp[r]; k < a.a_rp[r + 1]; ++k) {
+            const int32_t j = a.a_ci[k];
+            p = fma(a.a_v[k], j == v ? xbar : xb[j], p);
+        }
+        const T y0 = a.y0[r];
+        T yt, yn;
+        dual_point<T>(y0, y0, T(a.sigma[K]), T(halpern_a(0)), T(2), T(a.rl[r]), T(a.ru[r]), p, yt,
+                      yn);
+        T* o = side + 4 + 3 * q;
+        o[0] = yt;
+        o[1] = yn;
+        o[2] = yt - y0;
+    }
+}
+
+// Evaluation terms of x row i (x~, dx, x^0 at i given; y~ and dy at row r of A
+// from yat) and of y row r (y~, dy, y^0 at r given; x~ and dx at column j from
+// xat): the products in CSR order and the terms of k_eval.
+template <typename T, typename YAt>
+__device__ __forceinline__ void sp_xterms(const SharedArgs<T>& a, int32_t i, T xt, T dx, T x0,
+                                          int32_t varkind, int32_t s, YAt yat, double* tv) {
+    double g = 0.0, h = 0.0, pdy = 0.0;
+    for (int32_t k = a.t_rp[i]; k < a.t_rp[i + 1]; ++k) {
+        const int32_t r = a.t_ci[k];
+        T yv, dv;
+        yat(r, yv, dv);
+        const double w = (double)a.t_v[k], d = (double)dv;
+        g = fma(w, (double)yv, g);
+        h = fma(w, d, h);
+        pdy = fma(w, barrier_code(d, a.rcode[r]), pdy);
+    }
+    finish_xrow(XRowIn<T>{xt, dx, x0, a.c[i], a.xl[i], a.xu[i]}.wide(), g, h, pdy, varkind,
+                a.sl.dval, s, i, tv);
+}
+template <typename T, typename XAt>
+__device__ __forceinline__ void sp_yterms(const SharedArgs<T>& a, int32_t r, T yt, T dy, T y0,
+                                          XAt xat, double* tv) {
+    double ax = 0.0, adx = 0.0;
+    for (int32_t k = a.a_rp[r]; k < a.a_rp[r + 1]; ++k) {
+        T xv, dv;
+        xat(a.a_ci[k], xv, dv);
+        const double w = (double)a.a_v[k];
+        ax = fma(w, (double)xv, ax);
+        adx = fma(w, (double)dv, adx);
+    }
+    finish_yrow(YRowIn<T>{yt, dy, y0, a.rl[r], a.ru[r]}.wide(), ax, adx, tv);
+}
+
+// Terms of every row of each base LP, and its chain and panel sums: one
+// workgroup per (panel, base LP) in the layout of k_eval_narrow (wave w sums
+// rows [p0 + w pw, p0 + (w + 1) pw) in row order, 64 rows at a time, lane q
+// adding term q; the panel sum is ((c0 + c1) + c2) + c3).
+template <typename T>
+__global__ __launch_bounds__(256) void k_sp_terms(SharedArgs<T> a) {
+    __shared__ double terms[4][64][NTERM + 1];
+    __shared__ double red[4][NTERM];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int32_t pidx = blockIdx.x, K = blockIdx.y;
+    const int32_t np = a.npx + a.npy;
+    const bool xside = pidx < a.npx;
+    const int32_t panel = xside ? pidx : pidx - a.npx;
+    const int32_t pw = xside ? a.pw_x : a.pw_y;
+    const int32_t rows = xside ? a.n : a.m;
+    const int32_t r0 = panel * 4 * pw + wave * pw;
+    const int32_t r1 = min(r0 + pw, rows);
+    const int32_t key = sp_base_key(a, K);
+    const T* xt = a.xt + (size_t)K * a.n;
+    const T* dx = a.dx + (size_t)K * a.n;
+    const T* yt = a.yt + (size_t)K * a.m;
+    const T* dy = a.dy + (size_t)K * a.m;
+    double* rt = a.rt + (size_t)K * ((size_t)a.n + a.m) * NTERM;
+    double acc = 0.0;
+    for (int32_t off = 0; off < pw; off += 64) {
+        const int32_t rb = r0 + off;
+        const int32_t i = rb + lane;
+        if (i < r1) {
+            double tq[NTERM];
+            if (xside) {
+                sp_xterms(a, i, xt[i], dx[i], a.x0[i], key, 0,
+                          [&](int32_t r, T& yv, T& dv) {
+                              yv = yt[r];
+                              dv = dy[r];
+                          },
+                          tq);
+            } else {
+                sp_yterms(a, i, yt[i], dy[i], a.y0[i],
+                          [&](int32_t j, T& xv, T& dv) {
+                              xv = xt[j];
+                              dv = dx[j];
+                          },
+                          tq);
+            }
+            double* o = rt + (size_t)(xside ? i : a.n + i) * NTERM;
+#pragma unroll
+            for (int q = 0; q < NTERM; ++q) {
+                o[q] = tq[q];
+                terms[wave][lane][q] = tq[q];
+            }
+        }
+        __syncthreads();
+        if (lane < NTERM) {
+            const int32_t cnt = min(64, r1 - rb);
+            for (int32_t j = 0; j < cnt; ++j) acc += terms[wave][j][lane];
+        }
+        __syncthreads();
+    }
+    if (lane < NTERM) {
+        red[wave][lane] = acc;
+        a.bwave[(((size_t)K * np + pidx) * 4 + wave) * NTERM + lane] = acc;
+    }
+    __syncthreads();
+    if (wave == 0 && lane < NTERM)
+        a.bpanel[((size_t)K * np + pidx) * NTERM + lane] =
+            ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+}
+
+// Every running LP's panel sums set to its base LP's; k_sp_touched then
+// replaces those of the panels the LP changes.
+template <typename T>
+__global__ __launch_bounds__(256) void k_sp_bcast(SharedArgs<T> a) {
+    const int32_t pidx = blockIdx.x;
+    const int32_t s = blockIdx.y * 256 + threadIdx.x;
+    if (s >= a.nslots) return;
+    const int32_t K = sp_class(a, a.sl.key[s].varkind);
+    const bool xside = pidx < a.npx;
+    double* out = (xside ? a.part_x + (size_t)pidx * NTERM * a.ld
+                         : a.part_y + (size_t)(pidx - a.npx) * NTERM * a.ld) + s;
+    const double* bp = a.bpanel + ((size_t)K * (a.npx + a.npy) + pidx) * NTERM;
+#pragma unroll
+    for (int q = 0; q < NTERM; ++q) out[(size_t)q * a.ld] = bp[q];
+}
+
+constexpr int SP_SPLIT = 4;   // workgroups per LP in k_sp_touched
+
+// Panel sums of one LP on the panels it changes: the x panels of v and of every
+// column of the rows of A through v, the y panels of those rows.  SP_SPLIT
+// one-wave workgroups per LP take its panels in turn.  A chain of rows with
+// no row the LP changes takes its base LP's sum; any other chain is summed
+// again in row order, from the LP's own terms on the rows it changes and its
+// base LP's terms elsewhere.
+template <typename T>
+__global__ __launch_bounds__(64) void k_sp_touched(SharedArgs<T> a) {
+    __shared__ double terms[64][NTERM + 1];
+    __shared__ int32_t rv[SP_MAX_COL];   // the rows of A through v
+    __shared__ uint32_t bits[128];       // changed panels: x in words [0, 64), y in [64, 128)
+    __shared__ uint16_t list[4096];      // ... in panel order, x first
+    __shared__ int32_t nlist;
+    const int lane = threadIdx.x;
+    const int32_t s = blockIdx.x;
+    const int32_t vk = a.sl.key[s].varkind;
+    const int32_t v = vk & VAR_MASK;
+    if (v == VAR_NONE) return;
+    const int32_t K = sp_class(a, vk);
+    const int32_t kb = a.t_rp[v];
+    const int32_t nv = min(a.t_rp[v + 1] - kb, SP_MAX_COL);
+    const T* side = a.side + (size_t)s * SP_SIDE;
+    const T* bxt = a.xt + (size_t)K * a.n;
+    const T* bdx = a.dx + (size_t)K * a.n;
+    const T* byt = a.yt + (size_t)K * a.m;
+    const T* bdy = a.dy + (size_t)K * a.m;
+    const double* rt = a.rt + (size_t)K * ((size_t)a.n + a.m) * NTERM;
+    const int32_t np = a.npx + a.npy;
+    const int32_t px = 4 * a.pw_x, py = 4 * a.pw_y;
+    for (int32_t w = lane; w < 128; w += 64) bits[w] = 0u;
+    for (int32_t q = lane; q < nv; q += 64) rv[q] = a.t_ci[kb + q];
+    __syncthreads();
+    if (lane == 0) atomicOr(&bits[(v / px) >> 5], 1u << ((v / px) & 31));
+    for (int32_t q = 0; q < nv; ++q) {
+        const int32_t r = rv[q];
+        if (lane == 0) atomicOr(&bits[64 + ((r / py) >> 5)], 1u << ((r / py) & 31));
+        for (int32_t k = a.a_rp[r] + lane; k < a.a_rp[r + 1]; k += 64) {
+            const int32_t p = a.a_ci[k] / px;
+            atomicOr(&bits[p >> 5], 1u << (p & 31));
+        }
+    }
+    __syncthreads();
+    if (lane == 0) {
+        int32_t cnt = 0;
+        for (int32_t w = 0; w < 128; ++w) {
+            uint32_t b = bits[w];
+            while (b) {
+                const int32_t bit = __ffs(b) - 1;
+                b &= b - 1;
+                list[cnt++] = (uint16_t)(w < 64 ? w * 32 + bit : a.npx + (w - 64) * 32 + bit);
+            }
+        }
+        nlist = cnt;
+    }
+    __syncthreads();
+    const int32_t total = nlist;
+    // the LP's y~, dy at row r of A and x~, dx at column j
+    auto yat = [&](int32_t r, T& yv, T& dv) {
+        for (int32_t q = 0; q < nv; ++q)
+            if (rv[q] == r) {
+                yv = side[4 + 3 * q];
+                dv = side[4 + 3 * q + 2];
+                return;
+            }
+        yv = byt[r];
+        dv = bdy[r];
+    };
+    auto xat = [&](int32_t j, T& xv, T& dv) {
+        if (j == v) {
+            xv = side[1];
+            dv = side[3];
+        } else {
+            xv = bxt[j];
+            dv = bdx[j];
+        }
+    };
+    // evaluation row i of one side reads a coordinate the LP changes
+    auto changed = [&](bool xside, int32_t i) -> bool {
+        if (xside) {
+            if (i == v) return true;
+            for (int32_t k = a.t_rp[i]; k < a.t_rp[i + 1]; ++k) {
+                const int32_t r = a.t_ci[k];
+                for (int32_t q = 0; q < nv; ++q)
+                    if (rv[q] == r) return true;
+            }
+            return false;
+        }
+        for (int32_t q = 0; q < nv; ++q)
+            if (rv[q] == i) return true;
+        return false;
+    };
+    for (int32_t li = blockIdx.y; li < total; li += SP_SPLIT) {
+        const int32_t pidx = list[li];
+        const bool xside = pidx < a.npx;
+        const int32_t panel = xside ? pidx : pidx - a.npx;
+        const int32_t pw = xside ? a.pw_x : a.pw_y;
+        const int32_t rows = xside ? a.n : a.m;
+        double sum[4];
+        for (int u = 0; u < 4; ++u) {
+            const int32_t r0 = panel * 4 * pw + u * pw;
+            const int32_t r1 = min(r0 + pw, rows);
+            bool mine = false;
+            for (int32_t off = 0; off < pw; off += 64) {
+                const int32_t i = r0 + off + lane;
+                if (i < r1 && changed(xside, i)) mine = true;
+            }
+            double acc = 0.0;
+            if (!__syncthreads_or(mine)) {
+                if (lane < NTERM) acc = a.bwave[(((size_t)K * np + pidx) * 4 + u) * NTERM + lane];
+            } else {
+                for (int32_t off = 0; off < pw; off += 64) {
+                    const int32_t rb = r0 + off;
+                    const int32_t i = rb + lane;
+                    if (i < r1) {
+                        double tq[NTERM];
+                        if (!changed(xside, i)) {
+                            const double* o = rt + (size_t)(xside ? i : a.n + i) * NTERM;
+#pragma unroll
+                            for (int q = 0; q < NTERM; ++q) tq[q] = o[q];
+                        } else if (xside) {
+                            const bool at_v = i == v;
+                            sp_xterms(a, i, at_v ? side[1] : bxt[i], at_v ? side[3] : bdx[i],
+                                      at_v ? side[0] : a.x0[i], vk, s, yat, tq);
+                        } else {
+                            int32_t q0 = 0;   // i is a row through v
+                            while (rv[q0] != i) ++q0;
+                            sp_yterms(a, i, side[4 + 3 * q0], side[4 + 3 * q0 + 2], a.y0[i], xat, tq);
+                        }
+#pragma unroll
+                        for (int q = 0; q < NTERM; ++q) terms[lane][q] = tq[q];
+                    }
+                    __syncthreads();
+                    if (lane < NTERM) {
+                        const int32_t cnt = min(64, r1 - rb);
+                        for (int32_t j = 0; j < cnt; ++j) acc += terms[j][lane];
+                    }
+                    __syncthreads();
+                }
+            }
+            sum[u] = acc;
+        }
+        if (lane < NTERM) {
+            double* out = (xside ? a.part_x : a.part_y) + (size_t)panel * NTERM * a.ld + s;
+            out[(size_t)lane * a.ld] = ((sum[0] + sum[1]) + sum[2]) + sum[3];
+        }
+    }
+}
+
+// Live columns after the control pass: column e < n_cols_next holds the LP of
+// slot map[e] (its own, or the one the plan moves into it), of base LP
+// map[nslots + e].
+template <typename T>
+__global__ __launch_bounds__(1024) void k_sp_map(SharedArgs<T> a) {
+    const int32_t nc = a.g->n_cols_next, nm = a.g->n_move;
+    for (int32_t e = threadIdx.x; e < nc; e += blockDim.x) a.map[e] = e;
+    __syncthreads();
+    for (int32_t k = threadIdx.x; k < nm; k += blockDim.x) a.map[a.moves[k].dst] = a.moves[k].src;
+    __syncthreads();
+    for (int32_t e = threadIdx.x; e < nc; e += blockDim.x)
+        a.map[a.nslots + e] = sp_class(a, a.sl.key[a.map[e]].varkind);
+}
+
+// Xbar, X0 (x rows) and Y, Y0 (y rows) of the live columns from their base
+// LPs; k_sp_patch writes each LP's own values over them.  A wave writes 64
+// consecutive columns of a row.
+template <typename T>
+__global__ __launch_bounds__(256) void k_sp_dense(SharedArgs<T> a) {
+    const int32_t e = blockIdx.y * 64 + (threadIdx.x & 63);
+    if (e >= a.g->n_cols_next) return;
+    const int32_t K = a.map[a.nslots + e];
+    const int32_t total = a.n + a.m;
+    for (int32_t row = blockIdx.x * 4 + (threadIdx.x >> 6); row < total; row += gridDim.x * 4) {
+        if (row < a.n) {
+            const size_t o = (size_t)row * a.ld + e;
+            a.blk[0][o] = a.xbar[(size_t)K * a.n + row];
+            a.blk[1][o] = a.x0[row];
+        } else {
+            const int32_t r = row - a.n;
+            const size_t o = (size_t)r * a.ld + e;
+            a.blk[4][o] = a.yn[(size_t)K * a.m + r];
+            a.blk[5][o] = a.y0[r];
+        }
+    }
+}
+
+// Results of the LPs stopped at t = 0 from their base LPs (x~, the Halpern
+// iterate rebuilt from x-bar and x^0 as k_compact does, y~, y^1); one
+// workgroup row per plan entry, contiguous along the LP's result rows.
+template <typename T>
+__global__ __launch_bounds__(256) void k_sp_results(SharedArgs<T> a) {
+    const int32_t q = blockIdx.y;
+    if (q >= a.g->n_retire) return;
+    const RetireEntry re = a.retire[q];
+    const int32_t K = sp_class(a, a.sl.key[re.slot].varkind);
+    const size_t lp = (size_t)re.lp;
+    const int32_t total = a.n + a.m;
+    for (int32_t row = blockIdx.x * 256 + threadIdx.x; row < total; row += gridDim.x * 256) {
+        if (row < a.n) {
+            const size_t e = (size_t)K * a.n + row;
+            a.res[0][lp * a.n + row] = a.xt[e];
+            a.res[1][lp * a.n + row] = halpern_last<T>(re.a, re.kp2, a.xbar[e], a.x0[row]);
+        } else {
+            const int32_t r = row - a.n;
+            const size_t e = (size_t)K * a.m + r;
+            a.res[2][lp * a.m + r] = a.yt[e];
+            a.res[3][lp * a.m + r] = a.yn[e];
+        }
+    }
+}
+
+// Each LP's own values at its variable and the rows through it, over the base
+// values k_sp_dense and k_sp_results wrote: items [0, nslots) are live
+// columns, items [nslots, 2 nslots) plan entries of stopped LPs.  One wave per
+// item.
+template <typename T>
+__global__ __launch_bounds__(256) void k_sp_patch(SharedArgs<T> a) {
+    const int lane = threadIdx.x & 63;
+    const int32_t item = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const bool live = item < a.nslots;
+    int32_t f, e = 0;
+    RetireEntry re{};
+    if (live) {
+        e = item;
+        if (e >= a.g->n_cols_next) return;
+        f = a.map[e];
+    } else {
+        const int32_t q = item - a.nslots;
+        if (q >= a.nslots || q >= a.g->n_retire) return;
+        re = a.retire[q];
+        f = re.slot;
+    }
+    const int32_t v = a.sl.key[f].varkind & VAR_MASK;
+    if (v == VAR_NONE) return;
+    const T* side = a.side + (size_t)f * SP_SIDE;
+    const int32_t kb = a.t_rp[v];
+    const int32_t nv = min(a.t_rp[v + 1] - kb, SP_MAX_COL);
+    if (live) {
+        if (lane == 0) {
+            a.blk[0][(size_t)v * a.ld + e] = side[2];
+            a.blk[1][(size_t)v * a.ld + e] = side[0];
+        }
+        for (int32_t q = lane; q < nv; q += 64)
+            a.blk[4][(size_t)a.t_ci[kb + q] * a.ld + e] = side[4 + 3 * q + 1];
+    } else {
+        const size_t lp = (size_t)re.lp;
+        if (lane == 0) {
+            a.res[0][lp * a.n + v] = side[1];
+            a.res[1][lp * a.n + v] = halpern_last<T>(re.a, re.kp2, side[2], side[0]);
+        }
+        for (int32_t q = lane; q < nv; q += 64) {
+            const int32_t r = a.t_ci[kb + q];
+            a.res[2][lp * a.m + r] = side[4 + 3 * q];
+            a.res[3][lp * a.m + r] = side[4 + 3 * q + 1];
+        }
+    }
+}
+
+// Slot state of the moved LPs and the new column count, after every kernel
+// that reads the old slots.
+__global__ __launch_bounds__(1024) void k_sp_finish(Slots sl, const MoveEntry* moves, Globals* g) {
+    const int32_t nm = g->n_move;
+    for (int32_t k = threadIdx.x; k < nm; k += blockDim.x) {
+        const MoveEntry mv = moves[k];
+        sl.key[mv.dst] = sl.key[mv.src];
+        sl.tau[mv.dst] = sl.tau[mv.src];
+        sl.sigma[mv.dst] = sl.sigma[mv.src];
+        sl.dval[mv.dst] = sl.dval[mv.src];
+        sl.t_start[mv.dst] = sl.t_start[mv.src];
+        sl.lp[mv.dst] = sl.lp[mv.src];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) g->n_cols = g->n_cols_next;
+}
+
 template <typename T, int G, int VEC, int EW, bool PRIMAL>
 hipError_t launch_step_gve(const StepArgs<T>& a, hipStream_t s) {
     constexpr int RPW = 64 / G;
@@ -2058,7 +2578,47 @@ hipError_t launch_fill(double* x, int32_t len, double v, hipStream_t s) {
     return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_sp_iterate(const SharedArgs<T>& a, hipStream_t s) {
+    if (a.n > 0) hipLaunchKernelGGL(k_sp_primal<T>, dim3((a.n + 255) / 256), dim3(256), 0, s, a);
+    if (a.m > 0) hipLaunchKernelGGL(k_sp_dual<T>, dim3((a.m + 255) / 256), dim3(256), 0, s, a);
+    if (a.nslots > 0)
+        hipLaunchKernelGGL(k_sp_side<T>, dim3((a.nslots + 3) / 4), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_sp_eval(const SharedArgs<T>& a, hipStream_t s) {
+    const int32_t np = a.npx + a.npy;
+    if (np == 0 || a.nslots == 0) return hipSuccess;
+    if (a.npx > 2048 || a.npy > 2048 || a.ncls < 1 || a.ncls > 2) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_sp_terms<T>, dim3(np, a.ncls), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_sp_bcast<T>, dim3(np, (a.nslots + 255) / 256), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_sp_touched<T>, dim3(a.nslots, SP_SPLIT), dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_sp_place(const SharedArgs<T>& a, hipStream_t s) {
+    if (a.nslots == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_sp_map<T>, dim3(1), dim3(1024), 0, s, a);
+    const int64_t total = (int64_t)a.n + a.m;
+    const uint32_t gx = (uint32_t)(((total + 3) / 4) < 4096 ? (total + 3) / 4 : 4096);
+    hipLaunchKernelGGL(k_sp_dense<T>, dim3(gx, (a.nslots + 63) / 64), dim3(256), 0, s, a);
+    const uint32_t rx = (uint32_t)(((total + 255) / 256) < 64 ? (total + 255) / 256 : 64);
+    hipLaunchKernelGGL(k_sp_results<T>, dim3(rx, a.nslots), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_sp_patch<T>, dim3((2 * a.nslots + 3) / 4), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_sp_finish, dim3(1), dim3(1024), 0, s, a.sl, a.moves, a.g);
+    return hipGetLastError();
+}
+
 // explicit instantiations
+template hipError_t launch_sp_iterate<double>(const SharedArgs<double>&, hipStream_t);
+template hipError_t launch_sp_iterate<float>(const SharedArgs<float>&, hipStream_t);
+template hipError_t launch_sp_eval<double>(const SharedArgs<double>&, hipStream_t);
+template hipError_t launch_sp_eval<float>(const SharedArgs<float>&, hipStream_t);
+template hipError_t launch_sp_place<double>(const SharedArgs<double>&, hipStream_t);
+template hipError_t launch_sp_place<float>(const SharedArgs<float>&, hipStream_t);
 template hipError_t launch_primal<double>(const StepArgs<double>&, int, int, hipStream_t);
 template hipError_t launch_primal<float>(const StepArgs<float>&, int, int, hipStream_t);
 template hipError_t launch_dual<double>(const StepArgs<double>&, int, int, hipStream_t);

@@ -153,6 +153,18 @@ struct pdlpb_ctx {
     double* tail_sum = nullptr;     //   and its evaluation chain and panel sums
     int32_t tail_cap = 0;           //   LPs the two buffers hold
     int32_t* h_pinned = nullptr;    // n_active read-back
+    // shared start: a batch whose running LPs start from one point with the same
+    // step sizes makes its first iteration and evaluation per base LP and per
+    // change (kernels launch_sp_*)
+    std::vector<uint8_t> h_sp_ok;   // per variable: its column and the rows through it fit the caps
+    bool sp_batch = false;          // the batch set runs its first iteration that way
+    int32_t sp_ncls = 0, sp_cls_obj = -1, sp_cls_bound = -1, sp_kind[2] = {0, 0};
+    double sp_tau[2] = {0.0, 0.0}, sp_sigma[2] = {0.0, 0.0};   // per base LP
+    void* sp_vec = nullptr;         // base vectors: x0, y0, then per base LP xt, xbar, dx, yt, yn, dy
+    void* sp_side = nullptr;        // per slot: SP_SIDE values where its LP differs
+    double* sp_terms = nullptr;     // per base LP: row terms, chain sums, panel sums
+    int32_t* sp_map = nullptr;      // live columns after the first compaction
+    size_t cap_sp_vec = 0, cap_sp_side = 0, cap_sp_terms = 0, cap_sp_map = 0;   // bytes
 
     // state
     bool batch_set = false;
@@ -870,6 +882,150 @@ void free_narrow(pdlpb_ctx* x) {
     for (int q = 0; q < 8; ++q) x->release(x->nblk[q], 0);
 }
 
+// ---- shared start ------------------------------------------------------------
+constexpr double SP_AUTO_BYTES = 8e6;   // automatic choice: blocks at least this large
+
+int ensure_bytes(pdlpb_ctx* x, void** p, size_t* cap, size_t bytes) {
+    if (bytes <= *cap && *p) return PDLPB_OK;
+    x->release(*p, *cap);
+    *cap = 0;
+    HIP_TRY(x, x->alloc(p, bytes));
+    *cap = bytes;
+    return PDLPB_OK;
+}
+
+void free_shared_start(pdlpb_ctx* x) {
+    x->sp_batch = false;
+    x->release(x->sp_vec, 0);
+    x->release(x->sp_side, 0);
+    x->release(x->sp_terms, 0);
+    x->release(x->sp_map, 0);
+    x->cap_sp_vec = x->cap_sp_side = x->cap_sp_terms = x->cap_sp_map = 0;
+}
+
+// Whether the batch just placed in slots makes its first iteration and
+// evaluation through the shared start (option shared_start): every running LP
+// starts from the shared warm point (or zero), the LPs of one base LP share
+// their step sizes, and every change is of a variable within the caps.  Sets
+// the base LPs and sizes the buffers when it does.
+int plan_shared_start(pdlpb_ctx* x, int32_t warm_mode, const std::vector<SlotKey>& key,
+                      const std::vector<double>& tau, const std::vector<double>& sigma) {
+    x->sp_batch = false;
+    const int32_t nr = (int32_t)key.size();
+    if (x->opt.shared_start < 0 || nr == 0) return PDLPB_OK;
+    if (warm_mode != PDLPB_WARM_NONE && warm_mode != PDLPB_WARM_SHARED) return PDLPB_OK;
+    const size_t esz = x->fp32 ? sizeof(float) : sizeof(double);
+    const size_t rows = (size_t)x->n + x->m;
+    if (x->opt.shared_start == 0 && (double)rows * nr * esz < SP_AUTO_BYTES) return PDLPB_OK;
+    // first LP of each base LP (0: bound changes and the base LP, 1: objective changes)
+    int32_t first[2] = {-1, -1};
+    for (int32_t s = 0; s < nr; ++s) {
+        const int32_t v = key[s].varkind & VAR_MASK;
+        if (v != VAR_NONE && !x->h_sp_ok[v]) return PDLPB_OK;
+        const int f = ((uint32_t)key[s].varkind >> 28) == (uint32_t)PDLPB_OBJ_UNIT ? 1 : 0;
+        if (first[f] < 0) first[f] = s;
+        if (tau[s] != tau[first[f]] || sigma[s] != sigma[first[f]]) return PDLPB_OK;
+    }
+    x->sp_ncls = 0;
+    x->sp_cls_obj = x->sp_cls_bound = -1;
+    for (int f = 0; f < 2; ++f) {
+        if (first[f] < 0) continue;
+        const int32_t K = x->sp_ncls++;
+        if (f == 0) x->sp_cls_bound = K;
+        else x->sp_cls_obj = K;
+        x->sp_kind[K] = f == 0 ? PDLPB_BASE : PDLPB_OBJ_UNIT;
+        x->sp_tau[K] = tau[first[f]];
+        x->sp_sigma[K] = sigma[first[f]];
+    }
+    const size_t K = (size_t)x->sp_ncls;
+    const size_t panels = (size_t)x->npx + x->npy;
+    int rc = ensure_bytes(x, &x->sp_vec, &x->cap_sp_vec, rows * (1 + 3 * K) * esz);
+    if (!rc) rc = ensure_bytes(x, &x->sp_side, &x->cap_sp_side, (size_t)nr * SP_SIDE * esz);
+    if (!rc)
+        rc = ensure_bytes(x, reinterpret_cast<void**>(&x->sp_terms), &x->cap_sp_terms,
+                          K * (rows + panels * 5) * NTERM * sizeof(double));
+    if (!rc)
+        rc = ensure_bytes(x, reinterpret_cast<void**>(&x->sp_map), &x->cap_sp_map,
+                          (size_t)2 * nr * sizeof(int32_t));
+    if (rc) return rc;
+    x->sp_batch = true;
+    return PDLPB_OK;
+}
+
+template <typename T>
+SharedArgs<T> shared_args(pdlpb_ctx* x, const double* xw = nullptr, const double* yw = nullptr) {
+    SharedArgs<T> a{};
+    a.n = x->n;
+    a.m = x->m;
+    a.ld = x->ld;
+    a.nslots = x->n_run0;
+    a.ncls = x->sp_ncls;
+    a.cls_kind[0] = x->sp_kind[0];
+    a.cls_kind[1] = x->sp_kind[1];
+    a.cls_obj = x->sp_cls_obj;
+    a.cls_bound = x->sp_cls_bound;
+    a.a_rp = x->a_rp; a.a_ci = x->a_ci;
+    a.t_rp = x->t_rp; a.t_ci = x->t_ci;
+    if constexpr (sizeof(T) == 8) {
+        a.a_v = reinterpret_cast<const T*>(x->a_v64);
+        a.t_v = reinterpret_cast<const T*>(x->t_v64);
+    } else {
+        a.a_v = reinterpret_cast<const T*>(x->a_v32);
+        a.t_v = reinterpret_cast<const T*>(x->t_v32);
+    }
+    a.c = x->c; a.xl = x->xl; a.xu = x->xu; a.rl = x->rl; a.ru = x->ru;
+    a.rcode = x->rcode;
+    a.xw = xw;
+    a.yw = yw;
+    for (int K = 0; K < 2; ++K) {
+        a.tau[K] = x->sp_tau[K];
+        a.sigma[K] = x->sp_sigma[K];
+    }
+    const size_t n = x->n, m = x->m, K = x->sp_ncls;
+    a.x0 = static_cast<T*>(x->sp_vec);
+    a.y0 = a.x0 + n;
+    a.xt = a.y0 + m;
+    a.xbar = a.xt + K * n;
+    a.dx = a.xbar + K * n;
+    a.yt = a.dx + K * n;
+    a.yn = a.yt + K * m;
+    a.dy = a.yn + K * m;
+    a.side = static_cast<T*>(x->sp_side);
+    a.sl = x->sl;
+    a.pw_x = x->pw_x; a.pw_y = x->pw_y; a.npx = x->npx; a.npy = x->npy;
+    a.rt = x->sp_terms;
+    a.bwave = a.rt + K * (n + m) * NTERM;
+    a.bpanel = a.bwave + K * ((size_t)x->npx + x->npy) * 4 * NTERM;
+    a.part_x = x->part;
+    a.part_y = x->part + (size_t)x->npx * NTERM * x->ld;
+    a.g = x->g;
+    a.retire = x->retire;
+    a.moves = x->moves;
+    a.map = x->sp_map;
+    for (int b = 0; b < 8; ++b) a.blk[b] = static_cast<T*>(x->blk[b]);
+    for (int b = 0; b < 4; ++b) a.res[b] = static_cast<T*>(x->res[b]);
+    return a;
+}
+
+// t = 0 of a shared-start batch (its first iteration was made at set_batch):
+// the evaluation sums, the control pass (a full evaluation), then the blocks of
+// the LPs still running and the results of those that stopped.
+template <typename T>
+int enqueue_shared_prologue(pdlpb_ctx* x, std::vector<std::pair<int, int>>* rec) {
+    const SharedArgs<T> a = shared_args<T>(x);
+    const ControlArgs c = control_args(x, 0, 1, 0);
+    int idx = -1;
+    if (rec) idx = timed_begin(x, 2, *rec);
+    HIP_TRY(x, launch_sp_eval<T>(a, x->stream));
+    if (rec && idx >= 0) (void)hipEventRecord(x->ev[2 * idx + 1], x->stream);
+    if (rec) idx = timed_begin(x, 3, *rec);
+    HIP_TRY(x, launch_reduce(c, x->stream));
+    HIP_TRY(x, launch_control(c, x->stream));
+    HIP_TRY(x, launch_sp_place<T>(a, x->stream));
+    if (rec && idx >= 0) (void)hipEventRecord(x->ev[2 * idx + 1], x->stream);
+    return PDLPB_OK;
+}
+
 template <typename T>
 int run_solve(pdlpb_ctx* x, double tol, int32_t max_iters) {
     x->live = shape_cols(x, x->n_run0);
@@ -892,8 +1048,14 @@ int run_solve(pdlpb_ctx* x, double tol, int32_t max_iters) {
     };
     // prologue: t = 0 is a full evaluation
     x->cur_cols = x->n_run0;
-    int rc = enqueue_iteration<T>(x, 0, 2, prec);
-    if (!rc) rc = enqueue_evaluation<T>(x, 0, 1, 0, prec);
+    int rc = PDLPB_OK;
+    if (x->sp_batch) {
+        x->sp_batch = false;
+        rc = enqueue_shared_prologue<T>(x, prec);
+    } else {
+        rc = enqueue_iteration<T>(x, 0, 2, prec);
+        if (!rc) rc = enqueue_evaluation<T>(x, 0, 1, 0, prec);
+    }
     if (rc) return rc;
     int32_t n_active = 0, n_cols = 0;
     rc = read_counts(x, &n_active, &n_cols);
@@ -1482,6 +1644,7 @@ int pdlpb_create(pdlpb_ctx** out, int32_t m, int32_t n, int64_t nnz, const int64
     if (o.tile_vec != 0 && o.tile_vec != 1 && o.tile_vec != 2 && o.tile_vec != 4)
         return bad("tile_vec must be 0, 1, 2 or 4");
     if (o.tail_cols < 0 || o.tail_cols > 64) return bad("tail_cols must be in [0, 64]");
+    if (o.shared_start < -1 || o.shared_start > 1) return bad("shared_start must be -1, 0 or 1");
     if (o.stop_every != 0 && o.stop_every != o.eval_every &&
         (o.stop_every < 2 || o.eval_every % o.stop_every != 0))
         return bad("stop_every must be 0 or a divisor >= 2 of eval_every");
@@ -1604,6 +1767,16 @@ int pdlpb_create(pdlpb_ctx** out, int32_t m, int32_t n, int64_t nnz, const int64
                 h_tci[p] = i;
                 h_tv[p] = val[k];
             }
+    }
+    // shared start: a change of variable v qualifies when its column and the
+    // rows through it are small enough for the per-LP kernels
+    x->h_sp_ok.assign(n, 0);
+    for (int32_t v = 0; v < n; ++v) {
+        if (h_trp[v + 1] - h_trp[v] > SP_MAX_COL) continue;
+        int64_t touch = 1;
+        for (int32_t k = h_trp[v]; k < h_trp[v + 1]; ++k)
+            touch += h_arp[h_tci[k] + 1] - h_arp[h_tci[k]];
+        x->h_sp_ok[v] = touch <= SP_MAX_TOUCH ? 1 : 0;
     }
     auto up = [&](auto** dst, const auto* src, size_t count) -> hipError_t {
         using E = std::remove_pointer_t<std::remove_reference_t<decltype(*dst)>>;
@@ -1793,6 +1966,10 @@ int pdlpb_set_batch(pdlpb_ctx* x, int32_t B, const pdlpb_delta* deltas, const do
         int rc = ensure_storage(x, B, B, &ld);
         if (rc) return rc;
     }
+    {
+        int rc = plan_shared_start(x, warm_mode, h_key, h_tau, h_sigma);
+        if (rc) return rc;
+    }
     const size_t esz = x->fp32 ? sizeof(float) : sizeof(double);
     // captured graphs stay valid: their keys hold the launch shapes, and
     // ensure_storage drops them when it moves a buffer
@@ -1870,7 +2047,12 @@ int pdlpb_set_batch(pdlpb_ctx* x, int32_t B, const pdlpb_delta* deltas, const do
             yw = x->stage + nx;
         }
     }
-    if (x->fp32) {
+    if (x->sp_batch) {
+        // the first iteration of the base LPs and of each change; the blocks are
+        // written after the first evaluation, for the LPs that still run
+        if (x->fp32) HIP_TRY(x, launch_sp_iterate<float>(shared_args<float>(x, xw, yw), x->stream));
+        else HIP_TRY(x, launch_sp_iterate<double>(shared_args<double>(x, xw, yw), x->stream));
+    } else if (x->fp32) {
         float* const* b = reinterpret_cast<float* const*>(x->blk);
         HIP_TRY(x, launch_init_blocks<float>(n, m, ld, n_run0, x->sl, x->xl, x->xu, xw,
                                              yw, warm_mode, b[0], b[1], b[4], b[5], x->stream));
@@ -2157,9 +2339,11 @@ int pdlpb_serve_begin(pdlpb_ctx* x, int32_t result_capacity) {
         return x->fail(PDLPB_EINVAL, "result_capacity out of range");
     HIP_TRY(x, hipSetDevice(x->device));
     HIP_TRY(x, hipStreamSynchronize(x->stream));
-    // a session holds only what its LPs need: no narrow copies of a batch
+    // a session holds only what its LPs need: no narrow copies or shared-start
+    // buffers of a batch
     x->drop_graph();
     free_narrow(x);
+    free_shared_start(x);
     // storage starts at one column and one result row and grows with the LPs
     // submitted (pdlpb_serve_footprint, pdlpb_serve_trim)
     x->n_cols = 0;

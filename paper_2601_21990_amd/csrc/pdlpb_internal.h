@@ -212,6 +212,53 @@ __host__ __device__ inline size_t tail_sum_doubles(int32_t npx, int32_t npy) {
     return (size_t)(4 * (npx + npy) + (npx + npy) + 2) * NTERM;
 }
 
+// ---- shared start ------------------------------------------------------------
+// A batch whose running LPs all start from one warm point (or from zero), with
+// the same step sizes for every LP of one base LP, makes its first iteration
+// and evaluation (t = 0) once per base LP -- the LP without a change, and for
+// objective changes that LP with objective 0 -- and per LP only where its
+// change reaches: its variable v, the rows of A through v, and the evaluation
+// rows that read them.
+constexpr int32_t SP_MAX_COL = 64;       // nonzeros of a changed variable's column of A
+constexpr int32_t SP_MAX_TOUCH = 4096;   // 1 + nonzeros of the rows of A through it
+constexpr int32_t SP_SIDE = 4 + 3 * SP_MAX_COL;   // values of one LP where it differs
+
+template <typename T>
+struct SharedArgs {
+    int32_t n, m, ld;
+    int32_t nslots;            // running LPs: slots [0, nslots)
+    int32_t ncls;              // base LPs (1 or 2)
+    int32_t cls_kind[2];       // change kind of base LP K: PDLPB_BASE (objective c) or
+                               // PDLPB_OBJ_UNIT (objective 0)
+    int32_t cls_obj;           // base LP of the objective changes (-1: none in the batch)
+    int32_t cls_bound;         // base LP of every other LP (-1: none)
+    const int32_t* a_rp; const int32_t* a_ci; const T* a_v;    // A (m x n)
+    const int32_t* t_rp; const int32_t* t_ci; const T* t_v;    // A' (n x m)
+    const double *c, *xl, *xu, *rl, *ru;
+    const int8_t* rcode;       // per row of A: 1 if its lower bound is -inf, | 2 if its upper is +inf
+    const double *xw, *yw;     // the shared warm start (NULL: zero)
+    double tau[2], sigma[2];   // step sizes of every LP of base LP K
+    T *x0, *y0;                // x^0 on the base box (n), y^0 (m)
+    T *xt, *xbar, *dx;         // [ncls][n]: x~, x-bar = 2 x~ - x^0, x~ - x^0 of each base LP
+    T *yt, *yn, *dy;           // [ncls][m]: y~, y^1, y~ - y^0
+    T* side;                   // [slot][SP_SIDE]: x^0, x~, x-bar, dx at v, then y~, y^1, dy
+                               // at each row of A through v (in the order of A's column v)
+    Slots sl;
+    int32_t pw_x, pw_y, npx, npy;   // evaluation layout (as k_eval)
+    double* rt;                // [ncls][n + m][NTERM]: terms of every row of each base LP
+    double* bwave;             // [ncls][npx + npy][4][NTERM]: its chain sums
+    double* bpanel;            // [ncls][npx + npy][NTERM]: its panel sums
+    double* part_x;            // evaluation sums, laid out as k_eval writes them
+    double* part_y;
+    Globals* g;
+    const RetireEntry* retire;
+    const MoveEntry* moves;
+    int32_t* map;              // [2][nslots]: slot whose LP a live column holds after the
+                               // compaction, and that LP's base LP
+    T* blk[8];                 // Xbar, X0, Xt, DX, Y, Y0, Yt, DY (row-major, stride ld)
+    T* res[4];                 // Rx, Rxi (B x n), Ry, Ryi (B x m): LP-major results
+};
+
 // ---- launchers (kernels.hip) ---------------------------------------------------
 // Each returns hipSuccess or the launch error.
 template <typename T>
@@ -228,6 +275,22 @@ hipError_t launch_control(const ControlArgs& a, hipStream_t s);
 // its results to the result blocks.
 template <typename T>
 hipError_t launch_tail(const TailArgs<T>& a, size_t dyn_lds, hipStream_t s);
+
+// Shared start.  launch_sp_iterate: the first iteration (t = 0) of every base
+// LP (x^0, x~, x-bar, dx; y^0, y~, y^1, dy), then of every LP at its variable
+// and at the rows of A through it, as the step kernels compute them.
+// launch_sp_eval: the evaluation sums at t = 0 of every running LP into
+// part_x / part_y, the bits k_eval computes from the blocks.  launch_sp_place,
+// after the control pass: the blocks Xbar, X0, Y, Y0 of the LPs that still
+// run, at their slots after the compaction; the results of the stopped LPs;
+// the slot state of moved LPs and the new column count (what k_compact does
+// after a full evaluation; no LP restarts at t = 0).
+template <typename T>
+hipError_t launch_sp_iterate(const SharedArgs<T>& a, hipStream_t s);
+template <typename T>
+hipError_t launch_sp_eval(const SharedArgs<T>& a, hipStream_t s);
+template <typename T>
+hipError_t launch_sp_place(const SharedArgs<T>& a, hipStream_t s);
 
 // Fill the iterate blocks of a new batch (Xbar = X0 = the projected warm x,
 // Y = Y0 = the warm y).  Warm vectors: mode 0 none, 1 shared (xw: n, yw: m),

@@ -62,7 +62,7 @@ class Options(C.Structure):
                 ("pw_ratio", C.c_int32), ("device", C.c_int32), ("stream", C.c_void_p),
                 ("max_batch", C.c_int32), ("use_graphs", C.c_int32),
                 ("tile_lanes", C.c_int32), ("tile_vec", C.c_int32),
-                ("autotune", C.c_int32), ("reserved_pad", C.c_int32),
+                ("autotune", C.c_int32), ("shared_start", C.c_int32),
                 ("dual_tol", C.c_double), ("max_blocks", C.c_int32),
                 ("scaling", C.c_int32), ("tail_cols", C.c_int32), ("stop_every", C.c_int32),
                 ("dev_alloc", C.c_void_p), ("dev_free", C.c_void_p),

@@ -107,6 +107,8 @@ def test_create_rejects_malformed_input(over, msg):
     (dict(eval_every=24, stop_every=1), "stop_every"),
     (dict(eval_every=24, stop_every=5), "stop_every"),
     (dict(eval_every=24, stop_every=48), "stop_every"),
+    (dict(shared_start=2), "shared_start"),
+    (dict(shared_start=-2), "shared_start"),
 ])
 def test_create_rejects_bad_options(opt, msg):
     with pytest.raises(P.PdlpbError) as e:
