@@ -74,6 +74,11 @@ struct Tile {
 };
 
 constexpr int32_t DEFAULT_MAX_BLOCKS = 16384;
+// narrow storage: strides for at most 16, 4, 2, 1 live LPs, and the smallest
+// blocks worth the copy
+constexpr int32_t NARROW_LD = 16;
+constexpr int32_t TINY_LD = 4;
+constexpr double NARROW_MIN_BLOCK_BYTES = 256e6;   // one block pair (x rows + y rows)
 // largest matrix whose LPs the persistent tail iterates with one workgroup each
 constexpr int64_t TAIL_MAX_NNZ = 65536;
 constexpr int64_t RUN_AHEAD_AFTER = 8;      // blocks of a solve before replays run ahead of the host
@@ -125,6 +130,8 @@ struct pdlpb_ctx {
     // run_solve copies them into blocks of stride NARROW_LD and works there
     // until it returns (blk and ld point at them meanwhile).
     void* nblk[8] = {};             // the narrow blocks (allocated on first use)
+    void* tblk[3][8] = {};          // blocks of stride 4, 2 and 1 for the last few LPs (one set
+                                    // per stride: captured graphs keep their pointers)
     void* wblk[8] = {};             // the batch's own blocks while narrow storage is in use
     int32_t wld = 0;                // and their stride
     bool narrow = false;
@@ -394,6 +401,14 @@ int compute_opnorm(pdlpb_ctx* x, double* out) {
 // the 200k x 500k sweeps at B = 64 ... 512 in both precisions; vec never
 // exceeds the width ld was padded for
 Tile heuristic_tile(const pdlpb_ctx* x, int32_t ncols) {
+    if (x->narrow && x->ld <= TINY_LD) {
+        // blocks of stride 4, 2 or 1: one lane per row covers every column
+        Tile t;
+        t.lanes = 1;
+        t.vec = x->ld;
+        t.blocks = x->opt.max_blocks > 0 ? x->opt.max_blocks : DEFAULT_MAX_BLOCKS;
+        return t;
+    }
     const int32_t w = std::min<int32_t>(64, next_pow2(ncols > 0 ? ncols : 1));
     int vec = w >= 64 ? (x->fp32 ? 4 : 2) : 1;
     if (x->opt.tile_vec > 0) vec = x->opt.tile_vec;
@@ -835,37 +850,45 @@ int run_tail(pdlpb_ctx* x, int32_t n_cols, std::vector<std::pair<int, int>>* rec
 // stride 8.  Once at most NARROW_LD columns of a batch at least four times as
 // wide still run, and its blocks exceed the last-level cache, run_solve copies
 // those columns into blocks of stride NARROW_LD and works there until it
-// returns.  Every kernel takes the stride
-// as an argument and every LP's arithmetic is independent of it, so results
-// do not change.
-constexpr int32_t NARROW_LD = 16;
-constexpr double NARROW_MIN_BLOCK_BYTES = 256e6;   // one block pair (x rows + y rows)
+// returns; once at most 4, 2 or 1 run, into blocks of that stride, where one
+// lane takes a whole row (all its columns) and a wave 64 rows: a lone LP's
+// vectors are then contiguous, and the one the products gather stays in the
+// L2 cache.  Every kernel takes the stride as an argument and every LP's
+// arithmetic is independent of it, so results do not change.
 
-bool narrow_applies(const pdlpb_ctx* x, int32_t n_cols) {
+// stride the live columns move to now (0: they stay)
+int32_t narrow_target(const pdlpb_ctx* x, int32_t n_cols) {
+    if (x->serving || n_cols <= 0 || n_cols > NARROW_LD) return 0;
     // blocks that the caches hold gain nothing from the copy
     const double esz = x->fp32 ? 4.0 : 8.0;
     const double row_bytes = ((double)x->n + (double)x->m) * esz;
-    return !x->serving && !x->narrow && n_cols > 0 && n_cols <= NARROW_LD &&
-           x->ld >= 4 * NARROW_LD && NARROW_LD % x->vec_ld == 0 &&
-           row_bytes * x->ld >= NARROW_MIN_BLOCK_BYTES;
+    const int32_t wide = x->narrow ? x->wld : x->ld;
+    if (wide < 4 * NARROW_LD || row_bytes * wide < NARROW_MIN_BLOCK_BYTES) return 0;
+    // fixed tile shapes (options, pdlpb_set_tile) keep to the stride-16 blocks
+    const bool fixed = x->opt.tile_lanes > 0 || x->opt.tile_vec > 0;
+    int32_t want = NARROW_LD;
+    if (!fixed) want = n_cols <= 1 ? 1 : n_cols <= 2 ? 2 : n_cols <= TINY_LD ? TINY_LD : NARROW_LD;
+    if (want == NARROW_LD && NARROW_LD % x->vec_ld != 0) return 0;
+    return want < x->ld ? want : 0;
 }
 
-int enter_narrow(pdlpb_ctx* x) {
+int enter_narrow(pdlpb_ctx* x, int32_t ld) {
     const size_t esz = x->fp32 ? sizeof(float) : sizeof(double);
-    const size_t pitch = (size_t)NARROW_LD * esz;
+    void** dst = ld == NARROW_LD ? x->nblk : x->tblk[ld == TINY_LD ? 0 : ld == 2 ? 1 : 2];
     for (int q = 0; q < 8; ++q) {
         const int32_t rows = q < 4 ? x->n : x->m;
-        if (!x->nblk[q]) HIP_TRY(x, x->alloc(&x->nblk[q], (size_t)rows * pitch));
+        if (!dst[q]) HIP_TRY(x, x->alloc(&dst[q], (size_t)rows * ld * esz));
         if (rows > 0)
-            HIP_TRY(x, hipMemcpy2DAsync(x->nblk[q], pitch, x->blk[q], (size_t)x->ld * esz, pitch,
-                                        (size_t)rows, hipMemcpyDeviceToDevice, x->stream));
+            HIP_TRY(x, hipMemcpy2DAsync(dst[q], (size_t)ld * esz, x->blk[q], (size_t)x->ld * esz,
+                                        (size_t)ld * esz, (size_t)rows, hipMemcpyDeviceToDevice,
+                                        x->stream));
     }
-    for (int q = 0; q < 8; ++q) {
-        x->wblk[q] = x->blk[q];
-        x->blk[q] = x->nblk[q];
+    if (!x->narrow) {
+        for (int q = 0; q < 8; ++q) x->wblk[q] = x->blk[q];
+        x->wld = x->ld;
     }
-    x->wld = x->ld;
-    x->ld = NARROW_LD;
+    for (int q = 0; q < 8; ++q) x->blk[q] = dst[q];
+    x->ld = ld;
     x->narrow = true;
     return PDLPB_OK;
 }
@@ -879,7 +902,10 @@ void leave_narrow(pdlpb_ctx* x) {
 
 void free_narrow(pdlpb_ctx* x) {
     leave_narrow(x);
-    for (int q = 0; q < 8; ++q) x->release(x->nblk[q], 0);
+    for (int q = 0; q < 8; ++q) {
+        x->release(x->nblk[q], 0);
+        for (int k = 0; k < 3; ++k) x->release(x->tblk[k][q], 0);
+    }
 }
 
 // ---- shared start ------------------------------------------------------------
@@ -1103,14 +1129,14 @@ int run_solve(pdlpb_ctx* x, double tol, int32_t max_iters) {
             if (prec) harvest();
             return PDLPB_OK;
         }
-        if (narrow_applies(x, n_cols)) {
+        if (const int32_t nld = narrow_target(x, n_cols)) {
             if (in_flight) {
                 rc = wait_counts(x, in_slot, &n_active, &n_cols);
                 if (rc) return rc;
                 in_flight = false;
                 continue;
             }
-            rc = enter_narrow(x);
+            rc = enter_narrow(x, nld);
             if (rc) return rc;
             x->live = -1;   // shape the launches (and their graphs) for the new stride
         }

@@ -140,3 +140,29 @@ def test_strong_branching_line_sampled_lps_match_oracle(P, line_root):
                           eval_every=C, stop_every=S)
         print("LP", j, "iters", res[j][0]["iters"], "restarts", res[j][1]["restart_log"][:8])
         assert_trajectory_match(*res[j], ores, what=f"line LP {j}", floor="rms")
+
+
+def test_repeated_line_solves_replay_the_same_bits(P, line_root):
+    """One context solves three draws of the line, then the first again: its
+    captured blocks of iterations are replayed across solves and across the
+    narrow strides the last LPs move through (16, 4, 2, 1), and every solve
+    gives the statuses, iteration counts, KKT measures and objectives of the
+    same draw solved without graphs."""
+    inst, lp, eta, root, w, D0 = line_root
+    draws = [D0] + [fsb_deltas(root["x"], choose_fractional(root["x"], 256, seed_for(5, 100 + r)))
+                    for r in (1, 2)]
+    order = [0, 1, 2, 0]
+    got = {}
+    for graphs, seq in ((1, order), (0, [0, 1, 2])):
+        with P.Context.from_instance(inst, eval_every=24, stop_every=12, max_batch=512,
+                                     step_size=eta, use_graphs=graphs) as ctx:
+            for k, i in enumerate(seq):
+                ctx.set_batch(draws[i], x_warm=root["x"], y_warm=root["y"],
+                              w_warm=np.full(512, w))
+                ctx.solve(tol=1e-4, max_iters=100000)
+                st = ctx.get_batch(want_x=False, want_y=False)
+                got[(graphs, k, i)] = st
+    for (graphs, k, i), st in got.items():
+        ref = got[(0, i, i)]
+        for key in ("status", "iters", "kkt", "obj"):
+            assert np.array_equal(st[key], ref[key], equal_nan=True), (graphs, k, i, key)
