@@ -525,14 +525,17 @@ struct YRowIn {
     double l, u;
     __device__ YRow wide() const { return YRow{(double)yt, (double)dy, (double)y0, l, u}; }
 };
-template <typename T>
+// (KKT: a stopping test alone, which reads z~ only)
+template <typename T, bool KKT = false>
 __device__ __forceinline__ XRowIn<T> load_xrow(const EvalArgs<T>& a, int32_t i, int32_t s) {
     const size_t e = (size_t)i * a.ld + s;
+    if constexpr (KKT) return XRowIn<T>{a.Xt[e], T(0), T(0), a.c[i], a.xl[i], a.xu[i]};
     return XRowIn<T>{a.Xt[e], a.DX[e], a.X0[e], a.c[i], a.xl[i], a.xu[i]};
 }
-template <typename T>
+template <typename T, bool KKT = false>
 __device__ __forceinline__ YRowIn<T> load_yrow(const EvalArgs<T>& a, int32_t i, int32_t s) {
     const size_t e = (size_t)i * a.ld + s;
+    if constexpr (KKT) return YRowIn<T>{a.Yt[e], T(0), T(0), a.rl[i], a.ru[i]};
     return YRowIn<T>{a.Yt[e], a.DY[e], a.Y0[e], a.rl[i], a.ru[i]};
 }
 // x side of column i: g = (A' y~)_i, h = (A' dy)_i, pdy = (A' Pi_B[l,u](dy))_i.
@@ -579,8 +582,34 @@ __device__ __forceinline__ void finish_yrow(const YRow& r, double ax, double adx
     tv[8] = 0.0;
     tv[9] = 0.0;
 }
+// The terms of a stopping test alone (eq:stopping: x side 1-4, y side 2-4),
+// the same expressions as in finish_xrow / finish_yrow, from the products at
+// z~ only; the other terms are 0 (the control pass reads none of them there).
+__device__ __forceinline__ void finish_xrow_kkt(const XRow& r, double g, int32_t varkind,
+                                                const double* dval, int32_t s, int32_t i,
+                                                double* tv) {
+#pragma clang fp contract(off)
+    const VarData d = var_data(varkind, dval, s, i, r.c, r.lo, r.hi);
+    const double rc = barrier(-d.c - g, d.lo, d.hi);        // r~ (reduced cost at y~)
+    const double dres = d.c + g + rc;
+#pragma unroll
+    for (int q = 0; q < NTERM; ++q) tv[q] = 0.0;
+    tv[1] = d.c * r.xt;
+    tv[2] = support1(rc, d.lo, d.hi);
+    tv[3] = dres * dres;
+    tv[4] = d.c * d.c;
+}
+__device__ __forceinline__ void finish_yrow_kkt(const YRow& r, double ax, double* tv) {
+#pragma clang fp contract(off)
+    const double pres = ax - clampd(ax, r.l, r.u);
+#pragma unroll
+    for (int q = 0; q < NTERM; ++q) tv[q] = 0.0;
+    tv[2] = support1(r.yt, r.l, r.u);
+    tv[3] = pres * pres;
+    tv[4] = ax * ax;
+}
 
-template <typename T>
+template <typename T, bool KKT>
 __global__ __launch_bounds__(256) void k_eval(EvalArgs<T> a) {
     __shared__ double red[4][NTERM][64];
     const int lane = threadIdx.x & 63;
@@ -618,16 +647,17 @@ __global__ __launch_bounds__(256) void k_eval(EvalArgs<T> a) {
             const int32_t kbeg = a.t_rp[r0], kend = a.t_rp[r1];
             int32_t i = r0;
             int32_t ke = a.t_rp[r0 + 1];
-            XRowIn<T> cur = load_xrow(a, r0, s), nxt{};
+            XRowIn<T> cur = load_xrow<T, KKT>(a, r0, s), nxt{};
             int32_t ke_n = 0;
             if (r0 + 1 < r1) {
-                nxt = load_xrow(a, r0 + 1, s);
+                nxt = load_xrow<T, KKT>(a, r0 + 1, s);
                 ke_n = a.t_rp[r0 + 2];
             }
             double g = 0.0, h = 0.0, pdy = 0.0;
             auto advance = [&]() {
                 double tv[NTERM];
-                finish_xrow(cur.wide(), g, h, pdy, varkind, a.sl.dval, s, i, tv);
+                if constexpr (KKT) finish_xrow_kkt(cur.wide(), g, varkind, a.sl.dval, s, i, tv);
+                else finish_xrow(cur.wide(), g, h, pdy, varkind, a.sl.dval, s, i, tv);
 #pragma unroll
                 for (int q = 0; q < NTERM; ++q) acc[q] += tv[q];
                 g = h = pdy = 0.0;
@@ -635,7 +665,7 @@ __global__ __launch_bounds__(256) void k_eval(EvalArgs<T> a) {
                 cur = nxt;
                 ke = ke_n;
                 if (i + 1 < r1) {
-                    nxt = load_xrow(a, i + 1, s);
+                    nxt = load_xrow<T, KKT>(a, i + 1, s);
                     ke_n = a.t_rp[i + 2];
                 }
             };
@@ -659,18 +689,23 @@ __global__ __launch_bounds__(256) void k_eval(EvalArgs<T> a) {
                     if (k0 + u < kend) {
                         const size_t f = (size_t)jj[u] * a.ld + s;
                         yv[u] = a.Yt[f];
-                        dv[u] = a.DY[f];
-                        cd[u] = a.rcode[jj[u]];
+                        if constexpr (!KKT) {
+                            dv[u] = a.DY[f];
+                            cd[u] = a.rcode[jj[u]];
+                        }
                     }
                 }
 #pragma unroll
                 for (int u = 0; u < CH; ++u) {
                     if (k0 + u < kend) {
                         while (k0 + u >= ke) advance();
-                        const double w = (double)vv[u], d = (double)dv[u];
+                        const double w = (double)vv[u];
                         g = fma(w, (double)yv[u], g);
-                        h = fma(w, d, h);
-                        pdy = fma(w, barrier_code(d, cd[u]), pdy);
+                        if constexpr (!KKT) {
+                            const double d = (double)dv[u];
+                            h = fma(w, d, h);
+                            pdy = fma(w, barrier_code(d, cd[u]), pdy);
+                        }
                     }
                 }
             }
@@ -679,16 +714,17 @@ __global__ __launch_bounds__(256) void k_eval(EvalArgs<T> a) {
             const int32_t kbeg = a.a_rp[r0], kend = a.a_rp[r1];
             int32_t i = r0;
             int32_t ke = a.a_rp[r0 + 1];
-            YRowIn<T> cur = load_yrow(a, r0, s), nxt{};
+            YRowIn<T> cur = load_yrow<T, KKT>(a, r0, s), nxt{};
             int32_t ke_n = 0;
             if (r0 + 1 < r1) {
-                nxt = load_yrow(a, r0 + 1, s);
+                nxt = load_yrow<T, KKT>(a, r0 + 1, s);
                 ke_n = a.a_rp[r0 + 2];
             }
             double ax = 0.0, adx = 0.0;                       // (A x~)_i, (A dx)_i
             auto advance = [&]() {
                 double tv[NTERM];
-                finish_yrow(cur.wide(), ax, adx, tv);
+                if constexpr (KKT) finish_yrow_kkt(cur.wide(), ax, tv);
+                else finish_yrow(cur.wide(), ax, adx, tv);
 #pragma unroll
                 for (int q = 0; q < NTERM; ++q) acc[q] += tv[q];
                 ax = adx = 0.0;
@@ -696,7 +732,7 @@ __global__ __launch_bounds__(256) void k_eval(EvalArgs<T> a) {
                 cur = nxt;
                 ke = ke_n;
                 if (i + 1 < r1) {
-                    nxt = load_yrow(a, i + 1, s);
+                    nxt = load_yrow<T, KKT>(a, i + 1, s);
                     ke_n = a.a_rp[i + 2];
                 }
             };
@@ -717,7 +753,7 @@ __global__ __launch_bounds__(256) void k_eval(EvalArgs<T> a) {
                     if (k0 + u < kend) {
                         const size_t f = (size_t)jj[u] * a.ld + s;
                         xv[u] = a.Xt[f];
-                        dv[u] = a.DX[f];
+                        if constexpr (!KKT) dv[u] = a.DX[f];
                     }
                 }
 #pragma unroll
@@ -726,7 +762,7 @@ __global__ __launch_bounds__(256) void k_eval(EvalArgs<T> a) {
                         while (k0 + u >= ke) advance();
                         const double w = (double)vv[u];
                         ax = fma(w, (double)xv[u], ax);
-                        adx = fma(w, (double)dv[u], adx);
+                        if constexpr (!KKT) adx = fma(w, (double)dv[u], adx);
                     }
                 }
             }
@@ -759,7 +795,7 @@ __global__ __launch_bounds__(256) void k_eval(EvalArgs<T> a) {
 // ---------------------------------------------------------------------------
 constexpr int NCH = 4;   // nonzeros of a row loaded together by k_eval_narrow
 
-template <typename T>
+template <typename T, bool KKT>
 __global__ __launch_bounds__(256) void k_eval_narrow(EvalArgs<T> a) {
     __shared__ double terms[4][64][NTERM + 1];
     __shared__ double red[4][NTERM];
@@ -796,7 +832,7 @@ __global__ __launch_bounds__(256) void k_eval_narrow(EvalArgs<T> a) {
         if (i < r1) {
             double tq[NTERM];
             if (xside) {
-                const XRowIn<T> r = load_xrow(a, i, s);
+                const XRowIn<T> r = load_xrow<T, KKT>(a, i, s);
                 double g = 0.0, h = 0.0, pdy = 0.0;
                 const int32_t kb = a.t_rp[i], ke = a.t_rp[i + 1];
                 // NCH nonzeros at a time: their indices, then their gathers, are
@@ -818,23 +854,29 @@ __global__ __launch_bounds__(256) void k_eval_narrow(EvalArgs<T> a) {
                         if (k0 + u < ke) {
                             const size_t f = (size_t)jj[u] * a.ld + s;
                             yv[u] = a.Yt[f];
-                            dv[u] = a.DY[f];
-                            cd[u] = a.rcode[jj[u]];
+                            if constexpr (!KKT) {
+                                dv[u] = a.DY[f];
+                                cd[u] = a.rcode[jj[u]];
+                            }
                         }
                     }
 #pragma unroll
                     for (int u = 0; u < NCH; ++u) {
                         if (k0 + u < ke) {
-                            const double w = (double)vv[u], d = (double)dv[u];
+                            const double w = (double)vv[u];
                             g = fma(w, (double)yv[u], g);
-                            h = fma(w, d, h);
-                            pdy = fma(w, barrier_code(d, cd[u]), pdy);
+                            if constexpr (!KKT) {
+                                const double d = (double)dv[u];
+                                h = fma(w, d, h);
+                                pdy = fma(w, barrier_code(d, cd[u]), pdy);
+                            }
                         }
                     }
                 }
-                finish_xrow(r.wide(), g, h, pdy, varkind, a.sl.dval, s, i, tq);
+                if constexpr (KKT) finish_xrow_kkt(r.wide(), g, varkind, a.sl.dval, s, i, tq);
+                else finish_xrow(r.wide(), g, h, pdy, varkind, a.sl.dval, s, i, tq);
             } else {
-                const YRowIn<T> r = load_yrow(a, i, s);
+                const YRowIn<T> r = load_yrow<T, KKT>(a, i, s);
                 double ax = 0.0, adx = 0.0;
                 const int32_t kb = a.a_rp[i], ke = a.a_rp[i + 1];
                 for (int32_t k0 = kb; k0 < ke; k0 += NCH) {
@@ -854,7 +896,7 @@ __global__ __launch_bounds__(256) void k_eval_narrow(EvalArgs<T> a) {
                         if (k0 + u < ke) {
                             const size_t f = (size_t)jj[u] * a.ld + s;
                             xv[u] = a.Xt[f];
-                            dv[u] = a.DX[f];
+                            if constexpr (!KKT) dv[u] = a.DX[f];
                         }
                     }
 #pragma unroll
@@ -862,11 +904,12 @@ __global__ __launch_bounds__(256) void k_eval_narrow(EvalArgs<T> a) {
                         if (k0 + u < ke) {
                             const double w = (double)vv[u];
                             ax = fma(w, (double)xv[u], ax);
-                            adx = fma(w, (double)dv[u], adx);
+                            if constexpr (!KKT) adx = fma(w, (double)dv[u], adx);
                         }
                     }
                 }
-                finish_yrow(r.wide(), ax, adx, tq);
+                if constexpr (KKT) finish_yrow_kkt(r.wide(), ax, tq);
+                else finish_yrow(r.wide(), ax, adx, tq);
             }
 #pragma unroll
             for (int q = 0; q < NTERM; ++q) terms[wave][lane][q] = tq[q];
@@ -2440,12 +2483,16 @@ hipError_t launch_eval(const EvalArgs<T>& a, hipStream_t s) {
     if (a.ncols <= EVAL_NARROW_COLS) {
         const int64_t groups = ((int64_t)a.npx + a.npy + 7) / 8 * 8 * a.ncols;
         if (groups <= 0) return hipSuccess;
-        hipLaunchKernelGGL(k_eval_narrow<T>, dim3((uint32_t)groups), dim3(256), 0, s, a);
+        if (a.kkt_only)
+            hipLaunchKernelGGL((k_eval_narrow<T, true>), dim3((uint32_t)groups), dim3(256), 0, s, a);
+        else
+            hipLaunchKernelGGL((k_eval_narrow<T, false>), dim3((uint32_t)groups), dim3(256), 0, s, a);
         return hipGetLastError();
     }
     const dim3 grid(a.npx + a.npy, (a.ncols + 63) / 64);
     if (grid.x == 0 || grid.y == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_eval<T>, grid, dim3(256), 0, s, a);
+    if (a.kkt_only) hipLaunchKernelGGL((k_eval<T, true>), grid, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((k_eval<T, false>), grid, dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

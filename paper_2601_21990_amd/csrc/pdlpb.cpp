@@ -583,8 +583,10 @@ template <typename T>
 int enqueue_evaluation(pdlpb_ctx* x, int32_t it, int32_t full, int32_t advance,
                        std::vector<std::pair<int, int>>* rec, int32_t admit = 0,
                        int32_t stop = 0) {
-    // a stopping test alone needs the sums of every running LP, as a full evaluation does
+    // a stopping test alone needs the sums of every running LP, as a full evaluation
+    // does, but only the terms of the stopping measures
     EvalArgs<T> e = eval_args<T>(x, it, full || stop);
+    e.kkt_only = stop && !full;
     ControlArgs c = control_args(x, it, full, advance, admit);
     c.stop_only = stop;
     int idx = -1;

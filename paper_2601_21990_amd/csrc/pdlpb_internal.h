@@ -153,6 +153,9 @@ struct EvalArgs {
     int32_t it;              // iteration index inside the block; global t = g->t0 + it
     int32_t full;            // 1: every running LP's sums; 0: only LPs at the start of a
                              // restart cycle (k = 0) or at their last iteration need them
+    int32_t kkt_only;        // 1 (with full = 1): a stopping test alone, whose control pass
+                             // reads the terms of eq:stopping only (x side 1-4, y side 2-4):
+                             // the displacement products are skipped and the other terms are 0
 };
 
 struct ControlArgs {
