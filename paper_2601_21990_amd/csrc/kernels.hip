@@ -1279,11 +1279,13 @@ __global__ __launch_bounds__(1024) void k_control(ControlArgs a) {
 //     stopped one, after that slot's results are copied out (the same thread
 //     reads the old column and then writes the new one), taking a restart
 //     decided at this evaluation on the way.
-// A workgroup owns TR consecutive rows (x rows first, then y rows) and 64
-// plan entries, one per lane; its four waves take every fourth row.  Reads
-// and writes of the row-major blocks run along slots; the results pass
-// through LDS so that each LP's TR values of a result block are written as
-// one contiguous segment.  TR * sizeof(T) = 256 bytes.
+// A workgroup owns TR consecutive rows (x rows first, then y rows) and takes
+// the plan entries 64 at a time, one per lane; its four waves take every
+// fourth row.  Reads and writes of the row-major blocks run along slots, and
+// the entries of one row tile share its lines, so one workgroup walking all of
+// them reads each line once; the results pass through LDS so that each LP's
+// TR values of a result block are written as one contiguous segment.
+// TR * sizeof(T) = 256 bytes.
 // ---------------------------------------------------------------------------
 template <typename T>
 struct Blocks8 {
@@ -1301,15 +1303,13 @@ __global__ __launch_bounds__(256) void k_compact(int32_t n, int32_t m, int32_t l
     const int32_t nr = g->n_retire, nf = g->n_fresh, nm = g->n_move;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const int32_t q0 = (int32_t)blockIdx.y * 64;
-    const int32_t q = q0 + lane;                          // this lane's plan entry
     const int32_t tiles_x = (n + TR - 1) / TR;
     const bool xside = (int32_t)blockIdx.x < tiles_x;
     const int32_t r0 = (xside ? (int32_t)blockIdx.x : (int32_t)blockIdx.x - tiles_x) * TR;
     const int32_t rows = xside ? n : m;
     const int32_t rcount = min(TR, rows - r0);
 
-    if (q < nf) {
+    for (int32_t q = lane; q < nf; q += 64) {
         const int32_t s = fresh[q];
         for (int32_t rr = wave; rr < rcount; rr += 4) {
             const size_t e = (size_t)(r0 + rr) * ld + s;
@@ -1322,7 +1322,8 @@ __global__ __launch_bounds__(256) void k_compact(int32_t n, int32_t m, int32_t l
             }
         }
     }
-    if (q0 < nr) {
+    for (int32_t q0 = 0; q0 < nr; q0 += 64) {
+        const int32_t q = q0 + lane;                      // this lane's plan entry
         if (q < nr) {
             const RetireEntry re = retire[q];
             for (int32_t rr = wave; rr < rcount; rr += 4) {
@@ -1369,8 +1370,9 @@ __global__ __launch_bounds__(256) void k_compact(int32_t n, int32_t m, int32_t l
             rt[o] = res_t[qq][rr];
             rh[o] = res_h[qq][rr];
         }
+        __syncthreads();   // the next entries reuse the LDS rows
     }
-    if (blockIdx.x == 0 && blockIdx.y == 0) {
+    if (blockIdx.x == 0) {
         // slot state of the moved LPs; no other workgroup of this launch reads it
         for (int32_t k = threadIdx.x; k < nm; k += blockDim.x) {
             const MoveEntry mv = moves[k];
@@ -2525,9 +2527,9 @@ hipError_t launch_compact(int32_t n, int32_t m, int32_t ld, int32_t ncols, T* co
     for (int b = 0; b < 8; ++b) B.b[b] = blk[b];
     for (int b = 0; b < 4; ++b) R.b[b] = res[b];
     const int64_t tiles = ((int64_t)n + TR - 1) / TR + ((int64_t)m + TR - 1) / TR;
-    const int64_t chunks = ((int64_t)ncols + 63) / 64;
+    (void)ncols;
     if (tiles > 0x7fffffff) return hipErrorInvalidValue;
-    const dim3 grid((uint32_t)(tiles > 0 ? tiles : 1), (uint32_t)(chunks > 0 ? chunks : 1));
+    const dim3 grid((uint32_t)(tiles > 0 ? tiles : 1));
     hipLaunchKernelGGL(k_compact<T>, grid, dim3(256), 0, s, n, m, ld, B, R, retire, moves, fresh,
                        sl, g);
     return hipGetLastError();
