@@ -949,9 +949,10 @@ def headline(args):
     m, n, nnz = inst.m, inst.n, inst.nnz
     C = args.cfg5_eval
     log(f"instance m={m} n={n} nnz={nnz}")
-    # the root LP (the MIP's relaxation) is solved once, at the evaluation
-    # interval alone, so the candidates do not depend on the batch's options
-    with P.Context.from_instance(inst, device=0, eval_every=C, max_batch=1) as ctx_root:
+    # the root LP (the MIP's relaxation) is solved once, with options of its
+    # own, so the candidates do not depend on the batch's options
+    with P.Context.from_instance(inst, device=0, eval_every=args.cfg5_root_eval,
+                                 max_batch=1) as ctx_root:
         eta, norm_a = ctx_root.step_size
         log(f"eta={eta:.6g} ||A||={norm_a:.6g}")
         t0 = time.perf_counter()
@@ -1139,7 +1140,7 @@ def headline(args):
                                f"{len(draws)} of the candidates",
                    "m": m, "n": n, "nnz": nnz, "B": B, "tol": 1e-4, "draws": len(draws),
                    "eval_every": C, "stop_every": args.cfg5_stop_every,
-                   "root_iters": int(root["iters"])},
+                   "root_eval_every": args.cfg5_root_eval, "root_iters": int(root["iters"])},
         "plain": {"value": round(plain_value, 2), "unit": "LPs/s", "lps": n_plain,
                   "iters_median": int(np.median(plain_iters)), "eval_every": args.cfg5_plain_eval,
                   "ms_per_lp_median": round(float(np.median(plain_s)) * 1e3, 3)},
@@ -1449,9 +1450,12 @@ def main():
                     help="workgroup caps of the step launches; 0 = the library default")
     ap.add_argument("--cfg5-vars", type=int, default=256,
                     help="default line: branching candidates on the 200k x 500k base (B = 2x)")
-    ap.add_argument("--cfg5-eval", type=int, default=24,
+    ap.add_argument("--cfg5-eval", type=int, default=18,
                     help="default line: iterations between evaluations of the batch")
-    ap.add_argument("--cfg5-stop-every", type=int, default=12,
+    ap.add_argument("--cfg5-root-eval", type=int, default=24,
+                    help="default line: evaluation interval of the root solve (the candidates "
+                         "come from its point, so they do not depend on the batch's options)")
+    ap.add_argument("--cfg5-stop-every", type=int, default=6,
                     help="default line: stopping tests every S iterations between evaluations "
                          "(0: off)")
     ap.add_argument("--cfg5-draw-seed", type=int, default=100,
