@@ -120,7 +120,8 @@ typedef struct pdlpb_options {
                                  and the rows of A through it; the evaluation at t = 0 likewise; the
                                  dense blocks are then written only for the LPs still running.  The
                                  results are those of the full-width path, bit for bit.  0 (default):
-                                 when the batch's blocks hold at least 8 MB; 1: whenever the batch
+                                 when the batch's blocks hold at least 256 MB (one block pair over
+                                 the running LPs); 1: whenever the batch
                                  qualifies; -1: never.  A change qualifies when its variable's
                                  column has at most 64 nonzeros and the rows through it at most
                                  4095 in all */

@@ -911,7 +911,11 @@ void free_narrow(pdlpb_ctx* x) {
 }
 
 // ---- shared start ------------------------------------------------------------
-constexpr double SP_AUTO_BYTES = 8e6;   // automatic choice: blocks at least this large
+// Automatic choice: blocks of the batch at least this large.  Below, the
+// full-width start costs little, while an LP's change may reach a tenth of the
+// evaluation panels (20k x 50k, 8 nonzeros per column), each then recomputed
+// for that LP alone.
+constexpr double SP_AUTO_BYTES = 256e6;
 
 int ensure_bytes(pdlpb_ctx* x, void** p, size_t* cap, size_t bytes) {
     if (bytes <= *cap && *p) return PDLPB_OK;
