@@ -1208,15 +1208,16 @@ __global__ __launch_bounds__(1024) void k_control(ControlArgs a) {
     if (threadIdx.x == 0 && (a.full || a.admit))
         g->quiet = (a.full && !a.admit && !a.batch_avg && sh_n[0] == 0) ? 1 : 0;
 
-    // compaction plan (full evaluations and stopping tests): live prefix [0, n_run)
-    if (a.admit) {
+    // compaction plan (full evaluations, stopping tests, and admissions that ask
+    // for one): live prefix [0, n_run)
+    if (a.admit && !a.admit_plan) {
         if (threadIdx.x == 0) {
             g->n_retire = 0;
             g->n_move = 0;
             g->n_fresh = 0;
             g->n_cols_next = nc;
         }
-    } else if (a.full || a.stop_only) {
+    } else if (a.full || a.stop_only || a.admit) {
         for (int32_t s = threadIdx.x; s < nc; s += blockDim.x) sh_flags[s] = a.sl.key[s].flags;
         __syncthreads();
         if (threadIdx.x == 0) {
@@ -1226,8 +1227,11 @@ __global__ __launch_bounds__(1024) void k_control(ControlArgs a) {
                 const int32_t fl = sh_flags[s];
                 if (!(fl & SLOT_RETIRE)) {
                     // restarted LPs that keep their slot; those beyond n_run restart
-                    // as they move
-                    if ((fl & SLOT_ACTIVE) && (fl & SLOT_FRESH) && s < n_run) a.fresh[nf++] = s;
+                    // as they move (at an admission the flag of an LP restarted by the
+                    // last full evaluation still waits for its residual evaluation,
+                    // and that evaluation's plan already made z~ its anchor)
+                    if ((fl & SLOT_ACTIVE) && (fl & SLOT_FRESH) && s < n_run && !a.admit)
+                        a.fresh[nf++] = s;
                     continue;
                 }
                 const int32_t lp = a.sl.lp[s];
@@ -1249,7 +1253,7 @@ __global__ __launch_bounds__(1024) void k_control(ControlArgs a) {
                         a.moves[nm].dst = s;
                         nm += 1;
                         re.src = mover;
-                        re.src_fresh = (sh_flags[mover] & SLOT_FRESH) ? 1 : 0;
+                        re.src_fresh = (!a.admit && (sh_flags[mover] & SLOT_FRESH)) ? 1 : 0;
                         ++mover;
                     }
                 }

@@ -160,6 +160,10 @@ struct pdlpb_ctx {
     double* tail_sum = nullptr;     //   and its evaluation chain and panel sums
     int32_t tail_cap = 0;           //   LPs the two buffers hold
     int32_t* h_pinned = nullptr;    // n_active read-back
+    // serving: the plan of the last admission's compaction (Globals, then up to
+    // max_batch retire entries), read by the next serve_wait
+    int32_t* h_adm_pin = nullptr;
+    bool adm_report = false;
     // shared start: a batch whose running LPs start from one point with the same
     // step sizes makes its first iteration and evaluation per base LP and per
     // change (kernels launch_sp_*)
@@ -327,6 +331,7 @@ void free_all(pdlpb_ctx* x) {
     for (auto& kv : x->dev_sizes) live.push_back(kv.first);
     for (void* p : live) x->free_raw(p);
     if (x->h_pinned) (void)hipHostFree(x->h_pinned);
+    if (x->h_adm_pin) (void)hipHostFree(x->h_adm_pin);
     if (x->own_stream && x->stream) (void)hipStreamDestroy(x->stream);
     delete x;
 }
@@ -589,6 +594,7 @@ int enqueue_evaluation(pdlpb_ctx* x, int32_t it, int32_t full, int32_t advance,
     e.kkt_only = stop && !full;
     ControlArgs c = control_args(x, it, full, advance, admit);
     c.stop_only = stop;
+    c.admit_plan = admit;
     int idx = -1;
     if (rec) idx = timed_begin(x, 2, *rec);
     HIP_TRY(x, launch_eval<T>(e, x->stream));
@@ -2384,6 +2390,11 @@ int pdlpb_serve_begin(pdlpb_ctx* x, int32_t result_capacity) {
     x->n_run0 = 0;
     x->batch_set = false;
     x->solved = false;
+    if (!x->h_adm_pin) {
+        const size_t bytes = 8 * sizeof(int32_t) + sizeof(RetireEntry) * (size_t)x->opt.max_batch;
+        HIP_TRY(x, hipHostMalloc((void**)&x->h_adm_pin, bytes, hipHostMallocDefault));
+    }
+    x->adm_report = false;
     x->serving = true;
     x->res_cap = result_capacity;
     x->free_rows.clear();
@@ -2551,7 +2562,15 @@ int serve_admit(pdlpb_ctx* x) {
     }
     int rc = enqueue_iteration<T>(x, 0, 2, nullptr, 1);
     if (!rc) rc = enqueue_evaluation<T>(x, 0, 1, 0, nullptr, 1);
-    return rc;
+    if (rc) return rc;
+    // the admitted LPs that stopped at their first evaluation left in its
+    // compaction; its plan goes to the host with the block, for serve_wait
+    const hipMemcpyKind d2h = hipMemcpyDeviceToHost;
+    HIP_TRY(x, hipMemcpyAsync(x->h_adm_pin, x->g, 8 * sizeof(int32_t), d2h, x->stream));
+    HIP_TRY(x, hipMemcpyAsync(x->h_adm_pin + 8, x->retire, sizeof(RetireEntry) * x->n_cols, d2h,
+                              x->stream));
+    x->adm_report = true;
+    return PDLPB_OK;
 }
 
 template <typename T>
@@ -2609,6 +2628,16 @@ int pdlpb_serve_wait(pdlpb_ctx* x, int32_t* n_running, int32_t* n_queued) {
         HIP_TRY(x, hipStreamSynchronize(x->stream));
         x->launched = false;
         x->t0 += x->opt.eval_every;
+        if (x->adm_report) {
+            // LPs that stopped at their first evaluation, as admitted in this block
+            x->adm_report = false;
+            const int32_t na = x->h_adm_pin[4];       // Globals::n_retire
+            const RetireEntry* ae = reinterpret_cast<const RetireEntry*>(x->h_adm_pin + 8);
+            for (int32_t k = 0; k < na; ++k) {
+                x->row_state[ae[k].lp] = pdlpb_ctx::ROW_STOPPED;
+                x->completed.push_back(x->row_id[ae[k].lp]);
+            }
+        }
         const int32_t nr = x->h_pinned[4];            // Globals::n_retire
         x->n_cols = x->h_pinned[3];                   // Globals::n_cols
         if (nr > 0) {

@@ -176,7 +176,9 @@ struct ControlArgs {
     int32_t advance;         // 1: move g->t0 on by `block` after this pass
     int32_t block;           // C
     int32_t batch_avg;       // restart scope
-    int32_t admit;           // 1: first evaluation of newly admitted LPs only (no compaction)
+    int32_t admit;           // 1: first evaluation of newly admitted LPs only
+    int32_t admit_plan;      // with admit = 1: plan the compaction too, so admitted LPs that
+                             //    stopped at once leave before the block's iterations
     int32_t pw_literal;      // primal weight ratio as printed
     double beta_s, beta_n, beta_a, theta, cross_sign;
     double infeas_tol;       // eps of the infeasibility tests; < 0: the stopping tolerance; 0: off
