@@ -2303,49 +2303,59 @@ __global__ __launch_bounds__(1024) void k_sp_map(SharedArgs<T> a) {
 }
 
 // Xbar, X0 (x rows) and Y, Y0 (y rows) of the live columns from their base
-// LPs; k_sp_patch writes each LP's own values over them.  A wave writes 64
-// consecutive columns of a row.
+// LPs; k_sp_patch writes each LP's own values over them.  A workgroup writes
+// the live columns of one row at a time, a contiguous run per block.
 template <typename T>
 __global__ __launch_bounds__(256) void k_sp_dense(SharedArgs<T> a) {
-    const int32_t e = blockIdx.y * 64 + (threadIdx.x & 63);
-    if (e >= a.g->n_cols_next) return;
-    const int32_t K = a.map[a.nslots + e];
+    const int32_t nc = a.g->n_cols_next;
     const int32_t total = a.n + a.m;
-    for (int32_t row = blockIdx.x * 4 + (threadIdx.x >> 6); row < total; row += gridDim.x * 4) {
-        if (row < a.n) {
-            const size_t o = (size_t)row * a.ld + e;
-            a.blk[0][o] = a.xbar[(size_t)K * a.n + row];
-            a.blk[1][o] = a.x0[row];
-        } else {
-            const int32_t r = row - a.n;
-            const size_t o = (size_t)r * a.ld + e;
-            a.blk[4][o] = a.yn[(size_t)K * a.m + r];
-            a.blk[5][o] = a.y0[r];
+    for (int32_t row = blockIdx.x; row < total; row += gridDim.x) {
+        for (int32_t e = threadIdx.x; e < nc; e += blockDim.x) {
+            const int32_t K = a.map[a.nslots + e];
+            if (row < a.n) {
+                const size_t o = (size_t)row * a.ld + e;
+                a.blk[0][o] = a.xbar[(size_t)K * a.n + row];
+                a.blk[1][o] = a.x0[row];
+            } else {
+                const int32_t r = row - a.n;
+                const size_t o = (size_t)r * a.ld + e;
+                a.blk[4][o] = a.yn[(size_t)K * a.m + r];
+                a.blk[5][o] = a.y0[r];
+            }
         }
     }
 }
 
 // Results of the LPs stopped at t = 0 from their base LPs (x~, the Halpern
-// iterate rebuilt from x-bar and x^0 as k_compact does, y~, y^1); one
-// workgroup row per plan entry, contiguous along the LP's result rows.
+// iterate rebuilt from x-bar and x^0 as k_compact does, y~, y^1): one thread
+// per row loads the row's base values once and writes them into every stopped
+// LP's result rows, a workgroup writing 256 consecutive entries of one LP at a
+// time.
 template <typename T>
 __global__ __launch_bounds__(256) void k_sp_results(SharedArgs<T> a) {
-    const int32_t q = blockIdx.y;
-    if (q >= a.g->n_retire) return;
-    const RetireEntry re = a.retire[q];
-    const int32_t K = sp_class(a, a.sl.key[re.slot].varkind);
-    const size_t lp = (size_t)re.lp;
-    const int32_t total = a.n + a.m;
-    for (int32_t row = blockIdx.x * 256 + threadIdx.x; row < total; row += gridDim.x * 256) {
-        if (row < a.n) {
-            const size_t e = (size_t)K * a.n + row;
-            a.res[0][lp * a.n + row] = a.xt[e];
-            a.res[1][lp * a.n + row] = halpern_last<T>(re.a, re.kp2, a.xbar[e], a.x0[row]);
+    const int32_t nr = a.g->n_retire;
+    const int32_t row = blockIdx.x * blockDim.x + threadIdx.x;
+    if (row >= a.n + a.m) return;
+    const bool xside = row < a.n;
+    const int32_t i = xside ? row : row - a.n;
+    // per base LP K: x~ and x-bar (y~ and y^1) of this row
+    const T* p0 = xside ? a.xt : a.yt;
+    const T* p1 = xside ? a.xbar : a.yn;
+    const size_t len = xside ? (size_t)a.n : (size_t)a.m;
+    const T a0 = p0[i], a1 = p1[i];
+    const T b0 = a.ncls > 1 ? p0[len + i] : T(0), b1 = a.ncls > 1 ? p1[len + i] : T(0);
+    const T x0 = xside ? a.x0[i] : T(0);
+    for (int32_t q = 0; q < nr; ++q) {
+        const RetireEntry re = a.retire[q];
+        const bool second = sp_class(a, a.sl.key[re.slot].varkind) == 1;
+        const T v0 = second ? b0 : a0, v1 = second ? b1 : a1;
+        const size_t lp = (size_t)re.lp;
+        if (xside) {
+            a.res[0][lp * a.n + i] = v0;
+            a.res[1][lp * a.n + i] = halpern_last<T>(re.a, re.kp2, v1, x0);
         } else {
-            const int32_t r = row - a.n;
-            const size_t e = (size_t)K * a.m + r;
-            a.res[2][lp * a.m + r] = a.yt[e];
-            a.res[3][lp * a.m + r] = a.yn[e];
+            a.res[2][lp * a.m + i] = v0;
+            a.res[3][lp * a.m + i] = v1;
         }
     }
 }
@@ -2656,10 +2666,9 @@ hipError_t launch_sp_place(const SharedArgs<T>& a, hipStream_t s) {
     if (a.nslots == 0) return hipSuccess;
     hipLaunchKernelGGL(k_sp_map<T>, dim3(1), dim3(1024), 0, s, a);
     const int64_t total = (int64_t)a.n + a.m;
-    const uint32_t gx = (uint32_t)(((total + 3) / 4) < 4096 ? (total + 3) / 4 : 4096);
-    hipLaunchKernelGGL(k_sp_dense<T>, dim3(gx, (a.nslots + 63) / 64), dim3(256), 0, s, a);
-    const uint32_t rx = (uint32_t)(((total + 255) / 256) < 64 ? (total + 255) / 256 : 64);
-    hipLaunchKernelGGL(k_sp_results<T>, dim3(rx, a.nslots), dim3(256), 0, s, a);
+    const uint32_t gd = (uint32_t)(total < 16384 ? total : 16384);
+    hipLaunchKernelGGL(k_sp_dense<T>, dim3(gd), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_sp_results<T>, dim3((uint32_t)((total + 255) / 256)), dim3(256), 0, s, a);
     hipLaunchKernelGGL(k_sp_patch<T>, dim3((2 * a.nslots + 3) / 4), dim3(256), 0, s, a);
     hipLaunchKernelGGL(k_sp_finish, dim3(1), dim3(1024), 0, s, a.sl, a.moves, a.g);
     return hipGetLastError();
