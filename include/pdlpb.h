@@ -451,9 +451,13 @@ int pdlpb_kernel_columns(pdlpb_ctx* ctx, int64_t cols[5]);
 /* Bytes of device memory held by the context.  Besides the matrix, base
  * vectors, batch storage and results, a context that has solved a batch whose
  * eight blocks exceed the last-level cache (n + m rows at its stride, at least
- * 256 MB per pair of blocks) keeps eight blocks of 16 columns, (n + m) * 16 *
- * element size * 4 bytes, where a batch's last LPs finish (Section 5: the LPs
- * left once most have stopped); pdlpb_serve_begin releases them. */
+ * 256 MB per pair of blocks) keeps eight blocks each of 16, 4, 2 and 1
+ * columns, (n + m) * 23 * element size * 4 bytes in all, where a batch's last
+ * LPs finish (Section 5: the LPs left once most have stopped); one whose batch
+ * took the shared start (option shared_start) keeps its base vectors,
+ * (n + m)(1 + 3K) elements for K <= 2 base LPs, 196 elements per LP column,
+ * and 80 (n + m) K bytes of evaluation terms; pdlpb_serve_begin releases
+ * both. */
 int64_t pdlpb_device_bytes(const pdlpb_ctx* ctx);
 
 /* Number of blocks of C iterations captured as graphs over the context's life.
