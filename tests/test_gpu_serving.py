@@ -251,3 +251,41 @@ def test_serve_matches_batch_solve_mixed32(P, base):
         assert got[i]["iters"] == ref["iters"][j]
         np.testing.assert_array_equal(got[i]["x"], ref["X"][j])
         np.testing.assert_array_equal(got[i]["y"], ref["Y"][j])
+
+
+def test_lps_stopping_at_admission_leave_with_the_first_block(P):
+    """Strong branching from the root of the 2000 x 5000 family at a tolerance
+    that about half of the branches meet at z~ = T(z^0): after the first
+    block every LP that stopped at its first evaluation is reported, the
+    running count is the LPs still iterating, and every result equals the
+    same LPs solved as a batch, bit for bit (the admission's compaction moves
+    running LPs into the freed columns before the block's iterations)."""
+    from tests.gpu_common import cfg2_setup
+    inst, lp, eta, root, D = cfg2_setup()
+    tol = 1e-3
+    with make_ctx(inst, eta, eval_every=16) as ctx:
+        ctx.set_batch(D, x_warm=root.x, y_warm=root.y, w_warm=np.full(len(D), root.w))
+        ctx.solve(tol=tol, max_iters=20000)
+        ref = ctx.get_batch()
+    first = int(np.sum(ref["iters"] == 1))
+    assert len(D) // 4 < first < 3 * len(D) // 4
+    with make_ctx(inst, eta, eval_every=16) as ctx:
+        ctx.set_base_warm(root.x, root.y, root.w)
+        ctx.serve_begin(128)
+        ids = list(ctx.submit(D, P.WARM_BASE, tol, 20000))
+        ctx.serve_launch()
+        running, _ = ctx.serve_wait()
+        done = set(ctx.poll())
+        # the LPs that stopped at t = 0 and those that stopped within the block
+        stopped_by_16 = {ids[j] for j in range(len(D)) if ref["iters"][j] <= 17}
+        assert {ids[j] for j in range(len(D)) if ref["iters"][j] == 1} <= done
+        assert done == stopped_by_16
+        assert running == len(D) - len(done)
+        got = _serve_until_done(P, ctx, [i for i in ids if i not in done])
+        for i in done:
+            got[i] = ctx.result(i)
+    for j, i in enumerate(ids):
+        assert got[i]["status"] == ref["status"][j]
+        assert got[i]["iters"] == ref["iters"][j]
+        np.testing.assert_array_equal(got[i]["x"], ref["X"][j])
+        np.testing.assert_array_equal(got[i]["y"], ref["Y"][j])
