@@ -236,6 +236,23 @@ int pdlpb_get(pdlpb_ctx* ctx, int32_t j, double* x, double* y, int32_t* status,
               double kkt[4], double* obj, int64_t* iters, int32_t mem);
 
 /*
+ * Result blocks of the caller for the batches that follow: X (capacity x n
+ * doubles) and Y (capacity x m doubles), LP-major device memory on the
+ * context's device.  pdlpb_solve then writes every LP's x~ and y~ there as it
+ * stops (LPs that never run get zeros at pdlpb_set_batch), instead of into
+ * the context's own result blocks, so that pdlpb_get_batch into the same
+ * pointers copies nothing (pdlpb_get, pdlpb_get_batch into other memory and
+ * pdlpb_get_batch_noalloc read them from there).  The caller must keep them
+ * valid and must not write them while a batch is set.  FP64 contexts without
+ * scaling only.  Both NULL returns to the context's own blocks.  Either way
+ * the current batch is dropped (call pdlpb_set_batch again).  Serving ignores
+ * them.  EINVAL: one pointer NULL, an FP32 or scaled context, capacity
+ * outside [1, max_batch]; pdlpb_set_batch then refuses a batch of more than
+ * capacity LPs (EINVAL).
+ */
+int pdlpb_set_result_buffers(pdlpb_ctx* ctx, double* X, double* Y, int32_t capacity);
+
+/*
  * Results of the whole batch at once: X (B*n) and Y (B*m) LP-major, status
  * (B), kkt (4*B: gap, primal, dual, max per LP), obj (B), iters (B).  Any
  * pointer may be NULL.  mem applies to X and Y; the per-LP arrays are host.

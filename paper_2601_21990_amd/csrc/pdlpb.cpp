@@ -137,6 +137,16 @@ struct pdlpb_ctx {
     bool narrow = false;
     size_t cap_res_x = 0, cap_res_y = 0;
     void* res[4] = {};              // Rx, Rxi (B x n), Ry, Ryi (B x m): LP-major results
+    // the caller's blocks for x~ and y~ of a batch (pdlpb_set_result_buffers)
+    double* ext_x = nullptr;
+    double* ext_y = nullptr;
+    int32_t ext_cap = 0;            // LPs they hold
+    // result block q as the kernels write it and the copies read it
+    void* out(int q) const {
+        if (!serving && ext_x && q == 0) return ext_x;
+        if (!serving && ext_y && q == 2) return ext_y;
+        return res[q];
+    }
     int32_t cap_slots = 0;          // slot (column) capacity
     int32_t cap_lps = 0;            // LP rows of ctl / rlog
     Slots sl{};                     // per-slot arrays (key, tau, sigma, dval, t_start, lp)
@@ -190,10 +200,13 @@ struct pdlpb_ctx {
     struct GraphKey {
         int32_t live, ld, wpb, narrow;
         int32_t tp_lanes, tp_vec, tp_blocks, td_lanes, td_vec, td_blocks;
+        const void* rx;   // result blocks the compactions write (the caller's or the context's)
+        const void* ry;
         bool operator==(const GraphKey& o) const {
             return live == o.live && ld == o.ld && wpb == o.wpb && narrow == o.narrow &&
                    tp_lanes == o.tp_lanes && tp_vec == o.tp_vec && tp_blocks == o.tp_blocks &&
-                   td_lanes == o.td_lanes && td_vec == o.td_vec && td_blocks == o.td_blocks;
+                   td_lanes == o.td_lanes && td_vec == o.td_vec && td_blocks == o.td_blocks &&
+                   rx == o.rx && ry == o.ry;
         }
     };
     std::vector<std::pair<GraphKey, hipGraphExec_t>> graphs;
@@ -299,8 +312,8 @@ struct pdlpb_ctx {
         graphs.clear();
     }
     GraphKey graph_key() const {
-        return GraphKey{live,     ld,       wpb,      narrow ? 1 : 0, tp.lanes, tp.vec,
-                        tp.blocks, td.lanes, td.vec,   td.blocks};
+        return GraphKey{live,      ld,       wpb,    narrow ? 1 : 0, tp.lanes, tp.vec,
+                        tp.blocks, td.lanes, td.vec, td.blocks,      out(0),   out(2)};
     }
 };
 
@@ -604,7 +617,8 @@ int enqueue_evaluation(pdlpb_ctx* x, int32_t it, int32_t full, int32_t advance,
     HIP_TRY(x, launch_control(c, x->stream));
     if (full || stop) {
         T* const* b = reinterpret_cast<T* const*>(x->blk);
-        T* const* r = reinterpret_cast<T* const*>(x->res);
+        T* const r[4] = {static_cast<T*>(x->out(0)), static_cast<T*>(x->out(1)),
+                         static_cast<T*>(x->out(2)), static_cast<T*>(x->out(3))};
         HIP_TRY(x, launch_compact<T>(x->n, x->m, x->ld, x->live, b, r, x->retire, x->moves,
                                      x->fresh, x->sl, x->g, x->stream));
     }
@@ -833,7 +847,7 @@ int run_tail(pdlpb_ctx* x, int32_t n_cols, std::vector<std::pair<int, int>>* rec
     a.a_e8ci = x->a_e8ci;
     a.t_e8ci = x->t_e8ci;
     for (int b = 0; b < 8; ++b) a.blk[b] = static_cast<T*>(x->blk[b]);
-    for (int b = 0; b < 4; ++b) a.res[b] = static_cast<T*>(x->res[b]);
+    for (int b = 0; b < 4; ++b) a.res[b] = static_cast<T*>(x->out(b));
     a.c = x->c; a.xl = x->xl; a.xu = x->xu; a.rl = x->rl; a.ru = x->ru;
     a.sl = x->sl; a.ctl = x->ctl; a.rlog = x->rlog; a.g = x->g;
     a.ca = control_args(x, 0, 1, 0);
@@ -1041,7 +1055,7 @@ SharedArgs<T> shared_args(pdlpb_ctx* x, const double* xw = nullptr, const double
     a.moves = x->moves;
     a.map = x->sp_map;
     for (int b = 0; b < 8; ++b) a.blk[b] = static_cast<T*>(x->blk[b]);
-    for (int b = 0; b < 4; ++b) a.res[b] = static_cast<T*>(x->res[b]);
+    for (int b = 0; b < 4; ++b) a.res[b] = static_cast<T*>(x->out(b));
     return a;
 }
 
@@ -1237,6 +1251,10 @@ int copy_results(pdlpb_ctx* x, int q, int32_t first, int32_t count, double* dst,
     const int64_t rows = (q < 2) ? x->n : x->m;
     const int64_t cnt = rows * count;
     if (cnt == 0) return PDLPB_OK;
+    // results the solve wrote into these very buffers (pdlpb_set_result_buffers)
+    if (mem == PDLPB_MEM_DEVICE && !x->fp32 && !x->scaled &&
+        dst == static_cast<const double*>(x->out(q)) + (size_t)first * rows)
+        return PDLPB_OK;
     const hipMemcpyKind kind = mem == PDLPB_MEM_DEVICE ? hipMemcpyDeviceToDevice
                                                         : hipMemcpyDeviceToHost;
     if (x->scaled) {
@@ -1249,10 +1267,10 @@ int copy_results(pdlpb_ctx* x, int q, int32_t first, int32_t count, double* dst,
             buf = x->stage;
         }
         if (x->fp32) {
-            const float* src = static_cast<const float*>(x->res[q]) + (size_t)first * rows;
+            const float* src = static_cast<const float*>(x->out(q)) + (size_t)first * rows;
             HIP_TRY(x, launch_widen(src, cnt, buf, x->stream));
         } else {
-            const double* src = static_cast<const double*>(x->res[q]) + (size_t)first * rows;
+            const double* src = static_cast<const double*>(x->out(q)) + (size_t)first * rows;
             HIP_TRY(x, hipMemcpyAsync(buf, src, cnt * sizeof(double), hipMemcpyDeviceToDevice,
                                       x->stream));
         }
@@ -1263,7 +1281,7 @@ int copy_results(pdlpb_ctx* x, int q, int32_t first, int32_t count, double* dst,
         return PDLPB_OK;
     }
     if (x->fp32) {
-        const float* src = static_cast<const float*>(x->res[q]) + (size_t)first * rows;
+        const float* src = static_cast<const float*>(x->out(q)) + (size_t)first * rows;
         if (mem == PDLPB_MEM_DEVICE) {
             HIP_TRY(x, launch_widen(src, cnt, dst, x->stream));
         } else {
@@ -1273,7 +1291,7 @@ int copy_results(pdlpb_ctx* x, int q, int32_t first, int32_t count, double* dst,
             HIP_TRY(x, hipMemcpyAsync(dst, x->stage, cnt * sizeof(double), kind, x->stream));
         }
     } else {
-        const double* src = static_cast<const double*>(x->res[q]) + (size_t)first * rows;
+        const double* src = static_cast<const double*>(x->out(q)) + (size_t)first * rows;
         HIP_TRY(x, hipMemcpyAsync(dst, src, cnt * sizeof(double), kind, x->stream));
     }
     HIP_TRY(x, hipStreamSynchronize(x->stream));
@@ -1941,6 +1959,8 @@ int pdlpb_set_batch(pdlpb_ctx* x, int32_t B, const pdlpb_delta* deltas, const do
         return x->fail(PDLPB_EINVAL, "unknown warm mode");
     if (warm_mode != PDLPB_WARM_NONE && (!x_warm || (x->m > 0 && !y_warm)))
         return x->fail(PDLPB_EINVAL, "warm start vectors missing");
+    if (x->ext_x && B > x->ext_cap)
+        return x->fail(PDLPB_EINVAL, "batch larger than the result buffers (pdlpb_set_result_buffers)");
     HIP_TRY(x, hipSetDevice(x->device));
     if (x->launched) {
         // a serving block still in flight ends before its storage is reused
@@ -2044,7 +2064,7 @@ int pdlpb_set_batch(pdlpb_ctx* x, int32_t B, const pdlpb_delta* deltas, const do
         for (int q = 0; q < 4; ++q) {
             const size_t len = (size_t)(q < 2 ? n : m) * esz;
             if (len)
-                HIP_TRY(x, hipMemsetAsync(static_cast<char*>(x->res[q]) + (size_t)j * len, 0, len,
+                HIP_TRY(x, hipMemsetAsync(static_cast<char*>(x->out(q)) + (size_t)j * len, 0, len,
                                           x->stream));
         }
     }
@@ -2144,6 +2164,26 @@ int pdlpb_get(pdlpb_ctx* x, int32_t j, double* xo, double* yo, int32_t* status, 
     return rc;
 }
 
+int pdlpb_set_result_buffers(pdlpb_ctx* x, double* X, double* Y, int32_t capacity) {
+    if (!x) return PDLPB_EINVAL;
+    if (!X && !Y) {
+        x->ext_x = x->ext_y = nullptr;
+        x->ext_cap = 0;
+        x->batch_set = false;   // the last batch's results stay where they were written
+        return PDLPB_OK;
+    }
+    if (!X || !Y) return x->fail(PDLPB_EINVAL, "set both result buffers or neither");
+    if (x->fp32 || x->scaled)
+        return x->fail(PDLPB_EINVAL, "result buffers need an FP64 context without scaling");
+    if (capacity < 1 || capacity > x->opt.max_batch)
+        return x->fail(PDLPB_EINVAL, "capacity out of range [1, max_batch]");
+    x->ext_x = X;
+    x->ext_y = Y;
+    x->ext_cap = capacity;
+    x->batch_set = false;       // results of an earlier batch are not in these buffers
+    return PDLPB_OK;
+}
+
 int pdlpb_get_batch(pdlpb_ctx* x, double* X, double* Y, int32_t* status, double* kkt, double* obj,
                     int64_t* iters, int32_t mem) {
     if (!x) return PDLPB_EINVAL;
@@ -2191,10 +2231,10 @@ int copy_results_noalloc(pdlpb_ctx* x, int q, int32_t count, double* dst, int32_
         const int32_t k = std::min(per, count - c0);
         const int64_t cnt = rows * k;
         if (x->fp32) {
-            const float* src = static_cast<const float*>(x->res[q]) + (size_t)c0 * rows;
+            const float* src = static_cast<const float*>(x->out(q)) + (size_t)c0 * rows;
             HIP_TRY(x, launch_widen(src, cnt, scr, x->stream));
         } else {
-            const double* src = static_cast<const double*>(x->res[q]) + (size_t)c0 * rows;
+            const double* src = static_cast<const double*>(x->out(q)) + (size_t)c0 * rows;
             HIP_TRY(x, hipMemcpyAsync(scr, src, cnt * sizeof(double), hipMemcpyDeviceToDevice,
                                       x->stream));
         }

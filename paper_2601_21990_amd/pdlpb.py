@@ -44,7 +44,7 @@ EXPORTED = ["pdlpb_default_options", "pdlpb_create", "pdlpb_set_batch", "pdlpb_s
             "pdlpb_set_kernel_timing", "pdlpb_kernel_times", "pdlpb_kernel_columns",
             "pdlpb_device_bytes", "pdlpb_graph_captures", "pdlpb_estimate_batch",
             "pdlpb_get_batch_noalloc", "pdlpb_serve_ready", "pdlpb_serve_footprint",
-            "pdlpb_serve_trim",
+            "pdlpb_serve_trim", "pdlpb_set_result_buffers",
             "pdlpb_destroy", "pdlpb_last_error"]
 
 
@@ -108,6 +108,7 @@ def _load():
         "pdlpb_get": (C.c_int, [P, i32, P, P, i32p, dp, dp, i64p, i32]),
         "pdlpb_get_batch": (C.c_int, [P, P, P, i32p, dp, dp, i64p, i32]),
         "pdlpb_get_batch_noalloc": (C.c_int, [P, P, P, i32p, dp, dp, i64p, i32]),
+        "pdlpb_set_result_buffers": (C.c_int, [P, P, P, i32]),
         "pdlpb_get_trace": (C.c_int, [P, i32, dp, dp, dp, i32p, i32p, i32]),
         "pdlpb_get_dual_objective": (C.c_int, [P, dp]),
         "pdlpb_obbt_tighten": (C.c_int, [P, d, d, dp, dp, i32p, i32p]),
@@ -365,6 +366,12 @@ class Context:
         self._check(lib.pdlpb_get(self._h, int(j), _ptr(x), _ptr(y), C.byref(st), kkt,
                                   C.byref(obj), C.byref(it), MEM_HOST))
         return dict(x=x, y=y, status=st.value, kkt=list(kkt), obj=obj.value, iters=it.value)
+
+    def set_result_buffers(self, X=None, Y=None, capacity: int = 0):
+        """x~ and y~ of the following batches go straight into the device
+        tensors X (capacity x n) and Y (capacity x m), FP64; get_batch into
+        them then copies nothing.  No arguments: the context's own blocks."""
+        self._check(lib.pdlpb_set_result_buffers(self._h, _ptr(X), _ptr(Y), int(capacity)))
 
     def get_batch(self, want_x=True, want_y=True, X=None, Y=None, mem: int = MEM_HOST):
         B = self.B

@@ -137,4 +137,5 @@ def test_null_context_calls_are_rejected():
     assert P.lib.pdlpb_set_batch(None, 1, None, None, None, None, 0, 0) == P.EINVAL
     assert P.lib.pdlpb_device_bytes(None) == 0
     assert P.lib.pdlpb_estimate_batch(None, None, 0, 10, None, None) == P.EINVAL
+    assert P.lib.pdlpb_set_result_buffers(None, None, None, 0) == P.EINVAL
     P.lib.pdlpb_destroy(None)
