@@ -131,3 +131,19 @@ def test_evaluation_chains_longer_than_a_wave(P):
     D = np.concatenate([obbt_deltas(vars_), fsb_deltas(np.full(inst.n, 0.5), vars_)])
     for tol, K in ((0.0, 1), (0.0, 30)):
         _both(inst, eta, D, tol, K, eval_every=8)
+
+
+@pytest.mark.parametrize("C", [32, 8])
+def test_persistent_tail_after_the_shared_start(P, C):
+    """The persistent tail takes the last LPs of converging batches
+    (tail_cols = 8): it reads the blocks the shared start writes for the LPs
+    still running, and its results equal the full-width path's bit for bit;
+    at a fixed iteration count every LP runs to the cap together and neither
+    path reaches the tail."""
+    inst, lp, eta, base, D = cfg2_setup()
+    for batch in (D, D[:10]):
+        for tol, K in ((1e-4, 100000), (0.0, 40)):
+            a = _run(inst, eta, batch, tol, K, 1, warm=base, eval_every=C, tail_cols=8)
+            b = _run(inst, eta, batch, tol, K, -1, warm=base, eval_every=C, tail_cols=8)
+            assert a["launches"][4] == b["launches"][4] == (1 if tol > 0 else 0)
+            _same(a, b)
