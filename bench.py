@@ -1391,7 +1391,8 @@ def fsb2_leg(args, with_cpu=False):
     return line
 
 
-def main():
+def make_parser():
+    """The command line; its defaults are the default line's options."""
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--workload", default="line",
                     choices=["line", "fsb2", "sweep", "copy", "serve", "obbt", "mixed",
@@ -1499,7 +1500,11 @@ def main():
     ap.add_argument("--tile-vec", type=int, default=0, help="fixed LPs per lane (0: auto)")
     ap.add_argument("--plain-lps", type=int, default=64, help="LPs of the batch solved one at a time")
     ap.add_argument("--graphs", type=int, default=1)
-    args = ap.parse_args()
+    return ap
+
+
+def main():
+    args = make_parser().parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only; the batch shards by LP columns with no "
               "communication, so N GPUs give N independent copies of this measurement",

@@ -4,10 +4,12 @@ column), FP64, B = 512.
 * Bound tightening at a fixed iteration count, default options (the tile
   autotuner times its candidate shapes on the first block of iterations), 65
   iterations (one full evaluation with its restart tests).
-* The strong-branching batch of the benchmark line, converged: the base LP
+* The strong-branching batch of the benchmark line, converged, in the
+  options the benchmark times (its command line's defaults): the base LP
   solved on the GPU, 512 bound changes on 256 fractional variables of its
-  root, warm start from it, C = 24 with stopping tests every 12 iterations,
-  tolerance 1e-4.
+  root, warm start from it, C = 18 with stopping tests every 6 iterations,
+  tolerance 1e-4, captured blocks of iterations, results written into the
+  caller's device tensors.
 
 The oracle recomputes a sample of the LPs one at a time with the same step
 size and start; every LP of the batch must also be finite and still running
@@ -15,6 +17,7 @@ or stopped with a valid status."""
 import numpy as np
 import pytest
 
+import bench
 import oracle as O
 from tests.gpu_common import make_ctx, lp_for, assert_trajectory_match
 from tests.gpu_common import oracle_run
@@ -24,6 +27,7 @@ from workloads import make_cfg5, obbt_deltas, choose_vars, choose_fractional, fs
 pytestmark = pytest.mark.gpu
 
 K = 65
+LINE = bench.make_parser().parse_args([])
 
 
 @pytest.fixture(scope="module")
@@ -56,14 +60,15 @@ def line_root(P):
     candidates."""
     inst = make_cfg5(base=0)
     lp = O.from_instance(inst)
-    with P.Context.from_instance(inst, eval_every=24, max_batch=1) as ctx:
+    with P.Context.from_instance(inst, eval_every=LINE.cfg5_root_eval, max_batch=1) as ctx:
         eta, _ = ctx.step_size
         ctx.set_batch(deltas([BASE], [0], [0.0]))
         ctx.solve(tol=1e-6, max_iters=200000)
         root = ctx.get(0)
         w = ctx.get_trace(0)["w"]
     assert root["status"] == P.STATUS_OPTIMAL
-    D = fsb_deltas(root["x"], choose_fractional(root["x"], 256, seed_for(5, 100)))
+    D = fsb_deltas(root["x"], choose_fractional(root["x"], LINE.cfg5_vars,
+                                                seed_for(5, LINE.cfg5_draw_seed)))
     return inst, lp, eta, root, w, D
 
 
@@ -75,10 +80,11 @@ def test_mixed32_line_points_meet_tolerance_against_a(P, line_root):
     inst, lp, eta, root, w, D = line_root
     res = {}
     for prec in (P.FP64, P.MIXED32):
-        with P.Context.from_instance(inst, eval_every=24, stop_every=12, max_batch=512,
+        with P.Context.from_instance(inst, eval_every=LINE.cfg5_eval,
+                                     stop_every=LINE.cfg5_stop_every, max_batch=512,
                                      step_size=eta, precision=prec) as ctx:
             ctx.set_batch(D, x_warm=root["x"], y_warm=root["y"], w_warm=np.full(len(D), w))
-            ctx.solve(tol=1e-4, max_iters=3000)
+            ctx.solve(tol=1e-4, max_iters=LINE.cfg5_mixed_iters)
             res[prec] = ctx.get_batch()
     a, b = res[P.FP64], res[P.MIXED32]
     both = (a["status"] == P.STATUS_OPTIMAL) & (b["status"] == P.STATUS_OPTIMAL)
@@ -100,24 +106,35 @@ def test_strong_branching_line_sampled_lps_match_oracle(P, line_root):
     three-quarter point of the iteration counts and the slowest LP follow the
     oracle's trajectories from the same root (statuses, iteration counts,
     restart logs, iterates and KKT measures), and solved alone they give the
-    batch's bits (the batch's last LPs run in narrow storage).
+    batch's bits (the batch's last LPs run in narrow storage).  The batch
+    writes its results into device tensors of the caller, as the benchmark
+    does; each read of them gives the same bits.
 
     Per coordinate the iterates are compared on the scale max(|o_i|, rms(o), 1)
     (elem_scale): after hundreds of iterations on duals whose entries are in
     the thousands (rms 1765 for the slowest LP), a dual entry near zero carries
     the rounding of the terms mixed into it, e.g. 4.1e-9 on an entry of 0.58,
     2.3e-12 of the vector's scale; the norm-relative check stays at 1e-9."""
+    import torch
     inst, lp, eta, root, w, D = line_root
-    C, S = 24, 12
+    C, S = LINE.cfg5_eval, LINE.cfg5_stop_every
     assert len(D) == 512
+    dev = torch.device("cuda:0")
+    X = torch.full((len(D), inst.n), float("nan"), dtype=torch.float64, device=dev)
+    Y = torch.full((len(D), inst.m), float("nan"), dtype=torch.float64, device=dev)
     with P.Context.from_instance(inst, eval_every=C, stop_every=S, max_batch=512,
-                                 step_size=eta) as ctx:
+                                 step_size=eta, use_graphs=LINE.graphs) as ctx:
+        ctx.set_result_buffers(X, Y, len(D))
         ctx.set_batch(D, x_warm=root["x"], y_warm=root["y"], w_warm=np.full(len(D), w))
         ctx.solve(tol=1e-4, max_iters=100000)
-        st = ctx.get_batch(want_x=False, want_y=False)
+        st = ctx.get_batch(X=X, Y=Y, mem=P.MEM_DEVICE)
         order = np.argsort(st["iters"], kind="stable")
         sample = sorted({0, int(order[3 * len(order) // 4]), int(order[-1])})
         res = {j: (ctx.get(j), ctx.get_trace(j)) for j in sample}
+    for j in sample:
+        assert np.array_equal(X[j].cpu().numpy(), res[j][0]["x"]), j
+        assert np.array_equal(Y[j].cpu().numpy(), res[j][0]["y"]), j
+    assert not torch.isnan(X).any().item() and not torch.isnan(Y).any().item()
     # the same LPs alone (one column, never moved to narrow storage): the same
     # bits as in the batch, whose last LPs ran in blocks of stride 16
     with P.Context.from_instance(inst, eval_every=C, stop_every=S, max_batch=1,
@@ -143,26 +160,42 @@ def test_strong_branching_line_sampled_lps_match_oracle(P, line_root):
 
 
 def test_repeated_line_solves_replay_the_same_bits(P, line_root):
-    """One context solves three draws of the line, then the first again: its
-    captured blocks of iterations are replayed across solves and across the
-    narrow strides the last LPs move through (16, 4, 2, 1), and every solve
-    gives the statuses, iteration counts, KKT measures and objectives of the
-    same draw solved without graphs."""
+    """One context solves three draws of the line, then the first again, in
+    the benchmark's options (captured blocks, results in the caller's
+    tensors): its captured blocks of iterations are replayed across solves
+    and across the narrow strides the last LPs move through (16, 4, 2, 1),
+    and every solve gives the statuses, iteration counts, KKT measures,
+    objectives and result rows of the same draw solved without graphs into
+    the context's own blocks."""
+    import torch
     inst, lp, eta, root, w, D0 = line_root
-    draws = [D0] + [fsb_deltas(root["x"], choose_fractional(root["x"], 256, seed_for(5, 100 + r)))
-                    for r in (1, 2)]
-    order = [0, 1, 2, 0]
+    draws = [D0] + [fsb_deltas(root["x"], choose_fractional(
+        root["x"], LINE.cfg5_vars, seed_for(5, LINE.cfg5_draw_seed + r))) for r in (1, 2)]
+    B = len(D0)
+    dev = torch.device("cuda:0")
+    X = torch.empty((B, inst.n), dtype=torch.float64, device=dev)
+    Y = torch.empty((B, inst.m), dtype=torch.float64, device=dev)
+    rows = [0, B // 2, B - 1]
     got = {}
-    for graphs, seq in ((1, order), (0, [0, 1, 2])):
-        with P.Context.from_instance(inst, eval_every=24, stop_every=12, max_batch=512,
+    for graphs, seq in ((1, [0, 1, 2, 0]), (0, [0, 1, 2])):
+        with P.Context.from_instance(inst, eval_every=LINE.cfg5_eval,
+                                     stop_every=LINE.cfg5_stop_every, max_batch=B,
                                      step_size=eta, use_graphs=graphs) as ctx:
+            if graphs:
+                ctx.set_result_buffers(X, Y, B)
             for k, i in enumerate(seq):
-                ctx.set_batch(draws[i], x_warm=root["x"], y_warm=root["y"],
-                              w_warm=np.full(512, w))
+                ctx.set_batch(draws[i], x_warm=root["x"], y_warm=root["y"], w_warm=np.full(B, w))
                 ctx.solve(tol=1e-4, max_iters=100000)
                 st = ctx.get_batch(want_x=False, want_y=False)
+                st["rows"] = [(ctx.get(j)["x"], ctx.get(j)["y"]) for j in rows]
+                if graphs:
+                    st["ext"] = [(X[j].cpu().numpy(), Y[j].cpu().numpy()) for j in rows]
                 got[(graphs, k, i)] = st
     for (graphs, k, i), st in got.items():
         ref = got[(0, i, i)]
         for key in ("status", "iters", "kkt", "obj"):
             assert np.array_equal(st[key], ref[key], equal_nan=True), (graphs, k, i, key)
+        for r, (a, b) in enumerate(zip(st["rows"], ref["rows"])):
+            assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]), (graphs, k, i, r)
+        for r, (a, b) in enumerate(zip(st.get("ext", ()), ref["rows"])):
+            assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]), (graphs, k, i, r)
