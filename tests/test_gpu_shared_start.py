@@ -7,14 +7,15 @@ statuses, iteration counts, KKT measures, objectives, restart logs, primal
 weights): bound changes and objective changes, both base LPs in one batch,
 LPs settled at submission, budgets of one and two iterations, loose
 tolerances that stop most LPs at t = 0, the batch-average restart scope,
-stopping tests between evaluations, FP32 iterates, a scaled LP, and
-evaluation chains longer than 64 rows."""
+stopping tests between evaluations, FP32 iterates, a scaled LP, evaluation
+chains longer than 64 rows, and batches holding a change beyond the per-LP
+kernels' reach, which take the full-width path."""
 import numpy as np
 import pytest
 
 from tests.gpu_common import cfg2_setup, make_ctx
-from workloads import (fsb_deltas, obbt_deltas, choose_vars, deltas, make_packing, BASE, SET_LO,
-                       SET_HI)
+from workloads import (fsb_deltas, obbt_deltas, choose_vars, deltas, make_packing, make_facility,
+                       BASE, SET_LO, SET_HI)
 
 pytestmark = pytest.mark.gpu
 
@@ -146,4 +147,46 @@ def test_persistent_tail_after_the_shared_start(P, C):
             a = _run(inst, eta, batch, tol, K, 1, warm=base, eval_every=C, tail_cols=8)
             b = _run(inst, eta, batch, tol, K, -1, warm=base, eval_every=C, tail_cols=8)
             assert a["launches"][4] == b["launches"][4] == (1 if tol > 0 else 0)
+            _same(a, b)
+
+
+def _reach(inst):
+    """Per variable v: the entries of column v of A, and the columns the rows
+    through v reach (v counted once more), the coordinates a change of v moves
+    in one LP's first evaluation."""
+    import scipy.sparse as sp
+    A = sp.csr_matrix((inst.val, inst.col_idx, inst.row_ptr), shape=(inst.m, inst.n))
+    row_len = np.diff(inst.row_ptr)
+    T = A.tocsc()
+    ncol = np.diff(T.indptr)
+    reach = np.array([1 + row_len[T.indices[T.indptr[v]:T.indptr[v + 1]]].sum()
+                      for v in range(inst.n)])
+    return ncol, reach
+
+
+@pytest.mark.parametrize("F, C, k, cap", [(100, 1000, 10, "column"), (2, 9000, 1, "reach")])
+def test_changes_beyond_the_per_lp_reach_take_the_full_width_path(P, F, C, k, cap):
+    """The per-LP kernels of the shared start take a change of v when column v
+    holds at most 64 entries and the rows through v reach at most 4096
+    columns.  Facility location has both kinds beyond: a facility's column
+    holds about C k / F entries, and with two facilities the capacity row
+    through a customer's variable reaches thousands of columns.  A batch of
+    changes within the reach takes the shared start; one change beyond it
+    sends the whole batch down the full-width path; the bits are the same."""
+    inst = make_facility(0, F=F, C=C, k=k)
+    ncol, reach = _reach(inst)
+    within = np.flatnonzero((ncol <= 64) & (reach <= 4096))
+    beyond = np.flatnonzero(ncol > 64) if cap == "column" else \
+        np.flatnonzero((ncol <= 64) & (reach > 4096))
+    assert within.size >= 8 and beyond.size >= 1
+    with make_ctx(inst, None, max_batch=1) as ctx:
+        eta = ctx.step_size[0]
+    rng = np.random.default_rng(F)
+    good = obbt_deltas(np.sort(rng.choice(within, 4, replace=False)))
+    mixed = np.concatenate([good[:3], obbt_deltas(rng.choice(beyond, 1)), good[3:]])
+    for D, shared in ((good, True), (mixed, False)):
+        for tol, K in ((0.0, 1), (0.0, 30), (1e-4, 2000)):
+            a = _run(inst, eta, D, tol, K, 1, eval_every=8)
+            b = _run(inst, eta, D, tol, K, -1, eval_every=8)
+            assert a["launches"][0] == b["launches"][0] - (1 if shared else 0), (shared, K)
             _same(a, b)
