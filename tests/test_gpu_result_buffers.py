@@ -2,9 +2,9 @@
 a batch solved with its x~ and y~ written straight into device tensors gives
 the bits of the same batch written into the context's own blocks, through
 every way of reading them (get_batch into the same tensors, into host
-arrays, get, get_trace), with LPs settled at submission, the shared start,
-the full-width start, and captured graphs replayed over several batches;
-bad calls are refused."""
+arrays, get, get_trace, the entry point that allocates nothing), with LPs
+settled at submission, the shared start, the full-width start, and captured
+graphs replayed over several batches; bad calls are refused."""
 import numpy as np
 import pytest
 
@@ -62,6 +62,11 @@ def test_results_in_caller_tensors_equal_own_blocks(P, torch, shared):
             # and every other read sees the same bits
             got = ext.get_batch()
             assert np.array_equal(got["X"], ref["X"]) and np.array_equal(got["Y"], ref["Y"])
+            Xh, Yh = np.full((B, inst.n), np.nan), np.full((B, inst.m), np.nan)
+            rc = P.lib.pdlpb_get_batch_noalloc(ext._h, Xh.ctypes.data, Yh.ctypes.data, None,
+                                               None, None, None, P.MEM_HOST)
+            assert rc == P.OK
+            assert np.array_equal(Xh, ref["X"]) and np.array_equal(Yh, ref["Y"])
             for j in (0, 20, 21, B - 1):
                 a, b = ext.get(j), own.get(j)
                 assert np.array_equal(a["x"], b["x"]) and np.array_equal(a["y"], b["y"])
@@ -104,3 +109,60 @@ def test_bad_calls_are_refused(P, torch):
     with make_ctx(inst, eta, scaling=1) as ctx:
         with pytest.raises(P.PdlpbError):
             ctx.set_result_buffers(X, Y, 8)
+
+
+def _serve(P, ctx, D, tol, max_iters):
+    ids = list(ctx.submit(D, P.WARM_NONE, tol, max_iters))
+    want, got = set(ids), {}
+    for _ in range(100000):
+        if not want:
+            break
+        ctx.serve_launch()
+        ctx.serve_wait()
+        for i in ctx.poll():
+            if i in want:
+                got[i] = ctx.result(i)
+                want.discard(i)
+    assert not want
+    return [got[i] for i in ids]
+
+
+def test_batches_around_a_serving_session(P, torch):
+    """One context with result tensors and the shared start solves a batch,
+    serves a few requests, then solves the batch again.  The session writes
+    its results into its own rows and leaves the tensors alone (its storage
+    drops the batch's shared-start buffers and captured graphs); both batches
+    give the bits of a fresh context, and the served LPs those of the same
+    LPs solved as a batch."""
+    inst, eta, base, batches = _batches()
+    D = batches[1]
+    B = len(D)
+    served = D[:6]
+    dev = torch.device("cuda:0")
+    X = torch.full((B, inst.n), float("nan"), dtype=torch.float64, device=dev)
+    Y = torch.full((B, inst.m), float("nan"), dtype=torch.float64, device=dev)
+    with make_ctx(inst, eta, eval_every=32, shared_start=1) as fresh:
+        _solve(fresh, D, base)
+        ref = fresh.get_batch()
+        fresh.set_batch(served)
+        fresh.solve(tol=1e-5, max_iters=20000)
+        ref_served = fresh.get_batch()
+    with make_ctx(inst, eta, eval_every=32, shared_start=1) as ctx:
+        ctx.set_result_buffers(X, Y, B)
+        for rnd in range(2):
+            _solve(ctx, D, base)
+            got = ctx.get_batch(X=X, Y=Y, mem=P.MEM_DEVICE)
+            for key in ("status", "iters", "kkt", "obj"):
+                assert np.array_equal(got[key], ref[key]), (rnd, key)
+            assert np.array_equal(X.cpu().numpy(), ref["X"]), rnd
+            assert np.array_equal(Y.cpu().numpy(), ref["Y"]), rnd
+            if rnd:
+                break
+            ctx.serve_begin(8)
+            out = _serve(P, ctx, served, 1e-5, 20000)
+            for j, g in enumerate(out):
+                assert g["status"] == ref_served["status"][j] and g["iters"] == ref_served["iters"][j]
+                assert np.array_equal(g["x"], ref_served["X"][j]), j
+                assert np.array_equal(g["y"], ref_served["Y"][j]), j
+            assert np.array_equal(X.cpu().numpy(), ref["X"])
+            assert np.array_equal(Y.cpu().numpy(), ref["Y"])
