@@ -370,8 +370,25 @@ class Context:
     def set_result_buffers(self, X=None, Y=None, capacity: int = 0):
         """x~ and y~ of the following batches go straight into the device
         tensors X (capacity x n) and Y (capacity x m), FP64; get_batch into
-        them then copies nothing.  No arguments: the context's own blocks."""
-        self._check(lib.pdlpb_set_result_buffers(self._h, _ptr(X), _ptr(Y), int(capacity)))
+        them then copies nothing.  No arguments: the context's own blocks.
+        Both must be contiguous float64 tensors on the context's device with
+        room for capacity LPs; the context keeps them alive until they are
+        replaced or cleared."""
+        capacity = int(capacity)
+        for name, t, cols in (("X", X, self.n), ("Y", Y, self.m)):
+            if t is None:
+                continue            # one of the two alone is refused by the library
+            if not (hasattr(t, "is_cuda") and t.is_cuda):
+                raise TypeError(f"{name} must be a device tensor")
+            if str(t.dtype) != "torch.float64" or not t.is_contiguous():
+                raise TypeError(f"{name} must be a contiguous float64 tensor")
+            if t.device.index != int(self.options.device):
+                raise ValueError(f"{name} is on device {t.device.index}, the context on "
+                                 f"{int(self.options.device)}")
+            if t.numel() < max(capacity, 0) * cols:
+                raise ValueError(f"{name} holds {t.numel()} entries, fewer than {capacity} x {cols}")
+        self._check(lib.pdlpb_set_result_buffers(self._h, _ptr(X), _ptr(Y), capacity))
+        self._result_buffers = None if X is None else (X, Y)
 
     def get_batch(self, want_x=True, want_y=True, X=None, Y=None, mem: int = MEM_HOST):
         B = self.B

@@ -5,6 +5,9 @@ every way of reading them (get_batch into the same tensors, into host
 arrays, get, get_trace, the entry point that allocates nothing), with LPs
 settled at submission, the shared start, the full-width start, and captured
 graphs replayed over several batches; bad calls are refused."""
+import gc
+import weakref
+
 import numpy as np
 import pytest
 
@@ -90,6 +93,25 @@ def test_bad_calls_are_refused(P, torch):
             ctx.set_result_buffers(X, None, 8)
         with pytest.raises(P.PdlpbError):
             ctx.set_result_buffers(X, Y, 0)
+        # the binding checks what the library cannot see behind a pointer
+        with pytest.raises(TypeError):
+            ctx.set_result_buffers(X.float(), Y.float(), 8)
+        with pytest.raises(TypeError):
+            ctx.set_result_buffers(X.cpu().numpy(), Y.cpu().numpy(), 8)
+        with pytest.raises(TypeError):
+            ctx.set_result_buffers(X.t(), Y, 8)
+        with pytest.raises(ValueError):
+            ctx.set_result_buffers(X[:4], Y[:4], 8)
+        # the context keeps the tensors alive while it writes into them
+        Xt, Yt = X.clone(), Y.clone()
+        wx = weakref.ref(Xt)
+        ctx.set_result_buffers(Xt, Yt, 8)
+        del Xt, Yt
+        gc.collect()
+        assert wx() is not None
+        ctx.set_result_buffers()
+        gc.collect()
+        assert wx() is None
         ctx.set_result_buffers(X, Y, 8)
         with pytest.raises(P.PdlpbError) as e:
             ctx.set_batch(batches[1])               # 50 LPs > 8
