@@ -243,6 +243,19 @@ def _ptr(a) -> Optional[int]:
     raise TypeError(f"unsupported buffer type {type(a)}")
 
 
+def _device_f64(name, t, count, device):
+    """Check a device tensor the library reads or writes through its address:
+    contiguous float64 on `device` with at least `count` entries."""
+    if not (hasattr(t, "is_cuda") and t.is_cuda):
+        raise TypeError(f"{name} must be a device tensor")
+    if str(t.dtype) != "torch.float64" or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous float64 tensor")
+    if t.device.index != device:
+        raise ValueError(f"{name} is on device {t.device.index}, the context on {device}")
+    if t.numel() < count:
+        raise ValueError(f"{name} holds {t.numel()} entries, fewer than {count}")
+
+
 def _f64(a, n=None):
     a = np.ascontiguousarray(a, dtype=np.float64)
     if n is not None and a.size != n:
@@ -329,19 +342,23 @@ class Context:
 
     def set_batch(self, deltas, x_warm=None, y_warm=None, w_warm=None,
                   warm_mode: Optional[int] = None, mem: int = MEM_HOST):
-        if mem == MEM_HOST:
-            B = len(deltas)
-        else:                       # a device tensor holding B 16-byte records
-            B = deltas.numel() * deltas.element_size() // 16
+        """B LPs, one change each (deltas: B records); warm start from one
+        point (x_warm n, y_warm m) or one per LP (B*n, B*m), inferred from the
+        size of x_warm unless warm_mode says; w_warm: B primal weights.  With
+        mem = MEM_DEVICE every array is a device tensor on the context's
+        device (deltas: any dtype, B 16-byte records)."""
         if mem == MEM_HOST:
             dd = np.ascontiguousarray(deltas)
             if dd.dtype.itemsize != 16:
                 raise ValueError("deltas must have the 16-byte (kind, var, value) layout")
-            xw = None if x_warm is None else _f64(x_warm)
-            yw = None if y_warm is None else _f64(y_warm)
-            ww = None if w_warm is None else _f64(w_warm, B)
+            B = len(dd)
         else:
-            dd, xw, yw, ww = deltas, x_warm, y_warm, w_warm
+            dd = deltas
+            if not (hasattr(dd, "is_cuda") and dd.is_cuda and dd.is_contiguous()):
+                raise TypeError("deltas must be a contiguous device tensor")
+            if dd.numel() * dd.element_size() % 16:
+                raise ValueError("deltas must hold whole 16-byte (kind, var, value) records")
+            B = dd.numel() * dd.element_size() // 16
         if warm_mode is None:
             if x_warm is None:
                 warm_mode = WARM_NONE
@@ -349,6 +366,25 @@ class Context:
                 nx = x_warm.size if hasattr(x_warm, "size") and not callable(x_warm.size) \
                     else x_warm.numel()
                 warm_mode = WARM_SHARED if nx == self.n else WARM_PER_LP
+        per = B if warm_mode == WARM_PER_LP else 1
+        warm = warm_mode in (WARM_SHARED, WARM_PER_LP)
+        if mem == MEM_HOST:
+            xw = _f64(x_warm, per * self.n) if warm and x_warm is not None else None
+            yw = _f64(y_warm, per * self.m) if warm and y_warm is not None else None
+            ww = None if w_warm is None else _f64(w_warm, B)
+        else:
+            dev = int(self.options.device)
+            if dd.device.index != dev:
+                raise ValueError(f"deltas are on device {dd.device.index}, the context on {dev}")
+            xw = x_warm if warm else None
+            yw = y_warm if warm else None
+            ww = w_warm
+            if xw is not None:
+                _device_f64("x_warm", xw, per * self.n, dev)
+            if yw is not None:
+                _device_f64("y_warm", yw, per * self.m, dev)
+            if ww is not None:
+                _device_f64("w_warm", ww, B, dev)
         self._check(lib.pdlpb_set_batch(self._h, B, _ptr(dd), _ptr(xw), _ptr(yw), _ptr(ww),
                                         int(warm_mode), int(mem)))
         self.B = B
@@ -376,17 +412,8 @@ class Context:
         replaced or cleared."""
         capacity = int(capacity)
         for name, t, cols in (("X", X, self.n), ("Y", Y, self.m)):
-            if t is None:
-                continue            # one of the two alone is refused by the library
-            if not (hasattr(t, "is_cuda") and t.is_cuda):
-                raise TypeError(f"{name} must be a device tensor")
-            if str(t.dtype) != "torch.float64" or not t.is_contiguous():
-                raise TypeError(f"{name} must be a contiguous float64 tensor")
-            if t.device.index != int(self.options.device):
-                raise ValueError(f"{name} is on device {t.device.index}, the context on "
-                                 f"{int(self.options.device)}")
-            if t.numel() < max(capacity, 0) * cols:
-                raise ValueError(f"{name} holds {t.numel()} entries, fewer than {capacity} x {cols}")
+            if t is not None:       # one of the two alone is refused by the library
+                _device_f64(name, t, max(capacity, 0) * cols, int(self.options.device))
         self._check(lib.pdlpb_set_result_buffers(self._h, _ptr(X), _ptr(Y), capacity))
         self._result_buffers = None if X is None else (X, Y)
 
@@ -395,6 +422,11 @@ class Context:
         if mem == MEM_HOST:
             X = np.empty((B, self.n)) if want_x else None
             Y = np.empty((B, self.m)) if want_y else None
+        else:
+            if X is not None:
+                _device_f64("X", X, B * self.n, int(self.options.device))
+            if Y is not None:
+                _device_f64("Y", Y, B * self.m, int(self.options.device))
         status = np.empty(B, dtype=np.int32)
         kkt = np.empty((B, 4))
         obj = np.empty(B)

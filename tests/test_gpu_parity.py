@@ -482,6 +482,52 @@ def test_caller_stream_and_device_buffers(P):
     np.testing.assert_allclose(row_sums.cpu().numpy(), ref["X"].sum(axis=1), rtol=1e-12)
 
 
+def test_binding_checks_arrays_it_passes_by_address(P):
+    """The library reads and writes device arrays through bare addresses, so
+    the binding refuses what would send it past an array's end or into the
+    wrong type: host arrays given as device memory, FP32 or strided tensors,
+    too few entries for the warm-start mode, and result tensors too small for
+    the batch.  A refused call changes nothing; the right arrays then work."""
+    import torch
+    inst, lp, eta, base, D = cfg2_setup()
+    dev = torch.device("cuda:0")
+    B = 8
+    dD = torch.from_numpy(D[:B].view(np.uint8).copy()).to(dev)
+    dx = torch.from_numpy(base.x).to(dev)
+    dy = torch.from_numpy(base.y).to(dev)
+    dw = torch.full((B,), base.w, dtype=torch.float64, device=dev)
+    M = P.MEM_DEVICE
+    with make_ctx(inst, eta, eval_every=32) as ctx:
+        bad = [
+            (TypeError, dict(deltas=D[:B])),
+            (ValueError, dict(deltas=dD[:40])),
+            (TypeError, dict(x_warm=dx.float())),
+            (TypeError, dict(x_warm=torch.stack([dx, dx], 1)[:, 0])),
+            (ValueError, dict(x_warm=dx, warm_mode=P.WARM_PER_LP)),
+            (ValueError, dict(y_warm=dy[:-1], warm_mode=P.WARM_SHARED)),
+            (ValueError, dict(w_warm=dw[:B - 1])),
+        ]
+        for err, kw in bad:
+            args = dict(deltas=dD, x_warm=dx, y_warm=dy, w_warm=dw, mem=M)
+            args.update(kw)
+            with pytest.raises(err):
+                ctx.set_batch(args.pop("deltas"), **args)
+        with pytest.raises(ValueError):
+            ctx.set_batch(D[:B], x_warm=base.x[:-1], y_warm=base.y)
+        ctx.set_batch(dD, x_warm=dx, y_warm=dy, w_warm=dw, mem=M)
+        ctx.solve(tol=1e-4, max_iters=100000)
+        X = torch.empty((B, inst.n), dtype=torch.float64, device=dev)
+        Y = torch.empty((B, inst.m), dtype=torch.float64, device=dev)
+        with pytest.raises(ValueError):
+            ctx.get_batch(X=X[:B - 1], Y=Y, mem=M)
+        with pytest.raises(TypeError):
+            ctx.get_batch(X=X.float(), Y=Y, mem=M)
+        out = ctx.get_batch(X=X, Y=Y, mem=M)
+        ref = ctx.get_batch()
+    assert np.array_equal(X.cpu().numpy(), ref["X"]) and np.array_equal(Y.cpu().numpy(), ref["Y"])
+    assert np.array_equal(out["status"], ref["status"])
+
+
 @pytest.mark.parametrize("K", [1, 66, 200])
 def test_per_lp_warm_starts(P, K):
     """Each LP starts from its own primal point (partly outside the box, which
