@@ -287,8 +287,18 @@ class Context:
                                   if isinstance(sense, (bytes, bytearray)) else sense,
                                   dtype=np.uint8)
         ll, uu = _f64(l, self.n), _f64(u, self.n)
+        # the library reads these by address: m + 1 row pointers, nnz = row_ptr[m]
+        # entries of col_idx and val, m row senses
+        if rp.size != self.m + 1:
+            raise ValueError(f"row_ptr needs m + 1 = {self.m + 1} entries, got {rp.size}")
+        nnz = int(rp[-1])
+        if nnz > 0 and (ci.size < nnz or vv.size < nnz):
+            raise ValueError(f"col_idx and val need row_ptr[m] = {nnz} entries, got "
+                             f"{ci.size} and {vv.size}")
+        if ss.size != self.m:
+            raise ValueError(f"sense needs m = {self.m} entries, got {ss.size}")
         h = C.c_void_p()
-        rc = lib.pdlpb_create(C.byref(h), self.m, self.n, int(rp[-1]) if rp.size else 0,
+        rc = lib.pdlpb_create(C.byref(h), self.m, self.n, nnz,
                               _ptr(rp), _ptr(ci), _ptr(vv), _ptr(cc), _ptr(bb), _ptr(ss),
                               _ptr(ll), _ptr(uu), C.byref(opts))
         if rc != OK:
@@ -484,6 +494,8 @@ class Context:
     def submit(self, deltas, warm_mode: int = WARM_NONE, tol: float = 1e-4,
                max_iters: int = 100000) -> range:
         dd = np.ascontiguousarray(deltas)
+        if dd.dtype.itemsize != 16:
+            raise ValueError("deltas must have the 16-byte (kind, var, value) layout")
         first = C.c_int64()
         self._check(lib.pdlpb_submit(self._h, len(dd), _ptr(dd), int(warm_mode), float(tol),
                                      int(max_iters), MEM_HOST, C.byref(first)))

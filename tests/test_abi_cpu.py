@@ -91,6 +91,24 @@ def test_create_rejects_malformed_input(over, msg):
     assert msg in str(e.value)
 
 
+@pytest.mark.parametrize("over, msg", [
+    (dict(row_ptr=[0, 2]), "row_ptr needs m + 1"),
+    (dict(row_ptr=[0, 2, 3, 3]), "row_ptr needs m + 1"),
+    (dict(col_idx=[0, 2]), "col_idx and val need"),
+    (dict(val=[1.0, 2.0]), "col_idx and val need"),
+    (dict(sense=b"E"), "sense needs m"),
+    (dict(c=np.zeros(2)), "expected 3 entries"),
+    (dict(b=np.zeros(3)), "expected 2 entries"),
+])
+def test_binding_checks_array_lengths_before_the_library_reads_them(over, msg):
+    """The library takes plain pointers: an array shorter than the sizes say
+    would be read past its end, so the binding refuses it first (no HIP call
+    is made, which is why this runs without a GPU)."""
+    with pytest.raises(ValueError) as e:
+        _ctx(**over)
+    assert msg in str(e.value)
+
+
 @pytest.mark.parametrize("opt, msg", [
     (dict(precision=7), "precision"),
     (dict(eval_every=1), "eval_every"),
