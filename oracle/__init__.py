@@ -17,6 +17,8 @@ the problem scaling named in Section 2).
 
 Pins: every function is checked in the CPU test suite against closed forms,
 brute-force vertex enumeration, an independent LP solver (HiGHS via scipy),
+Farkas' lemma for the infeasibility tests (rays of infeasible and unbounded
+LPs are flagged; on feasible LPs the ratios stay above 1/||x^|| and 1/||c||),
 first-order optimality of the proximal steps, firm nonexpansiveness, and
 KKT/complementary-slackness invariants; the scaling against its own closed
 forms (a diagonal matrix equilibrated in one pass, the Pock-Chambolle bound

@@ -95,3 +95,86 @@ def test_infeasible_strong_branching_child_detected():
                  x_init=base.x, y_init=base.y, w_init=base.w)
     assert up.status == O.PRIMAL_INFEASIBLE and up.iters < 20000
     assert dn.status == O.OPTIMAL
+
+
+# ---------------------------------------------------------------------------
+# The tests themselves, against Farkas' lemma.  If x^ is feasible (s = A x^ in
+# [l, u], x^ in the box), then for any dy and dr in the barrier cones
+#   phi(dy) + phi(dr) >= s'dy + x^'dr = x^'(A'dy + dr) >= -||x^|| ||A'dy + dr||,
+# so whenever the support sum is negative the primal ratio is at least
+# 1 / ||x^||: a feasible LP is never flagged for eps below that.  An
+# infeasible LP has a ray dy with A'dy + dr = 0 and a negative support sum,
+# which the test must flag.  On the dual side, a finite box has the recession
+# cone {0}, so the dual ratio is at least ||dx|| / |c'dx| >= 1 / ||c||; an
+# unbounded LP has a ray dx in the recession cones with c'dx < 0.
+# ---------------------------------------------------------------------------
+
+def _displaced(lp, x, y, dx, dy, eps):
+    return O.infeasibility(lp, x, y, x + dx, y + dy, eps)
+
+
+@pytest.mark.parametrize("s", [1e-3, 1.0, 1e3])
+def test_farkas_ray_is_flagged_and_feasible_sibling_never(s):
+    rng = np.random.default_rng(int(s * 1000) % 97)
+    # x1 + x2 = 5 over [0, 1]^2: the ray dy = -1 (dr = (1, 1)) has support sum
+    # -5 + 2 = -3 and A'dy + dr = 0
+    bad = _lp([[1.0, 1.0]], [5.0], "E", [1.0, -1.0], [0.0, 0.0], [1.0, 1.0])
+    x, y = rng.uniform(0, 1, 2), rng.normal(size=1)
+    got = _displaced(bad, x, y, np.zeros(2), np.array([-s]), 1e-6)
+    assert got.primal and not got.dual
+    # x2 + x3 >= 3 over [0, 1]^3: the ray on the second row, dy = (0, -1)
+    bad2 = _lp([[1.0, 2.0, 0.0], [0.0, 1.0, 1.0]], [10.0, 3.0], "LG", [1.0, 1.0, 1.0],
+               [0.0, 0.0, 0.0], [1.0, 1.0, 1.0])
+    got = _displaced(bad2, rng.uniform(0, 1, 3), np.array([0.0, 0.0]), np.zeros(3),
+                     np.array([0.0, -s]), 1e-6)
+    assert got.primal
+    # x1 + x2 = 1 is feasible: no displacement of y is a certificate
+    ok = _lp([[1.0, 1.0]], [1.0], "E", [1.0, -1.0], [0.0, 0.0], [1.0, 1.0])
+    for dy in (-s, s):
+        got = _displaced(ok, x, y, np.zeros(2), np.array([dy]), 0.5)
+        assert not got.primal and got.primal_ratio == np.inf
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_feasible_lp_primal_ratio_bounded_below(seed):
+    """Random displacements on feasible LPs with finite and infinite bounds:
+    whenever the support sum is negative, the ratio is at least 1 / ||x^||
+    for the generator's feasible witness x^."""
+    inst = make_tiny(seed, m=4, n=6, senses="ELG", box=(0.0, 4.0))
+    rng = np.random.default_rng(100 + seed)
+    xl = np.where(rng.random(inst.n) < 0.5, -INF, inst.l)
+    xu = np.where(rng.random(inst.n) < 0.5, INF, inst.u)
+    lp = O.from_arrays(inst.m, inst.n, inst.row_ptr, inst.col_idx, inst.val, inst.c, inst.b,
+                       inst.sense, xl, xu)
+    xh = inst.x0
+    ax = lp.A @ xh
+    assert np.all(ax >= lp.l - 1e-9) and np.all(ax <= lp.u + 1e-9)
+    bound = 1.0 / np.linalg.norm(xh)
+    negative = 0
+    for _ in range(400):
+        y = rng.normal(size=inst.m) * 3
+        dy = rng.normal(size=inst.m) * 10.0 ** rng.uniform(-3, 3)
+        got = _displaced(lp, xh, y, np.zeros(inst.n), dy, 0.5 * bound)
+        assert not got.primal
+        if np.isfinite(got.primal_ratio):
+            negative += 1
+            assert got.primal_ratio >= bound * (1 - 1e-9)
+    assert negative > 0          # the bound was exercised, not only phi >= 0
+
+
+def test_unbounded_ray_is_flagged_and_bounded_sibling_never():
+    # min -x1, x1 - x2 = 0, x >= 0: the ray dx = (1, 1) has c'dx = -1, lies in
+    # the recession cone of the box and A dx = 0
+    bad = _lp([[1.0, -1.0]], [0.0], "E", [-1.0, 0.0], [0.0, 0.0], [INF, INF])
+    ok = _lp([[1.0, -1.0]], [0.0], "E", [-1.0, 0.0], [0.0, 0.0], [5.0, 5.0])
+    rng = np.random.default_rng(4)
+    for t in (1e-3, 1.0, 1e3):
+        x, y = rng.uniform(0, 5, 2), rng.normal(size=1)
+        got = _displaced(bad, x, y, np.array([t, t]), np.zeros(1), 1e-9)
+        assert got.dual and got.dual_ratio <= 1e-12
+        # a finite box: the recession cone is {0}, ratio >= ||dx|| / |c'dx| >= 1 / ||c||
+        for dx in (np.array([t, t]), rng.normal(size=2) * t):
+            got = _displaced(ok, x, y, dx, np.zeros(1), 0.5)
+            assert not got.dual
+            if np.isfinite(got.dual_ratio):
+                assert got.dual_ratio >= 1.0 / np.linalg.norm(ok.c) * (1 - 1e-12)
