@@ -479,9 +479,9 @@ int64_t pdlpb_device_bytes(const pdlpb_ctx* ctx);
 
 /* Number of blocks of C iterations captured as graphs over the context's life.
  * A captured block is replayed for every later batch or serving round with the
- * same launch shape (live column bound, row stride, tile shapes, batch or
- * 16-column storage), and is captured again only when the context's storage is
- * reallocated. */
+ * same launch shape (live column bound, row stride, tile shapes, the batch's
+ * blocks or those of 16, 4, 2 or 1 columns, the result blocks written), and is
+ * captured again only when the context's storage is reallocated. */
 int64_t pdlpb_graph_captures(const pdlpb_ctx* ctx);
 
 /* Release every device buffer and the context.  NULL is a no-op. */
