@@ -1284,12 +1284,13 @@ __global__ __launch_bounds__(1024) void k_control(ControlArgs a) {
 //     reads the old column and then writes the new one), taking a restart
 //     decided at this evaluation on the way.
 // A workgroup owns TR consecutive rows (x rows first, then y rows) and takes
-// the plan entries 64 at a time, one per lane; its four waves take every
-// fourth row.  Reads and writes of the row-major blocks run along slots, and
-// the entries of one row tile share its lines, so one workgroup walking all of
-// them reads each line once; the results pass through LDS so that each LP's
-// TR values of a result block are written as one contiguous segment.
-// TR * sizeof(T) = 256 bytes.
+// the plan entries 64 at a time; its threads take the (entry, row) pairs of
+// the tile, entries fastest, so a few retiring LPs still occupy every thread
+// and issue the tile's loads at once.  Reads and writes of the row-major
+// blocks run along slots, and the entries of one row tile share its lines, so
+// one workgroup walking all of them reads each line once; the results pass
+// through LDS so that each LP's TR values of a result block are written as one
+// contiguous segment.  TR * sizeof(T) = 256 bytes.
 // ---------------------------------------------------------------------------
 template <typename T>
 struct Blocks8 {
@@ -1304,72 +1305,72 @@ __global__ __launch_bounds__(256) void k_compact(int32_t n, int32_t m, int32_t l
     constexpr int TR = 256 / (int)sizeof(T);
     __shared__ T res_t[64][TR + 1];   // z~ of each entry's LP, rows of the tile
     __shared__ T res_h[64][TR + 1];   // its last Halpern iterate
+    __shared__ RetireEntry ent[64];   // the entries of the current chunk
     const int32_t nr = g->n_retire, nf = g->n_fresh, nm = g->n_move;
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
     const int32_t tiles_x = (n + TR - 1) / TR;
     const bool xside = (int32_t)blockIdx.x < tiles_x;
     const int32_t r0 = (xside ? (int32_t)blockIdx.x : (int32_t)blockIdx.x - tiles_x) * TR;
     const int32_t rows = xside ? n : m;
     const int32_t rcount = min(TR, rows - r0);
 
-    for (int32_t q = lane; q < nf; q += 64) {
-        const int32_t s = fresh[q];
-        for (int32_t rr = wave; rr < rcount; rr += 4) {
-            const size_t e = (size_t)(r0 + rr) * ld + s;
-            if (xside) {
-                B.b[1][e] = B.b[2][e];
-            } else {
-                const T v = B.b[6][e];
-                B.b[5][e] = v;
-                B.b[4][e] = v;
-            }
+    // (slot, row) pairs of the restarted slots that stay in place, slots fastest
+    for (int32_t idx = threadIdx.x; idx < nf * rcount; idx += 256) {
+        const int32_t q = idx % nf, rr = idx / nf;
+        const size_t e = (size_t)(r0 + rr) * ld + fresh[q];
+        if (xside) {
+            B.b[1][e] = B.b[2][e];
+        } else {
+            const T v = B.b[6][e];
+            B.b[5][e] = v;
+            B.b[4][e] = v;
         }
     }
     for (int32_t q0 = 0; q0 < nr; q0 += 64) {
-        const int32_t q = q0 + lane;                      // this lane's plan entry
-        if (q < nr) {
-            const RetireEntry re = retire[q];
-            for (int32_t rr = wave; rr < rcount; rr += 4) {
-                const size_t base = (size_t)(r0 + rr) * ld;
-                const size_t e = base + re.slot;
+        const int32_t nq = min(64, nr - q0);
+        if ((int32_t)threadIdx.x < nq) ent[threadIdx.x] = retire[q0 + threadIdx.x];
+        __syncthreads();
+        // (entry, row) pairs of the tile, entries fastest; the thread of a pair
+        // reads the entry's old column at that row and then writes the new one
+        for (int32_t idx = threadIdx.x; idx < nq * rcount; idx += 256) {
+            const int32_t qq = idx % nq, rr = idx / nq;
+            const RetireEntry& re = ent[qq];
+            const size_t base = (size_t)(r0 + rr) * ld;
+            const size_t e = base + re.slot;
+            if (xside) {
+                const T xb = B.b[0][e], x0 = B.b[1][e], xt = B.b[2][e];
+                res_t[qq][rr] = xt;
+                res_h[qq][rr] = halpern_last<T>(re.a, re.kp2, xb, x0);
+            } else {
+                res_t[qq][rr] = B.b[6][e];   // y~
+                res_h[qq][rr] = B.b[4][e];   // Halpern iterate y^{k+1}
+            }
+            if (re.src >= 0) {
+                // a moving LP takes its iterate and anchor along (z~ as both
+                // when it restarted at this evaluation); its z~ and
+                // displacement are written again by the iteration before any
+                // later evaluation reads them
+                const size_t f = base + re.src;
                 if (xside) {
-                    const T xb = B.b[0][e], x0 = B.b[1][e], xt = B.b[2][e];
-                    res_t[lane][rr] = xt;
-                    res_h[lane][rr] = halpern_last<T>(re.a, re.kp2, xb, x0);
+                    const T v0 = B.b[0][f];
+                    const T v1 = re.src_fresh ? B.b[2][f] : B.b[1][f];
+                    B.b[0][e] = v0;
+                    B.b[1][e] = v1;
                 } else {
-                    res_t[lane][rr] = B.b[6][e];   // y~
-                    res_h[lane][rr] = B.b[4][e];   // Halpern iterate y^{k+1}
-                }
-                if (re.src >= 0) {
-                    // a moving LP takes its iterate and anchor along (z~ as both
-                    // when it restarted at this evaluation); its z~ and
-                    // displacement are written again by the iteration before any
-                    // later evaluation reads them
-                    const size_t f = base + re.src;
-                    if (xside) {
-                        const T v0 = B.b[0][f];
-                        const T v1 = re.src_fresh ? B.b[2][f] : B.b[1][f];
-                        B.b[0][e] = v0;
-                        B.b[1][e] = v1;
-                    } else {
-                        const T v4 = re.src_fresh ? B.b[6][f] : B.b[4][f];
-                        const T v5 = re.src_fresh ? v4 : B.b[5][f];
-                        B.b[4][e] = v4;
-                        B.b[5][e] = v5;
-                    }
+                    const T v4 = re.src_fresh ? B.b[6][f] : B.b[4][f];
+                    const T v5 = re.src_fresh ? v4 : B.b[5][f];
+                    B.b[4][e] = v4;
+                    B.b[5][e] = v5;
                 }
             }
         }
         __syncthreads();
         // transposed write: each entry's rows of the tile as one contiguous run
-        const int32_t nq = min(64, nr - q0);
         T* rt = xside ? R.b[0] : R.b[2];
         T* rh = xside ? R.b[1] : R.b[3];
         for (int32_t idx = threadIdx.x; idx < nq * TR; idx += 256) {
             const int32_t qq = idx / TR, rr = idx % TR;
             if (rr >= rcount) continue;
-            const int32_t lp = retire[q0 + qq].lp;
+            const int32_t lp = ent[qq].lp;
             const size_t o = (size_t)lp * rows + r0 + rr;
             rt[o] = res_t[qq][rr];
             rh[o] = res_h[qq][rr];
